@@ -1,0 +1,207 @@
+/*
+ * ks.h -- C ABI of libksmul: exact dense multiplication in Z[x] and (Z/pZ)[x] by multipoint
+ * Kronecker substitution, on AMD Instinct MI355X (gfx950) GPUs.
+ *
+ * Method: D. Harvey, "Faster polynomial multiplication via multipoint Kronecker
+ * substitution" (arXiv 0712.4046).  Problem statement (Section 3): f, g in Z[x] with
+ * coefficients of length at most b bits; compute h = f g.  With e = ceil(log2 L) every
+ * coefficient of h has length at most 2b + e (eq. h-inequality).  The variants reduce the
+ * product to integer multiplications:
+ *   KS1  -- evaluate at 2^N, N = 2b + e: one product                          (Section 3.1)
+ *   NEG2 -- evaluate at +2^N and -2^N, N = b + ceil(e/2): two products, then
+ *           halving, even/odd coefficients read off at 2^(2N)                   (Section 3.3)
+ *   KS4  -- evaluate at +-2^N and +-2^-N (the latter through reversed inputs),
+ *           N = ceil((2b+e)/4): four products, halving, and Section 3.2's
+ *           carry-aware reconstruction on even and odd parts                   (Section 3.4)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Coefficient layout: a polynomial of length L with b-bit coefficients is L * W consecutive
+ *   uint32 limbs, W = ceil(b / 32); coefficient i is limbs [i W, (i+1) W), little-endian.
+ *   Unsigned: value in [0, 2^b), limbs above bit b zero.  KS_SIGNED: value in
+ *   [-2^(b-1), 2^(b-1)) stored as two's complement sign-extended to 32 W bits (b counts the
+ *   sign bit; the paper states non-negative inputs, the signed case is this library's
+ *   extension).
+ * Output layout: h has D = len_f + len_g - 1 coefficients of W_out = ks_out_limbs(...) limbs
+ *   each, two's complement (one spare bit above the paper's 2b + e bound).
+ * Pointers: f, g, h, arenas and workspaces are DEVICE pointers owned by the caller (for
+ *   example torch tensors); the library never frees them.  Descriptor arrays passed to the
+ *   batch planner are HOST pointers.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work and
+ *   return; results are valid once the stream is synchronised.
+ * Errors: every int-returning call returns KS_OK or a negative KS_E* code; nothing else
+ *   crosses the ABI.  Argument errors are found on the host before anything is enqueued.
+ *   Coefficients outside the declared range are found on the device: the call still
+ *   returns KS_OK, h is unspecified, and the next status query reports KS_ERANGE.
+ * Threads: calls on different streams may run concurrently from different host threads.
+ *   Calls that share a stream must not be issued concurrently from several host threads.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- variants and flags (the `variant` argument) ------------------------------------------ */
+#define KS_VARIANT_AUTO 0      /* library picks KS1 / NEG2 / KS4 from its size model         */
+#define KS_VARIANT_KS1 1       /* Section 3.1: one point 2^N                                 */
+#define KS_VARIANT_NEG2 2      /* Section 3.3: points +-2^N                                  */
+#define KS_VARIANT_KS4 4       /* Section 3.4: points +-2^N, +-2^-N                          */
+#define KS_VARIANT_MASK 0xff
+#define KS_SIGNED 0x100        /* coefficients are signed two's complement                   */
+#define KS_ENGINE_VALU 0x1000  /* force the vector-ALU 32x32-bit limb multiplier            */
+#define KS_ENGINE_MFMA 0x2000  /* force the int8 matrix-core (MFMA) limb multiplier          */
+#define KS_MOD 0x10000         /* batch descriptor flag: residues mod desc.mod_p (see below) */
+
+/* ---- status codes ------------------------------------------------------------------------- */
+#define KS_OK 0
+#define KS_EINVAL (-1)        /* bad argument: length < 1, bits out of [1, KS_MAX_BITS], bad variant, NULL */
+#define KS_ENOMEM (-2)        /* device or host allocation failed                            */
+#define KS_EHIP (-3)          /* a HIP runtime call failed                                   */
+#define KS_ERANGE (-4)        /* (status query) a coefficient was outside its declared range */
+#define KS_EUNSUPPORTED (-5)  /* valid request this build does not handle (e.g. no gfx950)   */
+#define KS_EINTERNAL (-6)     /* (status query) an on-device self-check of the reconstruction failed */
+
+#define KS_MAX_BITS 256       /* largest coeff_bits accepted                                  */
+#define KS_MAX_LEN (1LL << 24) /* largest polynomial length accepted                           */
+
+/* Version of this ABI (major * 100 + minor). */
+int32_t ks_version(void);
+
+/* Message for a status code (static storage, never NULL). */
+const char *ks_strerror(int code);
+
+/*
+ * Limbs per output coefficient for a product of lengths len_f, len_g with coeff_bits-bit
+ * coefficients: ceil((2 b + e + 1) / 32), e = ceil(log2 min(len_f, len_g)) (Section 3's
+ * bound 2b + e on the length of each h_i, plus a sign bit).  Returns KS_EINVAL (< 0) for
+ * invalid sizes.
+ */
+int64_t ks_out_limbs(int64_t len_f, int64_t len_g, int32_t coeff_bits);
+
+/*
+ * h = f g in Z[x] (Section 3; variant as above).
+ *   f       device, len_f * W limbs, W = ceil(coeff_bits / 32)
+ *   g       device, len_g * W limbs
+ *   len_f, len_g  >= 1 (unequal lengths allowed; e uses the smaller)
+ *   coeff_bits    b in [1, KS_MAX_BITS]
+ *   variant       KS_VARIANT_* | optional KS_SIGNED | optional KS_ENGINE_*
+ *   stream        hipStream_t or NULL
+ *   h       device, (len_f + len_g - 1) * ks_out_limbs(len_f, len_g, coeff_bits) limbs;
+ *           must not overlap f or g
+ * Scratch space comes from a library-owned pool kept per stream (grown on demand; growing
+ * synchronises that stream once).  Returns KS_OK once the work is enqueued.
+ */
+int ks_mul(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, int32_t coeff_bits,
+           int32_t variant, void *stream, uint32_t *h);
+
+/*
+ * h = f g in (Z/pZ)[x] (Section 4: lift to Z[x], multiply by a Section 3 variant, reduce).
+ *   f, g    device, len_f (len_g) uint64 residues, each in [0, p)
+ *   p       odd modulus, 3 <= p < 2^63
+ *   variant KS_VARIANT_* | optional KS_ENGINE_* (KS_SIGNED is rejected)
+ *   h       device, len_f + len_g - 1 uint64 residues in [0, p)
+ * Residues >= p are reported as KS_ERANGE by the next status query.
+ */
+int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_g, uint64_t p,
+               int32_t variant, void *stream, uint64_t *h);
+
+/*
+ * Synchronise `stream`, then return and clear the device status of the library-owned pool
+ * of that stream: KS_OK, KS_ERANGE or KS_EINTERNAL (KS_EHIP if the synchronisation fails).
+ */
+int ks_stream_status(void *stream);
+
+/* ---- batches (many independent products in one launch sequence) --------------------------- */
+
+/*
+ * One product of a batch.  Offsets count uint32 limbs from the start of the arenas.
+ * Without KS_MOD: f is len_f * W limbs, g is len_g * W limbs (W = ceil(coeff_bits / 32)),
+ *   h is (len_f + len_g - 1) * ks_out_limbs(len_f, len_g, coeff_bits) limbs; flags may hold
+ *   KS_SIGNED.
+ * With KS_MOD: f and g are uint64 residues in [0, mod_p) (2 limbs each), h is len_f + len_g
+ *   - 1 uint64 residues; coeff_bits is ignored (the bit length of mod_p is used).
+ * Offsets of 64-bit data must be even.
+ */
+typedef struct ks_desc {
+    uint64_t f_off;
+    uint64_t g_off;
+    uint64_t h_off;
+    int32_t len_f;
+    int32_t len_g;
+    int32_t coeff_bits;
+    int32_t flags;      /* KS_SIGNED, KS_MOD */
+    uint64_t mod_p;     /* odd modulus < 2^63 when flags & KS_MOD */
+} ks_desc;
+
+typedef struct ks_batch_plan ks_batch_plan; /* opaque */
+
+/*
+ * Plan a batch once: validates every descriptor (KS_EINVAL names nothing; use
+ * ks_batch_plan_bad_index), sizes the scratch, orders the work, and uploads the job tables
+ * to device memory owned by the plan (a synchronous upload).  `variant` applies to every
+ * product (KS_VARIANT_AUTO lets the planner choose per product).
+ */
+int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, ks_batch_plan **plan);
+/* Index of the first descriptor rejected by the last failed ks_batch_plan_create (-1 if none). */
+int64_t ks_batch_plan_bad_index(void);
+/* Device scratch bytes a run of this plan needs. */
+size_t ks_batch_plan_workspace_bytes(const ks_batch_plan *plan);
+/*
+ * Enqueue the whole batch on `stream`.  Allocates nothing and copies nothing from the host,
+ * so it may be captured into a hipGraph and replayed.  `workspace` (device, >= the bytes
+ * above, 256-byte aligned) must not be shared by runs that may overlap.
+ */
+int ks_batch_run(const ks_batch_plan *plan, const uint32_t *arena_in, uint32_t *arena_out,
+                 void *workspace, size_t ws_bytes, void *stream);
+/* Synchronise `stream`, return and clear the status kept in `workspace` (as ks_stream_status). */
+int ks_batch_status(const ks_batch_plan *plan, void *workspace, void *stream);
+void ks_batch_plan_destroy(ks_batch_plan *plan);
+
+/*
+ * One-shot convenience: plan, run on `workspace`, and keep the plan until the stream has
+ * finished with it.  Not for graph capture (it uploads tables).
+ */
+size_t ks_batch_workspace_bytes(const ks_desc *descs, int64_t count, int32_t variant);
+int ks_mul_batch(const uint32_t *arena_in, uint32_t *arena_out, const ks_desc *descs, int64_t count,
+                 int32_t variant, void *workspace, size_t ws_bytes, void *stream);
+
+/* ---- planning and measurement helpers (host only, no device work) ------------------------- */
+
+typedef struct ks_plan_info {
+    int32_t variant;          /* resolved KS_VARIANT_* */
+    int32_t engine;           /* KS_ENGINE_VALU or KS_ENGINE_MFMA */
+    int32_t e;                /* ceil(log2 min(len_f, len_g)) */
+    int32_t slot_bits;        /* N of the resolved variant */
+    int32_t n_products;       /* 1, 2 or 4 integer products */
+    int32_t out_limbs;        /* W_out */
+    int64_t operand_limbs_f;  /* limbs of each evaluation of f */
+    int64_t operand_limbs_g;  /* limbs of each evaluation of g */
+    double limb_mults;        /* 32x32-bit partial products of the multiplier actually run */
+    double schoolbook_limb_mults; /* sum over products of (limbs of a) * (limbs of b) */
+    double hbm_bytes;         /* algorithmic bytes: inputs + outputs + operands + products */
+} ks_plan_info;
+
+int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, ks_plan_info *out);
+
+/*
+ * Per-kernel timing of the library's own launches, for roofline reports.  While enabled,
+ * each launch made by ks_mul / ks_mul_mod / ks_batch_run is bracketed by HIP events on the
+ * stream it is launched on; ks_profile_read synchronises those streams and returns, for
+ * kernel `name`, the number of launches and their summed duration in milliseconds.  Names:
+ * "pack", "mul_valu", "mul_mfma", "normalize", "anchor", "recon", "extract", "digitize".
+ * Returns KS_EINVAL for an unknown name.
+ */
+int ks_profile_enable(int32_t on);
+int ks_profile_read(const char *name, int64_t *launches, double *total_ms);
+int ks_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KS_H */

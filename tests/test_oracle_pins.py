@@ -1,0 +1,339 @@
+"""Pins for the CPU oracle and the paper-order spec, against things other than themselves.
+
+* the paper's printed worked examples (tests/golden/paper_examples.json, each cited);
+* closed forms (all-max / all-min coefficient bounds, binomials, monomials, geometric rows);
+* invariants (h(1), h(-1), h(r) mod a prime q, symmetry, reversal);
+* exhaustive tiny inputs against numpy's polynomial multiplication on Python integers;
+* the paper's operand-length propositions and the reconstruction's unused relations.
+"""
+import json
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+from oracle import ks_spec
+from paper_0712_4046_amd import workloads as wl
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+EX = GOLD["inputs"]
+
+
+def _ints(o, arr, signed):
+    return o.limbs_to_ints(arr, signed)
+
+
+# ---- the paper's worked examples -----------------------------------------------------------
+
+def test_example_product_classical_and_ks1(oracle):
+    f = oracle.ints_to_limbs(EX["f"], 1)
+    g = oracle.ints_to_limbs(EX["g"], 1)
+    b = 10  # all coefficients < 1024
+    w = oracle.out_limbs(4, 4, b)
+    assert _ints(oracle, oracle.mul_classical(f, g, False, w), False) == EX["h"]
+    assert _ints(oracle, oracle.mul_ks1(f, g, b, False, w), False) == EX["h"]
+
+
+def test_example_ks1_base10():
+    G = GOLD["ks1_base10"]
+    t = ks_spec.Trace()
+    h = ks_spec.ks1(EX["f"], EX["g"], G["R"], G["N"], trace=t)
+    assert h == EX["h"]
+    for k in ("f(X)", "g(X)", "h(X)"):
+        assert t[k] == int(G[k]), k
+
+
+def test_example_recip2_base10():
+    G = GOLD["recip2_base10"]
+    t = ks_spec.Trace()
+    h = ks_spec.recip2(EX["f"], EX["g"], G["R"], G["N"], trace=t)
+    assert h == EX["h"]
+    for k in ("f(X)", "X^(L-1) f(1/X)", "g(X)", "X^(L-1) g(1/X)", "h(X)", "X^(2L-2) h(1/X)"):
+        assert t[k] == int(G[k]), k
+    assert t["u"][0] == G["u_0"] and t["w"][1] == G["w_1"] and t["eps_0"] == G["eps_0"]
+    assert t["beta"][0] == G["beta_0"] and h[0] == G["h_0"]
+    X = 10 ** G["N"]
+    assert t["h(X)"] - h[0] == int(G["h(X) - h_0"])
+    assert t["X^(2L-2) h(1/X)"] - X ** 6 * h[0] == int(G["X^(2L-2) h(1/X) - X^(2L-2) h_0"])
+
+
+def test_example_neg2_base10():
+    G = GOLD["neg2_base10"]
+    t = ks_spec.Trace()
+    h = ks_spec.neg2(EX["f"], EX["g"], G["R"], G["N"], trace=t)
+    assert h == EX["h"]
+    for k in ("f0(X^2)", "X f1(X^2)", "f(X)", "f(-X)", "g(X)", "g(-X)", "h(X)", "h(-X)", "h0(X^2)", "X h1(X^2)"):
+        assert t[k] == int(G[k]), k
+
+
+def test_example_ks4_base10():
+    G = GOLD["ks4_base10"]
+    t = ks_spec.Trace()
+    h = ks_spec.ks4(EX["f"], EX["g"], G["R"], G["N"], trace=t)
+    assert h == EX["h"]
+    L = 4
+    sgn = (-1) ** (L - 1)
+    assert t["f(X)"] == int(G["f(X)"]) and t["f(-X)"] == int(G["f(-X)"])
+    assert t["g(X)"] == int(G["g(X)"]) and t["g(-X)"] == int(G["g(-X)"])
+    assert t["f^rev(X)"] == int(G["X^(L-1) f(1/X)"]) and t["g^rev(X)"] == int(G["X^(L-1) g(1/X)"])
+    # X^(L-1) f(-1/X) = (-1)^(L-1) f^rev(-X); the paper prints the former
+    assert sgn * t["f^rev(-X)"] == int(G["X^(L-1) f(-1/X)"])
+    assert sgn * t["g^rev(-X)"] == int(G["X^(L-1) g(-1/X)"])
+    assert t["H1"] == int(G["h(X)"]) and t["H2"] == int(G["h(-X)"])
+    assert t["H3"] == int(G["X^(2L-2) h(1/X)"]) and t["H4"] == int(G["X^(2L-2) h(-1/X)"])
+    assert t["P0"] == int(G["h0(X^2)"]) and t["X P1"] == int(G["X h1(X^2)"])
+    assert t["Q0"] == int(G["X^(2L-2) h0(1/X^2)"]) and t["X Q1"] == int(G["X^(2L-3) h1(1/X^2)"])
+
+
+# ---- closed forms --------------------------------------------------------------------------
+
+def _terms(lf, lg, k):
+    return min(k, lf - 1) - max(0, k - lg + 1) + 1
+
+
+@pytest.mark.parametrize("b", [1, 2, 31, 32, 33, 60, 64, 65, 128])
+@pytest.mark.parametrize("lf,lg", [(1, 1), (3, 5), (16, 16), (37, 20)])
+def test_all_max_unsigned_bound_is_tight(oracle, b, lf, lg):
+    # eq. (h-inequality) is attained: h_k = T_k (2^b - 1)^2 with T_k the number of terms
+    f = wl.special_coeffs("max", lf, b, False)
+    g = wl.special_coeffs("max", lg, b, False)
+    w = oracle.out_limbs(lf, lg, b)
+    want = [_terms(lf, lg, k) * (2 ** b - 1) ** 2 for k in range(lf + lg - 1)]
+    assert _ints(oracle, oracle.mul_classical(f, g, False, w), False) == want
+    assert _ints(oracle, oracle.mul_ks1(f, g, b, False, w), False) == want
+
+
+@pytest.mark.parametrize("b", [1, 2, 16, 32, 33, 64, 128])
+@pytest.mark.parametrize("lf,lg", [(1, 1), (4, 4), (16, 16), (9, 30)])
+def test_signed_extremes(oracle, b, lf, lg):
+    mx, mn = 2 ** (b - 1) - 1, -(2 ** (b - 1))
+    w = oracle.out_limbs(lf, lg, b)
+    for kf, kg, vf, vg in (("min", "min", mn, mn), ("max", "max", mx, mx), ("max", "min", mx, mn)):
+        f = wl.special_coeffs(kf, lf, b, True)
+        g = wl.special_coeffs(kg, lg, b, True)
+        assert _ints(oracle, f, True) == [vf] * lf
+        want = [_terms(lf, lg, k) * vf * vg for k in range(lf + lg - 1)]
+        assert _ints(oracle, oracle.mul_classical(f, g, True, w), True) == want
+        assert _ints(oracle, oracle.mul_ks1(f, g, b, True, w), True) == want
+
+
+@pytest.mark.parametrize("a,c", [(0, 0), (1, 1), (5, 9), (30, 33), (62, 60)])
+def test_binomials(oracle, a, c):
+    # (1+x)^a (1+x)^c = (1+x)^(a+c)
+    b = 64
+    f = oracle.ints_to_limbs([math.comb(a, i) for i in range(a + 1)], 2)
+    g = oracle.ints_to_limbs([math.comb(c, i) for i in range(c + 1)], 2)
+    w = oracle.out_limbs(a + 1, c + 1, b)
+    want = [math.comb(a + c, k) for k in range(a + c + 1)]
+    assert _ints(oracle, oracle.mul_classical(f, g, False, w), False) == want
+    assert _ints(oracle, oracle.mul_ks1(f, g, b, False, w), False) == want
+
+
+def test_monomials(oracle):
+    r = random.Random(7)
+    for _ in range(40):
+        lf, lg = r.randint(1, 40), r.randint(1, 40)
+        b = r.choice([3, 32, 45, 96])
+        i, j = r.randrange(lf), r.randrange(lg)
+        u = r.randrange(-(2 ** (b - 1)), 2 ** (b - 1))
+        v = r.randrange(-(2 ** (b - 1)), 2 ** (b - 1))
+        fw = [0] * lf
+        gw = [0] * lg
+        fw[i], gw[j] = u, v
+        W = wl.limbs_for_bits(b)
+        f, g = oracle.ints_to_limbs(fw, W), oracle.ints_to_limbs(gw, W)
+        want = [0] * (lf + lg - 1)
+        want[i + j] = u * v
+        w = oracle.out_limbs(lf, lg, b)
+        assert _ints(oracle, oracle.mul_classical(f, g, True, w), True) == want
+        assert _ints(oracle, oracle.mul_ks1(f, g, b, True, w), True) == want
+
+
+def test_geometric_row(oracle):
+    # f = all ones, g_j = 2^j: h_k = sum_{j=lo}^{hi} 2^j = 2^(hi+1) - 2^lo
+    lf, lg, b = 13, 40, 41
+    f = oracle.ints_to_limbs([1] * lf, 2)
+    g = oracle.ints_to_limbs([2 ** j for j in range(lg)], 2)
+    want = []
+    for k in range(lf + lg - 1):
+        lo, hi = max(0, k - lf + 1), min(k, lg - 1)
+        want.append(2 ** (hi + 1) - 2 ** lo)
+    w = oracle.out_limbs(lf, lg, b)
+    assert _ints(oracle, oracle.mul_classical(f, g, False, w), False) == want
+    assert _ints(oracle, oracle.mul_ks1(f, g, b, False, w), False) == want
+
+
+@pytest.mark.parametrize("b", [1, 7, 32, 33, 64, 100, 256])
+def test_length_one_is_integer_product(oracle, b):
+    gen = wl.rng(b)
+    for signed in (False, True):
+        f = wl.random_coeffs(gen, 1, b, signed)
+        g = wl.random_coeffs(gen, 1, b, signed)
+        w = oracle.out_limbs(1, 1, b)
+        want = [_ints(oracle, f, signed)[0] * _ints(oracle, g, signed)[0]]
+        assert _ints(oracle, oracle.mul_classical(f, g, signed, w), signed) == want
+        assert _ints(oracle, oracle.mul_ks1(f, g, b, signed, w), signed) == want
+
+
+# ---- exhaustive tiny inputs against a library routine --------------------------------------
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_exhaustive_tiny(oracle, signed):
+    b = 2
+    vals = list(range(-2, 2)) if signed else list(range(0, 4))
+    import itertools
+    polys = []
+    for L in (1, 2, 3):
+        polys += [list(t) for t in itertools.product(vals, repeat=L)]
+    r = random.Random(11)
+    pairs = [(p, q) for p in polys for q in polys if len(p) <= 2 or len(q) <= 2]
+    pairs += [(r.choice(polys), r.choice(polys)) for _ in range(2000)]
+    for p, q in pairs:
+        f, g = oracle.ints_to_limbs(p, 1), oracle.ints_to_limbs(q, 1)
+        w = oracle.out_limbs(len(p), len(q), b)
+        want = [int(x) for x in np.polynomial.polynomial.polymul(np.array(p, dtype=object), np.array(q, dtype=object))]
+        want += [0] * (len(p) + len(q) - 1 - len(want))  # polymul trims trailing zeros
+        assert _ints(oracle, oracle.mul_classical(f, g, signed, w), signed) == want, (p, q)
+        assert _ints(oracle, oracle.mul_ks1(f, g, b, signed, w), signed) == want, (p, q)
+
+
+# ---- invariants on random inputs -----------------------------------------------------------
+
+def _eval(c, x):
+    return ks_spec.evaluate(c, x)
+
+
+Q61 = 2 ** 61 - 1  # a Mersenne prime
+
+
+@pytest.mark.parametrize("lf,lg,b,signed", [(1, 1, 32, False), (256, 256, 32, False), (300, 301, 64, True),
+                                            (64, 17, 128, True), (1000, 999, 60, False), (33, 512, 7, True),
+                                            (128, 128, 256, True)])
+def test_invariants_random(oracle, lf, lg, b, signed):
+    gen = wl.rng(lf * 7 + lg + b)
+    f = wl.random_coeffs(gen, lf, b, signed)
+    g = wl.random_coeffs(gen, lg, b, signed)
+    w = oracle.out_limbs(lf, lg, b)
+    hc = oracle.mul_classical(f, g, signed, w)
+    hk = oracle.mul_ks1(f, g, b, signed, w)
+    assert np.array_equal(hc, hk)
+    F, G, H = (_ints(oracle, x, signed) for x in (f, g, hc))
+    assert _eval(H, 1) == _eval(F, 1) * _eval(G, 1)
+    assert _eval(H, -1) == _eval(F, -1) * _eval(G, -1)
+    r = random.Random(lf + lg)
+    for _ in range(4):
+        x = r.randrange(2, Q61)
+        assert _eval(H, x) % Q61 == (_eval(F, x) * _eval(G, x)) % Q61
+    # symmetry and reversal
+    assert np.array_equal(oracle.mul_classical(g, f, signed, w), hc)
+    hr = oracle.mul_classical(f[::-1].copy(), g[::-1].copy(), signed, w)
+    assert np.array_equal(hr, hc[::-1])
+    # bound of eq. (h-inequality), with the signed analogue |h_k| <= T_k 2^(2b-2)
+    for k, v in enumerate(H):
+        T = _terms(lf, lg, k)
+        if signed:
+            assert abs(v) <= T * 2 ** (2 * b - 2)
+        else:
+            assert 0 <= v <= T * (2 ** b - 1) ** 2
+
+
+def test_sampled_coefficients_match_full(oracle):
+    gen = wl.rng(99)
+    f = wl.random_coeffs(gen, 500, 64, True)
+    g = wl.random_coeffs(gen, 380, 64, True)
+    w = oracle.out_limbs(500, 380, 64)
+    h = oracle.mul_classical(f, g, True, w)
+    ks = [0, 1, 379, 380, 499, 500, 878]
+    assert np.array_equal(oracle.coeffs_classical(f, g, True, ks, w), h[ks])
+
+
+# ---- modular route -------------------------------------------------------------------------
+
+def test_mod_p(oracle):
+    p = wl.config4_modulus()
+    assert p % 2 == 1 and 2 ** 59 <= p < 2 ** 60
+    gen = wl.rng(5)
+    f = gen.integers(0, p, size=300, dtype=np.uint64)
+    g = gen.integers(0, p, size=257, dtype=np.uint64)
+    h = oracle.mul_mod(f, g, p)
+    F, G = [int(x) for x in f], [int(x) for x in g]
+    r = random.Random(3)
+    for _ in range(4):
+        x = r.randrange(p)
+        assert _eval([int(v) for v in h], x) % p == (_eval(F, x) * _eval(G, x)) % p
+    # all-max residues: h_k = T_k (p-1)^2 = T_k (mod p); long enough rows that the exact sums
+    # pass 2^128 (T_k (p-1)^2 > 2^129), so an accumulator that never reduces would wrap
+    for lf, lg in ((40, 23), (1200, 1100)):
+        fm = np.full(lf, p - 1, dtype=np.uint64)
+        gm = np.full(lg, p - 1, dtype=np.uint64)
+        hm = oracle.mul_mod(fm, gm, p)
+        assert [int(x) for x in hm] == [_terms(lf, lg, k) % p for k in range(lf + lg - 1)]
+    ks = [0, 5, 299, 555]
+    assert [int(x) for x in oracle.coeffs_mod(f, g, p, ks)] == [int(h[k]) for k in ks]
+    # cross-route: lift, classical over Z, reduce
+    fl = oracle.ints_to_limbs(F, 2)
+    gl = oracle.ints_to_limbs(G, 2)
+    hz = _ints(oracle, oracle.mul_classical(fl, gl, False, oracle.out_limbs(300, 257, 60)), False)
+    assert [v % p for v in hz] == [int(x) for x in h]
+
+
+# ---- the variants at base 2 (readings for signed inputs and unequal lengths) ---------------
+
+@pytest.mark.parametrize("variant", ["ks1", "neg2", "recip2", "ks4"])
+def test_variants_base2_match_oracle(oracle, variant):
+    r = random.Random(hash(variant) & 0xFFFF)
+    cases = [(1, 1, 1, False), (1, 1, 5, True), (2, 1, 3, True), (4, 4, 10, False), (5, 8, 16, True),
+             (6, 7, 32, False), (33, 20, 64, True), (64, 64, 33, True), (17, 16, 128, False), (9, 2, 2, True)]
+    for lf, lg, b, signed in cases + [(r.randint(1, 50), r.randint(1, 50), r.randint(1, 140), r.random() < 0.5)
+                                      for _ in range(25)]:
+        for kind in ("rand", "max", "min"):
+            gen = wl.rng(lf * 1000 + lg * 10 + b)
+            if kind == "rand":
+                f, g = wl.random_coeffs(gen, lf, b, signed), wl.random_coeffs(gen, lg, b, signed)
+            else:
+                f, g = wl.special_coeffs(kind, lf, b, signed), wl.special_coeffs(kind, lg, b, signed)
+            w = oracle.out_limbs(lf, lg, b)
+            want = _ints(oracle, oracle.mul_classical(f, g, signed, w), signed)
+            got = ks_spec.multiply(_ints(oracle, f, signed), _ints(oracle, g, signed), b, variant, signed)
+            assert got == want, (variant, lf, lg, b, signed, kind)
+
+
+def test_operand_length_propositions():
+    # Propositions of Sections 3.1-3.4: lengths of the integers multiplied
+    r = random.Random(5)
+    for _ in range(60):
+        L = r.randint(1, 300)
+        b = r.randint(1, 100)
+        e = ks_spec.e_of(L, L)
+        f = [2 ** b - 1] * L  # largest values give the longest evaluations
+        for variant, bound in (("ks1", (2 * b + e) * (L - 1) + b),
+                               ("neg2", (b + (e + 1) // 2) * (L - 1) + b),
+                               ("recip2", (b + (e + 1) // 2) * (L - 1) + b),
+                               ("ks4", ((2 * b + e + 3) // 4) * (L - 1) + b)):
+            N = ks_spec.slot_bits(variant, b, e)
+            X = 2 ** N
+            # when slots overlap (N < b, only in Section 3.4) the sum of overlapping
+            # coefficients can carry one bit past the stated length
+            slack = 1 if N < b else 0
+            assert ks_spec.evaluate(f, X).bit_length() <= bound + slack
+            assert abs(ks_spec.evaluate(f, -X)).bit_length() <= bound + slack
+            if slack == 0:
+                assert ks_spec.evaluate(f, X).bit_length() == bound or L == 1
+
+
+def test_reconstruction_unused_relations_hold():
+    r = random.Random(9)
+    for _ in range(200):
+        m = r.randint(1, 40)
+        N = r.randint(1, 40)
+        X = 2 ** N
+        h = [r.randrange(0, X * (X - 1)) for _ in range(m)]
+        if r.random() < 0.3:
+            h = [r.choice([0, 1, X - 1, X, X * (X - 1) - 1]) for _ in range(m)]
+        A = sum(c * X ** i for i, c in enumerate(h))
+        B = sum(c * X ** (m - 1 - i) for i, c in enumerate(h))
+        t = ks_spec.Trace()
+        assert ks_spec.recip_reconstruct(A, B, m, X, t) == h
+        assert t["check_top_alpha"] and t["check_top_carry"]
