@@ -1,0 +1,689 @@
+// ks_api.cpp -- host side of libksmul: planner, scratch pools, launch sequencing, C ABI.
+//
+// One product runs as a short pipeline of kernels on the caller's stream:
+//   pack       evaluations of f and g at the variant's points        (paper 3.1, 3.3, 3.4)
+//   mul_valu   the 1, 2 or 4 integer products                        (3.1 - 3.4)
+//   normalize  carry resolution, recombination and exact halving     (3.3, 3.4)
+//   extract    coefficients read off their slots                     (3.1, 3.3)
+//   anchor + chain   Section 3.2's reconstruction, in parallel segments  (3.4)
+// The planner below turns (lengths, bits, variant) into sizes and job descriptors; the same
+// descriptors drive single products (passed by value) and batches (device tables).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ks.h"
+#include "ks_jobs.h"
+#include "ks_launch.h"
+#include "ks_plan.h"
+
+namespace ks {
+
+// ---- small integer helpers --------------------------------------------------------------------
+
+int ceil_log2(int64_t x) {
+    int e = 0;
+    while (((int64_t)1 << e) < x) ++e;
+    return e;
+}
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
+
+static int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+// ---- planning -----------------------------------------------------------------------------------
+
+static int64_t slot_bits(int variant, int b, int e) {
+    switch (variant) {
+        case KS_VARIANT_KS1: return 2 * (int64_t)b + e;                 // Section 3.1
+        case KS_VARIANT_NEG2: return (int64_t)b + (e + 1) / 2;          // Section 3.3
+        case KS_VARIANT_KS4: return (2 * (int64_t)b + e + 3) / 4;       // Section 3.4
+    }
+    return 0;
+}
+
+// Simple cost model for KS_VARIANT_AUTO: schoolbook limb products plus a per-limb overhead.
+static int auto_variant(int64_t lf, int64_t lg, int b, int e) {
+    double best = 1e300;
+    int pick = KS_VARIANT_KS1;
+    for (int v : {KS_VARIANT_KS1, KS_VARIANT_NEG2, KS_VARIANT_KS4}) {
+        int64_t N = slot_bits(v, b, e);
+        int k = v == KS_VARIANT_KS1 ? 1 : (v == KS_VARIANT_NEG2 ? 2 : 4);
+        double na = (double)cdiv(N * (lf - 1) + b + 2, 32), nb = (double)cdiv(N * (lg - 1) + b + 2, 32);
+        double cost = k * na * nb + 64.0 * k * (na + nb) + (v == KS_VARIANT_KS4 ? 2048.0 * (lf + lg) : 0.0);
+        if (cost < best) { best = cost; pick = v; }
+    }
+    return pick;
+}
+
+int plan_product(const Spec &sp, Geom &G) {
+    G = Geom();
+    G.sp = sp;
+    const int64_t lf = sp.lf, lg = sp.lg;
+    const int b = sp.bits;
+    G.e = ceil_log2(std::min(lf, lg));
+    G.D = lf + lg - 1;
+    G.m0 = (G.D + 1) / 2;
+    G.m1 = G.D / 2;
+    G.w_out = (int)cdiv(2 * (int64_t)b + G.e + 1, 32);
+    G.off = sp.sgn ? 2 * b - 2 + G.e : -1;
+    int v = sp.variant;
+    if (v == KS_VARIANT_AUTO) v = auto_variant(lf, lg, b, G.e);
+    if (v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_KS4) return KS_EINVAL;
+    G.variant = v;
+    const int64_t N = slot_bits(v, b, G.e);
+    G.N = N;
+    const int64_t nf = cdiv(N * (lf - 1) + b + 2, 32), ng = cdiv(N * (lg - 1) + b + 2, 32);
+    G.nf = nf;
+    G.ng = ng;
+
+    // evaluations: f points first, then the same points for g
+    std::vector<int> pf;
+    if (v == KS_VARIANT_KS1) pf = {0};
+    else if (v == KS_VARIANT_NEG2) pf = {0, PK_ALTERNATE};
+    else pf = {0, PK_ALTERNATE, PK_REVERSE, PK_REVERSE | PK_ALTERNATE};
+    const int npts = (int)pf.size();
+    int64_t off = 0;
+    for (int which = 0; which < 2; ++which)
+        for (int q = 0; q < npts; ++q) {
+            PackGeom p;
+            p.which = which;
+            p.flags = pf[q] | (sp.sgn ? PK_SIGNED : 0) | (q == 0 ? PK_CHECK : 0);
+            p.L = which ? lg : lf;
+            p.n_out = which ? ng : nf;
+            p.op_off = off;
+            p.blocks = cdiv(p.n_out, SCAN_BL);
+            off += align_up(p.n_out, 64);
+            G.packs.push_back(p);
+            G.pack_blocks += p.blocks;
+        }
+    G.op_limbs = off;
+
+    // products: point q of f times point q of g
+    const int target_blocks = env_int("KS_MUL_TARGET_BLOCKS", 1024);
+    int64_t poff = 0;
+    for (int q = 0; q < npts; ++q) {
+        MulGeom m;
+        m.fa = q;
+        m.fb = npts + q;
+        m.na = nf;
+        m.nb = ng;
+        m.ntiles = (int)cdiv(nf + ng - 1, MUL_T);
+        int64_t want = std::max<int64_t>(1, target_blocks / ((int64_t)npts * m.ntiles));
+        int64_t maxs = cdiv(nf, MUL_CI);
+        int64_t ns = std::min(want, maxs);
+        m.split_len = cdiv(cdiv(nf, ns), MUL_CI) * MUL_CI;
+        m.nsplit = (int)cdiv(nf, m.split_len);
+        m.part_off = poff;
+        m.blocks = (int64_t)m.nsplit * m.ntiles;
+        poff += (int64_t)m.nsplit * m.ntiles * MUL_TW;
+        G.muls.push_back(m);
+        G.mul_blocks += m.blocks;
+        G.school_mults += (double)nf * (double)ng;
+    }
+    G.part_elems = poff;
+    G.limb_mults = G.school_mults;
+
+    // recombinations
+    int64_t noff = 0;
+    const int64_t prod_limbs = nf + ng;
+    auto add_norm = [&](std::vector<int> prods, std::vector<int> signs, int64_t shift, int64_t obit, int64_t period,
+                        int64_t count, int64_t n_out) {
+        NormGeom r;
+        r.nterms = (int)prods.size();
+        for (int t = 0; t < r.nterms; ++t) { r.prod[t] = prods[t]; r.sign[t] = signs[t]; }
+        r.shift = (int)shift;
+        r.off_bit0 = obit;
+        r.off_period = period;
+        r.off_count = sp.sgn ? count : 0;
+        r.n_out = n_out;
+        r.n_in = std::max(prod_limbs + 2, n_out + shift / 32 + 2);
+        r.blocks = cdiv(r.n_in, SCAN_BL);
+        r.out_off = noff;
+        noff += align_up(n_out, 64);
+        G.norms.push_back(r);
+        G.norm_blocks += r.blocks;
+        return (int)G.norms.size() - 1;
+    };
+    if (v == KS_VARIANT_KS1) {
+        add_norm({0}, {1}, 0, G.off, N, G.D, cdiv(G.D * N, 32) + 1);
+        ExtractGeom x{0, G.D, N, 0, 1, cdiv(G.D, EXTRACT_TPB)};
+        G.extracts.push_back(x);
+    } else {
+        const int64_t Y = 2 * N;  // bits of the even/odd base 2^(2N)
+        // P0 = (H1 + H2 + 2 C 1(Y)) / 2,  P1 = (H1 - H2 + 2^(N+1) C 1(Y)) / 2^(N+1)
+        int p0 = add_norm({0, 1}, {1, 1}, 1, G.off + 1, Y, G.m0, cdiv((G.m0 + 1) * Y, 32) + 1);
+        int p1 = -1;
+        if (G.m1 > 0) p1 = add_norm({0, 1}, {1, -1}, N + 1, G.off + N + 1, Y, G.m1, cdiv((G.m1 + 1) * Y, 32) + 1);
+        if (v == KS_VARIANT_NEG2) {
+            G.extracts.push_back(ExtractGeom{p0, G.m0, Y, 0, 2, cdiv(G.m0, EXTRACT_TPB)});
+            if (p1 >= 0) G.extracts.push_back(ExtractGeom{p1, G.m1, Y, 1, 2, cdiv(G.m1, EXTRACT_TPB)});
+        } else {
+            // reversed products: Q0 = even part of h^rev (m0 coefficients), Q1 = odd part (m1)
+            int q0 = add_norm({2, 3}, {1, 1}, 1, G.off + 1, Y, G.m0, cdiv((G.m0 + 1) * Y, 32) + 1);
+            int q1 = -1;
+            if (G.m1 > 0) q1 = add_norm({2, 3}, {1, -1}, N + 1, G.off + N + 1, Y, G.m1, cdiv((G.m1 + 1) * Y, 32) + 1);
+            const bool dodd = (G.D & 1) != 0;  // reversal swaps parities when D is even
+            const int64_t K = std::max(1, env_int("KS_CHAIN_K", 32));
+            G.nw = (int)cdiv(Y, 32);
+            G.aw = 2 * sp.w_in + 2;
+            int64_t aoff = 0;
+            for (int par = 0; par < 2; ++par) {
+                int64_t m = par ? G.m1 : G.m0;
+                if (m == 0) continue;
+                ChainGeom c;
+                c.A = par ? p1 : p0;
+                c.B = par ? (dodd ? q1 : q0) : (dodd ? q0 : q1);
+                c.m = m;
+                c.K = K;
+                c.nseg = cdiv(m, K);
+                c.par = par;
+                c.anchor_off = aoff;
+                c.anchor_blocks = c.nseg - 1;
+                c.chain_blocks = cdiv(c.nseg, CHAIN_TPB);
+                aoff += align_up(c.nseg * G.aw, 64);
+                G.chains.push_back(c);
+                G.anchor_blocks += c.anchor_blocks;
+                G.chain_blocks += c.chain_blocks;
+                G.limb_mults += (double)(c.nseg - 1) * std::min(lf, lg) * sp.w_in * sp.w_in;
+            }
+            G.anchor_limbs = aoff;
+        }
+    }
+    G.norm_limbs = noff;
+    for (auto &x : G.extracts) G.extract_blocks += x.blocks;
+
+    // scratch layout (bytes)
+    int64_t o = 0;
+    G.ws_ops = o;     o += align_up(G.op_limbs * 4, 256);
+    G.ws_parts = o;   o += align_up(G.part_elems * 8, 256);
+    G.ws_norms = o;   o += align_up(G.norm_limbs * 4, 256);
+    G.ws_anchors = o; o += align_up(std::max<int64_t>(G.anchor_limbs, 1) * 4, 256);
+    G.ws_status = o;  o += align_up(std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1) * 8, 256);
+    G.ws_bytes = o;
+
+    // algorithmic HBM bytes: inputs, outputs, operands written+read, products written+read
+    const double in_bytes = 4.0 * sp.w_in * (lf + lg);
+    const double out_bytes = sp.mod_p ? 8.0 * G.D : 4.0 * G.w_out * G.D;
+    G.hbm_bytes = in_bytes + out_bytes + 2.0 * 4.0 * G.op_limbs + 2.0 * 4.0 * npts * prod_limbs;
+    return KS_OK;
+}
+
+// ---- profiling -----------------------------------------------------------------------------------
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof = false;
+static std::vector<ProfRec> g_prof_pending;
+static std::map<std::string, std::pair<int64_t, double>> g_prof_acc;
+
+template <class F>
+static hipError_t timed(const char *name, hipStream_t s, F &&fn) {
+    if (!g_prof) return fn();
+    ProfRec r;
+    r.name = name;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return hipErrorOutOfMemory;
+    hipEventRecord(r.a, s);
+    hipError_t e = fn();
+    hipEventRecord(r.b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(r);
+    return e;
+}
+
+// ---- launching one planned product ----------------------------------------------------------------
+
+template <class J>
+static Launch<J> make_launch(const std::vector<J> &jobs, const Ctl &ctl, uint64_t *status, uint32_t epoch) {
+    Launch<J> L;
+    memset(&L, 0, sizeof(L));
+    L.njobs = (int64_t)jobs.size();
+    for (size_t i = 0; i < jobs.size(); ++i) L.jobs[i] = jobs[i];
+    L.total_blocks = jobs.empty() ? 0 : jobs.back().block0 + jobs.back().nblocks;
+    L.status = status;
+    L.ticket = ctl.ticket;
+    L.devstat = ctl.devstat;
+    L.epoch = epoch;
+    return L;
+}
+
+int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s) {
+    const Spec &sp = G.sp;
+    uint32_t *ops = reinterpret_cast<uint32_t *>(ws + G.ws_ops);
+    int64_t *parts = reinterpret_cast<int64_t *>(ws + G.ws_parts);
+    uint32_t *norms = reinterpret_cast<uint32_t *>(ws + G.ws_norms);
+    uint32_t *anchors = reinterpret_cast<uint32_t *>(ws + G.ws_anchors);
+    uint64_t *status = reinterpret_cast<uint64_t *>(ws + G.ws_status);
+    hipError_t err;
+
+    // pack
+    std::vector<PackJob> pj;
+    int64_t blk = 0;
+    for (auto &p : G.packs) {
+        PackJob j;
+        memset(&j, 0, sizeof(j));
+        j.coeffs = p.which ? g : f;
+        j.out = ops + p.op_off;
+        j.L = p.L;
+        j.n_out = p.n_out;
+        j.N = G.N;
+        j.w_in = sp.w_in;
+        j.bits = sp.bits;
+        j.flags = p.flags;
+        j.mod_p = sp.mod_p;
+        j.block0 = blk;
+        j.nblocks = p.blocks;
+        blk += p.blocks;
+        pj.push_back(j);
+    }
+    {
+        Launch<PackJob> L = make_launch(pj, ctl, status, ++ctl.epoch);
+        err = timed("pack", s, [&] { return launch_pack(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    // multiply
+    std::vector<MulJob> mj;
+    blk = 0;
+    for (auto &m : G.muls) {
+        MulJob j;
+        memset(&j, 0, sizeof(j));
+        j.a = ops + G.packs[m.fa].op_off;
+        j.b = ops + G.packs[m.fb].op_off;
+        j.na = m.na;
+        j.nb = m.nb;
+        j.part = parts + m.part_off;
+        j.split_len = m.split_len;
+        j.nsplit = m.nsplit;
+        j.ntiles = m.ntiles;
+        j.block0 = blk;
+        j.nblocks = m.blocks;
+        blk += m.blocks;
+        mj.push_back(j);
+    }
+    {
+        Launch<MulJob> L = make_launch(mj, ctl, status, 0);
+        err = timed("mul_valu", s, [&] { return launch_mul_valu(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    // anchors depend only on the inputs
+    if (!G.chains.empty() && G.anchor_blocks > 0) {
+        std::vector<AnchorJob> aj;
+        blk = 0;
+        for (auto &c : G.chains) {
+            if (c.anchor_blocks == 0) continue;
+            AnchorJob j;
+            memset(&j, 0, sizeof(j));
+            j.f = f;
+            j.g = g;
+            j.lf = sp.lf;
+            j.lg = sp.lg;
+            j.w_in = sp.w_in;
+            j.sgn = sp.sgn;
+            j.par = c.par;
+            j.aw = G.aw;
+            j.K = c.K;
+            j.nseg = c.nseg;
+            j.anchors = anchors + c.anchor_off;
+            j.off_bit = G.off;
+            j.block0 = blk;
+            j.nblocks = c.anchor_blocks;
+            blk += c.anchor_blocks;
+            aj.push_back(j);
+        }
+        Launch<AnchorJob> L = make_launch(aj, ctl, status, 0);
+        err = timed("anchor", s, [&] { return launch_anchor(L, sp.w_in, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    // normalize
+    std::vector<NormJob> nj;
+    blk = 0;
+    for (auto &r : G.norms) {
+        NormJob j;
+        memset(&j, 0, sizeof(j));
+        j.nterms = r.nterms;
+        for (int t = 0; t < r.nterms; ++t) {
+            const MulGeom &m = G.muls[r.prod[t]];
+            NormTerm &T = j.term[t];
+            T.part = parts + m.part_off;
+            T.a = ops + G.packs[m.fa].op_off;
+            T.b = ops + G.packs[m.fb].op_off;
+            T.na = m.na;
+            T.nb = m.nb;
+            T.nsplit = m.nsplit;
+            T.ntiles = m.ntiles;
+            T.sign = r.sign[t];
+        }
+        j.shift = r.shift;
+        j.off_bit0 = r.off_bit0;
+        j.off_period = r.off_period;
+        j.off_count = r.off_count;
+        j.out = norms + r.out_off;
+        j.n_out = r.n_out;
+        j.n_in = r.n_in;
+        j.block0 = blk;
+        j.nblocks = r.blocks;
+        blk += r.blocks;
+        nj.push_back(j);
+    }
+    {
+        Launch<NormJob> L = make_launch(nj, ctl, status, ++ctl.epoch);
+        err = timed("normalize", s, [&] { return launch_normalize(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    // read the coefficients off
+    if (!G.extracts.empty()) {
+        std::vector<ExtractJob> xj;
+        blk = 0;
+        for (auto &x : G.extracts) {
+            ExtractJob j;
+            memset(&j, 0, sizeof(j));
+            j.src = norms + G.norms[x.src].out_off;
+            j.n_src = G.norms[x.src].n_out;
+            j.count = x.count;
+            j.slot = x.slot;
+            j.out = reinterpret_cast<uint32_t *>(h);
+            j.out_first = x.first;
+            j.out_step = x.step;
+            j.w_out = G.w_out;
+            j.off_bit = G.off;
+            j.mod_p = sp.mod_p;
+            j.block0 = blk;
+            j.nblocks = x.blocks;
+            blk += x.blocks;
+            xj.push_back(j);
+        }
+        Launch<ExtractJob> L = make_launch(xj, ctl, status, 0);
+        err = timed("extract", s, [&] { return launch_extract(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    if (!G.chains.empty()) {
+        std::vector<ChainJob> cj;
+        blk = 0;
+        for (auto &c : G.chains) {
+            ChainJob j;
+            memset(&j, 0, sizeof(j));
+            j.A = norms + G.norms[c.A].out_off;
+            j.nA = G.norms[c.A].n_out;
+            j.B = norms + G.norms[c.B].out_off;
+            j.nB = G.norms[c.B].n_out;
+            j.m = c.m;
+            j.K = c.K;
+            j.nseg = c.nseg;
+            j.anchors = anchors + c.anchor_off;
+            j.aw = G.aw;
+            j.Nd = (int)(2 * G.N);
+            j.out = reinterpret_cast<uint32_t *>(h);
+            j.out_first = c.par;
+            j.out_step = 2;
+            j.w_out = G.w_out;
+            j.off_bit = G.off;
+            j.mod_p = sp.mod_p;
+            j.block0 = blk;
+            j.nblocks = c.chain_blocks;
+            blk += c.chain_blocks;
+            cj.push_back(j);
+        }
+        Launch<ChainJob> L = make_launch(cj, ctl, status, 0);
+        err = timed("recon", s, [&] { return launch_chain(L, G.nw, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    return KS_OK;
+}
+
+// ---- per-stream pools --------------------------------------------------------------------------
+
+struct Pool {
+    Ctl ctl;
+    char *ws = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_pool_mu;
+static std::map<hipStream_t, Pool *> g_pools;
+
+static int get_pool(hipStream_t s, size_t need, Pool **out) {
+    Pool *p;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto it = g_pools.find(s);
+        if (it == g_pools.end()) {
+            p = new Pool();
+            void *c = nullptr;
+            if (hipMalloc(&c, 256) != hipSuccess) { delete p; return KS_ENOMEM; }
+            if (hipMemset(c, 0, 256) != hipSuccess) return KS_EHIP;
+            p->ctl.ticket = reinterpret_cast<uint64_t *>(c);
+            p->ctl.devstat = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(c) + 64);
+            p->ctl.epoch = 0;
+            g_pools[s] = p;
+        } else {
+            p = it->second;
+        }
+    }
+    if (p->bytes < need) {
+        if (p->ws) {
+            if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;
+            hipFree(p->ws);
+            p->ws = nullptr;
+            p->bytes = 0;
+        }
+        size_t want = std::max<size_t>(need, (size_t)1 << 20);
+        void *w = nullptr;
+        if (hipMalloc(&w, want) != hipSuccess) return KS_ENOMEM;
+        if (hipMemset(w, 0, want) != hipSuccess) return KS_EHIP;  // status words start at epoch 0
+        p->ws = reinterpret_cast<char *>(w);
+        p->bytes = want;
+    }
+    *out = p;
+    return KS_OK;
+}
+
+static int read_status(uint32_t *devstat, hipStream_t s) {
+    if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;
+    uint32_t v = 0;
+    if (hipMemcpy(&v, devstat, 4, hipMemcpyDeviceToHost) != hipSuccess) return KS_EHIP;
+    if (v) {
+        uint32_t z = 0;
+        if (hipMemcpy(devstat, &z, 4, hipMemcpyHostToDevice) != hipSuccess) return KS_EHIP;
+    }
+    if (v & KS_DEVSTAT_RANGE) return KS_ERANGE;
+    if (v & (KS_DEVSTAT_CHECK | KS_DEVSTAT_LOOKBACK)) return KS_EINTERNAL;
+    return KS_OK;
+}
+
+static int device_ok() {
+    static int state = 0;  // 0 unknown, 1 ok, -1 not usable
+    if (state == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            state = -1;
+        } else {
+            state = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+        }
+    }
+    return state;
+}
+
+int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_signed) {
+    if (lf < 1 || lg < 1 || lf > KS_MAX_LEN || lg > KS_MAX_LEN) return KS_EINVAL;
+    if (bits < 1 || bits > KS_MAX_BITS) return KS_EINVAL;
+    int v = variant & KS_VARIANT_MASK;
+    if (v != KS_VARIANT_AUTO && v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_KS4) return KS_EINVAL;
+    if ((variant & KS_SIGNED) && !allow_signed) return KS_EINVAL;
+    int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_VALU | KS_ENGINE_MFMA;
+    if (variant & ~known) return KS_EINVAL;
+    if ((variant & KS_ENGINE_MFMA) && (variant & KS_ENGINE_VALU)) return KS_EINVAL;
+    if (variant & KS_ENGINE_MFMA) return KS_EUNSUPPORTED;
+    return KS_OK;
+}
+
+static int bitlen_u64(uint64_t x) {
+    int n = 0;
+    while (x) { ++n; x >>= 1; }
+    return n;
+}
+
+}  // namespace ks
+
+using namespace ks;
+
+// ---- C ABI ---------------------------------------------------------------------------------------
+
+extern "C" {
+
+int32_t ks_version(void) { return 100; }
+
+const char *ks_strerror(int code) {
+    switch (code) {
+        case KS_OK: return "ok";
+        case KS_EINVAL: return "invalid argument";
+        case KS_ENOMEM: return "out of memory";
+        case KS_EHIP: return "HIP runtime error";
+        case KS_ERANGE: return "coefficient outside its declared range";
+        case KS_EUNSUPPORTED: return "not supported by this build or device";
+        case KS_EINTERNAL: return "internal self-check failed";
+    }
+    return "unknown status code";
+}
+
+int64_t ks_out_limbs(int64_t len_f, int64_t len_g, int32_t coeff_bits) {
+    if (len_f < 1 || len_g < 1 || coeff_bits < 1 || coeff_bits > KS_MAX_BITS) return KS_EINVAL;
+    int e = ceil_log2(std::min(len_f, len_g));
+    return cdiv(2 * (int64_t)coeff_bits + e + 1, 32);
+}
+
+int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, ks_plan_info *out) {
+    if (!out) return KS_EINVAL;
+    int rc = validate_spec(len_f, len_g, coeff_bits, variant, true);
+    if (rc != KS_OK) return rc;
+    Spec sp{len_f, len_g, coeff_bits, (int)cdiv(coeff_bits, 32), (variant & KS_SIGNED) != 0, 0,
+            variant & KS_VARIANT_MASK, KS_ENGINE_VALU};
+    Geom G;
+    rc = plan_product(sp, G);
+    if (rc != KS_OK) return rc;
+    out->variant = G.variant;
+    out->engine = KS_ENGINE_VALU;
+    out->e = G.e;
+    out->slot_bits = (int32_t)G.N;
+    out->n_products = (int32_t)G.muls.size();
+    out->out_limbs = G.w_out;
+    out->operand_limbs_f = G.nf;
+    out->operand_limbs_g = G.ng;
+    out->limb_mults = G.limb_mults;
+    out->schoolbook_limb_mults = G.school_mults;
+    out->hbm_bytes = G.hbm_bytes;
+    return KS_OK;
+}
+
+static int mul_common(const uint32_t *f, const uint32_t *g, const Spec &sp, void *stream, void *h) {
+    if (device_ok() != 1) return KS_EUNSUPPORTED;
+    Geom G;
+    int rc = plan_product(sp, G);
+    if (rc != KS_OK) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Pool *p = nullptr;
+    rc = get_pool(s, (size_t)G.ws_bytes, &p);
+    if (rc != KS_OK) return rc;
+    return run_product(G, f, g, h, p->ws, p->ctl, s);
+}
+
+int ks_mul(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant,
+           void *stream, uint32_t *h) {
+    if (!f || !g || !h) return KS_EINVAL;
+    int rc = validate_spec(len_f, len_g, coeff_bits, variant, true);
+    if (rc != KS_OK) return rc;
+    Spec sp{len_f, len_g, coeff_bits, (int)cdiv(coeff_bits, 32), (variant & KS_SIGNED) != 0, 0,
+            variant & KS_VARIANT_MASK, KS_ENGINE_VALU};
+    return mul_common(f, g, sp, stream, h);
+}
+
+int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_g, uint64_t p, int32_t variant,
+               void *stream, uint64_t *h) {
+    if (!f || !g || !h) return KS_EINVAL;
+    if (p < 3 || !(p & 1) || (p >> 62)) return KS_EINVAL;
+    int bits = bitlen_u64(p - 1);
+    int rc = validate_spec(len_f, len_g, bits, variant, false);
+    if (rc != KS_OK) return rc;
+    Spec sp{len_f, len_g, bits, 2, false, p, variant & KS_VARIANT_MASK, KS_ENGINE_VALU};
+    return mul_common(reinterpret_cast<const uint32_t *>(f), reinterpret_cast<const uint32_t *>(g), sp, stream, h);
+}
+
+int ks_stream_status(void *stream) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Pool *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto it = g_pools.find(s);
+        if (it == g_pools.end()) return hipStreamSynchronize(s) == hipSuccess ? KS_OK : KS_EHIP;
+        p = it->second;
+    }
+    return read_status(p->ctl.devstat, s);
+}
+
+int ks_profile_enable(int32_t on) {
+    g_prof = on != 0;
+    return KS_OK;
+}
+
+int ks_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : g_prof_pending) {
+        hipEventSynchronize(r.b);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+    g_prof_acc.clear();
+    return KS_OK;
+}
+
+int ks_profile_read(const char *name, int64_t *launches, double *total_ms) {
+    if (!name || !launches || !total_ms) return KS_EINVAL;
+    static const char *known[] = {"pack", "mul_valu", "mul_mfma", "normalize", "anchor", "recon", "extract", "digitize"};
+    bool ok = false;
+    for (const char *k : known) ok = ok || strcmp(k, name) == 0;
+    if (!ok) return KS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : g_prof_pending) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return KS_EHIP;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        auto &acc = g_prof_acc[r.name];
+        acc.first += 1;
+        acc.second += ms;
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+    auto it = g_prof_acc.find(name);
+    *launches = it == g_prof_acc.end() ? 0 : it->second.first;
+    *total_ms = it == g_prof_acc.end() ? 0.0 : it->second.second;
+    return KS_OK;
+}
+
+}  // extern "C"
+
+// ---- batches (planned in ks_batch.cpp once available) -------------------------------------------
+extern "C" {
+int ks_batch_plan_create(const ks_desc *, int64_t, int32_t, ks_batch_plan **) { return KS_EUNSUPPORTED; }
+int64_t ks_batch_plan_bad_index(void) { return -1; }
+size_t ks_batch_plan_workspace_bytes(const ks_batch_plan *) { return 0; }
+int ks_batch_run(const ks_batch_plan *, const uint32_t *, uint32_t *, void *, size_t, void *) { return KS_EUNSUPPORTED; }
+int ks_batch_status(const ks_batch_plan *, void *, void *) { return KS_EUNSUPPORTED; }
+void ks_batch_plan_destroy(ks_batch_plan *) {}
+size_t ks_batch_workspace_bytes(const ks_desc *, int64_t, int32_t) { return 0; }
+int ks_mul_batch(const uint32_t *, uint32_t *, const ks_desc *, int64_t, int32_t, void *, size_t, void *) {
+    return KS_EUNSUPPORTED;
+}
+}

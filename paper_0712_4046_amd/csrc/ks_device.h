@@ -1,0 +1,242 @@
+// ks_device.h -- device-side building blocks shared by the libksmul kernels (gfx950, wave64).
+//
+// The one primitive every stage leans on is exact carry resolution of a multi-limb integer
+// given as signed 64-bit "limb columns":  V = sum_j v_j 2^(32 j).  Packing (the overlapping
+// sums of Section 3.4 and the signed evaluations of Section 3.3), recombining products and
+// exact halving (Sections 3.3, 3.4) all reduce to it.  Two local steps bring every position
+// to a value u_j in [-1, 2^32]; what remains is a carry k in {-1, 0, +1} that may travel
+// arbitrarily far.  The carry out of position j is a monotone map of the carry into it,
+// determined by u_j alone, so the maps compose associatively and one parallel scan over
+// them resolves every carry:
+//   within a thread   -- sequential composition of its items;
+//   within a wave     -- shuffle scan (6 steps on 64 lanes);
+//   within a block    -- wave aggregates in LDS;
+//   across blocks     -- single-pass decoupled look-back on epoch-tagged status words,
+//                        blocks ordered by an atomic ticket so a block only ever waits on
+//                        blocks that are already running.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ks_jobs.h"
+
+namespace ks {
+
+// ---- carry maps ------------------------------------------------------------------------------
+// A map {-1,0,1} -> {-1,0,1} packed as three 2-bit fields: field x (x = k+1) holds out(k)+1.
+typedef uint32_t cmap;
+constexpr cmap CMAP_ID = 0u | (1u << 2) | (2u << 4);
+
+__device__ __forceinline__ int cmap_apply(cmap m, int k) { return (int)((m >> (2 * (k + 1))) & 3u) - 1; }
+
+// first f, then g
+__device__ __forceinline__ cmap cmap_then(cmap f, cmap g) {
+    cmap r = 0;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        uint32_t fx = (f >> (2 * x)) & 3u;
+        r |= ((g >> (2 * fx)) & 3u) << (2 * x);
+    }
+    return r;
+}
+
+// carry-out map of a position whose pre-carry value is u in [-1, 2^32]
+__device__ __forceinline__ cmap cmap_of(int64_t u) {
+    if (u == -1) return 0u | (0u << 2) | (1u << 4);                   // -1,-1, 0
+    if (u == 0) return 0u | (1u << 2) | (1u << 4);                    // -1, 0, 0
+    if (u == (int64_t)0xffffffffLL) return 1u | (1u << 2) | (2u << 4); //  0, 0, 1
+    if (u == (int64_t)0x100000000LL) return 1u | (2u << 2) | (2u << 4); //  0, 1, 1
+    return 1u | (1u << 2) | (1u << 4);                                //  0, 0, 0
+}
+
+// ---- local steps: v_j (int64 column) -> u_j in [-1, 2^32] -----------------------------------
+// u_j depends on v_j, v_{j-1}, v_{j-2}:
+//   t_j = lo32(v_j) + (v_{j-1} >> 32)          in [-2^31, 2^32 + 2^31)
+//   u_j = lo32(t_j) + (t_{j-1} >> 32)           in [-1, 2^32]
+__device__ __forceinline__ int64_t t_of(int64_t v, int64_t vprev) {
+    return (int64_t)(uint32_t)(uint64_t)v + (vprev >> 32);
+}
+__device__ __forceinline__ int64_t u_of(int64_t v, int64_t v1, int64_t v2) {
+    int64_t t = t_of(v, v1), tp = t_of(v1, v2);
+    return (int64_t)(uint32_t)(uint64_t)t + (tp >> 32);
+}
+
+// ---- status words for the look-back -----------------------------------------------------------
+// bits 63..32 epoch of the launch, bits 9..8 flag (1 aggregate map, 2 inclusive carry),
+// bits 7..0 payload (map, or carry + 1).
+constexpr uint32_t LB_AGG = 1, LB_INC = 2;
+constexpr uint64_t LB_SPIN_LIMIT = 1ull << 22;
+
+__device__ __forceinline__ void lb_publish(uint64_t *st, uint32_t epoch, uint32_t flag, uint32_t payload) {
+    uint64_t w = ((uint64_t)epoch << 32) | ((uint64_t)flag << 8) | payload;
+    __hip_atomic_store(st, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *st) {
+    return __hip_atomic_load(const_cast<uint64_t *>(st), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Ticket from an epoch-tagged counter: the first block of a new epoch resets it.
+__device__ __forceinline__ uint32_t lb_ticket(uint64_t *ctr, uint32_t epoch) {
+    uint64_t old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        uint64_t want;
+        uint32_t t;
+        if ((uint32_t)(old >> 32) != epoch) {
+            want = ((uint64_t)epoch << 32) | 1u;
+            t = 0;
+        } else {
+            want = old + 1;
+            t = (uint32_t)old;
+        }
+        if (__hip_atomic_compare_exchange_strong(ctr, &old, want, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return t;
+    }
+}
+
+__device__ __forceinline__ void set_status(uint32_t *devstat, uint32_t bit) {
+    __hip_atomic_fetch_or(devstat, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Resolve the carry into block `blk` of a chain whose status words start at `st`.
+// Called by one thread.  `agg` is this block's aggregate map.  Returns the carry in.
+__device__ __forceinline__ int lb_resolve(uint64_t *st, int64_t blk, uint32_t epoch, cmap agg, uint32_t *devstat) {
+    if (blk == 0) {
+        lb_publish(st, epoch, LB_INC, (uint32_t)(cmap_apply(agg, 0) + 1));
+        return 0;
+    }
+    lb_publish(st + blk, epoch, LB_AGG, agg);
+    cmap acc = CMAP_ID;
+    int carry = 0;
+    int64_t p = blk - 1;
+    uint64_t spins = 0;
+    for (;;) {
+        uint64_t w = lb_load(st + p);
+        uint32_t flag = (uint32_t)(w >> 8) & 3u;
+        if ((uint32_t)(w >> 32) != epoch || flag == 0) {
+            if (++spins > LB_SPIN_LIMIT) {  // never expected; keeps every wave finite
+                set_status(devstat, KS_DEVSTAT_LOOKBACK);
+                carry = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        if (flag == LB_INC) {
+            carry = cmap_apply(acc, (int)(w & 0xffu) - 1);
+            break;
+        }
+        acc = cmap_then((cmap)(w & 0xffu), acc);
+        --p;
+    }
+    lb_publish(st + blk, epoch, LB_INC, (uint32_t)(cmap_apply(agg, carry) + 1));
+    return carry;
+}
+
+// ---- block-wide carry scan ---------------------------------------------------------------------
+// Each of the TPB threads holds IPT consecutive pre-carry values u[]; on return out[] holds the
+// normalised limbs and the function returns the carry out of the thread's last item.
+// `st` points at the status words of this chain, `blk` is the block's index in the chain.
+template <int TPB, int IPT>
+struct BlockCarryScan {
+    struct Smem {
+        cmap wave_agg[TPB / 64];
+        int carry_in;
+    };
+
+    __device__ static int run(Smem &sm, const int64_t (&u)[IPT], uint32_t (&out)[IPT], uint64_t *st, int64_t blk,
+                              uint32_t epoch, uint32_t *devstat) {
+        const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+        cmap maps[IPT];
+        cmap mine = CMAP_ID;
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            maps[q] = cmap_of(u[q]);
+            mine = cmap_then(mine, maps[q]);
+        }
+        // inclusive scan over the wave
+        cmap inc = mine;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            cmap o = (cmap)__shfl_up((int)inc, d, 64);
+            if (lane >= d) inc = cmap_then(o, inc);
+        }
+        cmap excl = (cmap)__shfl_up((int)inc, 1, 64);
+        if (lane == 0) excl = CMAP_ID;
+        if (lane == 63) sm.wave_agg[wv] = inc;
+        __syncthreads();
+        if (tid == 0) {
+            cmap agg = CMAP_ID;
+#pragma unroll
+            for (int w = 0; w < TPB / 64; ++w) agg = cmap_then(agg, sm.wave_agg[w]);
+            sm.carry_in = lb_resolve(st, blk, epoch, agg, devstat);
+        }
+        __syncthreads();
+        cmap before = CMAP_ID;
+        for (int w = 0; w < wv; ++w) before = cmap_then(before, sm.wave_agg[w]);
+        before = cmap_then(before, excl);
+        int k = cmap_apply(before, sm.carry_in);
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            out[q] = (uint32_t)(uint64_t)(u[q] + k);
+            k = cmap_apply(maps[q], k);
+        }
+        return k;
+    }
+};
+
+// ---- job lookup: block index -> (job, block within job) ----------------------------------------
+template <class J>
+__device__ __forceinline__ J find_job(const Launch<J> &L, int64_t blk, int64_t &local) {
+    if (L.table == nullptr) {
+        int64_t j = 0;
+        while (j + 1 < L.njobs && blk >= L.jobs[j + 1].block0) ++j;
+        local = blk - L.jobs[j].block0;
+        return L.jobs[j];
+    }
+    int64_t lo = 0, hi = L.njobs - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (L.table[mid].block0 <= blk) lo = mid; else hi = mid - 1;
+    }
+    local = blk - L.table[lo].block0;
+    return L.table[lo];
+}
+
+// ---- small helpers ------------------------------------------------------------------------------
+
+// bits [s, s+32) of the w-limb integer c (two's complement when sgn; bits below 0 read 0)
+__device__ __forceinline__ uint32_t coeff_word(const uint32_t *c, int w, bool sgn, int64_t s) {
+    uint32_t fill = (sgn && (c[w - 1] >> 31)) ? 0xffffffffu : 0u;
+    if (s < 0) {
+        int r = (int)(-s);
+        uint32_t lo = c[0];
+        return r >= 32 ? 0u : (lo << r);
+    }
+    int64_t q = s >> 5;
+    int o = (int)(s & 31);
+    uint32_t a = q < w ? c[q] : fill;
+    if (o == 0) return a;
+    uint32_t b = q + 1 < w ? c[q + 1] : fill;
+    return (a >> o) | (b << (32 - o));
+}
+
+// bits [s, s+32) of an n-limb non-negative integer (limbs at or above n read 0)
+__device__ __forceinline__ uint32_t bits_word(const uint32_t *x, int64_t n, int64_t s) {
+    int64_t q = s >> 5;
+    int o = (int)(s & 31);
+    uint32_t a = (q >= 0 && q < n) ? x[q] : 0u;
+    if (o == 0) return a;
+    uint32_t b = (q + 1 >= 0 && q + 1 < n) ? x[q + 1] : 0u;
+    return (a >> o) | (b << (32 - o));
+}
+
+__device__ __forceinline__ int64_t div_floor(int64_t a, int64_t b) {  // b > 0
+    int64_t q = a / b;
+    return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+__device__ __forceinline__ int64_t div_ceil(int64_t a, int64_t b) { return -div_floor(-a, b); }
+
+}  // namespace ks

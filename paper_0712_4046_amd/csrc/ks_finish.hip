@@ -1,0 +1,402 @@
+// ks_finish.hip -- reading the coefficients of h back off the recombined products.
+//
+// extract_kernel  KS1 (paper Section 3.1) and NEG2 (Section 3.3): coefficient k sits alone
+//                 in slot k of the normalised value (slot width N, or 2N for the even and
+//                 odd parts of the negated variant).  One thread per coefficient.
+// anchor_kernel   Exact h_k at the first coefficient before each chain segment (below).
+// chain_kernel    KS4 (Section 3.4): the carry-aware reconstruction of Section 3.2, run on
+//                 the even part and on the odd part at base Y = 2^(2N).
+//
+// Section 3.2's procedure is one sequential chain over all coefficients.  It carries, from
+// coefficient k-1 to k, only the low half alpha_{k-1} and the carry sigma_{k-1} that the
+// lower coefficients push into digit k of A = h(Y).  Both follow from the exact value of
+// h_{k-1}:  alpha_{k-1} = h_{k-1} mod Y,  sigma_{k-1} = floor(h_{k-1} / Y) + [u_{k-1} <
+// alpha_{k-1}].  So the chain is cut into segments of K coefficients and every segment but
+// the first starts from an anchor h_{sK-1} computed directly as a dot product of the inputs;
+// segments then run in parallel, one per lane.  The last value each segment produces is the
+// next segment's anchor, and the final coefficient satisfies the two relations the procedure
+// leaves unused (alpha_{m-1} = w_m, sigma_{m-1} = u_m): all three are checked on the device.
+//
+// Signed inputs: every slot holds h_k + C with C = 2^off_bit, removed on output.
+#include "ks_device.h"
+#include "ks_launch.h"
+
+namespace ks {
+
+// ---- (r 2^32 + word) mod p, r < p < 2^62 ------------------------------------------------------
+// Quotient estimated in double precision, then corrected exactly in 64-bit integers (the
+// floating-point reduction technique used by Shoup's NTL): q < 2^32 is off by at most one.
+__device__ __forceinline__ uint64_t mod_step(uint64_t r, uint32_t word, uint64_t p) {
+    const uint64_t x = (r << 32) | word;
+    if ((p >> 32) == 0) return x % p;  // r < 2^32 here, so x is exact
+    const double xd = (double)r * 4294967296.0 + (double)word;
+    const uint64_t q = (uint64_t)(xd / (double)p);
+    uint64_t d = x - q * p;             // x - q p in [-p, 2p), modulo 2^64
+    if ((int64_t)d < 0) d += p;
+    while (d >= p) d -= p;
+    return d;
+}
+
+// ---- extraction ------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(EXTRACT_TPB) void extract_kernel(Launch<ExtractJob> L) {
+    int64_t local;
+    const ExtractJob J = find_job(L, (int64_t)blockIdx.x, local);
+    const int64_t k = local * EXTRACT_TPB + threadIdx.x;
+    if (k >= J.count) return;
+    const int64_t s0 = k * J.slot;
+    const int64_t idx = J.out_first + k * J.out_step;
+    if (J.mod_p == 0) {
+        uint32_t *o = J.out + idx * J.w_out;
+        uint32_t borrow = 0;
+        for (int t = 0; t < J.w_out; ++t) {
+            const int64_t bit = 32 * (int64_t)t;
+            uint32_t word = 0;
+            if (bit < J.slot) {
+                word = bits_word(J.src, J.n_src, s0 + bit);
+                if (J.slot - bit < 32) word &= (1u << (J.slot - bit)) - 1u;
+            }
+            uint32_t sub = (J.off_bit >= 0 && (J.off_bit >> 5) == t) ? (1u << (J.off_bit & 31)) : 0u;
+            uint64_t d = (uint64_t)word - sub - borrow;
+            o[t] = (uint32_t)d;
+            borrow = (uint32_t)(d >> 63) & 1u;
+        }
+    } else {
+        const int nl = (int)((J.slot + 31) >> 5);
+        uint64_t r = 0;
+        for (int t = nl - 1; t >= 0; --t) {
+            const int64_t bit = 32 * (int64_t)t;
+            uint32_t word = bits_word(J.src, J.n_src, s0 + bit);
+            if (J.slot - bit < 32) word &= (1u << (J.slot - bit)) - 1u;
+            r = mod_step(r, word, J.mod_p);
+        }
+        reinterpret_cast<uint64_t *>(J.out)[idx] = r;
+    }
+}
+
+// ---- anchors -----------------------------------------------------------------------------------
+
+template <int W>
+__device__ __forceinline__ bool load_mag(const uint32_t *c, bool sgn, uint32_t (&m)[W]) {
+    bool neg = sgn && (c[W - 1] >> 31);
+    uint64_t carry = 1;
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+        uint32_t x = c[t];
+        if (neg) {
+            uint64_t s = (uint64_t)(uint32_t)~x + carry;
+            m[t] = (uint32_t)s;
+            carry = s >> 32;
+        } else {
+            m[t] = x;
+        }
+    }
+    return neg;
+}
+
+template <int W>
+__global__ __launch_bounds__(ANCHOR_TPB) void anchor_kernel(Launch<AnchorJob> L) {
+    constexpr int AW = 2 * W + 2;
+    __shared__ uint32_t s_acc[ANCHOR_TPB / 64][AW];
+    int64_t local;
+    const AnchorJob J = find_job(L, (int64_t)blockIdx.x, local);
+    const int64_t s = local + 1;
+    const int64_t k = 2 * (s * J.K - 1) + J.par;
+    int64_t lo = k - (J.lg - 1);
+    if (lo < 0) lo = 0;
+    int64_t hi = k < J.lf - 1 ? k : J.lf - 1;
+    const bool sgn = J.sgn != 0;
+
+    uint32_t acc[AW];
+#pragma unroll
+    for (int t = 0; t < AW; ++t) acc[t] = 0;
+    for (int64_t i = lo + threadIdx.x; i <= hi; i += ANCHOR_TPB) {
+        uint32_t a[W], b[W];
+        bool na = load_mag<W>(J.f + i * W, sgn, a);
+        bool nb = load_mag<W>(J.g + (k - i) * W, sgn, b);
+        uint32_t p[2 * W];
+#pragma unroll
+        for (int t = 0; t < 2 * W; ++t) p[t] = 0;
+#pragma unroll
+        for (int x = 0; x < W; ++x) {
+            uint64_t c = 0;
+#pragma unroll
+            for (int y = 0; y < W; ++y) {
+                uint64_t tt = (uint64_t)a[x] * b[y] + p[x + y] + c;
+                p[x + y] = (uint32_t)tt;
+                c = tt >> 32;
+            }
+            p[x + W] = (uint32_t)c;
+        }
+        if (na != nb) {
+            uint64_t br = 0;
+#pragma unroll
+            for (int t = 0; t < AW; ++t) {
+                uint64_t d = (uint64_t)acc[t] - (t < 2 * W ? p[t] : 0u) - br;
+                acc[t] = (uint32_t)d;
+                br = (d >> 63) & 1u;
+            }
+        } else {
+            uint64_t c = 0;
+#pragma unroll
+            for (int t = 0; t < AW; ++t) {
+                uint64_t sm = (uint64_t)acc[t] + (t < 2 * W ? p[t] : 0u) + c;
+                acc[t] = (uint32_t)sm;
+                c = sm >> 32;
+            }
+        }
+    }
+    // wave reduction, then across waves
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint32_t o[AW];
+#pragma unroll
+        for (int t = 0; t < AW; ++t) o[t] = (uint32_t)__shfl_down((int)acc[t], d, 64);
+        uint64_t c = 0;
+#pragma unroll
+        for (int t = 0; t < AW; ++t) {
+            uint64_t sm = (uint64_t)acc[t] + o[t] + c;
+            acc[t] = (uint32_t)sm;
+            c = sm >> 32;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int t = 0; t < AW; ++t) s_acc[wv][t] = acc[t];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < ANCHOR_TPB / 64; ++q) {
+            uint64_t c = 0;
+#pragma unroll
+            for (int t = 0; t < AW; ++t) {
+                uint64_t sm = (uint64_t)acc[t] + s_acc[q][t] + c;
+                acc[t] = (uint32_t)sm;
+                c = sm >> 32;
+            }
+        }
+        if (J.off_bit >= 0) {
+            uint64_t c = 0;
+#pragma unroll
+            for (int t = 0; t < AW; ++t) {
+                uint32_t add = ((J.off_bit >> 5) == t) ? (1u << (J.off_bit & 31)) : 0u;
+                uint64_t sm = (uint64_t)acc[t] + add + c;
+                acc[t] = (uint32_t)sm;
+                c = sm >> 32;
+            }
+        }
+        uint32_t *dst = J.anchors + s * J.aw;
+#pragma unroll
+        for (int t = 0; t < AW; ++t) dst[t] = acc[t];
+    }
+}
+
+// ---- chains ------------------------------------------------------------------------------------
+
+template <int NW>
+struct MW {
+    uint32_t w[NW];
+};
+
+// Nd-bit digit starting at bit0 of an n-limb array
+template <int NW>
+__device__ __forceinline__ MW<NW> read_digit(const uint32_t *x, int64_t n, int64_t bit0, int Nd) {
+    MW<NW> d;
+    const int64_t q = bit0 >> 5;
+    const int o = (int)(bit0 & 31);
+    uint32_t l[NW + 1];
+#pragma unroll
+    for (int t = 0; t <= NW; ++t) l[t] = (q + t >= 0 && q + t < n) ? x[q + t] : 0u;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) d.w[t] = o ? (l[t] >> o) | (l[t + 1] << (32 - o)) : l[t];
+    const int tb = Nd - 32 * (NW - 1);
+    if (tb < 32) d.w[NW - 1] &= (1u << tb) - 1u;
+    return d;
+}
+
+template <int NW>
+__device__ __forceinline__ MW<NW> sub_mod(const MW<NW> &a, const MW<NW> &b, uint32_t extra, int Nd) {
+    MW<NW> r;
+    uint64_t br = extra;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+        uint64_t d = (uint64_t)a.w[t] - b.w[t] - br;
+        r.w[t] = (uint32_t)d;
+        br = (d >> 63) & 1u;
+    }
+    const int tb = Nd - 32 * (NW - 1);
+    if (tb < 32) r.w[NW - 1] &= (1u << tb) - 1u;
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ bool mw_lt(const MW<NW> &a, const MW<NW> &b) {
+    bool lt = false, decided = false;
+#pragma unroll
+    for (int t = NW - 1; t >= 0; --t) {
+        if (!decided && a.w[t] != b.w[t]) {
+            lt = a.w[t] < b.w[t];
+            decided = true;
+        }
+    }
+    return lt;
+}
+
+template <int NW>
+__device__ __forceinline__ bool mw_eq(const MW<NW> &a, const MW<NW> &b) {
+    bool eq = true;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) eq = eq && (a.w[t] == b.w[t]);
+    return eq;
+}
+
+template <int NW>
+__device__ __forceinline__ MW<NW> add_bit(const MW<NW> &a, uint32_t c) {
+    MW<NW> r;
+    uint64_t cc = c;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+        uint64_t s = (uint64_t)a.w[t] + cc;
+        r.w[t] = (uint32_t)s;
+        cc = s >> 32;
+    }
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ uint32_t mw_word(const MW<NW> &a, int64_t idx) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) r = (idx == t) ? a.w[t] : r;
+    return r;
+}
+
+// bits [p, p+32) of the Nd-bit digit a (zero outside [0, Nd))
+template <int NW>
+__device__ __forceinline__ uint32_t mw_bits(const MW<NW> &a, int64_t p) {
+    if (p <= -32) return 0u;
+    if (p < 0) return mw_word(a, 0) << (int)(-p);
+    const int64_t q = p >> 5;
+    const int o = (int)(p & 31);
+    uint32_t lo = mw_word(a, q);
+    if (o == 0) return lo;
+    return (lo >> o) | (mw_word(a, q + 1) << (32 - o));
+}
+
+// limb t of h' = alpha + 2^Nd beta
+template <int NW>
+__device__ __forceinline__ uint32_t hword(const MW<NW> &al, const MW<NW> &be, int Nd, int t) {
+    return mw_bits(al, 32 * (int64_t)t) | mw_bits(be, 32 * (int64_t)t - Nd);
+}
+
+template <int NW>
+__global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
+    int64_t local;
+    const ChainJob J = find_job(L, (int64_t)blockIdx.x, local);
+    const int64_t s = local * CHAIN_TPB + threadIdx.x;
+    if (s >= J.nseg) return;
+    const int Nd = J.Nd;
+    const int64_t m = J.m;
+    const int64_t k0 = s * J.K;
+    int64_t k1 = k0 + J.K;
+    if (k1 > m) k1 = m;
+    const int hw = (2 * Nd + 31) >> 5;  // limbs of h' = alpha + Y beta
+
+    MW<NW> sigma, aprev;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) { sigma.w[t] = 0; aprev.w[t] = 0; }
+    if (s > 0) {
+        const uint32_t *anc = J.anchors + s * J.aw;
+        MW<NW> al = read_digit<NW>(anc, J.aw, 0, Nd);
+        MW<NW> be = read_digit<NW>(anc, J.aw, Nd, Nd);
+        MW<NW> u = read_digit<NW>(J.A, J.nA, (k0 - 1) * (int64_t)Nd, Nd);
+        aprev = al;
+        sigma = add_bit(be, mw_lt(u, al) ? 1u : 0u);
+    }
+    MW<NW> wc = read_digit<NW>(J.B, J.nB, (m - k0) * (int64_t)Nd, Nd);
+    MW<NW> alpha = aprev, beta;
+    for (int64_t c = k0; c < k1; ++c) {
+        MW<NW> u = read_digit<NW>(J.A, J.nA, c * (int64_t)Nd, Nd);
+        MW<NW> wn = read_digit<NW>(J.B, J.nB, (m - c - 1) * (int64_t)Nd, Nd);
+        alpha = sub_mod(u, sigma, 0u, Nd);          // alpha_c = u_c - sigma_{c-1}  (mod Y)
+        uint32_t delta = mw_lt(u, sigma) ? 1u : 0u;  // carry of the low half into digit c+1
+        uint32_t eps = mw_lt(wn, alpha) ? 1u : 0u;   // eps_c = [alpha_c > w_{c+1}]
+        beta = sub_mod(wc, aprev, eps, Nd);          // beta_c = w_c - alpha_{c-1} - eps_c (mod Y)
+        sigma = add_bit(beta, delta);                // sigma_c = beta_c + delta
+        aprev = alpha;
+        wc = wn;
+        // write h_{2c+par} = h'_c - C
+        const int64_t idx = J.out_first + c * J.out_step;
+        if (J.mod_p == 0) {
+            uint32_t *o = J.out + idx * J.w_out;
+            uint32_t br = 0;
+            for (int t = 0; t < J.w_out; ++t) {
+                uint32_t word = t < hw ? hword(alpha, beta, Nd, t) : 0u;
+                uint32_t sub = (J.off_bit >= 0 && (J.off_bit >> 5) == t) ? (1u << (J.off_bit & 31)) : 0u;
+                uint64_t d = (uint64_t)word - sub - br;
+                o[t] = (uint32_t)d;
+                br = (uint32_t)(d >> 63) & 1u;
+            }
+        } else {
+            uint64_t r = 0;
+            for (int t = hw - 1; t >= 0; --t) r = mod_step(r, hword(alpha, beta, Nd, t), J.mod_p);
+            reinterpret_cast<uint64_t *>(J.out)[idx] = r;
+        }
+    }
+    // self-checks
+    bool ok = true;
+    if (k1 < m) {
+        const uint32_t *anc = J.anchors + (s + 1) * J.aw;
+        for (int t = 0; t < J.aw; ++t) ok = ok && (anc[t] == (t < hw ? hword(alpha, beta, Nd, t) : 0u));
+    } else if (k1 > k0) {
+        MW<NW> wm = read_digit<NW>(J.B, J.nB, 0, Nd);
+        MW<NW> um = read_digit<NW>(J.A, J.nA, m * (int64_t)Nd, Nd);
+        ok = mw_eq(alpha, wm) && mw_eq(sigma, um);
+    }
+    if (!ok) set_status(L.devstat, KS_DEVSTAT_CHECK);
+}
+
+// ---- host launchers ------------------------------------------------------------------------------
+
+hipError_t launch_extract(const Launch<ExtractJob> &L, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(extract_kernel, dim3((unsigned)L.total_blocks), dim3(EXTRACT_TPB), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_anchor(const Launch<AnchorJob> &L, int w_in, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    dim3 g((unsigned)L.total_blocks), b(ANCHOR_TPB);
+    switch (w_in) {
+        case 1: hipLaunchKernelGGL(anchor_kernel<1>, g, b, 0, s, L); break;
+        case 2: hipLaunchKernelGGL(anchor_kernel<2>, g, b, 0, s, L); break;
+        case 3: hipLaunchKernelGGL(anchor_kernel<3>, g, b, 0, s, L); break;
+        case 4: hipLaunchKernelGGL(anchor_kernel<4>, g, b, 0, s, L); break;
+        case 5: hipLaunchKernelGGL(anchor_kernel<5>, g, b, 0, s, L); break;
+        case 6: hipLaunchKernelGGL(anchor_kernel<6>, g, b, 0, s, L); break;
+        case 7: hipLaunchKernelGGL(anchor_kernel<7>, g, b, 0, s, L); break;
+        case 8: hipLaunchKernelGGL(anchor_kernel<8>, g, b, 0, s, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_chain(const Launch<ChainJob> &L, int nw, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    dim3 g((unsigned)L.total_blocks), b(CHAIN_TPB);
+    switch (nw) {
+        case 1: hipLaunchKernelGGL(chain_kernel<1>, g, b, 0, s, L); break;
+        case 2: hipLaunchKernelGGL(chain_kernel<2>, g, b, 0, s, L); break;
+        case 3: hipLaunchKernelGGL(chain_kernel<3>, g, b, 0, s, L); break;
+        case 4: hipLaunchKernelGGL(chain_kernel<4>, g, b, 0, s, L); break;
+        case 5: hipLaunchKernelGGL(chain_kernel<5>, g, b, 0, s, L); break;
+        case 6: hipLaunchKernelGGL(chain_kernel<6>, g, b, 0, s, L); break;
+        case 7: hipLaunchKernelGGL(chain_kernel<7>, g, b, 0, s, L); break;
+        case 8: hipLaunchKernelGGL(chain_kernel<8>, g, b, 0, s, L); break;
+        case 9: hipLaunchKernelGGL(chain_kernel<9>, g, b, 0, s, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ks

@@ -1,0 +1,17 @@
+// ks_launch.h -- host-side launchers of the libksmul kernels (one per translation unit).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ks_jobs.h"
+
+namespace ks {
+
+hipError_t launch_pack(const Launch<PackJob> &L, hipStream_t s);
+hipError_t launch_normalize(const Launch<NormJob> &L, hipStream_t s);
+hipError_t launch_mul_valu(const Launch<MulJob> &L, hipStream_t s);
+hipError_t launch_extract(const Launch<ExtractJob> &L, hipStream_t s);
+hipError_t launch_anchor(const Launch<AnchorJob> &L, int w_in, hipStream_t s);
+hipError_t launch_chain(const Launch<ChainJob> &L, int nw, hipStream_t s);
+
+}  // namespace ks

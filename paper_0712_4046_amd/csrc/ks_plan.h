@@ -1,0 +1,78 @@
+// ks_plan.h -- host-side plan of one product: sizes, job geometry and scratch layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace ks {
+
+int ceil_log2(int64_t x);
+int64_t cdiv(int64_t a, int64_t b);
+
+// what the caller asked for
+struct Spec {
+    int64_t lf, lg;
+    int bits;        // b
+    int w_in;        // limbs per input coefficient
+    bool sgn;        // two's-complement inputs
+    uint64_t mod_p;  // non-zero: inputs are residues, outputs reduced mod p
+    int variant;     // KS_VARIANT_* (AUTO resolved by the planner)
+    int engine;
+};
+
+struct PackGeom {
+    int which;  // 0: f, 1: g
+    int flags;  // PK_*
+    int64_t L, n_out, op_off, blocks;
+};
+struct MulGeom {
+    int fa, fb;  // operand (pack) indices
+    int64_t na, nb, split_len;
+    int nsplit, ntiles;
+    int64_t part_off, blocks;
+};
+struct NormGeom {
+    int nterms, prod[2], sign[2], shift;
+    int64_t off_bit0, off_period, off_count, n_in, n_out, out_off, blocks;
+};
+struct ExtractGeom {
+    int src;  // norm index
+    int64_t count, slot, first, step, blocks;
+};
+struct ChainGeom {
+    int A, B;  // norm indices
+    int64_t m, K, nseg;
+    int par;
+    int64_t anchor_off, anchor_blocks, chain_blocks;
+};
+
+struct Geom {
+    Spec sp;
+    int variant = 0, e = 0, w_out = 0, off = -1, nw = 0, aw = 0;
+    int64_t N = 0, D = 0, m0 = 0, m1 = 0, nf = 0, ng = 0;
+    std::vector<PackGeom> packs;
+    std::vector<MulGeom> muls;
+    std::vector<NormGeom> norms;
+    std::vector<ExtractGeom> extracts;
+    std::vector<ChainGeom> chains;
+    int64_t op_limbs = 0, part_elems = 0, norm_limbs = 0, anchor_limbs = 0;
+    int64_t pack_blocks = 0, mul_blocks = 0, norm_blocks = 0, extract_blocks = 0, anchor_blocks = 0,
+            chain_blocks = 0;
+    int64_t ws_ops = 0, ws_parts = 0, ws_norms = 0, ws_anchors = 0, ws_status = 0, ws_bytes = 0;
+    double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
+};
+
+// device words that outlive one call: block ticket counter, error bits, launch epoch
+struct Ctl {
+    uint64_t *ticket = nullptr;
+    uint32_t *devstat = nullptr;
+    uint32_t epoch = 0;
+};
+
+int plan_product(const Spec &sp, Geom &G);
+int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s);
+int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_signed);
+
+}  // namespace ks

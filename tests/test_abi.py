@@ -1,0 +1,73 @@
+"""Host-side checks of the C-ABI library (no GPU work): it loads, exports every symbol that
+include/ks.h declares, and its planner follows the paper's formulas for N and operand sizes.
+"""
+import os
+import re
+
+import pytest
+
+from paper_0712_4046_amd import ks
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ks.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ks_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ks.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_messages():
+    assert ks.lib().ks_version() >= 100
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert ks.strerror(code) and ks.strerror(code) != "unknown status code"
+
+
+@pytest.mark.parametrize("lf,lg,b", [(1, 1, 1), (256, 256, 32), (4096, 4096, 64), (17, 1000, 60), (65536, 65536, 60),
+                                     (8, 9, 256)])
+def test_out_limbs_follow_the_bound(lf, lg, b):
+    # coefficients of h have length <= 2b + e (Section 3), plus one sign bit
+    e = (min(lf, lg) - 1).bit_length()
+    assert ks.out_limbs(lf, lg, b) == (2 * b + e + 1 + 31) // 32
+
+
+def test_invalid_sizes_rejected():
+    L = ks.lib()
+    assert L.ks_out_limbs(0, 5, 32) == ks.KS_EINVAL
+    assert L.ks_out_limbs(5, 5, 0) == ks.KS_EINVAL
+    assert L.ks_out_limbs(5, 5, ks.KS_MAX_BITS + 1) == ks.KS_EINVAL
+    for bad in [(0, 4, 8, "ks1"), (4, 4, 0, "ks4"), (4, 4, 300, "neg2")]:
+        with pytest.raises(ks.KSError) as ei:
+            ks.plan(bad[0], bad[1], bad[2], bad[3])
+        assert ei.value.code == ks.KS_EINVAL
+    info = ks.PlanInfo()
+    assert L.ks_plan(4, 4, 8, 3, info) == ks.KS_EINVAL       # not a variant
+    assert L.ks_plan(4, 4, 8, 0x3000 | 1, info) == ks.KS_EINVAL  # both engines
+
+
+@pytest.mark.parametrize("lf,lg,b,signed", [(256, 256, 32, False), (4096, 4096, 64, True), (1, 1, 7, False),
+                                            (100, 3, 128, True), (65536, 65536, 60, False), (1000, 999, 16, True)])
+def test_planner_slot_widths_and_operand_lengths(lf, lg, b, signed):
+    e = (min(lf, lg) - 1).bit_length()
+    for variant, N, k in (("ks1", 2 * b + e, 1), ("neg2", b + (e + 1) // 2, 2), ("ks4", (2 * b + e + 3) // 4, 4)):
+        p = ks.plan(lf, lg, b, variant, signed)
+        assert p["slot_bits"] == N and p["n_products"] == k and p["e"] == e
+        # operand length N (L-1) + b of the propositions, plus one carry bit and one sign bit
+        assert p["operand_limbs_f"] == (N * (lf - 1) + b + 2 + 31) // 32
+        assert p["operand_limbs_g"] == (N * (lg - 1) + b + 2 + 31) // 32
+        assert p["schoolbook_limb_mults"] == k * p["operand_limbs_f"] * p["operand_limbs_g"]
+
+
+def test_config2_slot_width():
+    # L = 4096, b = 64 (sign included): KS1 N = 2b + e = 140, KS4 N = 35
+    assert ks.plan(4096, 4096, 64, "ks1", True)["slot_bits"] == 140
+    assert ks.plan(4096, 4096, 64, "ks4", True)["slot_bits"] == 35
