@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark: exact dense products in Z[x] by multipoint Kronecker substitution on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config1]
+
+A step is one whole product f*g through the library's hot path (pack -> integer products ->
+carry resolution and halving -> reconstruction / read-off), with the inputs already in HBM.
+Workload (default): one product of two length-4096 polynomials with signed 64-bit
+coefficients drawn from seed 2 (the single-product configuration the paper's comparison is
+quoted on, at a size that fits one GPU).  The four-point variant (paper Section 3.4) is the
+reported value; the standard substitution (3.1) and the negated variant (3.3) are timed the
+same way for the speedup.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# vector-ALU peak for the limb multiplier: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# v_mad_u64_u32 (32x32+64 -> 64) every 4 cycles per lane (quarter rate) -> 9.83e12 limb-mults/s
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 4 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="config2", choices=["config1", "config2"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def time_variant(ks, torch, tf, tg, bits, variant, signed, steps, warmup, out):
+    for _ in range(warmup):
+        ks.mul(tf, tg, bits, variant, signed, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ks.mul(tf, tg, bits, variant, signed, out=out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "products shard by instance across GPUs, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_0712_4046_amd import ks
+    from paper_0712_4046_amd import workloads as wl
+
+    P = wl.config2() if args.workload == "config2" else wl.config1()
+    L, bits, signed = P.f.shape[0], P.bits, P.signed
+    tf, tg = ks.to_device(P.f), ks.to_device(P.g)
+    wo = ks.out_limbs(L, L, bits)
+    outs = {v: torch.empty((2 * L - 1, wo), dtype=torch.int32, device="cuda") for v in ("ks4", "ks1", "neg2")}
+
+    t = {}
+    for v in ("ks4", "ks1", "neg2"):
+        t[v] = time_variant(ks, torch, tf, tg, bits, v, signed, args.steps, args.warmup, outs[v])
+    rc = ks.status()
+    if rc != ks.KS_OK:
+        raise SystemExit(f"device status after timing: {ks.strerror(rc)}")
+
+    plans = {v: ks.plan(L, L, bits, v, signed) for v in ("ks4", "ks1", "neg2")}
+
+    # per-kernel durations on the library's own stream, HIP events around every launch
+    ks.profile_reset()
+    ks.profile_enable(True)
+    for _ in range(args.steps):
+        ks.mul(tf, tg, bits, "ks4", signed, out=outs["ks4"])
+    torch.cuda.synchronize()
+    ks.profile_enable(False)
+    kern = {}
+    for name in ("pack", "mul_valu", "normalize", "anchor", "recon", "extract"):
+        n, ms = ks.profile_read(name)
+        if n:
+            kern[name] = {"launches": n, "avg_us": 1000.0 * ms / n}
+    dom = max(kern, key=lambda k: kern[k]["avg_us"])
+    p4 = plans["ks4"]
+    if dom == "mul_valu":
+        ops = p4["schoolbook_limb_mults"]
+        achieved = ops / (kern[dom]["avg_us"] * 1e-6) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                "op": "32x32->64-bit limb multiply-accumulate", "ops_per_launch": ops}
+    else:
+        nbytes = p4["hbm_bytes"]
+        achieved = nbytes / (kern[dom]["avg_us"] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nbytes}
+
+    # bit-exact check of every variant against the oracle (also the CPU baseline sample)
+    cpu = None
+    exact = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        n = 0
+        exp = None
+        while True:
+            exp = O.mul_classical(P.f, P.g, signed, wo)
+            n += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": n / el, "unit": "products/s", "cores": O.threads(), "kind": "oracle",
+               "sample": f"{n} full products of the same workload (classical convolution, OpenMP over coefficients)"}
+        exact = all(np.array_equal(ks.to_host(outs[v]), exp) for v in outs)
+        if not exact:
+            raise SystemExit("GPU result differs from the oracle")
+
+    ms = t["ks4"] * 1000.0
+    rec = {
+        "metric": "polynomial products/s + limb-mults/s at 1 GPU; KS4 vs KS1 speedup, bit-exact",
+        "value": 1.0 / t["ks4"],
+        "unit": "products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: one Z[x] product, L={L}, {'signed' if signed else 'unsigned'} "
+                               f"{bits}-bit coefficients, four-point Kronecker substitution",
+                   "len": L, "coeff_bits": bits, "signed": signed, "variant": "ks4"},
+        "limb_mults_per_s": p4["limb_mults"] / t["ks4"],
+        "schoolbook_limb_mults_per_s": p4["schoolbook_limb_mults"] / t["ks4"],
+        "variants_ms": {v: t[v] * 1000.0 for v in t},
+        "variants_products_per_s": {v: 1.0 / t[v] for v in t},
+        "speedup_ks4_vs_ks1": t["ks1"] / t["ks4"],
+        "speedup_neg2_vs_ks1": t["ks1"] / t["neg2"],
+        "bit_exact": exact,
+        "kernels_us": kern,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -109,28 +110,22 @@ int plan_product(const Spec &sp, Geom &G) {
     G.op_limbs = off;
 
     // products: point q of f times point q of g
-    const int target_blocks = env_int("KS_MUL_TARGET_BLOCKS", 1024);
-    int64_t poff = 0;
+    int64_t coff = 0;
     for (int q = 0; q < npts; ++q) {
         MulGeom m;
         m.fa = q;
         m.fb = npts + q;
         m.na = nf;
         m.nb = ng;
-        m.ntiles = (int)cdiv(nf + ng - 1, MUL_T);
-        int64_t want = std::max<int64_t>(1, target_blocks / ((int64_t)npts * m.ntiles));
-        int64_t maxs = cdiv(nf, MUL_CI);
-        int64_t ns = std::min(want, maxs);
-        m.split_len = cdiv(cdiv(nf, ns), MUL_CI) * MUL_CI;
-        m.nsplit = (int)cdiv(nf, m.split_len);
-        m.part_off = poff;
-        m.blocks = (int64_t)m.nsplit * m.ntiles;
-        poff += (int64_t)m.nsplit * m.ntiles * MUL_TW;
+        m.ntiles = cdiv(nf + ng - 1, MUL_T);
+        m.cols_off = coff;
+        m.blocks = m.ntiles;
+        coff += align_up(3 * m.ntiles * MUL_T, 64);
         G.muls.push_back(m);
         G.mul_blocks += m.blocks;
         G.school_mults += (double)nf * (double)ng;
     }
-    G.part_elems = poff;
+    G.col_words = coff;
     G.limb_mults = G.school_mults;
 
     // recombinations
@@ -173,7 +168,14 @@ int plan_product(const Spec &sp, Geom &G) {
             int q1 = -1;
             if (G.m1 > 0) q1 = add_norm({2, 3}, {1, -1}, N + 1, G.off + N + 1, Y, G.m1, cdiv((G.m1 + 1) * Y, 32) + 1);
             const bool dodd = (G.D & 1) != 0;  // reversal swaps parities when D is even
-            const int64_t K = std::max(1, env_int("KS_CHAIN_K", 32));
+            // segment length K: every segment but the first costs one anchor (a dot product of
+            // min(lf, lg) coefficient products, spread over the GPU), and a segment's lane runs K
+            // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement)
+            const double Lm = (double)std::min(lf, lg);
+            int64_t K = (int64_t)(std::sqrt((double)G.D * Lm * sp.w_in * sp.w_in / 2.0e6) + 0.5);
+            K = std::max<int64_t>(4, std::min<int64_t>(K, 512));
+            K = env_int("KS_CHAIN_K", (int)K);
+            if (K < 1) K = 1;
             G.nw = (int)cdiv(Y, 32);
             G.aw = 2 * sp.w_in + 2;
             int64_t aoff = 0;
@@ -205,7 +207,7 @@ int plan_product(const Spec &sp, Geom &G) {
     // scratch layout (bytes)
     int64_t o = 0;
     G.ws_ops = o;     o += align_up(G.op_limbs * 4, 256);
-    G.ws_parts = o;   o += align_up(G.part_elems * 8, 256);
+    G.ws_cols = o;    o += align_up(G.col_words * 4, 256);
     G.ws_norms = o;   o += align_up(G.norm_limbs * 4, 256);
     G.ws_anchors = o; o += align_up(std::max<int64_t>(G.anchor_limbs, 1) * 4, 256);
     G.ws_status = o;  o += align_up(std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1) * 8, 256);
@@ -262,7 +264,7 @@ static Launch<J> make_launch(const std::vector<J> &jobs, const Ctl &ctl, uint64_
 int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s) {
     const Spec &sp = G.sp;
     uint32_t *ops = reinterpret_cast<uint32_t *>(ws + G.ws_ops);
-    int64_t *parts = reinterpret_cast<int64_t *>(ws + G.ws_parts);
+    uint32_t *cols = reinterpret_cast<uint32_t *>(ws + G.ws_cols);
     uint32_t *norms = reinterpret_cast<uint32_t *>(ws + G.ws_norms);
     uint32_t *anchors = reinterpret_cast<uint32_t *>(ws + G.ws_anchors);
     uint64_t *status = reinterpret_cast<uint64_t *>(ws + G.ws_status);
@@ -279,6 +281,7 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
         j.L = p.L;
         j.n_out = p.n_out;
         j.N = G.N;
+        j.N_recip = div_recip((uint64_t)G.N);
         j.w_in = sp.w_in;
         j.bits = sp.bits;
         j.flags = p.flags;
@@ -303,10 +306,7 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
         j.b = ops + G.packs[m.fb].op_off;
         j.na = m.na;
         j.nb = m.nb;
-        j.part = parts + m.part_off;
-        j.split_len = m.split_len;
-        j.nsplit = m.nsplit;
-        j.ntiles = m.ntiles;
+        j.cols = cols + m.cols_off;
         j.block0 = blk;
         j.nblocks = m.blocks;
         blk += m.blocks;
@@ -356,18 +356,18 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
         for (int t = 0; t < r.nterms; ++t) {
             const MulGeom &m = G.muls[r.prod[t]];
             NormTerm &T = j.term[t];
-            T.part = parts + m.part_off;
+            T.cols = cols + m.cols_off;
+            T.ncols = m.ntiles * MUL_T;
             T.a = ops + G.packs[m.fa].op_off;
             T.b = ops + G.packs[m.fb].op_off;
             T.na = m.na;
             T.nb = m.nb;
-            T.nsplit = m.nsplit;
-            T.ntiles = m.ntiles;
             T.sign = r.sign[t];
         }
         j.shift = r.shift;
         j.off_bit0 = r.off_bit0;
         j.off_period = r.off_period;
+        j.off_recip = div_recip((uint64_t)r.off_period);
         j.off_count = r.off_count;
         j.out = norms + r.out_off;
         j.n_out = r.n_out;
@@ -461,7 +461,9 @@ static int get_pool(hipStream_t s, size_t need, Pool **out) {
             p = new Pool();
             void *c = nullptr;
             if (hipMalloc(&c, 256) != hipSuccess) { delete p; return KS_ENOMEM; }
-            if (hipMemset(c, 0, 256) != hipSuccess) return KS_EHIP;
+            // cleared on the caller's stream, so the clear is ordered before this stream's kernels
+            // (a non-blocking stream does not wait for work on the null stream)
+            if (hipMemsetAsync(c, 0, 256, s) != hipSuccess) return KS_EHIP;
             p->ctl.ticket = reinterpret_cast<uint64_t *>(c);
             p->ctl.devstat = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(c) + 64);
             p->ctl.epoch = 0;
@@ -480,7 +482,7 @@ static int get_pool(hipStream_t s, size_t need, Pool **out) {
         size_t want = std::max<size_t>(need, (size_t)1 << 20);
         void *w = nullptr;
         if (hipMalloc(&w, want) != hipSuccess) return KS_ENOMEM;
-        if (hipMemset(w, 0, want) != hipSuccess) return KS_EHIP;  // status words start at epoch 0
+        if (hipMemsetAsync(w, 0, want, s) != hipSuccess) return KS_EHIP;  // status words start at epoch 0
         p->ws = reinterpret_cast<char *>(w);
         p->bytes = want;
     }

@@ -64,36 +64,28 @@ __device__ __forceinline__ int64_t u_of(int64_t v, int64_t v1, int64_t v2) {
 
 // ---- status words for the look-back -----------------------------------------------------------
 // bits 63..32 epoch of the launch, bits 9..8 flag (1 aggregate map, 2 inclusive carry),
-// bits 7..0 payload (map, or carry + 1).
+// bits 7..0 payload (map, or carry + 1).  The whole message travels inside one 64-bit word,
+// so relaxed device-scope atomics suffice: no other memory is published through it, and the
+// limbs a block writes are only read by later kernels on the stream.
 constexpr uint32_t LB_AGG = 1, LB_INC = 2;
 constexpr uint64_t LB_SPIN_LIMIT = 1ull << 22;
 
 __device__ __forceinline__ void lb_publish(uint64_t *st, uint32_t epoch, uint32_t flag, uint32_t payload) {
     uint64_t w = ((uint64_t)epoch << 32) | ((uint64_t)flag << 8) | payload;
-    __hip_atomic_store(st, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(st, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t lb_load(const uint64_t *st) {
-    return __hip_atomic_load(const_cast<uint64_t *>(st), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(const_cast<uint64_t *>(st), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Ticket from an epoch-tagged counter: the first block of a new epoch resets it.
+// Block ticket: launch e draws from counter e & 1 with one fetch-and-add and clears the other
+// counter, which the previous launch on the stream used and the next one will use.  (Launches
+// of one stream run one after the other, and the counters start at zero.)
 __device__ __forceinline__ uint32_t lb_ticket(uint64_t *ctr, uint32_t epoch) {
-    uint64_t old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        uint64_t want;
-        uint32_t t;
-        if ((uint32_t)(old >> 32) != epoch) {
-            want = ((uint64_t)epoch << 32) | 1u;
-            t = 0;
-        } else {
-            want = old + 1;
-            t = (uint32_t)old;
-        }
-        if (__hip_atomic_compare_exchange_strong(ctr, &old, want, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT))
-            return t;
-    }
+    uint64_t t = __hip_atomic_fetch_add(ctr + (epoch & 1u), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == 0) __hip_atomic_store(ctr + ((epoch + 1u) & 1u), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (uint32_t)t;
 }
 
 __device__ __forceinline__ void set_status(uint32_t *devstat, uint32_t bit) {
@@ -188,11 +180,17 @@ struct BlockCarryScan {
 };
 
 // ---- job lookup: block index -> (job, block within job) ----------------------------------------
+// Inline jobs: all block0 values are loaded at once (independent scalar loads, one round
+// trip) rather than walked one after another.  Device tables: binary search.
 template <class J>
 __device__ __forceinline__ J find_job(const Launch<J> &L, int64_t blk, int64_t &local) {
     if (L.table == nullptr) {
-        int64_t j = 0;
-        while (j + 1 < L.njobs && blk >= L.jobs[j + 1].block0) ++j;
+        int j = 0;
+#pragma unroll
+        for (int q = 1; q < MAX_INLINE_JOBS; ++q) {
+            const int64_t b0 = L.jobs[q].block0;
+            if (q < L.njobs && blk >= b0) j = q;
+        }
         local = blk - L.jobs[j].block0;
         return L.jobs[j];
     }
@@ -233,10 +231,9 @@ __device__ __forceinline__ uint32_t bits_word(const uint32_t *x, int64_t n, int6
     return (a >> o) | (b << (32 - o));
 }
 
-__device__ __forceinline__ int64_t div_floor(int64_t a, int64_t b) {  // b > 0
-    int64_t q = a / b;
-    return (a % b != 0 && a < 0) ? q - 1 : q;
+// floor(a / d) for 0 <= a < 2^40 with recip = div_recip(d) computed on the host
+__device__ __forceinline__ int64_t div_by(int64_t a, uint64_t recip) {
+    return recip == 0 ? a : (int64_t)__umul64hi((uint64_t)a, recip);
 }
-__device__ __forceinline__ int64_t div_ceil(int64_t a, int64_t b) { return -div_floor(-a, b); }
 
 }  // namespace ks

@@ -110,39 +110,52 @@ __global__ __launch_bounds__(ANCHOR_TPB) void anchor_kernel(Launch<AnchorJob> L)
     uint32_t acc[AW];
 #pragma unroll
     for (int t = 0; t < AW; ++t) acc[t] = 0;
-    for (int64_t i = lo + threadIdx.x; i <= hi; i += ANCHOR_TPB) {
-        uint32_t a[W], b[W];
-        bool na = load_mag<W>(J.f + i * W, sgn, a);
-        bool nb = load_mag<W>(J.g + (k - i) * W, sgn, b);
-        uint32_t p[2 * W];
+    // ANCHOR_U terms per round, their loads issued together (clamped addresses, masked terms)
+    constexpr int U = 4;
+    for (int64_t i0 = lo + threadIdx.x; i0 <= hi; i0 += U * ANCHOR_TPB) {
+        uint32_t a[U][W], b[U][W];
+        bool na[U], nb[U], live[U];
 #pragma unroll
-        for (int t = 0; t < 2 * W; ++t) p[t] = 0;
-#pragma unroll
-        for (int x = 0; x < W; ++x) {
-            uint64_t c = 0;
-#pragma unroll
-            for (int y = 0; y < W; ++y) {
-                uint64_t tt = (uint64_t)a[x] * b[y] + p[x + y] + c;
-                p[x + y] = (uint32_t)tt;
-                c = tt >> 32;
-            }
-            p[x + W] = (uint32_t)c;
+        for (int q = 0; q < U; ++q) {
+            const int64_t i = i0 + (int64_t)q * ANCHOR_TPB;
+            live[q] = i <= hi;
+            const int64_t ii = live[q] ? i : lo;
+            na[q] = load_mag<W>(J.f + ii * W, sgn, a[q]);
+            nb[q] = load_mag<W>(J.g + (k - ii) * W, sgn, b[q]);
         }
-        if (na != nb) {
-            uint64_t br = 0;
 #pragma unroll
-            for (int t = 0; t < AW; ++t) {
-                uint64_t d = (uint64_t)acc[t] - (t < 2 * W ? p[t] : 0u) - br;
-                acc[t] = (uint32_t)d;
-                br = (d >> 63) & 1u;
+        for (int q = 0; q < U; ++q) {
+            if (!live[q]) continue;
+            uint32_t p[2 * W];
+#pragma unroll
+            for (int t = 0; t < 2 * W; ++t) p[t] = 0;
+#pragma unroll
+            for (int x = 0; x < W; ++x) {
+                uint64_t c = 0;
+#pragma unroll
+                for (int y = 0; y < W; ++y) {
+                    uint64_t tt = (uint64_t)a[q][x] * b[q][y] + p[x + y] + c;
+                    p[x + y] = (uint32_t)tt;
+                    c = tt >> 32;
+                }
+                p[x + W] = (uint32_t)c;
             }
-        } else {
-            uint64_t c = 0;
+            if (na[q] != nb[q]) {
+                uint64_t br = 0;
 #pragma unroll
-            for (int t = 0; t < AW; ++t) {
-                uint64_t sm = (uint64_t)acc[t] + (t < 2 * W ? p[t] : 0u) + c;
-                acc[t] = (uint32_t)sm;
-                c = sm >> 32;
+                for (int t = 0; t < AW; ++t) {
+                    uint64_t d = (uint64_t)acc[t] - (t < 2 * W ? p[t] : 0u) - br;
+                    acc[t] = (uint32_t)d;
+                    br = (d >> 63) & 1u;
+                }
+            } else {
+                uint64_t c = 0;
+#pragma unroll
+                for (int t = 0; t < AW; ++t) {
+                    uint64_t sm = (uint64_t)acc[t] + (t < 2 * W ? p[t] : 0u) + c;
+                    acc[t] = (uint32_t)sm;
+                    c = sm >> 32;
+                }
             }
         }
     }
@@ -289,8 +302,16 @@ __device__ __forceinline__ uint32_t hword(const MW<NW> &al, const MW<NW> &be, in
     return mw_bits(al, 32 * (int64_t)t) | mw_bits(be, 32 * (int64_t)t - Nd);
 }
 
+// One lane per segment.  Digits are read straight from the recombined products; a lane loads
+// the digits of CHAIN_G(NW) steps at once so their latencies overlap, then runs the steps.
+template <int NW>
+struct ChainGroup {
+    static constexpr int G = NW <= 2 ? 8 : (NW <= 4 ? 4 : 2);
+};
+
 template <int NW>
 __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
+    constexpr int G = ChainGroup<NW>::G;
     int64_t local;
     const ChainJob J = find_job(L, (int64_t)blockIdx.x, local);
     const int64_t s = local * CHAIN_TPB + threadIdx.x;
@@ -301,6 +322,8 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
     int64_t k1 = k0 + J.K;
     if (k1 > m) k1 = m;
     const int hw = (2 * Nd + 31) >> 5;  // limbs of h' = alpha + Y beta
+#define U_DIGIT(c) read_digit<NW>(J.A, J.nA, (c) * (int64_t)Nd, Nd)
+#define W_DIGIT(c) read_digit<NW>(J.B, J.nB, (m - (c)) * (int64_t)Nd, Nd)
 
     MW<NW> sigma, aprev;
 #pragma unroll
@@ -309,51 +332,65 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
         const uint32_t *anc = J.anchors + s * J.aw;
         MW<NW> al = read_digit<NW>(anc, J.aw, 0, Nd);
         MW<NW> be = read_digit<NW>(anc, J.aw, Nd, Nd);
-        MW<NW> u = read_digit<NW>(J.A, J.nA, (k0 - 1) * (int64_t)Nd, Nd);
+        MW<NW> u = U_DIGIT(k0 - 1);
         aprev = al;
         sigma = add_bit(be, mw_lt(u, al) ? 1u : 0u);
     }
-    MW<NW> wc = read_digit<NW>(J.B, J.nB, (m - k0) * (int64_t)Nd, Nd);
+    MW<NW> wc = W_DIGIT(k0);
     MW<NW> alpha = aprev, beta;
-    for (int64_t c = k0; c < k1; ++c) {
-        MW<NW> u = read_digit<NW>(J.A, J.nA, c * (int64_t)Nd, Nd);
-        MW<NW> wn = read_digit<NW>(J.B, J.nB, (m - c - 1) * (int64_t)Nd, Nd);
-        alpha = sub_mod(u, sigma, 0u, Nd);          // alpha_c = u_c - sigma_{c-1}  (mod Y)
-        uint32_t delta = mw_lt(u, sigma) ? 1u : 0u;  // carry of the low half into digit c+1
-        uint32_t eps = mw_lt(wn, alpha) ? 1u : 0u;   // eps_c = [alpha_c > w_{c+1}]
-        beta = sub_mod(wc, aprev, eps, Nd);          // beta_c = w_c - alpha_{c-1} - eps_c (mod Y)
-        sigma = add_bit(beta, delta);                // sigma_c = beta_c + delta
-        aprev = alpha;
-        wc = wn;
-        // write h_{2c+par} = h'_c - C
-        const int64_t idx = J.out_first + c * J.out_step;
-        if (J.mod_p == 0) {
-            uint32_t *o = J.out + idx * J.w_out;
-            uint32_t br = 0;
-            for (int t = 0; t < J.w_out; ++t) {
-                uint32_t word = t < hw ? hword(alpha, beta, Nd, t) : 0u;
-                uint32_t sub = (J.off_bit >= 0 && (J.off_bit >> 5) == t) ? (1u << (J.off_bit & 31)) : 0u;
-                uint64_t d = (uint64_t)word - sub - br;
-                o[t] = (uint32_t)d;
-                br = (uint32_t)(d >> 63) & 1u;
+    for (int64_t cg = k0; cg < k1; cg += G) {
+        MW<NW> us[G], ws[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (cg + g < k1) {
+                us[g] = U_DIGIT(cg + g);
+                ws[g] = W_DIGIT(cg + g + 1);
             }
-        } else {
-            uint64_t r = 0;
-            for (int t = hw - 1; t >= 0; --t) r = mod_step(r, hword(alpha, beta, Nd, t), J.mod_p);
-            reinterpret_cast<uint64_t *>(J.out)[idx] = r;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (cg + g < k1) {
+                const int64_t c = cg + g;
+                const MW<NW> &u = us[g];
+                const MW<NW> &wn = ws[g];
+                alpha = sub_mod(u, sigma, 0u, Nd);          // alpha_c = u_c - sigma_{c-1}  (mod Y)
+                uint32_t delta = mw_lt(u, sigma) ? 1u : 0u;  // carry of the low half into digit c+1
+                uint32_t eps = mw_lt(wn, alpha) ? 1u : 0u;   // eps_c = [alpha_c > w_{c+1}]
+                beta = sub_mod(wc, aprev, eps, Nd);          // beta_c = w_c - alpha_{c-1} - eps_c (mod Y)
+                sigma = add_bit(beta, delta);                // sigma_c = beta_c + delta
+                aprev = alpha;
+                wc = wn;
+                // write h_{2c+par} = h'_c - C
+                const int64_t idx = J.out_first + c * J.out_step;
+                if (J.mod_p == 0) {
+                    uint32_t *o = J.out + idx * J.w_out;
+                    uint32_t br = 0;
+                    for (int t = 0; t < J.w_out; ++t) {
+                        uint32_t word = t < hw ? hword(alpha, beta, Nd, t) : 0u;
+                        uint32_t sub = (J.off_bit >= 0 && (J.off_bit >> 5) == t) ? (1u << (J.off_bit & 31)) : 0u;
+                        uint64_t d = (uint64_t)word - sub - br;
+                        o[t] = (uint32_t)d;
+                        br = (uint32_t)(d >> 63) & 1u;
+                    }
+                } else {
+                    uint64_t r = 0;
+                    for (int t = hw - 1; t >= 0; --t) r = mod_step(r, hword(alpha, beta, Nd, t), J.mod_p);
+                    reinterpret_cast<uint64_t *>(J.out)[idx] = r;
+                }
+            }
         }
     }
-    // self-checks
+    // self-checks: the segment ends on the next anchor; the chain ends on the two unused relations
     bool ok = true;
     if (k1 < m) {
         const uint32_t *anc = J.anchors + (s + 1) * J.aw;
         for (int t = 0; t < J.aw; ++t) ok = ok && (anc[t] == (t < hw ? hword(alpha, beta, Nd, t) : 0u));
     } else if (k1 > k0) {
-        MW<NW> wm = read_digit<NW>(J.B, J.nB, 0, Nd);
-        MW<NW> um = read_digit<NW>(J.A, J.nA, m * (int64_t)Nd, Nd);
-        ok = mw_eq(alpha, wm) && mw_eq(sigma, um);
+        ok = mw_eq(alpha, W_DIGIT(m)) && mw_eq(sigma, U_DIGIT(m));
     }
     if (!ok) set_status(L.devstat, KS_DEVSTAT_CHECK);
+#undef U_DIGIT
+#undef W_DIGIT
 }
 
 // ---- host launchers ------------------------------------------------------------------------------

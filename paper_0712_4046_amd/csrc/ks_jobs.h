@@ -21,13 +21,13 @@ constexpr int SCAN_TPB = 256;
 constexpr int SCAN_IPT = 8;
 constexpr int64_t SCAN_BL = (int64_t)SCAN_TPB * SCAN_IPT;
 
-// vector-ALU multiplier: 256 threads x 4 columns = 1024 product limbs per tile, spilling two
-// limbs into the next tile (96-bit column sums)
-constexpr int MUL_TPB = 256;
-constexpr int MUL_R = 4;
-constexpr int MUL_T = MUL_TPB * MUL_R;
-constexpr int MUL_TW = MUL_T + 2;
-constexpr int MUL_CI = 256;  // i-chunk staged through LDS
+// vector-ALU multiplier: a block of MUL_WAVES waves owns MUL_T = 64 * MUL_R product columns;
+// its waves take interleaved MUL_CI-long chunks of the i range and add up in LDS at the end
+constexpr int MUL_WAVES = 8;
+constexpr int MUL_TPB = 64 * MUL_WAVES;
+constexpr int MUL_R = 2;
+constexpr int MUL_T = 64 * MUL_R;
+constexpr int MUL_CI = 128;
 
 constexpr int EXTRACT_TPB = 256;
 constexpr int CHAIN_TPB = 64;
@@ -43,6 +43,7 @@ struct PackJob {
     int64_t L;
     int64_t n_out;
     int64_t N;
+    uint64_t N_recip;  // division by N (see div_by)
     int32_t w_in;
     int32_t bits;
     int32_t flags;
@@ -52,30 +53,27 @@ struct PackJob {
     int64_t nblocks;
 };
 
-// unsigned product of the limb arrays a (na) and b (nb); tile t of split s accumulates
-// columns [t T, t T + T) over i in [s split_len, (s+1) split_len) into part[s][t][0..TW)
+// unsigned product of the limb arrays a (na) and b (nb): block t writes the 96-bit sums of
+// columns [t T, t T + T) as three 32-bit pieces, cols[3 k + 0..2]
 struct MulJob {
     const uint32_t *a;
     const uint32_t *b;
     int64_t na;
     int64_t nb;
-    int64_t *part;
-    int64_t split_len;
-    int32_t nsplit;
-    int32_t ntiles;
+    uint32_t *cols;
     int64_t block0;
-    int64_t nblocks;
+    int64_t nblocks;  // = number of column tiles
 };
 
-// one product read back from its partial sums, corrected for two's-complement operands
+// one product read back from its column sums, corrected for two's-complement operands;
+// column j of the value gets piece 0 of column j, piece 1 of j-1 and piece 2 of j-2
 struct NormTerm {
-    const int64_t *part;
+    const uint32_t *cols;
     const uint32_t *a;
     const uint32_t *b;
+    int64_t ncols;
     int64_t na;
     int64_t nb;
-    int32_t nsplit;
-    int32_t ntiles;
     int32_t sign;  // +1 or -1
     int32_t pad;
 };
@@ -88,6 +86,7 @@ struct NormJob {
     int32_t shift;
     int64_t off_bit0;
     int64_t off_period;
+    uint64_t off_recip;  // division by off_period (see div_by)
     int64_t off_count;
     uint32_t *out;
     int64_t n_out;
@@ -155,6 +154,10 @@ struct ChainJob {
     int64_t nblocks;
 };
 
+// floor(a / d) for 0 <= a < 2^40 and 1 <= d < 2^24 as umulhi(a, recip), recip = floor(2^64/d)+1
+// (recip = 0 stands for d = 1): a reciprocal multiply instead of a 64-bit division
+inline uint64_t div_recip(uint64_t d) { return d <= 1 ? 0 : (uint64_t)(~0ull / d) + 1; }
+
 template <class J>
 struct Launch {
     J jobs[MAX_INLINE_JOBS];
@@ -162,7 +165,7 @@ struct Launch {
     int64_t njobs;
     int64_t total_blocks;
     uint64_t *status;  // look-back words, one per block of the launch
-    uint64_t *ticket;  // epoch-tagged block ticket counter
+    uint64_t *ticket;  // two block-ticket counters (see lb_ticket)
     uint32_t *devstat;
     uint32_t epoch;
     uint32_t pad;

@@ -2,17 +2,17 @@
 // Sections 3.1-3.4, i.e. M(b) for KS1 and the two or four smaller products of the multipoint
 // variants).
 //
-// Product scanning: output limb column k of A*B is sum_i a_i b_{k-i}.  A block owns a tile of
-// MUL_T = 1024 consecutive columns and one split of the i range (split-K, so that even a
-// single product fills the GPU); each thread owns MUL_R = 4 adjacent columns and keeps a
+// Product scanning: output limb column k of A*B is sum_i a_i b_{k-i}.  A block owns MUL_T
+// consecutive columns (MUL_R adjacent columns per lane) and its MUL_WAVES waves split the
+// i range between them in interleaved chunks of MUL_CI, so even one product of a few
+// thousand limbs fills the GPU without partial sums leaving the block.  Each lane keeps a
 // 96-bit sum per column: v_mad_u64_u32 accumulates the 32x32-bit product into 64 bits and
-// hands its carry to a v_addc into the top 32 bits.  Both operands stream through LDS in
-// chunks of MUL_CI limbs; a_i is read as a broadcast, b as one aligned 128-bit read per four
-// i steps (the four columns of a thread see a sliding window of b).
+// hands its carry to a v_addc into the top 32 bits.  Operand chunks go through LDS; a_i is
+// read as a broadcast, b as one aligned 64-bit read per MUL_R steps (a lane's columns see a
+// sliding window of b).
 //
-// Output: the 96-bit column sums are split into three 32-bit pieces landing on columns
-// k, k+1, k+2, so each tile writes MUL_T + 2 int64 partial columns; the consumer
-// (normalize_kernel) adds the tiles' overlaps and the splits.
+// Output: per column the 96-bit sum as three 32-bit pieces (weights 2^0, 2^32, 2^64); the
+// consumer (normalize_kernel) adds piece p of column k into limb k + p.
 #include "ks_device.h"
 #include "ks_launch.h"
 
@@ -28,75 +28,76 @@ __device__ __forceinline__ void mac96(uint64_t &lo, uint32_t &hi, uint32_t a, ui
 }
 
 __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
-    __shared__ __attribute__((aligned(16))) uint32_t sa[MUL_CI];
-    __shared__ __attribute__((aligned(16))) uint32_t sb[MUL_T + MUL_CI];
-    __shared__ uint64_t sspill[MUL_TPB][2];
+    __shared__ __attribute__((aligned(16))) uint32_t sa[MUL_WAVES][MUL_CI];
+    __shared__ __attribute__((aligned(16))) uint32_t sb[MUL_WAVES][MUL_T + MUL_CI];
+    __shared__ uint64_t s_lo[MUL_WAVES][MUL_T];
+    __shared__ uint32_t s_hi[MUL_WAVES][MUL_T];
 
     int64_t local;
     const MulJob J = find_job(L, (int64_t)blockIdx.x, local);
-    const int tid = threadIdx.x;
-    const int64_t s = local / J.ntiles;
-    const int64_t t = local - s * J.ntiles;
-    const int64_t k0 = t * MUL_T;
-
-    int64_t ilo = s * J.split_len;
-    if (ilo < k0 - J.nb + 1) ilo = k0 - J.nb + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t k0 = local * MUL_T;
+    int64_t ilo = k0 - J.nb + 1;
     if (ilo < 0) ilo = 0;
-    int64_t ihi = (s + 1) * J.split_len;
-    if (ihi > J.na) ihi = J.na;
-    if (ihi > k0 + MUL_T) ihi = k0 + MUL_T;
+    int64_t ihi = J.na < k0 + MUL_T ? J.na : k0 + MUL_T;
 
     uint64_t lo[MUL_R];
     uint32_t hi[MUL_R];
 #pragma unroll
     for (int r = 0; r < MUL_R; ++r) { lo[r] = 0; hi[r] = 0; }
 
-    const int base = tid * MUL_R + MUL_CI - MUL_R;
-    for (int64_t c0 = ilo; c0 < ihi; c0 += MUL_CI) {
-        __syncthreads();
-        sa[tid] = (c0 + tid < ihi) ? J.a[c0 + tid] : 0u;
-        const int64_t bfirst = k0 - c0 - MUL_CI + 1;  // b index held in sb[0]
-        for (int x = tid; x < MUL_T + MUL_CI; x += MUL_TPB) {
-            int64_t bi = bfirst + x;
-            sb[x] = (bi >= 0 && bi < J.nb) ? J.b[bi] : 0u;
+    // the waves take interleaved chunks of the i range: wave w runs chunks w, w + WAVES, ...
+    const int64_t span = (int64_t)MUL_WAVES * MUL_CI;
+    const int64_t niter = ihi > ilo ? (ihi - ilo + span - 1) / span : 0;
+    const int base = lane * MUL_R + MUL_CI - MUL_R;
+    for (int64_t it = 0; it < niter; ++it) {
+        const int64_t c0 = ilo + it * span + (int64_t)wv * MUL_CI;
+        const bool active = c0 < ihi;
+        for (int x = lane; x < MUL_CI; x += 64) sa[wv][x] = (active && c0 + x < ihi) ? J.a[c0 + x] : 0u;
+        const int64_t bfirst = k0 - c0 - MUL_CI + 1;  // b index held in sb[wv][0]
+        for (int x = lane; x < MUL_T + MUL_CI; x += 64) {
+            const int64_t bi = bfirst + x;
+            sb[wv][x] = (active && bi >= 0 && bi < J.nb) ? J.b[bi] : 0u;
         }
         __syncthreads();
-        // E[idx] = sb[base - x0 + idx], idx in [0, 2R); column r at step x0+u uses E[R-1+r-u]
-        uint4 ehi = *reinterpret_cast<const uint4 *>(&sb[base + MUL_R]);
-        for (int x0 = 0; x0 < MUL_CI; x0 += MUL_R) {
-            uint4 elo = *reinterpret_cast<const uint4 *>(&sb[base - x0]);
-            uint4 av = *reinterpret_cast<const uint4 *>(&sa[x0]);
-            uint32_t E[2 * MUL_R] = {elo.x, elo.y, elo.z, elo.w, ehi.x, ehi.y, ehi.z, ehi.w};
-            uint32_t A[MUL_R] = {av.x, av.y, av.z, av.w};
+        if (active) {
+            // E[idx] = sb[base - x0 + idx]; column r at step x0 + u uses E[R - 1 + r - u]
+            uint2 ehi = *reinterpret_cast<const uint2 *>(&sb[wv][base + MUL_R]);
+            for (int x0 = 0; x0 < MUL_CI; x0 += MUL_R) {
+                const uint2 elo = *reinterpret_cast<const uint2 *>(&sb[wv][base - x0]);
+                const uint2 av = *reinterpret_cast<const uint2 *>(&sa[wv][x0]);
+                const uint32_t E[2 * MUL_R] = {elo.x, elo.y, ehi.x, ehi.y};
+                const uint32_t A[MUL_R] = {av.x, av.y};
 #pragma unroll
-            for (int u = 0; u < MUL_R; ++u)
+                for (int u = 0; u < MUL_R; ++u)
 #pragma unroll
-                for (int r = 0; r < MUL_R; ++r) mac96(lo[r], hi[r], A[u], E[MUL_R - 1 + r - u]);
-            ehi = elo;
+                    for (int r = 0; r < MUL_R; ++r) mac96(lo[r], hi[r], A[u], E[MUL_R - 1 + r - u]);
+                ehi = elo;
+            }
         }
+        __syncthreads();
     }
 
-    // split the 96-bit sums into 32-bit pieces on columns k, k+1, k+2
-    int64_t own[MUL_R];
+    // add the waves' 96-bit sums and store them as three 32-bit pieces per column
 #pragma unroll
     for (int r = 0; r < MUL_R; ++r) {
-        own[r] = (int64_t)(uint32_t)lo[r];
-        if (r >= 1) own[r] += (int64_t)(lo[r - 1] >> 32);
-        if (r >= 2) own[r] += (int64_t)hi[r - 2];
+        s_lo[wv][lane * MUL_R + r] = lo[r];
+        s_hi[wv][lane * MUL_R + r] = hi[r];
     }
-    sspill[tid][0] = (lo[MUL_R - 1] >> 32) + (uint64_t)hi[MUL_R - 2];
-    sspill[tid][1] = (uint64_t)hi[MUL_R - 1];
     __syncthreads();
-    if (tid > 0) {
-        own[0] += (int64_t)sspill[tid - 1][0];
-        own[1] += (int64_t)sspill[tid - 1][1];
-    }
-    int64_t *out = J.part + local * MUL_TW;
+    for (int t = tid; t < MUL_T; t += MUL_TPB) {
+        uint64_t l = 0;
+        uint32_t h = 0;
 #pragma unroll
-    for (int r = 0; r < MUL_R; ++r) out[tid * MUL_R + r] = own[r];
-    if (tid == MUL_TPB - 1) {
-        out[MUL_T] = (int64_t)sspill[tid][0];
-        out[MUL_T + 1] = (int64_t)sspill[tid][1];
+        for (int w = 0; w < MUL_WAVES; ++w) {
+            const uint64_t x = s_lo[w][t];
+            l += x;
+            h += (l < x ? 1u : 0u) + s_hi[w][t];
+        }
+        uint32_t *o = J.cols + 3 * (k0 + t);
+        o[0] = (uint32_t)l;
+        o[1] = (uint32_t)(l >> 32);
+        o[2] = h;
     }
 }
 

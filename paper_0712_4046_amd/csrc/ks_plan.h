@@ -29,9 +29,8 @@ struct PackGeom {
 };
 struct MulGeom {
     int fa, fb;  // operand (pack) indices
-    int64_t na, nb, split_len;
-    int nsplit, ntiles;
-    int64_t part_off, blocks;
+    int64_t na, nb, ntiles;
+    int64_t cols_off, blocks;  // column sums: 3 words per column, ntiles * MUL_T columns
 };
 struct NormGeom {
     int nterms, prod[2], sign[2], shift;
@@ -50,17 +49,17 @@ struct ChainGeom {
 
 struct Geom {
     Spec sp;
-    int variant = 0, e = 0, w_out = 0, off = -1, nw = 0, aw = 0;
+    int variant = 0, e = 0, w_out = 0, off = -1, nw = 0, aw = 0, chain_lds = 0;
     int64_t N = 0, D = 0, m0 = 0, m1 = 0, nf = 0, ng = 0;
     std::vector<PackGeom> packs;
     std::vector<MulGeom> muls;
     std::vector<NormGeom> norms;
     std::vector<ExtractGeom> extracts;
     std::vector<ChainGeom> chains;
-    int64_t op_limbs = 0, part_elems = 0, norm_limbs = 0, anchor_limbs = 0;
+    int64_t op_limbs = 0, col_words = 0, norm_limbs = 0, anchor_limbs = 0;
     int64_t pack_blocks = 0, mul_blocks = 0, norm_blocks = 0, extract_blocks = 0, anchor_blocks = 0,
             chain_blocks = 0;
-    int64_t ws_ops = 0, ws_parts = 0, ws_norms = 0, ws_anchors = 0, ws_status = 0, ws_bytes = 0;
+    int64_t ws_ops = 0, ws_cols = 0, ws_norms = 0, ws_anchors = 0, ws_status = 0, ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
 };
 

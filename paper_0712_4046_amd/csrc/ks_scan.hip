@@ -17,84 +17,109 @@ namespace ks {
 
 // ---- pack ------------------------------------------------------------------------------------
 
-__device__ __forceinline__ void check_range(const uint32_t *c, int w, int bits, bool sgn, uint64_t mod_p,
-                                            uint32_t *devstat) {
-    int top = bits - 32 * (w - 1);  // bits used in the top limb, 1..32
-    uint32_t t = c[w - 1];
-    bool ok;
-    if (mod_p) {
-        ok = (((uint64_t)c[1] << 32) | c[0]) < mod_p;
-    } else if (sgn) {
-        int32_t s = (int32_t)t >> (top - 1);
-        ok = (s == 0 || s == -1);
-    } else {
-        ok = top == 32 ? true : (t >> top) == 0;
-    }
-    if (!ok) set_status(devstat, KS_DEVSTAT_RANGE);
-}
+// Pack by scattering: each thread takes whole coefficients (coalesced loads, all independent)
+// and adds their 32-bit pieces into the block's LDS limb columns; the columns before and after
+// the block's range that the carry scan needs are filled the same way.
+constexpr int PK_MAXW = 8;  // limbs of one input coefficient (coeff_bits <= 256)
 
-__device__ int64_t pack_column(const PackJob &J, int64_t j, uint32_t *devstat) {
-    if (j < 0 || j >= J.n_out) return 0;
-    const int64_t N = J.N;
-    const int bits = J.bits;
-    const bool sgn = (J.flags & PK_SIGNED) != 0;
-    int64_t ilo = div_ceil(32 * j - bits + 1, N);
-    int64_t ihi = div_floor(32 * j + 31, N);
-    if (ilo < 0) ilo = 0;
-    if (ihi > J.L - 1) ihi = J.L - 1;
-    int64_t v = 0;
-    for (int64_t i = ilo; i <= ihi; ++i) {
-        int64_t src = (J.flags & PK_REVERSE) ? J.L - 1 - i : i;
-        const uint32_t *c = J.coeffs + src * J.w_in;
-        int64_t p = i * N;
-        int64_t w = p >> 5;
-        int r = (int)(p & 31);
-        int64_t t = j - w;
-        int64_t npieces = (bits + r + 31) >> 5;
-        uint32_t word = coeff_word(c, J.w_in, sgn, 32 * t - r);
-        int64_t piece = (sgn && t == npieces - 1) ? (int64_t)(int32_t)word : (int64_t)word;
-        if ((J.flags & PK_ALTERNATE) && (i & 1)) v -= piece; else v += piece;
-        if ((J.flags & PK_CHECK) && devstat && t == 0) check_range(c, J.w_in, bits, sgn, J.mod_p, devstat);
+// bits [s, s+32) of a coefficient held in registers (s may be negative: bits below 0 read 0)
+__device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[PK_MAXW], int w, uint32_t fill, int s) {
+    if (s <= -32) return 0u;
+    if (s < 0) return cl[0] << (-s);
+    const int q = s >> 5, o = s & 31;
+    uint32_t a = fill, b = fill;
+#pragma unroll
+    for (int t = 0; t < PK_MAXW; ++t) {
+        if (t < w && t == q) a = cl[t];
+        if (t < w && t == q + 1) b = cl[t];
     }
-    return v;
+    return o ? (a >> o) | (b << (32 - o)) : a;
 }
 
 __global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) {
     typedef BlockCarryScan<SCAN_TPB, SCAN_IPT> Scan;
     __shared__ typename Scan::Smem sm;
     __shared__ uint32_t s_ticket;
-    __shared__ int64_t s_last[SCAN_TPB][2];
+    __shared__ int64_t s_v[SCAN_BL + 3];  // s_v[x + 2] = column jb + x, x in [-2, SCAN_BL]
     if (threadIdx.x == 0) s_ticket = lb_ticket(L.ticket, L.epoch);
+    for (int x = threadIdx.x; x < SCAN_BL + 3; x += SCAN_TPB) s_v[x] = 0;
     __syncthreads();
     const int64_t blk = s_ticket;
     int64_t local;
     const PackJob J = find_job(L, blk, local);
     const int tid = threadIdx.x;
-    const int64_t j0 = local * SCAN_BL + (int64_t)tid * SCAN_IPT;
-
-    int64_t v[SCAN_IPT];
+    const int64_t jb = local * SCAN_BL;
+    const int64_t jlo = jb - 2, jhi = jb + SCAN_BL + 1;  // columns [jlo, jhi)
+    const int64_t N = J.N;
+    const int bits = J.bits, w_in = J.w_in;
+    const bool sgn = (J.flags & PK_SIGNED) != 0;
+    // coefficients i whose bits [i N, i N + bits) meet limbs [jlo, jhi)
+    const int64_t a = 32 * jlo - bits + 1;
+    int64_t i0 = a <= 0 ? 0 : div_by(a + N - 1, J.N_recip);
+    int64_t i1 = jhi <= 0 ? -1 : div_by(32 * jhi - 1, J.N_recip);
+    if (i1 > J.L - 1) i1 = J.L - 1;
+    constexpr int U = 4;  // coefficients per thread per round, loads issued together
+    for (int64_t ib = i0 + tid; ib <= i1; ib += U * SCAN_TPB) {
+        uint32_t cl[U][PK_MAXW];
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q) v[q] = pack_column(J, j0 + q, L.devstat);
-    s_last[tid][0] = v[SCAN_IPT - 2];
-    s_last[tid][1] = v[SCAN_IPT - 1];
-    __syncthreads();
-    int64_t vm2, vm1;
-    if (tid == 0) {
-        vm2 = pack_column(J, j0 - 2, nullptr);
-        vm1 = pack_column(J, j0 - 1, nullptr);
-    } else {
-        vm2 = s_last[tid - 1][0];
-        vm1 = s_last[tid - 1][1];
+        for (int q = 0; q < U; ++q) {
+            const int64_t i = ib + (int64_t)q * SCAN_TPB;
+            const int64_t ii = i <= i1 ? i : i0;
+            const int64_t src = (J.flags & PK_REVERSE) ? J.L - 1 - ii : ii;
+            const uint32_t *c = J.coeffs + src * w_in;
+#pragma unroll
+            for (int t = 0; t < PK_MAXW; ++t) {
+                const uint32_t x = c[t < w_in ? t : w_in - 1];
+                cl[q][t] = t < w_in ? x : 0u;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t i = ib + (int64_t)q * SCAN_TPB;
+            if (i > i1) continue;
+            uint32_t top = 0;
+#pragma unroll
+            for (int t = 0; t < PK_MAXW; ++t) top = (t == w_in - 1) ? cl[q][t] : top;
+            const uint32_t fill = (sgn && (top >> 31)) ? 0xffffffffu : 0u;
+            const int64_t p = i * N;
+            const int64_t w = p >> 5;
+            const int r = (int)(p & 31);
+            const int npieces = (bits + r + 31) >> 5;
+            const bool neg = (J.flags & PK_ALTERNATE) && (i & 1);
+            for (int t = 0; t < npieces; ++t) {
+                const int64_t j = w + t;
+                if (j < jlo || j >= jhi) continue;
+                const uint32_t word = reg_word(cl[q], w_in, fill, 32 * t - r);
+                int64_t piece = (sgn && t == npieces - 1) ? (int64_t)(int32_t)word : (int64_t)word;
+                if (neg) piece = -piece;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&s_v[j - jb + 2]), (unsigned long long)piece);
+            }
+            if ((J.flags & PK_CHECK) && w >= jb && w < jb + SCAN_BL) {
+                // range check, once per coefficient (in the block holding its lowest limb)
+                bool ok;
+                if (J.mod_p) {
+                    ok = (((uint64_t)cl[q][1] << 32) | cl[q][0]) < J.mod_p;
+                } else {
+                    const int tb = bits - 32 * (w_in - 1);  // bits used in the top limb, 1..32
+                    if (sgn) {
+                        const int32_t sx = (int32_t)top >> (tb - 1);
+                        ok = (sx == 0 || sx == -1);
+                    } else {
+                        ok = tb == 32 ? true : (top >> tb) == 0;
+                    }
+                }
+                if (!ok) set_status(L.devstat, KS_DEVSTAT_RANGE);
+            }
+        }
     }
+    __syncthreads();
+    const int b0 = tid * SCAN_IPT;
     int64_t u[SCAN_IPT];
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q) {
-        int64_t a1 = q >= 1 ? v[q - 1] : vm1;
-        int64_t a2 = q >= 2 ? v[q - 2] : (q == 1 ? vm1 : vm2);
-        u[q] = u_of(v[q], a1, a2);
-    }
+    for (int q = 0; q < SCAN_IPT; ++q) u[q] = u_of(s_v[b0 + q + 2], s_v[b0 + q + 1], s_v[b0 + q]);
     uint32_t out[SCAN_IPT];
     Scan::run(sm, u, out, L.status + J.block0, local, L.epoch, L.devstat);
+    const int64_t j0 = jb + b0;
 #pragma unroll
     for (int q = 0; q < SCAN_IPT; ++q)
         if (j0 + q < J.n_out) J.out[j0 + q] = out[q];
@@ -102,51 +127,97 @@ __global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) {
 
 // ---- normalize --------------------------------------------------------------------------------
 
-__device__ __forceinline__ int64_t term_column(const NormTerm &T, int64_t j) {
-    int64_t s = 0;
-    const int64_t t = j / MUL_T;
-    const int64_t x = j - t * MUL_T;
-    const int64_t stride = (int64_t)T.ntiles * MUL_TW;
-    for (int sp = 0; sp < T.nsplit; ++sp) {
-        const int64_t *base = T.part + sp * stride;
-        if (t < T.ntiles) s += base[t * MUL_TW + x];
-        if (x < 2 && t >= 1 && t - 1 < T.ntiles) s += base[(t - 1) * MUL_TW + MUL_T + x];
+// Each thread handles SCAN_IPT consecutive limb positions j0 .. j0+IPT-1 and needs the column
+// values v at j0-2 .. j0+IPT-1.  Column j of a product is piece 0 of column-sum j, piece 1
+// of j-1 and piece 2 of j-2, so the thread reads one contiguous window of column sums
+// (columns j0-4 .. j0+IPT-1) plus the operand limbs of the sign corrections -- fixed-size,
+// branch-free, clamped loads that are all in flight together.
+constexpr int NWIN = SCAN_IPT + 4;  // column-sum window
+constexpr int NV = SCAN_IPT + 2;    // column values j0-2 .. j0+IPT-1
+
+struct TermSigns {
+    bool negA[2], negB[2];
+};
+
+// v[m] += sign * (column j0 - 2 + m of the product), m in [0, NV)
+__device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bool negB, int64_t j0,
+                                                int64_t (&v)[NV]) {
+    const int64_t c0 = j0 - 4;
+    uint32_t x[3 * NWIN];
+#pragma unroll
+    for (int t = 0; t < 3 * NWIN; ++t) {
+        const int64_t col = c0 + t / 3;
+        const bool ok = col >= 0 && col < T.ncols;
+        x[t] = T.cols[ok ? 3 * c0 + t : 0];
+        x[t] = ok ? x[t] : 0u;
+    }
+    int64_t acc[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const int w = m + 2;  // window column of position j0 - 2 + m
+        acc[m] = (int64_t)x[3 * w] + (int64_t)x[3 * (w - 1) + 1] + (int64_t)x[3 * (w - 2) + 2];
     }
     // the multiplier works on the unsigned readings of two's-complement operands:
     // A B = Au Bu - [A<0] Bu 2^(32 na) - [B<0] Au 2^(32 nb) + [A<0][B<0] 2^(32 (na+nb))
-    const bool negA = (T.a[T.na - 1] >> 31) != 0, negB = (T.b[T.nb - 1] >> 31) != 0;
-    if (negA && j >= T.na && j - T.na < T.nb) s -= (int64_t)T.b[j - T.na];
-    if (negB && j >= T.nb && j - T.nb < T.na) s -= (int64_t)T.a[j - T.nb];
-    if (negA && negB && j == T.na + T.nb) s += 1;
-    return s;
-}
-
-__device__ int64_t norm_column(const NormJob &J, int64_t j) {
-    if (j < 0 || j >= J.n_in) return 0;
-    int64_t v = 0;
+    if (negA) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        if (q < J.nterms) {
-            int64_t s = term_column(J.term[q], j);
-            v += J.term[q].sign > 0 ? s : -s;
+        for (int m = 0; m < NV; ++m) {
+            const int64_t ib = j0 - 2 + m - T.na;
+            const bool ok = ib >= 0 && ib < T.nb;
+            const uint32_t bv = T.b[ok ? ib : 0];
+            acc[m] -= ok ? (int64_t)bv : 0;
         }
     }
-    if (J.off_count > 0) {
-        int64_t klo = div_ceil(32 * j - J.off_bit0, J.off_period);
-        int64_t khi = div_floor(32 * j + 31 - J.off_bit0, J.off_period);
-        if (klo < 0) klo = 0;
+    if (negB) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            const int64_t ia = j0 - 2 + m - T.nb;
+            const bool ok = ia >= 0 && ia < T.na;
+            const uint32_t av = T.a[ok ? ia : 0];
+            acc[m] -= ok ? (int64_t)av : 0;
+        }
+    }
+    if (negA && negB) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m) acc[m] += (j0 - 2 + m == T.na + T.nb) ? 1 : 0;
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m] += T.sign > 0 ? acc[m] : -acc[m];
+}
+
+// the slot constants 2^(off_bit0 + k period) that land in limb j
+__device__ __forceinline__ int64_t offset_column(const NormJob &J, int64_t j) {
+    int64_t v = 0;
+    if (J.off_count > 0 && j >= 0 && 32 * j + 31 >= J.off_bit0) {
+        const int64_t a = 32 * j - J.off_bit0;
+        int64_t klo = a <= 0 ? 0 : div_by(a + J.off_period - 1, J.off_recip);
+        int64_t khi = div_by(32 * j + 31 - J.off_bit0, J.off_recip);
         if (khi > J.off_count - 1) khi = J.off_count - 1;
         for (int64_t k = klo; k <= khi; ++k) v += (int64_t)1 << (J.off_bit0 + k * J.off_period - 32 * j);
     }
     return v;
 }
 
+// column values for positions j0-2 .. j0+IPT-1 (zero outside [0, n_in))
+__device__ __forceinline__ void norm_window(const NormJob &J, const TermSigns &ts, int64_t j0, int64_t (&v)[NV]) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m] = 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        if (q < J.nterms) add_term_window(J.term[q], ts.negA[q], ts.negB[q], j0, v);
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const int64_t j = j0 - 2 + m;
+        v[m] = (j >= 0 && j < J.n_in) ? v[m] + offset_column(J, j) : 0;
+    }
+}
+
 __global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) {
     typedef BlockCarryScan<SCAN_TPB, SCAN_IPT> Scan;
     __shared__ typename Scan::Smem sm;
     __shared__ uint32_t s_ticket;
-    __shared__ int64_t s_last[SCAN_TPB][2];
     __shared__ uint32_t s_limb[SCAN_BL + 1];
+    __shared__ int64_t s_tail[2];
     if (threadIdx.x == 0) s_ticket = lb_ticket(L.ticket, L.epoch);
     __syncthreads();
     const int64_t blk = s_ticket;
@@ -155,48 +226,40 @@ __global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) 
     const int tid = threadIdx.x;
     const int64_t jb = local * SCAN_BL;
     const int64_t j0 = jb + (int64_t)tid * SCAN_IPT;
-
-    int64_t v[SCAN_IPT];
+    TermSigns ts;
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q) v[q] = norm_column(J, j0 + q);
-    s_last[tid][0] = v[SCAN_IPT - 2];
-    s_last[tid][1] = v[SCAN_IPT - 1];
-    __syncthreads();
-    int64_t vm2, vm1;
-    if (tid == 0) {
-        vm2 = norm_column(J, j0 - 2);
-        vm1 = norm_column(J, j0 - 1);
-    } else {
-        vm2 = s_last[tid - 1][0];
-        vm1 = s_last[tid - 1][1];
+    for (int q = 0; q < 2; ++q) {
+        const NormTerm &T = J.term[q];
+        ts.negA[q] = q < J.nterms && (T.a[T.na - 1] >> 31) != 0;
+        ts.negB[q] = q < J.nterms && (T.b[T.nb - 1] >> 31) != 0;
     }
+    int64_t v[NV];
+    norm_window(J, ts, j0, v);
     int64_t u[SCAN_IPT];
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q) {
-        int64_t a1 = q >= 1 ? v[q - 1] : vm1;
-        int64_t a2 = q >= 2 ? v[q - 2] : (q == 1 ? vm1 : vm2);
-        u[q] = u_of(v[q], a1, a2);
+    for (int q = 0; q < SCAN_IPT; ++q) u[q] = u_of(v[q + 2], v[q + 1], v[q]);
+    if (tid == SCAN_TPB - 1) {
+        // the first limb of the next block is needed by the shift: its value before carries
+        int64_t vn[NV];
+        norm_window(J, ts, j0 + SCAN_IPT, vn);
+        s_tail[0] = u_of(vn[2], vn[1], vn[0]);
     }
     uint32_t out[SCAN_IPT];
-    int kout = Scan::run(sm, u, out, L.status + J.block0, local, L.epoch, L.devstat);
+    const int kout = Scan::run(sm, u, out, L.status + J.block0, local, L.epoch, L.devstat);
 #pragma unroll
     for (int q = 0; q < SCAN_IPT; ++q) s_limb[tid * SCAN_IPT + q] = out[q];
-    if (tid == SCAN_TPB - 1) {
-        // the first limb of the next block, needed by the shift
-        int64_t vn = norm_column(J, jb + SCAN_BL);
-        s_limb[SCAN_BL] = (uint32_t)(uint64_t)(u_of(vn, v[SCAN_IPT - 1], v[SCAN_IPT - 2]) + kout);
-    }
+    if (tid == SCAN_TPB - 1) s_limb[SCAN_BL] = (uint32_t)(uint64_t)(s_tail[0] + kout);
     __syncthreads();
+    // write V >> shift: output limb o takes limbs o + w and o + w + 1 (striped, coalesced)
     const int64_t w = J.shift >> 5;
     const int r = J.shift & 31;
 #pragma unroll
     for (int q = 0; q < SCAN_IPT; ++q) {
-        int64_t o = j0 + q - w;
+        const int li = q * SCAN_TPB + tid;
+        const int64_t o = jb + li - w;
         if (o < 0 || o >= J.n_out) continue;
-        int li = tid * SCAN_IPT + q;
-        uint32_t lo = s_limb[li];
-        uint32_t val = r ? ((lo >> r) | (s_limb[li + 1] << (32 - r))) : lo;
-        J.out[o] = val;
+        const uint32_t lo = s_limb[li];
+        J.out[o] = r ? ((lo >> r) | (s_limb[li + 1] << (32 - r))) : lo;
     }
 }
 
