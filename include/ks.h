@@ -102,7 +102,7 @@ int ks_mul(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, i
 /*
  * h = f g in (Z/pZ)[x] (Section 4: lift to Z[x], multiply by a Section 3 variant, reduce).
  *   f, g    device, len_f (len_g) uint64 residues, each in [0, p)
- *   p       odd modulus, 3 <= p < 2^63
+ *   p       odd modulus, 3 <= p < 2^62
  *   variant KS_VARIANT_* | optional KS_ENGINE_* (KS_SIGNED is rejected)
  *   h       device, len_f + len_g - 1 uint64 residues in [0, p)
  * Residues >= p are reported as KS_ERANGE by the next status query.
@@ -135,10 +135,11 @@ typedef struct ks_desc {
     int32_t len_g;
     int32_t coeff_bits;
     int32_t flags;      /* KS_SIGNED, KS_MOD */
-    uint64_t mod_p;     /* odd modulus < 2^63 when flags & KS_MOD */
+    uint64_t mod_p;     /* odd modulus, 3 <= mod_p < 2^62, when flags & KS_MOD */
 } ks_desc;
 
 typedef struct ks_batch_plan ks_batch_plan; /* opaque */
+struct ks_plan_info;
 
 /*
  * Plan a batch once: validates every descriptor (KS_EINVAL names nothing; use
@@ -151,20 +152,23 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
 int64_t ks_batch_plan_bad_index(void);
 /* Device scratch bytes a run of this plan needs. */
 size_t ks_batch_plan_workspace_bytes(const ks_batch_plan *plan);
+/* Totals over the plan's products (limb products, algorithmic bytes; variant -1 if mixed). */
+int ks_batch_plan_info(const ks_batch_plan *plan, struct ks_plan_info *out);
 /*
  * Enqueue the whole batch on `stream`.  Allocates nothing and copies nothing from the host,
  * so it may be captured into a hipGraph and replayed.  `workspace` (device, >= the bytes
- * above, 256-byte aligned) must not be shared by runs that may overlap.
+ * above, 256-byte aligned, contents irrelevant) must not be shared by runs that may overlap.
  */
 int ks_batch_run(const ks_batch_plan *plan, const uint32_t *arena_in, uint32_t *arena_out,
                  void *workspace, size_t ws_bytes, void *stream);
-/* Synchronise `stream`, return and clear the status kept in `workspace` (as ks_stream_status). */
+/* Synchronise `stream`, return and clear the status kept in `workspace` (as ks_stream_status).
+   Each run starts by clearing it, so this reports the latest run on that workspace. */
 int ks_batch_status(const ks_batch_plan *plan, void *workspace, void *stream);
 void ks_batch_plan_destroy(ks_batch_plan *plan);
 
 /*
- * One-shot convenience: plan, run on `workspace`, and keep the plan until the stream has
- * finished with it.  Not for graph capture (it uploads tables).
+ * One-shot convenience: plan, run on `workspace`, synchronise `stream` and free the plan, so
+ * it returns after the batch is complete.  Not for graph capture (it uploads tables).
  */
 size_t ks_batch_workspace_bytes(const ks_desc *descs, int64_t count, int32_t variant);
 int ks_mul_batch(const uint32_t *arena_in, uint32_t *arena_out, const ks_desc *descs, int64_t count,

@@ -245,39 +245,25 @@ static hipError_t timed(const char *name, hipStream_t s, F &&fn) {
     return e;
 }
 
-// ---- launching one planned product ----------------------------------------------------------------
+// ---- job emission (shared by single products and batches) --------------------------------------
 
-template <class J>
-static Launch<J> make_launch(const std::vector<J> &jobs, const Ctl &ctl, uint64_t *status, uint32_t epoch) {
-    Launch<J> L;
-    memset(&L, 0, sizeof(L));
-    L.njobs = (int64_t)jobs.size();
-    for (size_t i = 0; i < jobs.size(); ++i) L.jobs[i] = jobs[i];
-    L.total_blocks = jobs.empty() ? 0 : jobs.back().block0 + jobs.back().nblocks;
-    L.status = status;
-    L.ticket = ctl.ticket;
-    L.devstat = ctl.devstat;
-    L.epoch = epoch;
-    return L;
-}
-
-int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s) {
+// Append the jobs of one planned product.  f, g, h, ws are addresses (single products) or byte
+// offsets from the run's bases (batches); each job's block0 continues its list.
+void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t ws, JobLists &JL) {
     const Spec &sp = G.sp;
-    uint32_t *ops = reinterpret_cast<uint32_t *>(ws + G.ws_ops);
-    uint32_t *cols = reinterpret_cast<uint32_t *>(ws + G.ws_cols);
-    uint32_t *norms = reinterpret_cast<uint32_t *>(ws + G.ws_norms);
-    uint32_t *anchors = reinterpret_cast<uint32_t *>(ws + G.ws_anchors);
-    uint64_t *status = reinterpret_cast<uint64_t *>(ws + G.ws_status);
-    hipError_t err;
+    auto ops = [&](int64_t limb_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_ops + 4 * limb_off); };
+    auto cols = [&](int64_t word_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_cols + 4 * word_off); };
+    auto norms = [&](int64_t limb_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_norms + 4 * limb_off); };
+    auto anchors = [&](int64_t limb_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_anchors + 4 * limb_off); };
+    auto next_block = [](auto &list) -> int64_t {
+        return list.empty() ? 0 : list.back().block0 + list.back().nblocks;
+    };
 
-    // pack
-    std::vector<PackJob> pj;
-    int64_t blk = 0;
     for (auto &p : G.packs) {
         PackJob j;
         memset(&j, 0, sizeof(j));
-        j.coeffs = p.which ? g : f;
-        j.out = ops + p.op_off;
+        j.coeffs = reinterpret_cast<const uint32_t *>(p.which ? g : f);
+        j.out = ops(p.op_off);
         j.L = p.L;
         j.n_out = p.n_out;
         j.N = G.N;
@@ -286,69 +272,43 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
         j.bits = sp.bits;
         j.flags = p.flags;
         j.mod_p = sp.mod_p;
-        j.block0 = blk;
+        j.block0 = next_block(JL.pack);
         j.nblocks = p.blocks;
-        blk += p.blocks;
-        pj.push_back(j);
+        JL.pack.push_back(j);
     }
-    {
-        Launch<PackJob> L = make_launch(pj, ctl, status, ++ctl.epoch);
-        err = timed("pack", s, [&] { return launch_pack(L, s); });
-        if (err != hipSuccess) return KS_EHIP;
-    }
-    // multiply
-    std::vector<MulJob> mj;
-    blk = 0;
     for (auto &m : G.muls) {
         MulJob j;
         memset(&j, 0, sizeof(j));
-        j.a = ops + G.packs[m.fa].op_off;
-        j.b = ops + G.packs[m.fb].op_off;
+        j.a = ops(G.packs[m.fa].op_off);
+        j.b = ops(G.packs[m.fb].op_off);
         j.na = m.na;
         j.nb = m.nb;
-        j.cols = cols + m.cols_off;
-        j.block0 = blk;
+        j.cols = cols(m.cols_off);
+        j.block0 = next_block(JL.mul);
         j.nblocks = m.blocks;
-        blk += m.blocks;
-        mj.push_back(j);
+        JL.mul.push_back(j);
     }
-    {
-        Launch<MulJob> L = make_launch(mj, ctl, status, 0);
-        err = timed("mul_valu", s, [&] { return launch_mul_valu(L, s); });
-        if (err != hipSuccess) return KS_EHIP;
+    for (auto &c : G.chains) {
+        if (c.anchor_blocks == 0) continue;
+        auto &list = JL.anchor[sp.w_in];
+        AnchorJob j;
+        memset(&j, 0, sizeof(j));
+        j.f = reinterpret_cast<const uint32_t *>(f);
+        j.g = reinterpret_cast<const uint32_t *>(g);
+        j.lf = sp.lf;
+        j.lg = sp.lg;
+        j.w_in = sp.w_in;
+        j.sgn = sp.sgn;
+        j.par = c.par;
+        j.aw = G.aw;
+        j.K = c.K;
+        j.nseg = c.nseg;
+        j.anchors = anchors(c.anchor_off);
+        j.off_bit = G.off;
+        j.block0 = next_block(list);
+        j.nblocks = c.anchor_blocks;
+        list.push_back(j);
     }
-    // anchors depend only on the inputs
-    if (!G.chains.empty() && G.anchor_blocks > 0) {
-        std::vector<AnchorJob> aj;
-        blk = 0;
-        for (auto &c : G.chains) {
-            if (c.anchor_blocks == 0) continue;
-            AnchorJob j;
-            memset(&j, 0, sizeof(j));
-            j.f = f;
-            j.g = g;
-            j.lf = sp.lf;
-            j.lg = sp.lg;
-            j.w_in = sp.w_in;
-            j.sgn = sp.sgn;
-            j.par = c.par;
-            j.aw = G.aw;
-            j.K = c.K;
-            j.nseg = c.nseg;
-            j.anchors = anchors + c.anchor_off;
-            j.off_bit = G.off;
-            j.block0 = blk;
-            j.nblocks = c.anchor_blocks;
-            blk += c.anchor_blocks;
-            aj.push_back(j);
-        }
-        Launch<AnchorJob> L = make_launch(aj, ctl, status, 0);
-        err = timed("anchor", s, [&] { return launch_anchor(L, sp.w_in, s); });
-        if (err != hipSuccess) return KS_EHIP;
-    }
-    // normalize
-    std::vector<NormJob> nj;
-    blk = 0;
     for (auto &r : G.norms) {
         NormJob j;
         memset(&j, 0, sizeof(j));
@@ -356,10 +316,10 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
         for (int t = 0; t < r.nterms; ++t) {
             const MulGeom &m = G.muls[r.prod[t]];
             NormTerm &T = j.term[t];
-            T.cols = cols + m.cols_off;
+            T.cols = cols(m.cols_off);
             T.ncols = m.ntiles * MUL_T;
-            T.a = ops + G.packs[m.fa].op_off;
-            T.b = ops + G.packs[m.fb].op_off;
+            T.a = ops(G.packs[m.fa].op_off);
+            T.b = ops(G.packs[m.fb].op_off);
             T.na = m.na;
             T.nb = m.nb;
             T.sign = r.sign[t];
@@ -369,77 +329,132 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
         j.off_period = r.off_period;
         j.off_recip = div_recip((uint64_t)r.off_period);
         j.off_count = r.off_count;
-        j.out = norms + r.out_off;
+        j.out = norms(r.out_off);
         j.n_out = r.n_out;
         j.n_in = r.n_in;
-        j.block0 = blk;
+        j.block0 = next_block(JL.norm);
         j.nblocks = r.blocks;
-        blk += r.blocks;
-        nj.push_back(j);
+        JL.norm.push_back(j);
+    }
+    for (auto &x : G.extracts) {
+        ExtractJob j;
+        memset(&j, 0, sizeof(j));
+        j.src = norms(G.norms[x.src].out_off);
+        j.n_src = G.norms[x.src].n_out;
+        j.count = x.count;
+        j.slot = x.slot;
+        j.out = reinterpret_cast<uint32_t *>(h);
+        j.out_first = x.first;
+        j.out_step = x.step;
+        j.w_out = G.w_out;
+        j.off_bit = G.off;
+        j.mod_p = sp.mod_p;
+        j.block0 = next_block(JL.extract);
+        j.nblocks = x.blocks;
+        JL.extract.push_back(j);
+    }
+    for (auto &c : G.chains) {
+        auto &list = JL.chain[G.nw];
+        ChainJob j;
+        memset(&j, 0, sizeof(j));
+        j.A = norms(G.norms[c.A].out_off);
+        j.nA = G.norms[c.A].n_out;
+        j.B = norms(G.norms[c.B].out_off);
+        j.nB = G.norms[c.B].n_out;
+        j.m = c.m;
+        j.K = c.K;
+        j.nseg = c.nseg;
+        j.anchors = anchors(c.anchor_off);
+        j.aw = G.aw;
+        j.Nd = (int)(2 * G.N);
+        j.out = reinterpret_cast<uint32_t *>(h);
+        j.out_first = c.par;
+        j.out_step = 2;
+        j.w_out = G.w_out;
+        j.off_bit = G.off;
+        j.mod_p = sp.mod_p;
+        j.block0 = next_block(list);
+        j.nblocks = c.chain_blocks;
+        list.push_back(j);
+    }
+}
+
+template <class J>
+static int64_t list_blocks(const std::vector<J> &v) {
+    return v.empty() ? 0 : v.back().block0 + v.back().nblocks;
+}
+
+// Launch every stage of a set of job lists.  Lists of at most MAX_INLINE_JOBS jobs travel in
+// the kernel arguments; longer ones need device tables (`tables`, built by a batch plan).
+template <class J>
+static Launch<J> make_launch(const std::vector<J> &jobs, const DevList *tab, const LaunchEnv &env, uint32_t epoch) {
+    Launch<J> L;
+    memset(&L, 0, sizeof(L));
+    L.njobs = (int64_t)jobs.size();
+    L.total_blocks = list_blocks(jobs);
+    if (tab) {
+        L.table = reinterpret_cast<const J *>(tab->table);
+        L.block_job = tab->block_job;
+    } else {
+        for (size_t i = 0; i < jobs.size(); ++i) L.jobs[i] = jobs[i];
+    }
+    L.status = env.status;
+    L.ticket = env.ticket;
+    L.devstat = env.devstat;
+    L.epoch = epoch;
+    L.base_in = env.base_in;
+    L.base_out = env.base_out;
+    L.base_ws = env.base_ws;
+    return L;
+}
+
+int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, uint32_t epoch_pack,
+                 uint32_t epoch_norm, hipStream_t s) {
+    hipError_t err;
+    {
+        auto L = make_launch(JL.pack, T ? &T->pack : nullptr, env, epoch_pack);
+        err = timed("pack", s, [&] { return launch_pack(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
     }
     {
-        Launch<NormJob> L = make_launch(nj, ctl, status, ++ctl.epoch);
+        auto L = make_launch(JL.mul, T ? &T->mul : nullptr, env, 0);
+        err = timed("mul_valu", s, [&] { return launch_mul_valu(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    for (auto &kv : JL.anchor) {
+        auto L = make_launch(kv.second, T ? &T->anchor.at(kv.first) : nullptr, env, 0);
+        err = timed("anchor", s, [&] { return launch_anchor(L, kv.first, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    {
+        auto L = make_launch(JL.norm, T ? &T->norm : nullptr, env, epoch_norm);
         err = timed("normalize", s, [&] { return launch_normalize(L, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
-    // read the coefficients off
-    if (!G.extracts.empty()) {
-        std::vector<ExtractJob> xj;
-        blk = 0;
-        for (auto &x : G.extracts) {
-            ExtractJob j;
-            memset(&j, 0, sizeof(j));
-            j.src = norms + G.norms[x.src].out_off;
-            j.n_src = G.norms[x.src].n_out;
-            j.count = x.count;
-            j.slot = x.slot;
-            j.out = reinterpret_cast<uint32_t *>(h);
-            j.out_first = x.first;
-            j.out_step = x.step;
-            j.w_out = G.w_out;
-            j.off_bit = G.off;
-            j.mod_p = sp.mod_p;
-            j.block0 = blk;
-            j.nblocks = x.blocks;
-            blk += x.blocks;
-            xj.push_back(j);
-        }
-        Launch<ExtractJob> L = make_launch(xj, ctl, status, 0);
+    if (!JL.extract.empty()) {
+        auto L = make_launch(JL.extract, T ? &T->extract : nullptr, env, 0);
         err = timed("extract", s, [&] { return launch_extract(L, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
-    if (!G.chains.empty()) {
-        std::vector<ChainJob> cj;
-        blk = 0;
-        for (auto &c : G.chains) {
-            ChainJob j;
-            memset(&j, 0, sizeof(j));
-            j.A = norms + G.norms[c.A].out_off;
-            j.nA = G.norms[c.A].n_out;
-            j.B = norms + G.norms[c.B].out_off;
-            j.nB = G.norms[c.B].n_out;
-            j.m = c.m;
-            j.K = c.K;
-            j.nseg = c.nseg;
-            j.anchors = anchors + c.anchor_off;
-            j.aw = G.aw;
-            j.Nd = (int)(2 * G.N);
-            j.out = reinterpret_cast<uint32_t *>(h);
-            j.out_first = c.par;
-            j.out_step = 2;
-            j.w_out = G.w_out;
-            j.off_bit = G.off;
-            j.mod_p = sp.mod_p;
-            j.block0 = blk;
-            j.nblocks = c.chain_blocks;
-            blk += c.chain_blocks;
-            cj.push_back(j);
-        }
-        Launch<ChainJob> L = make_launch(cj, ctl, status, 0);
-        err = timed("recon", s, [&] { return launch_chain(L, G.nw, s); });
+    for (auto &kv : JL.chain) {
+        auto L = make_launch(kv.second, T ? &T->chain.at(kv.first) : nullptr, env, 0);
+        err = timed("recon", s, [&] { return launch_chain(L, kv.first, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     return KS_OK;
+}
+
+int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s) {
+    JobLists JL;
+    emit_jobs(G, reinterpret_cast<uintptr_t>(f), reinterpret_cast<uintptr_t>(g), reinterpret_cast<uintptr_t>(h),
+              reinterpret_cast<uintptr_t>(ws), JL);
+    LaunchEnv env;
+    env.status = reinterpret_cast<uint64_t *>(ws + G.ws_status);
+    env.ticket = ctl.ticket;
+    env.devstat = ctl.devstat;
+    const uint32_t ep = ++ctl.epoch;
+    const uint32_t en = ++ctl.epoch;
+    return launch_lists(JL, nullptr, env, ep, en, s);
 }
 
 // ---- per-stream pools --------------------------------------------------------------------------
@@ -490,7 +505,7 @@ static int get_pool(hipStream_t s, size_t need, Pool **out) {
     return KS_OK;
 }
 
-static int read_status(uint32_t *devstat, hipStream_t s) {
+int read_status(uint32_t *devstat, hipStream_t s) {
     if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;
     uint32_t v = 0;
     if (hipMemcpy(&v, devstat, 4, hipMemcpyDeviceToHost) != hipSuccess) return KS_EHIP;
@@ -503,7 +518,7 @@ static int read_status(uint32_t *devstat, hipStream_t s) {
     return KS_OK;
 }
 
-static int device_ok() {
+int device_ok() {
     static int state = 0;  // 0 unknown, 1 ok, -1 not usable
     if (state == 0) {
         int dev = 0;
@@ -530,7 +545,7 @@ int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_
     return KS_OK;
 }
 
-static int bitlen_u64(uint64_t x) {
+int bitlen_u64(uint64_t x) {
     int n = 0;
     while (x) { ++n; x >>= 1; }
     return n;
@@ -676,16 +691,3 @@ int ks_profile_read(const char *name, int64_t *launches, double *total_ms) {
 
 }  // extern "C"
 
-// ---- batches (planned in ks_batch.cpp once available) -------------------------------------------
-extern "C" {
-int ks_batch_plan_create(const ks_desc *, int64_t, int32_t, ks_batch_plan **) { return KS_EUNSUPPORTED; }
-int64_t ks_batch_plan_bad_index(void) { return -1; }
-size_t ks_batch_plan_workspace_bytes(const ks_batch_plan *) { return 0; }
-int ks_batch_run(const ks_batch_plan *, const uint32_t *, uint32_t *, void *, size_t, void *) { return KS_EUNSUPPORTED; }
-int ks_batch_status(const ks_batch_plan *, void *, void *) { return KS_EUNSUPPORTED; }
-void ks_batch_plan_destroy(ks_batch_plan *) {}
-size_t ks_batch_workspace_bytes(const ks_desc *, int64_t, int32_t) { return 0; }
-int ks_mul_batch(const uint32_t *, uint32_t *, const ks_desc *, int64_t, int32_t, void *, size_t, void *) {
-    return KS_EUNSUPPORTED;
-}
-}

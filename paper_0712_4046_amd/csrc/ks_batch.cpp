@@ -1,0 +1,228 @@
+// ks_batch.cpp -- many independent products planned once and run as one launch sequence.
+//
+// Every product of a batch is planned like a single product (ks_api.cpp); their jobs are
+// concatenated per stage, so each stage is one kernel launch over all products (one per
+// template parameter for the anchor and chain stages).  Job tables and block -> job maps live
+// in device memory owned by the plan; pointers in them are byte offsets from the run's
+// arenas and workspace.  A run allocates nothing and copies nothing from the host: it clears
+// the look-back words with a kernel and launches the stages, so it can be graph-captured.
+//
+// Workspace layout (bytes): [0, 8) device status word, [64, 80) block-ticket counters,
+// [80, 80 + 8 S) look-back status words, then each product's scratch, 256-byte aligned.
+// Every run clears [0, 80 + 8 S) first, so a fresh (uninitialised) workspace needs no set-up.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/ks.h"
+#include "ks_jobs.h"
+#include "ks_launch.h"
+#include "ks_plan.h"
+
+namespace ks {
+
+int read_status(uint32_t *devstat, hipStream_t s);
+int device_ok();
+int bitlen_u64(uint64_t x);
+
+static thread_local int64_t g_bad_index = -1;
+
+static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+template <class J>
+static int upload(const std::vector<J> &jobs, DevList &d, std::vector<void *> &allocs) {
+    if (jobs.empty()) return KS_OK;
+    const int64_t nb = jobs.back().block0 + jobs.back().nblocks;
+    std::vector<uint32_t> map((size_t)nb);
+    for (size_t i = 0; i < jobs.size(); ++i)
+        for (int64_t b = 0; b < jobs[i].nblocks; ++b) map[(size_t)(jobs[i].block0 + b)] = (uint32_t)i;
+    void *t = nullptr, *m = nullptr;
+    if (hipMalloc(&t, sizeof(J) * jobs.size()) != hipSuccess) return KS_ENOMEM;
+    allocs.push_back(t);
+    if (hipMalloc(&m, sizeof(uint32_t) * std::max<int64_t>(nb, 1)) != hipSuccess) return KS_ENOMEM;
+    allocs.push_back(m);
+    if (hipMemcpy(t, jobs.data(), sizeof(J) * jobs.size(), hipMemcpyHostToDevice) != hipSuccess) return KS_EHIP;
+    if (nb > 0 && hipMemcpy(m, map.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice) != hipSuccess)
+        return KS_EHIP;
+    d.table = t;
+    d.block_job = reinterpret_cast<uint32_t *>(m);
+    return KS_OK;
+}
+
+template <class J>
+static int64_t blocks_of(const std::vector<J> &v) {
+    return v.empty() ? 0 : v.back().block0 + v.back().nblocks;
+}
+
+}  // namespace ks
+
+struct ks_batch_plan {
+    int64_t count = 0;
+    ks::JobLists JL;
+    ks::DevTables T;
+    std::vector<void *> allocs;
+    int64_t status_words = 0;
+    int64_t ws_bytes = 0;
+    double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
+    int variant = -1;
+};
+
+using namespace ks;
+
+static const int64_t WS_DEVSTAT = 0, WS_TICKET = 64, WS_STATUS = 80;
+
+extern "C" {
+
+int64_t ks_batch_plan_bad_index(void) { return g_bad_index; }
+
+void ks_batch_plan_destroy(ks_batch_plan *plan) {
+    if (!plan) return;
+    for (void *p : plan->allocs) hipFree(p);
+    delete plan;
+}
+
+int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, ks_batch_plan **out) {
+    g_bad_index = -1;
+    if (!descs || !out || count < 1) return KS_EINVAL;
+    *out = nullptr;
+    const int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_VALU | KS_ENGINE_MFMA;
+    if (variant & ~known) return KS_EINVAL;
+    if (variant & KS_ENGINE_MFMA) return KS_EUNSUPPORTED;
+    const int v = variant & KS_VARIANT_MASK;
+    if (v != KS_VARIANT_AUTO && v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_KS4) return KS_EINVAL;
+    ks_batch_plan *P = new ks_batch_plan();
+    P->count = count;
+    int64_t off = align256(WS_STATUS);  // product scratch starts after the status words (fixed below)
+    std::vector<Geom> geoms((size_t)count);
+    std::vector<int64_t> inst_off((size_t)count);
+    int64_t scratch = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const ks_desc &d = descs[i];
+        Spec sp;
+        const bool mod = (d.flags & KS_MOD) != 0;
+        if (d.flags & ~(KS_SIGNED | KS_MOD)) { g_bad_index = i; delete P; return KS_EINVAL; }
+        if (mod) {
+            const uint64_t p = d.mod_p;
+            if (p < 3 || !(p & 1) || (p >> 62) || (d.flags & KS_SIGNED) || (d.f_off & 1) || (d.g_off & 1) ||
+                (d.h_off & 1)) {
+                g_bad_index = i;
+                delete P;
+                return KS_EINVAL;
+            }
+            sp = Spec{d.len_f, d.len_g, bitlen_u64(p - 1), 2, false, p, v, KS_ENGINE_VALU};
+        } else {
+            sp = Spec{d.len_f, d.len_g, d.coeff_bits, (d.coeff_bits + 31) / 32, (d.flags & KS_SIGNED) != 0, 0, v,
+                      KS_ENGINE_VALU};
+        }
+        if (validate_spec(sp.lf, sp.lg, sp.bits, v, true) != KS_OK) { g_bad_index = i; delete P; return KS_EINVAL; }
+        int rc = plan_product(sp, geoms[(size_t)i]);
+        if (rc != KS_OK) { g_bad_index = i; delete P; return rc; }
+        inst_off[(size_t)i] = scratch;
+        scratch += align256(geoms[(size_t)i].ws_status);  // the product's own scratch regions
+        P->limb_mults += geoms[(size_t)i].limb_mults;
+        P->school_mults += geoms[(size_t)i].school_mults;
+        P->hbm_bytes += geoms[(size_t)i].hbm_bytes;
+        int rv = geoms[(size_t)i].variant;
+        P->variant = i == 0 ? rv : (P->variant == rv ? rv : -1);
+    }
+    // jobs with offsets relative to the run's bases; scratch placed after the status words,
+    // whose count is only known once every job is emitted -- emit relative to 0, then shift
+    JobLists JL;
+    for (int64_t i = 0; i < count; ++i) {
+        const ks_desc &d = descs[i];
+        emit_jobs(geoms[(size_t)i], (uintptr_t)(4 * d.f_off), (uintptr_t)(4 * d.g_off), (uintptr_t)(4 * d.h_off),
+                  (uintptr_t)inst_off[(size_t)i], JL);
+    }
+    P->status_words = std::max(blocks_of(JL.pack), blocks_of(JL.norm));
+    const int64_t base = align256(WS_STATUS + 8 * std::max<int64_t>(P->status_words, 1));
+    auto sh = [&](auto *&ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(reinterpret_cast<uintptr_t>(ptr) + base); };
+    for (auto &j : JL.pack) sh(j.out);
+    for (auto &j : JL.mul) { sh(j.a); sh(j.b); sh(j.cols); }
+    for (auto &kv : JL.anchor) for (auto &j : kv.second) sh(j.anchors);
+    for (auto &j : JL.norm) {
+        for (int q = 0; q < j.nterms; ++q) { sh(j.term[q].cols); sh(j.term[q].a); sh(j.term[q].b); }
+        sh(j.out);
+    }
+    for (auto &j : JL.extract) sh(j.src);
+    for (auto &kv : JL.chain) for (auto &j : kv.second) { sh(j.A); sh(j.B); sh(j.anchors); }
+    P->ws_bytes = base + scratch;
+    (void)off;
+
+    int rc = KS_OK;
+    if (rc == KS_OK) rc = upload(JL.pack, P->T.pack, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.mul, P->T.mul, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.norm, P->T.norm, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.extract, P->T.extract, P->allocs);
+    for (auto &kv : JL.anchor) if (rc == KS_OK) rc = upload(kv.second, P->T.anchor[kv.first], P->allocs);
+    for (auto &kv : JL.chain) if (rc == KS_OK) rc = upload(kv.second, P->T.chain[kv.first], P->allocs);
+    if (rc != KS_OK) { ks_batch_plan_destroy(P); return rc; }
+    P->JL = std::move(JL);
+    *out = P;
+    return KS_OK;
+}
+
+size_t ks_batch_plan_workspace_bytes(const ks_batch_plan *plan) { return plan ? (size_t)plan->ws_bytes : 0; }
+
+int ks_batch_plan_info(const ks_batch_plan *plan, ks_plan_info *out) {
+    if (!plan || !out) return KS_EINVAL;
+    memset(out, 0, sizeof(*out));
+    out->variant = plan->variant;
+    out->engine = KS_ENGINE_VALU;
+    out->n_products = (int32_t)std::min<int64_t>(plan->count, 0x7fffffff);
+    out->limb_mults = plan->limb_mults;
+    out->schoolbook_limb_mults = plan->school_mults;
+    out->hbm_bytes = plan->hbm_bytes;
+    return KS_OK;
+}
+
+int ks_batch_run(const ks_batch_plan *plan, const uint32_t *arena_in, uint32_t *arena_out, void *workspace,
+                 size_t ws_bytes, void *stream) {
+    if (!plan || !arena_in || !arena_out || !workspace) return KS_EINVAL;
+    if (ws_bytes < (size_t)plan->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255)) return KS_EINVAL;
+    if (device_ok() != 1) return KS_EUNSUPPORTED;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = reinterpret_cast<char *>(workspace);
+    // the status word, ticket counters and look-back words start every run at zero (a kernel,
+    // not a memset, so the run can be graph-captured); the status thus reports the latest run
+    if (launch_fill_zero(reinterpret_cast<uint64_t *>(ws), WS_STATUS / 8 + plan->status_words, s) != hipSuccess)
+        return KS_EHIP;
+    LaunchEnv env;
+    env.status = reinterpret_cast<uint64_t *>(ws + WS_STATUS);
+    env.ticket = reinterpret_cast<uint64_t *>(ws + WS_TICKET);
+    env.devstat = reinterpret_cast<uint32_t *>(ws + WS_DEVSTAT);
+    env.base_in = reinterpret_cast<uintptr_t>(arena_in);
+    env.base_out = reinterpret_cast<uintptr_t>(arena_out);
+    env.base_ws = reinterpret_cast<uintptr_t>(ws);
+    return launch_lists(plan->JL, &plan->T, env, 1u, 2u, s);
+}
+
+int ks_batch_status(const ks_batch_plan *plan, void *workspace, void *stream) {
+    if (!plan || !workspace) return KS_EINVAL;
+    return read_status(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(workspace) + WS_DEVSTAT),
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t ks_batch_workspace_bytes(const ks_desc *descs, int64_t count, int32_t variant) {
+    ks_batch_plan *P = nullptr;
+    if (ks_batch_plan_create(descs, count, variant, &P) != KS_OK) return 0;
+    size_t b = (size_t)P->ws_bytes;
+    ks_batch_plan_destroy(P);
+    return b;
+}
+
+int ks_mul_batch(const uint32_t *arena_in, uint32_t *arena_out, const ks_desc *descs, int64_t count, int32_t variant,
+                 void *workspace, size_t ws_bytes, void *stream) {
+    ks_batch_plan *P = nullptr;
+    int rc = ks_batch_plan_create(descs, count, variant, &P);
+    if (rc != KS_OK) return rc;
+    rc = ks_batch_run(P, arena_in, arena_out, workspace, ws_bytes, stream);
+    // the plan's tables must outlive the kernels that read them
+    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess && rc == KS_OK) rc = KS_EHIP;
+    ks_batch_plan_destroy(P);
+    return rc;
+}
+
+}  // extern "C"

@@ -181,7 +181,7 @@ struct BlockCarryScan {
 
 // ---- job lookup: block index -> (job, block within job) ----------------------------------------
 // Inline jobs: all block0 values are loaded at once (independent scalar loads, one round
-// trip) rather than walked one after another.  Device tables: binary search.
+// trip).  Device tables: one load from the block -> job map.
 template <class J>
 __device__ __forceinline__ J find_job(const Launch<J> &L, int64_t blk, int64_t &local) {
     if (L.table == nullptr) {
@@ -194,13 +194,57 @@ __device__ __forceinline__ J find_job(const Launch<J> &L, int64_t blk, int64_t &
         local = blk - L.jobs[j].block0;
         return L.jobs[j];
     }
-    int64_t lo = 0, hi = L.njobs - 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (L.table[mid].block0 <= blk) lo = mid; else hi = mid - 1;
+    const J job = L.table[L.block_job[blk]];
+    local = blk - job.block0;
+    return job;
+}
+
+template <class T>
+__device__ __forceinline__ T *at(uintptr_t base, T *rel) {
+    return reinterpret_cast<T *>(base + reinterpret_cast<uintptr_t>(rel));
+}
+
+// turn a job's relative pointers into addresses
+template <class J> __device__ __forceinline__ void rebase(J &, const Launch<J> &);
+template <> __device__ __forceinline__ void rebase(PackJob &J, const Launch<PackJob> &L) {
+    J.coeffs = at(L.base_in, J.coeffs);
+    J.out = at(L.base_ws, J.out);
+}
+template <> __device__ __forceinline__ void rebase(MulJob &J, const Launch<MulJob> &L) {
+    J.a = at(L.base_ws, J.a);
+    J.b = at(L.base_ws, J.b);
+    J.cols = at(L.base_ws, J.cols);
+}
+template <> __device__ __forceinline__ void rebase(NormJob &J, const Launch<NormJob> &L) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        J.term[q].cols = at(L.base_ws, J.term[q].cols);
+        J.term[q].a = at(L.base_ws, J.term[q].a);
+        J.term[q].b = at(L.base_ws, J.term[q].b);
     }
-    local = blk - L.table[lo].block0;
-    return L.table[lo];
+    J.out = at(L.base_ws, J.out);
+}
+template <> __device__ __forceinline__ void rebase(ExtractJob &J, const Launch<ExtractJob> &L) {
+    J.src = at(L.base_ws, J.src);
+    J.out = at(L.base_out, J.out);
+}
+template <> __device__ __forceinline__ void rebase(AnchorJob &J, const Launch<AnchorJob> &L) {
+    J.f = at(L.base_in, J.f);
+    J.g = at(L.base_in, J.g);
+    J.anchors = at(L.base_ws, J.anchors);
+}
+template <> __device__ __forceinline__ void rebase(ChainJob &J, const Launch<ChainJob> &L) {
+    J.A = at(L.base_ws, J.A);
+    J.B = at(L.base_ws, J.B);
+    J.anchors = at(L.base_ws, J.anchors);
+    J.out = at(L.base_out, J.out);
+}
+
+template <class J>
+__device__ __forceinline__ J get_job(const Launch<J> &L, int64_t blk, int64_t &local) {
+    J job = find_job(L, blk, local);
+    rebase(job, L);
+    return job;
 }
 
 // ---- small helpers ------------------------------------------------------------------------------

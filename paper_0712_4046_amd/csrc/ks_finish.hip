@@ -41,7 +41,7 @@ __device__ __forceinline__ uint64_t mod_step(uint64_t r, uint32_t word, uint64_t
 
 __global__ __launch_bounds__(EXTRACT_TPB) void extract_kernel(Launch<ExtractJob> L) {
     int64_t local;
-    const ExtractJob J = find_job(L, (int64_t)blockIdx.x, local);
+    const ExtractJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int64_t k = local * EXTRACT_TPB + threadIdx.x;
     if (k >= J.count) return;
     const int64_t s0 = k * J.slot;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(ANCHOR_TPB) void anchor_kernel(Launch<AnchorJob> L)
     constexpr int AW = 2 * W + 2;
     __shared__ uint32_t s_acc[ANCHOR_TPB / 64][AW];
     int64_t local;
-    const AnchorJob J = find_job(L, (int64_t)blockIdx.x, local);
+    const AnchorJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int64_t s = local + 1;
     const int64_t k = 2 * (s * J.K - 1) + J.par;
     int64_t lo = k - (J.lg - 1);
@@ -313,7 +313,7 @@ template <int NW>
 __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
     constexpr int G = ChainGroup<NW>::G;
     int64_t local;
-    const ChainJob J = find_job(L, (int64_t)blockIdx.x, local);
+    const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int64_t s = local * CHAIN_TPB + threadIdx.x;
     if (s >= J.nseg) return;
     const int Nd = J.Nd;

@@ -158,10 +158,14 @@ struct ChainJob {
 // (recip = 0 stands for d = 1): a reciprocal multiply instead of a 64-bit division
 inline uint64_t div_recip(uint64_t d) { return d <= 1 ? 0 : (uint64_t)(~0ull / d) + 1; }
 
+// Pointer fields of a job are addresses relative to a base: inputs (f, g) to base_in,
+// outputs (h) to base_out, scratch to base_ws.  Single products pass absolute addresses with
+// zero bases; batch plans store byte offsets once and the bases arrive with each run.
 template <class J>
 struct Launch {
     J jobs[MAX_INLINE_JOBS];
-    const J *table;  // device table (batches); null when jobs are inline
+    const J *table;              // device job table (batches); null when jobs are inline
+    const uint32_t *block_job;   // device map block -> job index (with table)
     int64_t njobs;
     int64_t total_blocks;
     uint64_t *status;  // look-back words, one per block of the launch
@@ -169,6 +173,7 @@ struct Launch {
     uint32_t *devstat;
     uint32_t epoch;
     uint32_t pad;
+    uintptr_t base_in, base_out, base_ws;
 };
 
 }  // namespace ks

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
     __shared__ uint32_t s_hi[MUL_WAVES][MUL_T];
 
     int64_t local;
-    const MulJob J = find_job(L, (int64_t)blockIdx.x, local);
+    const MulJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t k0 = local * MUL_T;
     int64_t ilo = k0 - J.nb + 1;

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <vector>
+
+#include "ks_jobs.h"
 
 namespace ks {
 
@@ -70,7 +73,37 @@ struct Ctl {
     uint32_t epoch = 0;
 };
 
+// jobs of one or many products, per stage (anchor and chain lists keyed by template parameter)
+struct JobLists {
+    std::vector<PackJob> pack;
+    std::vector<MulJob> mul;
+    std::vector<NormJob> norm;
+    std::vector<ExtractJob> extract;
+    std::map<int, std::vector<AnchorJob>> anchor;  // by limbs per input coefficient
+    std::map<int, std::vector<ChainJob>> chain;    // by words per reconstruction digit
+};
+
+// a job list uploaded to the device: the table and its block -> job map
+struct DevList {
+    void *table = nullptr;
+    uint32_t *block_job = nullptr;
+};
+struct DevTables {
+    DevList pack, mul, norm, extract;
+    std::map<int, DevList> anchor, chain;
+};
+
+struct LaunchEnv {
+    uint64_t *status = nullptr;
+    uint64_t *ticket = nullptr;
+    uint32_t *devstat = nullptr;
+    uintptr_t base_in = 0, base_out = 0, base_ws = 0;
+};
+
 int plan_product(const Spec &sp, Geom &G);
+void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t ws, JobLists &JL);
+int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, uint32_t epoch_pack,
+                 uint32_t epoch_norm, hipStream_t s);
 int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s);
 int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_signed);
 

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) {
     __syncthreads();
     const int64_t blk = s_ticket;
     int64_t local;
-    const PackJob J = find_job(L, blk, local);
+    const PackJob J = get_job(L, blk, local);
     const int tid = threadIdx.x;
     const int64_t jb = local * SCAN_BL;
     const int64_t jlo = jb - 2, jhi = jb + SCAN_BL + 1;  // columns [jlo, jhi)
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) 
     __syncthreads();
     const int64_t blk = s_ticket;
     int64_t local;
-    const NormJob J = find_job(L, blk, local);
+    const NormJob J = get_job(L, blk, local);
     const int tid = threadIdx.x;
     const int64_t jb = local * SCAN_BL;
     const int64_t j0 = jb + (int64_t)tid * SCAN_IPT;
@@ -261,6 +261,20 @@ __global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) 
         const uint32_t lo = s_limb[li];
         J.out[o] = r ? ((lo >> r) | (s_limb[li + 1] << (32 - r))) : lo;
     }
+}
+
+// ---- clearing scratch words (a kernel rather than a memset, so runs can be graph-captured) ------
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint64_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
+hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
 }
 
 // ---- host launchers -----------------------------------------------------------------------------

@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
         "ks_batch_plan_create": ([P, i64, i32, ctypes.POINTER(P)], ctypes.c_int),
         "ks_batch_plan_bad_index": ([], i64),
         "ks_batch_plan_workspace_bytes": ([P], sz),
+        "ks_batch_plan_info": ([P, ctypes.POINTER(PlanInfo)], ctypes.c_int),
         "ks_batch_run": ([P, P, P, P, sz, P], ctypes.c_int),
         "ks_batch_status": ([P, P, P], ctypes.c_int),
         "ks_batch_plan_destroy": ([P], None),
@@ -199,3 +200,114 @@ def profile_read(name: str):
     ms = ctypes.c_double()
     _check(lib().ks_profile_read(name.encode(), ctypes.byref(n), ctypes.byref(ms)), "ks_profile_read")
     return int(n.value), float(ms.value)
+
+
+# ---- batches ---------------------------------------------------------------------------------
+
+class Batch:
+    """Host-side layout of many products in two arenas (marshalling only).
+
+    add(f, g, bits, signed) appends limb arrays; add_mod(f, g, p) appends residues.  The
+    arena_in / descriptor arrays then go to BatchPlan; out_slice(i) locates product i's output.
+    """
+
+    def __init__(self):
+        self._in = []
+        self._in_len = 0
+        self._out_len = 0
+        self.descs = []
+        self._out = []  # (offset, count, width, kind)
+
+    def _push(self, a: np.ndarray) -> int:
+        off = self._in_len
+        a = np.ascontiguousarray(a).view(np.uint32).reshape(-1)
+        if off % 2:
+            self._in.append(np.zeros(1, dtype=np.uint32))
+            self._in_len += 1
+            off += 1
+        self._in.append(a)
+        self._in_len += a.size
+        return off
+
+    def add(self, f: np.ndarray, g: np.ndarray, bits: int, signed: bool) -> int:
+        lf, lg = f.shape[0], g.shape[0]
+        fo, go = self._push(f), self._push(g)
+        wo = out_limbs(lf, lg, bits)
+        ho = self._out_len
+        self._out_len += (lf + lg - 1) * wo
+        self.descs.append((fo, go, ho, lf, lg, bits, KS_SIGNED if signed else 0, 0))
+        self._out.append((ho, lf + lg - 1, wo, "z"))
+        return len(self.descs) - 1
+
+    def add_mod(self, f: np.ndarray, g: np.ndarray, p: int) -> int:
+        lf, lg = len(f), len(g)
+        fo, go = self._push(np.asarray(f, dtype=np.uint64)), self._push(np.asarray(g, dtype=np.uint64))
+        if self._out_len % 2:
+            self._out_len += 1
+        ho = self._out_len
+        self._out_len += 2 * (lf + lg - 1)
+        self.descs.append((fo, go, ho, lf, lg, 0, KS_MOD, p))
+        self._out.append((ho, lf + lg - 1, 2, "mod"))
+        return len(self.descs) - 1
+
+    def arena_in(self) -> np.ndarray:
+        return np.concatenate(self._in) if self._in else np.zeros(1, dtype=np.uint32)
+
+    def out_words(self) -> int:
+        return max(self._out_len, 1)
+
+    def desc_array(self):
+        arr = (Desc * len(self.descs))()
+        for i, d in enumerate(self.descs):
+            arr[i] = Desc(*d)
+        return arr
+
+    def result(self, arena_out: np.ndarray, i: int) -> np.ndarray:
+        off, count, width, kind = self._out[i]
+        a = arena_out[off:off + count * width]
+        return a.view(np.uint64) if kind == "mod" else a.reshape(count, width)
+
+
+class BatchPlan:
+    """A planned batch (ks_batch_plan_*): tables live on the device until close()."""
+
+    def __init__(self, descs, variant: str = "auto", engine=None):
+        self._descs = descs
+        h = ctypes.c_void_p()
+        flags = KS_VARIANT[variant] | KS_ENGINE[engine]
+        rc = lib().ks_batch_plan_create(ctypes.cast(descs, ctypes.c_void_p), len(descs), flags, ctypes.byref(h))
+        if rc != KS_OK:
+            raise KSError(rc, f"ks_batch_plan_create (descriptor {lib().ks_batch_plan_bad_index()})")
+        self.handle = h
+        self.workspace_bytes = int(lib().ks_batch_plan_workspace_bytes(h))
+
+    def info(self) -> dict:
+        info = PlanInfo()
+        _check(lib().ks_batch_plan_info(self.handle, ctypes.byref(info)), "ks_batch_plan_info")
+        return {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+
+    def run(self, arena_in, arena_out, workspace, stream=None):
+        rc = lib().ks_batch_run(self.handle, ctypes.c_void_p(arena_in.data_ptr()), ctypes.c_void_p(arena_out.data_ptr()),
+                                ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                                _stream_ptr(stream))
+        _check(rc, "ks_batch_run")
+
+    def status(self, workspace, stream=None) -> int:
+        return int(lib().ks_batch_status(self.handle, ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().ks_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def alloc_workspace(nbytes: int, device="cuda"):
+    """A 256-byte aligned device buffer (torch allocations are at least 512-byte aligned)."""
+    import torch
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
