@@ -24,9 +24,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# vector-ALU peak for the limb multiplier: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
-# v_mad_u64_u32 (32x32+64 -> 64) every 4 cycles per lane (quarter rate) -> 9.83e12 limb-mults/s
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 4 / 1e12
+# vector-ALU peak for the limb multiplier: one limb-mult is a v_mad_u64_u32 (32x32+64 -> 64)
+# plus a v_addc (carry into the top word of a 96-bit column sum), both issuing at full rate:
+# 256 CUs x 64 lanes x 2.4 GHz / 2 instructions = 19.66e12 limb-mults/s
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
