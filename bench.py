@@ -29,6 +29,16 @@ sys.path.insert(0, ROOT)
 # 256 CUs x 64 lanes x 2.4 GHz / 2 instructions = 19.66e12 limb-mults/s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated) for
+# this workload's four-point product; see profiles/config2_ks4_hbm_traffic.txt.  A kernel whose
+# code changed after the counters were taken has no entry (traffic reported as null).
+MEASURED_TRAFFIC = {
+    "mul_valu": 1641728,
+    "normalize": 1602355,
+    "pack": 610737,
+    "anchor": 688597,
+    "recon": 661824,
+}
 
 
 def parse():
@@ -86,23 +96,25 @@ def main():
     torch.cuda.synchronize()
     ks.profile_enable(False)
     kern = {}
-    for name in ("pack", "mul_valu", "normalize", "anchor", "recon", "extract"):
+    for name in ("pack", "mul_valu", "mul_mfma", "normalize", "anchor", "recon", "extract"):
         n, ms = ks.profile_read(name)
         if n:
             kern[name] = {"launches": n, "avg_us": 1000.0 * ms / n}
     dom = max(kern, key=lambda k: kern[k]["avg_us"])
     p4 = plans["ks4"]
-    if dom == "mul_valu":
-        ops = p4["schoolbook_limb_mults"]
-        achieved = ops / (kern[dom]["avg_us"] * 1e-6) / 1e12
+    sec = kern[dom]["avg_us"] * 1e-6
+    traffic = MEASURED_TRAFFIC.get(dom) if args.workload == "config2" else None
+    if dom in ("mul_valu", "anchor"):
+        ops = p4["schoolbook_limb_mults"] if dom == "mul_valu" else p4["anchor_limb_mults"]
+        achieved = ops / sec / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
                 "op": "32x32->64-bit limb multiply-accumulate", "ops_per_launch": ops}
     else:
-        nbytes = p4["hbm_bytes"]
-        achieved = nbytes / (kern[dom]["avg_us"] * 1e-6) / 1e9
+        nbytes = {"pack": p4["pack_bytes"], "normalize": p4["normalize_bytes"]}.get(dom, p4["finish_bytes"])
+        achieved = nbytes / sec / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nbytes}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": nbytes}
 
     # bit-exact check of every variant against the oracle (also the CPU baseline sample)
     cpu = None

@@ -188,6 +188,10 @@ typedef struct ks_plan_info {
     double limb_mults;        /* 32x32-bit partial products of the multiplier actually run */
     double schoolbook_limb_mults; /* sum over products of (limbs of a) * (limbs of b) */
     double hbm_bytes;         /* algorithmic bytes: inputs + outputs + operands + products */
+    double pack_bytes;        /* per stage, algorithmic bytes moved: inputs read + operands written */
+    double normalize_bytes;   /*   product column sums read once + recombined values written       */
+    double finish_bytes;      /*   recombined values read + h written (extract or reconstruction)  */
+    double anchor_limb_mults; /*   limb products of the reconstruction anchors (KS4)              */
 } ks_plan_info;
 
 int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, ks_plan_info *out);

@@ -196,7 +196,7 @@ int plan_product(const Spec &sp, Geom &G) {
                 G.chains.push_back(c);
                 G.anchor_blocks += c.anchor_blocks;
                 G.chain_blocks += c.chain_blocks;
-                G.limb_mults += (double)(c.nseg - 1) * std::min(lf, lg) * sp.w_in * sp.w_in;
+                G.anchor_mults += (double)(c.nseg - 1) * std::min(lf, lg) * sp.w_in * sp.w_in;
             }
             G.anchor_limbs = aoff;
         }
@@ -217,6 +217,12 @@ int plan_product(const Spec &sp, Geom &G) {
     const double in_bytes = 4.0 * sp.w_in * (lf + lg);
     const double out_bytes = sp.mod_p ? 8.0 * G.D : 4.0 * G.w_out * G.D;
     G.hbm_bytes = in_bytes + out_bytes + 2.0 * 4.0 * G.op_limbs + 2.0 * 4.0 * npts * prod_limbs;
+    G.limb_mults += G.anchor_mults;
+    double norm_out = 0;
+    for (auto &r : G.norms) norm_out += 4.0 * r.n_out;
+    G.pack_bytes = in_bytes + 4.0 * G.op_limbs;
+    G.normalize_bytes = 12.0 * npts * prod_limbs + norm_out;
+    G.finish_bytes = norm_out + out_bytes;
     return KS_OK;
 }
 
@@ -559,7 +565,7 @@ using namespace ks;
 
 extern "C" {
 
-int32_t ks_version(void) { return 100; }
+int32_t ks_version(void) { return 101; }
 
 const char *ks_strerror(int code) {
     switch (code) {
@@ -600,6 +606,10 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
     out->limb_mults = G.limb_mults;
     out->schoolbook_limb_mults = G.school_mults;
     out->hbm_bytes = G.hbm_bytes;
+    out->pack_bytes = G.pack_bytes;
+    out->normalize_bytes = G.normalize_bytes;
+    out->finish_bytes = G.finish_bytes;
+    out->anchor_limb_mults = G.anchor_mults;
     return KS_OK;
 }
 

@@ -35,7 +35,9 @@ class PlanInfo(ctypes.Structure):
                 ("slot_bits", ctypes.c_int32), ("n_products", ctypes.c_int32), ("out_limbs", ctypes.c_int32),
                 ("operand_limbs_f", ctypes.c_int64), ("operand_limbs_g", ctypes.c_int64),
                 ("limb_mults", ctypes.c_double), ("schoolbook_limb_mults", ctypes.c_double),
-                ("hbm_bytes", ctypes.c_double)]
+                ("hbm_bytes", ctypes.c_double), ("pack_bytes", ctypes.c_double),
+                ("normalize_bytes", ctypes.c_double), ("finish_bytes", ctypes.c_double),
+                ("anchor_limb_mults", ctypes.c_double)]
 
 
 class Desc(ctypes.Structure):

@@ -1,0 +1,90 @@
+#!/usr/bin/env python3
+"""Helpers for rocprofv3 measurements of the library (used to make the files in profiles/).
+
+    python -m paper_0712_4046_amd.prof_tools workload            # counter-run workload
+    python -m paper_0712_4046_amd.prof_tools summarize DB "cmd"  # kernel-trace summary table
+    python -m paper_0712_4046_amd.prof_tools counters FETCH_DB WRITE_DB   # HBM bytes per kernel
+
+The workload is a plain device copy of known size (to calibrate FETCH_SIZE / WRITE_SIZE) and
+then the benchmark product (one Z[x] product, L = 4096, signed 64-bit coefficients, seed 2)
+through the four-point variant.
+"""
+import os
+import sqlite3
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_MIB = 256
+
+
+def workload(reps: int = 5):
+    sys.path.insert(0, ROOT)
+    import torch
+    from paper_0712_4046_amd import ks
+    from paper_0712_4046_amd import workloads as wl
+    src = torch.ones(COPY_MIB * 1024 * 1024 // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # known traffic: COPY_MIB MiB read and COPY_MIB MiB written
+    torch.cuda.synchronize()
+    P = wl.config2()
+    tf, tg = ks.to_device(P.f), ks.to_device(P.g)
+    for _ in range(reps):
+        ks.mul(tf, tg, P.bits, "ks4", P.signed)
+    ks.check()
+    print("workload done", flush=True)
+
+
+def summarize(db: str, cmd: str = ""):
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
+        "from kernels group by name order by sum(duration) desc").fetchall()
+    print("# rocprofv3 --kernel-trace --stats summary")
+    print(f"# command: {cmd}")
+    print("# durations in microseconds")
+    print(f"{'kernel':60s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}")
+    for name, n, tot, avg, mn, mx in rows:
+        short = name if len(name) <= 60 else name[:57] + "..."
+        print(f"{short:60s} {n:6d} {tot / 1e3:11.1f} {avg / 1e3:9.2f} {mn / 1e3:9.2f} {mx / 1e3:9.2f}")
+
+
+def counter_per_kernel(db: str):
+    """(kernel name -> list of per-dispatch counter values) from a --pmc run."""
+    con = sqlite3.connect(db)
+    out = {}
+    for k, v in con.execute("select kernel_name, value from counters_collection order by dispatch_id"):
+        out.setdefault(k, []).append(float(v))
+    return out
+
+
+def counters(fetch_db: str, write_db: str):
+    f, w = counter_per_kernel(fetch_db), counter_per_kernel(write_db)
+    copy = [k for k in f if "copyBuffer" in k]
+    skip = set(copy) | {k for k in f if "FillFunctor" in k or "fillBuffer" in k}
+    print("# HBM traffic from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch),")
+    print(f"# scaled by the same counters on a plain {COPY_MIB} MiB device copy in the same run")
+    kib = COPY_MIB * 1024
+    fk = max((max(f[k]) for k in copy), default=0.0)
+    wk = max((max(w.get(k, [0.0])) for k in copy), default=0.0)
+    cal = (kib / fk if fk else 1.0, kib / wk if wk else 1.0)
+    print(f"# calibration copy: FETCH {fk:.0f} KiB, WRITE {wk:.0f} KiB for {kib} KiB each way")
+    print(f"# factors: fetch x{cal[0]:.3f}, write x{cal[1]:.3f}")
+    print(f"{'kernel':60s} {'n':>4s} {'fetch_KiB':>10s} {'write_KiB':>10s} {'bytes':>12s}")
+    for k in f:
+        if k in skip:
+            continue
+        fa = sum(f[k]) / len(f[k])
+        wa = sum(w.get(k, [0])) / max(len(w.get(k, [1])), 1)
+        tot = (fa * cal[0] + wa * cal[1]) * 1024
+        short = k if len(k) <= 60 else k[:57] + "..."
+        print(f"{short:60s} {len(f[k]):4d} {fa:10.1f} {wa:10.1f} {tot:12.0f}")
+
+
+if __name__ == "__main__":
+    cmd = sys.argv[1] if len(sys.argv) > 1 else "workload"
+    if cmd == "workload":
+        workload()
+    elif cmd == "summarize":
+        summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
+    elif cmd == "counters":
+        counters(sys.argv[2], sys.argv[3])

@@ -1,0 +1,44 @@
+"""GPU tests of the serving loop: products admitted while others run give the same bits as
+the same product computed alone, and the oracle agrees on a sample; a tight memory budget
+makes requests queue instead of failing."""
+import numpy as np
+import pytest
+
+from paper_0712_4046_amd import ks
+from paper_0712_4046_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ks.lib()
+    return torch
+
+
+def test_results_in_mix_equal_results_alone(torch_dev, oracle):
+    reqs = serve.make_requests(160, rate_per_s=20000.0, seed=51, max_len=2048, max_bits=256)
+    srv = serve.Server(slots=8, streams=4)
+    st = srv.run(reqs)
+    assert st.completed == len(reqs)
+    assert st.max_inflight > 1, "requests never overlapped"
+    for d in st.results:
+        r = reqs[d.idx]
+        alone = ks.mul(ks.to_device(r.f), ks.to_device(r.g), r.bits, "auto", True)
+        ks.check()
+        assert np.array_equal(ks.to_host(d.out), ks.to_host(alone)), d.idx
+    for d in st.results[::8]:
+        r = reqs[d.idx]
+        exp = oracle.mul_classical(r.f, r.g, True, oracle.out_limbs(r.f.shape[0], r.g.shape[0], r.bits))
+        assert np.array_equal(ks.to_host(d.out), exp), d.idx
+    assert st.p99_ms >= st.p50_ms > 0
+
+
+def test_small_memory_budget_queues(torch_dev):
+    reqs = serve.make_requests(40, rate_per_s=0.0, seed=52, max_len=512, max_bits=64)
+    srv = serve.Server(slots=8, streams=2, mem_budget=1)  # one request at a time
+    st = srv.run(reqs)
+    assert st.completed == len(reqs)
+    assert st.max_inflight == 1
