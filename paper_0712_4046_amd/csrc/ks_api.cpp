@@ -109,23 +109,49 @@ int plan_product(const Spec &sp, Geom &G) {
         }
     G.op_limbs = off;
 
-    // products: point q of f times point q of g
-    int64_t coff = 0;
+    // products: point q of f times point q of g, on the vector ALU or the matrix cores
+    int64_t coff = 0, doff = 0;
     for (int q = 0; q < npts; ++q) {
         MulGeom m;
         m.fa = q;
         m.fb = npts + q;
         m.na = nf;
         m.nb = ng;
-        m.ntiles = cdiv(nf + ng - 1, MUL_T);
+        m.nad = cdiv(32 * nf, 7);
+        m.nbd = cdiv(32 * ng, 7);
+        m.nA32 = cdiv(m.nad, 32);
+        m.nB32 = cdiv(m.nbd + 31, 32);
+        // the matrix-core engine keeps each int32 accumulator within MFMA_MAX_STEPS shifts
+        const bool mfma_fits = std::min(m.nA32 + MFMA_ROWS, m.nB32) <= (int64_t)MFMA_WAVES * MFMA_MAX_STEPS;
+        int eng = sp.engine;
+        if (eng == 0) eng = (mfma_fits && std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", 512)) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
+        if (eng == KS_ENGINE_MFMA && !mfma_fits) return KS_EUNSUPPORTED;
+        m.engine = eng;
+        if (eng == KS_ENGINE_MFMA) {
+            const int64_t rows = cdiv(m.nad + m.nbd - 1, 32);
+            m.blocks = cdiv(rows, MFMA_ROWS);
+            m.ncols = m.blocks * MFMA_LIMBS;
+            m.a_front = 32 * (MFMA_ROWS + MFMA_TC);
+            m.a_len = align_up(m.a_front + 32 * m.nA32 + 32 * (MFMA_ROWS + MFMA_TC), 1024);
+            m.b_len = align_up(32 * m.nB32 + 2 * MFMA_PADB + 32, 1024);
+            m.b_top = m.b_len - 1 - MFMA_PADB;
+            m.ad_off = doff;
+            doff += m.a_len;
+            m.bd_off = doff;
+            doff += m.b_len;
+        } else {
+            m.ntiles = cdiv(nf + ng - 1, MUL_T);
+            m.blocks = m.ntiles;
+            m.ncols = m.ntiles * MUL_T;
+        }
         m.cols_off = coff;
-        m.blocks = m.ntiles;
-        coff += align_up(3 * m.ntiles * MUL_T, 64);
+        coff += align_up(3 * m.ncols, 64);
         G.muls.push_back(m);
         G.mul_blocks += m.blocks;
         G.school_mults += (double)nf * (double)ng;
     }
     G.col_words = coff;
+    G.digit_bytes = doff;
     G.limb_mults = G.school_mults;
 
     // recombinations
@@ -208,6 +234,7 @@ int plan_product(const Spec &sp, Geom &G) {
     int64_t o = 0;
     G.ws_ops = o;     o += align_up(G.op_limbs * 4, 256);
     G.ws_cols = o;    o += align_up(G.col_words * 4, 256);
+    G.ws_digits = o;  o += align_up(G.digit_bytes, 256);
     G.ws_norms = o;   o += align_up(G.norm_limbs * 4, 256);
     G.ws_anchors = o; o += align_up(std::max<int64_t>(G.anchor_limbs, 1) * 4, 256);
     G.ws_status = o;  o += align_up(std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1) * 8, 256);
@@ -282,7 +309,38 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.nblocks = p.blocks;
         JL.pack.push_back(j);
     }
+    auto digits = [&](int64_t byte_off) { return reinterpret_cast<uint8_t *>(ws + G.ws_digits + byte_off); };
     for (auto &m : G.muls) {
+        if (m.engine == KS_ENGINE_MFMA) {
+            for (int side = 0; side < 2; ++side) {
+                DigitJob d;
+                memset(&d, 0, sizeof(d));
+                d.limbs = ops(G.packs[side ? m.fb : m.fa].op_off);
+                d.n = side ? m.nb : m.na;
+                d.out = digits(side ? m.bd_off : m.ad_off);
+                d.len = side ? m.b_len : m.a_len;
+                d.nd = side ? m.nbd : m.nad;
+                d.base = side ? m.b_top : m.a_front;
+                d.reversed = side;
+                d.block0 = next_block(JL.digit);
+                d.nblocks = cdiv(d.len, 1024);
+                JL.digit.push_back(d);
+            }
+            MfmaJob j;
+            memset(&j, 0, sizeof(j));
+            j.ad = digits(m.ad_off);
+            j.bd = digits(m.bd_off);
+            j.a_front = m.a_front;
+            j.nA32 = m.nA32;
+            j.b_top = m.b_top;
+            j.b_len = m.b_len;
+            j.nB32 = m.nB32;
+            j.cols = cols(m.cols_off);
+            j.block0 = next_block(JL.mfma);
+            j.nblocks = m.blocks;
+            JL.mfma.push_back(j);
+            continue;
+        }
         MulJob j;
         memset(&j, 0, sizeof(j));
         j.a = ops(G.packs[m.fa].op_off);
@@ -323,7 +381,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
             const MulGeom &m = G.muls[r.prod[t]];
             NormTerm &T = j.term[t];
             T.cols = cols(m.cols_off);
-            T.ncols = m.ntiles * MUL_T;
+            T.ncols = m.ncols;
             T.a = ops(G.packs[m.fa].op_off);
             T.b = ops(G.packs[m.fb].op_off);
             T.na = m.na;
@@ -422,9 +480,17 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         err = timed("pack", s, [&] { return launch_pack(L, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
-    {
+    if (!JL.mul.empty()) {
         auto L = make_launch(JL.mul, T ? &T->mul : nullptr, env, 0);
         err = timed("mul_valu", s, [&] { return launch_mul_valu(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    if (!JL.mfma.empty()) {
+        auto Ld = make_launch(JL.digit, T ? &T->digit : nullptr, env, 0);
+        err = timed("digitize", s, [&] { return launch_digitize(Ld, s); });
+        if (err != hipSuccess) return KS_EHIP;
+        auto L = make_launch(JL.mfma, T ? &T->mfma : nullptr, env, 0);
+        err = timed("mul_mfma", s, [&] { return launch_mul_mfma(L, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     for (auto &kv : JL.anchor) {
@@ -547,7 +613,6 @@ int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_
     int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_VALU | KS_ENGINE_MFMA;
     if (variant & ~known) return KS_EINVAL;
     if ((variant & KS_ENGINE_MFMA) && (variant & KS_ENGINE_VALU)) return KS_EINVAL;
-    if (variant & KS_ENGINE_MFMA) return KS_EUNSUPPORTED;
     return KS_OK;
 }
 
@@ -591,12 +656,12 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
     int rc = validate_spec(len_f, len_g, coeff_bits, variant, true);
     if (rc != KS_OK) return rc;
     Spec sp{len_f, len_g, coeff_bits, (int)cdiv(coeff_bits, 32), (variant & KS_SIGNED) != 0, 0,
-            variant & KS_VARIANT_MASK, KS_ENGINE_VALU};
+            variant & KS_VARIANT_MASK, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
     Geom G;
     rc = plan_product(sp, G);
     if (rc != KS_OK) return rc;
     out->variant = G.variant;
-    out->engine = KS_ENGINE_VALU;
+    out->engine = G.muls.empty() ? KS_ENGINE_VALU : G.muls[0].engine;
     out->e = G.e;
     out->slot_bits = (int32_t)G.N;
     out->n_products = (int32_t)G.muls.size();
@@ -631,7 +696,7 @@ int ks_mul(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, i
     int rc = validate_spec(len_f, len_g, coeff_bits, variant, true);
     if (rc != KS_OK) return rc;
     Spec sp{len_f, len_g, coeff_bits, (int)cdiv(coeff_bits, 32), (variant & KS_SIGNED) != 0, 0,
-            variant & KS_VARIANT_MASK, KS_ENGINE_VALU};
+            variant & KS_VARIANT_MASK, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
     return mul_common(f, g, sp, stream, h);
 }
 
@@ -642,7 +707,7 @@ int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_
     int bits = bitlen_u64(p - 1);
     int rc = validate_spec(len_f, len_g, bits, variant, false);
     if (rc != KS_OK) return rc;
-    Spec sp{len_f, len_g, bits, 2, false, p, variant & KS_VARIANT_MASK, KS_ENGINE_VALU};
+    Spec sp{len_f, len_g, bits, 2, false, p, variant & KS_VARIANT_MASK, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
     return mul_common(reinterpret_cast<const uint32_t *>(f), reinterpret_cast<const uint32_t *>(g), sp, stream, h);
 }
 

@@ -90,8 +90,8 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     *out = nullptr;
     const int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_VALU | KS_ENGINE_MFMA;
     if (variant & ~known) return KS_EINVAL;
-    if (variant & KS_ENGINE_MFMA) return KS_EUNSUPPORTED;
     const int v = variant & KS_VARIANT_MASK;
+    const int eng = variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA);
     if (v != KS_VARIANT_AUTO && v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_KS4) return KS_EINVAL;
     ks_batch_plan *P = new ks_batch_plan();
     P->count = count;
@@ -112,10 +112,10 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
                 delete P;
                 return KS_EINVAL;
             }
-            sp = Spec{d.len_f, d.len_g, bitlen_u64(p - 1), 2, false, p, v, KS_ENGINE_VALU};
+            sp = Spec{d.len_f, d.len_g, bitlen_u64(p - 1), 2, false, p, v, eng};
         } else {
             sp = Spec{d.len_f, d.len_g, d.coeff_bits, (d.coeff_bits + 31) / 32, (d.flags & KS_SIGNED) != 0, 0, v,
-                      KS_ENGINE_VALU};
+                      eng};
         }
         if (validate_spec(sp.lf, sp.lg, sp.bits, v, true) != KS_OK) { g_bad_index = i; delete P; return KS_EINVAL; }
         int rc = plan_product(sp, geoms[(size_t)i]);
@@ -141,6 +141,8 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     auto sh = [&](auto *&ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(reinterpret_cast<uintptr_t>(ptr) + base); };
     for (auto &j : JL.pack) sh(j.out);
     for (auto &j : JL.mul) { sh(j.a); sh(j.b); sh(j.cols); }
+    for (auto &j : JL.digit) { sh(j.limbs); sh(j.out); }
+    for (auto &j : JL.mfma) { sh(j.ad); sh(j.bd); sh(j.cols); }
     for (auto &kv : JL.anchor) for (auto &j : kv.second) sh(j.anchors);
     for (auto &j : JL.norm) {
         for (int q = 0; q < j.nterms; ++q) { sh(j.term[q].cols); sh(j.term[q].a); sh(j.term[q].b); }
@@ -154,6 +156,8 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     int rc = KS_OK;
     if (rc == KS_OK) rc = upload(JL.pack, P->T.pack, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mul, P->T.mul, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.digit, P->T.digit, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.mfma, P->T.mfma, P->allocs);
     if (rc == KS_OK) rc = upload(JL.norm, P->T.norm, P->allocs);
     if (rc == KS_OK) rc = upload(JL.extract, P->T.extract, P->allocs);
     for (auto &kv : JL.anchor) if (rc == KS_OK) rc = upload(kv.second, P->T.anchor[kv.first], P->allocs);

@@ -240,6 +240,16 @@ template <> __device__ __forceinline__ void rebase(ChainJob &J, const Launch<Cha
     J.out = at(L.base_out, J.out);
 }
 
+template <> __device__ __forceinline__ void rebase(DigitJob &J, const Launch<DigitJob> &L) {
+    J.limbs = at(L.base_ws, J.limbs);
+    J.out = at(L.base_ws, J.out);
+}
+template <> __device__ __forceinline__ void rebase(MfmaJob &J, const Launch<MfmaJob> &L) {
+    J.ad = at(L.base_ws, J.ad);
+    J.bd = at(L.base_ws, J.bd);
+    J.cols = at(L.base_ws, J.cols);
+}
+
 template <class J>
 __device__ __forceinline__ J get_job(const Launch<J> &L, int64_t blk, int64_t &local) {
     J job = find_job(L, blk, local);

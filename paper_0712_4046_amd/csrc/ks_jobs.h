@@ -29,6 +29,18 @@ constexpr int MUL_R = 2;
 constexpr int MUL_T = 64 * MUL_R;
 constexpr int MUL_CI = 128;
 
+// int8 matrix-core multiplier (7-bit digits): a block of MFMA_WAVES waves owns MFMA_RT row
+// tiles of 32 output digit blocks (32 digits each) = 7 * MFMA_ROWS output limbs, and stages
+// MFMA_TC block shifts at a time; an int32 accumulator takes at most MFMA_MAX_STEPS shifts
+constexpr int MFMA_WAVES = 4;
+constexpr int MFMA_TPB = 64 * MFMA_WAVES;
+constexpr int MFMA_RT = 4;
+constexpr int MFMA_ROWS = 32 * MFMA_RT;
+constexpr int MFMA_TC = 32;
+constexpr int MFMA_LIMBS = 7 * MFMA_ROWS;
+constexpr int64_t MFMA_MAX_STEPS = 4096;
+constexpr int64_t MFMA_PADB = 64;
+
 constexpr int EXTRACT_TPB = 256;
 constexpr int CHAIN_TPB = 64;
 constexpr int ANCHOR_TPB = 256;  // four waves per anchor coefficient
@@ -63,6 +75,36 @@ struct MulJob {
     uint32_t *cols;
     int64_t block0;
     int64_t nblocks;  // = number of column tiles
+};
+
+// 7-bit digits of a limb array into a zero-padded byte buffer: out[x] = digit(x - base), or
+// digit(base - x) when reversed (the Toeplitz operand is read in descending digit order)
+struct DigitJob {
+    const uint32_t *limbs;
+    int64_t n;
+    uint8_t *out;
+    int64_t len;
+    int64_t nd;
+    int64_t base;
+    int32_t reversed;
+    int32_t pad;
+    int64_t block0;
+    int64_t nblocks;
+};
+
+// product of two digit buffers on the matrix cores; block t writes the three-piece column sums
+// of limbs [t MFMA_LIMBS, (t+1) MFMA_LIMBS)
+struct MfmaJob {
+    const uint8_t *ad;  // a digits, a_i at ad[a_front + i]
+    const uint8_t *bd;  // b digits reversed, b_i at bd[b_top - i]
+    int64_t a_front;
+    int64_t nA32;       // ceil(digits of a / 32)
+    int64_t b_top;
+    int64_t b_len;
+    int64_t nB32;       // number of block shifts t
+    uint32_t *cols;
+    int64_t block0;
+    int64_t nblocks;
 };
 
 // one product read back from its column sums, corrected for two's-complement operands;

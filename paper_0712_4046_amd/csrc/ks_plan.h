@@ -32,8 +32,12 @@ struct PackGeom {
 };
 struct MulGeom {
     int fa, fb;  // operand (pack) indices
+    int engine;  // KS_ENGINE_VALU or KS_ENGINE_MFMA
     int64_t na, nb, ntiles;
-    int64_t cols_off, blocks;  // column sums: 3 words per column, ntiles * MUL_T columns
+    int64_t ncols, cols_off, blocks;  // column sums: 3 words per column
+    // matrix-core engine: 7-bit digit buffers (byte offsets in the digit region)
+    int64_t nad = 0, nbd = 0, nA32 = 0, nB32 = 0, a_front = 0, a_len = 0, b_len = 0, b_top = 0;
+    int64_t ad_off = 0, bd_off = 0;
 };
 struct NormGeom {
     int nterms, prod[2], sign[2], shift;
@@ -59,10 +63,10 @@ struct Geom {
     std::vector<NormGeom> norms;
     std::vector<ExtractGeom> extracts;
     std::vector<ChainGeom> chains;
-    int64_t op_limbs = 0, col_words = 0, norm_limbs = 0, anchor_limbs = 0;
+    int64_t op_limbs = 0, col_words = 0, norm_limbs = 0, anchor_limbs = 0, digit_bytes = 0;
     int64_t pack_blocks = 0, mul_blocks = 0, norm_blocks = 0, extract_blocks = 0, anchor_blocks = 0,
             chain_blocks = 0;
-    int64_t ws_ops = 0, ws_cols = 0, ws_norms = 0, ws_anchors = 0, ws_status = 0, ws_bytes = 0;
+    int64_t ws_ops = 0, ws_cols = 0, ws_digits = 0, ws_norms = 0, ws_anchors = 0, ws_status = 0, ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
     double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0;
 };
@@ -78,6 +82,8 @@ struct Ctl {
 struct JobLists {
     std::vector<PackJob> pack;
     std::vector<MulJob> mul;
+    std::vector<DigitJob> digit;
+    std::vector<MfmaJob> mfma;
     std::vector<NormJob> norm;
     std::vector<ExtractJob> extract;
     std::map<int, std::vector<AnchorJob>> anchor;  // by limbs per input coefficient
@@ -90,7 +96,7 @@ struct DevList {
     uint32_t *block_job = nullptr;
 };
 struct DevTables {
-    DevList pack, mul, norm, extract;
+    DevList pack, mul, digit, mfma, norm, extract;
     std::map<int, DevList> anchor, chain;
 };
 

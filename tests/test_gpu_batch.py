@@ -24,9 +24,9 @@ def torch_dev():
     return torch
 
 
-def run_batch(torch, B, variant="auto"):
+def run_batch(torch, B, variant="auto", engine=None):
     descs = B.desc_array()
-    plan = ks.BatchPlan(descs, variant)
+    plan = ks.BatchPlan(descs, variant, engine)
     ain = ks.to_device(B.arena_in())
     aout = torch.zeros(B.out_words(), dtype=torch.int32, device="cuda")
     ws = ks.alloc_workspace(plan.workspace_bytes)
@@ -38,8 +38,9 @@ def run_batch(torch, B, variant="auto"):
     return out
 
 
+@pytest.mark.parametrize("engine", [None, "valu", "mfma"])
 @pytest.mark.parametrize("variant", ["ks1", "neg2", "ks4", "auto"])
-def test_mixed_batch(torch_dev, oracle, variant):
+def test_mixed_batch(torch_dev, oracle, variant, engine):
     gen = wl.rng(31)
     B = ks.Batch()
     cases = []
@@ -49,7 +50,7 @@ def test_mixed_batch(torch_dev, oracle, variant):
         signed = bool(gen.integers(0, 2))
         f, g = wl.random_coeffs(gen, lf, bits, signed), wl.random_coeffs(gen, lg, bits, signed)
         cases.append((B.add(f, g, bits, signed), f, g, bits, signed))
-    out = run_batch(torch_dev, B, variant)
+    out = run_batch(torch_dev, B, variant, engine)
     for i, f, g, bits, signed in cases:
         exp = oracle.mul_classical(f, g, signed, oracle.out_limbs(f.shape[0], g.shape[0], bits))
         assert np.array_equal(B.result(out, i), exp), (variant, i, f.shape[0], g.shape[0], bits, signed)
@@ -82,7 +83,7 @@ def test_config4_modular_batch_sampled(torch_dev, oracle):
     B = ks.Batch()
     for f, g in pairs:
         B.add_mod(f, g, p)
-    out = run_batch(torch_dev, B, "ks4")
+    out = run_batch(torch_dev, B, "ks4", "mfma")
     D = 2 * 65536 - 1
     gen = wl.rng(44)
     for i, (f, g) in enumerate(pairs):

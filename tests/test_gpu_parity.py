@@ -24,9 +24,12 @@ def torch_dev():
     return torch
 
 
-def gpu_mul(f, g, bits, variant, signed):
+ENGINES = ["valu", "mfma"]
+
+
+def gpu_mul(f, g, bits, variant, signed, engine=None):
     tf, tg = ks.to_device(f), ks.to_device(g)
-    h = ks.mul(tf, tg, bits, variant, signed)
+    h = ks.mul(tf, tg, bits, variant, signed, engine=engine)
     rc = ks.status()
     assert rc == ks.KS_OK, ks.strerror(rc)
     return ks.to_host(h)
@@ -50,26 +53,29 @@ def test_paper_example(torch_dev, oracle):
         assert got == [151522, 418982, 788467, 1082839, 1043046, 964034, 490590], v
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_config1_full(torch_dev, oracle, variant):
+def test_config1_full(torch_dev, oracle, variant, engine):
     P = wl.config1()
-    assert_same(gpu_mul(P.f, P.g, P.bits, variant, P.signed), want(oracle, P.f, P.g, P.bits, P.signed),
-                f"config1 {variant}")
+    assert_same(gpu_mul(P.f, P.g, P.bits, variant, P.signed, engine), want(oracle, P.f, P.g, P.bits, P.signed),
+                f"config1 {variant} {engine}")
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_config2_full(torch_dev, oracle, variant):
+def test_config2_full(torch_dev, oracle, variant, engine):
     P = wl.config2()
-    assert_same(gpu_mul(P.f, P.g, P.bits, variant, P.signed), want(oracle, P.f, P.g, P.bits, P.signed),
-                f"config2 {variant}")
+    assert_same(gpu_mul(P.f, P.g, P.bits, variant, P.signed, engine), want(oracle, P.f, P.g, P.bits, P.signed),
+                f"config2 {variant} {engine}")
 
 
 EDGE_LENGTHS = [(1, 1), (1, 2), (2, 1), (2, 2), (3, 3), (3, 5), (5, 3), (4, 7), (17, 16), (33, 2), (64, 64)]
 EDGE_BITS = [1, 2, 31, 32, 33, 60, 64, 65, 128, 256]
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("bits", EDGE_BITS)
-def test_edge_grid(torch_dev, oracle, bits):
+def test_edge_grid(torch_dev, oracle, bits, engine):
     for lf, lg in EDGE_LENGTHS:
         for signed in (False, True):
             gen = wl.rng(lf * 100 + lg + bits)
@@ -77,7 +83,8 @@ def test_edge_grid(torch_dev, oracle, bits):
             g = wl.random_coeffs(gen, lg, bits, signed)
             exp = want(oracle, f, g, bits, signed)
             for v in VARIANTS:
-                assert_same(gpu_mul(f, g, bits, v, signed), exp, f"{v} lf={lf} lg={lg} b={bits} s={signed}")
+                assert_same(gpu_mul(f, g, bits, v, signed, engine), exp,
+                            f"{v} {engine} lf={lf} lg={lg} b={bits} s={signed}")
 
 
 @pytest.mark.parametrize("kind", ["max", "min", "zero", "onehot", "sparse", "tiny"])
@@ -88,7 +95,8 @@ def test_structured_inputs(torch_dev, oracle, kind, bits, signed):
     g = wl.special_coeffs(kind, 300, bits, signed, gen)
     exp = want(oracle, f, g, bits, signed)
     for v in VARIANTS:
-        assert_same(gpu_mul(f, g, bits, v, signed), exp, f"{kind} {v} b={bits} s={signed}")
+        for e in ENGINES:
+            assert_same(gpu_mul(f, g, bits, v, signed, e), exp, f"{kind} {v} {e} b={bits} s={signed}")
 
 
 @pytest.mark.parametrize("lf,lg,bits,signed", [(5000, 4999, 128, True), (3000, 1001, 64, False), (3000, 1000, 64, True),
@@ -100,7 +108,8 @@ def test_multi_block_sizes(torch_dev, oracle, lf, lg, bits, signed):
     g = wl.random_coeffs(gen, lg, bits, signed)
     exp = want(oracle, f, g, bits, signed)
     for v in VARIANTS:
-        assert_same(gpu_mul(f, g, bits, v, signed), exp, f"{v} lf={lf} lg={lg} b={bits}")
+        for e in ENGINES:
+            assert_same(gpu_mul(f, g, bits, v, signed, e), exp, f"{v} {e} lf={lf} lg={lg} b={bits}")
 
 
 def test_deterministic(torch_dev):
@@ -132,7 +141,7 @@ def test_mod_small(torch_dev, oracle):
             for v in VARIANTS:
                 tf = torch.from_numpy(f.view(np.int64)).cuda()
                 tg = torch.from_numpy(g.view(np.int64)).cuda()
-                h = ks.mul_mod(tf, tg, p, v)
+                h = ks.mul_mod(tf, tg, p, v, engine="mfma" if lf >= 300 else None)
                 assert ks.status() == ks.KS_OK
                 got = h.cpu().numpy().view(np.uint64)
                 assert np.array_equal(got, exp), (p, lf, lg, v)
@@ -147,11 +156,11 @@ def test_mod_config4_one_product_sampled(torch_dev, oracle):
     D = len(f) + len(g) - 1
     ks_idx = np.unique(np.concatenate([np.arange(0, 40), np.arange(D - 40, D), wl.rng(11).integers(0, D, 400)]))
     exp = oracle.coeffs_mod(f, g, p, ks_idx)
-    for v in ("ks4", "ks1"):
-        h = ks.mul_mod(tf, tg, p, v)
+    for v, e in (("ks4", "mfma"), ("ks4", "valu"), ("ks1", None)):
+        h = ks.mul_mod(tf, tg, p, v, engine=e)
         assert ks.status() == ks.KS_OK
         got = h.cpu().numpy().view(np.uint64)[ks_idx]
-        assert np.array_equal(got, exp), v
+        assert np.array_equal(got, exp), (v, e)
 
 
 def test_invalid_arguments(torch_dev):
