@@ -121,18 +121,25 @@ int plan_product(const Spec &sp, Geom &G) {
         m.nbd = cdiv(32 * ng, 7);
         m.nA32 = cdiv(m.nad, 32);
         m.nB32 = cdiv(m.nbd + 31, 32);
-        // the matrix-core engine keeps each int32 accumulator within MFMA_MAX_STEPS shifts
-        const bool mfma_fits = std::min(m.nA32 + MFMA_ROWS, m.nB32) <= (int64_t)MFMA_WAVES * MFMA_MAX_STEPS;
         int eng = sp.engine;
-        if (eng == 0) eng = (mfma_fits && std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", 512)) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
-        if (eng == KS_ENGINE_MFMA && !mfma_fits) return KS_EUNSUPPORTED;
+        if (eng == 0) eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", 6000) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
         m.engine = eng;
         if (eng == KS_ENGINE_MFMA) {
             const int64_t rows = cdiv(m.nad + m.nbd - 1, 32);
-            m.blocks = cdiv(rows, MFMA_ROWS);
-            m.ncols = m.blocks * MFMA_LIMBS;
-            m.a_front = 32 * (MFMA_ROWS + MFMA_TC);
-            m.a_len = align_up(m.a_front + 32 * m.nA32 + 32 * (MFMA_ROWS + MFMA_TC), 1024);
+            m.groups = cdiv(rows, MFMA_ROWS);
+            // the longest shift range of a row group, cut into parts: at most MFMA_MAX_PART
+            // shifts each (int32 accumulators), enough parts to give the launch about
+            // KS_MFMA_BLOCKS blocks, but not shorter than KS_MFMA_MIN_PART shifts
+            const int64_t tmax = std::min(m.nA32 + MFMA_ROWS - 1, m.nB32);
+            const int64_t s_min = cdiv(tmax, MFMA_MAX_PART);
+            const int64_t s_fill = cdiv(env_int("KS_MFMA_BLOCKS", 1024), (int64_t)npts * m.groups);
+            const int64_t s_cap = std::max<int64_t>(1, tmax / std::max<int64_t>(1, env_int("KS_MFMA_MIN_PART", 128)));
+            m.splits = std::max(s_min, std::min(s_fill, s_cap));
+            m.part = cdiv(tmax, m.splits);
+            m.blocks = m.groups * m.splits;
+            m.ncols = m.groups * MFMA_LIMBS;
+            m.a_front = 32 * MFMA_ROWS;
+            m.a_len = align_up(m.a_front + 32 * m.nA32 + 32 * MFMA_ROWS, 1024);
             m.b_len = align_up(32 * m.nB32 + 2 * MFMA_PADB + 32, 1024);
             m.b_top = m.b_len - 1 - MFMA_PADB;
             m.ad_off = doff;
@@ -145,7 +152,7 @@ int plan_product(const Spec &sp, Geom &G) {
             m.ncols = m.ntiles * MUL_T;
         }
         m.cols_off = coff;
-        coff += align_up(3 * m.ncols, 64);
+        coff += align_up((eng == KS_ENGINE_MFMA ? 4 : 3) * m.ncols, 64);
         G.muls.push_back(m);
         G.mul_blocks += m.blocks;
         G.school_mults += (double)nf * (double)ng;
@@ -248,7 +255,8 @@ int plan_product(const Spec &sp, Geom &G) {
     double norm_out = 0;
     for (auto &r : G.norms) norm_out += 4.0 * r.n_out;
     G.pack_bytes = in_bytes + 4.0 * G.op_limbs;
-    G.normalize_bytes = 12.0 * npts * prod_limbs + norm_out;
+    const double col_bytes = (!G.muls.empty() && G.muls[0].engine == KS_ENGINE_MFMA) ? 16.0 : 12.0;
+    G.normalize_bytes = col_bytes * npts * prod_limbs + norm_out;
     G.finish_bytes = norm_out + out_bytes;
     return KS_OK;
 }
@@ -322,8 +330,10 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
                 d.nd = side ? m.nbd : m.nad;
                 d.base = side ? m.b_top : m.a_front;
                 d.reversed = side;
+                d.zero = reinterpret_cast<uint8_t *>(cols(m.cols_off));
+                d.zero_len = side ? 0 : 16 * m.ncols;
                 d.block0 = next_block(JL.digit);
-                d.nblocks = cdiv(d.len, 1024);
+                d.nblocks = cdiv(d.len + d.zero_len, 1024);
                 JL.digit.push_back(d);
             }
             MfmaJob j;
@@ -335,7 +345,9 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
             j.b_top = m.b_top;
             j.b_len = m.b_len;
             j.nB32 = m.nB32;
-            j.cols = cols(m.cols_off);
+            j.splits = m.splits;
+            j.part = m.part;
+            j.cols = reinterpret_cast<unsigned long long *>(cols(m.cols_off));
             j.block0 = next_block(JL.mfma);
             j.nblocks = m.blocks;
             JL.mfma.push_back(j);
@@ -387,6 +399,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
             T.na = m.na;
             T.nb = m.nb;
             T.sign = r.sign[t];
+            T.fmt = m.engine == KS_ENGINE_MFMA ? NORM_FMT_XY : NORM_FMT_PIECES;
         }
         j.shift = r.shift;
         j.off_bit0 = r.off_bit0;

@@ -141,7 +141,7 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     auto sh = [&](auto *&ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(reinterpret_cast<uintptr_t>(ptr) + base); };
     for (auto &j : JL.pack) sh(j.out);
     for (auto &j : JL.mul) { sh(j.a); sh(j.b); sh(j.cols); }
-    for (auto &j : JL.digit) { sh(j.limbs); sh(j.out); }
+    for (auto &j : JL.digit) { sh(j.limbs); sh(j.out); sh(j.zero); }
     for (auto &j : JL.mfma) { sh(j.ad); sh(j.bd); sh(j.cols); }
     for (auto &kv : JL.anchor) for (auto &j : kv.second) sh(j.anchors);
     for (auto &j : JL.norm) {

@@ -243,6 +243,7 @@ template <> __device__ __forceinline__ void rebase(ChainJob &J, const Launch<Cha
 template <> __device__ __forceinline__ void rebase(DigitJob &J, const Launch<DigitJob> &L) {
     J.limbs = at(L.base_ws, J.limbs);
     J.out = at(L.base_ws, J.out);
+    J.zero = at(L.base_ws, J.zero);
 }
 template <> __device__ __forceinline__ void rebase(MfmaJob &J, const Launch<MfmaJob> &L) {
     J.ad = at(L.base_ws, J.ad);

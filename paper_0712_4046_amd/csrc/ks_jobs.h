@@ -30,15 +30,16 @@ constexpr int MUL_T = 64 * MUL_R;
 constexpr int MUL_CI = 128;
 
 // int8 matrix-core multiplier (7-bit digits): a block of MFMA_WAVES waves owns MFMA_RT row
-// tiles of 32 output digit blocks (32 digits each) = 7 * MFMA_ROWS output limbs, and stages
-// MFMA_TC block shifts at a time; an int32 accumulator takes at most MFMA_MAX_STEPS shifts
-constexpr int MFMA_WAVES = 4;
+// tiles of 32 output digit blocks (32 digits each) = 7 * MFMA_ROWS output limbs and a part of
+// at most MFMA_MAX_PART block shifts; wave w takes the shifts t = t_a + c (mod 32) for the four
+// residues c = w, w+8, w+16, w+24, so an int32 accumulator sees at most 4 * MFMA_MAX_PART / 32
+// = 4096 shifts (each adds at most 32 * 127^2)
+constexpr int MFMA_WAVES = 8;
 constexpr int MFMA_TPB = 64 * MFMA_WAVES;
-constexpr int MFMA_RT = 4;
+constexpr int MFMA_RT = 8;
 constexpr int MFMA_ROWS = 32 * MFMA_RT;
-constexpr int MFMA_TC = 32;
 constexpr int MFMA_LIMBS = 7 * MFMA_ROWS;
-constexpr int64_t MFMA_MAX_STEPS = 4096;
+constexpr int64_t MFMA_MAX_PART = 32768;
 constexpr int64_t MFMA_PADB = 64;
 
 constexpr int EXTRACT_TPB = 256;
@@ -79,6 +80,8 @@ struct MulJob {
 
 // 7-bit digits of a limb array into a zero-padded byte buffer: out[x] = digit(x - base), or
 // digit(base - x) when reversed (the Toeplitz operand is read in descending digit order)
+// (x in [0, len)); the job's later blocks clear zero_len bytes at `zero` (the product's
+// column buffer, which the matrix-core multiplier accumulates into)
 struct DigitJob {
     const uint32_t *limbs;
     int64_t n;
@@ -88,12 +91,15 @@ struct DigitJob {
     int64_t base;
     int32_t reversed;
     int32_t pad;
+    uint8_t *zero;
+    int64_t zero_len;
     int64_t block0;
     int64_t nblocks;
 };
 
-// product of two digit buffers on the matrix cores; block t writes the three-piece column sums
-// of limbs [t MFMA_LIMBS, (t+1) MFMA_LIMBS)
+// product of two digit buffers on the matrix cores.  Block (group, part) adds the column sums
+// of limbs [group MFMA_LIMBS, (group+1) MFMA_LIMBS) over its part of the block shifts into
+// cols, two uint64 per limb column (weights 2^0 and 2^32), which must start at zero
 struct MfmaJob {
     const uint8_t *ad;  // a digits, a_i at ad[a_front + i]
     const uint8_t *bd;  // b digits reversed, b_i at bd[b_top - i]
@@ -102,10 +108,16 @@ struct MfmaJob {
     int64_t b_top;
     int64_t b_len;
     int64_t nB32;       // number of block shifts t
-    uint32_t *cols;
+    int64_t splits;     // parts per row group
+    int64_t part;       // block shifts per part (at most MFMA_MAX_PART)
+    unsigned long long *cols;
     int64_t block0;
     int64_t nblocks;
 };
+
+// column-sum formats: three uint32 pieces per column (weights 2^0, 2^32, 2^64; the vector-ALU
+// multiplier) or two uint64 sums per column (weights 2^0, 2^32; the matrix-core multiplier)
+enum : int32_t { NORM_FMT_PIECES = 0, NORM_FMT_XY = 1 };
 
 // one product read back from its column sums, corrected for two's-complement operands;
 // column j of the value gets piece 0 of column j, piece 1 of j-1 and piece 2 of j-2
@@ -117,7 +129,7 @@ struct NormTerm {
     int64_t na;
     int64_t nb;
     int32_t sign;  // +1 or -1
-    int32_t pad;
+    int32_t fmt;   // NORM_FMT_PIECES or NORM_FMT_XY
 };
 
 // V = sum_terms sign * product + sum_{k < off_count} 2^(off_bit0 + k off_period);

@@ -8,18 +8,22 @@
 // each block shift t is a 32x32x32 matrix product: rows s (a 32-digit output block), columns
 // r, contraction q; the a-matrix rows are contiguous 32-digit runs of a and the b-matrix is a
 // Toeplitz tile of b.  One v_mfma_i32_32x32x32_i8 computes it, accumulating exactly in int32
-// (at most 32 * 127^2 per step, so up to MFMA_MAX_STEPS steps per accumulator).
+// (at most 32 * 127^2 per step; a wave takes at most 4096 steps).
 //
 // Lane layout of v_mfma_i32_32x32x32_i8 (checked on the device): lane l supplies row (A) or
 // column (B) l % 32 and contraction indices 16 (l / 32) .. + 15 as 16 bytes; result register
 // i of lane l is row 8 (i / 4) + 4 (l / 32) + (i % 4), column l % 32.
 //
-// A block covers MFMA_RT row tiles (32 rows each, so 32 * 32 * MFMA_RT output digits =
-// MFMA_LIMBS limbs) and its MFMA_WAVES waves split the block's range of t between them.  Each
-// wave stages its digit windows through LDS (the b window is read back at per-lane byte
-// offsets and realigned with v_alignbyte).  At the end the waves add their column sums into
-// LDS limb accumulators, and the block writes the same three-piece columns as the vector-ALU
-// multiplier, so the recombination stage is shared.
+// A block covers MFMA_RT row tiles (32 rows each: 32 * 32 * MFMA_RT output digits =
+// MFMA_LIMBS limbs) and one part of the range of t.  Wave w takes the shifts of its part that
+// are congruent to w, w+8, w+16 or w+24 mod 32, one residue class after the other.  Within a
+// class t advances by 32, which moves every row tile's a-rows by exactly one tile: the
+// a-fragment of tile rt at one step is that of tile rt-1 at the step before.  So a step loads
+// one new a-fragment (16 contiguous bytes per lane) and one Toeplitz b-window (68 bytes, one
+// dword per lane, spread by lane shuffles and realigned with v_alignbyte) straight from global
+// memory, PF steps ahead, and issues MFMA_RT matrix operations.  At the end the waves add
+// their digit sums into LDS, the block turns them into limb columns and adds those into the
+// product's column buffer with 64-bit atomics, so any number of parts may share a row group.
 #include "ks_device.h"
 #include "ks_launch.h"
 
@@ -31,12 +35,16 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // ---- digits ------------------------------------------------------------------------------------
 
 // out[x] for x in [0, len): digit d = (reversed ? base - x : x - base) of the limb array, where
-// digit d is bits [7 d, 7 d + 7) for 0 <= d < nd and 0 otherwise.  Four bytes per thread.
+// digit d is bits [7 d, 7 d + 7) for 0 <= d < nd and 0 otherwise; then zero[0, zero_len).
+// Four bytes per thread.
 __global__ __launch_bounds__(256) void digitize_kernel(Launch<DigitJob> L) {
     int64_t local;
     const DigitJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int64_t x0 = (local * 256 + threadIdx.x) * 4;
-    if (x0 >= J.len) return;
+    if (x0 >= J.len) {
+        if (x0 - J.len < J.zero_len) *reinterpret_cast<uint32_t *>(J.zero + (x0 - J.len)) = 0u;
+        return;
+    }
     uint32_t word = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -51,113 +59,145 @@ __global__ __launch_bounds__(256) void digitize_kernel(Launch<DigitJob> L) {
 
 // ---- products ----------------------------------------------------------------------------------
 
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// loads through global (not flat) pointers, so waiting for LDS traffic never waits for them
+typedef __attribute__((address_space(1))) const v4i gv4i;
+typedef __attribute__((address_space(1))) const uint32_t gu32;
+
+__device__ __forceinline__ v4i mfma_frag(const uint8_t *arow, int64_t R) {
+    return *(gv4i *)(arow + 32 * R);
+}
+
+// b-operand of one shift from its window: lane l holds dword l (l <= 16) of the 68 bytes the
+// shift reads; lane (m, g) needs dwords sel .. sel+4 and the 16 bytes at byte offset sh in them
+__device__ __forceinline__ v4i mfma_bop(uint32_t win, int sel, uint32_t sh) {
+    uint32_t w[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) w[i] = (uint32_t)__shfl((int)win, sel + i, 64);
+    v4i b;
+    b[0] = (int)__builtin_amdgcn_alignbyte(w[1], w[0], sh);
+    b[1] = (int)__builtin_amdgcn_alignbyte(w[2], w[1], sh);
+    b[2] = (int)__builtin_amdgcn_alignbyte(w[3], w[2], sh);
+    b[3] = (int)__builtin_amdgcn_alignbyte(w[4], w[3], sh);
+    return b;
+}
+
 __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
-    // per wave: a window (32 (MFMA_ROWS + MFMA_TC) bytes) and b window (32 MFMA_TC + 64 bytes)
-    constexpr int AWIN = 32 * (MFMA_ROWS + MFMA_TC);
-    constexpr int BWIN = 32 * MFMA_TC + 64;
-    constexpr int WBYTES = AWIN + BWIN;
-    __shared__ __attribute__((aligned(16))) uint8_t lds[MFMA_WAVES * WBYTES];
-    static_assert(MFMA_WAVES * WBYTES >= 2 * MFMA_LIMBS * 8, "LDS too small for the reduction");
+    constexpr int RT = MFMA_RT;
+    constexpr int PF = 8;  // steps loaded ahead (the b-window is consumed one step early)
+    static_assert(RT % PF == 0, "prefetch ring must divide the unrolled step count");
+    constexpr int NDIG = 32 * MFMA_ROWS;  // output digits of a block
+    __shared__ unsigned long long D[NDIG];
 
     int64_t local;
     const MfmaJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 31, g = lane >> 5;
-    const int64_t S0 = local * MFMA_ROWS;  // first output row (32-digit block) of the block
+    const int64_t grp = local / J.splits, part = local - grp * J.splits;
+    const int64_t S0 = grp * MFMA_ROWS;  // first output row (32-digit block) of the block
 
-    // block range of t, split evenly between the waves
+    // shifts t with a[32 (s - t) ..] and b[32 t ..] both inside the operands for some row s
+    // of the block, cut into parts
     int64_t tlo = S0 - J.nA32 + 1;
     if (tlo < 0) tlo = 0;
     int64_t thi = S0 + MFMA_ROWS - 1;
     if (thi > J.nB32 - 1) thi = J.nB32 - 1;
-    const int64_t tcount = thi >= tlo ? thi - tlo + 1 : 0;
-    const int64_t per = (tcount + MFMA_WAVES - 1) / MFMA_WAVES;
-    const int64_t wlo = tlo + wv * per;
-    int64_t whi = wlo + per;  // exclusive
-    if (whi > thi + 1) whi = thi + 1;
-    const int64_t nchunks = (per + MFMA_TC - 1) / MFMA_TC;  // same for every wave
+    const int64_t ta = tlo + part * J.part;
+    int64_t tb = ta + J.part;
+    if (tb > thi + 1) tb = thi + 1;
 
-    uint8_t *aw = lds + wv * WBYTES;
-    uint8_t *bw = aw + AWIN;
+    for (int x = tid; x < NDIG; x += MFMA_TPB) D[x] = 0ull;
 
-    v16i acc[MFMA_RT];
+    v16i acc[RT];
 #pragma unroll
-    for (int rt = 0; rt < MFMA_RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[rt][i] = 0;
 
-    for (int64_t ch = 0; ch < nchunks; ++ch) {
-        const int64_t tc = wlo + ch * MFMA_TC;
-        const int64_t tn = whi - tc < MFMA_TC ? whi - tc : MFMA_TC;  // steps in this chunk (may be <= 0)
-        // stage the a window: a indices [32 (S0 - tc - TC + 1), 32 (S0 + ROWS - tc))
-        const int64_t abase = J.a_front + 32 * (S0 - tc - MFMA_TC + 1);
-        for (int x = lane; x < AWIN / 16; x += 64) {
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (tn > 0) v = *reinterpret_cast<const uint4 *>(J.ad + abase + 16 * x);
-            *reinterpret_cast<uint4 *>(aw + 16 * x) = v;
-        }
-        // stage the b window (reversed digits): offsets from LB - 1 - PADB - 32 (tc + TC - 1) - 31
-        const int64_t bo_min = J.b_top - 32 * (tc + MFMA_TC - 1) - 31;
-        const int64_t bstart = bo_min & ~(int64_t)3;
-        for (int x = lane; x < BWIN / 4; x += 64) {
-            uint32_t v = 0;
-            const int64_t o = bstart + 4 * x;
-            if (tn > 0 && o >= 0 && o + 4 <= J.b_len) v = *reinterpret_cast<const uint32_t *>(J.bd + o);
-            *reinterpret_cast<uint32_t *>(bw + 4 * x) = v;
-        }
-        __syncthreads();
-        for (int64_t u = 0; u < tn; ++u) {
-            const int64_t t = tc + u;
-            // B operand: 16 bytes of reversed b at offset b_top - 32 t - m + 16 g (column m)
-            const int64_t o = J.b_top - 32 * t - m + 16 * g - bstart;
-            const uint32_t *bw32 = reinterpret_cast<const uint32_t *>(bw) + (o >> 2);
-            const uint32_t sh = (uint32_t)(o & 3);
-            uint32_t w0 = bw32[0], w1 = bw32[1], w2 = bw32[2], w3 = bw32[3], w4 = bw32[4];
-            v4i bop;
-            bop[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
-            bop[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
-            bop[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
-            bop[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
-#pragma unroll
-            for (int rt = 0; rt < MFMA_RT; ++rt) {
-                // A operand: a[32 (S0 + 32 rt + m - t) + 16 g .. + 15] (row m of tile rt)
-                const int64_t ao = 32 * (32 * rt + m - u + MFMA_TC - 1) + 16 * g;
-                const v4i aop = *reinterpret_cast<const v4i *>(aw + ao);
-                acc[rt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aop, bop, acc[rt], 0, 0, 0);
-            }
-        }
-        __syncthreads();
-    }
+    // lane (m, g) supplies a-row m and b-column m, contraction bytes 16 g .. 16 g + 15:
+    //   a-fragment of the tile whose rows start at R: ad[a_front + 32 (R + m) + 16 g ..]
+    //   b-bytes of shift t: bd[b_top - 32 t - m + 16 g ..]; the wave loads the dword-aligned
+    //   window from bd[wb - 32 t] (one dword per lane) and lanes gather theirs by shuffles
+    const uint8_t *arow = J.ad + J.a_front + 32 * m + 16 * g;
+    const uint32_t sh = (uint32_t)((J.b_top - m) & 3);
+    const int64_t wb = (J.b_top - 31) & ~(int64_t)3;
+    const int sel = (int)((((J.b_top - m + 16 * g) & ~(int64_t)3) - wb) >> 2);  // 0 .. 12
+    const uint32_t *bw = reinterpret_cast<const uint32_t *>(J.bd + wb) + (lane < 16 ? lane : 16);
 
-    // add the waves' digit sums into limb accumulators: digit k of the block (k = 32 row + col)
-    // sits at bit 7 k; its lower 32 bits after the shift go to limb 7k >> 5 (X), the rest to the
-    // next limb (Y)
-    unsigned long long *X = reinterpret_cast<unsigned long long *>(lds);
-    unsigned long long *Y = X + MFMA_LIMBS;
-    for (int x = tid; x < 2 * MFMA_LIMBS; x += MFMA_TPB) X[x] = 0ull;
-    __syncthreads();
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);  // wave-uniform: scalar loop control
+    for (int ci = 0; ci < 4; ++ci) {
+        const int64_t t0 = ta + wvu + 8 * ci;
+        if (t0 >= tb) break;
+        const int64_t ns = uniform64((tb - t0 + 31) / 32);  // steps t = t0 + 32 k, k < ns
+        // fragment slots: tile rt at step k uses fr[(rt - k) mod RT]; the loads of step k + PF
+        // go into ring slot k mod PF (clamped to the last step, which stays in bounds)
+        v4i fr[RT];
 #pragma unroll
-    for (int rt = 0; rt < MFMA_RT; ++rt) {
+        for (int rt = 1; rt < RT; ++rt) fr[rt] = mfma_frag(arow, S0 + 32 * rt - t0);
+        v4i pa[PF];
+        uint32_t pb[PF];
+        auto fetch = [&](int q, int64_t k) {
+            const int64_t kk = k < ns ? k : ns - 1;
+            pa[q] = mfma_frag(arow, S0 - t0 - 32 * kk);
+            pb[q] = *(gu32 *)(bw - 8 * (t0 + 32 * kk));
+        };
+#pragma unroll
+        for (int q = 0; q < PF; ++q) fetch(q, q);
+        // the b-operand of step k + 1 is assembled (shuffles, realignment) while the matrix
+        // operations of step k run
+        v4i bop = mfma_bop(pb[0], sel, sh);
+        auto step = [&](int j, int64_t k) {
+            fr[(RT - j) % RT] = pa[j % PF];
+            fetch(j % PF, k + PF);
+            // keep the loads at the head of their step (the scheduler would otherwise sink
+            // them towards their uses and shorten the prefetch distance)
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fr[(rt - j + RT) % RT], bop, acc[rt], 0, 0, 0);
+            bop = mfma_bop(pb[(j + 1) % PF], sel, sh);
+        };
+        int64_t kb = 0;
+        for (; kb + RT <= ns; kb += RT) {
+#pragma unroll
+            for (int j = 0; j < RT; ++j) step(j, kb + j);
+        }
+#pragma unroll
+        for (int j = 0; j < RT - 1; ++j)
+            if (kb + j < ns) step(j, kb + j);
+    }
+    __syncthreads();
+
+    // digit sums of the block: digit 32 row + col; result register i of lane (m, g) in tile rt
+    // is row 32 rt + 8 (i / 4) + 4 g + i % 4, column m
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int row = 32 * rt + 8 * (i >> 2) + 4 * g + (i & 3);
-            const int k = 32 * row + m;
-            const uint64_t v = (uint64_t)(uint32_t)acc[rt][i] << ((7 * k) & 31);
-            const int j = (7 * k) >> 5;
-            if (v) {
-                atomicAdd(&X[j], (unsigned long long)(uint32_t)v);
-                if (v >> 32) atomicAdd(&Y[j], (unsigned long long)(v >> 32));
-            }
+            const uint32_t v = (uint32_t)acc[rt][i];
+            if (v) atomicAdd(&D[32 * (32 * rt + 8 * (i >> 2) + 4 * g + (i & 3)) + m], (unsigned long long)v);
         }
-    }
     __syncthreads();
-    uint32_t *out = J.cols + 3 * (local * MFMA_LIMBS);
+
+    // limb column j of the block takes the digits k with 7 k in [32 j, 32 j + 32):
+    // D[k] 2^(7k - 32j) split as x (low 32 bits, weight 2^0) + y (weight 2^32)
+    unsigned long long *out = J.cols + 2 * grp * MFMA_LIMBS;
     for (int j = tid; j < MFMA_LIMBS; j += MFMA_TPB) {
-        const uint64_t xv = X[j], yv = Y[j];
-        const uint64_t rest = (xv >> 32) + yv;  // weight 2^32 relative to limb j
-        out[3 * j + 0] = (uint32_t)xv;
-        out[3 * j + 1] = (uint32_t)rest;
-        out[3 * j + 2] = (uint32_t)(rest >> 32);
+        const int k0 = (32 * j + 6) / 7, k1 = (32 * j + 31) / 7;
+        unsigned long long x = 0, y = 0;
+        for (int k = k0; k <= k1; ++k) {
+            const unsigned long long v = D[k];
+            const int s = 7 * k - 32 * j;
+            x += (unsigned long long)((uint32_t)v << s);
+            y += s ? (v >> (32 - s)) : (v >> 32);
+        }
+        if (x) __hip_atomic_fetch_add(out + 2 * j, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (y) __hip_atomic_fetch_add(out + 2 * j + 1, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -34,9 +34,11 @@ struct MulGeom {
     int fa, fb;  // operand (pack) indices
     int engine;  // KS_ENGINE_VALU or KS_ENGINE_MFMA
     int64_t na, nb, ntiles;
-    int64_t ncols, cols_off, blocks;  // column sums: 3 words per column
-    // matrix-core engine: 7-bit digit buffers (byte offsets in the digit region)
+    int64_t ncols, cols_off, blocks;  // column sums: 3 words (vector ALU) or 4 words (matrix cores)
+    // matrix-core engine: 7-bit digit buffers (byte offsets in the digit region), row groups
+    // of MFMA_ROWS output rows, each cut into `splits` parts of `part` block shifts
     int64_t nad = 0, nbd = 0, nA32 = 0, nB32 = 0, a_front = 0, a_len = 0, b_len = 0, b_top = 0;
+    int64_t groups = 0, splits = 1, part = 0;
     int64_t ad_off = 0, bd_off = 0;
 };
 struct NormGeom {

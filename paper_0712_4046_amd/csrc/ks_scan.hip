@@ -139,24 +139,39 @@ struct TermSigns {
     bool negA[2], negB[2];
 };
 
-// v[m] += sign * (column j0 - 2 + m of the product), m in [0, NV)
-__device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bool negB, int64_t j0,
-                                                int64_t (&v)[NV]) {
+// v[m] += sign * (column j0 - 2 + m of the product), m in [0, NV).  Column sums come as
+// three uint32 pieces per column (value j gets piece 0 of j, 1 of j-1, 2 of j-2) or as two
+// uint64 per column, i.e. four uint32 words (value j gets word 0 of j, words 1 and 2 of j-1,
+// word 3 of j-2).
+template <int P>
+__device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int64_t (&acc)[NV]) {
     const int64_t c0 = j0 - 4;
-    uint32_t x[3 * NWIN];
+    uint32_t x[P * NWIN];
 #pragma unroll
-    for (int t = 0; t < 3 * NWIN; ++t) {
-        const int64_t col = c0 + t / 3;
+    for (int t = 0; t < P * NWIN; ++t) {
+        const int64_t col = c0 + t / P;
         const bool ok = col >= 0 && col < T.ncols;
-        x[t] = T.cols[ok ? 3 * c0 + t : 0];
+        x[t] = T.cols[ok ? P * c0 + t : 0];
         x[t] = ok ? x[t] : 0u;
     }
-    int64_t acc[NV];
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
         const int w = m + 2;  // window column of position j0 - 2 + m
-        acc[m] = (int64_t)x[3 * w] + (int64_t)x[3 * (w - 1) + 1] + (int64_t)x[3 * (w - 2) + 2];
+        if (P == 3)
+            acc[m] = (int64_t)x[3 * w] + (int64_t)x[3 * (w - 1) + 1] + (int64_t)x[3 * (w - 2) + 2];
+        else
+            acc[m] = (int64_t)x[4 * w] + (int64_t)x[4 * (w - 1) + 1] + (int64_t)x[4 * (w - 1) + 2] +
+                     (int64_t)x[4 * (w - 2) + 3];
     }
+}
+
+__device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bool negB, int64_t j0,
+                                                int64_t (&v)[NV]) {
+    int64_t acc[NV];
+    if (T.fmt == NORM_FMT_XY)
+        column_window<4>(T, j0, acc);
+    else
+        column_window<3>(T, j0, acc);
     // the multiplier works on the unsigned readings of two's-complement operands:
     // A B = Au Bu - [A<0] Bu 2^(32 na) - [B<0] Au 2^(32 nb) + [A<0][B<0] 2^(32 (na+nb))
     if (negA) {

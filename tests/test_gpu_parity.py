@@ -189,3 +189,35 @@ def test_out_of_range_coefficient_is_reported(torch_dev, oracle):
     fb = oracle.ints_to_limbs([1, 200, 3, 4], 1)  # 200 is not an 8-bit signed value
     ks.mul(ks.to_device(fb), ks.to_device(fs), 8, "ks4", True)
     assert ks.status() == ks.KS_ERANGE
+
+
+@pytest.mark.parametrize("blocks,min_part", [("1", "1000000"), ("4096", "32"), ("1024", "128")])
+def test_mfma_part_splits(torch_dev, oracle, monkeypatch, blocks, min_part):
+    # the matrix-core multiplier cuts each row group's shift range into parts whose column sums
+    # meet in 64-bit atomics: one part per group, many short parts, and the default
+    monkeypatch.setenv("KS_MFMA_BLOCKS", blocks)
+    monkeypatch.setenv("KS_MFMA_MIN_PART", min_part)
+    P = wl.config2()
+    exp = want(oracle, P.f, P.g, P.bits, P.signed)
+    for v in VARIANTS:
+        assert_same(gpu_mul(P.f, P.g, P.bits, v, P.signed, "mfma"), exp, f"config2 {v} blocks={blocks} part>={min_part}")
+
+
+@pytest.mark.parametrize("variant", ["ks1", "neg2"])
+def test_mfma_long_shift_ranges_sampled(torch_dev, oracle, variant):
+    # L = 65536 signed 64-bit: the standard substitution's operands hold ~295k limbs (~1.35M
+    # digits), more block shifts per row group than one part may take (32768), so every row
+    # group is split; checked on the first and last coefficients and a random sample
+    L, bits = 65536, 64
+    gen = wl.rng(41)
+    f = wl.random_coeffs(gen, L, bits, True)
+    g = wl.random_coeffs(gen, L, bits, True)
+    tf, tg = ks.to_device(f), ks.to_device(g)
+    h = ks.mul(tf, tg, bits, variant, True, engine="mfma")
+    assert ks.status() == ks.KS_OK
+    got = ks.to_host(h)
+    D = 2 * L - 1
+    idx = np.unique(np.concatenate([np.arange(0, 40), np.arange(D - 40, D), np.arange(L - 20, L + 20),
+                                    wl.rng(42).integers(0, D, 300)]))
+    exp = oracle.coeffs_classical(f, g, True, idx, got.shape[1])
+    assert_same(got[idx], exp, f"L=65536 {variant} mfma sampled")
