@@ -18,7 +18,7 @@ constexpr int MAX_INLINE_JOBS = 8;
 
 // carry-scan kernels (pack, normalize): 256 threads x 8 limbs per block
 constexpr int SCAN_TPB = 256;
-constexpr int SCAN_IPT = 8;
+constexpr int SCAN_IPT = 2;
 constexpr int64_t SCAN_BL = (int64_t)SCAN_TPB * SCAN_IPT;
 
 // vector-ALU multiplier: a block of MUL_WAVES waves owns MUL_T = 64 * MUL_R product columns;
