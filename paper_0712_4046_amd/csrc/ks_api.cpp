@@ -488,9 +488,16 @@ static Launch<J> make_launch(const std::vector<J> &jobs, const DevList *tab, con
 int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, uint32_t epoch_pack,
                  uint32_t epoch_norm, hipStream_t s) {
     hipError_t err;
+    // the first anchor list rides in the pack launch (anchors read only the inputs)
+    auto first_anchor = JL.anchor.begin();
     {
         auto L = make_launch(JL.pack, T ? &T->pack : nullptr, env, epoch_pack);
-        err = timed("pack", s, [&] { return launch_pack(L, s); });
+        if (first_anchor != JL.anchor.end()) {
+            auto La = make_launch(first_anchor->second, T ? &T->anchor.at(first_anchor->first) : nullptr, env, 0);
+            err = timed("pack", s, [&] { return launch_pack_anchor(L, La, first_anchor->first, s); });
+        } else {
+            err = timed("pack", s, [&] { return launch_pack(L, s); });
+        }
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.mul.empty()) {
@@ -506,7 +513,9 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         err = timed("mul_mfma", s, [&] { return launch_mul_mfma(L, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
-    for (auto &kv : JL.anchor) {
+    for (auto it = JL.anchor.begin(); it != JL.anchor.end(); ++it) {
+        if (it == first_anchor) continue;
+        const auto &kv = *it;
         auto L = make_launch(kv.second, T ? &T->anchor.at(kv.first) : nullptr, env, 0);
         err = timed("anchor", s, [&] { return launch_anchor(L, kv.first, s); });
         if (err != hipSuccess) return KS_EHIP;

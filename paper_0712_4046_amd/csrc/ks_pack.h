@@ -1,0 +1,118 @@
+// ks_pack.h -- evaluation of the inputs at the Kronecker points (the pack stage): the block
+// body shared by the pack kernel and the fused pack-and-anchor launch.
+#pragma once
+
+#include "ks_device.h"
+
+namespace ks {
+
+// Pack by scattering: each thread takes whole coefficients (coalesced loads, all independent)
+// and adds their 32-bit pieces into the block's LDS limb columns; the columns before and after
+// the block's range that the carry scan needs are filled the same way.
+constexpr int PK_MAXW = 8;  // limbs of one input coefficient (coeff_bits <= 256)
+
+// bits [s, s+32) of a coefficient held in registers (s may be negative: bits below 0 read 0)
+__device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[PK_MAXW], int w, uint32_t fill, int s) {
+    if (s <= -32) return 0u;
+    if (s < 0) return cl[0] << (-s);
+    const int q = s >> 5, o = s & 31;
+    uint32_t a = fill, b = fill;
+#pragma unroll
+    for (int t = 0; t < PK_MAXW; ++t) {
+        if (t < w && t == q) a = cl[t];
+        if (t < w && t == q + 1) b = cl[t];
+    }
+    return o ? (a >> o) | (b << (32 - o)) : a;
+}
+
+// One block of the pack launch (its position in the look-back order comes from the ticket).
+__device__ __forceinline__ void pack_block(const Launch<PackJob> &L) {
+    typedef BlockCarryScan<SCAN_TPB, SCAN_IPT> Scan;
+    __shared__ typename Scan::Smem sm;
+    __shared__ uint32_t s_ticket;
+    __shared__ int64_t s_v[SCAN_BL + 3];  // s_v[x + 2] = column jb + x, x in [-2, SCAN_BL]
+    if (threadIdx.x == 0) s_ticket = lb_ticket(L.ticket, L.epoch);
+    for (int x = threadIdx.x; x < SCAN_BL + 3; x += SCAN_TPB) s_v[x] = 0;
+    __syncthreads();
+    const int64_t blk = s_ticket;
+    int64_t local;
+    const PackJob J = get_job(L, blk, local);
+    const int tid = threadIdx.x;
+    const int64_t jb = local * SCAN_BL;
+    const int64_t jlo = jb - 2, jhi = jb + SCAN_BL + 1;  // columns [jlo, jhi)
+    const int64_t N = J.N;
+    const int bits = J.bits, w_in = J.w_in;
+    const bool sgn = (J.flags & PK_SIGNED) != 0;
+    // coefficients i whose bits [i N, i N + bits) meet limbs [jlo, jhi)
+    const int64_t a = 32 * jlo - bits + 1;
+    int64_t i0 = a <= 0 ? 0 : div_by(a + N - 1, J.N_recip);
+    int64_t i1 = jhi <= 0 ? -1 : div_by(32 * jhi - 1, J.N_recip);
+    if (i1 > J.L - 1) i1 = J.L - 1;
+    constexpr int U = 4;  // coefficients per thread per round, loads issued together
+    for (int64_t ib = i0 + tid; ib <= i1; ib += U * SCAN_TPB) {
+        uint32_t cl[U][PK_MAXW];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t i = ib + (int64_t)q * SCAN_TPB;
+            const int64_t ii = i <= i1 ? i : i0;
+            const int64_t src = (J.flags & PK_REVERSE) ? J.L - 1 - ii : ii;
+            const uint32_t *c = J.coeffs + src * w_in;
+#pragma unroll
+            for (int t = 0; t < PK_MAXW; ++t) {
+                const uint32_t x = c[t < w_in ? t : w_in - 1];
+                cl[q][t] = t < w_in ? x : 0u;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t i = ib + (int64_t)q * SCAN_TPB;
+            if (i > i1) continue;
+            uint32_t top = 0;
+#pragma unroll
+            for (int t = 0; t < PK_MAXW; ++t) top = (t == w_in - 1) ? cl[q][t] : top;
+            const uint32_t fill = (sgn && (top >> 31)) ? 0xffffffffu : 0u;
+            const int64_t p = i * N;
+            const int64_t w = p >> 5;
+            const int r = (int)(p & 31);
+            const int npieces = (bits + r + 31) >> 5;
+            const bool neg = (J.flags & PK_ALTERNATE) && (i & 1);
+            for (int t = 0; t < npieces; ++t) {
+                const int64_t j = w + t;
+                if (j < jlo || j >= jhi) continue;
+                const uint32_t word = reg_word(cl[q], w_in, fill, 32 * t - r);
+                int64_t piece = (sgn && t == npieces - 1) ? (int64_t)(int32_t)word : (int64_t)word;
+                if (neg) piece = -piece;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&s_v[j - jb + 2]), (unsigned long long)piece);
+            }
+            if ((J.flags & PK_CHECK) && w >= jb && w < jb + SCAN_BL) {
+                // range check, once per coefficient (in the block holding its lowest limb)
+                bool ok;
+                if (J.mod_p) {
+                    ok = (((uint64_t)cl[q][1] << 32) | cl[q][0]) < J.mod_p;
+                } else {
+                    const int tb = bits - 32 * (w_in - 1);  // bits used in the top limb, 1..32
+                    if (sgn) {
+                        const int32_t sx = (int32_t)top >> (tb - 1);
+                        ok = (sx == 0 || sx == -1);
+                    } else {
+                        ok = tb == 32 ? true : (top >> tb) == 0;
+                    }
+                }
+                if (!ok) set_status(L.devstat, KS_DEVSTAT_RANGE);
+            }
+        }
+    }
+    __syncthreads();
+    const int b0 = tid * SCAN_IPT;
+    int64_t u[SCAN_IPT];
+#pragma unroll
+    for (int q = 0; q < SCAN_IPT; ++q) u[q] = u_of(s_v[b0 + q + 2], s_v[b0 + q + 1], s_v[b0 + q]);
+    uint32_t out[SCAN_IPT];
+    Scan::run(sm, u, out, L.status + J.block0, local, L.epoch, L.devstat);
+    const int64_t j0 = jb + b0;
+#pragma unroll
+    for (int q = 0; q < SCAN_IPT; ++q)
+        if (j0 + q < J.n_out) J.out[j0 + q] = out[q];
+}
+
+}  // namespace ks
