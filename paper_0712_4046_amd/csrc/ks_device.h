@@ -179,6 +179,14 @@ struct BlockCarryScan {
     }
 };
 
+// ---- loads through global (not flat) pointers ---------------------------------------------------
+// A flat load also counts against the LDS wait counter, so a kernel that prefetches from
+// global memory while it works out of LDS would drain its prefetches at every LDS wait.
+template <class T>
+__device__ __forceinline__ T ldg(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
 // ---- job lookup: block index -> (job, block within job) ----------------------------------------
 // Inline jobs: all block0 values are loaded at once (independent scalar loads, one round
 // trip).  Device tables: one load from the block -> job map.

@@ -46,20 +46,39 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
 #pragma unroll
     for (int r = 0; r < MUL_R; ++r) { lo[r] = 0; hi[r] = 0; }
 
-    // the waves take interleaved chunks of the i range: wave w runs chunks w, w + WAVES, ...
+    // the waves take interleaved chunks of the i range: wave w runs chunks w, w + WAVES, ...;
+    // the next chunk's operands are loaded into registers while the current one is computed
     const int64_t span = (int64_t)MUL_WAVES * MUL_CI;
     const int64_t niter = ihi > ilo ? (ihi - ilo + span - 1) / span : 0;
     const int base = lane * MUL_R + MUL_CI - MUL_R;
+    constexpr int NA = MUL_CI / 64, NB = (MUL_T + MUL_CI) / 64;
+    static_assert(MUL_CI % 64 == 0 && (MUL_T + MUL_CI) % 64 == 0, "staging is 64 words per lane round");
+    uint32_t ra[NA], rb[NB];
+    auto fetch = [&](int64_t it) {
+        const int64_t c0 = ilo + it * span + (int64_t)wv * MUL_CI;
+        const bool active = c0 < ihi;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int64_t i = c0 + lane + 64 * q;
+            ra[q] = (active && i < ihi) ? ldg(J.a + i) : 0u;
+        }
+        const int64_t bfirst = k0 - c0 - MUL_CI + 1;  // b index held in sb[wv][0]
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int64_t bi = bfirst + lane + 64 * q;
+            rb[q] = (active && bi >= 0 && bi < J.nb) ? ldg(J.b + bi) : 0u;
+        }
+    };
+    if (niter > 0) fetch(0);
     for (int64_t it = 0; it < niter; ++it) {
         const int64_t c0 = ilo + it * span + (int64_t)wv * MUL_CI;
         const bool active = c0 < ihi;
-        for (int x = lane; x < MUL_CI; x += 64) sa[wv][x] = (active && c0 + x < ihi) ? J.a[c0 + x] : 0u;
-        const int64_t bfirst = k0 - c0 - MUL_CI + 1;  // b index held in sb[wv][0]
-        for (int x = lane; x < MUL_T + MUL_CI; x += 64) {
-            const int64_t bi = bfirst + x;
-            sb[wv][x] = (active && bi >= 0 && bi < J.nb) ? J.b[bi] : 0u;
-        }
+#pragma unroll
+        for (int q = 0; q < NA; ++q) sa[wv][lane + 64 * q] = ra[q];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) sb[wv][lane + 64 * q] = rb[q];
         __syncthreads();
+        if (it + 1 < niter) fetch(it + 1);
         if (active) {
             // E[idx] = sb[base - x0 + idx]; column r at step x0 + u uses E[R - 1 + r - u]
             uint2 ehi = *reinterpret_cast<const uint2 *>(&sb[wv][base + MUL_R]);
