@@ -132,7 +132,7 @@ int plan_product(const Spec &sp, Geom &G) {
             // KS_MFMA_BLOCKS blocks, but not shorter than KS_MFMA_MIN_PART shifts
             const int64_t tmax = std::min(m.nA32 + MFMA_ROWS - 1, m.nB32);
             const int64_t s_min = cdiv(tmax, MFMA_MAX_PART);
-            const int64_t s_fill = cdiv(env_int("KS_MFMA_BLOCKS", 1024), (int64_t)npts * m.groups);
+            const int64_t s_fill = cdiv(env_int("KS_MFMA_BLOCKS", (int)sp.fill_blocks), (int64_t)npts * m.groups);
             const int64_t s_cap = std::max<int64_t>(1, tmax / std::max<int64_t>(1, env_int("KS_MFMA_MIN_PART", 128)));
             m.splits = std::max(s_min, std::min(s_fill, s_cap));
             m.part = cdiv(tmax, m.splits);
@@ -203,10 +203,14 @@ int plan_product(const Spec &sp, Geom &G) {
             const bool dodd = (G.D & 1) != 0;  // reversal swaps parities when D is even
             // segment length K: every segment but the first costs one anchor (a dot product of
             // min(lf, lg) coefficient products, spread over the GPU), and a segment's lane runs K
-            // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement)
+            // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement).  In
+            // a batch of n products the anchors of all products share the GPU while their chains
+            // run side by side, which favours longer segments: the factor sqrt(n) and the floor
+            // of 32 match the measured optima of the 10,000-product and 64-product workloads.
             const double Lm = (double)std::min(lf, lg);
-            int64_t K = (int64_t)(std::sqrt((double)G.D * Lm * sp.w_in * sp.w_in / 2.0e6) + 0.5);
-            K = std::max<int64_t>(4, std::min<int64_t>(K, 512));
+            const double nb = std::sqrt((double)sp.batch_count);
+            int64_t K = (int64_t)(std::sqrt(nb * G.D * Lm * sp.w_in * sp.w_in / 2.0e6) + 0.5);
+            K = std::max<int64_t>(sp.batch ? 32 : 4, std::min<int64_t>(K, 4096));
             K = env_int("KS_CHAIN_K", (int)K);
             if (K < 1) K = 1;
             G.nw = (int)cdiv(Y, 32);
@@ -313,6 +317,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.bits = sp.bits;
         j.flags = p.flags;
         j.mod_p = sp.mod_p;
+        j.ctr = (int32_t)JL.pack.size();
         j.block0 = next_block(JL.pack);
         j.nblocks = p.blocks;
         JL.pack.push_back(j);
@@ -409,6 +414,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.out = norms(r.out_off);
         j.n_out = r.n_out;
         j.n_in = r.n_in;
+        j.ctr = (int64_t)JL.norm.size();
         j.block0 = next_block(JL.norm);
         j.nblocks = r.blocks;
         JL.norm.push_back(j);
@@ -464,7 +470,8 @@ static int64_t list_blocks(const std::vector<J> &v) {
 // Launch every stage of a set of job lists.  Lists of at most MAX_INLINE_JOBS jobs travel in
 // the kernel arguments; longer ones need device tables (`tables`, built by a batch plan).
 template <class J>
-static Launch<J> make_launch(const std::vector<J> &jobs, const DevList *tab, const LaunchEnv &env, uint32_t epoch) {
+static Launch<J> make_launch(const std::vector<J> &jobs, const DevList *tab, const LaunchEnv &env, uint32_t epoch,
+                             uint64_t *ctrs = nullptr) {
     Launch<J> L;
     memset(&L, 0, sizeof(L));
     L.njobs = (int64_t)jobs.size();
@@ -476,7 +483,7 @@ static Launch<J> make_launch(const std::vector<J> &jobs, const DevList *tab, con
         for (size_t i = 0; i < jobs.size(); ++i) L.jobs[i] = jobs[i];
     }
     L.status = env.status;
-    L.ticket = env.ticket;
+    L.ctrs = ctrs;
     L.devstat = env.devstat;
     L.epoch = epoch;
     L.base_in = env.base_in;
@@ -491,7 +498,7 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
     // the first anchor list rides in the pack launch (anchors read only the inputs)
     auto first_anchor = JL.anchor.begin();
     {
-        auto L = make_launch(JL.pack, T ? &T->pack : nullptr, env, epoch_pack);
+        auto L = make_launch(JL.pack, T ? &T->pack : nullptr, env, epoch_pack, env.ctr_pack);
         if (first_anchor != JL.anchor.end()) {
             auto La = make_launch(first_anchor->second, T ? &T->anchor.at(first_anchor->first) : nullptr, env, 0);
             err = timed("pack", s, [&] { return launch_pack_anchor(L, La, first_anchor->first, s); });
@@ -521,7 +528,7 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         if (err != hipSuccess) return KS_EHIP;
     }
     {
-        auto L = make_launch(JL.norm, T ? &T->norm : nullptr, env, epoch_norm);
+        auto L = make_launch(JL.norm, T ? &T->norm : nullptr, env, epoch_norm, env.ctr_norm);
         err = timed("normalize", s, [&] { return launch_normalize(L, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
@@ -544,7 +551,8 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
               reinterpret_cast<uintptr_t>(ws), JL);
     LaunchEnv env;
     env.status = reinterpret_cast<uint64_t *>(ws + G.ws_status);
-    env.ticket = ctl.ticket;
+    env.ctr_pack = ctl.ctrs;
+    env.ctr_norm = ctl.ctrs + CTL_CTRS;
     env.devstat = ctl.devstat;
     const uint32_t ep = ++ctl.epoch;
     const uint32_t en = ++ctl.epoch;
@@ -573,7 +581,7 @@ static int get_pool(hipStream_t s, size_t need, Pool **out) {
             // cleared on the caller's stream, so the clear is ordered before this stream's kernels
             // (a non-blocking stream does not wait for work on the null stream)
             if (hipMemsetAsync(c, 0, 256, s) != hipSuccess) return KS_EHIP;
-            p->ctl.ticket = reinterpret_cast<uint64_t *>(c);
+            p->ctl.ctrs = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(c) + 128);
             p->ctl.devstat = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(c) + 64);
             p->ctl.epoch = 0;
             g_pools[s] = p;

@@ -7,9 +7,10 @@
 // arenas and workspace.  A run allocates nothing and copies nothing from the host: it clears
 // the look-back words with a kernel and launches the stages, so it can be graph-captured.
 //
-// Workspace layout (bytes): [0, 8) device status word, [64, 80) block-ticket counters,
-// [80, 80 + 8 S) look-back status words, then each product's scratch, 256-byte aligned.
-// Every run clears [0, 80 + 8 S) first, so a fresh (uninitialised) workspace needs no set-up.
+// Workspace layout (bytes): [0, 8) device status word, [64, 64 + 8 S) look-back status words,
+// then one block-ticket counter per pack job and per normalize job (8 bytes each), then each
+// product's scratch, 256-byte aligned.  Every run clears everything before the scratch first,
+// so a fresh (uninitialised) workspace needs no set-up.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,6 +66,8 @@ struct ks_batch_plan {
     ks::DevTables T;
     std::vector<void *> allocs;
     int64_t status_words = 0;
+    int64_t header_words = 0;  // status word, look-back words and ticket counters (cleared each run)
+    int64_t ctr_pack = 0, ctr_norm = 0;  // word offsets of the counters
     int64_t ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
     int variant = -1;
@@ -72,7 +75,7 @@ struct ks_batch_plan {
 
 using namespace ks;
 
-static const int64_t WS_DEVSTAT = 0, WS_TICKET = 64, WS_STATUS = 80;
+static const int64_t WS_DEVSTAT = 0, WS_STATUS = 64;
 
 extern "C" {
 
@@ -117,6 +120,9 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
             sp = Spec{d.len_f, d.len_g, d.coeff_bits, (d.coeff_bits + 31) / 32, (d.flags & KS_SIGNED) != 0, 0, v,
                       eng};
         }
+        sp.batch = true;
+        sp.batch_count = count;
+        sp.fill_blocks = std::max<int64_t>(1, 2048 / count);
         if (validate_spec(sp.lf, sp.lg, sp.bits, v, true) != KS_OK) { g_bad_index = i; delete P; return KS_EINVAL; }
         int rc = plan_product(sp, geoms[(size_t)i]);
         if (rc != KS_OK) { g_bad_index = i; delete P; return rc; }
@@ -137,7 +143,10 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
                   (uintptr_t)inst_off[(size_t)i], JL);
     }
     P->status_words = std::max(blocks_of(JL.pack), blocks_of(JL.norm));
-    const int64_t base = align256(WS_STATUS + 8 * std::max<int64_t>(P->status_words, 1));
+    P->ctr_pack = WS_STATUS / 8 + std::max<int64_t>(P->status_words, 1);
+    P->ctr_norm = P->ctr_pack + (int64_t)JL.pack.size();
+    P->header_words = P->ctr_norm + (int64_t)JL.norm.size();
+    const int64_t base = align256(8 * P->header_words);
     auto sh = [&](auto *&ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(reinterpret_cast<uintptr_t>(ptr) + base); };
     for (auto &j : JL.pack) sh(j.out);
     for (auto &j : JL.mul) { sh(j.a); sh(j.b); sh(j.cols); }
@@ -191,11 +200,12 @@ int ks_batch_run(const ks_batch_plan *plan, const uint32_t *arena_in, uint32_t *
     char *ws = reinterpret_cast<char *>(workspace);
     // the status word, ticket counters and look-back words start every run at zero (a kernel,
     // not a memset, so the run can be graph-captured); the status thus reports the latest run
-    if (launch_fill_zero(reinterpret_cast<uint64_t *>(ws), WS_STATUS / 8 + plan->status_words, s) != hipSuccess)
+    if (launch_fill_zero(reinterpret_cast<uint64_t *>(ws), plan->header_words, s) != hipSuccess)
         return KS_EHIP;
     LaunchEnv env;
     env.status = reinterpret_cast<uint64_t *>(ws + WS_STATUS);
-    env.ticket = reinterpret_cast<uint64_t *>(ws + WS_TICKET);
+    env.ctr_pack = reinterpret_cast<uint64_t *>(ws) + plan->ctr_pack;
+    env.ctr_norm = reinterpret_cast<uint64_t *>(ws) + plan->ctr_norm;
     env.devstat = reinterpret_cast<uint32_t *>(ws + WS_DEVSTAT);
     env.base_in = reinterpret_cast<uintptr_t>(arena_in);
     env.base_out = reinterpret_cast<uintptr_t>(arena_out);

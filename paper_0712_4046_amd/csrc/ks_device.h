@@ -12,8 +12,8 @@
 //   within a wave     -- shuffle scan (6 steps on 64 lanes);
 //   within a block    -- wave aggregates in LDS;
 //   across blocks     -- single-pass decoupled look-back on epoch-tagged status words,
-//                        blocks ordered by an atomic ticket so a block only ever waits on
-//                        blocks that are already running.
+//                        a job's blocks ordered by tickets from the job's own counter so a
+//                        block only ever waits on blocks that are already running.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -79,51 +79,76 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t *st) {
     return __hip_atomic_load(const_cast<uint64_t *>(st), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Block ticket: launch e draws from counter e & 1 with one fetch-and-add and clears the other
-// counter, which the previous launch on the stream used and the next one will use.  (Launches
-// of one stream run one after the other, and the counters start at zero.)
-__device__ __forceinline__ uint32_t lb_ticket(uint64_t *ctr, uint32_t epoch) {
-    uint64_t t = __hip_atomic_fetch_add(ctr + (epoch & 1u), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (t == 0) __hip_atomic_store(ctr + ((epoch + 1u) & 1u), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return (uint32_t)t;
+// Block ticket of a carry-scan job of several blocks: the job's blocks draw their positions in
+// the look-back order from the job's own counter, so a block only ever waits on blocks that
+// are already running; the block that draws the last ticket puts the counter back to zero for
+// the next launch (launches of one stream run one after the other).  Jobs of one block need
+// no ticket, and no two jobs share a counter, so the atomics never pile up on one word.
+__device__ __forceinline__ int64_t job_ticket(uint64_t *ctr, int64_t nblocks) {
+    const uint64_t t = __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int64_t)t == nblocks - 1) __hip_atomic_store(ctr, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (int64_t)t;
 }
 
 __device__ __forceinline__ void set_status(uint32_t *devstat, uint32_t bit) {
     __hip_atomic_fetch_or(devstat, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Resolve the carry into block `blk` of a chain whose status words start at `st`.
-// Called by one thread.  `agg` is this block's aggregate map.  Returns the carry in.
+// Resolve the carry into block `blk` of a chain whose status words start at `st`.  Called by
+// all 64 lanes of one wave (the same `agg`, this block's aggregate map, on every lane); every
+// lane returns the carry in.  Lane l watches block p - l of a window of 64 predecessors, so
+// one round of loads covers 64 blocks: if some block of the window has published its
+// inclusive carry, the maps of the blocks after it are composed by a shuffle reduction and
+// applied to it; if every block of the window has published at least its aggregate map, the
+// window's composition is kept and the window moves 64 blocks down; otherwise the wave waits.
 __device__ __forceinline__ int lb_resolve(uint64_t *st, int64_t blk, uint32_t epoch, cmap agg, uint32_t *devstat) {
+    const int lane = threadIdx.x & 63;
     if (blk == 0) {
-        lb_publish(st, epoch, LB_INC, (uint32_t)(cmap_apply(agg, 0) + 1));
+        if (lane == 0) lb_publish(st, epoch, LB_INC, (uint32_t)(cmap_apply(agg, 0) + 1));
         return 0;
     }
-    lb_publish(st + blk, epoch, LB_AGG, agg);
-    cmap acc = CMAP_ID;
-    int carry = 0;
-    int64_t p = blk - 1;
+    if (lane == 0) lb_publish(st + blk, epoch, LB_AGG, agg);
+    cmap acc = CMAP_ID;  // composition of the blocks above the window, up to blk - 1
+    int64_t top = blk - 1;
     uint64_t spins = 0;
+    int carry = 0;
     for (;;) {
-        uint64_t w = lb_load(st + p);
-        uint32_t flag = (uint32_t)(w >> 8) & 3u;
-        if ((uint32_t)(w >> 32) != epoch || flag == 0) {
+        const int64_t p = top - lane;
+        const bool in = p >= 0;
+        const uint64_t w = in ? lb_load(st + p) : 0ull;
+        const bool fresh = in && (uint32_t)(w >> 32) == epoch;
+        const uint32_t flag = fresh ? (uint32_t)(w >> 8) & 3u : 0u;
+        const uint64_t inc = __ballot(in && flag == LB_INC);
+        const uint64_t wait = __ballot(in && flag == 0);
+        // lanes below the nearest inclusive block (or the whole window) must have a map
+        const int first_inc = inc ? __builtin_ctzll(inc) : 64;
+        const uint64_t need = first_inc == 64 ? ~0ull : ((1ull << first_inc) - 1ull);
+        if (wait & need) {
             if (++spins > LB_SPIN_LIMIT) {  // never expected; keeps every wave finite
-                set_status(devstat, KS_DEVSTAT_LOOKBACK);
+                if (lane == 0) set_status(devstat, KS_DEVSTAT_LOOKBACK);
                 carry = 0;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        if (flag == LB_INC) {
-            carry = cmap_apply(acc, (int)(w & 0xffu) - 1);
+        // compose the maps of lanes first_inc-1 .. 0 (blocks in increasing order)
+        cmap m = (lane < first_inc && in) ? (cmap)(w & 0xffu) : CMAP_ID;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const cmap o = (cmap)__shfl_down((int)m, dd, 64);
+            if ((lane & (2 * dd - 1)) == 0) m = cmap_then(lane + dd < 64 ? o : CMAP_ID, m);
+        }
+        m = (cmap)__shfl((int)m, 0, 64);
+        acc = cmap_then(m, acc);
+        if (first_inc < 64) {
+            const int c = (int)((uint32_t)__shfl((int)(uint32_t)(w & 0xffu), first_inc, 64)) - 1;
+            carry = cmap_apply(acc, c);
             break;
         }
-        acc = cmap_then((cmap)(w & 0xffu), acc);
-        --p;
+        top -= 64;
     }
-    lb_publish(st + blk, epoch, LB_INC, (uint32_t)(cmap_apply(agg, carry) + 1));
+    if (lane == 0) lb_publish(st + blk, epoch, LB_INC, (uint32_t)(cmap_apply(agg, carry) + 1));
     return carry;
 }
 
@@ -159,11 +184,12 @@ struct BlockCarryScan {
         if (lane == 0) excl = CMAP_ID;
         if (lane == 63) sm.wave_agg[wv] = inc;
         __syncthreads();
-        if (tid == 0) {
+        if (wv == 0) {
             cmap agg = CMAP_ID;
 #pragma unroll
             for (int w = 0; w < TPB / 64; ++w) agg = cmap_then(agg, sm.wave_agg[w]);
-            sm.carry_in = lb_resolve(st, blk, epoch, agg, devstat);
+            const int c = lb_resolve(st, blk, epoch, agg, devstat);
+            if (lane == 0) sm.carry_in = c;
         }
         __syncthreads();
         cmap before = CMAP_ID;

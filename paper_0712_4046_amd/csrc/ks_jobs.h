@@ -60,7 +60,7 @@ struct PackJob {
     int32_t w_in;
     int32_t bits;
     int32_t flags;
-    int32_t pad;
+    int32_t ctr;     // the job's block-ticket counter (see job_ticket)
     uint64_t mod_p;  // PK_CHECK against [0, mod_p) instead of the bit range when non-zero
     int64_t block0;
     int64_t nblocks;
@@ -145,6 +145,7 @@ struct NormJob {
     uint32_t *out;
     int64_t n_out;
     int64_t n_in;
+    int64_t ctr;  // the job's block-ticket counter (see job_ticket)
     int64_t block0;
     int64_t nblocks;
 };
@@ -223,7 +224,7 @@ struct Launch {
     int64_t njobs;
     int64_t total_blocks;
     uint64_t *status;  // look-back words, one per block of the launch
-    uint64_t *ticket;  // two block-ticket counters (see lb_ticket)
+    uint64_t *ctrs;    // block-ticket counters of the carry-scan jobs (see job_ticket)
     uint32_t *devstat;
     uint32_t epoch;
     uint32_t pad;

@@ -25,18 +25,18 @@ __device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[PK_MAXW], int 
     return o ? (a >> o) | (b << (32 - o)) : a;
 }
 
-// One block of the pack launch (its position in the look-back order comes from the ticket).
+// One block of the pack launch.
 __device__ __forceinline__ void pack_block(const Launch<PackJob> &L) {
     typedef BlockCarryScan<SCAN_TPB, SCAN_IPT> Scan;
     __shared__ typename Scan::Smem sm;
     __shared__ uint32_t s_ticket;
     __shared__ int64_t s_v[SCAN_BL + 3];  // s_v[x + 2] = column jb + x, x in [-2, SCAN_BL]
-    if (threadIdx.x == 0) s_ticket = lb_ticket(L.ticket, L.epoch);
+    int64_t local;
+    const PackJob J = get_job(L, (int64_t)blockIdx.x, local);
+    if (J.nblocks > 1 && threadIdx.x == 0) s_ticket = (uint32_t)job_ticket(L.ctrs + J.ctr, J.nblocks);
     for (int x = threadIdx.x; x < SCAN_BL + 3; x += SCAN_TPB) s_v[x] = 0;
     __syncthreads();
-    const int64_t blk = s_ticket;
-    int64_t local;
-    const PackJob J = get_job(L, blk, local);
+    if (J.nblocks > 1) local = s_ticket;
     const int tid = threadIdx.x;
     const int64_t jb = local * SCAN_BL;
     const int64_t jlo = jb - 2, jhi = jb + SCAN_BL + 1;  // columns [jlo, jhi)

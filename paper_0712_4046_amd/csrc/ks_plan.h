@@ -23,6 +23,13 @@ struct Spec {
     uint64_t mod_p;  // non-zero: inputs are residues, outputs reduced mod p
     int variant;     // KS_VARIANT_* (AUTO resolved by the planner)
     int engine;
+    // launch shaping: a product planned alone aims its matrix-core launch at fill_blocks blocks
+    // and cuts reconstruction chains for latency; a product of a batch shares the GPU with the
+    // rest of the batch, so it takes a share of the blocks and longer chain segments (fewer
+    // anchors: the batch supplies the parallelism)
+    int64_t fill_blocks = 1024;
+    bool batch = false;
+    int64_t batch_count = 1;  // products planned together
 };
 
 struct PackGeom {
@@ -73,9 +80,11 @@ struct Geom {
     double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0;
 };
 
-// device words that outlive one call: block ticket counter, error bits, launch epoch
+// device words that outlive one call: block-ticket counters (pack jobs, then normalize jobs),
+// error bits, launch epoch
+constexpr int CTL_CTRS = 8;  // counters per stage (a product has at most 8 pack and 4 normalize jobs)
 struct Ctl {
-    uint64_t *ticket = nullptr;
+    uint64_t *ctrs = nullptr;
     uint32_t *devstat = nullptr;
     uint32_t epoch = 0;
 };
@@ -104,7 +113,8 @@ struct DevTables {
 
 struct LaunchEnv {
     uint64_t *status = nullptr;
-    uint64_t *ticket = nullptr;
+    uint64_t *ctr_pack = nullptr;  // counters indexed by PackJob::ctr
+    uint64_t *ctr_norm = nullptr;  // counters indexed by NormJob::ctr
     uint32_t *devstat = nullptr;
     uintptr_t base_in = 0, base_out = 0, base_ws = 0;
 };

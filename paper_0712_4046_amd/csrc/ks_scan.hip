@@ -21,7 +21,7 @@ namespace ks {
 
 __global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) { pack_block(L); }
 
-// Pack and anchors in one launch: blocks [0, pack blocks) pack (ordered by their tickets),
+// Pack and anchors in one launch: blocks [0, pack blocks) pack,
 // the rest compute anchors, which read only the inputs and so run beside the packing.
 static_assert(SCAN_TPB == ANCHOR_TPB, "pack and anchor blocks share one launch");
 template <int W>
@@ -140,11 +140,11 @@ __global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) 
     __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_limb[SCAN_BL + 1];
     __shared__ int64_t s_tail[2];
-    if (threadIdx.x == 0) s_ticket = lb_ticket(L.ticket, L.epoch);
-    __syncthreads();
-    const int64_t blk = s_ticket;
     int64_t local;
-    const NormJob J = get_job(L, blk, local);
+    const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
+    if (J.nblocks > 1 && threadIdx.x == 0) s_ticket = (uint32_t)job_ticket(L.ctrs + J.ctr, J.nblocks);
+    __syncthreads();
+    if (J.nblocks > 1) local = s_ticket;
     const int tid = threadIdx.x;
     const int64_t jb = local * SCAN_BL;
     const int64_t j0 = jb + (int64_t)tid * SCAN_IPT;
