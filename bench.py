@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: exact dense products in Z[x] by multipoint Kronecker substitution on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config1] [--no-batch]
 
 A step is one whole product f*g through the library's hot path (pack -> integer products ->
 carry resolution and halving -> reconstruction / read-off), with the inputs already in HBM.
@@ -9,7 +9,10 @@ Workload (default): one product of two length-4096 polynomials with signed 64-bi
 coefficients drawn from seed 2 (the single-product configuration the paper's comparison is
 quoted on, at a size that fits one GPU).  The four-point variant (paper Section 3.4) is the
 reported value; the standard substitution (3.1) and the negated variant (3.3) are timed the
-same way for the speedup.  Prints ONE JSON line.
+same way for the speedup; each product runs on the engine the planner picks (vector ALU or
+int8 matrix cores).  Extra fields: per-kernel durations and the dominant kernel's roofline,
+the CPU oracle's rate on the host cores, and the two batched workloads (10,000 mixed products;
+64 products mod a 60-bit prime of length 65536) with their own rooflines.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -28,17 +31,18 @@ sys.path.insert(0, ROOT)
 # plus a v_addc (carry into the top word of a 96-bit column sum), both issuing at full rate:
 # 256 CUs x 64 lanes x 2.4 GHz / 2 instructions = 19.66e12 limb-mults/s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
+# int8 matrix cores (dense, no sparsity): 5.0e15 operations/s, one multiply-add = 2 operations
+MFMA_I8_PEAK_TOPS = 5000.0
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch measured with rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated) for
-# this workload's four-point product; see profiles/config2_ks4_hbm_traffic.txt.  A kernel whose
-# code changed after the counters were taken has no entry (traffic reported as null).
-MEASURED_TRAFFIC = {
-    "mul_valu": 1641728,
-    "normalize": 1602355,
-    "pack": 610737,
-    "anchor": 688597,
-    "recon": 661824,
-}
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated: FETCH x2,
+# WRITE x1) for the four-point product of the L=4096 workload (profiles/config2_ks4_hbm_traffic.txt)
+# and for the 64-product modular batch (profiles/config4_ks4_hbm_traffic.txt).  A kernel whose
+# code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
+# pack-and-anchor launch, "recon" the reconstruction chain.
+MEASURED_TRAFFIC = {"pack": 1009704, "mul_valu": 1641732, "normalize": 1255011, "recon": 658550}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 1020121474, "digitize": 950000387, "mul_mfma": 2530584193,
+                            "normalize": 1217221764, "recon": 288719068}
+KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "extract")
 
 
 def parse():
@@ -48,6 +52,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="config2", choices=["config1", "config2"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
 
@@ -61,6 +66,75 @@ def time_variant(ks, torch, tf, tg, bits, variant, signed, steps, warmup, out):
         ks.mul(tf, tg, bits, variant, signed, out=out)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def kernel_times(ks, run, reps):
+    """Average duration of each stage's launch, from HIP events the library records around
+    every launch on its own stream (ks_profile_*)."""
+    ks.profile_reset()
+    ks.profile_enable(True)
+    for _ in range(reps):
+        run()
+    import torch
+    torch.cuda.synchronize()
+    ks.profile_enable(False)
+    out = {}
+    for name in KERNELS:
+        n, ms = ks.profile_read(name)
+        if n:
+            out[name] = {"launches": n, "avg_us": 1000.0 * ms / n}
+    return out
+
+
+def roofline(kern, info, traffic_table=None):
+    """The dominant launch's achieved rate against its bound.  Work per launch is algorithmic:
+    limb products (vector-ALU multiplier), int8 operations (matrix cores) or the stage's bytes."""
+    dom = max(kern, key=lambda k: kern[k]["avg_us"])
+    sec = kern[dom]["avg_us"] * 1e-6
+    traffic = (traffic_table or {}).get(dom)
+    if dom == "mul_mfma":
+        ops = info["mfma_ops"]
+        achieved = ops / sec / 1e12
+        return {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / MFMA_I8_PEAK_TOPS, "traffic": traffic,
+                "op": "int8 multiply-add of 7-bit digits (2 operations)", "ops_per_launch": ops}
+    if dom in ("mul_valu", "anchor"):
+        ops = info["schoolbook_limb_mults"] if dom == "mul_valu" else info["anchor_limb_mults"]
+        achieved = ops / sec / 1e12
+        return {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                "op": "32x32->64-bit limb multiply-accumulate", "ops_per_launch": ops}
+    nbytes = {"pack": info["pack_bytes"], "normalize": info["normalize_bytes"]}.get(dom, info["finish_bytes"])
+    achieved = nbytes / sec / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": nbytes}
+
+
+def batch_line(ks, torch, B, count, variant, reps, traffic=None):
+    """One batched workload through ks_batch_run: products/s, limb-mults/s, stage times and the
+    dominant stage's roofline."""
+    plan = ks.BatchPlan(B.desc_array(), variant)
+    ain = ks.to_device(B.arena_in())
+    aout = torch.zeros(B.out_words(), dtype=torch.int32, device="cuda")
+    ws = ks.alloc_workspace(plan.workspace_bytes)
+    plan.run(ain, aout, ws)
+    torch.cuda.synchronize()
+    rc = plan.status(ws)
+    if rc != ks.KS_OK:
+        raise SystemExit(f"batch status: {ks.strerror(rc)}")
+    info = plan.info()
+    kern = kernel_times(ks, lambda: plan.run(ain, aout, ws), 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run(ain, aout, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    plan.close()
+    eng = {ks.KS_ENGINE_VALU: "valu", ks.KS_ENGINE_MFMA: "mfma"}.get(info["engine"], "valu+mfma")
+    return {"variant": variant, "engine": eng, "ms_per_batch": dt * 1e3, "products_per_s": count / dt,
+            "limb_mults_per_s": info["limb_mults"] / dt, "mfma_ops_per_s": info["mfma_ops"] / dt,
+            "kernels_us": {k: v["avg_us"] for k, v in kern.items()}, "roofline": roofline(kern, info, traffic)}
 
 
 def main():
@@ -77,44 +151,21 @@ def main():
     L, bits, signed = P.f.shape[0], P.bits, P.signed
     tf, tg = ks.to_device(P.f), ks.to_device(P.g)
     wo = ks.out_limbs(L, L, bits)
-    outs = {v: torch.empty((2 * L - 1, wo), dtype=torch.int32, device="cuda") for v in ("ks4", "ks1", "neg2")}
+    variants = ("ks4", "ks1", "neg2")
+    outs = {v: torch.empty((2 * L - 1, wo), dtype=torch.int32, device="cuda") for v in variants}
 
     t = {}
-    for v in ("ks4", "ks1", "neg2"):
+    for v in variants:
         t[v] = time_variant(ks, torch, tf, tg, bits, v, signed, args.steps, args.warmup, outs[v])
     rc = ks.status()
     if rc != ks.KS_OK:
         raise SystemExit(f"device status after timing: {ks.strerror(rc)}")
+    plans = {v: ks.plan(L, L, bits, v, signed) for v in variants}
+    engine_name = {ks.KS_ENGINE_VALU: "valu", ks.KS_ENGINE_MFMA: "mfma"}
 
-    plans = {v: ks.plan(L, L, bits, v, signed) for v in ("ks4", "ks1", "neg2")}
-
-    # per-kernel durations on the library's own stream, HIP events around every launch
-    ks.profile_reset()
-    ks.profile_enable(True)
-    for _ in range(args.steps):
-        ks.mul(tf, tg, bits, "ks4", signed, out=outs["ks4"])
-    torch.cuda.synchronize()
-    ks.profile_enable(False)
-    kern = {}
-    for name in ("pack", "mul_valu", "mul_mfma", "normalize", "anchor", "recon", "extract"):
-        n, ms = ks.profile_read(name)
-        if n:
-            kern[name] = {"launches": n, "avg_us": 1000.0 * ms / n}
-    dom = max(kern, key=lambda k: kern[k]["avg_us"])
-    p4 = plans["ks4"]
-    sec = kern[dom]["avg_us"] * 1e-6
-    traffic = MEASURED_TRAFFIC.get(dom) if args.workload == "config2" else None
-    if dom in ("mul_valu", "anchor"):
-        ops = p4["schoolbook_limb_mults"] if dom == "mul_valu" else p4["anchor_limb_mults"]
-        achieved = ops / sec / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                "op": "32x32->64-bit limb multiply-accumulate", "ops_per_launch": ops}
-    else:
-        nbytes = {"pack": p4["pack_bytes"], "normalize": p4["normalize_bytes"]}.get(dom, p4["finish_bytes"])
-        achieved = nbytes / sec / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": nbytes}
+    # per-kernel durations of the four-point product on the library's own stream
+    kern = kernel_times(ks, lambda: ks.mul(tf, tg, bits, "ks4", signed, out=outs["ks4"]), args.steps)
+    roof = roofline(kern, plans["ks4"], MEASURED_TRAFFIC if args.workload == "config2" else None)
 
     # bit-exact check of every variant against the oracle (also the CPU baseline sample)
     cpu = None
@@ -136,6 +187,32 @@ def main():
         if not exact:
             raise SystemExit("GPU result differs from the oracle")
 
+    # the batched workloads (throughput; their results are checked by the GPU tests)
+    batch = None
+    if not args.no_batch:
+        batch = {}
+        prods = wl.config3()
+        B = ks.Batch()
+        for Q in prods:
+            B.add(Q.f, Q.g, Q.bits, Q.signed)
+        for v in ("ks4", "ks1"):
+            batch[f"config3_{v}"] = batch_line(ks, torch, B, len(prods), v, 10)
+        del B
+        p, pairs = wl.config4()
+        B = ks.Batch()
+        for f, g in pairs:
+            B.add_mod(f, g, p)
+        for v in ("ks4", "ks1"):
+            batch[f"config4_{v}"] = batch_line(ks, torch, B, len(pairs), v, 3,
+                                               MEASURED_TRAFFIC_CONFIG4 if v == "ks4" else None)
+        del B
+        batch["speedup_ks4_vs_ks1"] = {
+            c: batch[f"{c}_ks1"]["ms_per_batch"] / batch[f"{c}_ks4"]["ms_per_batch"] for c in ("config3", "config4")}
+        batch["workloads"] = {
+            "config3": "10,000 signed products, L log-uniform in [16, 1024], b in {16, 32, 64, 128}, seed 3",
+            "config4": "64 products mod a 60-bit odd p, L = 65536, residues uniform in [0, p), seed 4"}
+
+    p4 = plans["ks4"]
     ms = t["ks4"] * 1000.0
     rec = {
         "metric": "polynomial products/s + limb-mults/s at 1 GPU; KS4 vs KS1 speedup, bit-exact",
@@ -157,12 +234,14 @@ def main():
         "schoolbook_limb_mults_per_s": p4["schoolbook_limb_mults"] / t["ks4"],
         "variants_ms": {v: t[v] * 1000.0 for v in t},
         "variants_products_per_s": {v: 1.0 / t[v] for v in t},
+        "variants_engine": {v: engine_name.get(plans[v]["engine"], "?") for v in variants},
         "speedup_ks4_vs_ks1": t["ks1"] / t["ks4"],
         "speedup_neg2_vs_ks1": t["ks1"] / t["neg2"],
         "bit_exact": exact,
         "kernels_us": kern,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batch": batch,
     }
     print(json.dumps(rec))
 

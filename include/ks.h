@@ -152,7 +152,7 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
 int64_t ks_batch_plan_bad_index(void);
 /* Device scratch bytes a run of this plan needs. */
 size_t ks_batch_plan_workspace_bytes(const ks_batch_plan *plan);
-/* Totals over the plan's products (limb products, algorithmic bytes; variant -1 if mixed). */
+/* Totals over the plan's products (limb products, int8 operations, algorithmic bytes). */
 int ks_batch_plan_info(const ks_batch_plan *plan, struct ks_plan_info *out);
 /*
  * Enqueue the whole batch on `stream`.  Allocates nothing and copies nothing from the host,
@@ -178,7 +178,7 @@ int ks_mul_batch(const uint32_t *arena_in, uint32_t *arena_out, const ks_desc *d
 
 typedef struct ks_plan_info {
     int32_t variant;          /* resolved KS_VARIANT_* */
-    int32_t engine;           /* KS_ENGINE_VALU or KS_ENGINE_MFMA */
+    int32_t engine;           /* KS_ENGINE_VALU or KS_ENGINE_MFMA (a batch: the OR of its products') */
     int32_t e;                /* ceil(log2 min(len_f, len_g)) */
     int32_t slot_bits;        /* N of the resolved variant */
     int32_t n_products;       /* 1, 2 or 4 integer products */
@@ -192,6 +192,8 @@ typedef struct ks_plan_info {
     double normalize_bytes;   /*   product column sums read once + recombined values written       */
     double finish_bytes;      /*   recombined values read + h written (extract or reconstruction)  */
     double anchor_limb_mults; /*   limb products of the reconstruction anchors (KS4)              */
+    double mfma_ops;          /* int8 operations (2 per multiply-add) of the 7-bit digit products
+                                 run on the matrix cores: 2 * sum of (digits of a) * (digits of b) */
 } ks_plan_info;
 
 int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, ks_plan_info *out);

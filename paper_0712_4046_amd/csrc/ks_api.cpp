@@ -156,6 +156,7 @@ int plan_product(const Spec &sp, Geom &G) {
         G.muls.push_back(m);
         G.mul_blocks += m.blocks;
         G.school_mults += (double)nf * (double)ng;
+        if (eng == KS_ENGINE_MFMA) G.mfma_ops += 2.0 * (double)m.nad * (double)m.nbd;
     }
     G.col_words = coff;
     G.digit_bytes = doff;
@@ -660,7 +661,7 @@ using namespace ks;
 
 extern "C" {
 
-int32_t ks_version(void) { return 101; }
+int32_t ks_version(void) { return 102; }
 
 const char *ks_strerror(int code) {
     switch (code) {
@@ -705,6 +706,7 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
     out->normalize_bytes = G.normalize_bytes;
     out->finish_bytes = G.finish_bytes;
     out->anchor_limb_mults = G.anchor_mults;
+    out->mfma_ops = G.mfma_ops;
     return KS_OK;
 }
 

@@ -70,6 +70,8 @@ struct ks_batch_plan {
     int64_t ctr_pack = 0, ctr_norm = 0;  // word offsets of the counters
     int64_t ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
+    double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0;
+    int32_t engines = 0;  // OR of the engines the products use
     int variant = -1;
 };
 
@@ -131,6 +133,12 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
         P->limb_mults += geoms[(size_t)i].limb_mults;
         P->school_mults += geoms[(size_t)i].school_mults;
         P->hbm_bytes += geoms[(size_t)i].hbm_bytes;
+        P->pack_bytes += geoms[(size_t)i].pack_bytes;
+        P->normalize_bytes += geoms[(size_t)i].normalize_bytes;
+        P->finish_bytes += geoms[(size_t)i].finish_bytes;
+        P->anchor_mults += geoms[(size_t)i].anchor_mults;
+        P->mfma_ops += geoms[(size_t)i].mfma_ops;
+        for (const auto &m : geoms[(size_t)i].muls) P->engines |= m.engine;
         int rv = geoms[(size_t)i].variant;
         P->variant = i == 0 ? rv : (P->variant == rv ? rv : -1);
     }
@@ -183,11 +191,16 @@ int ks_batch_plan_info(const ks_batch_plan *plan, ks_plan_info *out) {
     if (!plan || !out) return KS_EINVAL;
     memset(out, 0, sizeof(*out));
     out->variant = plan->variant;
-    out->engine = KS_ENGINE_VALU;
+    out->engine = plan->engines ? plan->engines : KS_ENGINE_VALU;
     out->n_products = (int32_t)std::min<int64_t>(plan->count, 0x7fffffff);
     out->limb_mults = plan->limb_mults;
     out->schoolbook_limb_mults = plan->school_mults;
     out->hbm_bytes = plan->hbm_bytes;
+    out->pack_bytes = plan->pack_bytes;
+    out->normalize_bytes = plan->normalize_bytes;
+    out->finish_bytes = plan->finish_bytes;
+    out->anchor_limb_mults = plan->anchor_mults;
+    out->mfma_ops = plan->mfma_ops;
     return KS_OK;
 }
 

@@ -77,7 +77,7 @@ struct Geom {
             chain_blocks = 0;
     int64_t ws_ops = 0, ws_cols = 0, ws_digits = 0, ws_norms = 0, ws_anchors = 0, ws_status = 0, ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
-    double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0;
+    double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0;
 };
 
 // device words that outlive one call: block-ticket counters (pack jobs, then normalize jobs),

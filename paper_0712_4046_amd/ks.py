@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libksmul.so")
 
 KS_VARIANT = {"auto": 0, "ks1": 1, "neg2": 2, "ks4": 4}
 KS_SIGNED = 0x100
-KS_ENGINE = {None: 0, "valu": 0x1000, "mfma": 0x2000}
+KS_ENGINE_VALU, KS_ENGINE_MFMA = 0x1000, 0x2000
+KS_ENGINE = {None: 0, "valu": KS_ENGINE_VALU, "mfma": KS_ENGINE_MFMA}
 KS_MOD = 0x10000
 KS_OK, KS_EINVAL, KS_ENOMEM, KS_EHIP, KS_ERANGE, KS_EUNSUPPORTED, KS_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 KS_MAX_BITS = 256
@@ -37,7 +38,7 @@ class PlanInfo(ctypes.Structure):
                 ("limb_mults", ctypes.c_double), ("schoolbook_limb_mults", ctypes.c_double),
                 ("hbm_bytes", ctypes.c_double), ("pack_bytes", ctypes.c_double),
                 ("normalize_bytes", ctypes.c_double), ("finish_bytes", ctypes.c_double),
-                ("anchor_limb_mults", ctypes.c_double)]
+                ("anchor_limb_mults", ctypes.c_double), ("mfma_ops", ctypes.c_double)]
 
 
 class Desc(ctypes.Structure):

@@ -1,13 +1,13 @@
 #!/usr/bin/env python3
 """Helpers for rocprofv3 measurements of the library (used to make the files in profiles/).
 
-    python -m paper_0712_4046_amd.prof_tools workload            # counter-run workload
+    python -m paper_0712_4046_amd.prof_tools workload [config2|config3|config4]  # counter runs
     python -m paper_0712_4046_amd.prof_tools summarize DB "cmd"  # kernel-trace summary table
     python -m paper_0712_4046_amd.prof_tools counters FETCH_DB WRITE_DB   # HBM bytes per kernel
 
 The workload is a plain device copy of known size (to calibrate FETCH_SIZE / WRITE_SIZE) and
 then the benchmark product (one Z[x] product, L = 4096, signed 64-bit coefficients, seed 2)
-through the four-point variant.
+through the four-point variant, or one four-point run of a batched workload.
 """
 import os
 import sqlite3
@@ -17,7 +17,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_MIB = 256
 
 
-def workload(reps: int = 5):
+def workload(name: str = "config2", reps: int = 5):
+    """A plain device copy of COPY_MIB MiB (the FETCH_SIZE / WRITE_SIZE calibration), then
+    config2: `reps` four-point products of the L = 4096 signed 64-bit workload (seed 2);
+    config3: one four-point run of the 10,000-product batch (seed 3);
+    config4: one four-point run of the 64-product modular batch (seed 4)."""
     sys.path.insert(0, ROOT)
     import torch
     from paper_0712_4046_amd import ks
@@ -26,11 +30,29 @@ def workload(reps: int = 5):
     dst = torch.empty_like(src)
     dst.copy_(src)  # known traffic: COPY_MIB MiB read and COPY_MIB MiB written
     torch.cuda.synchronize()
-    P = wl.config2()
-    tf, tg = ks.to_device(P.f), ks.to_device(P.g)
-    for _ in range(reps):
-        ks.mul(tf, tg, P.bits, "ks4", P.signed)
-    ks.check()
+    if name == "config2":
+        P = wl.config2()
+        tf, tg = ks.to_device(P.f), ks.to_device(P.g)
+        for _ in range(reps):
+            ks.mul(tf, tg, P.bits, "ks4", P.signed)
+        ks.check()
+    else:
+        B = ks.Batch()
+        if name == "config3":
+            for P in wl.config3():
+                B.add(P.f, P.g, P.bits, P.signed)
+        else:
+            p, pairs = wl.config4()
+            for f, g in pairs:
+                B.add_mod(f, g, p)
+        plan = ks.BatchPlan(B.desc_array(), "ks4")
+        ain = ks.to_device(B.arena_in())
+        aout = torch.zeros(B.out_words(), dtype=torch.int32, device="cuda")
+        ws = ks.alloc_workspace(plan.workspace_bytes)
+        plan.run(ain, aout, ws)
+        if plan.status(ws) != ks.KS_OK:
+            raise SystemExit("batch status not OK")
+        plan.close()
     print("workload done", flush=True)
 
 
@@ -83,7 +105,7 @@ def counters(fetch_db: str, write_db: str):
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else "workload"
     if cmd == "workload":
-        workload()
+        workload(sys.argv[2] if len(sys.argv) > 2 else "config2")
     elif cmd == "summarize":
         summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
     elif cmd == "counters":
