@@ -8,8 +8,8 @@ carry resolution and halving -> reconstruction / read-off), with the inputs alre
 Workload (default): one product of two length-4096 polynomials with signed 64-bit
 coefficients drawn from seed 2 (the single-product configuration the paper's comparison is
 quoted on, at a size that fits one GPU).  The four-point variant (paper Section 3.4) is the
-reported value; the standard substitution (3.1) and the negated variant (3.3) are timed the
-same way for the speedup; each product runs on the engine the planner picks (vector ALU or
+reported value; the standard substitution (3.1), the negated variant (3.3) and the two-point
+reciprocal variant (3.2) are timed the same way for the speedups; each product runs on the engine the planner picks (vector ALU or
 int8 matrix cores).  Extra fields: per-kernel durations and the dominant kernel's roofline,
 the CPU oracle's rate on the host cores, and the two batched workloads (10,000 mixed products;
 64 products mod a 60-bit prime of length 65536) with their own rooflines.  Prints ONE JSON line.
@@ -151,7 +151,7 @@ def main():
     L, bits, signed = P.f.shape[0], P.bits, P.signed
     tf, tg = ks.to_device(P.f), ks.to_device(P.g)
     wo = ks.out_limbs(L, L, bits)
-    variants = ("ks4", "ks1", "neg2")
+    variants = ("ks4", "ks1", "neg2", "recip2")
     outs = {v: torch.empty((2 * L - 1, wo), dtype=torch.int32, device="cuda") for v in variants}
 
     t = {}
@@ -237,6 +237,7 @@ def main():
         "variants_engine": {v: engine_name.get(plans[v]["engine"], "?") for v in variants},
         "speedup_ks4_vs_ks1": t["ks1"] / t["ks4"],
         "speedup_neg2_vs_ks1": t["ks1"] / t["neg2"],
+        "speedup_recip2_vs_ks1": t["ks1"] / t["recip2"],
         "bit_exact": exact,
         "kernels_us": kern,
         "roofline": roof,

@@ -50,6 +50,10 @@ extern "C" {
 #define KS_VARIANT_AUTO 0      /* library picks KS1 / NEG2 / KS4 from its size model         */
 #define KS_VARIANT_KS1 1       /* Section 3.1: one point 2^N                                 */
 #define KS_VARIANT_NEG2 2      /* Section 3.3: points +-2^N                                  */
+#define KS_VARIANT_RECIP2 3    /* Section 3.2: points 2^N and 2^-N (reversed polynomials),
+                                  N = b + ceil(e/2), the carry-aware reconstruction at base 2^N;
+                                  never chosen by KS_VARIANT_AUTO (same products as NEG2 plus the
+                                  reconstruction, which the paper also finds slower)            */
 #define KS_VARIANT_KS4 4       /* Section 3.4: points +-2^N, +-2^-N                          */
 #define KS_VARIANT_MASK 0xff
 #define KS_SIGNED 0x100        /* coefficients are signed two's complement                   */

@@ -33,7 +33,7 @@ __device__ __forceinline__ void anchor_block(const Launch<AnchorJob> &L, int64_t
     int64_t local;
     const AnchorJob J = get_job(L, blk, local);
     const int64_t s = local + 1;
-    const int64_t k = 2 * (s * J.K - 1) + J.par;
+    const int64_t k = J.kstep * (s * J.K - 1) + J.par;
     int64_t lo = k - (J.lg - 1);
     if (lo < 0) lo = 0;
     int64_t hi = k < J.lf - 1 ? k : J.lf - 1;

@@ -47,6 +47,7 @@ static int64_t slot_bits(int variant, int b, int e) {
     switch (variant) {
         case KS_VARIANT_KS1: return 2 * (int64_t)b + e;                 // Section 3.1
         case KS_VARIANT_NEG2: return (int64_t)b + (e + 1) / 2;          // Section 3.3
+        case KS_VARIANT_RECIP2: return (int64_t)b + (e + 1) / 2;        // Section 3.2
         case KS_VARIANT_KS4: return (2 * (int64_t)b + e + 3) / 4;       // Section 3.4
     }
     return 0;
@@ -79,7 +80,8 @@ int plan_product(const Spec &sp, Geom &G) {
     G.off = sp.sgn ? 2 * b - 2 + G.e : -1;
     int v = sp.variant;
     if (v == KS_VARIANT_AUTO) v = auto_variant(lf, lg, b, G.e);
-    if (v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_KS4) return KS_EINVAL;
+    if (v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_RECIP2 && v != KS_VARIANT_KS4)
+        return KS_EINVAL;
     G.variant = v;
     const int64_t N = slot_bits(v, b, G.e);
     G.N = N;
@@ -91,6 +93,7 @@ int plan_product(const Spec &sp, Geom &G) {
     std::vector<int> pf;
     if (v == KS_VARIANT_KS1) pf = {0};
     else if (v == KS_VARIANT_NEG2) pf = {0, PK_ALTERNATE};
+    else if (v == KS_VARIANT_RECIP2) pf = {0, PK_REVERSE};
     else pf = {0, PK_ALTERNATE, PK_REVERSE, PK_REVERSE | PK_ALTERNATE};
     const int npts = (int)pf.size();
     int64_t off = 0;
@@ -183,10 +186,52 @@ int plan_product(const Spec &sp, Geom &G) {
         G.norm_blocks += r.blocks;
         return (int)G.norms.size() - 1;
     };
+    // Section 3.2's reconstruction of m coefficients from A = norm a (digits u, base 2^Nd) and
+    // B = norm bb (digits w from the top); output coefficients first, first + step, ...
+    // segment length K: every segment but the first costs one anchor (a dot product of
+    // min(lf, lg) coefficient products, spread over the GPU), and a segment's lane runs K
+    // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement).  In a
+    // batch of n products the anchors of all products share the GPU while their chains run
+    // side by side, which favours longer segments: the factor sqrt(n) and the floor of 32
+    // match the measured optima of the 10,000-product and 64-product workloads.
+    auto add_chain = [&](int a, int bb, int64_t m, int first, int64_t Nd, int step) {
+        const double Lm = (double)std::min(lf, lg);
+        const double nbat = std::sqrt((double)sp.batch_count);
+        int64_t K = (int64_t)(std::sqrt(nbat * G.D * Lm * sp.w_in * sp.w_in / 2.0e6) + 0.5);
+        K = std::max<int64_t>(sp.batch ? 32 : 4, std::min<int64_t>(K, 4096));
+        K = env_int("KS_CHAIN_K", (int)K);
+        if (K < 1) K = 1;
+        G.nw = (int)cdiv(Nd, 32);
+        G.chain_nd = Nd;
+        G.aw = 2 * sp.w_in + 2;
+        ChainGeom c;
+        c.A = a;
+        c.B = bb;
+        c.m = m;
+        c.K = K;
+        c.nseg = cdiv(m, K);
+        c.par = first;
+        c.step = step;
+        c.anchor_off = G.anchor_limbs;
+        c.anchor_blocks = c.nseg - 1;
+        c.chain_blocks = cdiv(c.nseg, CHAIN_TPB);
+        G.anchor_limbs += align_up(c.nseg * G.aw, 64);
+        G.chains.push_back(c);
+        G.anchor_blocks += c.anchor_blocks;
+        G.chain_blocks += c.chain_blocks;
+        G.anchor_mults += (double)(c.nseg - 1) * std::min(lf, lg) * sp.w_in * sp.w_in;
+    };
     if (v == KS_VARIANT_KS1) {
         add_norm({0}, {1}, 0, G.off, N, G.D, cdiv(G.D * N, 32) + 1);
         ExtractGeom x{0, G.D, N, 0, 1, cdiv(G.D, EXTRACT_TPB)};
         G.extracts.push_back(x);
+    } else if (v == KS_VARIANT_RECIP2) {
+        // A = h(2^N) and B = h^rev(2^N) (Section 3.2), each with the slot constant, then the
+        // reconstruction at base 2^N over all D coefficients
+        const int64_t n_out = cdiv((G.D + 1) * N, 32) + 1;
+        const int a = add_norm({0}, {1}, 0, G.off, N, G.D, n_out);
+        const int bb = add_norm({1}, {1}, 0, G.off, N, G.D, n_out);
+        add_chain(a, bb, G.D, 0, N, 1);
     } else {
         const int64_t Y = 2 * N;  // bits of the even/odd base 2^(2N)
         // P0 = (H1 + H2 + 2 C 1(Y)) / 2,  P1 = (H1 - H2 + 2^(N+1) C 1(Y)) / 2^(N+1)
@@ -202,41 +247,8 @@ int plan_product(const Spec &sp, Geom &G) {
             int q1 = -1;
             if (G.m1 > 0) q1 = add_norm({2, 3}, {1, -1}, N + 1, G.off + N + 1, Y, G.m1, cdiv((G.m1 + 1) * Y, 32) + 1);
             const bool dodd = (G.D & 1) != 0;  // reversal swaps parities when D is even
-            // segment length K: every segment but the first costs one anchor (a dot product of
-            // min(lf, lg) coefficient products, spread over the GPU), and a segment's lane runs K
-            // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement).  In
-            // a batch of n products the anchors of all products share the GPU while their chains
-            // run side by side, which favours longer segments: the factor sqrt(n) and the floor
-            // of 32 match the measured optima of the 10,000-product and 64-product workloads.
-            const double Lm = (double)std::min(lf, lg);
-            const double nb = std::sqrt((double)sp.batch_count);
-            int64_t K = (int64_t)(std::sqrt(nb * G.D * Lm * sp.w_in * sp.w_in / 2.0e6) + 0.5);
-            K = std::max<int64_t>(sp.batch ? 32 : 4, std::min<int64_t>(K, 4096));
-            K = env_int("KS_CHAIN_K", (int)K);
-            if (K < 1) K = 1;
-            G.nw = (int)cdiv(Y, 32);
-            G.aw = 2 * sp.w_in + 2;
-            int64_t aoff = 0;
-            for (int par = 0; par < 2; ++par) {
-                int64_t m = par ? G.m1 : G.m0;
-                if (m == 0) continue;
-                ChainGeom c;
-                c.A = par ? p1 : p0;
-                c.B = par ? (dodd ? q1 : q0) : (dodd ? q0 : q1);
-                c.m = m;
-                c.K = K;
-                c.nseg = cdiv(m, K);
-                c.par = par;
-                c.anchor_off = aoff;
-                c.anchor_blocks = c.nseg - 1;
-                c.chain_blocks = cdiv(c.nseg, CHAIN_TPB);
-                aoff += align_up(c.nseg * G.aw, 64);
-                G.chains.push_back(c);
-                G.anchor_blocks += c.anchor_blocks;
-                G.chain_blocks += c.chain_blocks;
-                G.anchor_mults += (double)(c.nseg - 1) * std::min(lf, lg) * sp.w_in * sp.w_in;
-            }
-            G.anchor_limbs = aoff;
+            add_chain(p0, dodd ? q0 : q1, G.m0, 0, 2 * N, 2);
+            if (G.m1 > 0) add_chain(p1, dodd ? q1 : q0, G.m1, 1, 2 * N, 2);
         }
     }
     G.norm_limbs = noff;
@@ -387,6 +399,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.nseg = c.nseg;
         j.anchors = anchors(c.anchor_off);
         j.off_bit = G.off;
+        j.kstep = c.step;
         j.block0 = next_block(list);
         j.nblocks = c.anchor_blocks;
         list.push_back(j);
@@ -450,10 +463,10 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.nseg = c.nseg;
         j.anchors = anchors(c.anchor_off);
         j.aw = G.aw;
-        j.Nd = (int)(2 * G.N);
+        j.Nd = (int)G.chain_nd;
         j.out = reinterpret_cast<uint32_t *>(h);
         j.out_first = c.par;
-        j.out_step = 2;
+        j.out_step = c.step;
         j.w_out = G.w_out;
         j.off_bit = G.off;
         j.mod_p = sp.mod_p;
@@ -639,7 +652,9 @@ int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_
     if (lf < 1 || lg < 1 || lf > KS_MAX_LEN || lg > KS_MAX_LEN) return KS_EINVAL;
     if (bits < 1 || bits > KS_MAX_BITS) return KS_EINVAL;
     int v = variant & KS_VARIANT_MASK;
-    if (v != KS_VARIANT_AUTO && v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_KS4) return KS_EINVAL;
+    if (v != KS_VARIANT_AUTO && v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_RECIP2 &&
+        v != KS_VARIANT_KS4)
+        return KS_EINVAL;
     if ((variant & KS_SIGNED) && !allow_signed) return KS_EINVAL;
     int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_VALU | KS_ENGINE_MFMA;
     if (variant & ~known) return KS_EINVAL;

@@ -97,7 +97,9 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     if (variant & ~known) return KS_EINVAL;
     const int v = variant & KS_VARIANT_MASK;
     const int eng = variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA);
-    if (v != KS_VARIANT_AUTO && v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_KS4) return KS_EINVAL;
+    if (v != KS_VARIANT_AUTO && v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_RECIP2 &&
+        v != KS_VARIANT_KS4)
+        return KS_EINVAL;
     ks_batch_plan *P = new ks_batch_plan();
     P->count = count;
     int64_t off = align256(WS_STATUS);  // product scratch starts after the status words (fixed below)

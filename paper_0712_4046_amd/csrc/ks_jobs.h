@@ -181,13 +181,14 @@ struct AnchorJob {
     int64_t nseg;
     uint32_t *anchors;  // nseg * aw limbs; entry 0 unused
     int32_t off_bit;    // -1: nothing added
-    int32_t pad;
+    int32_t kstep;      // anchor s is coefficient kstep (s K - 1) + par
     int64_t block0;
     int64_t nblocks;
 };
 
-// one parity of a four-point product: Section 3.2's reconstruction on A (digits u) and
-// B (digits w, read from the top), base Y = 2^Nd, m coefficients, in segments of K
+// Section 3.2's reconstruction on A (digits u) and B (digits w, read from the top), base
+// Y = 2^Nd, m coefficients, in segments of K: one parity of a four-point product (Nd = 2N,
+// output coefficients par, par + 2, ...) or the whole two-point reciprocal product (Nd = N)
 struct ChainJob {
     const uint32_t *A;
     const uint32_t *B;

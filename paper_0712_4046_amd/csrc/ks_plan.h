@@ -59,13 +59,15 @@ struct ExtractGeom {
 struct ChainGeom {
     int A, B;  // norm indices
     int64_t m, K, nseg;
-    int par;
+    int par;   // first output coefficient (and anchor parity)
+    int step;  // output stride: 2 (a parity of the four-point product) or 1 (two-point reciprocal)
     int64_t anchor_off, anchor_blocks, chain_blocks;
 };
 
 struct Geom {
     Spec sp;
     int variant = 0, e = 0, w_out = 0, off = -1, nw = 0, aw = 0, chain_lds = 0;
+    int64_t chain_nd = 0;  // bits of a reconstruction digit (2N four-point, N reciprocal)
     int64_t N = 0, D = 0, m0 = 0, m1 = 0, nf = 0, ng = 0;
     std::vector<PackGeom> packs;
     std::vector<MulGeom> muls;

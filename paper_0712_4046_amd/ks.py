@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libksmul.so")
 
-KS_VARIANT = {"auto": 0, "ks1": 1, "neg2": 2, "ks4": 4}
+KS_VARIANT = {"auto": 0, "ks1": 1, "neg2": 2, "recip2": 3, "ks4": 4}
 KS_SIGNED = 0x100
 KS_ENGINE_VALU, KS_ENGINE_MFMA = 0x1000, 0x2000
 KS_ENGINE = {None: 0, "valu": KS_ENGINE_VALU, "mfma": KS_ENGINE_MFMA}

@@ -50,7 +50,7 @@ def test_invalid_sizes_rejected():
             ks.plan(bad[0], bad[1], bad[2], bad[3])
         assert ei.value.code == ks.KS_EINVAL
     info = ks.PlanInfo()
-    assert L.ks_plan(4, 4, 8, 3, info) == ks.KS_EINVAL       # not a variant
+    assert L.ks_plan(4, 4, 8, 5, info) == ks.KS_EINVAL       # not a variant
     assert L.ks_plan(4, 4, 8, 0x3000 | 1, info) == ks.KS_EINVAL  # both engines
 
 
@@ -58,7 +58,8 @@ def test_invalid_sizes_rejected():
                                             (100, 3, 128, True), (65536, 65536, 60, False), (1000, 999, 16, True)])
 def test_planner_slot_widths_and_operand_lengths(lf, lg, b, signed):
     e = (min(lf, lg) - 1).bit_length()
-    for variant, N, k in (("ks1", 2 * b + e, 1), ("neg2", b + (e + 1) // 2, 2), ("ks4", (2 * b + e + 3) // 4, 4)):
+    for variant, N, k in (("ks1", 2 * b + e, 1), ("neg2", b + (e + 1) // 2, 2), ("recip2", b + (e + 1) // 2, 2),
+                          ("ks4", (2 * b + e + 3) // 4, 4)):
         p = ks.plan(lf, lg, b, variant, signed)
         assert p["slot_bits"] == N and p["n_products"] == k and p["e"] == e
         # operand length N (L-1) + b of the propositions, plus one carry bit and one sign bit

@@ -39,7 +39,7 @@ def run_batch(torch, B, variant="auto", engine=None):
 
 
 @pytest.mark.parametrize("engine", [None, "valu", "mfma"])
-@pytest.mark.parametrize("variant", ["ks1", "neg2", "ks4", "auto"])
+@pytest.mark.parametrize("variant", ["ks1", "neg2", "recip2", "ks4", "auto"])
 def test_mixed_batch(torch_dev, oracle, variant, engine):
     gen = wl.rng(31)
     B = ks.Batch()

@@ -13,7 +13,7 @@ from paper_0712_4046_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["ks1", "neg2", "ks4"]
+VARIANTS = ["ks1", "neg2", "recip2", "ks4"]
 
 
 @pytest.fixture(scope="module")
@@ -171,7 +171,7 @@ def test_invalid_arguments(torch_dev):
     assert ks.mul_raw(t.data_ptr(), t.data_ptr(), 0, 4, 8, 1, s, h.data_ptr()) == ks.KS_EINVAL
     assert ks.mul_raw(t.data_ptr(), t.data_ptr(), 4, 4, 0, 1, s, h.data_ptr()) == ks.KS_EINVAL
     assert ks.mul_raw(t.data_ptr(), t.data_ptr(), 4, 4, 300, 1, s, h.data_ptr()) == ks.KS_EINVAL
-    assert ks.mul_raw(t.data_ptr(), t.data_ptr(), 4, 4, 8, 3, s, h.data_ptr()) == ks.KS_EINVAL
+    assert ks.mul_raw(t.data_ptr(), t.data_ptr(), 4, 4, 8, 5, s, h.data_ptr()) == ks.KS_EINVAL
     assert ks.mul_raw(0, t.data_ptr(), 4, 4, 8, 1, s, h.data_ptr()) == ks.KS_EINVAL
     assert ks.status() == ks.KS_OK
 
