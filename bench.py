@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {"pack": 1009704, "mul_valu": 1641732, "normalize": 1255011, "recon": 658550}
 MEASURED_TRAFFIC_CONFIG4 = {"pack": 1020121474, "digitize": 950000387, "mul_mfma": 2530584193,
                             "normalize": 1217221764, "recon": 288719068}
-KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "extract")
+KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract")
 
 
 def parse():

@@ -190,15 +190,17 @@ int plan_product(const Spec &sp, Geom &G) {
     // B = norm bb (digits w from the top); output coefficients first, first + step, ...
     // segment length K: every segment but the first costs one anchor (a dot product of
     // min(lf, lg) coefficient products, spread over the GPU), and a segment's lane runs K
-    // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement).  In a
-    // batch of n products the anchors of all products share the GPU while their chains run
-    // side by side, which favours longer segments: the factor sqrt(n) and the floor of 32
-    // match the measured optima of the 10,000-product and 64-product workloads.
+    // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement: K = 8 is
+    // the optimum of the L = 4096 product).  In a batch of n products the anchors of all
+    // products share the GPU while their chains run side by side, which favours longer
+    // segments: the factor sqrt(n), c = 5e5 and the floor of 64 match the measured optima of
+    // the 10,000-product (K = 64) and 64-product modular (K = 512-1024) workloads.
     auto add_chain = [&](int a, int bb, int64_t m, int first, int64_t Nd, int step) {
         const double Lm = (double)std::min(lf, lg);
         const double nbat = std::sqrt((double)sp.batch_count);
-        int64_t K = (int64_t)(std::sqrt(nbat * G.D * Lm * sp.w_in * sp.w_in / 2.0e6) + 0.5);
-        K = std::max<int64_t>(sp.batch ? 32 : 4, std::min<int64_t>(K, 4096));
+        const double cK = sp.batch ? 5.0e5 : 2.0e6;
+        int64_t K = (int64_t)(std::sqrt(nbat * G.D * Lm * sp.w_in * sp.w_in / cK) + 0.5);
+        K = std::max<int64_t>(sp.batch ? 64 : 4, std::min<int64_t>(K, 4096));
         K = env_int("KS_CHAIN_K", (int)K);
         if (K < 1) K = 1;
         G.nw = (int)cdiv(Nd, 32);
@@ -215,6 +217,10 @@ int plan_product(const Spec &sp, Geom &G) {
         c.anchor_off = G.anchor_limbs;
         c.anchor_blocks = c.nseg - 1;
         c.chain_blocks = cdiv(c.nseg, CHAIN_TPB);
+        c.hbuf_off = G.hbuf_words;
+        c.finish_blocks = cdiv(m, FINISH_TPB);
+        G.hbuf_words += align_up(m * 2 * cdiv(Nd, 32), 64);
+        G.finish_blocks += c.finish_blocks;
         G.anchor_limbs += align_up(c.nseg * G.aw, 64);
         G.chains.push_back(c);
         G.anchor_blocks += c.anchor_blocks;
@@ -261,6 +267,7 @@ int plan_product(const Spec &sp, Geom &G) {
     G.ws_digits = o;  o += align_up(G.digit_bytes, 256);
     G.ws_norms = o;   o += align_up(G.norm_limbs * 4, 256);
     G.ws_anchors = o; o += align_up(std::max<int64_t>(G.anchor_limbs, 1) * 4, 256);
+    G.ws_hbuf = o;    o += align_up(G.hbuf_words * 4, 256);
     G.ws_status = o;  o += align_up(std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1) * 8, 256);
     G.ws_bytes = o;
 
@@ -464,6 +471,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.anchors = anchors(c.anchor_off);
         j.aw = G.aw;
         j.Nd = (int)G.chain_nd;
+        j.hbuf = reinterpret_cast<uint32_t *>(ws + G.ws_hbuf + 4 * c.hbuf_off);
         j.out = reinterpret_cast<uint32_t *>(h);
         j.out_first = c.par;
         j.out_step = c.step;
@@ -473,6 +481,11 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.block0 = next_block(list);
         j.nblocks = c.chain_blocks;
         list.push_back(j);
+        // the finishing pass over the same chain: one thread per coefficient
+        auto &fl = JL.finish[G.nw];
+        j.block0 = next_block(fl);
+        j.nblocks = c.finish_blocks;
+        fl.push_back(j);
     }
 }
 
@@ -554,6 +567,11 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
     for (auto &kv : JL.chain) {
         auto L = make_launch(kv.second, T ? &T->chain.at(kv.first) : nullptr, env, 0);
         err = timed("recon", s, [&] { return launch_chain(L, kv.first, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    for (auto &kv : JL.finish) {
+        auto L = make_launch(kv.second, T ? &T->finish.at(kv.first) : nullptr, env, 0);
+        err = timed("finish", s, [&] { return launch_finish(L, kv.first, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     return KS_OK;
@@ -789,7 +807,8 @@ int ks_profile_reset(void) {
 
 int ks_profile_read(const char *name, int64_t *launches, double *total_ms) {
     if (!name || !launches || !total_ms) return KS_EINVAL;
-    static const char *known[] = {"pack", "mul_valu", "mul_mfma", "normalize", "anchor", "recon", "extract", "digitize"};
+    static const char *known[] = {"pack",  "mul_valu", "mul_mfma", "normalize", "anchor",
+                                  "recon", "extract",  "digitize", "finish"};
     bool ok = false;
     for (const char *k : known) ok = ok || strcmp(k, name) == 0;
     if (!ok) return KS_EINVAL;

@@ -168,7 +168,8 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
         sh(j.out);
     }
     for (auto &j : JL.extract) sh(j.src);
-    for (auto &kv : JL.chain) for (auto &j : kv.second) { sh(j.A); sh(j.B); sh(j.anchors); }
+    for (auto &kv : JL.chain) for (auto &j : kv.second) { sh(j.A); sh(j.B); sh(j.anchors); sh(j.hbuf); }
+    for (auto &kv : JL.finish) for (auto &j : kv.second) { sh(j.A); sh(j.B); sh(j.anchors); sh(j.hbuf); }
     P->ws_bytes = base + scratch;
     (void)off;
 
@@ -181,6 +182,7 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     if (rc == KS_OK) rc = upload(JL.extract, P->T.extract, P->allocs);
     for (auto &kv : JL.anchor) if (rc == KS_OK) rc = upload(kv.second, P->T.anchor[kv.first], P->allocs);
     for (auto &kv : JL.chain) if (rc == KS_OK) rc = upload(kv.second, P->T.chain[kv.first], P->allocs);
+    for (auto &kv : JL.finish) if (rc == KS_OK) rc = upload(kv.second, P->T.finish[kv.first], P->allocs);
     if (rc != KS_OK) { ks_batch_plan_destroy(P); return rc; }
     P->JL = std::move(JL);
     *out = P;

@@ -271,6 +271,7 @@ template <> __device__ __forceinline__ void rebase(ChainJob &J, const Launch<Cha
     J.A = at(L.base_ws, J.A);
     J.B = at(L.base_ws, J.B);
     J.anchors = at(L.base_ws, J.anchors);
+    J.hbuf = at(L.base_ws, J.hbuf);
     J.out = at(L.base_out, J.out);
 }
 

@@ -5,7 +5,10 @@
 //                 odd parts of the negated variant).  One thread per coefficient.
 // anchor_kernel   Exact h_k at the first coefficient before each chain segment (below).
 // chain_kernel    KS4 (Section 3.4): the carry-aware reconstruction of Section 3.2, run on
-//                 the even part and on the odd part at base Y = 2^(2N).
+//                 the even part and on the odd part at base Y = 2^(2N); RECIP2 (Section
+//                 3.2): the same reconstruction once at base 2^N.  It leaves alpha_k and
+//                 beta_k (h_k + C = alpha_k + Y beta_k) in scratch.
+// finish_kernel   One thread per coefficient: h_k from alpha_k, beta_k, written out.
 //
 // Section 3.2's procedure is one sequential chain over all coefficients.  It carries, from
 // coefficient k-1 to k, only the low half alpha_{k-1} and the carry sigma_{k-1} that the
@@ -25,13 +28,15 @@
 namespace ks {
 
 // ---- (r 2^32 + word) mod p, r < p < 2^62 ------------------------------------------------------
-// Quotient estimated in double precision, then corrected exactly in 64-bit integers (the
-// floating-point reduction technique used by Shoup's NTL): q < 2^32 is off by at most one.
-__device__ __forceinline__ uint64_t mod_step(uint64_t r, uint32_t word, uint64_t p) {
+// Quotient estimated in double precision from a reciprocal pinv = 1/p computed once, then
+// corrected exactly in 64-bit integers (the floating-point reduction technique used by Shoup's
+// NTL): q < 2^32 and the estimate's relative error is a few units in 2^-53, so it is off by
+// at most one.
+__device__ __forceinline__ uint64_t mod_step(uint64_t r, uint32_t word, uint64_t p, double pinv) {
     const uint64_t x = (r << 32) | word;
     if ((p >> 32) == 0) return x % p;  // r < 2^32 here, so x is exact
     const double xd = (double)r * 4294967296.0 + (double)word;
-    const uint64_t q = (uint64_t)(xd / (double)p);
+    const uint64_t q = (uint64_t)(xd * pinv);
     uint64_t d = x - q * p;             // x - q p in [-p, 2p), modulo 2^64
     if ((int64_t)d < 0) d += p;
     while (d >= p) d -= p;
@@ -64,12 +69,13 @@ __global__ __launch_bounds__(EXTRACT_TPB) void extract_kernel(Launch<ExtractJob>
         }
     } else {
         const int nl = (int)((J.slot + 31) >> 5);
+        const double pinv = 1.0 / (double)J.mod_p;
         uint64_t r = 0;
         for (int t = nl - 1; t >= 0; --t) {
             const int64_t bit = 32 * (int64_t)t;
             uint32_t word = bits_word(J.src, J.n_src, s0 + bit);
             if (J.slot - bit < 32) word &= (1u << (J.slot - bit)) - 1u;
-            r = mod_step(r, word, J.mod_p);
+            r = mod_step(r, word, J.mod_p, pinv);
         }
         reinterpret_cast<uint64_t *>(J.out)[idx] = r;
     }
@@ -100,6 +106,30 @@ __device__ __forceinline__ MW<NW> read_digit(const uint32_t *x, int64_t n, int64
     for (int t = 0; t <= NW; ++t) l[t] = (q + t >= 0 && q + t < n) ? x[q + t] : 0u;
 #pragma unroll
     for (int t = 0; t < NW; ++t) d.w[t] = o ? (l[t] >> o) | (l[t + 1] << (32 - o)) : l[t];
+    const int tb = Nd - 32 * (NW - 1);
+    if (tb < 32) d.w[NW - 1] &= (1u << tb) - 1u;
+    return d;
+}
+
+// the NW + 1 words that hold an Nd-bit digit at bit0 (loads only), and the digit from them
+template <int NW>
+struct RawDigit {
+    uint32_t l[NW + 1];
+};
+
+template <int NW>
+__device__ __forceinline__ void load_raw(RawDigit<NW> &r, const uint32_t *x, int64_t n, int64_t bit0) {
+    const int64_t q = bit0 >> 5;
+#pragma unroll
+    for (int t = 0; t <= NW; ++t) r.l[t] = (q + t >= 0 && q + t < n) ? x[q + t] : 0u;
+}
+
+template <int NW>
+__device__ __forceinline__ MW<NW> raw_digit(const RawDigit<NW> &r, int64_t bit0, int Nd) {
+    MW<NW> d;
+    const int o = (int)(bit0 & 31);
+#pragma unroll
+    for (int t = 0; t < NW; ++t) d.w[t] = o ? (r.l[t] >> o) | (r.l[t + 1] << (32 - o)) : r.l[t];
     const int tb = Nd - 32 * (NW - 1);
     if (tb < 32) d.w[NW - 1] &= (1u << tb) - 1u;
     return d;
@@ -180,16 +210,34 @@ __device__ __forceinline__ uint32_t hword(const MW<NW> &al, const MW<NW> &be, in
     return mw_bits(al, 32 * (int64_t)t) | mw_bits(be, 32 * (int64_t)t - Nd);
 }
 
-// One lane per segment.  Digits are read straight from the recombined products; a lane loads
-// the digits of CHAIN_G(NW) steps at once so their latencies overlap, then runs the steps.
+// all limbs of h' = alpha + 2^Nd beta (alpha, beta < 2^Nd), in a register array
 template <int NW>
-struct ChainGroup {
-    static constexpr int G = NW <= 2 ? 8 : (NW <= 4 ? 4 : 2);
+__device__ __forceinline__ void hprime(const MW<NW> &al, const MW<NW> &be, int Nd, uint32_t (&H)[2 * NW + 1]) {
+    const int q = Nd >> 5, o = Nd & 31;
+#pragma unroll
+    for (int t = 0; t < 2 * NW + 1; ++t) {
+        uint32_t v = t < NW ? al.w[t] : 0u;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            if (t == i + q) v |= be.w[i] << o;
+            if (o && t == i + q + 1) v |= be.w[i] >> (32 - o);
+        }
+        H[t] = v;
+    }
+}
+
+// One lane per segment.  Digits are read straight from the recombined products through a
+// ring of CHAIN_P(NW) prefetched steps: a step takes its digits from the ring and at once
+// issues the loads of the step CHAIN_P later, so the chain's dependent arithmetic overlaps
+// the memory latency of the steps ahead.
+template <int NW>
+struct ChainRing {
+    static constexpr int P = NW <= 3 ? 8 : (NW <= 5 ? 4 : 2);
 };
 
 template <int NW>
 __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
-    constexpr int G = ChainGroup<NW>::G;
+    constexpr int P = ChainRing<NW>::P;
     int64_t local;
     const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int64_t s = local * CHAIN_TPB + threadIdx.x;
@@ -216,21 +264,25 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
     }
     MW<NW> wc = W_DIGIT(k0);
     MW<NW> alpha = aprev, beta;
-    for (int64_t cg = k0; cg < k1; cg += G) {
-        MW<NW> us[G], ws[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            if (cg + g < k1) {
-                us[g] = U_DIGIT(cg + g);
-                ws[g] = W_DIGIT(cg + g + 1);
-            }
+    // ring slot j holds the digits u_c and w_{c+1} of the steps c = j (mod P)
+    RawDigit<NW> ru[P], rw[P];
+    auto fetch = [&](int j, int64_t c) {
+        if (c < k1) {
+            load_raw(ru[j], J.A, J.nA, c * (int64_t)Nd);
+            load_raw(rw[j], J.B, J.nB, (m - (c + 1)) * (int64_t)Nd);
         }
+    };
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            if (cg + g < k1) {
-                const int64_t c = cg + g;
-                const MW<NW> &u = us[g];
-                const MW<NW> &wn = ws[g];
+    for (int j = 0; j < P; ++j) fetch(j, k0 + j);
+    for (int64_t cb = k0; cb < k1; cb += P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int64_t c = cb + j;
+            if (c < k1) {
+                const MW<NW> u = raw_digit(ru[j], c * (int64_t)Nd, Nd);
+                const MW<NW> wn = raw_digit(rw[j], (m - (c + 1)) * (int64_t)Nd, Nd);
+                fetch(j, c + P);
+                __builtin_amdgcn_sched_barrier(0);
                 alpha = sub_mod(u, sigma, 0u, Nd);          // alpha_c = u_c - sigma_{c-1}  (mod Y)
                 uint32_t delta = mw_lt(u, sigma) ? 1u : 0u;  // carry of the low half into digit c+1
                 uint32_t eps = mw_lt(wn, alpha) ? 1u : 0u;   // eps_c = [alpha_c > w_{c+1}]
@@ -238,22 +290,12 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
                 sigma = add_bit(beta, delta);                // sigma_c = beta_c + delta
                 aprev = alpha;
                 wc = wn;
-                // write h_{2c+par} = h'_c - C
-                const int64_t idx = J.out_first + c * J.out_step;
-                if (J.mod_p == 0) {
-                    uint32_t *o = J.out + idx * J.w_out;
-                    uint32_t br = 0;
-                    for (int t = 0; t < J.w_out; ++t) {
-                        uint32_t word = t < hw ? hword(alpha, beta, Nd, t) : 0u;
-                        uint32_t sub = (J.off_bit >= 0 && (J.off_bit >> 5) == t) ? (1u << (J.off_bit & 31)) : 0u;
-                        uint64_t d = (uint64_t)word - sub - br;
-                        o[t] = (uint32_t)d;
-                        br = (uint32_t)(d >> 63) & 1u;
-                    }
-                } else {
-                    uint64_t r = 0;
-                    for (int t = hw - 1; t >= 0; --t) r = mod_step(r, hword(alpha, beta, Nd, t), J.mod_p);
-                    reinterpret_cast<uint64_t *>(J.out)[idx] = r;
+                // alpha_c and beta_c for the finishing pass
+                uint32_t *hb = J.hbuf + c * (2 * NW);
+#pragma unroll
+                for (int t = 0; t < NW; ++t) {
+                    hb[t] = alpha.w[t];
+                    hb[NW + t] = beta.w[t];
                 }
             }
         }
@@ -269,6 +311,50 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
     if (!ok) set_status(L.devstat, KS_DEVSTAT_CHECK);
 #undef U_DIGIT
 #undef W_DIGIT
+}
+
+// One thread per coefficient c of a chain: h' = alpha_c + 2^Nd beta_c from the chain's scratch,
+// written as h_{first + c step} = h' - C (w_out <= 2 NW + 1 limbs, since 2 Nd >= 2b + e) or as
+// h' - C mod p.  Kept out of the chain, whose lanes are few and whose steps are dependent.
+template <int NW>
+__global__ __launch_bounds__(FINISH_TPB) void finish_kernel(Launch<ChainJob> L) {
+    int64_t local;
+    const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const int64_t c = local * FINISH_TPB + threadIdx.x;
+    if (c >= J.m) return;
+    const int Nd = J.Nd;
+    MW<NW> alpha, beta;
+    const uint32_t *hb = J.hbuf + c * (2 * NW);
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+        alpha.w[t] = hb[t];
+        beta.w[t] = hb[NW + t];
+    }
+    uint32_t H[2 * NW + 1];
+    hprime(alpha, beta, Nd, H);
+    const int64_t idx = J.out_first + c * J.out_step;
+    if (J.mod_p == 0) {
+        uint32_t *o = J.out + idx * J.w_out;
+        uint32_t br = 0;
+#pragma unroll
+        for (int t = 0; t < 2 * NW + 1; ++t) {
+            if (t < J.w_out) {
+                const uint32_t sub = (J.off_bit >> 5) == t ? (1u << (J.off_bit & 31)) : 0u;
+                const uint64_t d = (uint64_t)H[t] - (J.off_bit >= 0 ? sub : 0u) - br;
+                o[t] = (uint32_t)d;
+                br = (uint32_t)(d >> 63) & 1u;
+            }
+        }
+    } else {
+        // h' < 2^(2 Nd) and the slot constant is zero for residue inputs (unsigned)
+        const int hw = (2 * Nd + 31) >> 5;
+        const double pinv = 1.0 / (double)J.mod_p;
+        uint64_t r = 0;
+#pragma unroll
+        for (int t = 2 * NW; t >= 0; --t)
+            if (t < hw) r = mod_step(r, H[t], J.mod_p, pinv);
+        reinterpret_cast<uint64_t *>(J.out)[idx] = r;
+    }
 }
 
 // ---- host launchers ------------------------------------------------------------------------------
@@ -291,6 +377,24 @@ hipError_t launch_anchor(const Launch<AnchorJob> &L, int w_in, hipStream_t s) {
         case 6: hipLaunchKernelGGL(anchor_kernel<6>, g, b, 0, s, L); break;
         case 7: hipLaunchKernelGGL(anchor_kernel<7>, g, b, 0, s, L); break;
         case 8: hipLaunchKernelGGL(anchor_kernel<8>, g, b, 0, s, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const Launch<ChainJob> &L, int nw, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    dim3 g((unsigned)L.total_blocks), b(FINISH_TPB);
+    switch (nw) {
+        case 1: hipLaunchKernelGGL(finish_kernel<1>, g, b, 0, s, L); break;
+        case 2: hipLaunchKernelGGL(finish_kernel<2>, g, b, 0, s, L); break;
+        case 3: hipLaunchKernelGGL(finish_kernel<3>, g, b, 0, s, L); break;
+        case 4: hipLaunchKernelGGL(finish_kernel<4>, g, b, 0, s, L); break;
+        case 5: hipLaunchKernelGGL(finish_kernel<5>, g, b, 0, s, L); break;
+        case 6: hipLaunchKernelGGL(finish_kernel<6>, g, b, 0, s, L); break;
+        case 7: hipLaunchKernelGGL(finish_kernel<7>, g, b, 0, s, L); break;
+        case 8: hipLaunchKernelGGL(finish_kernel<8>, g, b, 0, s, L); break;
+        case 9: hipLaunchKernelGGL(finish_kernel<9>, g, b, 0, s, L); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -31,19 +31,21 @@ constexpr int MUL_CI = 128;
 
 // int8 matrix-core multiplier (7-bit digits): a block of MFMA_WAVES waves owns MFMA_RT row
 // tiles of 32 output digit blocks (32 digits each) = 7 * MFMA_ROWS output limbs and a part of
-// at most MFMA_MAX_PART block shifts; wave w takes the shifts t = t_a + c (mod 32) for the four
-// residues c = w, w+8, w+16, w+24, so an int32 accumulator sees at most 4 * MFMA_MAX_PART / 32
-// = 4096 shifts (each adds at most 32 * 127^2)
+// at most MFMA_MAX_PART block shifts; wave w takes the shifts t = t_a + c (mod 32) for the
+// MFMA_CLASSES residues c = w, w + MFMA_WAVES, ..., so an int32 accumulator sees at most
+// MFMA_CLASSES * MFMA_MAX_PART / 32 = 4096 shifts (each adds at most 32 * 127^2)
 constexpr int MFMA_WAVES = 8;
 constexpr int MFMA_TPB = 64 * MFMA_WAVES;
+constexpr int MFMA_CLASSES = 32 / MFMA_WAVES;
 constexpr int MFMA_RT = 8;
 constexpr int MFMA_ROWS = 32 * MFMA_RT;
 constexpr int MFMA_LIMBS = 7 * MFMA_ROWS;
-constexpr int64_t MFMA_MAX_PART = 32768;
+constexpr int64_t MFMA_MAX_PART = 4096 * 32 / MFMA_CLASSES;
 constexpr int64_t MFMA_PADB = 64;
 
 constexpr int EXTRACT_TPB = 256;
 constexpr int CHAIN_TPB = 64;
+constexpr int FINISH_TPB = 256;
 constexpr int ANCHOR_TPB = 256;  // four waves per anchor coefficient
 
 enum : int32_t { PK_SIGNED = 1, PK_REVERSE = 2, PK_ALTERNATE = 4, PK_CHECK = 8 };
@@ -200,6 +202,7 @@ struct ChainJob {
     const uint32_t *anchors;
     int32_t aw;
     int32_t Nd;
+    uint32_t *hbuf;  // the chain's alpha_c, beta_c: 2 ceil(Nd/32) words per coefficient
     uint32_t *out;
     int64_t out_first;
     int64_t out_step;

@@ -14,6 +14,7 @@ hipError_t launch_mul_valu(const Launch<MulJob> &L, hipStream_t s);
 hipError_t launch_extract(const Launch<ExtractJob> &L, hipStream_t s);
 hipError_t launch_anchor(const Launch<AnchorJob> &L, int w_in, hipStream_t s);
 hipError_t launch_chain(const Launch<ChainJob> &L, int nw, hipStream_t s);
+hipError_t launch_finish(const Launch<ChainJob> &L, int nw, hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_digitize(const Launch<DigitJob> &L, hipStream_t s);
 hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, hipStream_t s);

@@ -16,7 +16,8 @@
 //
 // A block covers MFMA_RT row tiles (32 rows each: 32 * 32 * MFMA_RT output digits =
 // MFMA_LIMBS limbs) and one part of the range of t.  Wave w takes the shifts of its part that
-// are congruent to w, w+8, w+16 or w+24 mod 32, one residue class after the other.  Within a
+// are congruent to w mod MFMA_WAVES (32 / MFMA_WAVES residues mod 32), one residue class after
+// the other.  Within a
 // class t advances by 32, which moves every row tile's a-rows by exactly one tile: the
 // a-fragment of tile rt at one step is that of tile rt-1 at the step before.  So a step loads
 // one new a-fragment (16 contiguous bytes per lane) and one Toeplitz b-window (68 bytes, one
@@ -90,7 +91,8 @@ __device__ __forceinline__ v4i mfma_bop(uint32_t win, int sel, uint32_t sh) {
 __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
     constexpr int RT = MFMA_RT;
     constexpr int PF = 8;  // steps loaded ahead (the b-window is consumed one step early)
-    static_assert(RT % PF == 0, "prefetch ring must divide the unrolled step count");
+    constexpr int UN = RT > PF ? RT : PF;  // steps per unrolled group: slot and ring indices are constants
+    static_assert(UN % RT == 0 && UN % PF == 0, "fragment slots and prefetch ring must divide the unroll");
     constexpr int NDIG = 32 * MFMA_ROWS;  // output digits of a block
     __shared__ unsigned long long D[NDIG];
 
@@ -130,8 +132,8 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
     const uint32_t *bw = reinterpret_cast<const uint32_t *>(J.bd + wb) + (lane < 16 ? lane : 16);
 
     const int wvu = __builtin_amdgcn_readfirstlane(wv);  // wave-uniform: scalar loop control
-    for (int ci = 0; ci < 4; ++ci) {
-        const int64_t t0 = ta + wvu + 8 * ci;
+    for (int ci = 0; ci < MFMA_CLASSES; ++ci) {
+        const int64_t t0 = ta + wvu + MFMA_WAVES * ci;
         if (t0 >= tb) break;
         const int64_t ns = uniform64((tb - t0 + 31) / 32);  // steps t = t0 + 32 k, k < ns
         // fragment slots: tile rt at step k uses fr[(rt - k) mod RT]; the loads of step k + PF
@@ -152,23 +154,23 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
         // operations of step k run
         v4i bop = mfma_bop(pb[0], sel, sh);
         auto step = [&](int j, int64_t k) {
-            fr[(RT - j) % RT] = pa[j % PF];
+            fr[(RT - j % RT) % RT] = pa[j % PF];
             fetch(j % PF, k + PF);
             // keep the loads at the head of their step (the scheduler would otherwise sink
             // them towards their uses and shorten the prefetch distance)
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
-                acc[rt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fr[(rt - j + RT) % RT], bop, acc[rt], 0, 0, 0);
+                acc[rt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fr[(rt - j % RT + RT) % RT], bop, acc[rt], 0, 0, 0);
             bop = mfma_bop(pb[(j + 1) % PF], sel, sh);
         };
         int64_t kb = 0;
-        for (; kb + RT <= ns; kb += RT) {
+        for (; kb + UN <= ns; kb += UN) {
 #pragma unroll
-            for (int j = 0; j < RT; ++j) step(j, kb + j);
+            for (int j = 0; j < UN; ++j) step(j, kb + j);
         }
 #pragma unroll
-        for (int j = 0; j < RT - 1; ++j)
+        for (int j = 0; j < UN - 1; ++j)
             if (kb + j < ns) step(j, kb + j);
     }
     __syncthreads();

@@ -62,6 +62,7 @@ struct ChainGeom {
     int par;   // first output coefficient (and anchor parity)
     int step;  // output stride: 2 (a parity of the four-point product) or 1 (two-point reciprocal)
     int64_t anchor_off, anchor_blocks, chain_blocks;
+    int64_t hbuf_off, finish_blocks;  // words of alpha/beta scratch; blocks of the finishing pass
 };
 
 struct Geom {
@@ -74,10 +75,11 @@ struct Geom {
     std::vector<NormGeom> norms;
     std::vector<ExtractGeom> extracts;
     std::vector<ChainGeom> chains;
-    int64_t op_limbs = 0, col_words = 0, norm_limbs = 0, anchor_limbs = 0, digit_bytes = 0;
+    int64_t op_limbs = 0, col_words = 0, norm_limbs = 0, anchor_limbs = 0, digit_bytes = 0, hbuf_words = 0;
     int64_t pack_blocks = 0, mul_blocks = 0, norm_blocks = 0, extract_blocks = 0, anchor_blocks = 0,
-            chain_blocks = 0;
-    int64_t ws_ops = 0, ws_cols = 0, ws_digits = 0, ws_norms = 0, ws_anchors = 0, ws_status = 0, ws_bytes = 0;
+            chain_blocks = 0, finish_blocks = 0;
+    int64_t ws_ops = 0, ws_cols = 0, ws_digits = 0, ws_norms = 0, ws_anchors = 0, ws_hbuf = 0, ws_status = 0,
+            ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
     double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0;
 };
@@ -101,6 +103,7 @@ struct JobLists {
     std::vector<ExtractJob> extract;
     std::map<int, std::vector<AnchorJob>> anchor;  // by limbs per input coefficient
     std::map<int, std::vector<ChainJob>> chain;    // by words per reconstruction digit
+    std::map<int, std::vector<ChainJob>> finish;   // the same chains, one thread per coefficient
 };
 
 // a job list uploaded to the device: the table and its block -> job map
@@ -110,7 +113,7 @@ struct DevList {
 };
 struct DevTables {
     DevList pack, mul, digit, mfma, norm, extract;
-    std::map<int, DevList> anchor, chain;
+    std::map<int, DevList> anchor, chain, finish;
 };
 
 struct LaunchEnv {
