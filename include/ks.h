@@ -207,12 +207,30 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
  * each launch made by ks_mul / ks_mul_mod / ks_batch_run is bracketed by HIP events on the
  * stream it is launched on; ks_profile_read synchronises those streams and returns, for
  * kernel `name`, the number of launches and their summed duration in milliseconds.  Names:
- * "pack", "mul_valu", "mul_mfma", "normalize", "anchor", "recon", "extract", "digitize".
- * Returns KS_EINVAL for an unknown name.
+ * "pack" (with the anchors it carries), "mul_valu", "mul_mfma", "normalize", "anchor",
+ * "recon", "finish", "extract", "digitize".  Returns KS_EINVAL for an unknown name.
  */
 int ks_profile_enable(int32_t on);
 int ks_profile_read(const char *name, int64_t *launches, double *total_ms);
 int ks_profile_reset(void);
+
+/*
+ * Planner tunables (launch shapes), process-wide, read whenever a product or batch is planned;
+ * a value set here overrides the environment variable of the same name, which overrides the
+ * built-in default.  Names and defaults:
+ *   "KS_MFMA_MIN_LIMBS"  6000  both operands at least this many limbs -> matrix-core engine
+ *   "KS_MFMA_BLOCKS"     1024  matrix-core launch target of one product, in blocks (unset, a
+ *                              batch of n products gives each max(1, 2048 / n); set, each
+ *                              product of a batch aims at the value)
+ *   "KS_MFMA_MIN_PART"   128   shortest part (block shifts) the matrix-core planner cuts
+ *   "KS_CHAIN_K"         model reconstruction segment length (0 or unset: the cost model)
+ * ks_tune_set returns KS_EINVAL for an unknown name or a negative value; ks_tune_get returns
+ * the value in force (KS_EINVAL if unknown); ks_tune_reset clears every value set here.
+ * Plans made before a change keep their shapes.  Used by paper_0712_4046_amd/autotune.py.
+ */
+int ks_tune_set(const char *name, int64_t value);
+int ks_tune_get(const char *name, int64_t *value);
+int ks_tune_reset(void);
 
 #ifdef __cplusplus
 }

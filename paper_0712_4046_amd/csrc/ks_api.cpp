@@ -36,7 +36,23 @@ int ceil_log2(int64_t x) {
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
 
+// planner tunables: a value set through ks_tune_set, else the environment, else the default
+static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_CHAIN_K"};
+static std::mutex g_tune_mu;
+static std::map<std::string, int64_t> g_tune;
+
+static bool known_tunable(const char *name) {
+    for (const char *k : k_tunables)
+        if (strcmp(k, name) == 0) return true;
+    return false;
+}
+
 static int env_int(const char *name, int dflt) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(name);
+        if (it != g_tune.end()) return (int)std::min<int64_t>(it->second, 0x7fffffff);
+    }
     const char *v = getenv(name);
     return v && *v ? atoi(v) : dflt;
 }
@@ -201,8 +217,8 @@ int plan_product(const Spec &sp, Geom &G) {
         const double cK = sp.batch ? 5.0e5 : 2.0e6;
         int64_t K = (int64_t)(std::sqrt(nbat * G.D * Lm * sp.w_in * sp.w_in / cK) + 0.5);
         K = std::max<int64_t>(sp.batch ? 64 : 4, std::min<int64_t>(K, 4096));
-        K = env_int("KS_CHAIN_K", (int)K);
-        if (K < 1) K = 1;
+        const int64_t Kset = env_int("KS_CHAIN_K", 0);
+        if (Kset > 0) K = Kset;
         G.nw = (int)cdiv(Nd, 32);
         G.chain_nd = Nd;
         G.aw = 2 * sp.w_in + 2;
@@ -790,6 +806,29 @@ int ks_stream_status(void *stream) {
 
 int ks_profile_enable(int32_t on) {
     g_prof = on != 0;
+    return KS_OK;
+}
+
+int ks_tune_set(const char *name, int64_t value) {
+    if (!name || !known_tunable(name) || value < 0) return KS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[name] = value;
+    return KS_OK;
+}
+
+int ks_tune_get(const char *name, int64_t *value) {
+    if (!name || !value || !known_tunable(name)) return KS_EINVAL;
+    static const int dflt[] = {6000, 1024, 128, 0};
+    int d = 0;
+    for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
+        if (strcmp(k_tunables[q], name) == 0) d = dflt[q];
+    *value = env_int(name, d);
+    return KS_OK;
+}
+
+int ks_tune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
     return KS_OK;
 }
 

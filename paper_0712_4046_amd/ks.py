@@ -69,6 +69,9 @@ def lib() -> ctypes.CDLL:
         "ks_profile_enable": ([i32], ctypes.c_int),
         "ks_profile_read": ([ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "ks_profile_reset": ([], ctypes.c_int),
+        "ks_tune_set": ([ctypes.c_char_p, i64], ctypes.c_int),
+        "ks_tune_get": ([ctypes.c_char_p, ctypes.POINTER(i64)], ctypes.c_int),
+        "ks_tune_reset": ([], ctypes.c_int),
         "ks_batch_plan_create": ([P, i64, i32, ctypes.POINTER(P)], ctypes.c_int),
         "ks_batch_plan_bad_index": ([], i64),
         "ks_batch_plan_workspace_bytes": ([P], sz),
@@ -196,6 +199,31 @@ def profile_enable(on: bool = True):
 
 def profile_reset():
     _check(lib().ks_profile_reset(), "ks_profile_reset")
+
+
+TUNABLES = ("KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_CHAIN_K")
+
+
+def tune_set(name: str, value: int):
+    """Override a planner tunable (ks_tune_set); see include/ks.h for names and defaults."""
+    _check(lib().ks_tune_set(name.encode(), int(value)), f"ks_tune_set({name})")
+
+
+def tune_get(name: str) -> int:
+    v = ctypes.c_int64()
+    _check(lib().ks_tune_get(name.encode(), ctypes.byref(v)), f"ks_tune_get({name})")
+    return int(v.value)
+
+
+def tune_reset():
+    _check(lib().ks_tune_reset(), "ks_tune_reset")
+
+
+def apply_tuning(table: dict):
+    """Set every tunable of a table written by paper_0712_4046_amd.autotune."""
+    for k, v in table.items():
+        if k in TUNABLES:
+            tune_set(k, v)
 
 
 def profile_read(name: str):

@@ -72,3 +72,26 @@ def test_config2_slot_width():
     # L = 4096, b = 64 (sign included): KS1 N = 2b + e = 140, KS4 N = 35
     assert ks.plan(4096, 4096, 64, "ks1", True)["slot_bits"] == 140
     assert ks.plan(4096, 4096, 64, "ks4", True)["slot_bits"] == 35
+
+
+def test_tunables_round_trip_and_reach_the_planner():
+    L = ks.lib()
+    ks.tune_reset()
+    try:
+        assert ks.tune_get("KS_MFMA_MIN_LIMBS") == 6000
+        assert L.ks_tune_set(b"NO_SUCH_TUNABLE", 3) == ks.KS_EINVAL
+        assert L.ks_tune_set(b"KS_CHAIN_K", -1) == ks.KS_EINVAL
+        # engine threshold: a 2,241-limb product moves to the matrix cores when it is lowered
+        assert ks.plan(2048, 2048, 64, "ks4", True)["engine"] == ks.KS_ENGINE_VALU
+        ks.tune_set("KS_MFMA_MIN_LIMBS", 1)
+        assert ks.tune_get("KS_MFMA_MIN_LIMBS") == 1
+        assert ks.plan(2048, 2048, 64, "ks4", True)["engine"] == ks.KS_ENGINE_MFMA
+        # segment length: longer segments, fewer anchors
+        ks.tune_set("KS_CHAIN_K", 4)
+        a4 = ks.plan(4096, 4096, 64, "ks4", True)["anchor_limb_mults"]
+        ks.tune_set("KS_CHAIN_K", 64)
+        a64 = ks.plan(4096, 4096, 64, "ks4", True)["anchor_limb_mults"]
+        assert a4 > 10 * a64 > 0
+    finally:
+        ks.tune_reset()
+    assert ks.tune_get("KS_MFMA_MIN_LIMBS") == 6000
