@@ -224,6 +224,10 @@ int ks_profile_reset(void);
  *                              product of a batch aims at the value)
  *   "KS_MFMA_MIN_PART"   128   shortest part (block shifts) the matrix-core planner cuts
  *   "KS_CHAIN_K"         model reconstruction segment length (0 or unset: the cost model)
+ *   "KS_MUL_WAVE_MAX"    1024  vector-ALU products whose shorter operand has at most this many
+ *                              limbs run one wave per 128-column tile (else a block per tile)
+ *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
+ *                              128) run one wave per job (0: every job in 256-thread blocks)
  * ks_tune_set returns KS_EINVAL for an unknown name or a negative value; ks_tune_get returns
  * the value in force (KS_EINVAL if unknown); ks_tune_reset clears every value set here.
  * Plans made before a change keep their shapes.  Used by paper_0712_4046_amd/autotune.py.

@@ -6,8 +6,8 @@
 For one workload it times the whole run (HIP events on the stream the library launches on,
 median of a few runs after warm-up) for candidate values of each tunable in turn -- a
 coordinate descent, repeated while it still improves -- keeps the fastest value of each, and
-writes them as JSON together with the default and tuned times.  `ks.apply_tuning(table)` (or
-`--apply` in bench-like scripts) sets them for later plans.  The shapes change only how work
+writes them as JSON together with the default and tuned times; `ks.apply_tuning(table)` sets
+them for later plans.  The shapes change only how work
 is cut into launches and blocks, never the result: tests/test_gpu_autotune.py checks a tuned
 run bit for bit against the default one.
 
@@ -28,6 +28,8 @@ CANDIDATES = {
     "KS_MFMA_MIN_LIMBS": [2000, 4000, 6000, 10000, 20000, 1 << 30],
     "KS_MFMA_BLOCKS": [256, 512, 1024, 2048, 4096],
     "KS_MFMA_MIN_PART": [32, 64, 128, 256, 512],
+    "KS_MUL_WAVE_MAX": [0, 256, 512, 1024, 2048, 4096],
+    "KS_SCAN_SMALL": [0, 64, 128],
 }
 
 

@@ -25,13 +25,11 @@ __device__ __forceinline__ bool load_mag(const uint32_t *c, bool sgn, uint32_t (
     return neg;
 }
 
-// One block computes one anchor: block `blk` of the launch's anchor jobs.
+// One block computes one anchor: block `local` of anchor job J.
 template <int W>
-__device__ __forceinline__ void anchor_block(const Launch<AnchorJob> &L, int64_t blk) {
+__device__ __forceinline__ void anchor_block(const AnchorJob &J, int64_t local) {
     constexpr int AW = 2 * W + 2;
     __shared__ uint32_t s_acc[ANCHOR_TPB / 64][AW];
-    int64_t local;
-    const AnchorJob J = get_job(L, blk, local);
     const int64_t s = local + 1;
     const int64_t k = J.kstep * (s * J.K - 1) + J.par;
     int64_t lo = k - (J.lg - 1);

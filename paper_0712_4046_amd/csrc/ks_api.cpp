@@ -37,7 +37,8 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
 
 // planner tunables: a value set through ks_tune_set, else the environment, else the default
-static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_CHAIN_K"};
+static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_CHAIN_K",
+                                         "KS_MUL_WAVE_MAX",   "KS_SCAN_SMALL"};
 static std::mutex g_tune_mu;
 static std::map<std::string, int64_t> g_tune;
 
@@ -121,7 +122,8 @@ int plan_product(const Spec &sp, Geom &G) {
             p.L = which ? lg : lf;
             p.n_out = which ? ng : nf;
             p.op_off = off;
-            p.blocks = cdiv(p.n_out, SCAN_BL);
+            p.small = p.n_out <= std::min<int64_t>(SMALL_BL, env_int("KS_SCAN_SMALL", (int)SMALL_BL));
+            p.blocks = p.small ? 1 : cdiv(p.n_out, SCAN_BL);
             off += align_up(p.n_out, 64);
             G.packs.push_back(p);
             G.pack_blocks += p.blocks;
@@ -169,6 +171,9 @@ int plan_product(const Spec &sp, Geom &G) {
             m.ntiles = cdiv(nf + ng - 1, MUL_T);
             m.blocks = m.ntiles;
             m.ncols = m.ntiles * MUL_T;
+            // a tile's i range is at most min(nf, ng) limbs: when that is short, one wave per
+            // tile keeps the waves busy (the block mode splits the range over MUL_WAVES waves)
+            m.wave = std::min(nf, ng) <= env_int("KS_MUL_WAVE_MAX", 1024);
         }
         m.cols_off = coff;
         coff += align_up((eng == KS_ENGINE_MFMA ? 4 : 3) * m.ncols, 64);
@@ -195,7 +200,8 @@ int plan_product(const Spec &sp, Geom &G) {
         r.off_count = sp.sgn ? count : 0;
         r.n_out = n_out;
         r.n_in = std::max(prod_limbs + 2, n_out + shift / 32 + 2);
-        r.blocks = cdiv(r.n_in, SCAN_BL);
+        r.small = r.n_in <= std::min<int64_t>(SMALL_BL, env_int("KS_SCAN_SMALL", (int)SMALL_BL));
+        r.blocks = r.small ? 1 : cdiv(r.n_in, SCAN_BL);
         r.out_off = noff;
         noff += align_up(n_out, 64);
         G.norms.push_back(r);
@@ -353,10 +359,11 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.bits = sp.bits;
         j.flags = p.flags;
         j.mod_p = sp.mod_p;
-        j.ctr = (int32_t)JL.pack.size();
-        j.block0 = next_block(JL.pack);
+        auto &pl = p.small ? JL.pack_small : JL.pack;
+        j.ctr = (int32_t)pl.size();
+        j.block0 = next_block(pl);
         j.nblocks = p.blocks;
-        JL.pack.push_back(j);
+        pl.push_back(j);
     }
     auto digits = [&](int64_t byte_off) { return reinterpret_cast<uint8_t *>(ws + G.ws_digits + byte_off); };
     for (auto &m : G.muls) {
@@ -401,9 +408,10 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.na = m.na;
         j.nb = m.nb;
         j.cols = cols(m.cols_off);
-        j.block0 = next_block(JL.mul);
+        auto &ml = m.wave ? JL.mul_wave : JL.mul;
+        j.block0 = next_block(ml);
         j.nblocks = m.blocks;
-        JL.mul.push_back(j);
+        ml.push_back(j);
     }
     for (auto &c : G.chains) {
         if (c.anchor_blocks == 0) continue;
@@ -451,10 +459,11 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.out = norms(r.out_off);
         j.n_out = r.n_out;
         j.n_in = r.n_in;
-        j.ctr = (int64_t)JL.norm.size();
-        j.block0 = next_block(JL.norm);
+        auto &nl = r.small ? JL.norm_small : JL.norm;
+        j.ctr = (int64_t)nl.size();
+        j.block0 = next_block(nl);
         j.nblocks = r.blocks;
-        JL.norm.push_back(j);
+        nl.push_back(j);
     }
     for (auto &x : G.extracts) {
         ExtractJob j;
@@ -550,9 +559,19 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         }
         if (err != hipSuccess) return KS_EHIP;
     }
+    if (!JL.pack_small.empty()) {
+        auto L = make_launch(JL.pack_small, T ? &T->pack_small : nullptr, env, epoch_pack);
+        err = timed("pack", s, [&] { return launch_pack_small(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
     if (!JL.mul.empty()) {
         auto L = make_launch(JL.mul, T ? &T->mul : nullptr, env, 0);
         err = timed("mul_valu", s, [&] { return launch_mul_valu(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    if (!JL.mul_wave.empty()) {
+        auto L = make_launch(JL.mul_wave, T ? &T->mul_wave : nullptr, env, 0);
+        err = timed("mul_valu", s, [&] { return launch_mul_valu_wave(L, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.mfma.empty()) {
@@ -573,6 +592,11 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
     {
         auto L = make_launch(JL.norm, T ? &T->norm : nullptr, env, epoch_norm, env.ctr_norm);
         err = timed("normalize", s, [&] { return launch_normalize(L, s); });
+        if (err != hipSuccess) return KS_EHIP;
+    }
+    if (!JL.norm_small.empty()) {
+        auto L = make_launch(JL.norm_small, T ? &T->norm_small : nullptr, env, epoch_norm);
+        err = timed("normalize", s, [&] { return launch_normalize_small(L, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.extract.empty()) {
@@ -818,7 +842,7 @@ int ks_tune_set(const char *name, int64_t value) {
 
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
-    static const int dflt[] = {6000, 1024, 128, 0};
+    static const int dflt[] = {6000, 1024, 128, 0, 1024, (int)SMALL_BL};
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];

@@ -159,14 +159,17 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     const int64_t base = align256(8 * P->header_words);
     auto sh = [&](auto *&ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(reinterpret_cast<uintptr_t>(ptr) + base); };
     for (auto &j : JL.pack) sh(j.out);
+    for (auto &j : JL.pack_small) sh(j.out);
     for (auto &j : JL.mul) { sh(j.a); sh(j.b); sh(j.cols); }
+    for (auto &j : JL.mul_wave) { sh(j.a); sh(j.b); sh(j.cols); }
     for (auto &j : JL.digit) { sh(j.limbs); sh(j.out); sh(j.zero); }
     for (auto &j : JL.mfma) { sh(j.ad); sh(j.bd); sh(j.cols); }
     for (auto &kv : JL.anchor) for (auto &j : kv.second) sh(j.anchors);
-    for (auto &j : JL.norm) {
-        for (int q = 0; q < j.nterms; ++q) { sh(j.term[q].cols); sh(j.term[q].a); sh(j.term[q].b); }
-        sh(j.out);
-    }
+    for (auto *nl : {&JL.norm, &JL.norm_small})
+        for (auto &j : *nl) {
+            for (int q = 0; q < j.nterms; ++q) { sh(j.term[q].cols); sh(j.term[q].a); sh(j.term[q].b); }
+            sh(j.out);
+        }
     for (auto &j : JL.extract) sh(j.src);
     for (auto &kv : JL.chain) for (auto &j : kv.second) { sh(j.A); sh(j.B); sh(j.anchors); sh(j.hbuf); }
     for (auto &kv : JL.finish) for (auto &j : kv.second) { sh(j.A); sh(j.B); sh(j.anchors); sh(j.hbuf); }
@@ -175,10 +178,13 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
 
     int rc = KS_OK;
     if (rc == KS_OK) rc = upload(JL.pack, P->T.pack, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.pack_small, P->T.pack_small, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mul, P->T.mul, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.mul_wave, P->T.mul_wave, P->allocs);
     if (rc == KS_OK) rc = upload(JL.digit, P->T.digit, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mfma, P->T.mfma, P->allocs);
     if (rc == KS_OK) rc = upload(JL.norm, P->T.norm, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.norm_small, P->T.norm_small, P->allocs);
     if (rc == KS_OK) rc = upload(JL.extract, P->T.extract, P->allocs);
     for (auto &kv : JL.anchor) if (rc == KS_OK) rc = upload(kv.second, P->T.anchor[kv.first], P->allocs);
     for (auto &kv : JL.chain) if (rc == KS_OK) rc = upload(kv.second, P->T.chain[kv.first], P->allocs);

@@ -188,7 +188,8 @@ struct BlockCarryScan {
             cmap agg = CMAP_ID;
 #pragma unroll
             for (int w = 0; w < TPB / 64; ++w) agg = cmap_then(agg, sm.wave_agg[w]);
-            const int c = lb_resolve(st, blk, epoch, agg, devstat);
+            // a job of one block has no predecessors and no successors: nothing to publish
+            const int c = st ? lb_resolve(st, blk, epoch, agg, devstat) : 0;
             if (lane == 0) sm.carry_in = c;
         }
         __syncthreads();
@@ -211,6 +212,19 @@ struct BlockCarryScan {
 template <class T>
 __device__ __forceinline__ T ldg(const T *p) {
     return *(const __attribute__((address_space(1))) T *)p;
+}
+
+// The scalar fields of a launch that block bodies need, passed by value: a block body that took
+// the whole launch by reference (or by value) lost the kernel arguments' scalar loads.
+struct LaunchCtl {
+    uint64_t *status;
+    uint64_t *ctrs;
+    uint32_t *devstat;
+    uint32_t epoch;
+};
+template <class J>
+__device__ __forceinline__ LaunchCtl ctl_of(const Launch<J> &L) {
+    return LaunchCtl{L.status, L.ctrs, L.devstat, L.epoch};
 }
 
 // ---- job lookup: block index -> (job, block within job) ----------------------------------------

@@ -85,7 +85,9 @@ __global__ __launch_bounds__(EXTRACT_TPB) void extract_kernel(Launch<ExtractJob>
 
 template <int W>
 __global__ __launch_bounds__(ANCHOR_TPB) void anchor_kernel(Launch<AnchorJob> L) {
-    anchor_block<W>(L, (int64_t)blockIdx.x);
+    int64_t local;
+    const AnchorJob J = get_job(L, (int64_t)blockIdx.x, local);
+    anchor_block<W>(J, local);
 }
 
 // ---- chains ------------------------------------------------------------------------------------

@@ -20,6 +20,9 @@ constexpr int MAX_INLINE_JOBS = 8;
 constexpr int SCAN_TPB = 256;
 constexpr int SCAN_IPT = 2;
 constexpr int64_t SCAN_BL = (int64_t)SCAN_TPB * SCAN_IPT;
+// jobs of at most SMALL_BL limbs run one wave per job
+constexpr int SMALL_TPB = 64;
+constexpr int64_t SMALL_BL = (int64_t)SMALL_TPB * SCAN_IPT;
 
 // vector-ALU multiplier: a block of MUL_WAVES waves owns MUL_T = 64 * MUL_R product columns;
 // its waves take interleaved MUL_CI-long chunks of the i range and add up in LDS at the end

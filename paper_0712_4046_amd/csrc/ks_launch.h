@@ -10,7 +10,10 @@ namespace ks {
 hipError_t launch_pack(const Launch<PackJob> &L, hipStream_t s);
 hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, hipStream_t s);
 hipError_t launch_normalize(const Launch<NormJob> &L, hipStream_t s);
+hipError_t launch_pack_small(const Launch<PackJob> &L, hipStream_t s);
+hipError_t launch_normalize_small(const Launch<NormJob> &L, hipStream_t s);
 hipError_t launch_mul_valu(const Launch<MulJob> &L, hipStream_t s);
+hipError_t launch_mul_valu_wave(const Launch<MulJob> &L, hipStream_t s);
 hipError_t launch_extract(const Launch<ExtractJob> &L, hipStream_t s);
 hipError_t launch_anchor(const Launch<AnchorJob> &L, int w_in, hipStream_t s);
 hipError_t launch_chain(const Launch<ChainJob> &L, int nw, hipStream_t s);

@@ -27,15 +27,23 @@ __device__ __forceinline__ void mac96(uint64_t &lo, uint32_t &hi, uint32_t a, ui
         : "v"(a), "v"(b));
 }
 
+// WAVE = false: a block owns one MUL_T-column tile and its waves split the i range (large
+// products).  WAVE = true: every wave owns one tile and runs its whole i range alone, and the
+// waves of a block take consecutive tiles of the launch, of one product or of several (small
+// products, whose short i ranges would leave most of a block's waves idle); a job's blocks
+// then count tiles, not thread blocks.
+template <bool WAVE>
 __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
     __shared__ __attribute__((aligned(16))) uint32_t sa[MUL_WAVES][MUL_CI];
     __shared__ __attribute__((aligned(16))) uint32_t sb[MUL_WAVES][MUL_T + MUL_CI];
-    __shared__ uint64_t s_lo[MUL_WAVES][MUL_T];
-    __shared__ uint32_t s_hi[MUL_WAVES][MUL_T];
+    __shared__ uint64_t s_lo[WAVE ? 1 : MUL_WAVES][MUL_T];
+    __shared__ uint32_t s_hi[WAVE ? 1 : MUL_WAVES][MUL_T];
 
-    int64_t local;
-    const MulJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t item = WAVE ? (int64_t)blockIdx.x * MUL_WAVES + wv : (int64_t)blockIdx.x;
+    if (WAVE && item >= L.total_blocks) return;  // no block-wide barrier in this mode
+    int64_t local;
+    const MulJob J = get_job(L, item, local);
     const int64_t k0 = local * MUL_T;
     int64_t ilo = k0 - J.nb + 1;
     if (ilo < 0) ilo = 0;
@@ -46,16 +54,18 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
 #pragma unroll
     for (int r = 0; r < MUL_R; ++r) { lo[r] = 0; hi[r] = 0; }
 
-    // the waves take interleaved chunks of the i range: wave w runs chunks w, w + WAVES, ...;
-    // the next chunk's operands are loaded into registers while the current one is computed
-    const int64_t span = (int64_t)MUL_WAVES * MUL_CI;
+    // block mode: the waves take interleaved chunks of the i range (wave w runs chunks w,
+    // w + WAVES, ...); wave mode: the wave runs every chunk.  The next chunk's operands are
+    // loaded into registers while the current one is computed.
+    const int64_t span = WAVE ? (int64_t)MUL_CI : (int64_t)MUL_WAVES * MUL_CI;
+    const int64_t first = WAVE ? 0 : (int64_t)wv * MUL_CI;
     const int64_t niter = ihi > ilo ? (ihi - ilo + span - 1) / span : 0;
     const int base = lane * MUL_R + MUL_CI - MUL_R;
     constexpr int NA = MUL_CI / 64, NB = (MUL_T + MUL_CI) / 64;
     static_assert(MUL_CI % 64 == 0 && (MUL_T + MUL_CI) % 64 == 0, "staging is 64 words per lane round");
     uint32_t ra[NA], rb[NB];
     auto fetch = [&](int64_t it) {
-        const int64_t c0 = ilo + it * span + (int64_t)wv * MUL_CI;
+        const int64_t c0 = ilo + it * span + first;
         const bool active = c0 < ihi;
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
@@ -69,15 +79,25 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
             rb[q] = (active && bi >= 0 && bi < J.nb) ? ldg(J.b + bi) : 0u;
         }
     };
+    // the staging area of a wave is its own: in wave mode the wave's LDS accesses, performed
+    // in issue order, need only a compiler barrier between writing and reading
+    auto sync = [&]() {
+        if (WAVE) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            __syncthreads();
+        }
+    };
     if (niter > 0) fetch(0);
     for (int64_t it = 0; it < niter; ++it) {
-        const int64_t c0 = ilo + it * span + (int64_t)wv * MUL_CI;
+        const int64_t c0 = ilo + it * span + first;
         const bool active = c0 < ihi;
 #pragma unroll
         for (int q = 0; q < NA; ++q) sa[wv][lane + 64 * q] = ra[q];
 #pragma unroll
         for (int q = 0; q < NB; ++q) sb[wv][lane + 64 * q] = rb[q];
-        __syncthreads();
+        sync();
         if (it + 1 < niter) fetch(it + 1);
         if (active) {
             // E[idx] = sb[base - x0 + idx]; column r at step x0 + u uses E[R - 1 + r - u]
@@ -94,21 +114,32 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
                 ehi = elo;
             }
         }
-        __syncthreads();
+        sync();
     }
 
+    if (WAVE) {
+        // the wave's own sums, three 32-bit pieces per column
+#pragma unroll
+        for (int r = 0; r < MUL_R; ++r) {
+            uint32_t *o = J.cols + 3 * (k0 + lane * MUL_R + r);
+            o[0] = (uint32_t)lo[r];
+            o[1] = (uint32_t)(lo[r] >> 32);
+            o[2] = hi[r];
+        }
+        return;
+    }
     // add the waves' 96-bit sums and store them as three 32-bit pieces per column
 #pragma unroll
     for (int r = 0; r < MUL_R; ++r) {
-        s_lo[wv][lane * MUL_R + r] = lo[r];
-        s_hi[wv][lane * MUL_R + r] = hi[r];
+        s_lo[WAVE ? 0 : wv][lane * MUL_R + r] = lo[r];
+        s_hi[WAVE ? 0 : wv][lane * MUL_R + r] = hi[r];
     }
     __syncthreads();
     for (int t = tid; t < MUL_T; t += MUL_TPB) {
         uint64_t l = 0;
         uint32_t h = 0;
 #pragma unroll
-        for (int w = 0; w < MUL_WAVES; ++w) {
+        for (int w = 0; w < (WAVE ? 1 : MUL_WAVES); ++w) {
             const uint64_t x = s_lo[w][t];
             l += x;
             h += (l < x ? 1u : 0u) + s_hi[w][t];
@@ -122,7 +153,14 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
 
 hipError_t launch_mul_valu(const Launch<MulJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mul_valu_kernel, dim3((unsigned)L.total_blocks), dim3(MUL_TPB), 0, s, L);
+    hipLaunchKernelGGL(mul_valu_kernel<false>, dim3((unsigned)L.total_blocks), dim3(MUL_TPB), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_mul_valu_wave(const Launch<MulJob> &L, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    const int64_t blocks = (L.total_blocks + MUL_WAVES - 1) / MUL_WAVES;
+    hipLaunchKernelGGL(mul_valu_kernel<true>, dim3((unsigned)blocks), dim3(MUL_TPB), 0, s, L);
     return hipGetLastError();
 }
 

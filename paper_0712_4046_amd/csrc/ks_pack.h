@@ -25,21 +25,23 @@ __device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[PK_MAXW], int 
     return o ? (a >> o) | (b << (32 - o)) : a;
 }
 
-// One block of the pack launch.
-__device__ __forceinline__ void pack_block(const Launch<PackJob> &L) {
-    typedef BlockCarryScan<SCAN_TPB, SCAN_IPT> Scan;
+// A block of pack job J with TPB threads (TPB * SCAN_IPT limbs per block); `local` is its
+// position in the job when the job has one block (else it draws a ticket).  The caller looks
+// the job up in its own kernel arguments.
+template <int TPB>
+__device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, const LaunchCtl L) {
+    constexpr int64_t BL = (int64_t)TPB * SCAN_IPT;
+    typedef BlockCarryScan<TPB, SCAN_IPT> Scan;
     __shared__ typename Scan::Smem sm;
     __shared__ uint32_t s_ticket;
-    __shared__ int64_t s_v[SCAN_BL + 3];  // s_v[x + 2] = column jb + x, x in [-2, SCAN_BL]
-    int64_t local;
-    const PackJob J = get_job(L, (int64_t)blockIdx.x, local);
+    __shared__ int64_t s_v[BL + 3];  // s_v[x + 2] = column jb + x, x in [-2, BL]
     if (J.nblocks > 1 && threadIdx.x == 0) s_ticket = (uint32_t)job_ticket(L.ctrs + J.ctr, J.nblocks);
-    for (int x = threadIdx.x; x < SCAN_BL + 3; x += SCAN_TPB) s_v[x] = 0;
+    for (int x = threadIdx.x; x < BL + 3; x += TPB) s_v[x] = 0;
     __syncthreads();
     if (J.nblocks > 1) local = s_ticket;
     const int tid = threadIdx.x;
-    const int64_t jb = local * SCAN_BL;
-    const int64_t jlo = jb - 2, jhi = jb + SCAN_BL + 1;  // columns [jlo, jhi)
+    const int64_t jb = local * BL;
+    const int64_t jlo = jb - 2, jhi = jb + BL + 1;  // columns [jlo, jhi)
     const int64_t N = J.N;
     const int bits = J.bits, w_in = J.w_in;
     const bool sgn = (J.flags & PK_SIGNED) != 0;
@@ -49,11 +51,11 @@ __device__ __forceinline__ void pack_block(const Launch<PackJob> &L) {
     int64_t i1 = jhi <= 0 ? -1 : div_by(32 * jhi - 1, J.N_recip);
     if (i1 > J.L - 1) i1 = J.L - 1;
     constexpr int U = 4;  // coefficients per thread per round, loads issued together
-    for (int64_t ib = i0 + tid; ib <= i1; ib += U * SCAN_TPB) {
+    for (int64_t ib = i0 + tid; ib <= i1; ib += U * TPB) {
         uint32_t cl[U][PK_MAXW];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const int64_t i = ib + (int64_t)q * SCAN_TPB;
+            const int64_t i = ib + (int64_t)q * TPB;
             const int64_t ii = i <= i1 ? i : i0;
             const int64_t src = (J.flags & PK_REVERSE) ? J.L - 1 - ii : ii;
             const uint32_t *c = J.coeffs + src * w_in;
@@ -65,7 +67,7 @@ __device__ __forceinline__ void pack_block(const Launch<PackJob> &L) {
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const int64_t i = ib + (int64_t)q * SCAN_TPB;
+            const int64_t i = ib + (int64_t)q * TPB;
             if (i > i1) continue;
             uint32_t top = 0;
 #pragma unroll
@@ -84,7 +86,7 @@ __device__ __forceinline__ void pack_block(const Launch<PackJob> &L) {
                 if (neg) piece = -piece;
                 atomicAdd(reinterpret_cast<unsigned long long *>(&s_v[j - jb + 2]), (unsigned long long)piece);
             }
-            if ((J.flags & PK_CHECK) && w >= jb && w < jb + SCAN_BL) {
+            if ((J.flags & PK_CHECK) && w >= jb && w < jb + BL) {
                 // range check, once per coefficient (in the block holding its lowest limb)
                 bool ok;
                 if (J.mod_p) {
@@ -108,7 +110,7 @@ __device__ __forceinline__ void pack_block(const Launch<PackJob> &L) {
 #pragma unroll
     for (int q = 0; q < SCAN_IPT; ++q) u[q] = u_of(s_v[b0 + q + 2], s_v[b0 + q + 1], s_v[b0 + q]);
     uint32_t out[SCAN_IPT];
-    Scan::run(sm, u, out, L.status + J.block0, local, L.epoch, L.devstat);
+    Scan::run(sm, u, out, J.nblocks > 1 ? L.status + J.block0 : nullptr, local, L.epoch, L.devstat);
     const int64_t j0 = jb + b0;
 #pragma unroll
     for (int q = 0; q < SCAN_IPT; ++q)

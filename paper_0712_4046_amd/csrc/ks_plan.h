@@ -36,10 +36,12 @@ struct PackGeom {
     int which;  // 0: f, 1: g
     int flags;  // PK_*
     int64_t L, n_out, op_off, blocks;
+    bool small;  // at most SMALL_BL limbs: one wave
 };
 struct MulGeom {
     int fa, fb;  // operand (pack) indices
     int engine;  // KS_ENGINE_VALU or KS_ENGINE_MFMA
+    bool wave = false;  // vector ALU, one wave per tile (short i ranges)
     int64_t na, nb, ntiles;
     int64_t ncols, cols_off, blocks;  // column sums: 3 words (vector ALU) or 4 words (matrix cores)
     // matrix-core engine: 7-bit digit buffers (byte offsets in the digit region), row groups
@@ -51,6 +53,7 @@ struct MulGeom {
 struct NormGeom {
     int nterms, prod[2], sign[2], shift;
     int64_t off_bit0, off_period, off_count, n_in, n_out, out_off, blocks;
+    bool small;  // at most SMALL_BL limbs: one wave
 };
 struct ExtractGeom {
     int src;  // norm index
@@ -96,10 +99,13 @@ struct Ctl {
 // jobs of one or many products, per stage (anchor and chain lists keyed by template parameter)
 struct JobLists {
     std::vector<PackJob> pack;
+    std::vector<PackJob> pack_small;  // jobs of at most SMALL_BL limbs
     std::vector<MulJob> mul;
+    std::vector<MulJob> mul_wave;  // small products: one wave per tile (blocks count tiles)
     std::vector<DigitJob> digit;
     std::vector<MfmaJob> mfma;
     std::vector<NormJob> norm;
+    std::vector<NormJob> norm_small;  // jobs of at most SMALL_BL limbs
     std::vector<ExtractJob> extract;
     std::map<int, std::vector<AnchorJob>> anchor;  // by limbs per input coefficient
     std::map<int, std::vector<ChainJob>> chain;    // by words per reconstruction digit
@@ -112,7 +118,7 @@ struct DevList {
     uint32_t *block_job = nullptr;
 };
 struct DevTables {
-    DevList pack, mul, digit, mfma, norm, extract;
+    DevList pack, pack_small, mul, mul_wave, digit, mfma, norm, norm_small, extract;
     std::map<int, DevList> anchor, chain, finish;
 };
 

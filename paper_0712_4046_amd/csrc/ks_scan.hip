@@ -19,17 +19,32 @@ namespace ks {
 
 // ---- pack ------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) { pack_block(L); }
+__global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) {
+    int64_t local;
+    const PackJob J = get_job(L, (int64_t)blockIdx.x, local);
+    pack_block<SCAN_TPB>(J, local, ctl_of(L));
+}
+
+// jobs of at most SMALL_BL limbs (one block each): one wave per job
+__global__ __launch_bounds__(SMALL_TPB) void pack_small_kernel(Launch<PackJob> L) {
+    int64_t local;
+    const PackJob J = get_job(L, (int64_t)blockIdx.x, local);
+    pack_block<SMALL_TPB>(J, local, ctl_of(L));
+}
 
 // Pack and anchors in one launch: blocks [0, pack blocks) pack,
 // the rest compute anchors, which read only the inputs and so run beside the packing.
 static_assert(SCAN_TPB == ANCHOR_TPB, "pack and anchor blocks share one launch");
 template <int W>
 __global__ __launch_bounds__(SCAN_TPB) void pack_anchor_kernel(Launch<PackJob> Lp, Launch<AnchorJob> La) {
-    if ((int64_t)blockIdx.x < Lp.total_blocks)
-        pack_block(Lp);
-    else
-        anchor_block<W>(La, (int64_t)blockIdx.x - Lp.total_blocks);
+    int64_t local;
+    if ((int64_t)blockIdx.x < Lp.total_blocks) {
+        const PackJob J = get_job(Lp, (int64_t)blockIdx.x, local);
+        pack_block<SCAN_TPB>(J, local, ctl_of(Lp));
+    } else {
+        const AnchorJob J = get_job(La, (int64_t)blockIdx.x - Lp.total_blocks, local);
+        anchor_block<W>(J, local);
+    }
 }
 
 // ---- normalize --------------------------------------------------------------------------------
@@ -134,19 +149,21 @@ __device__ __forceinline__ void norm_window(const NormJob &J, const TermSigns &t
     }
 }
 
-__global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) {
-    typedef BlockCarryScan<SCAN_TPB, SCAN_IPT> Scan;
+// A block of recombination job J with TPB threads (TPB * SCAN_IPT limbs per block); the
+// caller looks the job up in its own kernel arguments.
+template <int TPB>
+__device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local, const LaunchCtl L) {
+    constexpr int64_t BL = (int64_t)TPB * SCAN_IPT;
+    typedef BlockCarryScan<TPB, SCAN_IPT> Scan;
     __shared__ typename Scan::Smem sm;
     __shared__ uint32_t s_ticket;
-    __shared__ uint32_t s_limb[SCAN_BL + 1];
+    __shared__ uint32_t s_limb[BL + 1];
     __shared__ int64_t s_tail[2];
-    int64_t local;
-    const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
     if (J.nblocks > 1 && threadIdx.x == 0) s_ticket = (uint32_t)job_ticket(L.ctrs + J.ctr, J.nblocks);
     __syncthreads();
     if (J.nblocks > 1) local = s_ticket;
     const int tid = threadIdx.x;
-    const int64_t jb = local * SCAN_BL;
+    const int64_t jb = local * BL;
     const int64_t j0 = jb + (int64_t)tid * SCAN_IPT;
     TermSigns ts;
 #pragma unroll
@@ -160,29 +177,41 @@ __global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) 
     int64_t u[SCAN_IPT];
 #pragma unroll
     for (int q = 0; q < SCAN_IPT; ++q) u[q] = u_of(v[q + 2], v[q + 1], v[q]);
-    if (tid == SCAN_TPB - 1) {
+    if (tid == TPB - 1) {
         // the first limb of the next block is needed by the shift: its value before carries
         int64_t vn[NV];
         norm_window(J, ts, j0 + SCAN_IPT, vn);
         s_tail[0] = u_of(vn[2], vn[1], vn[0]);
     }
     uint32_t out[SCAN_IPT];
-    const int kout = Scan::run(sm, u, out, L.status + J.block0, local, L.epoch, L.devstat);
+    const int kout = Scan::run(sm, u, out, J.nblocks > 1 ? L.status + J.block0 : nullptr, local, L.epoch, L.devstat);
 #pragma unroll
     for (int q = 0; q < SCAN_IPT; ++q) s_limb[tid * SCAN_IPT + q] = out[q];
-    if (tid == SCAN_TPB - 1) s_limb[SCAN_BL] = (uint32_t)(uint64_t)(s_tail[0] + kout);
+    if (tid == TPB - 1) s_limb[BL] = (uint32_t)(uint64_t)(s_tail[0] + kout);
     __syncthreads();
     // write V >> shift: output limb o takes limbs o + w and o + w + 1 (striped, coalesced)
     const int64_t w = J.shift >> 5;
     const int r = J.shift & 31;
 #pragma unroll
     for (int q = 0; q < SCAN_IPT; ++q) {
-        const int li = q * SCAN_TPB + tid;
+        const int li = q * TPB + tid;
         const int64_t o = jb + li - w;
         if (o < 0 || o >= J.n_out) continue;
         const uint32_t lo = s_limb[li];
         J.out[o] = r ? ((lo >> r) | (s_limb[li + 1] << (32 - r))) : lo;
     }
+}
+
+__global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) {
+    int64_t local;
+    const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
+    normalize_block<SCAN_TPB>(J, local, ctl_of(L));
+}
+
+__global__ __launch_bounds__(SMALL_TPB) void normalize_small_kernel(Launch<NormJob> L) {
+    int64_t local;
+    const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
+    normalize_block<SMALL_TPB>(J, local, ctl_of(L));
 }
 
 // ---- clearing scratch words (a kernel rather than a memset, so runs can be graph-captured) ------
@@ -221,6 +250,18 @@ hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob>
         case 8: hipLaunchKernelGGL(pack_anchor_kernel<8>, g, b, 0, s, Lp, La); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_small(const Launch<PackJob> &L, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize_small(const Launch<NormJob> &L, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normalize_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
     return hipGetLastError();
 }
 
