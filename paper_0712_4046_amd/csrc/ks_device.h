@@ -206,6 +206,16 @@ struct BlockCarryScan {
     }
 };
 
+// lo:hi (96 bits) += a * b: v_mad_u64_u32 accumulates the 32x32-bit product into 64 bits and
+// hands its carry to a v_addc into the top 32 bits
+__device__ __forceinline__ void mac96(uint64_t &lo, uint32_t &hi, uint32_t a, uint32_t b) {
+    uint64_t cc;
+    asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+        "v_addc_co_u32_e64 %2, %1, 0, %2, %1"
+        : "+v"(lo), "=&s"(cc), "+v"(hi)
+        : "v"(a), "v"(b));
+}
+
 // ---- loads through global (not flat) pointers ---------------------------------------------------
 // A flat load also counts against the LDS wait counter, so a kernel that prefetches from
 // global memory while it works out of LDS would drain its prefetches at every LDS wait.

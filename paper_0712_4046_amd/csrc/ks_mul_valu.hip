@@ -18,15 +18,6 @@
 
 namespace ks {
 
-// lo:hi (96 bits) += a * b
-__device__ __forceinline__ void mac96(uint64_t &lo, uint32_t &hi, uint32_t a, uint32_t b) {
-    uint64_t cc;
-    asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
-        "v_addc_co_u32_e64 %2, %1, 0, %2, %1"
-        : "+v"(lo), "=&s"(cc), "+v"(hi)
-        : "v"(a), "v"(b));
-}
-
 // WAVE = false: a block owns one MUL_T-column tile and its waves split the i range (large
 // products).  WAVE = true: every wave owns one tile and runs its whole i range alone, and the
 // waves of a block take consecutive tiles of the launch, of one product or of several (small
