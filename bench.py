@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # and for the 64-product modular batch (profiles/config4_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
-MEASURED_TRAFFIC = {"pack": 1009704, "mul_valu": 1641732, "normalize": 1255011, "recon": 658550}
-MEASURED_TRAFFIC_CONFIG4 = {"pack": 1020121474, "digitize": 950000387, "mul_mfma": 2530584193,
-                            "normalize": 1217221764, "recon": 288719068}
+MEASURED_TRAFFIC = {"pack": 993854, "mul_valu": 1656019, "normalize": 1270627, "recon": 692732, "finish": 436589}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 3141546908, "digitize": 950001456, "mul_mfma": 2530343907,
+                            "normalize": 1163794051, "recon": 349274099, "finish": 271331745}
 KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract")
 
 
@@ -69,8 +69,9 @@ def time_variant(ks, torch, tf, tg, bits, variant, signed, steps, warmup, out):
 
 
 def kernel_times(ks, run, reps):
-    """Average duration of each stage's launch, from HIP events the library records around
-    every launch on its own stream (ks_profile_*)."""
+    """Per stage: launches per run, average launch duration and the stage's time per run (its
+    launches added up), from HIP events the library records around every launch on its own
+    stream (ks_profile_*)."""
     ks.profile_reset()
     ks.profile_enable(True)
     for _ in range(reps):
@@ -82,32 +83,37 @@ def kernel_times(ks, run, reps):
     for name in KERNELS:
         n, ms = ks.profile_read(name)
         if n:
-            out[name] = {"launches": n, "avg_us": 1000.0 * ms / n}
+            out[name] = {"launches": n, "launches_per_run": n / reps, "avg_us": 1000.0 * ms / n,
+                         "per_run_us": 1000.0 * ms / reps}
     return out
 
 
 def roofline(kern, info, traffic_table=None):
-    """The dominant launch's achieved rate against its bound.  Work per launch is algorithmic:
-    limb products (vector-ALU multiplier), int8 operations (matrix cores) or the stage's bytes."""
-    dom = max(kern, key=lambda k: kern[k]["avg_us"])
-    sec = kern[dom]["avg_us"] * 1e-6
+    """The dominant stage's achieved rate against its bound: the stage's algorithmic work in one
+    run (limb products of the vector-ALU products, int8 operations of the matrix-core products,
+    or the stage's bytes) over the stage's time in one run.  A single product launches each
+    stage once, so there this is work per launch over the launch's duration; a batch may launch
+    a stage twice (block- and wave-mode multipliers, wide and one-wave scans)."""
+    dom = max(kern, key=lambda k: kern[k]["per_run_us"])
+    sec = kern[dom]["per_run_us"] * 1e-6
     traffic = (traffic_table or {}).get(dom)
+    lpr = kern[dom]["launches_per_run"]
     if dom == "mul_mfma":
         ops = info["mfma_ops"]
         achieved = ops / sec / 1e12
         return {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / MFMA_I8_PEAK_TOPS, "traffic": traffic,
-                "op": "int8 multiply-add of 7-bit digits (2 operations)", "ops_per_launch": ops}
+                "frac": achieved / MFMA_I8_PEAK_TOPS, "traffic": traffic, "launches_per_run": lpr,
+                "op": "int8 multiply-add of 7-bit digits (2 operations)", "ops_per_run": ops}
     if dom in ("mul_valu", "anchor"):
-        ops = info["schoolbook_limb_mults"] if dom == "mul_valu" else info["anchor_limb_mults"]
+        ops = info["valu_limb_mults"] if dom == "mul_valu" else info["anchor_limb_mults"]
         achieved = ops / sec / 1e12
         return {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                "op": "32x32->64-bit limb multiply-accumulate", "ops_per_launch": ops}
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic, "launches_per_run": lpr,
+                "op": "32x32->64-bit limb multiply-accumulate", "ops_per_run": ops}
     nbytes = {"pack": info["pack_bytes"], "normalize": info["normalize_bytes"]}.get(dom, info["finish_bytes"])
     achieved = nbytes / sec / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": nbytes}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launches_per_run": lpr, "bytes_per_run": nbytes}
 
 
 def batch_line(ks, torch, B, count, variant, reps, traffic=None):
@@ -134,7 +140,8 @@ def batch_line(ks, torch, B, count, variant, reps, traffic=None):
     eng = {ks.KS_ENGINE_VALU: "valu", ks.KS_ENGINE_MFMA: "mfma"}.get(info["engine"], "valu+mfma")
     return {"variant": variant, "engine": eng, "ms_per_batch": dt * 1e3, "products_per_s": count / dt,
             "limb_mults_per_s": info["limb_mults"] / dt, "mfma_ops_per_s": info["mfma_ops"] / dt,
-            "kernels_us": {k: v["avg_us"] for k, v in kern.items()}, "roofline": roofline(kern, info, traffic)}
+            "kernels_us_per_run": {k: v["per_run_us"] for k, v in kern.items()},
+            "roofline": roofline(kern, info, traffic)}
 
 
 def main():

@@ -198,6 +198,9 @@ typedef struct ks_plan_info {
     double anchor_limb_mults; /*   limb products of the reconstruction anchors (KS4)              */
     double mfma_ops;          /* int8 operations (2 per multiply-add) of the 7-bit digit products
                                  run on the matrix cores: 2 * sum of (digits of a) * (digits of b) */
+    double valu_limb_mults;   /* sum of (limbs of a) * (limbs of b) over the products run on the
+                                 vector ALU (the rest of schoolbook_limb_mults runs on the matrix
+                                 cores) */
 } ks_plan_info;
 
 int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, ks_plan_info *out);

@@ -181,6 +181,7 @@ int plan_product(const Spec &sp, Geom &G) {
         G.mul_blocks += m.blocks;
         G.school_mults += (double)nf * (double)ng;
         if (eng == KS_ENGINE_MFMA) G.mfma_ops += 2.0 * (double)m.nad * (double)m.nbd;
+        else G.valu_mults += (double)nf * (double)ng;
     }
     G.col_words = coff;
     G.digit_bytes = doff;
@@ -734,7 +735,7 @@ using namespace ks;
 
 extern "C" {
 
-int32_t ks_version(void) { return 102; }
+int32_t ks_version(void) { return 103; }
 
 const char *ks_strerror(int code) {
     switch (code) {
@@ -780,6 +781,7 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
     out->finish_bytes = G.finish_bytes;
     out->anchor_limb_mults = G.anchor_mults;
     out->mfma_ops = G.mfma_ops;
+    out->valu_limb_mults = G.valu_mults;
     return KS_OK;
 }
 

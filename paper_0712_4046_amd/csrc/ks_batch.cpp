@@ -70,7 +70,7 @@ struct ks_batch_plan {
     int64_t ctr_pack = 0, ctr_norm = 0;  // word offsets of the counters
     int64_t ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
-    double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0;
+    double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0, valu_mults = 0;
     int32_t engines = 0;  // OR of the engines the products use
     int variant = -1;
 };
@@ -140,6 +140,7 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
         P->finish_bytes += geoms[(size_t)i].finish_bytes;
         P->anchor_mults += geoms[(size_t)i].anchor_mults;
         P->mfma_ops += geoms[(size_t)i].mfma_ops;
+        P->valu_mults += geoms[(size_t)i].valu_mults;
         for (const auto &m : geoms[(size_t)i].muls) P->engines |= m.engine;
         int rv = geoms[(size_t)i].variant;
         P->variant = i == 0 ? rv : (P->variant == rv ? rv : -1);
@@ -211,6 +212,7 @@ int ks_batch_plan_info(const ks_batch_plan *plan, ks_plan_info *out) {
     out->finish_bytes = plan->finish_bytes;
     out->anchor_limb_mults = plan->anchor_mults;
     out->mfma_ops = plan->mfma_ops;
+    out->valu_limb_mults = plan->valu_mults;
     return KS_OK;
 }
 

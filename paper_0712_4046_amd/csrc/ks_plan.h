@@ -85,6 +85,7 @@ struct Geom {
             ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
     double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0;
+    double valu_mults = 0;  // schoolbook limb products of the vector-ALU products
 };
 
 // device words that outlive one call: block-ticket counters (pack jobs, then normalize jobs),

@@ -202,13 +202,15 @@ __device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local,
     }
 }
 
-__global__ __launch_bounds__(SCAN_TPB) void normalize_kernel(Launch<NormJob> L) {
+// at least five waves per SIMD: the register budget (96) that keeps the column window's loads
+// in flight without spilling, and one more wave than the unconstrained allocation (100)
+__global__ __launch_bounds__(SCAN_TPB, 5) void normalize_kernel(Launch<NormJob> L) {
     int64_t local;
     const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
     normalize_block<SCAN_TPB>(J, local, ctl_of(L));
 }
 
-__global__ __launch_bounds__(SMALL_TPB) void normalize_small_kernel(Launch<NormJob> L) {
+__global__ __launch_bounds__(SMALL_TPB, 5) void normalize_small_kernel(Launch<NormJob> L) {
     int64_t local;
     const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
     normalize_block<SMALL_TPB>(J, local, ctl_of(L));

@@ -38,7 +38,8 @@ class PlanInfo(ctypes.Structure):
                 ("limb_mults", ctypes.c_double), ("schoolbook_limb_mults", ctypes.c_double),
                 ("hbm_bytes", ctypes.c_double), ("pack_bytes", ctypes.c_double),
                 ("normalize_bytes", ctypes.c_double), ("finish_bytes", ctypes.c_double),
-                ("anchor_limb_mults", ctypes.c_double), ("mfma_ops", ctypes.c_double)]
+                ("anchor_limb_mults", ctypes.c_double), ("mfma_ops", ctypes.c_double),
+                ("valu_limb_mults", ctypes.c_double)]
 
 
 class Desc(ctypes.Structure):
