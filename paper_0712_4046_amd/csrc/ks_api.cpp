@@ -607,7 +607,7 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
     }
     for (auto &kv : JL.chain) {
         auto L = make_launch(kv.second, T ? &T->chain.at(kv.first) : nullptr, env, 0);
-        err = timed("recon", s, [&] { return launch_chain(L, kv.first, s); });
+        err = timed("recon", s, [&] { return launch_chain(L, kv.first, T != nullptr, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     for (auto &kv : JL.finish) {

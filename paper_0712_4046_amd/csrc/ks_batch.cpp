@@ -53,6 +53,23 @@ static int upload(const std::vector<J> &jobs, DevList &d, std::vector<void *> &a
     return KS_OK;
 }
 
+// Lists keyed by digit width -> one list under key 0 (the launchers' "any width" kernel), the
+// jobs' first blocks renumbered; a single width keeps its specialised kernel.
+template <class J>
+static void merge_widths(std::map<int, std::vector<J>> &lists) {
+    if (lists.size() <= 1) return;
+    std::vector<J> all;
+    int64_t b = 0;
+    for (auto &kv : lists)
+        for (J j : kv.second) {
+            j.block0 = b;
+            b += j.nblocks;
+            all.push_back(j);
+        }
+    lists.clear();
+    lists[0] = std::move(all);
+}
+
 template <class J>
 static int64_t blocks_of(const std::vector<J> &v) {
     return v.empty() ? 0 : v.back().block0 + v.back().nblocks;
@@ -176,6 +193,19 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     for (auto &kv : JL.finish) for (auto &j : kv.second) { sh(j.A); sh(j.B); sh(j.anchors); sh(j.hbuf); }
     P->ws_bytes = base + scratch;
     (void)off;
+    // a batch's chains are launched by segment (one lane each, jobs packed side by side in the
+    // waves), and chains (and finishing passes) of several digit widths go into one launch
+    // whose lanes (blocks) run their own width, rather than one launch per width in turn
+    for (auto &kv : JL.chain) {
+        int64_t b = 0;
+        for (auto &j : kv.second) {
+            j.block0 = b;
+            j.nblocks = j.nseg;
+            b += j.nseg;
+        }
+    }
+    merge_widths(JL.chain);
+    merge_widths(JL.finish);
 
     int rc = KS_OK;
     if (rc == KS_OK) rc = upload(JL.pack, P->T.pack, P->allocs);

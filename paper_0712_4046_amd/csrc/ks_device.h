@@ -224,6 +224,11 @@ __device__ __forceinline__ T ldg(const T *p) {
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
+template <class T>
+__device__ __forceinline__ void stg(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
 // The scalar fields of a launch that block bodies need, passed by value: a block body that took
 // the whole launch by reference (or by value) lost the kernel arguments' scalar loads.
 struct LaunchCtl {

@@ -105,7 +105,11 @@ __device__ __forceinline__ MW<NW> read_digit(const uint32_t *x, int64_t n, int64
     const int o = (int)(bit0 & 31);
     uint32_t l[NW + 1];
 #pragma unroll
-    for (int t = 0; t <= NW; ++t) l[t] = (q + t >= 0 && q + t < n) ? x[q + t] : 0u;
+    for (int t = 0; t <= NW; ++t) {
+        const bool ok = q + t >= 0 && q + t < n;
+        const uint32_t v = ldg(x + (ok ? q + t : 0));
+        l[t] = ok ? v : 0u;
+    }
 #pragma unroll
     for (int t = 0; t < NW; ++t) d.w[t] = o ? (l[t] >> o) | (l[t + 1] << (32 - o)) : l[t];
     const int tb = Nd - 32 * (NW - 1);
@@ -113,7 +117,9 @@ __device__ __forceinline__ MW<NW> read_digit(const uint32_t *x, int64_t n, int64
     return d;
 }
 
-// the NW + 1 words that hold an Nd-bit digit at bit0 (loads only), and the digit from them
+// The NW + 1 words that hold an Nd-bit digit at bit0, loaded as they are (clamped addresses, no
+// branches, global rather than flat loads), so that a ring of them stays in flight; words
+// outside [0, n) are zeroed only where the digit is formed from them.
 template <int NW>
 struct RawDigit {
     uint32_t l[NW + 1];
@@ -123,15 +129,22 @@ template <int NW>
 __device__ __forceinline__ void load_raw(RawDigit<NW> &r, const uint32_t *x, int64_t n, int64_t bit0) {
     const int64_t q = bit0 >> 5;
 #pragma unroll
-    for (int t = 0; t <= NW; ++t) r.l[t] = (q + t >= 0 && q + t < n) ? x[q + t] : 0u;
+    for (int t = 0; t <= NW; ++t) {
+        const bool ok = q + t >= 0 && q + t < n;
+        r.l[t] = ldg(x + (ok ? q + t : 0));
+    }
 }
 
 template <int NW>
-__device__ __forceinline__ MW<NW> raw_digit(const RawDigit<NW> &r, int64_t bit0, int Nd) {
+__device__ __forceinline__ MW<NW> raw_digit(const RawDigit<NW> &r, int64_t n, int64_t bit0, int Nd) {
     MW<NW> d;
+    const int64_t q = bit0 >> 5;
     const int o = (int)(bit0 & 31);
+    uint32_t l[NW + 1];
 #pragma unroll
-    for (int t = 0; t < NW; ++t) d.w[t] = o ? (r.l[t] >> o) | (r.l[t + 1] << (32 - o)) : r.l[t];
+    for (int t = 0; t <= NW; ++t) l[t] = (q + t >= 0 && q + t < n) ? r.l[t] : 0u;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) d.w[t] = o ? (l[t] >> o) | (l[t + 1] << (32 - o)) : l[t];
     const int tb = Nd - 32 * (NW - 1);
     if (tb < 32) d.w[NW - 1] &= (1u << tb) - 1u;
     return d;
@@ -237,12 +250,13 @@ struct ChainRing {
     static constexpr int P = NW <= 3 ? 8 : (NW <= 5 ? 4 : 2);
 };
 
-template <int NW>
-__global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
+// Segment s of chain J on this lane.  ROUNDS: whole rounds of P steps without guards, then the
+// last partial round (the same loads in flight on every path, so the waits stay partial:
+// long segments); else one guarded loop (half the code: short segments, where instruction
+// fetch is a large part of the time).
+template <int NW, bool ROUNDS>
+__device__ __forceinline__ void chain_seg(const ChainJob &J, int64_t s, uint32_t *devstat) {
     constexpr int P = ChainRing<NW>::P;
-    int64_t local;
-    const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
-    const int64_t s = local * CHAIN_TPB + threadIdx.x;
     if (s >= J.nseg) return;
     const int Nd = J.Nd;
     const int64_t m = J.m;
@@ -268,39 +282,48 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
     MW<NW> alpha = aprev, beta;
     // ring slot j holds the digits u_c and w_{c+1} of the steps c = j (mod P)
     RawDigit<NW> ru[P], rw[P];
+    // ROUNDS: a refill past the segment's last step re-reads the first step's words (cached,
+    // unused), so the refill needs no branch; else refills past the last step are skipped
     auto fetch = [&](int j, int64_t c) {
-        if (c < k1) {
-            load_raw(ru[j], J.A, J.nA, c * (int64_t)Nd);
-            load_raw(rw[j], J.B, J.nB, (m - (c + 1)) * (int64_t)Nd);
+        if (!ROUNDS && c >= k1) return;
+        const int64_t cc = c < k1 ? c : k0;
+        load_raw(ru[j], J.A, J.nA, cc * (int64_t)Nd);
+        load_raw(rw[j], J.B, J.nB, (m - (cc + 1)) * (int64_t)Nd);
+    };
+    // step c: digits from ring slot j, which is refilled with step c + P's
+    auto step = [&](int j, int64_t c) {
+        const MW<NW> u = raw_digit(ru[j], J.nA, c * (int64_t)Nd, Nd);
+        const MW<NW> wn = raw_digit(rw[j], J.nB, (m - (c + 1)) * (int64_t)Nd, Nd);
+        fetch(j, c + P);
+        __builtin_amdgcn_sched_barrier(0);
+        alpha = sub_mod(u, sigma, 0u, Nd);          // alpha_c = u_c - sigma_{c-1}  (mod Y)
+        uint32_t delta = mw_lt(u, sigma) ? 1u : 0u;  // carry of the low half into digit c+1
+        uint32_t eps = mw_lt(wn, alpha) ? 1u : 0u;   // eps_c = [alpha_c > w_{c+1}]
+        beta = sub_mod(wc, aprev, eps, Nd);          // beta_c = w_c - alpha_{c-1} - eps_c (mod Y)
+        sigma = add_bit(beta, delta);                // sigma_c = beta_c + delta
+        aprev = alpha;
+        wc = wn;
+        // alpha_c and beta_c for the finishing pass
+        uint32_t *hb = J.hbuf + c * (2 * NW);
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            stg(hb + t, alpha.w[t]);
+            stg(hb + NW + t, beta.w[t]);
         }
     };
 #pragma unroll
     for (int j = 0; j < P; ++j) fetch(j, k0 + j);
-    for (int64_t cb = k0; cb < k1; cb += P) {
+    int64_t cb = k0;
+    if (ROUNDS) {
+        for (; cb + P <= k1; cb += P) {
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int64_t c = cb + j;
-            if (c < k1) {
-                const MW<NW> u = raw_digit(ru[j], c * (int64_t)Nd, Nd);
-                const MW<NW> wn = raw_digit(rw[j], (m - (c + 1)) * (int64_t)Nd, Nd);
-                fetch(j, c + P);
-                __builtin_amdgcn_sched_barrier(0);
-                alpha = sub_mod(u, sigma, 0u, Nd);          // alpha_c = u_c - sigma_{c-1}  (mod Y)
-                uint32_t delta = mw_lt(u, sigma) ? 1u : 0u;  // carry of the low half into digit c+1
-                uint32_t eps = mw_lt(wn, alpha) ? 1u : 0u;   // eps_c = [alpha_c > w_{c+1}]
-                beta = sub_mod(wc, aprev, eps, Nd);          // beta_c = w_c - alpha_{c-1} - eps_c (mod Y)
-                sigma = add_bit(beta, delta);                // sigma_c = beta_c + delta
-                aprev = alpha;
-                wc = wn;
-                // alpha_c and beta_c for the finishing pass
-                uint32_t *hb = J.hbuf + c * (2 * NW);
-#pragma unroll
-                for (int t = 0; t < NW; ++t) {
-                    hb[t] = alpha.w[t];
-                    hb[NW + t] = beta.w[t];
-                }
-            }
+            for (int j = 0; j < P; ++j) step(j, cb + j);
         }
+    }
+    for (; cb < k1; cb += P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (cb + j < k1) step(j, cb + j);
     }
     // self-checks: the segment ends on the next anchor; the chain ends on the two unused relations
     bool ok = true;
@@ -310,18 +333,53 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
     } else if (k1 > k0) {
         ok = mw_eq(alpha, W_DIGIT(m)) && mw_eq(sigma, U_DIGIT(m));
     }
-    if (!ok) set_status(L.devstat, KS_DEVSTAT_CHECK);
+    if (!ok) set_status(devstat, KS_DEVSTAT_CHECK);
 #undef U_DIGIT
 #undef W_DIGIT
+}
+
+// A job's blocks of CHAIN_TPB lanes take its segments in order (single products).
+template <int NW>
+__global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
+    int64_t local;
+    const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const int64_t s = local * CHAIN_TPB + threadIdx.x;
+    if (s < J.nseg) chain_seg<NW, false>(J, s, L.devstat);
+}
+
+// Batches: the launch's units are segments, not blocks (a job's block0 and nblocks count its
+// segments), and every lane looks up its own job, so the few segments of many small chains
+// share waves.  NW = 0: the jobs have different digit widths (ascending in the table, so a
+// wave mixes at most two) and each lane runs the body of its job's width.
+template <int NW>
+__global__ __launch_bounds__(CHAIN_TPB) void chain_lanes_kernel(Launch<ChainJob> L) {
+    const int64_t g = (int64_t)blockIdx.x * CHAIN_TPB + threadIdx.x;
+    if (g >= L.total_blocks) return;
+    int64_t s;
+    const ChainJob J = get_job(L, g, s);
+    if (NW > 0) {
+        chain_seg<NW, true>(J, s, L.devstat);
+        return;
+    }
+    switch ((J.Nd + 31) >> 5) {
+        case 1: chain_seg<1, true>(J, s, L.devstat); break;
+        case 2: chain_seg<2, true>(J, s, L.devstat); break;
+        case 3: chain_seg<3, true>(J, s, L.devstat); break;
+        case 4: chain_seg<4, true>(J, s, L.devstat); break;
+        case 5: chain_seg<5, true>(J, s, L.devstat); break;
+        case 6: chain_seg<6, true>(J, s, L.devstat); break;
+        case 7: chain_seg<7, true>(J, s, L.devstat); break;
+        case 8: chain_seg<8, true>(J, s, L.devstat); break;
+        case 9: chain_seg<9, true>(J, s, L.devstat); break;
+        default: break;
+    }
 }
 
 // One thread per coefficient c of a chain: h' = alpha_c + 2^Nd beta_c from the chain's scratch,
 // written as h_{first + c step} = h' - C (w_out <= 2 NW + 1 limbs, since 2 Nd >= 2b + e) or as
 // h' - C mod p.  Kept out of the chain, whose lanes are few and whose steps are dependent.
 template <int NW>
-__global__ __launch_bounds__(FINISH_TPB) void finish_kernel(Launch<ChainJob> L) {
-    int64_t local;
-    const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
+__device__ __forceinline__ void finish_block(const ChainJob &J, int64_t local) {
     const int64_t c = local * FINISH_TPB + threadIdx.x;
     if (c >= J.m) return;
     const int Nd = J.Nd;
@@ -329,8 +387,8 @@ __global__ __launch_bounds__(FINISH_TPB) void finish_kernel(Launch<ChainJob> L) 
     const uint32_t *hb = J.hbuf + c * (2 * NW);
 #pragma unroll
     for (int t = 0; t < NW; ++t) {
-        alpha.w[t] = hb[t];
-        beta.w[t] = hb[NW + t];
+        alpha.w[t] = ldg(hb + t);
+        beta.w[t] = ldg(hb + NW + t);
     }
     uint32_t H[2 * NW + 1];
     hprime(alpha, beta, Nd, H);
@@ -356,6 +414,30 @@ __global__ __launch_bounds__(FINISH_TPB) void finish_kernel(Launch<ChainJob> L) 
         for (int t = 2 * NW; t >= 0; --t)
             if (t < hw) r = mod_step(r, H[t], J.mod_p, pinv);
         reinterpret_cast<uint64_t *>(J.out)[idx] = r;
+    }
+}
+
+template <int NW>
+__global__ __launch_bounds__(FINISH_TPB) void finish_kernel(Launch<ChainJob> L) {
+    int64_t local;
+    const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
+    finish_block<NW>(J, local);
+}
+
+__global__ __launch_bounds__(FINISH_TPB) void finish_any_kernel(Launch<ChainJob> L) {
+    int64_t local;
+    const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
+    switch ((J.Nd + 31) >> 5) {
+        case 1: finish_block<1>(J, local); break;
+        case 2: finish_block<2>(J, local); break;
+        case 3: finish_block<3>(J, local); break;
+        case 4: finish_block<4>(J, local); break;
+        case 5: finish_block<5>(J, local); break;
+        case 6: finish_block<6>(J, local); break;
+        case 7: finish_block<7>(J, local); break;
+        case 8: finish_block<8>(J, local); break;
+        case 9: finish_block<9>(J, local); break;
+        default: break;
     }
 }
 
@@ -388,6 +470,7 @@ hipError_t launch_finish(const Launch<ChainJob> &L, int nw, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     dim3 g((unsigned)L.total_blocks), b(FINISH_TPB);
     switch (nw) {
+        case 0: hipLaunchKernelGGL(finish_any_kernel, g, b, 0, s, L); break;
         case 1: hipLaunchKernelGGL(finish_kernel<1>, g, b, 0, s, L); break;
         case 2: hipLaunchKernelGGL(finish_kernel<2>, g, b, 0, s, L); break;
         case 3: hipLaunchKernelGGL(finish_kernel<3>, g, b, 0, s, L); break;
@@ -402,9 +485,27 @@ hipError_t launch_finish(const Launch<ChainJob> &L, int nw, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_chain(const Launch<ChainJob> &L, int nw, hipStream_t s) {
+hipError_t launch_chain(const Launch<ChainJob> &L, int nw, bool lanes, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    dim3 g((unsigned)L.total_blocks), b(CHAIN_TPB);
+    dim3 b(CHAIN_TPB);
+    if (lanes) {
+        dim3 g((unsigned)((L.total_blocks + CHAIN_TPB - 1) / CHAIN_TPB));
+        switch (nw) {
+            case 0: hipLaunchKernelGGL(chain_lanes_kernel<0>, g, b, 0, s, L); break;
+            case 1: hipLaunchKernelGGL(chain_lanes_kernel<1>, g, b, 0, s, L); break;
+            case 2: hipLaunchKernelGGL(chain_lanes_kernel<2>, g, b, 0, s, L); break;
+            case 3: hipLaunchKernelGGL(chain_lanes_kernel<3>, g, b, 0, s, L); break;
+            case 4: hipLaunchKernelGGL(chain_lanes_kernel<4>, g, b, 0, s, L); break;
+            case 5: hipLaunchKernelGGL(chain_lanes_kernel<5>, g, b, 0, s, L); break;
+            case 6: hipLaunchKernelGGL(chain_lanes_kernel<6>, g, b, 0, s, L); break;
+            case 7: hipLaunchKernelGGL(chain_lanes_kernel<7>, g, b, 0, s, L); break;
+            case 8: hipLaunchKernelGGL(chain_lanes_kernel<8>, g, b, 0, s, L); break;
+            case 9: hipLaunchKernelGGL(chain_lanes_kernel<9>, g, b, 0, s, L); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    dim3 g((unsigned)L.total_blocks);
     switch (nw) {
         case 1: hipLaunchKernelGGL(chain_kernel<1>, g, b, 0, s, L); break;
         case 2: hipLaunchKernelGGL(chain_kernel<2>, g, b, 0, s, L); break;

@@ -16,7 +16,9 @@ hipError_t launch_mul_valu(const Launch<MulJob> &L, hipStream_t s);
 hipError_t launch_mul_valu_wave(const Launch<MulJob> &L, hipStream_t s);
 hipError_t launch_extract(const Launch<ExtractJob> &L, hipStream_t s);
 hipError_t launch_anchor(const Launch<AnchorJob> &L, int w_in, hipStream_t s);
-hipError_t launch_chain(const Launch<ChainJob> &L, int nw, hipStream_t s);
+// lanes: the jobs' units are segments (batches), else blocks of CHAIN_TPB segments; nw = 0 only
+// with lanes (jobs of several widths)
+hipError_t launch_chain(const Launch<ChainJob> &L, int nw, bool lanes, hipStream_t s);
 hipError_t launch_finish(const Launch<ChainJob> &L, int nw, hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_digitize(const Launch<DigitJob> &L, hipStream_t s);
