@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--workload", default="config2", choices=["config1", "config2"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
+    ap.add_argument("--no-paper", action="store_true", help="skip the (Z/nZ)[x] sweep of the paper's figures")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
 
@@ -66,6 +67,45 @@ def time_variant(ks, torch, tf, tg, bits, variant, signed, steps, warmup, out):
         ks.mul(tf, tg, bits, variant, signed, out=out)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def paper_sweep(ks, torch, wl):
+    """The paper's example timings redone on this GPU: (Z/nZ)[x] products through every variant
+    for a random 4-bit and a random 48-bit odd modulus n at L = 4 .. 65536 (powers of 4), as
+    t(KS1) / t(variant) -- the quantity of the paper's Figures 1 and 2.  Each variant's result
+    must equal KS1's (checked on the device); the oracle checks these moduli in the GPU tests."""
+    out = {}
+    for nb in wl.PAPER_FIG_BITS:
+        rows = []
+        for L in wl.PAPER_FIG_LENGTHS:
+            n, f, g = wl.paper_fig_pair(nb, L)
+            tf = torch.from_numpy(f.view(np.int64)).cuda()
+            tg = torch.from_numpy(g.view(np.int64)).cuda()
+            res, ms = {}, {}
+            for v in ("ks1", "recip2", "neg2", "ks4"):
+                o = torch.empty(2 * L - 1, dtype=torch.int64, device="cuda")
+                ks.mul_mod(tf, tg, n, v, out=o)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ks.mul_mod(tf, tg, n, v, out=o)
+                torch.cuda.synchronize()
+                reps = max(5, min(200, int(0.03 / max(time.perf_counter() - t0, 1e-6))))
+                for _ in range(3):
+                    ks.mul_mod(tf, tg, n, v, out=o)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    ks.mul_mod(tf, tg, n, v, out=o)
+                torch.cuda.synchronize()
+                ms[v] = (time.perf_counter() - t0) / reps * 1e3
+                res[v] = o
+            ks.check()
+            same = all(torch.equal(res[v], res["ks1"]) for v in res)
+            if not same:
+                raise SystemExit(f"paper sweep: variants disagree at n of {nb} bits, L = {L}")
+            rows.append({"L": L, "ms": ms, "ks1_over": {v: ms["ks1"] / ms[v] for v in ("recip2", "neg2", "ks4")}})
+        out[f"n_{nb}_bit"] = {"n": n, "rows": rows}
+    return out
 
 
 def kernel_times(ks, run, reps):
@@ -136,9 +176,26 @@ def batch_line(ks, torch, B, count, variant, reps, traffic=None):
         plan.run(ain, aout, ws)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    # the same run captured once in a hipGraph and replayed (its launches issued by the graph)
+    eager = aout.clone()
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plan.run(ain, aout, ws, stream=s)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    dtg = (time.perf_counter() - t0) / reps
+    if plan.status(ws) != ks.KS_OK or not torch.equal(aout, eager):
+        raise SystemExit("batch graph replay differs from the eager run")
+    del graph
     plan.close()
     eng = {ks.KS_ENGINE_VALU: "valu", ks.KS_ENGINE_MFMA: "mfma"}.get(info["engine"], "valu+mfma")
     return {"variant": variant, "engine": eng, "ms_per_batch": dt * 1e3, "products_per_s": count / dt,
+            "ms_per_batch_graph": dtg * 1e3, "products_per_s_graph": count / dtg,
             "limb_mults_per_s": info["limb_mults"] / dt, "mfma_ops_per_s": info["mfma_ops"] / dt,
             "kernels_us_per_run": {k: v["per_run_us"] for k, v in kern.items()},
             "roofline": roofline(kern, info, traffic)}
@@ -219,6 +276,8 @@ def main():
             "config3": "10,000 signed products, L log-uniform in [16, 1024], b in {16, 32, 64, 128}, seed 3",
             "config4": "64 products mod a 60-bit odd p, L = 65536, residues uniform in [0, p), seed 4"}
 
+    paper = None if args.no_paper else paper_sweep(ks, torch, wl)
+
     p4 = plans["ks4"]
     ms = t["ks4"] * 1000.0
     rec = {
@@ -250,6 +309,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batch": batch,
+        "paper_figures": paper,
     }
     print(json.dumps(rec))
 

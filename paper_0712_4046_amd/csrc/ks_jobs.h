@@ -33,17 +33,18 @@ constexpr int MUL_T = 64 * MUL_R;
 constexpr int MUL_CI = 128;
 
 // int8 matrix-core multiplier (7-bit digits): a block of MFMA_WAVES waves owns MFMA_RT row
-// tiles of 32 output digit blocks (32 digits each) = 7 * MFMA_ROWS output limbs and a part of
+// tiles of 32 output digit blocks (32 digits each) = 8 * MFMA_ROWS output limbs and a part of
 // at most MFMA_MAX_PART block shifts; wave w takes the shifts t = t_a + c (mod 32) for the
 // MFMA_CLASSES residues c = w, w + MFMA_WAVES, ..., so an int32 accumulator sees at most
-// MFMA_CLASSES * MFMA_MAX_PART / 32 = 4096 shifts (each adds at most 32 * 127^2)
+// MFMA_CLASSES * MFMA_MAX_PART / 32 = 4064 shifts (each adds at most 32 * 128^2 in absolute
+// value, so the sum stays below 2^31)
 constexpr int MFMA_WAVES = 8;
 constexpr int MFMA_TPB = 64 * MFMA_WAVES;
 constexpr int MFMA_CLASSES = 32 / MFMA_WAVES;
 constexpr int MFMA_RT = 8;
 constexpr int MFMA_ROWS = 32 * MFMA_RT;
-constexpr int MFMA_LIMBS = 7 * MFMA_ROWS;
-constexpr int64_t MFMA_MAX_PART = 4096 * 32 / MFMA_CLASSES;
+constexpr int MFMA_LIMBS = 8 * MFMA_ROWS;
+constexpr int64_t MFMA_MAX_PART = 4064 * 32 / MFMA_CLASSES;
 constexpr int64_t MFMA_PADB = 64;
 
 constexpr int EXTRACT_TPB = 256;
@@ -83,10 +84,11 @@ struct MulJob {
     int64_t nblocks;  // = number of column tiles
 };
 
-// 7-bit digits of a limb array into a zero-padded byte buffer: out[x] = digit(x - base), or
-// digit(base - x) when reversed (the Toeplitz operand is read in descending digit order)
-// (x in [0, len)); the job's later blocks clear zero_len bytes at `zero` (the product's
-// column buffer, which the matrix-core multiplier accumulates into)
+// Balanced 8-bit digits of a limb array (n limbs: digits 0 .. 4n, see digitize_kernel) into a
+// zero-padded byte buffer: out[x] = digit(x - base), or digit(base - x) when reversed (the
+// Toeplitz operand is read in descending digit order) (x in [0, len)); the job's later blocks
+// clear zero_len bytes at `zero` (the product's column buffer, which the matrix-core
+// multiplier accumulates into)
 struct DigitJob {
     const uint32_t *limbs;
     int64_t n;

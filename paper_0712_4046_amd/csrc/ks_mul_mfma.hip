@@ -1,14 +1,16 @@
 // ks_mul_mfma.hip -- integer products on the int8 matrix cores (v_mfma_i32_32x32x32_i8).
 //
-// An integer product is a convolution of digit sequences: with 7-bit digits a_i, b_j
-// (values 0..127, so they fit the signed int8 operands exactly and no sign correction is
-// needed), C[k] = sum_i a_i b_{k-i} and A*B = sum_k C[k] 2^(7k).  Writing k = 32 s + r and
+// An integer product is a convolution of digit sequences: with balanced 8-bit digits a_i, b_j
+// (values -128..127, exactly the signed int8 operands: A = sum_i a_i 256^i, see
+// digitize_kernel), C[k] = sum_i a_i b_{k-i} and A*B = sum_k C[k] 2^(8k).  Writing k = 32 s + r and
 // splitting the shift into 32-digit blocks t,
 //     C[32 s + r] = sum_t sum_{q<32} a[32 (s - t) + q] * b[32 t + r - q],
 // each block shift t is a 32x32x32 matrix product: rows s (a 32-digit output block), columns
 // r, contraction q; the a-matrix rows are contiguous 32-digit runs of a and the b-matrix is a
 // Toeplitz tile of b.  One v_mfma_i32_32x32x32_i8 computes it, accumulating exactly in int32
-// (at most 32 * 127^2 per step; a wave takes at most 4096 steps).
+// (at most 32 * 128^2 in absolute value per step; a wave takes at most 4064 steps).  Against
+// 7-bit digits (0..127) the balanced digits need 8/7 fewer per operand, (8/7)^2 = 1.31x fewer
+// multiply-adds per product.
 //
 // Lane layout of v_mfma_i32_32x32x32_i8 (checked on the device): lane l supplies row (A) or
 // column (B) l % 32 and contraction indices 16 (l / 32) .. + 15 as 16 bytes; result register
@@ -35,27 +37,88 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 // ---- digits ------------------------------------------------------------------------------------
 
-// out[x] for x in [0, len): digit d = (reversed ? base - x : x - base) of the limb array, where
-// digit d is bits [7 d, 7 d + 7) for 0 <= d < nd and 0 otherwise; then zero[0, zero_len).
-// Four bytes per thread.
+// Balanced base-256 digits.  With bytes b_k of the limb array (4 n of them) and carries
+// c_0 = 0, c_{k+1} = [b_k + c_k >= 128], digit d_k = b_k + c_k - 256 c_{k+1} lies in [-128, 127]
+// and sum_k d_k 256^k = sum_k b_k 256^k, with the top digit d_{4n} = c_{4n}.  A byte 0x7f passes
+// its carry on and any other byte decides it, so the carry into limb q comes from the nearest
+// lower limb that is not 0x7f7f7f7f (zero below limb 0): from a lane of the same wave (ballot),
+// else from a backward search of the limbs below the wave, 64 per round by the whole wave.
+//
+// out[x] for x in [0, len): digit (reversed ? base - x : x - base), 0 outside [0, 4n]; then
+// zero[0, zero_len).  Four bytes (one limb's digits) per thread; the four digits of a thread
+// start at a multiple of 4 (base is 3 mod 4 when reversed, 0 mod 4 otherwise).
+__device__ __forceinline__ bool carry_out_of(uint32_t w) {  // limb not 0x7f7f7f7f: its carry out
+    bool c = false;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const uint32_t b = (w >> (8 * t)) & 0xffu;
+        c = b >= 128u || (b == 127u && c);
+    }
+    return c;
+}
+
 __global__ __launch_bounds__(256) void digitize_kernel(Launch<DigitJob> L) {
     int64_t local;
     const DigitJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const int lane = threadIdx.x & 63;
     const int64_t x0 = (local * 256 + threadIdx.x) * 4;
-    if (x0 >= J.len) {
-        if (x0 - J.len < J.zero_len) *reinterpret_cast<uint32_t *>(J.zero + (x0 - J.len)) = 0u;
-        return;
+    const bool rev = J.reversed != 0;
+    // the limb whose four digits this thread's position holds (lanes take consecutive limbs,
+    // ascending with the lane, or descending when reversed -- also past len, where nothing is
+    // written, so that every lane of a wave stands for its limb in the carry search)
+    const int64_t dlow = rev ? J.base - x0 - 3 : x0 - J.base;  // lowest digit, a multiple of 4
+    const int64_t q = dlow >> 2;
+    const bool real = q >= 0 && q < J.n;
+    const uint32_t w = real ? ldg(J.limbs + q) : 0u;
+    const bool decides = q < 0 || (real && w != 0x7f7f7f7fu);  // below limb 0: carry 0
+    const bool cout = real && carry_out_of(w);
+    const uint64_t dec = __ballot(decides), gen = __ballot(decides && cout);
+    // lanes holding lower limbs than this lane's
+    const uint64_t lower = rev ? (lane == 63 ? 0ull : (~0ull << (lane + 1))) : ((1ull << lane) - 1ull);
+    // carry into the wave's lowest limb: searched below it when some lane needs it
+    const int64_t qmin = rev ? q - (63 - lane) : q - lane;  // lane 63 (reversed) or lane 0 holds it
+    const int64_t wq = __shfl(qmin, 0, 64);
+    bool wave_cin = false;
+    if (__ballot((dec & lower) == 0ull && q >= 0 && q <= J.n) != 0ull) {
+        for (int64_t top = wq - 1; top >= 0; top -= 64) {
+            const int64_t qq = top - lane;  // lane 0 holds the highest limb of the round
+            const bool okq = qq >= 0 && qq < J.n;
+            const uint32_t ww = okq ? ldg(J.limbs + qq) : 0u;
+            const bool d2 = qq < 0 || (okq && ww != 0x7f7f7f7fu);
+            const uint64_t dm = __ballot(d2);
+            if (dm) {
+                const int src = __builtin_ctzll(dm);  // the nearest deciding limb
+                wave_cin = ((__ballot(d2 && okq && carry_out_of(ww)) >> src) & 1ull) != 0ull;
+                break;
+            }
+        }
     }
-    uint32_t word = 0;
+    const uint64_t cand = dec & lower;
+    bool c;
+    if (cand) {
+        const int src = rev ? __builtin_ctzll(cand) : 63 - __builtin_clzll(cand);
+        c = ((gen >> src) & 1ull) != 0ull;
+    } else {
+        c = wave_cin;
+    }
+    uint32_t d[4] = {0u, 0u, 0u, 0u};
+    if (real) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int64_t x = x0 + b;
-        const int64_t d = J.reversed ? J.base - x : x - J.base;
-        uint32_t v = 0;
-        if (d >= 0 && d < J.nd) v = bits_word(J.limbs, J.n, 7 * d) & 0x7fu;
-        word |= v << (8 * b);
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t s = ((w >> (8 * t)) & 0xffu) + (c ? 1u : 0u);
+            c = s >= 128u;
+            d[t] = (s - (c ? 256u : 0u)) & 0xffu;
+        }
+    } else if (q == J.n) {
+        d[0] = c ? 1u : 0u;  // the top carry
     }
-    *reinterpret_cast<uint32_t *>(J.out + x0) = word;
+    if (x0 < J.len) {
+        const uint32_t word = rev ? (d[3] | (d[2] << 8) | (d[1] << 16) | (d[0] << 24))
+                                  : (d[0] | (d[1] << 8) | (d[2] << 16) | (d[3] << 24));
+        *reinterpret_cast<uint32_t *>(J.out + x0) = word;
+    } else if (x0 - J.len < J.zero_len) {
+        *reinterpret_cast<uint32_t *>(J.zero + (x0 - J.len)) = 0u;
+    }
 }
 
 // ---- products ----------------------------------------------------------------------------------
@@ -181,22 +244,23 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const uint32_t v = (uint32_t)acc[rt][i];
-            if (v) atomicAdd(&D[32 * (32 * rt + 8 * (i >> 2) + 4 * g + (i & 3)) + m], (unsigned long long)v);
+            const int v = acc[rt][i];  // signed digit sums, added in two's complement
+            if (v) atomicAdd(&D[32 * (32 * rt + 8 * (i >> 2) + 4 * g + (i & 3)) + m],
+                             (unsigned long long)(long long)v);
         }
     __syncthreads();
 
-    // limb column j of the block takes the digits k with 7 k in [32 j, 32 j + 32):
-    // D[k] 2^(7k - 32j) split as x (low 32 bits, weight 2^0) + y (weight 2^32)
+    // limb column j of the block takes the digits k = 4 j .. 4 j + 3: the signed value
+    // D[k] 2^(8 (k - 4 j)) split as x (its low 32 bits, weight 2^0, non-negative) + y (the rest,
+    // weight 2^32, signed, added in two's complement)
     unsigned long long *out = J.cols + 2 * grp * MFMA_LIMBS;
     for (int j = tid; j < MFMA_LIMBS; j += MFMA_TPB) {
-        const int k0 = (32 * j + 6) / 7, k1 = (32 * j + 31) / 7;
         unsigned long long x = 0, y = 0;
-        for (int k = k0; k <= k1; ++k) {
-            const unsigned long long v = D[k];
-            const int s = 7 * k - 32 * j;
-            x += (unsigned long long)((uint32_t)v << s);
-            y += s ? (v >> (32 - s)) : (v >> 32);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const long long v = (long long)D[4 * j + t] * (1ll << (8 * t));
+            x += (unsigned long long)(uint32_t)v;
+            y += (unsigned long long)(v >> 32);
         }
         if (x) __hip_atomic_fetch_add(out + 2 * j, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (y) __hip_atomic_fetch_add(out + 2 * j + 1, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -63,8 +63,9 @@ struct TermSigns {
 
 // v[m] += sign * (column j0 - 2 + m of the product), m in [0, NV).  Column sums come as
 // three uint32 pieces per column (value j gets piece 0 of j, 1 of j-1, 2 of j-2) or as two
-// uint64 per column, i.e. four uint32 words (value j gets word 0 of j, words 1 and 2 of j-1,
-// word 3 of j-2).
+// uint64 per column, x + y 2^32 with x non-negative and y signed (the matrix cores' balanced
+// digits give signed partial sums), i.e. four uint32 words (value j gets word 0 of j, words 1
+// and 2 of j-1, word 3 of j-2 read as a signed 32-bit value).
 template <int P>
 __device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int64_t (&acc)[NV]) {
     const int64_t c0 = j0 - 4;
@@ -83,7 +84,7 @@ __device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int
             acc[m] = (int64_t)x[3 * w] + (int64_t)x[3 * (w - 1) + 1] + (int64_t)x[3 * (w - 2) + 2];
         else
             acc[m] = (int64_t)x[4 * w] + (int64_t)x[4 * (w - 1) + 1] + (int64_t)x[4 * (w - 1) + 2] +
-                     (int64_t)x[4 * (w - 2) + 3];
+                     (int64_t)(int32_t)x[4 * (w - 2) + 3];  // y is signed (balanced digits)
     }
 }
 

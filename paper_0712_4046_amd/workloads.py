@@ -116,6 +116,26 @@ def config4_modulus(seed: int = 4) -> int:
     return (1 << 59) + 2 * int(gen.integers(0, 1 << 58, dtype=np.uint64)) + 1
 
 
+# The paper's example timings (its Section 4, Figures 1-2): (Z/nZ)[x] with a random 4-bit and a
+# random 48-bit modulus n, across degrees.  The modular entry point takes odd moduli, so n is a
+# random odd number of the stated bit length.
+PAPER_FIG_BITS = (4, 48)
+PAPER_FIG_LENGTHS = tuple(4 ** k for k in range(1, 9))  # 4 .. 65536
+
+
+def paper_fig_modulus(bits: int, seed: int = 6) -> int:
+    """Random odd n with exactly `bits` bits: 2^(bits-1) + 2 U[0, 2^(bits-2)) + 1."""
+    gen = rng(seed + bits)
+    return (1 << (bits - 1)) + 2 * int(gen.integers(0, 1 << (bits - 2), dtype=np.uint64)) + 1
+
+
+def paper_fig_pair(bits: int, length: int, seed: int = 6):
+    """(n, f, g): residues uniform in [0, n), f and g of the given length."""
+    n = paper_fig_modulus(bits, seed)
+    gen = rng(seed * 1000 + bits * 100 + length)
+    return n, gen.integers(0, n, size=length, dtype=np.uint64), gen.integers(0, n, size=length, dtype=np.uint64)
+
+
 def config4(count: int = 64, length: int = 65536, seed: int = 4):
     """Modular batch: `count` products in (Z/pZ)[x], f, g uniform in [0, p), length 65536."""
     gen = rng(seed)

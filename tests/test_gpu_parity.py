@@ -163,6 +163,31 @@ def test_mod_config4_one_product_sampled(torch_dev, oracle):
         assert np.array_equal(got, exp), (v, e)
 
 
+@pytest.mark.parametrize("nbits", [4, 48])
+def test_mod_paper_moduli(torch_dev, oracle, nbits):
+    # the moduli and lengths of the paper's example timings (random odd 4-bit and 48-bit n):
+    # every variant against the oracle, in full up to L = 4096, sampled at L = 65536
+    torch = torch_dev
+    for L in wl.PAPER_FIG_LENGTHS:
+        n, f, g = wl.paper_fig_pair(nbits, L)
+        tf = torch.from_numpy(f.view(np.int64)).cuda()
+        tg = torch.from_numpy(g.view(np.int64)).cuda()
+        if L <= 4096:
+            idx = None
+            exp = oracle.mul_mod(f, g, n)
+        elif L == 65536:
+            D = 2 * L - 1
+            idx = np.unique(np.concatenate([np.arange(0, 30), np.arange(D - 30, D), wl.rng(L).integers(0, D, 200)]))
+            exp = oracle.coeffs_mod(f, g, n, idx)
+        else:
+            continue
+        for v in VARIANTS:
+            h = ks.mul_mod(tf, tg, n, v)
+            assert ks.status() == ks.KS_OK
+            got = h.cpu().numpy().view(np.uint64)
+            assert np.array_equal(got if idx is None else got[idx], exp), (nbits, L, v)
+
+
 def test_invalid_arguments(torch_dev):
     torch = torch_dev
     t = torch.zeros((4, 1), dtype=torch.int32, device="cuda")
@@ -201,6 +226,23 @@ def test_mfma_part_splits(torch_dev, oracle, monkeypatch, blocks, min_part):
     exp = want(oracle, P.f, P.g, P.bits, P.signed)
     for v in VARIANTS:
         assert_same(gpu_mul(P.f, P.g, P.bits, v, P.signed, "mfma"), exp, f"config2 {v} blocks={blocks} part>={min_part}")
+
+
+@pytest.mark.parametrize("pattern", [0x7F, 0x80, 0xFF])
+@pytest.mark.parametrize("L", [1, 7, 300])
+def test_mfma_balanced_digit_carries(torch_dev, oracle, pattern, L):
+    # the matrix-core digits are balanced base-256 digits, whose carries run through every
+    # byte 0x7f: coefficients of 0x7f bytes over a low byte `pattern` (0x80 and 0xff start a
+    # carry that must cross the whole run, within a wave's limbs and across waves)
+    bits = 256
+    w = bits // 32
+    one = np.full((L, w), 0x7F7F7F7F, dtype=np.uint32)
+    one[:, 0] = (one[:, 0] & np.uint32(0xFFFFFF00)) | np.uint32(pattern)
+    other = np.full((L, w), 0x7F7F7F7F, dtype=np.uint32)
+    for f, g in ((one, other), (one, one)):
+        exp = want(oracle, f, g, bits, False)
+        for v in VARIANTS:
+            assert_same(gpu_mul(f, g, bits, v, False, "mfma"), exp, f"0x7f runs over {pattern:#x} L={L} {v}")
 
 
 @pytest.mark.parametrize("variant", ["ks1", "neg2"])
