@@ -143,7 +143,13 @@ int plan_product(const Spec &sp, Geom &G) {
         m.nA32 = cdiv(m.nad, 32);
         m.nB32 = cdiv(m.nbd + 31, 32);
         int eng = sp.engine;
-        if (eng == 0) eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", 6000) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
+        // the matrix cores cost a digit launch more: a single product needs larger operands to
+        // gain (C2's four-point products of 4481 limbs: 0.054 ms on the vector ALU, 0.060 on
+        // the matrix cores); a batch shares that launch among its products (10,000-product
+        // batch, standard KS: 2.61 ms at 6000 limbs, 2.18 ms at 2500)
+        if (eng == 0)
+            eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 2500 : 6000) ? KS_ENGINE_MFMA
+                                                                                          : KS_ENGINE_VALU;
         m.engine = eng;
         if (eng == KS_ENGINE_MFMA) {
             const int64_t rows = cdiv(m.nad + m.nbd - 1, 32);
@@ -381,7 +387,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
                 d.base = side ? m.b_top : m.a_front;
                 d.reversed = side;
                 d.zero = reinterpret_cast<uint8_t *>(cols(m.cols_off));
-                d.zero_len = side ? 0 : 16 * m.ncols;
+                d.zero_len = (side || m.splits == 1) ? 0 : 16 * m.ncols;  // cleared for atomics only
                 d.block0 = next_block(JL.digit);
                 d.nblocks = cdiv(d.len + d.zero_len, 1024);
                 JL.digit.push_back(d);

@@ -26,7 +26,8 @@
 // dword per lane, spread by lane shuffles and realigned with v_alignbyte) straight from global
 // memory, PF steps ahead, and issues MFMA_RT matrix operations.  At the end the waves add
 // their digit sums into LDS, the block turns them into limb columns and adds those into the
-// product's column buffer with 64-bit atomics, so any number of parts may share a row group.
+// product's column buffer with 64-bit atomics, so any number of parts may share a row group
+// (a row group of one part stores its columns instead, into a buffer nobody clears).
 #include "ks_device.h"
 #include "ks_launch.h"
 
@@ -262,8 +263,13 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
             x += (unsigned long long)(uint32_t)v;
             y += (unsigned long long)(v >> 32);
         }
-        if (x) __hip_atomic_fetch_add(out + 2 * j, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (y) __hip_atomic_fetch_add(out + 2 * j + 1, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (J.splits == 1) {  // the only block of its columns: plain stores, nothing cleared before
+            out[2 * j] = x;
+            out[2 * j + 1] = y;
+        } else {
+            if (x) __hip_atomic_fetch_add(out + 2 * j, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (y) __hip_atomic_fetch_add(out + 2 * j + 1, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
