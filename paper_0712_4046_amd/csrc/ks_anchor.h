@@ -14,8 +14,7 @@ namespace ks {
 // exact modulo 2^(32 AW), which holds the anchor.
 template <int W>
 __device__ __forceinline__ void load_raw(const uint32_t *c, uint32_t (&m)[W]) {
-#pragma unroll
-    for (int t = 0; t < W; ++t) m[t] = ldg(c + t);
+    ldg_words<W>(c, m);
 }
 
 // acc (n words, mod 2^(32 n)) += v 2^(32 off), v given as words v[0..nv)

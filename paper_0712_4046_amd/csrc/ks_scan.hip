@@ -70,12 +70,14 @@ template <int P>
 __device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int64_t (&acc)[NV]) {
     const int64_t c0 = j0 - 4;
     uint32_t x[P * NWIN];
+    // one vector load per column (clamped address, zeroed outside the product)
 #pragma unroll
-    for (int t = 0; t < P * NWIN; ++t) {
-        const int64_t col = c0 + t / P;
+    for (int w = 0; w < NWIN; ++w) {
+        const int64_t col = c0 + w;
         const bool ok = col >= 0 && col < T.ncols;
-        x[t] = T.cols[ok ? P * c0 + t : 0];
-        x[t] = ok ? x[t] : 0u;
+        ldg_words<P>(T.cols + P * (ok ? col : 0), x + P * w);
+#pragma unroll
+        for (int t = 0; t < P; ++t) x[P * w + t] = ok ? x[P * w + t] : 0u;
     }
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
