@@ -53,17 +53,26 @@ __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, cons
     constexpr int U = 4;  // coefficients per thread per round, loads issued together
     for (int64_t ib = i0 + tid; ib <= i1; ib += U * TPB) {
         uint32_t cl[U][PK_MAXW];
+        const uint32_t *cq[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int64_t i = ib + (int64_t)q * TPB;
             const int64_t ii = i <= i1 ? i : i0;
             const int64_t src = (J.flags & PK_REVERSE) ? J.L - 1 - ii : ii;
-            const uint32_t *c = J.coeffs + src * w_in;
+            cq[q] = J.coeffs + src * w_in;
 #pragma unroll
-            for (int t = 0; t < PK_MAXW; ++t) {
-                const uint32_t x = c[t < w_in ? t : w_in - 1];
-                cl[q][t] = t < w_in ? x : 0u;
-            }
+            for (int t = 0; t < PK_MAXW; ++t) cl[q][t] = 0u;
+        }
+        // the round's coefficients with vector loads of exactly w_in words each, all in one
+        // block (w_in is uniform: one scalar branch per round)
+        switch (w_in) {
+#define PK_LOAD(W)                                                              \
+    case W:                                                                     \
+        _Pragma("unroll") for (int q = 0; q < U; ++q) ldg_words<W>(cq[q], cl[q]); \
+        break;
+            PK_LOAD(1) PK_LOAD(2) PK_LOAD(3) PK_LOAD(4) PK_LOAD(5) PK_LOAD(6) PK_LOAD(7) PK_LOAD(8)
+#undef PK_LOAD
+            default: break;
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
