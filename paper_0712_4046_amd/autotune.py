@@ -5,7 +5,10 @@
 
 For one workload it times the whole run (HIP events on the stream the library launches on,
 median of a few runs after warm-up) for candidate values of each tunable in turn -- a
-coordinate descent, repeated while it still improves -- keeps the fastest value of each, and
+coordinate descent, repeated while it still improves.  Each candidate is timed next to the
+current best, re-timed right before it, and kept only if it beats that pair partner: a GPU
+whose clocks drift over a long sweep (power or heat) then cannot pass drift off as a gain.
+It keeps the fastest value of each tunable, and
 writes them as JSON together with the default and tuned times; `ks.apply_tuning(table)` sets
 them for later plans.  The shapes change only how work
 is cut into launches and blocks, never the result: tests/test_gpu_autotune.py checks a tuned
@@ -104,16 +107,19 @@ def tune(make, candidates=None, max_passes: int = 2, warmup: int = 2, reps: int 
             for v in values:
                 if v == best[name]:
                     continue
+                ks.tune_set(name, best[name])
+                ref = time_ms(make(), warmup, reps)  # the current best, timed just before
                 ks.tune_set(name, v)
                 ms = time_ms(make(), warmup, reps)
                 if log:
-                    log(f"{name}={v}: {ms:.4f} ms (best {best_ms:.4f})")
-                if ms < best_ms * 0.995:
+                    log(f"{name}={v}: {ms:.4f} ms (best {ref:.4f} now)")
+                if ms < ref * 0.995:
                     best_ms, best[name], improved = ms, v, True
                 ks.tune_set(name, best[name])
         if not improved:
             break
-    return {"tunables": best, "ms": best_ms, "default_ms": base}
+    final = time_ms(make(), warmup, reps)  # every tunable is at its best value here
+    return {"tunables": best, "ms": final, "default_ms": base}
 
 
 def main(argv=None):
