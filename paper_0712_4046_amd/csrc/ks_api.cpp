@@ -70,16 +70,42 @@ static int64_t slot_bits(int variant, int b, int e) {
     return 0;
 }
 
-// Simple cost model for KS_VARIANT_AUTO: schoolbook limb products plus a per-limb overhead.
-static int auto_variant(int64_t lf, int64_t lg, int b, int e) {
+// Time model for KS_VARIANT_AUTO (microseconds on one MI355X, fitted to single-product
+// measurements): the products on the engine the planner will pick -- vector ALU 0.21 fs per
+// limb product above a 5 us floor, matrix cores 0.69 fs per int8 operation on balanced digits
+// above a 14 us floor -- plus 0.15 ns per operand limb for the linear stages, 0.2 ns per
+// coefficient for KS4's reconstruction, and 4.5 us per launch (KS4 has one more; the matrix
+// cores add the digit launch).  A batch shares its launches, so there only the rates count.
+// It picks NEG2 for the L = 4096 signed 64-bit product (measured 0.047 ms, against 0.050 for
+// KS1 and 0.053 for KS4), KS4 for L = 65536 at 48 bits (0.54 ms, against 0.72 and 1.27), and
+// KS1 or NEG2 for short products, where every variant is launch-bound.
+static int auto_variant(int64_t lf, int64_t lg, int b, int e, bool batch, int engine) {
     double best = 1e300;
     int pick = KS_VARIANT_KS1;
     for (int v : {KS_VARIANT_KS1, KS_VARIANT_NEG2, KS_VARIANT_KS4}) {
-        int64_t N = slot_bits(v, b, e);
-        int k = v == KS_VARIANT_KS1 ? 1 : (v == KS_VARIANT_NEG2 ? 2 : 4);
-        double na = (double)cdiv(N * (lf - 1) + b + 2, 32), nb = (double)cdiv(N * (lg - 1) + b + 2, 32);
-        double cost = k * na * nb + 64.0 * k * (na + nb) + (v == KS_VARIANT_KS4 ? 2048.0 * (lf + lg) : 0.0);
-        if (cost < best) { best = cost; pick = v; }
+        const int64_t N = slot_bits(v, b, e);
+        const int k = v == KS_VARIANT_KS1 ? 1 : (v == KS_VARIANT_NEG2 ? 2 : 4);
+        const double na = (double)cdiv(N * (lf - 1) + b + 2, 32), nb = (double)cdiv(N * (lg - 1) + b + 2, 32);
+        int eng = engine;
+        if (eng == 0)
+            eng = std::min(na, nb) >= env_int("KS_MFMA_MIN_LIMBS", batch ? 2500 : 6000) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
+        double us = 0;
+        int launches = 4;  // pack, multiply, recombine, extract
+        if (eng == KS_ENGINE_MFMA) {
+            us += k * 2.0 * (4 * na + 1) * (4 * nb + 1) * 6.9e-10;
+            launches += 1;  // digits
+            if (!batch) us += 14.0;
+        } else {
+            us += k * na * nb * 2.1e-7;
+            if (!batch) us += 5.0;
+        }
+        if (v == KS_VARIANT_KS4) {
+            launches += 1;  // reconstruction chain and its finishing pass in place of extraction
+            us += 2e-4 * (double)(lf + lg);
+        }
+        us += 1.5e-4 * k * (na + nb);
+        if (!batch) us += 4.5 * launches;
+        if (us < best) { best = us; pick = v; }
     }
     return pick;
 }
@@ -96,7 +122,7 @@ int plan_product(const Spec &sp, Geom &G) {
     G.w_out = (int)cdiv(2 * (int64_t)b + G.e + 1, 32);
     G.off = sp.sgn ? 2 * b - 2 + G.e : -1;
     int v = sp.variant;
-    if (v == KS_VARIANT_AUTO) v = auto_variant(lf, lg, b, G.e);
+    if (v == KS_VARIANT_AUTO) v = auto_variant(lf, lg, b, G.e, sp.batch, sp.engine);
     if (v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_RECIP2 && v != KS_VARIANT_KS4)
         return KS_EINVAL;
     G.variant = v;
@@ -630,7 +656,7 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
     emit_jobs(G, reinterpret_cast<uintptr_t>(f), reinterpret_cast<uintptr_t>(g), reinterpret_cast<uintptr_t>(h),
               reinterpret_cast<uintptr_t>(ws), JL);
     LaunchEnv env;
-    env.status = reinterpret_cast<uint64_t *>(ws + G.ws_status);
+    env.status = ctl.status;
     env.ctr_pack = ctl.ctrs;
     env.ctr_norm = ctl.ctrs + CTL_CTRS;
     env.devstat = ctl.devstat;
@@ -649,7 +675,7 @@ struct Pool {
 static std::mutex g_pool_mu;
 static std::map<hipStream_t, Pool *> g_pools;
 
-static int get_pool(hipStream_t s, size_t need, Pool **out) {
+static int get_pool(hipStream_t s, size_t need, int64_t status_words, Pool **out) {
     Pool *p;
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -679,9 +705,23 @@ static int get_pool(hipStream_t s, size_t need, Pool **out) {
         size_t want = std::max<size_t>(need, (size_t)1 << 20);
         void *w = nullptr;
         if (hipMalloc(&w, want) != hipSuccess) return KS_ENOMEM;
-        if (hipMemsetAsync(w, 0, want, s) != hipSuccess) return KS_EHIP;  // status words start at epoch 0
+        if (hipMemsetAsync(w, 0, want, s) != hipSuccess) return KS_EHIP;
         p->ws = reinterpret_cast<char *>(w);
         p->bytes = want;
+    }
+    if (p->ctl.status_words < status_words) {
+        if (p->ctl.status) {
+            if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;
+            hipFree(p->ctl.status);
+            p->ctl.status = nullptr;
+            p->ctl.status_words = 0;
+        }
+        const int64_t want = std::max<int64_t>(status_words, 4096);
+        void *w = nullptr;
+        if (hipMalloc(&w, (size_t)want * 8) != hipSuccess) return KS_ENOMEM;
+        if (hipMemsetAsync(w, 0, (size_t)want * 8, s) != hipSuccess) return KS_EHIP;  // epoch 0: never fresh
+        p->ctl.status = reinterpret_cast<uint64_t *>(w);
+        p->ctl.status_words = want;
     }
     *out = p;
     return KS_OK;
@@ -799,7 +839,9 @@ static int mul_common(const uint32_t *f, const uint32_t *g, const Spec &sp, void
     if (rc != KS_OK) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Pool *p = nullptr;
-    rc = get_pool(s, (size_t)G.ws_bytes, &p);
+    // the scratch regions end where the status words would start; those live in the pool's
+    // own status buffer
+    rc = get_pool(s, (size_t)G.ws_status, std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1), &p);
     if (rc != KS_OK) return rc;
     return run_product(G, f, g, h, p->ws, p->ctl, s);
 }

@@ -147,6 +147,10 @@ __device__ __forceinline__ int lb_resolve(uint64_t *st, int64_t blk, uint32_t ep
             break;
         }
         top -= 64;
+        if (top < 0) {  // every block down to block 0 composed: block 0's carry in is 0
+            carry = cmap_apply(acc, 0);
+            break;
+        }
     }
     if (lane == 0) lb_publish(st + blk, epoch, LB_INC, (uint32_t)(cmap_apply(agg, carry) + 1));
     return carry;

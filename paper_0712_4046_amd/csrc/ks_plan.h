@@ -91,10 +91,18 @@ struct Geom {
 // device words that outlive one call: block-ticket counters (pack jobs, then normalize jobs),
 // error bits, launch epoch
 constexpr int CTL_CTRS = 8;  // counters per stage (a product has at most 8 pack and 4 normalize jobs)
+// A stream's control words: block-ticket counters, the device status word, the launch epoch,
+// and the look-back status words of its single products -- a buffer of their own that holds
+// nothing but status words (cleared when allocated), so a word a launch reads is either zero or
+// was published by a launch of this stream with an older epoch.  (Kept in the products' scratch,
+// whose layout differs from product to product, a status word could overlie data an earlier
+// product left there and read as a fresh status.)
 struct Ctl {
     uint64_t *ctrs = nullptr;
     uint32_t *devstat = nullptr;
     uint32_t epoch = 0;
+    uint64_t *status = nullptr;
+    int64_t status_words = 0;
 };
 
 // jobs of one or many products, per stage (anchor and chain lists keyed by template parameter)

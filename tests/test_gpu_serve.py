@@ -42,3 +42,20 @@ def test_small_memory_budget_queues(torch_dev):
     st = srv.run(reqs)
     assert st.completed == len(reqs)
     assert st.max_inflight == 1
+
+
+def test_large_mix_equals_alone(torch_dev):
+    # long products of every size on four streams, each stream's scratch reused by products of
+    # different layouts: every result equals the same product computed alone (regression: the
+    # look-back status words of a product once lived in that reused scratch, where data of an
+    # earlier product could read as a fresh status word)
+    reqs = serve.make_requests(1100, rate_per_s=0.0, seed=5, max_len=65536, max_bits=256)
+    srv = serve.Server(slots=16, streams=4)
+    srv.warm(reqs)
+    st = srv.run(reqs)
+    assert st.completed == len(reqs)
+    for d in st.results:
+        r = reqs[d.idx]
+        alone = ks.mul(ks.to_device(r.f), ks.to_device(r.g), r.bits, "auto", True)
+        ks.check()
+        assert torch_dev.equal(d.out, alone), d.idx
