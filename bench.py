@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # and for the 64-product modular batch (profiles/config4_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
-MEASURED_TRAFFIC = {"pack": 993854, "mul_valu": 1656019, "normalize": 1270627, "recon": 692732, "finish": 436589}
-MEASURED_TRAFFIC_CONFIG4 = {"pack": 3141546908, "digitize": 950001456, "mul_mfma": 2530343907,
-                            "normalize": 1163794051, "recon": 349274099, "finish": 271331745}
+MEASURED_TRAFFIC = {"pack": 996237, "mul_valu": 1656022, "normalize": 1209596, "recon": 757849, "finish": 441709}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 3110842364, "digitize": 344519850, "mul_mfma": 1777036942,
+                            "normalize": 1058233862, "recon": 348996550, "finish": 271313638}
 KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract")
 
 
