@@ -222,7 +222,7 @@ int ks_profile_reset(void);
  * a value set here overrides the environment variable of the same name, which overrides the
  * built-in default.  Names and defaults:
  *   "KS_MFMA_MIN_LIMBS"  6000  both operands at least this many limbs -> matrix-core engine
- *                              (unset, the products of a batch use 2500)
+ *                              (unset, the products of a batch use 1000)
  *   "KS_MFMA_BLOCKS"     1024  matrix-core launch target of one product, in blocks (unset, a
  *                              batch of n products gives each max(1, 2048 / n); set, each
  *                              product of a batch aims at the value)

@@ -88,7 +88,7 @@ static int auto_variant(int64_t lf, int64_t lg, int b, int e, bool batch, int en
         const double na = (double)cdiv(N * (lf - 1) + b + 2, 32), nb = (double)cdiv(N * (lg - 1) + b + 2, 32);
         int eng = engine;
         if (eng == 0)
-            eng = std::min(na, nb) >= env_int("KS_MFMA_MIN_LIMBS", batch ? 2500 : 6000) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
+            eng = std::min(na, nb) >= env_int("KS_MFMA_MIN_LIMBS", batch ? 1000 : 6000) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
         double us = 0;
         int launches = 4;  // pack, multiply, recombine, extract
         if (eng == KS_ENGINE_MFMA) {
@@ -172,9 +172,10 @@ int plan_product(const Spec &sp, Geom &G) {
         // the matrix cores cost a digit launch more: a single product needs larger operands to
         // gain (C2's four-point products of 4481 limbs: 0.054 ms on the vector ALU, 0.060 on
         // the matrix cores); a batch shares that launch among its products (10,000-product
-        // batch, standard KS: 2.61 ms at 6000 limbs, 2.18 ms at 2500)
+        // batch: standard KS 1.95 ms at 2500 limbs, 1.77-1.81 ms at 800-1200; four-point 2.02
+        // and 1.91 ms)
         if (eng == 0)
-            eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 2500 : 6000) ? KS_ENGINE_MFMA
+            eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 1000 : 6000) ? KS_ENGINE_MFMA
                                                                                           : KS_ENGINE_VALU;
         m.engine = eng;
         if (eng == KS_ENGINE_MFMA) {
