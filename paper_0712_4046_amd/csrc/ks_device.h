@@ -260,6 +260,35 @@ __device__ __forceinline__ void ldg_words(const uint32_t *p, uint32_t *o) {
     }
 }
 
+// N consecutive words stored through the widest global vector stores (dword alignment)
+template <int N>
+__device__ __forceinline__ void stg_words(uint32_t *p, const uint32_t *v) {
+    int t = 0;
+#pragma unroll
+    for (; t + 4 <= N; t += 4) {
+        u32x4 x;
+        x.x = v[t];
+        x.y = v[t + 1];
+        x.z = v[t + 2];
+        x.w = v[t + 3];
+        *(__attribute__((address_space(1))) u32x4 *)(p + t) = x;
+    }
+    if constexpr (N % 4 == 3) {
+        u32x3 x;
+        x.x = v[t];
+        x.y = v[t + 1];
+        x.z = v[t + 2];
+        *(__attribute__((address_space(1))) u32x3 *)(p + t) = x;
+    } else if constexpr (N % 4 == 2) {
+        u32x2 x;
+        x.x = v[t];
+        x.y = v[t + 1];
+        *(__attribute__((address_space(1))) u32x2 *)(p + t) = x;
+    } else if constexpr (N % 4 == 1) {
+        *(__attribute__((address_space(1))) uint32_t *)(p + t) = v[t];
+    }
+}
+
 template <class T>
 __device__ __forceinline__ void stg(T *p, T v) {
     *(__attribute__((address_space(1))) T *)p = v;

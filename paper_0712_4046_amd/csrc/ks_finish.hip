@@ -128,6 +128,10 @@ struct RawDigit {
 template <int NW>
 __device__ __forceinline__ void load_raw(RawDigit<NW> &r, const uint32_t *x, int64_t n, int64_t bit0) {
     const int64_t q = bit0 >> 5;
+    if (q >= 0 && q + NW < n) {  // the usual case: one vector load (lanes of a wave read far apart)
+        ldg_words<NW + 1>(x + q, r.l);
+        return;
+    }
 #pragma unroll
     for (int t = 0; t <= NW; ++t) {
         const bool ok = q + t >= 0 && q + t < n;
@@ -303,13 +307,14 @@ __device__ __forceinline__ void chain_seg(const ChainJob &J, int64_t s, uint32_t
         sigma = add_bit(beta, delta);                // sigma_c = beta_c + delta
         aprev = alpha;
         wc = wn;
-        // alpha_c and beta_c for the finishing pass
-        uint32_t *hb = J.hbuf + c * (2 * NW);
+        // alpha_c and beta_c for the finishing pass, one vector store
+        uint32_t ab[2 * NW];
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
-            stg(hb + t, alpha.w[t]);
-            stg(hb + NW + t, beta.w[t]);
+            ab[t] = alpha.w[t];
+            ab[NW + t] = beta.w[t];
         }
+        stg_words<2 * NW>(J.hbuf + c * (2 * NW), ab);
     };
 #pragma unroll
     for (int j = 0; j < P; ++j) fetch(j, k0 + j);
@@ -357,21 +362,21 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_lanes_kernel(Launch<ChainJob>
     if (g >= L.total_blocks) return;
     int64_t s;
     const ChainJob J = get_job(L, g, s);
-    if (NW > 0) {
+    if constexpr (NW > 0) {
         chain_seg<NW, true>(J, s, L.devstat);
-        return;
-    }
-    switch ((J.Nd + 31) >> 5) {
-        case 1: chain_seg<1, true>(J, s, L.devstat); break;
-        case 2: chain_seg<2, true>(J, s, L.devstat); break;
-        case 3: chain_seg<3, true>(J, s, L.devstat); break;
-        case 4: chain_seg<4, true>(J, s, L.devstat); break;
-        case 5: chain_seg<5, true>(J, s, L.devstat); break;
-        case 6: chain_seg<6, true>(J, s, L.devstat); break;
-        case 7: chain_seg<7, true>(J, s, L.devstat); break;
-        case 8: chain_seg<8, true>(J, s, L.devstat); break;
-        case 9: chain_seg<9, true>(J, s, L.devstat); break;
-        default: break;
+    } else {
+        switch ((J.Nd + 31) >> 5) {
+            case 1: chain_seg<1, true>(J, s, L.devstat); break;
+            case 2: chain_seg<2, true>(J, s, L.devstat); break;
+            case 3: chain_seg<3, true>(J, s, L.devstat); break;
+            case 4: chain_seg<4, true>(J, s, L.devstat); break;
+            case 5: chain_seg<5, true>(J, s, L.devstat); break;
+            case 6: chain_seg<6, true>(J, s, L.devstat); break;
+            case 7: chain_seg<7, true>(J, s, L.devstat); break;
+            case 8: chain_seg<8, true>(J, s, L.devstat); break;
+            case 9: chain_seg<9, true>(J, s, L.devstat); break;
+            default: break;
+        }
     }
 }
 
@@ -384,11 +389,12 @@ __device__ __forceinline__ void finish_block(const ChainJob &J, int64_t local) {
     if (c >= J.m) return;
     const int Nd = J.Nd;
     MW<NW> alpha, beta;
-    const uint32_t *hb = J.hbuf + c * (2 * NW);
+    uint32_t ab[2 * NW];
+    ldg_words<2 * NW>(J.hbuf + c * (2 * NW), ab);
 #pragma unroll
     for (int t = 0; t < NW; ++t) {
-        alpha.w[t] = ldg(hb + t);
-        beta.w[t] = ldg(hb + NW + t);
+        alpha.w[t] = ab[t];
+        beta.w[t] = ab[NW + t];
     }
     uint32_t H[2 * NW + 1];
     hprime(alpha, beta, Nd, H);
