@@ -223,10 +223,13 @@ int ks_profile_reset(void);
  * built-in default.  Names and defaults:
  *   "KS_MFMA_MIN_LIMBS"  6000  both operands at least this many limbs -> matrix-core engine
  *                              (unset, the products of a batch use 1000)
- *   "KS_MFMA_BLOCKS"     1024  matrix-core launch target of one product, in blocks (unset, a
- *                              batch of n products gives each max(1, 2048 / n); set, each
- *                              product of a batch aims at the value)
- *   "KS_MFMA_MIN_PART"   128   shortest part (block shifts) the matrix-core planner cuts
+ *   "KS_MFMA_BLOCKS"     0     matrix-core launch target of one product, in blocks; 0: the
+ *                              launch shape of least modelled time (unset, a batch of n
+ *                              products gives each max(1, 2048 / n); set, each product of a
+ *                              batch aims at the value)
+ *   "KS_MFMA_MIN_PART"   128   fewest block shifts the matrix-core planner gives one block
+ *   "KS_MFMA_BLOCK_COST" 10    fixed cost of a matrix-core block in the launch-shape model, in
+ *                              steps (MFMA_RT matrix operations of every wave)
  *   "KS_CHAIN_K"         model reconstruction segment length (0 or unset: the cost model)
  *   "KS_MUL_WAVE_MAX"    1024  vector-ALU products whose shorter operand has at most this many
  *                              limbs run one wave per 128-column tile (else a block per tile)

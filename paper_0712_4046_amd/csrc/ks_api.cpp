@@ -37,8 +37,9 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
 
 // planner tunables: a value set through ks_tune_set, else the environment, else the default
-static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_CHAIN_K",
-                                         "KS_MUL_WAVE_MAX",   "KS_SCAN_SMALL"};
+static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS",  "KS_MFMA_MIN_PART",
+                                         "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",     "KS_MUL_WAVE_MAX",
+                                         "KS_SCAN_SMALL"};
 static std::mutex g_tune_mu;
 static std::map<std::string, int64_t> g_tune;
 
@@ -59,6 +60,47 @@ static int env_int(const char *name, int dflt) {
 }
 
 // ---- planning -----------------------------------------------------------------------------------
+
+// Launch shape of the matrix-core products: parts per row group (splits) and residue groups
+// per part (rgroups) for `units` row groups of at most tmax block shifts each.  Every block
+// covers at least min_part shifts (unless one part per residue group is already shorter).
+// target > 0: aim at about `target` blocks, cutting the residues first (a wave's shifts then
+// form fewer, longer chains) and the shift range after.  target = 0: the shape of least
+// modelled time, the blocks running one per compute unit in rounds of MFMA_CUS, each taking
+// a fixed cost (start, LDS and column sums: KS_MFMA_BLOCK_COST steps), the start-up of each
+// residue class of a wave (its first loads: about MFMA_CLASS_COST steps) and its steps (a
+// step: MFMA_RT matrix operations of each wave).
+static constexpr int64_t MFMA_CUS = 256, MFMA_CLASS_COST = 3;
+static void mfma_shape(int64_t tmax, int64_t units, int64_t target, int64_t min_part, int64_t &splits,
+                       int64_t &rgroups) {
+    min_part = std::max<int64_t>(1, min_part);
+    auto s_min = [&](int64_t rg) { return cdiv(tmax, mfma_max_part(rg)); };
+    if (target > 0) {
+        const int64_t d = cdiv(target, units);
+        rgroups = d >= 4 ? 4 : d >= 2 ? 2 : 1;
+        const int64_t s_cap = std::max<int64_t>(1, tmax / (rgroups * min_part));
+        splits = std::max(s_min(rgroups), std::min(cdiv(d, rgroups), s_cap));
+        return;
+    }
+    const int64_t c0 = env_int("KS_MFMA_BLOCK_COST", 10);
+    double best = 0;
+    splits = s_min(1);
+    rgroups = 1;
+    for (int64_t rg = 1; rg <= 4; rg *= 2) {
+        const int64_t cpw = MFMA_CLASSES / rg;
+        for (int64_t s = s_min(rg); s <= std::max(s_min(rg), cdiv(4 * MFMA_CUS, units * rg)); ++s) {
+            const int64_t part = cdiv(tmax, s);
+            const int64_t steps = cpw * cdiv(part, 32);  // per wave
+            if (s > s_min(rg) && part < rg * min_part) break;
+            const double t = (double)cdiv(units * rg * s, MFMA_CUS) * (double)(c0 + cpw * MFMA_CLASS_COST + steps);
+            if (best == 0 || t < best) {
+                best = t;
+                splits = s;
+                rgroups = rg;
+            }
+        }
+    }
+}
 
 static int64_t slot_bits(int variant, int b, int e) {
     switch (variant) {
@@ -181,16 +223,14 @@ int plan_product(const Spec &sp, Geom &G) {
         if (eng == KS_ENGINE_MFMA) {
             const int64_t rows = cdiv(m.nad + m.nbd - 1, 32);
             m.groups = cdiv(rows, MFMA_ROWS);
-            // the longest shift range of a row group, cut into parts: at most MFMA_MAX_PART
-            // shifts each (int32 accumulators), enough parts to give the launch about
-            // KS_MFMA_BLOCKS blocks, but not shorter than KS_MFMA_MIN_PART shifts
+            // the longest shift range of a row group, cut into parts of at most
+            // mfma_max_part(rgroups) shifts (int32 accumulators), each shared by rgroups
+            // blocks (residue groups)
             const int64_t tmax = std::min(m.nA32 + MFMA_ROWS - 1, m.nB32);
-            const int64_t s_min = cdiv(tmax, MFMA_MAX_PART);
-            const int64_t s_fill = cdiv(env_int("KS_MFMA_BLOCKS", (int)sp.fill_blocks), (int64_t)npts * m.groups);
-            const int64_t s_cap = std::max<int64_t>(1, tmax / std::max<int64_t>(1, env_int("KS_MFMA_MIN_PART", 128)));
-            m.splits = std::max(s_min, std::min(s_fill, s_cap));
+            mfma_shape(tmax, (int64_t)npts * m.groups, env_int("KS_MFMA_BLOCKS", (int)sp.fill_blocks),
+                       env_int("KS_MFMA_MIN_PART", 128), m.splits, m.rgroups);
             m.part = cdiv(tmax, m.splits);
-            m.blocks = m.groups * m.splits;
+            m.blocks = m.groups * m.splits * m.rgroups;
             m.ncols = m.groups * MFMA_LIMBS;
             m.a_front = 32 * MFMA_ROWS;
             m.a_len = align_up(m.a_front + 32 * m.nA32 + 32 * MFMA_ROWS, 1024);
@@ -414,7 +454,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
                 d.base = side ? m.b_top : m.a_front;
                 d.reversed = side;
                 d.zero = reinterpret_cast<uint8_t *>(cols(m.cols_off));
-                d.zero_len = (side || m.splits == 1) ? 0 : 16 * m.ncols;  // cleared for atomics only
+                d.zero_len = (side || m.splits * m.rgroups == 1) ? 0 : 16 * m.ncols;  // cleared for atomics only
                 d.block0 = next_block(JL.digit);
                 d.nblocks = cdiv(d.len + d.zero_len, 1024);
                 JL.digit.push_back(d);
@@ -430,6 +470,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
             j.nB32 = m.nB32;
             j.splits = m.splits;
             j.part = m.part;
+            j.rgroups = m.rgroups;
             j.cols = reinterpret_cast<unsigned long long *>(cols(m.cols_off));
             j.block0 = next_block(JL.mfma);
             j.nblocks = m.blocks;
@@ -783,7 +824,7 @@ using namespace ks;
 
 extern "C" {
 
-int32_t ks_version(void) { return 103; }
+int32_t ks_version(void) { return 104; }
 
 const char *ks_strerror(int code) {
     switch (code) {

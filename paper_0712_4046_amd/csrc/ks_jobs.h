@@ -32,19 +32,20 @@ constexpr int MUL_R = 2;
 constexpr int MUL_T = 64 * MUL_R;
 constexpr int MUL_CI = 128;
 
-// int8 matrix-core multiplier (7-bit digits): a block of MFMA_WAVES waves owns MFMA_RT row
-// tiles of 32 output digit blocks (32 digits each) = 8 * MFMA_ROWS output limbs and a part of
-// at most MFMA_MAX_PART block shifts; wave w takes the shifts t = t_a + c (mod 32) for the
-// MFMA_CLASSES residues c = w, w + MFMA_WAVES, ..., so an int32 accumulator sees at most
-// MFMA_CLASSES * MFMA_MAX_PART / 32 = 4064 shifts (each adds at most 32 * 128^2 in absolute
-// value, so the sum stays below 2^31)
+// int8 matrix-core multiplier (balanced 8-bit digits): a block of MFMA_WAVES waves owns
+// MFMA_RT row tiles of 32 output digit blocks (32 digits each) = 8 * MFMA_ROWS output limbs, a
+// part of the block shifts and one of rgroups groups of their residues mod 32; wave w takes
+// the shifts t = t_a + c (mod 32) for the MFMA_CLASSES / rgroups residues c = w + MFMA_WAVES k
+// of its group, so with parts of at most mfma_max_part(rgroups) shifts an int32 accumulator
+// sees at most 4064 shifts (each adds at most 32 * 128^2 in absolute value, so the sum stays
+// below 2^31)
 constexpr int MFMA_WAVES = 8;
 constexpr int MFMA_TPB = 64 * MFMA_WAVES;
 constexpr int MFMA_CLASSES = 32 / MFMA_WAVES;
 constexpr int MFMA_RT = 8;
 constexpr int MFMA_ROWS = 32 * MFMA_RT;
 constexpr int MFMA_LIMBS = 8 * MFMA_ROWS;
-constexpr int64_t MFMA_MAX_PART = 4064 * 32 / MFMA_CLASSES;
+constexpr int64_t mfma_max_part(int64_t rgroups) { return 4064 * 32 / (MFMA_CLASSES / rgroups); }
 constexpr int64_t MFMA_PADB = 64;
 
 constexpr int EXTRACT_TPB = 256;
@@ -116,7 +117,8 @@ struct MfmaJob {
     int64_t b_len;
     int64_t nB32;       // number of block shifts t
     int64_t splits;     // parts per row group
-    int64_t part;       // block shifts per part (at most MFMA_MAX_PART)
+    int64_t part;       // block shifts per part (at most mfma_max_part(rgroups))
+    int64_t rgroups;    // residue groups per part: 1, 2 or 4 blocks share a part
     unsigned long long *cols;
     int64_t block0;
     int64_t nblocks;

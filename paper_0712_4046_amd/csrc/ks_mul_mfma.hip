@@ -2,32 +2,36 @@
 //
 // An integer product is a convolution of digit sequences: with balanced 8-bit digits a_i, b_j
 // (values -128..127, exactly the signed int8 operands: A = sum_i a_i 256^i, see
-// digitize_kernel), C[k] = sum_i a_i b_{k-i} and A*B = sum_k C[k] 2^(8k).  Writing k = 32 s + r and
-// splitting the shift into 32-digit blocks t,
-//     C[32 s + r] = sum_t sum_{q<32} a[32 (s - t) + q] * b[32 t + r - q],
-// each block shift t is a 32x32x32 matrix product: rows s (a 32-digit output block), columns
-// r, contraction q; the a-matrix rows are contiguous 32-digit runs of a and the b-matrix is a
-// Toeplitz tile of b.  One v_mfma_i32_32x32x32_i8 computes it, accumulating exactly in int32
-// (at most 32 * 128^2 in absolute value per step; a wave takes at most 4064 steps).  Against
-// 7-bit digits (0..127) the balanced digits need 8/7 fewer per operand, (8/7)^2 = 1.31x fewer
-// multiply-adds per product.
+// digitize_kernel), C[k] = sum_i a_i b_{k-i} and A*B = sum_k C[k] 2^(8k).  Writing k = 32 r + s
+// (output row r: a 32-digit block) and splitting the shift into 32-digit blocks t,
+//     C[32 r + s] = sum_t sum_{q<32} b[32 t + s - q] * a[32 (r - t) + q],
+// each block shift t is a 32x32x32 matrix product: matrix rows s (the digit within an output
+// row), matrix columns r, contraction q; the left matrix is a Toeplitz tile of b and the right
+// one holds contiguous 32-digit runs of a.  One v_mfma_i32_32x32x32_i8 computes it,
+// accumulating exactly in int32 (at most 32 * 128^2 in absolute value per step; a wave takes at
+// most 4064 steps).  Against 7-bit digits (0..127) the balanced digits need 8/7 fewer per
+// operand, (8/7)^2 = 1.31x fewer multiply-adds per product.
 //
-// Lane layout of v_mfma_i32_32x32x32_i8 (checked on the device): lane l supplies row (A) or
-// column (B) l % 32 and contraction indices 16 (l / 32) .. + 15 as 16 bytes; result register
-// i of lane l is row 8 (i / 4) + 4 (l / 32) + (i % 4), column l % 32.
+// Lane layout of v_mfma_i32_32x32x32_i8 (checked on the device): lane l supplies row (left
+// operand) or column (right operand) l % 32 and contraction indices 16 (l / 32) .. + 15 as 16
+// bytes; result register i of lane l is matrix row 8 (i / 4) + 4 (l / 32) + (i % 4), column
+// l % 32.  So a lane's registers 4 a .. 4 a + 3 hold the four digits of one limb: limb
+// 2 a + l / 32 of output row r = l % 32 of the tile, assembled in the lane itself.
 //
-// A block covers MFMA_RT row tiles (32 rows each: 32 * 32 * MFMA_RT output digits =
-// MFMA_LIMBS limbs) and one part of the range of t.  Wave w takes the shifts of its part that
-// are congruent to w mod MFMA_WAVES (32 / MFMA_WAVES residues mod 32), one residue class after
-// the other.  Within a
-// class t advances by 32, which moves every row tile's a-rows by exactly one tile: the
+// A block covers MFMA_RT tiles (32 output rows each: 32 * 32 * MFMA_RT output digits =
+// MFMA_LIMBS limbs), one part of the range of t and one of `rgroups` groups of the residues of
+// t mod 32.  Wave w takes the shifts of its part congruent to w mod MFMA_WAVES that fall in
+// the block's residue group: MFMA_CLASSES / rgroups residue classes, one after the other (one
+// class when rgroups = 4: a single long chain of steps, whose start-up latency is paid once).
+// Within a class t advances by 32, which moves every tile's a-runs by exactly one tile: the
 // a-fragment of tile rt at one step is that of tile rt-1 at the step before.  So a step loads
 // one new a-fragment (16 contiguous bytes per lane) and one Toeplitz b-window (68 bytes, one
 // dword per lane, spread by lane shuffles and realigned with v_alignbyte) straight from global
-// memory, PF steps ahead, and issues MFMA_RT matrix operations.  At the end the waves add
-// their digit sums into LDS, the block turns them into limb columns and adds those into the
-// product's column buffer with 64-bit atomics, so any number of parts may share a row group
-// (a row group of one part stores its columns instead, into a buffer nobody clears).
+// memory, PF steps ahead, and issues MFMA_RT matrix operations.  At the end every wave turns
+// its digit sums into limb values in registers and stores them into an LDS slice of its own;
+// the block adds the waves' slices and adds its limb columns into the product's column buffer
+// with 64-bit atomics, so any number of blocks may share a row group (the only block of a row
+// group stores its columns instead, into a buffer nobody clears).
 #include "ks_device.h"
 #include "ks_launch.h"
 
@@ -157,14 +161,21 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
     constexpr int PF = 8;  // steps loaded ahead (the b-window is consumed one step early)
     constexpr int UN = RT > PF ? RT : PF;  // steps per unrolled group: slot and ring indices are constants
     static_assert(UN % RT == 0 && UN % PF == 0, "fragment slots and prefetch ring must divide the unroll");
-    constexpr int NDIG = 32 * MFMA_ROWS;  // output digits of a block
-    __shared__ unsigned long long D[NDIG];
+    // limb sums of each wave: limb w of output row rb (w < 8, rb < MFMA_ROWS) at
+    // w * MFMA_ROWS + (rb ^ 8 w), so that both the waves' stores and the block's sums meet few
+    // LDS bank conflicts
+    __shared__ long long D[MFMA_WAVES][MFMA_LIMBS];
 
     int64_t local;
     const MfmaJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 31, g = lane >> 5;
-    const int64_t grp = local / J.splits, part = local - grp * J.splits;
+    // block index within the job: (row group, part, residue group), the residue group fastest
+    const int64_t per_grp = J.splits * J.rgroups;
+    const int64_t grp = local / per_grp, rem = local - grp * per_grp;
+    const int64_t part = rem / J.rgroups;
+    const int rg = (int)(rem - part * J.rgroups);
+    const int cpw = MFMA_CLASSES / (int)J.rgroups;  // residue classes per wave
     const int64_t S0 = grp * MFMA_ROWS;  // first output row (32-digit block) of the block
 
     // shifts t with a[32 (s - t) ..] and b[32 t ..] both inside the operands for some row s
@@ -176,8 +187,6 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
     const int64_t ta = tlo + part * J.part;
     int64_t tb = ta + J.part;
     if (tb > thi + 1) tb = thi + 1;
-
-    for (int x = tid; x < NDIG; x += MFMA_TPB) D[x] = 0ull;
 
     v16i acc[RT];
 #pragma unroll
@@ -196,8 +205,8 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
     const uint32_t *bw = reinterpret_cast<const uint32_t *>(J.bd + wb) + (lane < 16 ? lane : 16);
 
     const int wvu = __builtin_amdgcn_readfirstlane(wv);  // wave-uniform: scalar loop control
-    for (int ci = 0; ci < MFMA_CLASSES; ++ci) {
-        const int64_t t0 = ta + wvu + MFMA_WAVES * ci;
+    for (int ci = 0; ci < cpw; ++ci) {
+        const int64_t t0 = ta + wvu + MFMA_WAVES * (rg * cpw + ci);
         if (t0 >= tb) break;
         const int64_t ns = uniform64((tb - t0 + 31) / 32);  // steps t = t0 + 32 k, k < ns
         // fragment slots: tile rt at step k uses fr[(rt - k) mod RT]; the loads of step k + PF
@@ -225,7 +234,7 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
-                acc[rt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fr[(rt - j % RT + RT) % RT], bop, acc[rt], 0, 0, 0);
+                acc[rt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bop, fr[(rt - j % RT + RT) % RT], acc[rt], 0, 0, 0);
             bop = mfma_bop(pb[(j + 1) % PF], sel, sh);
         };
         int64_t kb = 0;
@@ -237,33 +246,31 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
         for (int j = 0; j < UN - 1; ++j)
             if (kb + j < ns) step(j, kb + j);
     }
-    __syncthreads();
-
-    // digit sums of the block: digit 32 row + col; result register i of lane (m, g) in tile rt
-    // is row 32 rt + 8 (i / 4) + 4 g + i % 4, column m
+    // limb 2 a + g of output row 32 rt + m: the digits in registers 4 a .. 4 a + 3 at weights
+    // 2^0, 2^8, 2^16, 2^24, exact in int64 (|digit sum| < 2^36 for a part of at most 2^17 shifts)
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int v = acc[rt][i];  // signed digit sums, added in two's complement
-            if (v) atomicAdd(&D[32 * (32 * rt + 8 * (i >> 2) + 4 * g + (i & 3)) + m],
-                             (unsigned long long)(long long)v);
+        for (int a4 = 0; a4 < 4; ++a4) {
+            const int64_t v = (int64_t)acc[rt][4 * a4] + (int64_t)acc[rt][4 * a4 + 1] * 256 +
+                              (int64_t)acc[rt][4 * a4 + 2] * 65536 + (int64_t)acc[rt][4 * a4 + 3] * 16777216;
+            const int w = 2 * a4 + g, rb = 32 * rt + m;
+            D[wv][w * MFMA_ROWS + (rb ^ (8 * w))] = v;
         }
     __syncthreads();
 
-    // limb column j of the block takes the digits k = 4 j .. 4 j + 3: the signed value
-    // D[k] 2^(8 (k - 4 j)) split as x (its low 32 bits, weight 2^0, non-negative) + y (the rest,
-    // weight 2^32, signed, added in two's complement)
+    // limb column j of the block: its value v split as x (the low 32 bits, weight 2^0,
+    // non-negative) + y (the rest, weight 2^32, signed, added in two's complement)
     unsigned long long *out = J.cols + 2 * grp * MFMA_LIMBS;
+    const bool alone = J.splits * J.rgroups == 1;
     for (int j = tid; j < MFMA_LIMBS; j += MFMA_TPB) {
-        unsigned long long x = 0, y = 0;
+        const int rb = j >> 3, w = j & 7;
+        const int pos = w * MFMA_ROWS + (rb ^ (8 * w));
+        long long v = 0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const long long v = (long long)D[4 * j + t] * (1ll << (8 * t));
-            x += (unsigned long long)(uint32_t)v;
-            y += (unsigned long long)(v >> 32);
-        }
-        if (J.splits == 1) {  // the only block of its columns: plain stores, nothing cleared before
+        for (int u = 0; u < MFMA_WAVES; ++u) v += D[u][pos];
+        const unsigned long long x = (uint32_t)v, y = (unsigned long long)(v >> 32);
+        if (alone) {  // the only block of its columns: plain stores, nothing cleared before
             out[2 * j] = x;
             out[2 * j + 1] = y;
         } else {

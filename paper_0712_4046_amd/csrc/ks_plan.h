@@ -23,11 +23,12 @@ struct Spec {
     uint64_t mod_p;  // non-zero: inputs are residues, outputs reduced mod p
     int variant;     // KS_VARIANT_* (AUTO resolved by the planner)
     int engine;
-    // launch shaping: a product planned alone aims its matrix-core launch at fill_blocks blocks
-    // and cuts reconstruction chains for latency; a product of a batch shares the GPU with the
-    // rest of the batch, so it takes a share of the blocks and longer chain segments (fewer
-    // anchors: the batch supplies the parallelism)
-    int64_t fill_blocks = 1024;
+    // launch shaping: a product planned alone takes the matrix-core launch shape of least
+    // modelled time (fill_blocks = 0) and cuts reconstruction chains for latency; a product of
+    // a batch shares the GPU with the rest of the batch, so it aims at a share of the blocks
+    // (fill_blocks) and takes longer chain segments (fewer anchors: the batch supplies the
+    // parallelism)
+    int64_t fill_blocks = 0;
     bool batch = false;
     int64_t batch_count = 1;  // products planned together
 };
@@ -44,10 +45,11 @@ struct MulGeom {
     bool wave = false;  // vector ALU, one wave per tile (short i ranges)
     int64_t na, nb, ntiles;
     int64_t ncols, cols_off, blocks;  // column sums: 3 words (vector ALU) or 4 words (matrix cores)
-    // matrix-core engine: 7-bit digit buffers (byte offsets in the digit region), row groups
-    // of MFMA_ROWS output rows, each cut into `splits` parts of `part` block shifts
+    // matrix-core engine: balanced 8-bit digit buffers (byte offsets in the digit region), row
+    // groups of MFMA_ROWS output rows, each cut into `splits` parts of `part` block shifts,
+    // each part shared by `rgroups` blocks (residue groups)
     int64_t nad = 0, nbd = 0, nA32 = 0, nB32 = 0, a_front = 0, a_len = 0, b_len = 0, b_top = 0;
-    int64_t groups = 0, splits = 1, part = 0;
+    int64_t groups = 0, splits = 1, part = 0, rgroups = 1;
     int64_t ad_off = 0, bd_off = 0;
 };
 struct NormGeom {

@@ -216,10 +216,13 @@ def test_out_of_range_coefficient_is_reported(torch_dev, oracle):
     assert ks.status() == ks.KS_ERANGE
 
 
-@pytest.mark.parametrize("blocks,min_part", [("1", "1000000"), ("4096", "32"), ("1024", "128")])
+@pytest.mark.parametrize("blocks,min_part", [("1", "1000000"), ("4096", "32"), ("1024", "128"), ("40", "128"),
+                                             ("0", "128"), ("0", "1")])
 def test_mfma_part_splits(torch_dev, oracle, monkeypatch, blocks, min_part):
-    # the matrix-core multiplier cuts each row group's shift range into parts whose column sums
-    # meet in 64-bit atomics: one part per group, many short parts, and the default
+    # the matrix-core multiplier cuts each row group's shift range into parts, and each part
+    # into residue groups, whose column sums meet in 64-bit atomics: one block per group, many
+    # short parts over four residue groups, two residue groups (40 blocks), the launch-shape
+    # model (0)
     monkeypatch.setenv("KS_MFMA_BLOCKS", blocks)
     monkeypatch.setenv("KS_MFMA_MIN_PART", min_part)
     P = wl.config2()
