@@ -39,9 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # and for the 64-product modular batch (profiles/config4_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
-MEASURED_TRAFFIC = {"pack": 996237, "mul_valu": 1656022, "normalize": 1209596, "recon": 757849, "finish": 441709}
-MEASURED_TRAFFIC_CONFIG4 = {"pack": 3110842364, "digitize": 344519850, "mul_mfma": 1777036942,
-                            "normalize": 1058233862, "recon": 348996550, "finish": 271313638}
+MEASURED_TRAFFIC = {"pack": 996137, "digitize": 1120122, "mul_mfma": 6082171, "normalize": 1372825, "recon": 778346,
+                    "finish": 441719}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 3129285102, "digitize": 344519688, "mul_mfma": 1777780716,
+                            "normalize": 1131572265, "recon": 349067080, "finish": 271321320}
 KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract")
 
 
@@ -110,8 +111,8 @@ def paper_sweep(ks, torch, wl):
 
 def kernel_times(ks, run, reps):
     """Per stage: launches per run, average launch duration and the stage's time per run (its
-    launches added up), from HIP events the library records around every launch on its own
-    stream (ks_profile_*)."""
+    launches added up), from the HIP events that every launch of the library records at its own
+    start and end on the stream it runs on (hipExtLaunchKernelGGL, via ks_profile_*)."""
     ks.profile_reset()
     ks.profile_enable(True)
     for _ in range(reps):
@@ -143,7 +144,7 @@ def roofline(kern, info, traffic_table=None):
         achieved = ops / sec / 1e12
         return {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS, "unit": "TOP/s",
                 "frac": achieved / MFMA_I8_PEAK_TOPS, "traffic": traffic, "launches_per_run": lpr,
-                "op": "int8 multiply-add of 7-bit digits (2 operations)", "ops_per_run": ops}
+                "op": "int8 multiply-add of balanced 8-bit digits (2 operations)", "ops_per_run": ops}
     if dom in ("mul_valu", "anchor"):
         ops = info["valu_limb_mults"] if dom == "mul_valu" else info["anchor_limb_mults"]
         achieved = ops / sec / 1e12

@@ -221,7 +221,7 @@ int ks_profile_reset(void);
  * Planner tunables (launch shapes), process-wide, read whenever a product or batch is planned;
  * a value set here overrides the environment variable of the same name, which overrides the
  * built-in default.  Names and defaults:
- *   "KS_MFMA_MIN_LIMBS"  6000  both operands at least this many limbs -> matrix-core engine
+ *   "KS_MFMA_MIN_LIMBS"  4000  both operands at least this many limbs -> matrix-core engine
  *                              (unset, the products of a batch use 1000)
  *   "KS_MFMA_BLOCKS"     0     matrix-core launch target of one product, in blocks; 0: the
  *                              launch shape of least modelled time (unset, a batch of n
@@ -231,8 +231,9 @@ int ks_profile_reset(void);
  *   "KS_MFMA_BLOCK_COST" 10    fixed cost of a matrix-core block in the launch-shape model, in
  *                              steps (MFMA_RT matrix operations of every wave)
  *   "KS_CHAIN_K"         model reconstruction segment length (0 or unset: the cost model)
- *   "KS_MUL_WAVE_MAX"    1024  vector-ALU products whose shorter operand has at most this many
- *                              limbs run one wave per 128-column tile (else a block per tile)
+ *   "KS_MUL_WAVE_MAX"    128   vector-ALU products whose shorter operand has at most this many
+ *                              limbs run one wave per 128-column tile, else a block per tile
+ *                              (unset, the products of a batch use 1024)
  *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
  *                              128) run one wave per job (0: every job in 256-thread blocks)
  * ks_tune_set returns KS_EINVAL for an unknown name or a negative value; ks_tune_get returns

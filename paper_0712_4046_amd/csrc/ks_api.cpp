@@ -115,11 +115,11 @@ static int64_t slot_bits(int variant, int b, int e) {
 // Time model for KS_VARIANT_AUTO (microseconds on one MI355X, fitted to single-product
 // measurements): the products on the engine the planner will pick -- vector ALU 0.21 fs per
 // limb product above a 5 us floor, matrix cores 0.69 fs per int8 operation on balanced digits
-// above a 14 us floor -- plus 0.15 ns per operand limb for the linear stages, 0.2 ns per
+// above a 10 us floor -- plus 0.15 ns per operand limb for the linear stages, 0.2 ns per
 // coefficient for KS4's reconstruction, and 4.5 us per launch (KS4 has one more; the matrix
 // cores add the digit launch).  A batch shares its launches, so there only the rates count.
-// It picks NEG2 for the L = 4096 signed 64-bit product (measured 0.047 ms, against 0.050 for
-// KS1 and 0.053 for KS4), KS4 for L = 65536 at 48 bits (0.54 ms, against 0.72 and 1.27), and
+// It picks NEG2 for the L = 4096 signed 64-bit product (measured 0.043 ms, against 0.045 for
+// KS1 and 0.051 for KS4), KS4 for L = 65536 at 48 bits (0.54 ms, against 0.72 and 1.27), and
 // KS1 or NEG2 for short products, where every variant is launch-bound.
 static int auto_variant(int64_t lf, int64_t lg, int b, int e, bool batch, int engine) {
     double best = 1e300;
@@ -130,13 +130,13 @@ static int auto_variant(int64_t lf, int64_t lg, int b, int e, bool batch, int en
         const double na = (double)cdiv(N * (lf - 1) + b + 2, 32), nb = (double)cdiv(N * (lg - 1) + b + 2, 32);
         int eng = engine;
         if (eng == 0)
-            eng = std::min(na, nb) >= env_int("KS_MFMA_MIN_LIMBS", batch ? 1000 : 6000) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
+            eng = std::min(na, nb) >= env_int("KS_MFMA_MIN_LIMBS", batch ? 1000 : 4000) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
         double us = 0;
         int launches = 4;  // pack, multiply, recombine, extract
         if (eng == KS_ENGINE_MFMA) {
             us += k * 2.0 * (4 * na + 1) * (4 * nb + 1) * 6.9e-10;
             launches += 1;  // digits
-            if (!batch) us += 14.0;
+            if (!batch) us += 10.0;
         } else {
             us += k * na * nb * 2.1e-7;
             if (!batch) us += 5.0;
@@ -217,7 +217,7 @@ int plan_product(const Spec &sp, Geom &G) {
         // batch: standard KS 1.95 ms at 2500 limbs, 1.77-1.81 ms at 800-1200; four-point 2.02
         // and 1.91 ms)
         if (eng == 0)
-            eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 1000 : 6000) ? KS_ENGINE_MFMA
+            eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 1000 : 4000) ? KS_ENGINE_MFMA
                                                                                           : KS_ENGINE_VALU;
         m.engine = eng;
         if (eng == KS_ENGINE_MFMA) {
@@ -246,7 +246,7 @@ int plan_product(const Spec &sp, Geom &G) {
             m.ncols = m.ntiles * MUL_T;
             // a tile's i range is at most min(nf, ng) limbs: when that is short, one wave per
             // tile keeps the waves busy (the block mode splits the range over MUL_WAVES waves)
-            m.wave = std::min(nf, ng) <= env_int("KS_MUL_WAVE_MAX", 1024);
+            m.wave = std::min(nf, ng) <= env_int("KS_MUL_WAVE_MAX", sp.batch ? 1024 : 128);
         }
         m.cols_off = coff;
         coff += align_up((eng == KS_ENGINE_MFMA ? 4 : 3) * m.ncols, 64);
@@ -390,6 +390,12 @@ struct ProfRec {
 };
 static std::mutex g_prof_mu;
 static bool g_prof = false;
+
+LaunchEvents &launch_events() {
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
 static std::vector<ProfRec> g_prof_pending;
 static std::map<std::string, std::pair<int64_t, double>> g_prof_acc;
 
@@ -399,9 +405,20 @@ static hipError_t timed(const char *name, hipStream_t s, F &&fn) {
     ProfRec r;
     r.name = name;
     if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return hipErrorOutOfMemory;
-    hipEventRecord(r.a, s);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipStreamIsCapturing(s, &cap);
+    const bool captured = cap != hipStreamCaptureStatusNone;
+    LaunchEvents &ev = launch_events();
+    if (captured) hipEventRecord(r.a, s);  // a captured stream: the events bracket the region
+    else ev = LaunchEvents{r.a, r.b, false};
     hipError_t e = fn();
-    hipEventRecord(r.b, s);
+    if (captured) {
+        hipEventRecord(r.b, s);
+    } else if (!ev.used) {  // nothing launched
+        hipEventRecord(r.a, s);
+        hipEventRecord(r.b, s);
+    }
+    ev = LaunchEvents{};
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_pending.push_back(r);
     return e;
@@ -935,7 +952,7 @@ int ks_tune_set(const char *name, int64_t value) {
 
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
-    static const int dflt[] = {6000, 1024, 128, 0, 1024, (int)SMALL_BL};
+    static const int dflt[] = {4000, 0, 128, 10, 0, 128, (int)SMALL_BL};  // as for a single product
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];

@@ -451,7 +451,7 @@ __global__ __launch_bounds__(FINISH_TPB) void finish_any_kernel(Launch<ChainJob>
 
 hipError_t launch_extract(const Launch<ExtractJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(extract_kernel, dim3((unsigned)L.total_blocks), dim3(EXTRACT_TPB), 0, s, L);
+    ks_launch(extract_kernel, dim3((unsigned)L.total_blocks), dim3(EXTRACT_TPB), 0, s, L);
     return hipGetLastError();
 }
 
@@ -459,14 +459,14 @@ hipError_t launch_anchor(const Launch<AnchorJob> &L, int w_in, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     dim3 g((unsigned)L.total_blocks), b(ANCHOR_TPB);
     switch (w_in) {
-        case 1: hipLaunchKernelGGL(anchor_kernel<1>, g, b, 0, s, L); break;
-        case 2: hipLaunchKernelGGL(anchor_kernel<2>, g, b, 0, s, L); break;
-        case 3: hipLaunchKernelGGL(anchor_kernel<3>, g, b, 0, s, L); break;
-        case 4: hipLaunchKernelGGL(anchor_kernel<4>, g, b, 0, s, L); break;
-        case 5: hipLaunchKernelGGL(anchor_kernel<5>, g, b, 0, s, L); break;
-        case 6: hipLaunchKernelGGL(anchor_kernel<6>, g, b, 0, s, L); break;
-        case 7: hipLaunchKernelGGL(anchor_kernel<7>, g, b, 0, s, L); break;
-        case 8: hipLaunchKernelGGL(anchor_kernel<8>, g, b, 0, s, L); break;
+        case 1: ks_launch(anchor_kernel<1>, g, b, 0, s, L); break;
+        case 2: ks_launch(anchor_kernel<2>, g, b, 0, s, L); break;
+        case 3: ks_launch(anchor_kernel<3>, g, b, 0, s, L); break;
+        case 4: ks_launch(anchor_kernel<4>, g, b, 0, s, L); break;
+        case 5: ks_launch(anchor_kernel<5>, g, b, 0, s, L); break;
+        case 6: ks_launch(anchor_kernel<6>, g, b, 0, s, L); break;
+        case 7: ks_launch(anchor_kernel<7>, g, b, 0, s, L); break;
+        case 8: ks_launch(anchor_kernel<8>, g, b, 0, s, L); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -476,16 +476,16 @@ hipError_t launch_finish(const Launch<ChainJob> &L, int nw, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     dim3 g((unsigned)L.total_blocks), b(FINISH_TPB);
     switch (nw) {
-        case 0: hipLaunchKernelGGL(finish_any_kernel, g, b, 0, s, L); break;
-        case 1: hipLaunchKernelGGL(finish_kernel<1>, g, b, 0, s, L); break;
-        case 2: hipLaunchKernelGGL(finish_kernel<2>, g, b, 0, s, L); break;
-        case 3: hipLaunchKernelGGL(finish_kernel<3>, g, b, 0, s, L); break;
-        case 4: hipLaunchKernelGGL(finish_kernel<4>, g, b, 0, s, L); break;
-        case 5: hipLaunchKernelGGL(finish_kernel<5>, g, b, 0, s, L); break;
-        case 6: hipLaunchKernelGGL(finish_kernel<6>, g, b, 0, s, L); break;
-        case 7: hipLaunchKernelGGL(finish_kernel<7>, g, b, 0, s, L); break;
-        case 8: hipLaunchKernelGGL(finish_kernel<8>, g, b, 0, s, L); break;
-        case 9: hipLaunchKernelGGL(finish_kernel<9>, g, b, 0, s, L); break;
+        case 0: ks_launch(finish_any_kernel, g, b, 0, s, L); break;
+        case 1: ks_launch(finish_kernel<1>, g, b, 0, s, L); break;
+        case 2: ks_launch(finish_kernel<2>, g, b, 0, s, L); break;
+        case 3: ks_launch(finish_kernel<3>, g, b, 0, s, L); break;
+        case 4: ks_launch(finish_kernel<4>, g, b, 0, s, L); break;
+        case 5: ks_launch(finish_kernel<5>, g, b, 0, s, L); break;
+        case 6: ks_launch(finish_kernel<6>, g, b, 0, s, L); break;
+        case 7: ks_launch(finish_kernel<7>, g, b, 0, s, L); break;
+        case 8: ks_launch(finish_kernel<8>, g, b, 0, s, L); break;
+        case 9: ks_launch(finish_kernel<9>, g, b, 0, s, L); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -497,31 +497,31 @@ hipError_t launch_chain(const Launch<ChainJob> &L, int nw, bool lanes, hipStream
     if (lanes) {
         dim3 g((unsigned)((L.total_blocks + CHAIN_TPB - 1) / CHAIN_TPB));
         switch (nw) {
-            case 0: hipLaunchKernelGGL(chain_lanes_kernel<0>, g, b, 0, s, L); break;
-            case 1: hipLaunchKernelGGL(chain_lanes_kernel<1>, g, b, 0, s, L); break;
-            case 2: hipLaunchKernelGGL(chain_lanes_kernel<2>, g, b, 0, s, L); break;
-            case 3: hipLaunchKernelGGL(chain_lanes_kernel<3>, g, b, 0, s, L); break;
-            case 4: hipLaunchKernelGGL(chain_lanes_kernel<4>, g, b, 0, s, L); break;
-            case 5: hipLaunchKernelGGL(chain_lanes_kernel<5>, g, b, 0, s, L); break;
-            case 6: hipLaunchKernelGGL(chain_lanes_kernel<6>, g, b, 0, s, L); break;
-            case 7: hipLaunchKernelGGL(chain_lanes_kernel<7>, g, b, 0, s, L); break;
-            case 8: hipLaunchKernelGGL(chain_lanes_kernel<8>, g, b, 0, s, L); break;
-            case 9: hipLaunchKernelGGL(chain_lanes_kernel<9>, g, b, 0, s, L); break;
+            case 0: ks_launch(chain_lanes_kernel<0>, g, b, 0, s, L); break;
+            case 1: ks_launch(chain_lanes_kernel<1>, g, b, 0, s, L); break;
+            case 2: ks_launch(chain_lanes_kernel<2>, g, b, 0, s, L); break;
+            case 3: ks_launch(chain_lanes_kernel<3>, g, b, 0, s, L); break;
+            case 4: ks_launch(chain_lanes_kernel<4>, g, b, 0, s, L); break;
+            case 5: ks_launch(chain_lanes_kernel<5>, g, b, 0, s, L); break;
+            case 6: ks_launch(chain_lanes_kernel<6>, g, b, 0, s, L); break;
+            case 7: ks_launch(chain_lanes_kernel<7>, g, b, 0, s, L); break;
+            case 8: ks_launch(chain_lanes_kernel<8>, g, b, 0, s, L); break;
+            case 9: ks_launch(chain_lanes_kernel<9>, g, b, 0, s, L); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     dim3 g((unsigned)L.total_blocks);
     switch (nw) {
-        case 1: hipLaunchKernelGGL(chain_kernel<1>, g, b, 0, s, L); break;
-        case 2: hipLaunchKernelGGL(chain_kernel<2>, g, b, 0, s, L); break;
-        case 3: hipLaunchKernelGGL(chain_kernel<3>, g, b, 0, s, L); break;
-        case 4: hipLaunchKernelGGL(chain_kernel<4>, g, b, 0, s, L); break;
-        case 5: hipLaunchKernelGGL(chain_kernel<5>, g, b, 0, s, L); break;
-        case 6: hipLaunchKernelGGL(chain_kernel<6>, g, b, 0, s, L); break;
-        case 7: hipLaunchKernelGGL(chain_kernel<7>, g, b, 0, s, L); break;
-        case 8: hipLaunchKernelGGL(chain_kernel<8>, g, b, 0, s, L); break;
-        case 9: hipLaunchKernelGGL(chain_kernel<9>, g, b, 0, s, L); break;
+        case 1: ks_launch(chain_kernel<1>, g, b, 0, s, L); break;
+        case 2: ks_launch(chain_kernel<2>, g, b, 0, s, L); break;
+        case 3: ks_launch(chain_kernel<3>, g, b, 0, s, L); break;
+        case 4: ks_launch(chain_kernel<4>, g, b, 0, s, L); break;
+        case 5: ks_launch(chain_kernel<5>, g, b, 0, s, L); break;
+        case 6: ks_launch(chain_kernel<6>, g, b, 0, s, L); break;
+        case 7: ks_launch(chain_kernel<7>, g, b, 0, s, L); break;
+        case 8: ks_launch(chain_kernel<8>, g, b, 0, s, L); break;
+        case 9: ks_launch(chain_kernel<9>, g, b, 0, s, L); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1,11 +1,32 @@
 // ks_launch.h -- host-side launchers of the libksmul kernels (one per translation unit).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "ks_jobs.h"
 
 namespace ks {
+
+// Launch timing: a timed region of the host code hands the kernel launches of its thread a pair
+// of events, which the first launch records at its start and the last at its end
+// (hipExtLaunchKernelGGL: the dispatch's own timestamps, not those of the stream around it).
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+LaunchEvents &launch_events();  // this thread's pair (none outside timed regions)
+
+template <typename K, typename... Args>
+inline void ks_launch(K kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, Args... args) {
+    LaunchEvents &ev = launch_events();
+    if (ev.stop) {
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, ev.used ? nullptr : ev.start, ev.stop, 0u, args...);
+        ev.used = true;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+    }
+}
 
 hipError_t launch_pack(const Launch<PackJob> &L, hipStream_t s);
 hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, hipStream_t s);

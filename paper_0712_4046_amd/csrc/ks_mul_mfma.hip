@@ -282,13 +282,13 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
 
 hipError_t launch_digitize(const Launch<DigitJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(digitize_kernel, dim3((unsigned)L.total_blocks), dim3(256), 0, s, L);
+    ks_launch(digitize_kernel, dim3((unsigned)L.total_blocks), dim3(256), 0, s, L);
     return hipGetLastError();
 }
 
 hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mul_mfma_kernel, dim3((unsigned)L.total_blocks), dim3(MFMA_TPB), 0, s, L);
+    ks_launch(mul_mfma_kernel, dim3((unsigned)L.total_blocks), dim3(MFMA_TPB), 0, s, L);
     return hipGetLastError();
 }
 

@@ -144,14 +144,14 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
 
 hipError_t launch_mul_valu(const Launch<MulJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mul_valu_kernel<false>, dim3((unsigned)L.total_blocks), dim3(MUL_TPB), 0, s, L);
+    ks_launch(mul_valu_kernel<false>, dim3((unsigned)L.total_blocks), dim3(MUL_TPB), 0, s, L);
     return hipGetLastError();
 }
 
 hipError_t launch_mul_valu_wave(const Launch<MulJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     const int64_t blocks = (L.total_blocks + MUL_WAVES - 1) / MUL_WAVES;
-    hipLaunchKernelGGL(mul_valu_kernel<true>, dim3((unsigned)blocks), dim3(MUL_TPB), 0, s, L);
+    ks_launch(mul_valu_kernel<true>, dim3((unsigned)blocks), dim3(MUL_TPB), 0, s, L);
     return hipGetLastError();
 }
 

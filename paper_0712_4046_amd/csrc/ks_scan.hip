@@ -229,7 +229,7 @@ hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    ks_launch(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -237,7 +237,7 @@ hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s) {
 
 hipError_t launch_pack(const Launch<PackJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
+    ks_launch(pack_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
     return hipGetLastError();
 }
 
@@ -245,14 +245,14 @@ hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob>
     if (La.total_blocks <= 0) return launch_pack(Lp, s);
     dim3 g((unsigned)(Lp.total_blocks + La.total_blocks)), b(SCAN_TPB);
     switch (w_in) {
-        case 1: hipLaunchKernelGGL(pack_anchor_kernel<1>, g, b, 0, s, Lp, La); break;
-        case 2: hipLaunchKernelGGL(pack_anchor_kernel<2>, g, b, 0, s, Lp, La); break;
-        case 3: hipLaunchKernelGGL(pack_anchor_kernel<3>, g, b, 0, s, Lp, La); break;
-        case 4: hipLaunchKernelGGL(pack_anchor_kernel<4>, g, b, 0, s, Lp, La); break;
-        case 5: hipLaunchKernelGGL(pack_anchor_kernel<5>, g, b, 0, s, Lp, La); break;
-        case 6: hipLaunchKernelGGL(pack_anchor_kernel<6>, g, b, 0, s, Lp, La); break;
-        case 7: hipLaunchKernelGGL(pack_anchor_kernel<7>, g, b, 0, s, Lp, La); break;
-        case 8: hipLaunchKernelGGL(pack_anchor_kernel<8>, g, b, 0, s, Lp, La); break;
+        case 1: ks_launch(pack_anchor_kernel<1>, g, b, 0, s, Lp, La); break;
+        case 2: ks_launch(pack_anchor_kernel<2>, g, b, 0, s, Lp, La); break;
+        case 3: ks_launch(pack_anchor_kernel<3>, g, b, 0, s, Lp, La); break;
+        case 4: ks_launch(pack_anchor_kernel<4>, g, b, 0, s, Lp, La); break;
+        case 5: ks_launch(pack_anchor_kernel<5>, g, b, 0, s, Lp, La); break;
+        case 6: ks_launch(pack_anchor_kernel<6>, g, b, 0, s, Lp, La); break;
+        case 7: ks_launch(pack_anchor_kernel<7>, g, b, 0, s, Lp, La); break;
+        case 8: ks_launch(pack_anchor_kernel<8>, g, b, 0, s, Lp, La); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -260,19 +260,19 @@ hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob>
 
 hipError_t launch_pack_small(const Launch<PackJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pack_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
+    ks_launch(pack_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
     return hipGetLastError();
 }
 
 hipError_t launch_normalize_small(const Launch<NormJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(normalize_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
+    ks_launch(normalize_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
     return hipGetLastError();
 }
 
 hipError_t launch_normalize(const Launch<NormJob> &L, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
+    ks_launch(normalize_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
     return hipGetLastError();
 }
 

@@ -202,8 +202,8 @@ def profile_reset():
     _check(lib().ks_profile_reset(), "ks_profile_reset")
 
 
-TUNABLES = ("KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_CHAIN_K", "KS_MUL_WAVE_MAX",
-            "KS_SCAN_SMALL")
+TUNABLES = ("KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",
+            "KS_MUL_WAVE_MAX", "KS_SCAN_SMALL")
 
 
 def tune_set(name: str, value: int):

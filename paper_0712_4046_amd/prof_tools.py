@@ -56,7 +56,16 @@ def workload(name: str = "config2", reps: int = 5):
     print("workload done", flush=True)
 
 
-def summarize(db: str, cmd: str = ""):
+def _table(rows):
+    print(f"{'kernel':60s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}")
+    for name, n, tot, avg, mn, mx in rows:
+        short = name if len(name) <= 60 else name[:57] + "..."
+        print(f"{short:60s} {n:6d} {tot / 1e3:11.1f} {avg / 1e3:9.2f} {mn / 1e3:9.2f} {mx / 1e3:9.2f}")
+
+
+def summarize(db: str, cmd: str = "", last: int = 0):
+    """Per-kernel durations of a --kernel-trace run; last > 0 adds a table over the last `last`
+    dispatches of each kernel (the calls a run profiles at its end)."""
     con = sqlite3.connect(db)
     rows = con.execute(
         "select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
@@ -64,10 +73,16 @@ def summarize(db: str, cmd: str = ""):
     print("# rocprofv3 --kernel-trace --stats summary")
     print(f"# command: {cmd}")
     print("# durations in microseconds")
-    print(f"{'kernel':60s} {'calls':>6s} {'total_us':>11s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}")
-    for name, n, tot, avg, mn, mx in rows:
-        short = name if len(name) <= 60 else name[:57] + "..."
-        print(f"{short:60s} {n:6d} {tot / 1e3:11.1f} {avg / 1e3:9.2f} {mn / 1e3:9.2f} {mx / 1e3:9.2f}")
+    _table(rows)
+    if last > 0:
+        print(f"# the last {last} dispatches of each kernel")
+        tail = []
+        for (name,) in con.execute("select distinct name from kernels"):
+            d = [r[0] for r in con.execute("select duration from kernels where name = ? order by start desc limit ?",
+                                            (name, last))]
+            if len(d) == last:
+                tail.append((name, len(d), sum(d), sum(d) / len(d), min(d), max(d)))
+        _table(sorted(tail, key=lambda r: -r[2]))
 
 
 def counter_per_kernel(db: str):
@@ -107,6 +122,6 @@ if __name__ == "__main__":
     if cmd == "workload":
         workload(sys.argv[2] if len(sys.argv) > 2 else "config2")
     elif cmd == "summarize":
-        summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
+        summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "", int(sys.argv[4]) if len(sys.argv) > 4 else 0)
     elif cmd == "counters":
         counters(sys.argv[2], sys.argv[3])
