@@ -235,7 +235,8 @@ int ks_profile_reset(void);
  *                              limbs run one wave per 128-column tile, else a block per tile
  *                              (unset, the products of a batch use 1024)
  *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
- *                              128) run one wave per job (0: every job in 256-thread blocks)
+ *                              128; 256 in a batch, and unset, a batch uses 256) run one wave
+ *                              per job (0: every job in 256-thread blocks)
  * ks_tune_set returns KS_EINVAL for an unknown name or a negative value; ks_tune_get returns
  * the value in force (KS_EINVAL if unknown); ks_tune_reset clears every value set here.
  * Plans made before a change keep their shapes.  Used by paper_0712_4046_amd/autotune.py.

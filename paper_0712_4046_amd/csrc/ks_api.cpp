@@ -155,6 +155,7 @@ static int auto_variant(int64_t lf, int64_t lg, int b, int e, bool batch, int en
 int plan_product(const Spec &sp, Geom &G) {
     G = Geom();
     G.sp = sp;
+    G.ipt = sp.batch ? SCAN_IPT_BATCH : SCAN_IPT_SINGLE;
     const int64_t lf = sp.lf, lg = sp.lg;
     const int b = sp.bits;
     G.e = ceil_log2(std::min(lf, lg));
@@ -190,8 +191,8 @@ int plan_product(const Spec &sp, Geom &G) {
             p.L = which ? lg : lf;
             p.n_out = which ? ng : nf;
             p.op_off = off;
-            p.small = p.n_out <= std::min<int64_t>(SMALL_BL, env_int("KS_SCAN_SMALL", (int)SMALL_BL));
-            p.blocks = p.small ? 1 : cdiv(p.n_out, SCAN_BL);
+            p.small = p.n_out <= std::min<int64_t>(small_bl(G.ipt), env_int("KS_SCAN_SMALL", (int)small_bl(G.ipt)));
+            p.blocks = p.small ? 1 : cdiv(p.n_out, scan_bl(G.ipt));
             off += align_up(p.n_out, 64);
             G.packs.push_back(p);
             G.pack_blocks += p.blocks;
@@ -274,8 +275,8 @@ int plan_product(const Spec &sp, Geom &G) {
         r.off_count = sp.sgn ? count : 0;
         r.n_out = n_out;
         r.n_in = std::max(prod_limbs + 2, n_out + shift / 32 + 2);
-        r.small = r.n_in <= std::min<int64_t>(SMALL_BL, env_int("KS_SCAN_SMALL", (int)SMALL_BL));
-        r.blocks = r.small ? 1 : cdiv(r.n_in, SCAN_BL);
+        r.small = r.n_in <= std::min<int64_t>(small_bl(G.ipt), env_int("KS_SCAN_SMALL", (int)small_bl(G.ipt)));
+        r.blocks = r.small ? 1 : cdiv(r.n_in, scan_bl(G.ipt));
         r.out_off = noff;
         noff += align_up(n_out, 64);
         G.norms.push_back(r);
@@ -430,6 +431,7 @@ static hipError_t timed(const char *name, hipStream_t s, F &&fn) {
 // offsets from the run's bases (batches); each job's block0 continues its list.
 void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t ws, JobLists &JL) {
     const Spec &sp = G.sp;
+    JL.ipt = G.ipt;  // the products of one list are planned alike (all single or all batched)
     auto ops = [&](int64_t limb_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_ops + 4 * limb_off); };
     auto cols = [&](int64_t word_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_cols + 4 * word_off); };
     auto norms = [&](int64_t limb_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_norms + 4 * limb_off); };
@@ -646,15 +648,15 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         auto L = make_launch(JL.pack, T ? &T->pack : nullptr, env, epoch_pack, env.ctr_pack);
         if (first_anchor != JL.anchor.end()) {
             auto La = make_launch(first_anchor->second, T ? &T->anchor.at(first_anchor->first) : nullptr, env, 0);
-            err = timed("pack", s, [&] { return launch_pack_anchor(L, La, first_anchor->first, s); });
+            err = timed("pack", s, [&] { return launch_pack_anchor(L, La, first_anchor->first, JL.ipt, s); });
         } else {
-            err = timed("pack", s, [&] { return launch_pack(L, s); });
+            err = timed("pack", s, [&] { return launch_pack(L, JL.ipt, s); });
         }
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.pack_small.empty()) {
         auto L = make_launch(JL.pack_small, T ? &T->pack_small : nullptr, env, epoch_pack);
-        err = timed("pack", s, [&] { return launch_pack_small(L, s); });
+        err = timed("pack", s, [&] { return launch_pack_small(L, JL.ipt, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.mul.empty()) {
@@ -684,12 +686,12 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
     }
     {
         auto L = make_launch(JL.norm, T ? &T->norm : nullptr, env, epoch_norm, env.ctr_norm);
-        err = timed("normalize", s, [&] { return launch_normalize(L, s); });
+        err = timed("normalize", s, [&] { return launch_normalize(L, JL.ipt, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.norm_small.empty()) {
         auto L = make_launch(JL.norm_small, T ? &T->norm_small : nullptr, env, epoch_norm);
-        err = timed("normalize", s, [&] { return launch_normalize_small(L, s); });
+        err = timed("normalize", s, [&] { return launch_normalize_small(L, JL.ipt, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.extract.empty()) {
@@ -952,7 +954,7 @@ int ks_tune_set(const char *name, int64_t value) {
 
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
-    static const int dflt[] = {4000, 0, 128, 10, 0, 128, (int)SMALL_BL};  // as for a single product
+    static const int dflt[] = {4000, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE)};  // as for a single product
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];

@@ -16,13 +16,14 @@ constexpr uint32_t KS_DEVSTAT_LOOKBACK = 4u;  // a look-back wait hit its spin l
 
 constexpr int MAX_INLINE_JOBS = 8;
 
-// carry-scan kernels (pack, normalize): 256 threads x 8 limbs per block
+// carry-scan kernels (pack, normalize): 256 threads x IPT limbs per block, jobs of at most
+// 64 IPT limbs one wave per job.  IPT = 2 for a single product (its launches are latency-bound:
+// short load windows per thread), 4 for a batch (half the blocks and look-backs per job)
 constexpr int SCAN_TPB = 256;
-constexpr int SCAN_IPT = 2;
-constexpr int64_t SCAN_BL = (int64_t)SCAN_TPB * SCAN_IPT;
-// jobs of at most SMALL_BL limbs run one wave per job
 constexpr int SMALL_TPB = 64;
-constexpr int64_t SMALL_BL = (int64_t)SMALL_TPB * SCAN_IPT;
+constexpr int SCAN_IPT_SINGLE = 2, SCAN_IPT_BATCH = 4;
+constexpr int64_t scan_bl(int ipt) { return (int64_t)SCAN_TPB * ipt; }
+constexpr int64_t small_bl(int ipt) { return (int64_t)SMALL_TPB * ipt; }
 
 // vector-ALU multiplier: a block of MUL_WAVES waves owns MUL_T = 64 * MUL_R product columns;
 // its waves take interleaved MUL_CI-long chunks of the i range and add up in LDS at the end

@@ -25,13 +25,13 @@ __device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[PK_MAXW], int 
     return o ? (a >> o) | (b << (32 - o)) : a;
 }
 
-// A block of pack job J with TPB threads (TPB * SCAN_IPT limbs per block); `local` is its
-// position in the job when the job has one block (else it draws a ticket).  The caller looks
-// the job up in its own kernel arguments.
-template <int TPB>
+// A block of pack job J with TPB threads (TPB * IPT limbs per block); `local` is its position
+// in the job when the job has one block (else it draws a ticket).  The caller looks the job
+// up in its own kernel arguments.
+template <int TPB, int IPT>
 __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, const LaunchCtl L) {
-    constexpr int64_t BL = (int64_t)TPB * SCAN_IPT;
-    typedef BlockCarryScan<TPB, SCAN_IPT> Scan;
+    constexpr int64_t BL = (int64_t)TPB * IPT;
+    typedef BlockCarryScan<TPB, IPT> Scan;
     __shared__ typename Scan::Smem sm;
     __shared__ uint32_t s_ticket;
     __shared__ int64_t s_v[BL + 3];  // s_v[x + 2] = column jb + x, x in [-2, BL]
@@ -114,15 +114,15 @@ __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, cons
         }
     }
     __syncthreads();
-    const int b0 = tid * SCAN_IPT;
-    int64_t u[SCAN_IPT];
+    const int b0 = tid * IPT;
+    int64_t u[IPT];
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q) u[q] = u_of(s_v[b0 + q + 2], s_v[b0 + q + 1], s_v[b0 + q]);
-    uint32_t out[SCAN_IPT];
+    for (int q = 0; q < IPT; ++q) u[q] = u_of(s_v[b0 + q + 2], s_v[b0 + q + 1], s_v[b0 + q]);
+    uint32_t out[IPT];
     Scan::run(sm, u, out, J.nblocks > 1 ? L.status + J.block0 : nullptr, local, L.epoch, L.devstat);
     const int64_t j0 = jb + b0;
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q)
+    for (int q = 0; q < IPT; ++q)
         if (j0 + q < J.n_out) J.out[j0 + q] = out[q];
 }
 

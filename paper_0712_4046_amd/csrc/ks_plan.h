@@ -37,7 +37,7 @@ struct PackGeom {
     int which;  // 0: f, 1: g
     int flags;  // PK_*
     int64_t L, n_out, op_off, blocks;
-    bool small;  // at most SMALL_BL limbs: one wave
+    bool small;  // at most small_bl(ipt) limbs: one wave
 };
 struct MulGeom {
     int fa, fb;  // operand (pack) indices
@@ -55,7 +55,7 @@ struct MulGeom {
 struct NormGeom {
     int nterms, prod[2], sign[2], shift;
     int64_t off_bit0, off_period, off_count, n_in, n_out, out_off, blocks;
-    bool small;  // at most SMALL_BL limbs: one wave
+    bool small;  // at most small_bl(ipt) limbs: one wave
 };
 struct ExtractGeom {
     int src;  // norm index
@@ -72,6 +72,7 @@ struct ChainGeom {
 
 struct Geom {
     Spec sp;
+    int ipt = SCAN_IPT_SINGLE;  // limbs per thread of the carry-scan kernels
     int variant = 0, e = 0, w_out = 0, off = -1, nw = 0, aw = 0, chain_lds = 0;
     int64_t chain_nd = 0;  // bits of a reconstruction digit (2N four-point, N reciprocal)
     int64_t N = 0, D = 0, m0 = 0, m1 = 0, nf = 0, ng = 0;
@@ -109,14 +110,15 @@ struct Ctl {
 
 // jobs of one or many products, per stage (anchor and chain lists keyed by template parameter)
 struct JobLists {
+    int ipt = SCAN_IPT_SINGLE;  // limbs per thread of the carry-scan launches (as planned)
     std::vector<PackJob> pack;
-    std::vector<PackJob> pack_small;  // jobs of at most SMALL_BL limbs
+    std::vector<PackJob> pack_small;  // jobs of at most small_bl(ipt) limbs
     std::vector<MulJob> mul;
     std::vector<MulJob> mul_wave;  // small products: one wave per tile (blocks count tiles)
     std::vector<DigitJob> digit;
     std::vector<MfmaJob> mfma;
     std::vector<NormJob> norm;
-    std::vector<NormJob> norm_small;  // jobs of at most SMALL_BL limbs
+    std::vector<NormJob> norm_small;  // jobs of at most small_bl(ipt) limbs
     std::vector<ExtractJob> extract;
     std::map<int, std::vector<AnchorJob>> anchor;  // by limbs per input coefficient
     std::map<int, std::vector<ChainJob>> chain;    // by words per reconstruction digit

@@ -19,28 +19,30 @@ namespace ks {
 
 // ---- pack ------------------------------------------------------------------------------------
 
+template <int IPT>
 __global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) {
     int64_t local;
     const PackJob J = get_job(L, (int64_t)blockIdx.x, local);
-    pack_block<SCAN_TPB>(J, local, ctl_of(L));
+    pack_block<SCAN_TPB, IPT>(J, local, ctl_of(L));
 }
 
-// jobs of at most SMALL_BL limbs (one block each): one wave per job
+// jobs of at most small_bl(IPT) limbs (one block each): one wave per job
+template <int IPT>
 __global__ __launch_bounds__(SMALL_TPB) void pack_small_kernel(Launch<PackJob> L) {
     int64_t local;
     const PackJob J = get_job(L, (int64_t)blockIdx.x, local);
-    pack_block<SMALL_TPB>(J, local, ctl_of(L));
+    pack_block<SMALL_TPB, IPT>(J, local, ctl_of(L));
 }
 
 // Pack and anchors in one launch: blocks [0, pack blocks) pack,
 // the rest compute anchors, which read only the inputs and so run beside the packing.
 static_assert(SCAN_TPB == ANCHOR_TPB, "pack and anchor blocks share one launch");
-template <int W>
+template <int W, int IPT>
 __global__ __launch_bounds__(SCAN_TPB) void pack_anchor_kernel(Launch<PackJob> Lp, Launch<AnchorJob> La) {
     int64_t local;
     if ((int64_t)blockIdx.x < Lp.total_blocks) {
         const PackJob J = get_job(Lp, (int64_t)blockIdx.x, local);
-        pack_block<SCAN_TPB>(J, local, ctl_of(Lp));
+        pack_block<SCAN_TPB, IPT>(J, local, ctl_of(Lp));
     } else {
         const AnchorJob J = get_job(La, (int64_t)blockIdx.x - Lp.total_blocks, local);
         anchor_block<W>(J, local);
@@ -49,25 +51,25 @@ __global__ __launch_bounds__(SCAN_TPB) void pack_anchor_kernel(Launch<PackJob> L
 
 // ---- normalize --------------------------------------------------------------------------------
 
-// Each thread handles SCAN_IPT consecutive limb positions j0 .. j0+IPT-1 and needs the column
+// Each thread handles IPT consecutive limb positions j0 .. j0+IPT-1 and needs the column
 // values v at j0-2 .. j0+IPT-1.  Column j of a product is piece 0 of column-sum j, piece 1
 // of j-1 and piece 2 of j-2, so the thread reads one contiguous window of column sums
 // (columns j0-4 .. j0+IPT-1) plus the operand limbs of the sign corrections -- fixed-size,
 // branch-free, clamped loads that are all in flight together.
-constexpr int NWIN = SCAN_IPT + 4;  // column-sum window
-constexpr int NV = SCAN_IPT + 2;    // column values j0-2 .. j0+IPT-1
+// (columns j0-4 .. j0+IPT-1: IPT + 4 of them; column values j0-2 .. j0+IPT-1: IPT + 2)
 
 struct TermSigns {
     bool negA[2], negB[2];
 };
 
-// v[m] += sign * (column j0 - 2 + m of the product), m in [0, NV).  Column sums come as
+// v[m] += sign * (column j0 - 2 + m of the product), m in [0, IPT + 2).  Column sums come as
 // three uint32 pieces per column (value j gets piece 0 of j, 1 of j-1, 2 of j-2) or as two
 // uint64 per column, x + y 2^32 with x non-negative and y signed (the matrix cores' balanced
 // digits give signed partial sums), i.e. four uint32 words (value j gets word 0 of j, words 1
 // and 2 of j-1, word 3 of j-2 read as a signed 32-bit value).
-template <int P>
-__device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int64_t (&acc)[NV]) {
+template <int P, int IPT>
+__device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int64_t (&acc)[IPT + 2]) {
+    constexpr int NWIN = IPT + 4, NV = IPT + 2;
     const int64_t c0 = j0 - 4;
     uint32_t x[P * NWIN];
     // one vector load per column (clamped address, zeroed outside the product)
@@ -90,13 +92,15 @@ __device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int
     }
 }
 
+template <int IPT>
 __device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bool negB, int64_t j0,
-                                                int64_t (&v)[NV]) {
+                                                int64_t (&v)[IPT + 2]) {
+    constexpr int NV = IPT + 2;
     int64_t acc[NV];
     if (T.fmt == NORM_FMT_XY)
-        column_window<4>(T, j0, acc);
+        column_window<4, IPT>(T, j0, acc);
     else
-        column_window<3>(T, j0, acc);
+        column_window<3, IPT>(T, j0, acc);
     // the multiplier works on the unsigned readings of two's-complement operands:
     // A B = Au Bu - [A<0] Bu 2^(32 na) - [B<0] Au 2^(32 nb) + [A<0][B<0] 2^(32 (na+nb))
     if (negA) {
@@ -139,12 +143,14 @@ __device__ __forceinline__ int64_t offset_column(const NormJob &J, int64_t j) {
 }
 
 // column values for positions j0-2 .. j0+IPT-1 (zero outside [0, n_in))
-__device__ __forceinline__ void norm_window(const NormJob &J, const TermSigns &ts, int64_t j0, int64_t (&v)[NV]) {
+template <int IPT>
+__device__ __forceinline__ void norm_window(const NormJob &J, const TermSigns &ts, int64_t j0, int64_t (&v)[IPT + 2]) {
+    constexpr int NV = IPT + 2;
 #pragma unroll
     for (int m = 0; m < NV; ++m) v[m] = 0;
 #pragma unroll
     for (int q = 0; q < 2; ++q)
-        if (q < J.nterms) add_term_window(J.term[q], ts.negA[q], ts.negB[q], j0, v);
+        if (q < J.nterms) add_term_window<IPT>(J.term[q], ts.negA[q], ts.negB[q], j0, v);
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
         const int64_t j = j0 - 2 + m;
@@ -152,12 +158,13 @@ __device__ __forceinline__ void norm_window(const NormJob &J, const TermSigns &t
     }
 }
 
-// A block of recombination job J with TPB threads (TPB * SCAN_IPT limbs per block); the
-// caller looks the job up in its own kernel arguments.
-template <int TPB>
+// A block of recombination job J with TPB threads (TPB * IPT limbs per block); the caller
+// looks the job up in its own kernel arguments.
+template <int TPB, int IPT>
 __device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local, const LaunchCtl L) {
-    constexpr int64_t BL = (int64_t)TPB * SCAN_IPT;
-    typedef BlockCarryScan<TPB, SCAN_IPT> Scan;
+    constexpr int64_t BL = (int64_t)TPB * IPT;
+    constexpr int NV = IPT + 2;
+    typedef BlockCarryScan<TPB, IPT> Scan;
     __shared__ typename Scan::Smem sm;
     __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_limb[BL + 1];
@@ -167,7 +174,7 @@ __device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local,
     if (J.nblocks > 1) local = s_ticket;
     const int tid = threadIdx.x;
     const int64_t jb = local * BL;
-    const int64_t j0 = jb + (int64_t)tid * SCAN_IPT;
+    const int64_t j0 = jb + (int64_t)tid * IPT;
     TermSigns ts;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -176,27 +183,27 @@ __device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local,
         ts.negB[q] = q < J.nterms && (T.b[T.nb - 1] >> 31) != 0;
     }
     int64_t v[NV];
-    norm_window(J, ts, j0, v);
-    int64_t u[SCAN_IPT];
+    norm_window<IPT>(J, ts, j0, v);
+    int64_t u[IPT];
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q) u[q] = u_of(v[q + 2], v[q + 1], v[q]);
+    for (int q = 0; q < IPT; ++q) u[q] = u_of(v[q + 2], v[q + 1], v[q]);
     if (tid == TPB - 1) {
         // the first limb of the next block is needed by the shift: its value before carries
         int64_t vn[NV];
-        norm_window(J, ts, j0 + SCAN_IPT, vn);
+        norm_window<IPT>(J, ts, j0 + IPT, vn);
         s_tail[0] = u_of(vn[2], vn[1], vn[0]);
     }
-    uint32_t out[SCAN_IPT];
+    uint32_t out[IPT];
     const int kout = Scan::run(sm, u, out, J.nblocks > 1 ? L.status + J.block0 : nullptr, local, L.epoch, L.devstat);
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q) s_limb[tid * SCAN_IPT + q] = out[q];
+    for (int q = 0; q < IPT; ++q) s_limb[tid * IPT + q] = out[q];
     if (tid == TPB - 1) s_limb[BL] = (uint32_t)(uint64_t)(s_tail[0] + kout);
     __syncthreads();
     // write V >> shift: output limb o takes limbs o + w and o + w + 1 (striped, coalesced)
     const int64_t w = J.shift >> 5;
     const int r = J.shift & 31;
 #pragma unroll
-    for (int q = 0; q < SCAN_IPT; ++q) {
+    for (int q = 0; q < IPT; ++q) {
         const int li = q * TPB + tid;
         const int64_t o = jb + li - w;
         if (o < 0 || o >= J.n_out) continue;
@@ -207,16 +214,18 @@ __device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local,
 
 // at least five waves per SIMD: the register budget (96) that keeps the column window's loads
 // in flight without spilling, and one more wave than the unconstrained allocation (100)
+template <int IPT>
 __global__ __launch_bounds__(SCAN_TPB, 5) void normalize_kernel(Launch<NormJob> L) {
     int64_t local;
     const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
-    normalize_block<SCAN_TPB>(J, local, ctl_of(L));
+    normalize_block<SCAN_TPB, IPT>(J, local, ctl_of(L));
 }
 
+template <int IPT>
 __global__ __launch_bounds__(SMALL_TPB, 5) void normalize_small_kernel(Launch<NormJob> L) {
     int64_t local;
     const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
-    normalize_block<SMALL_TPB>(J, local, ctl_of(L));
+    normalize_block<SMALL_TPB, IPT>(J, local, ctl_of(L));
 }
 
 // ---- clearing scratch words (a kernel rather than a memset, so runs can be graph-captured) ------
@@ -235,44 +244,60 @@ hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s) {
 
 // ---- host launchers -----------------------------------------------------------------------------
 
-hipError_t launch_pack(const Launch<PackJob> &L, hipStream_t s) {
+// the instantiation of a scan kernel for the plan's limbs per thread (2 or 4)
+#define KS_SCAN_IPT(ipt, K, ...)                            \
+    do {                                                    \
+        if ((ipt) == SCAN_IPT_BATCH)                        \
+            ks_launch(K<SCAN_IPT_BATCH>, __VA_ARGS__);      \
+        else                                                \
+            ks_launch(K<SCAN_IPT_SINGLE>, __VA_ARGS__);     \
+    } while (0)
+
+hipError_t launch_pack(const Launch<PackJob> &L, int ipt, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    ks_launch(pack_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
+    KS_SCAN_IPT(ipt, pack_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
     return hipGetLastError();
 }
 
-hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, hipStream_t s) {
-    if (La.total_blocks <= 0) return launch_pack(Lp, s);
+template <int IPT>
+static hipError_t pack_anchor_w(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, hipStream_t s) {
     dim3 g((unsigned)(Lp.total_blocks + La.total_blocks)), b(SCAN_TPB);
     switch (w_in) {
-        case 1: ks_launch(pack_anchor_kernel<1>, g, b, 0, s, Lp, La); break;
-        case 2: ks_launch(pack_anchor_kernel<2>, g, b, 0, s, Lp, La); break;
-        case 3: ks_launch(pack_anchor_kernel<3>, g, b, 0, s, Lp, La); break;
-        case 4: ks_launch(pack_anchor_kernel<4>, g, b, 0, s, Lp, La); break;
-        case 5: ks_launch(pack_anchor_kernel<5>, g, b, 0, s, Lp, La); break;
-        case 6: ks_launch(pack_anchor_kernel<6>, g, b, 0, s, Lp, La); break;
-        case 7: ks_launch(pack_anchor_kernel<7>, g, b, 0, s, Lp, La); break;
-        case 8: ks_launch(pack_anchor_kernel<8>, g, b, 0, s, Lp, La); break;
+        case 1: ks_launch(pack_anchor_kernel<1, IPT>, g, b, 0, s, Lp, La); break;
+        case 2: ks_launch(pack_anchor_kernel<2, IPT>, g, b, 0, s, Lp, La); break;
+        case 3: ks_launch(pack_anchor_kernel<3, IPT>, g, b, 0, s, Lp, La); break;
+        case 4: ks_launch(pack_anchor_kernel<4, IPT>, g, b, 0, s, Lp, La); break;
+        case 5: ks_launch(pack_anchor_kernel<5, IPT>, g, b, 0, s, Lp, La); break;
+        case 6: ks_launch(pack_anchor_kernel<6, IPT>, g, b, 0, s, Lp, La); break;
+        case 7: ks_launch(pack_anchor_kernel<7, IPT>, g, b, 0, s, Lp, La); break;
+        case 8: ks_launch(pack_anchor_kernel<8, IPT>, g, b, 0, s, Lp, La); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_pack_small(const Launch<PackJob> &L, hipStream_t s) {
+hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, int ipt,
+                              hipStream_t s) {
+    if (La.total_blocks <= 0) return launch_pack(Lp, ipt, s);
+    return ipt == SCAN_IPT_BATCH ? pack_anchor_w<SCAN_IPT_BATCH>(Lp, La, w_in, s)
+                                 : pack_anchor_w<SCAN_IPT_SINGLE>(Lp, La, w_in, s);
+}
+
+hipError_t launch_pack_small(const Launch<PackJob> &L, int ipt, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    ks_launch(pack_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
+    KS_SCAN_IPT(ipt, pack_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
     return hipGetLastError();
 }
 
-hipError_t launch_normalize_small(const Launch<NormJob> &L, hipStream_t s) {
+hipError_t launch_normalize_small(const Launch<NormJob> &L, int ipt, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    ks_launch(normalize_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
+    KS_SCAN_IPT(ipt, normalize_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
     return hipGetLastError();
 }
 
-hipError_t launch_normalize(const Launch<NormJob> &L, hipStream_t s) {
+hipError_t launch_normalize(const Launch<NormJob> &L, int ipt, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    ks_launch(normalize_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
+    KS_SCAN_IPT(ipt, normalize_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
     return hipGetLastError();
 }
 
