@@ -18,6 +18,22 @@
 
 namespace ks {
 
+// MUL_R consecutive LDS words (16-byte aligned for 4, 8-byte aligned for 2) in one read
+__device__ __forceinline__ void lds_words(const uint32_t *p, uint32_t (&v)[MUL_R]) {
+    static_assert(MUL_R == 2 || MUL_R == 4, "LDS reads of 2 or 4 words");
+    if constexpr (MUL_R == 4) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(p);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    } else {
+        const uint2 x = *reinterpret_cast<const uint2 *>(p);
+        v[0] = x.x;
+        v[1] = x.y;
+    }
+}
+
 // WAVE = false: a block owns one MUL_T-column tile and its waves split the i range (large
 // products).  WAVE = true: every wave owns one tile and runs its whole i range alone, and the
 // waves of a block take consecutive tiles of the launch, of one product or of several (small
@@ -92,17 +108,23 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
         if (it + 1 < niter) fetch(it + 1);
         if (active) {
             // E[idx] = sb[base - x0 + idx]; column r at step x0 + u uses E[R - 1 + r - u]
-            uint2 ehi = *reinterpret_cast<const uint2 *>(&sb[wv][base + MUL_R]);
+            uint32_t ehi[MUL_R];
+            lds_words(&sb[wv][base + MUL_R], ehi);
             for (int x0 = 0; x0 < MUL_CI; x0 += MUL_R) {
-                const uint2 elo = *reinterpret_cast<const uint2 *>(&sb[wv][base - x0]);
-                const uint2 av = *reinterpret_cast<const uint2 *>(&sa[wv][x0]);
-                const uint32_t E[2 * MUL_R] = {elo.x, elo.y, ehi.x, ehi.y};
-                const uint32_t A[MUL_R] = {av.x, av.y};
+                uint32_t elo[MUL_R], A[MUL_R], E[2 * MUL_R];
+                lds_words(&sb[wv][base - x0], elo);
+                lds_words(&sa[wv][x0], A);
+#pragma unroll
+                for (int t = 0; t < MUL_R; ++t) {
+                    E[t] = elo[t];
+                    E[MUL_R + t] = ehi[t];
+                }
 #pragma unroll
                 for (int u = 0; u < MUL_R; ++u)
 #pragma unroll
                     for (int r = 0; r < MUL_R; ++r) mac96(lo[r], hi[r], A[u], E[MUL_R - 1 + r - u]);
-                ehi = elo;
+#pragma unroll
+                for (int t = 0; t < MUL_R; ++t) ehi[t] = elo[t];
             }
         }
         sync();
