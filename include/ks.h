@@ -115,6 +115,28 @@ int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_
                int32_t variant, void *stream, uint64_t *h);
 
 /*
+ * h = f g in (Z/pZ)[x, y] by Kronecker substitution into (Z/pZ)[x] (Section 2).
+ *   f, g    device, len_y rows of len_x uint64 residues each (row i: the coefficients of
+ *           f_i(x), x^0 first, for f = sum_i f_i(x) y^i), each in [0, p)
+ *   len_x, len_y  >= 1, the same for f and g (the section's assumption)
+ *   p       odd modulus, 3 <= p < 2^62 (the negated points divide by 2)
+ *   variant the substitution: KS_VARIANT_KS1 (standard, y = x^N, N = 2 len_x - 1, one product
+ *           of length 2 len_x len_y - len_x - len_y + 1; Section 2.1), KS_VARIANT_RECIP2
+ *           (y = x^N and x^-N, N = len_x, two products of length len_x len_y; Section 2.2),
+ *           KS_VARIANT_NEG2 (y = +-x^N, N = len_x; Section 2.3), KS_VARIANT_KS4 (y = +-x^N,
+ *           +-x^-N, N = ceil(len_x / 2), four products of length N (len_y - 1) + len_x;
+ *           Section 2.4), KS_VARIANT_AUTO (four points)
+ *   inner   KS_VARIANT_* | optional KS_ENGINE_* for the products in (Z/pZ)[x], which run as
+ *           ks_mul_mod does (KS_SIGNED is rejected)
+ *   h       device, (2 len_y - 1) rows of (2 len_x - 1) uint64 residues in [0, p)
+ * Scratch (the evaluations, the univariate products) is held per stream by the library.
+ * Residues >= p are reported as KS_ERANGE by the next status query; a recovery whose
+ * coefficients above the product's length do not vanish as KS_EINTERNAL.
+ */
+int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t len_y, uint64_t p,
+                 int32_t variant, int32_t inner, void *stream, uint64_t *h);
+
+/*
  * Synchronise `stream`, then return and clear the device status of the library-owned pool
  * of that stream: KS_OK, KS_ERANGE or KS_EINTERNAL (KS_EHIP if the synchronisation fails).
  */

@@ -732,6 +732,8 @@ struct Pool {
     Ctl ctl;
     char *ws = nullptr;
     size_t bytes = 0;
+    char *stage = nullptr;  // bivariate products: evaluations, univariate products, chunk sums
+    size_t stage_bytes = 0;
 };
 static std::mutex g_pool_mu;
 static std::map<hipStream_t, Pool *> g_pools;
@@ -928,6 +930,132 @@ int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_
     return mul_common(reinterpret_cast<const uint32_t *>(f), reinterpret_cast<const uint32_t *>(g), sp, stream, h);
 }
 
+// ---- bivariate products over Z/pZ (Section 2) --------------------------------------------------
+
+int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t len_y, uint64_t p, int32_t variant,
+                 int32_t inner, void *stream, uint64_t *h) {
+    if (!f || !g || !h) return KS_EINVAL;
+    if (len_x < 1 || len_y < 1 || p < 3 || !(p & 1) || (p >> 62)) return KS_EINVAL;
+    if (variant & ~KS_VARIANT_MASK) return KS_EINVAL;
+    if (inner & KS_SIGNED) return KS_EINVAL;
+    int v = variant & KS_VARIANT_MASK;
+    if (v == KS_VARIANT_AUTO) v = KS_VARIANT_KS4;
+    int k;
+    int64_t n;
+    switch (v) {
+        case KS_VARIANT_KS1: k = 1; n = 2 * len_x - 1; break;       // Section 2.1
+        case KS_VARIANT_RECIP2: k = 2; n = len_x; break;            // Section 2.2
+        case KS_VARIANT_NEG2: k = 2; n = len_x; break;              // Section 2.3
+        case KS_VARIANT_KS4: k = 4; n = (len_x + 1) / 2; break;     // Section 2.4
+        default: return KS_EINVAL;
+    }
+    const int64_t le = n * (len_y - 1) + len_x, lh = 2 * le - 1;
+    if (le > (int64_t)1 << 30) return KS_EINVAL;
+    const int bits = bitlen_u64(p - 1);
+    int rc = validate_spec(le, le, bits, inner, false);
+    if (rc != KS_OK) return rc;
+    if (device_ok() != 1) return KS_EUNSUPPORTED;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Pool *pl = nullptr;
+    rc = get_pool(s, 0, 1, &pl);
+    if (rc != KS_OK) return rc;
+    // stage: 2k evaluations, k products, chunk sums of up to two gluings
+    const int64_t m = v == KS_VARIANT_KS4 ? 2 * n : n, count = v == KS_VARIANT_KS4 ? len_y : 2 * len_y - 1;
+    const int64_t nchunks = cdiv((count + 1) / 2, P2_CHUNK);
+    const int64_t words = 2 * k * le + k * lh + 2 * nchunks * 4 * m;
+    const size_t need = (size_t)words * 8;
+    if (pl->stage_bytes < need) {
+        if (pl->stage) {
+            if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;
+            hipFree(pl->stage);
+            pl->stage = nullptr;
+            pl->stage_bytes = 0;
+        }
+        void *w = nullptr;
+        if (hipMalloc(&w, need) != hipSuccess) return KS_ENOMEM;
+        pl->stage = reinterpret_cast<char *>(w);
+        pl->stage_bytes = need;
+    }
+    uint64_t *ev = reinterpret_cast<uint64_t *>(pl->stage), *prod = ev + 2 * k * le, *sums = prod + k * lh;
+    P2Eval E;
+    memset(&E, 0, sizeof(E));
+    E.f = f;
+    E.g = g;
+    E.out = ev;
+    E.lx = len_x;
+    E.ly = len_y;
+    E.n = n;
+    E.le = le;
+    E.p = p;
+    E.k = k;
+    E.devstat = pl->ctl.devstat;
+    // evaluation points in the order of the products: x^N, then -x^N or x^-N (two points),
+    // or x^N, -x^N, x^-N, -x^-N (four)
+    for (int q = 0; q < k; ++q) {
+        E.neg[q] = (v == KS_VARIANT_NEG2 && q == 1) || (v == KS_VARIANT_KS4 && (q & 1));
+        E.rev[q] = (v == KS_VARIANT_RECIP2 && q == 1) || (v == KS_VARIANT_KS4 && q >= 2);
+    }
+    if (timed("p2_eval", s, [&] { return launch_p2_eval(E, s); }) != hipSuccess) return KS_EHIP;
+    for (int q = 0; q < k; ++q) {
+        Spec sp{le, le, bits, 2, false, p, inner & KS_VARIANT_MASK, inner & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+        rc = mul_common(reinterpret_cast<const uint32_t *>(ev + q * le), reinterpret_cast<const uint32_t *>(ev + (k + q) * le),
+                        sp, stream, prod + q * lh);
+        if (rc != KS_OK) return rc;
+    }
+    auto side = [&](int a, int b, int comb, int64_t off) {
+        P2Side S;
+        memset(&S, 0, sizeof(S));
+        S.x = prod + a * lh;
+        S.y = b >= 0 ? prod + b * lh : nullptr;
+        S.len = lh;
+        S.off = off;
+        S.comb = comb;
+        return S;
+    };
+    const int64_t width = 2 * len_x - 1, rows = 2 * len_y - 1;
+    hipError_t err = hipSuccess;
+    if (v == KS_VARIANT_KS1 || v == KS_VARIANT_NEG2) {
+        P2Readoff R;
+        memset(&R, 0, sizeof(R));
+        R.even = v == KS_VARIANT_KS1 ? side(0, -1, 0, 0) : side(0, 1, 1, 0);
+        R.odd = v == KS_VARIANT_KS1 ? side(0, -1, 0, 0) : side(0, 1, -1, 0);
+        R.out = h;
+        R.rows = rows;
+        R.width = width;
+        R.n = n;
+        R.p = p;
+        err = timed("p2_recon", s, [&] { return launch_p2_readoff(R, s); });
+    } else {
+        P2Glue G;
+        memset(&G, 0, sizeof(G));
+        G.out = h;
+        G.m = m;
+        G.width = width;
+        G.p = p;
+        G.devstat = pl->ctl.devstat;
+        auto part = [&](int i, P2Side A, P2Side B, int64_t cnt, int64_t row0, int64_t rstep) {
+            P2GluePart &P = G.part[i];
+            P.A = A;
+            P.B = B;
+            P.sums = sums + i * nchunks * 4 * m;
+            P.count = cnt;
+            P.row0 = row0;
+            P.rstep = rstep;
+            P.nchunks = cdiv((cnt + 1) / 2, P2_CHUNK);
+            G.nparts = i + 1;
+        };
+        if (v == KS_VARIANT_RECIP2) {
+            part(0, side(0, -1, 0, 0), side(1, -1, 0, 0), rows, 0, 1);
+        } else {
+            // even part (H1 + H2) / 2 and (H3 + H4) / 2, odd part the halved differences / x^N
+            part(0, side(0, 1, 1, 0), side(2, 3, 1, 0), len_y, 0, 2);
+            if (len_y > 1) part(1, side(0, 1, -1, n), side(2, 3, -1, n), len_y - 1, 1, 2);
+        }
+        err = timed("p2_recon", s, [&] { return launch_p2_glue(G, s); });
+    }
+    return err == hipSuccess ? KS_OK : KS_EHIP;
+}
+
 int ks_stream_status(void *stream) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Pool *p = nullptr;
@@ -982,8 +1110,8 @@ int ks_profile_reset(void) {
 
 int ks_profile_read(const char *name, int64_t *launches, double *total_ms) {
     if (!name || !launches || !total_ms) return KS_EINVAL;
-    static const char *known[] = {"pack",  "mul_valu", "mul_mfma", "normalize", "anchor",
-                                  "recon", "extract",  "digitize", "finish"};
+    static const char *known[] = {"pack",  "mul_valu", "mul_mfma", "normalize", "anchor",  "recon",
+                                  "extract", "digitize", "finish",  "p2_eval",   "p2_recon"};
     bool ok = false;
     for (const char *k : known) ok = ok || strcmp(k, name) == 0;
     if (!ok) return KS_EINVAL;

@@ -225,6 +225,55 @@ struct ChainJob {
 // (recip = 0 stands for d = 1): a reciprocal multiply instead of a 64-bit division
 inline uint64_t div_recip(uint64_t d) { return d <= 1 ? 0 : (uint64_t)(~0ull / d) + 1; }
 
+// ---- bivariate products over Z/pZ (Section 2) -------------------------------------------------
+
+// the k evaluations of f and of g (k = 1, 2 or 4): out holds f's k polynomials of `le`
+// residues, then g's; evaluation q substitutes y = (neg[q] ? -1 : 1) x^(+-n), rev[q] for the
+// (normalised) reciprocal point
+struct P2Eval {
+    const uint64_t *f, *g;  // L_y rows of L_x residues
+    uint64_t *out;
+    int64_t lx, ly, n, le;
+    uint64_t p;
+    int32_t k, pad;
+    int32_t neg[4], rev[4];
+    uint32_t *devstat;
+};
+
+// one side of the recovery: value(pos) = x[pos + off] (comb 0) or (x +- y)[pos + off] / 2
+// (comb +-1), zero outside [0, len)
+struct P2Side {
+    const uint64_t *x, *y;
+    int64_t len, off;
+    int32_t comb, pad;
+};
+
+// h_k[c] = (k odd ? odd : even)(k n + c), rows x width residues
+struct P2Readoff {
+    P2Side even, odd;
+    uint64_t *out;
+    int64_t rows, width, n;
+    uint64_t p;
+};
+
+// gluing of `count` polynomials at block m from A (forward) and B (reversed); u_j goes to
+// output row row0 + j rstep (width residues per row); sums: nchunks x 4m chunk totals, chunks
+// of P2_CHUNK steps.  One launch glues up to two parts (the four-point even and odd parts).
+constexpr int P2_CHUNK = 8;
+struct P2GluePart {
+    P2Side A, B;
+    uint64_t *sums;
+    int64_t count, row0, rstep, nchunks;
+};
+struct P2Glue {
+    P2GluePart part[2];
+    int32_t nparts, pad;
+    uint64_t *out;
+    int64_t m, width;
+    uint64_t p;
+    uint32_t *devstat;
+};
+
 // Pointer fields of a job are addresses relative to a base: inputs (f, g) to base_in,
 // outputs (h) to base_out, scratch to base_ws.  Single products pass absolute addresses with
 // zero bases; batch plans store byte offsets once and the bases arrive with each run.

@@ -65,6 +65,7 @@ def lib() -> ctypes.CDLL:
         "ks_out_limbs": ([i64, i64, i32], i64),
         "ks_mul": ([P, P, i64, i64, i32, i32, P, P], ctypes.c_int),
         "ks_mul_mod": ([P, P, i64, i64, u64, i32, P, P], ctypes.c_int),
+        "ks_mul_poly2": ([P, P, i64, i64, u64, i32, i32, P, P], ctypes.c_int),
         "ks_stream_status": ([P], ctypes.c_int),
         "ks_plan": ([i64, i64, i32, i32, ctypes.POINTER(PlanInfo)], ctypes.c_int),
         "ks_profile_enable": ([i32], ctypes.c_int),
@@ -180,6 +181,24 @@ def mul_mod(f, g, p: int, variant: str = "auto", engine=None, stream=None, out=N
     rc = lib().ks_mul_mod(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()), lf, lg, p,
                           _flags(variant, False, engine), _stream_ptr(stream), ctypes.c_void_p(out.data_ptr()))
     _check(rc, "ks_mul_mod")
+    return out
+
+
+def mul_poly2(f, g, p: int, variant: str = "auto", inner: str = "auto", engine=None, stream=None, out=None):
+    """h = f g in (Z/pZ)[x, y] (ks_mul_poly2); f, g are (len_y, len_x) int64 CUDA tensors of
+    residues in [0, p) (row i: the coefficients of f_i(x)); h is (2 len_y - 1, 2 len_x - 1)."""
+    import torch
+    if f.dim() != 2 or f.shape != g.shape or f.dtype != torch.int64 or g.dtype != torch.int64:
+        raise ValueError("inputs must be 2-D int64 tensors of residues of the same shape")
+    if not (f.is_contiguous() and g.is_contiguous()):
+        raise ValueError("inputs must be contiguous")
+    ly, lx = f.shape
+    if out is None:
+        out = torch.empty((2 * ly - 1, 2 * lx - 1), dtype=torch.int64, device=f.device)
+    rc = lib().ks_mul_poly2(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()), lx, ly, p,
+                            KS_VARIANT[variant], _flags(inner, False, engine), _stream_ptr(stream),
+                            ctypes.c_void_p(out.data_ptr()))
+    _check(rc, "ks_mul_poly2")
     return out
 
 

@@ -136,6 +136,26 @@ def paper_fig_pair(bits: int, length: int, seed: int = 6):
     return n, gen.integers(0, n, size=length, dtype=np.uint64), gen.integers(0, n, size=length, dtype=np.uint64)
 
 
+def poly2_pair(ly: int, lx: int, p: int, seed: int):
+    """(f, g): bivariate polynomials over Z/pZ as (ly, lx) uint64 arrays of residues uniform in
+    [0, p) (row i: the coefficients of f_i(x))."""
+    gen = rng(seed)
+    return (gen.integers(0, p, size=(ly, lx), dtype=np.uint64), gen.integers(0, p, size=(ly, lx), dtype=np.uint64))
+
+
+# Bivariate workload of the paper's polynomial case (Section 2): products in (Z/pZ)[x, y] of
+# the shape of polynomials of length 4096 over an extension field of degree 16 (coefficients
+# of x-degree < 16), p a random odd 60-bit modulus
+POLY2_LX, POLY2_LY = 16, 4096
+
+
+def poly2_workload(seed: int = 7):
+    """(p, f, g) of the bivariate workload."""
+    p = paper_fig_modulus(60, seed)
+    f, g = poly2_pair(POLY2_LY, POLY2_LX, p, seed)
+    return p, f, g
+
+
 def config4(count: int = 64, length: int = 65536, seed: int = 4):
     """Modular batch: `count` products in (Z/pZ)[x], f, g uniform in [0, p), length 65536."""
     gen = rng(seed)
