@@ -43,7 +43,8 @@ MEASURED_TRAFFIC = {"pack": 996137, "digitize": 1120122, "mul_mfma": 6082171, "n
                     "finish": 441719}
 MEASURED_TRAFFIC_CONFIG4 = {"pack": 3129285102, "digitize": 344519688, "mul_mfma": 1777780716,
                             "normalize": 1131572265, "recon": 349067080, "finish": 271321320}
-KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract")
+KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
+           "p2_eval", "p2_recon")
 
 
 def parse():
@@ -55,6 +56,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-paper", action="store_true", help="skip the (Z/nZ)[x] sweep of the paper's figures")
+    ap.add_argument("--no-poly2", action="store_true", help="skip the bivariate (Z/pZ)[x, y] workload")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
 
@@ -68,6 +70,38 @@ def time_variant(ks, torch, tf, tg, bits, variant, signed, steps, warmup, out):
         ks.mul(tf, tg, bits, variant, signed, out=out)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def poly2_line(ks, torch, wl, reps=20):
+    """The paper's polynomial case (Section 2) on the bivariate workload: h = f g in
+    (Z/pZ)[x, y], L_x = 16, L_y = 4096, p a random odd 60-bit modulus, through the standard,
+    reciprocal, negated and four-point substitutions into (Z/pZ)[x] (ks_mul_poly2), timed with
+    inputs resident on the device; each substitution's result must equal the standard one's
+    (checked on the device; the oracle checks sampled coefficients in the GPU tests)."""
+    p, f, g = wl.poly2_workload()
+    tf = torch.from_numpy(f.view(np.int64)).cuda()
+    tg = torch.from_numpy(g.view(np.int64)).cuda()
+    ms, res = {}, {}
+    for v in ("ks1", "recip2", "neg2", "ks4"):
+        o = torch.empty((2 * f.shape[0] - 1, 2 * f.shape[1] - 1), dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            ks.mul_poly2(tf, tg, p, v, out=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ks.mul_poly2(tf, tg, p, v, out=o)
+        torch.cuda.synchronize()
+        ms[v] = (time.perf_counter() - t0) / reps * 1e3
+        res[v] = o
+    ks.check()
+    if not all(torch.equal(res[v], res["ks1"]) for v in res):
+        raise SystemExit("bivariate workload: substitutions disagree")
+    kern = kernel_times(ks, lambda: ks.mul_poly2(tf, tg, p, "ks4", out=res["ks4"]), 5)
+    return {"workload": f"(Z/pZ)[x, y], L_x = {f.shape[1]}, L_y = {f.shape[0]}, p = {p} (60-bit odd), "
+                        f"residues uniform in [0, p), seed 7",
+            "ms": ms, "products_per_s": {v: 1e3 / ms[v] for v in ms},
+            "speedup_vs_ks1": {v: ms["ks1"] / ms[v] for v in ("recip2", "neg2", "ks4")},
+            "ks4_kernels_us_per_run": {k: x["per_run_us"] for k, x in kern.items()}}
 
 
 def paper_sweep(ks, torch, wl):
@@ -278,6 +312,7 @@ def main():
             "config4": "64 products mod a 60-bit odd p, L = 65536, residues uniform in [0, p), seed 4"}
 
     paper = None if args.no_paper else paper_sweep(ks, torch, wl)
+    bivariate = None if args.no_poly2 else poly2_line(ks, torch, wl)
 
     p4 = plans["ks4"]
     ms = t["ks4"] * 1000.0
@@ -311,6 +346,7 @@ def main():
         "cpu_baseline": cpu,
         "batch": batch,
         "paper_figures": paper,
+        "poly2": bivariate,
     }
     print(json.dumps(rec))
 

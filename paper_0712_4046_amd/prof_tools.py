@@ -21,7 +21,8 @@ def workload(name: str = "config2", reps: int = 5):
     """A plain device copy of COPY_MIB MiB (the FETCH_SIZE / WRITE_SIZE calibration), then
     config2: `reps` four-point products of the L = 4096 signed 64-bit workload (seed 2);
     config3: one four-point run of the 10,000-product batch (seed 3);
-    config4: one four-point run of the 64-product modular batch (seed 4)."""
+    config4: one four-point run of the 64-product modular batch (seed 4);
+    poly2: `reps` four-point bivariate products of the (Z/pZ)[x, y] workload (seed 7)."""
     sys.path.insert(0, ROOT)
     import torch
     from paper_0712_4046_amd import ks
@@ -35,6 +36,14 @@ def workload(name: str = "config2", reps: int = 5):
         tf, tg = ks.to_device(P.f), ks.to_device(P.g)
         for _ in range(reps):
             ks.mul(tf, tg, P.bits, "ks4", P.signed)
+        ks.check()
+    elif name == "poly2":
+        import numpy as np
+        p, f, g = wl.poly2_workload()
+        tf = torch.from_numpy(f.view(np.int64)).cuda()
+        tg = torch.from_numpy(g.view(np.int64)).cuda()
+        for _ in range(reps):
+            ks.mul_poly2(tf, tg, p, "ks4")
         ks.check()
     else:
         B = ks.Batch()
