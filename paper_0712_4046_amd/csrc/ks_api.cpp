@@ -734,6 +734,12 @@ struct Pool {
     size_t bytes = 0;
     char *stage = nullptr;  // bivariate products: evaluations, univariate products, chunk sums
     size_t stage_bytes = 0;
+    // bivariate products: the batch plan of their univariate products, kept while the shape
+    // (length, count, modulus, inner variant) repeats
+    ks_batch_plan *p2plan = nullptr;
+    int64_t p2_le = 0, p2_k = 0;
+    uint64_t p2_p = 0;
+    int32_t p2_inner = -1;
 };
 static std::mutex g_pool_mu;
 static std::map<hipStream_t, Pool *> g_pools;
@@ -959,11 +965,43 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
     Pool *pl = nullptr;
     rc = get_pool(s, 0, 1, &pl);
     if (rc != KS_OK) return rc;
-    // stage: 2k evaluations, k products, chunk sums of up to two gluings
+    // two or four univariate products run as one batch (one set of launches: 0.82 -> 0.56 ms on
+    // the 16 x 4096 four-point workload), its plan cached per stream; arena offsets (uint32
+    // limbs) from the stage, evaluations first, then the products.  A single product keeps the
+    // single-product pipeline (reconstruction segments cut for latency: 1.16 against 1.22 ms).
+    const bool batched = k > 1;
+    if (batched &&
+        (!pl->p2plan || pl->p2_le != le || pl->p2_k != k || pl->p2_p != p || pl->p2_inner != inner)) {
+        if (pl->p2plan) {
+            if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;  // its tables may be in use
+            ks_batch_plan_destroy(pl->p2plan);
+            pl->p2plan = nullptr;
+        }
+        ks_desc d[4];
+        memset(d, 0, sizeof(d));
+        for (int q = 0; q < k; ++q) {
+            d[q].f_off = (uint64_t)(2 * q * le);
+            d[q].g_off = (uint64_t)(2 * (k + q) * le);
+            d[q].h_off = (uint64_t)(2 * (2 * k * le + q * lh));
+            d[q].len_f = (int32_t)le;
+            d[q].len_g = (int32_t)le;
+            d[q].coeff_bits = bits;
+            d[q].flags = KS_MOD;
+            d[q].mod_p = p;
+        }
+        rc = ks_batch_plan_create(d, k, inner, &pl->p2plan);
+        if (rc != KS_OK) return rc;
+        pl->p2_le = le;
+        pl->p2_k = k;
+        pl->p2_p = p;
+        pl->p2_inner = inner;
+    }
+    // stage: 2k evaluations, k products, chunk sums of up to two gluings, the batch workspace
     const int64_t m = v == KS_VARIANT_KS4 ? 2 * n : n, count = v == KS_VARIANT_KS4 ? len_y : 2 * len_y - 1;
     const int64_t nchunks = cdiv((count + 1) / 2, P2_CHUNK);
     const int64_t words = 2 * k * le + k * lh + 2 * nchunks * 4 * m;
-    const size_t need = (size_t)words * 8;
+    const size_t ws_off = ((size_t)words * 8 + 255) / 256 * 256;
+    const size_t need = ws_off + (batched ? ks_batch_plan_workspace_bytes(pl->p2plan) : 0);
     if (pl->stage_bytes < need) {
         if (pl->stage) {
             if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;
@@ -996,12 +1034,15 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
         E.rev[q] = (v == KS_VARIANT_RECIP2 && q == 1) || (v == KS_VARIANT_KS4 && q >= 2);
     }
     if (timed("p2_eval", s, [&] { return launch_p2_eval(E, s); }) != hipSuccess) return KS_EHIP;
-    for (int q = 0; q < k; ++q) {
+    if (batched) {
+        rc = batch_run_into(pl->p2plan, reinterpret_cast<const uint32_t *>(pl->stage),
+                            reinterpret_cast<uint32_t *>(pl->stage), pl->stage + ws_off, pl->ctl.devstat, s);
+    } else {
         Spec sp{le, le, bits, 2, false, p, inner & KS_VARIANT_MASK, inner & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
-        rc = mul_common(reinterpret_cast<const uint32_t *>(ev + q * le), reinterpret_cast<const uint32_t *>(ev + (k + q) * le),
-                        sp, stream, prod + q * lh);
-        if (rc != KS_OK) return rc;
+        rc = mul_common(reinterpret_cast<const uint32_t *>(ev), reinterpret_cast<const uint32_t *>(ev + le), sp,
+                        stream, prod);
     }
+    if (rc != KS_OK) return rc;
     auto side = [&](int a, int b, int comb, int64_t off) {
         P2Side S;
         memset(&S, 0, sizeof(S));

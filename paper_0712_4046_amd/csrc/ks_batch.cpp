@@ -96,6 +96,25 @@ using namespace ks;
 
 static const int64_t WS_DEVSTAT = 0, WS_STATUS = 64;
 
+namespace ks {
+// A run of a batch plan whose device status goes to `devstat` (a library-owned stream status
+// word) instead of the workspace's own word: the bivariate products run their univariate
+// products as one batch and report through the stream.
+int batch_run_into(const ks_batch_plan *plan, const uint32_t *arena_in, uint32_t *arena_out, char *ws,
+                   uint32_t *devstat, hipStream_t s) {
+    if (launch_fill_zero(reinterpret_cast<uint64_t *>(ws), plan->header_words, s) != hipSuccess) return KS_EHIP;
+    LaunchEnv env;
+    env.status = reinterpret_cast<uint64_t *>(ws + WS_STATUS);
+    env.ctr_pack = reinterpret_cast<uint64_t *>(ws) + plan->ctr_pack;
+    env.ctr_norm = reinterpret_cast<uint64_t *>(ws) + plan->ctr_norm;
+    env.devstat = devstat;
+    env.base_in = reinterpret_cast<uintptr_t>(arena_in);
+    env.base_out = reinterpret_cast<uintptr_t>(arena_out);
+    env.base_ws = reinterpret_cast<uintptr_t>(ws);
+    return launch_lists(plan->JL, &plan->T, env, 1u, 2u, s);
+}
+}  // namespace ks
+
 extern "C" {
 
 int64_t ks_batch_plan_bad_index(void) { return g_bad_index; }

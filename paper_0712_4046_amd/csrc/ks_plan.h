@@ -9,6 +9,8 @@
 
 #include "ks_jobs.h"
 
+struct ks_batch_plan;
+
 namespace ks {
 
 int ceil_log2(int64_t x);
@@ -145,6 +147,8 @@ struct LaunchEnv {
 
 int plan_product(const Spec &sp, Geom &G);
 void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t ws, JobLists &JL);
+int batch_run_into(const ks_batch_plan *plan, const uint32_t *arena_in, uint32_t *arena_out, char *ws,
+                   uint32_t *devstat, hipStream_t s);
 int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, uint32_t epoch_pack,
                  uint32_t epoch_norm, hipStream_t s);
 int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s);
