@@ -1,6 +1,7 @@
 """Host-side checks of the C-ABI library (no GPU work): it loads, exports every symbol that
 include/ks.h declares, and its planner follows the paper's formulas for N and operand sizes.
 """
+import ctypes
 import os
 import re
 
@@ -95,3 +96,26 @@ def test_tunables_round_trip_and_reach_the_planner():
     finally:
         ks.tune_reset()
     assert ks.tune_get("KS_MFMA_MIN_LIMBS") == 4000
+
+
+def test_poly2_arguments_checked_on_the_host():
+    # ks_mul_poly2 rejects bad arguments before touching the device (null buffers, lengths
+    # below 1, an even or too large modulus, an unknown substitution, signed inner products)
+    L = ks.lib()
+    P = ctypes.c_void_p
+    buf = P(256)  # never dereferenced: every call below fails validation first
+    ok = dict(f=buf, g=buf, lx=4, ly=3, p=(1 << 61) - 1, v=ks.KS_VARIANT["ks4"], inner=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.ks_mul_poly2(a["f"], a["g"], a["lx"], a["ly"], a["p"], a["v"], a["inner"], None, a.get("h", buf))
+
+    assert call(f=P(0)) == ks.KS_EINVAL
+    assert call(h=P(0)) == ks.KS_EINVAL
+    assert call(lx=0) == ks.KS_EINVAL
+    assert call(ly=0) == ks.KS_EINVAL
+    assert call(p=1 << 40) == ks.KS_EINVAL
+    assert call(p=1 << 62 | 1) == ks.KS_EINVAL
+    assert call(p=1) == ks.KS_EINVAL
+    assert call(v=0x55) == ks.KS_EINVAL
+    assert call(inner=ks.KS_SIGNED) == ks.KS_EINVAL
