@@ -239,8 +239,9 @@ def batch_line(ks, torch, B, count, variant, reps, traffic=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "products shard by instance across GPUs, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); across GPUs the batched and "
+              "serving products would shard by instance and a four-point product by its four sub-products",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_0712_4046_amd import ks
