@@ -125,7 +125,8 @@ int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_
  *           (y = x^N and x^-N, N = len_x, two products of length len_x len_y; Section 2.2),
  *           KS_VARIANT_NEG2 (y = +-x^N, N = len_x; Section 2.3), KS_VARIANT_KS4 (y = +-x^N,
  *           +-x^-N, N = ceil(len_x / 2), four products of length N (len_y - 1) + len_x;
- *           Section 2.4), KS_VARIANT_AUTO (four points)
+ *           Section 2.4), KS_VARIANT_AUTO (four points when len_x >= 2 and len_x len_y >=
+ *           24576, else the standard substitution)
  *   inner   KS_VARIANT_* | optional KS_ENGINE_* for the products in (Z/pZ)[x], which run as
  *           ks_mul_mod does (KS_SIGNED is rejected)
  *   h       device, (2 len_y - 1) rows of (2 len_x - 1) uint64 residues in [0, p)
