@@ -257,6 +257,8 @@ int ks_profile_reset(void);
  *   "KS_MUL_WAVE_MAX"    128   vector-ALU products whose shorter operand has at most this many
  *                              limbs run one wave per 128-column tile, else a block per tile
  *                              (unset, the products of a batch use 1024)
+ *   "KS_MFMA_RT"         0     row tiles per matrix-core block, 4 or 8 (0: 4 for a single product
+ *                              of at most 256 eight-tile row groups, else 8)
  *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
  *                              128; 256 in a batch, and unset, a batch uses 256) run one wave
  *                              per job (0: every job in 256-thread blocks)

@@ -39,7 +39,7 @@ static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
 // planner tunables: a value set through ks_tune_set, else the environment, else the default
 static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS",  "KS_MFMA_MIN_PART",
                                          "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",     "KS_MUL_WAVE_MAX",
-                                         "KS_SCAN_SMALL"};
+                                         "KS_SCAN_SMALL",      "KS_MFMA_RT"};
 static std::mutex g_tune_mu;
 static std::map<std::string, int64_t> g_tune;
 
@@ -71,6 +71,8 @@ static int env_int(const char *name, int dflt) {
 // residue class of a wave (its first loads: about MFMA_CLASS_COST steps) and its steps (a
 // step: MFMA_RT matrix operations of each wave).
 static constexpr int64_t MFMA_CUS = 256, MFMA_CLASS_COST = 3;
+// a single product whose launch has at most this many 8-tile row groups uses 4-tile blocks
+static constexpr int64_t MFMA_RT4_MAX_GROUPS = 256;
 static void mfma_shape(int64_t tmax, int64_t units, int64_t target, int64_t min_part, int64_t &splits,
                        int64_t &rgroups) {
     min_part = std::max<int64_t>(1, min_part);
@@ -223,18 +225,24 @@ int plan_product(const Spec &sp, Geom &G) {
         m.engine = eng;
         if (eng == KS_ENGINE_MFMA) {
             const int64_t rows = cdiv(m.nad + m.nbd - 1, 32);
-            m.groups = cdiv(rows, MFMA_ROWS);
+            // row tiles per block: 8 share each loaded a-fragment among more matrix operations
+            // (large products, batches); 4 give a small single product twice the blocks
+            m.rt = env_int("KS_MFMA_RT", 0);
+            if (m.rt != 4 && m.rt != 8)
+                m.rt = (!sp.batch && (int64_t)npts * cdiv(rows, mfma_rows(8)) <= MFMA_RT4_MAX_GROUPS) ? 4 : 8;
+            const int64_t grows = mfma_rows(m.rt), glimbs = mfma_limbs(m.rt);  // output rows, limbs of a group
+            m.groups = cdiv(rows, grows);
             // the longest shift range of a row group, cut into parts of at most
             // mfma_max_part(rgroups) shifts (int32 accumulators), each shared by rgroups
             // blocks (residue groups)
-            const int64_t tmax = std::min(m.nA32 + MFMA_ROWS - 1, m.nB32);
+            const int64_t tmax = std::min(m.nA32 + grows - 1, m.nB32);
             mfma_shape(tmax, (int64_t)npts * m.groups, env_int("KS_MFMA_BLOCKS", (int)sp.fill_blocks),
                        env_int("KS_MFMA_MIN_PART", 128), m.splits, m.rgroups);
             m.part = cdiv(tmax, m.splits);
             m.blocks = m.groups * m.splits * m.rgroups;
-            m.ncols = m.groups * MFMA_LIMBS;
-            m.a_front = 32 * MFMA_ROWS;
-            m.a_len = align_up(m.a_front + 32 * m.nA32 + 32 * MFMA_ROWS, 1024);
+            m.ncols = m.groups * glimbs;
+            m.a_front = 32 * grows;
+            m.a_len = align_up(m.a_front + 32 * m.nA32 + 32 * grows, 1024);
             m.b_len = align_up(32 * m.nB32 + 2 * MFMA_PADB + 32, 1024);
             m.b_top = m.b_len - 1 - MFMA_PADB;
             m.ad_off = doff;
@@ -432,6 +440,8 @@ static hipError_t timed(const char *name, hipStream_t s, F &&fn) {
 void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t ws, JobLists &JL) {
     const Spec &sp = G.sp;
     JL.ipt = G.ipt;  // the products of one list are planned alike (all single or all batched)
+    for (auto &m : G.muls)
+        if (m.engine == KS_ENGINE_MFMA) JL.mfma_rt = m.rt;
     auto ops = [&](int64_t limb_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_ops + 4 * limb_off); };
     auto cols = [&](int64_t word_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_cols + 4 * word_off); };
     auto norms = [&](int64_t limb_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_norms + 4 * limb_off); };
@@ -674,7 +684,7 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         err = timed("digitize", s, [&] { return launch_digitize(Ld, s); });
         if (err != hipSuccess) return KS_EHIP;
         auto L = make_launch(JL.mfma, T ? &T->mfma : nullptr, env, 0);
-        err = timed("mul_mfma", s, [&] { return launch_mul_mfma(L, s); });
+        err = timed("mul_mfma", s, [&] { return launch_mul_mfma(L, JL.mfma_rt, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     for (auto it = JL.anchor.begin(); it != JL.anchor.end(); ++it) {
@@ -1127,7 +1137,7 @@ int ks_tune_set(const char *name, int64_t value) {
 
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
-    static const int dflt[] = {4000, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE)};  // as for a single product
+    static const int dflt[] = {4000, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE), 0};  // as for a single product
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];

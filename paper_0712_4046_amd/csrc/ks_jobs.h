@@ -34,7 +34,8 @@ constexpr int MUL_T = 64 * MUL_R;
 constexpr int MUL_CI = 128;
 
 // int8 matrix-core multiplier (balanced 8-bit digits): a block of MFMA_WAVES waves owns
-// MFMA_RT row tiles of 32 output digit blocks (32 digits each) = 8 * MFMA_ROWS output limbs, a
+// RT tiles of 32 output rows (32 digits each), mfma_rows(RT) rows = mfma_limbs(RT) output
+// limbs (RT = 4 or 8, chosen per plan), a
 // part of the block shifts and one of rgroups groups of their residues mod 32; wave w takes
 // the shifts t = t_a + c (mod 32) for the MFMA_CLASSES / rgroups residues c = w + MFMA_WAVES k
 // of its group, so with parts of at most mfma_max_part(rgroups) shifts an int32 accumulator
@@ -43,9 +44,8 @@ constexpr int MUL_CI = 128;
 constexpr int MFMA_WAVES = 8;
 constexpr int MFMA_TPB = 64 * MFMA_WAVES;
 constexpr int MFMA_CLASSES = 32 / MFMA_WAVES;
-constexpr int MFMA_RT = 8;
-constexpr int MFMA_ROWS = 32 * MFMA_RT;
-constexpr int MFMA_LIMBS = 8 * MFMA_ROWS;
+constexpr int mfma_rows(int rt) { return 32 * rt; }
+constexpr int mfma_limbs(int rt) { return 256 * rt; }
 constexpr int64_t mfma_max_part(int64_t rgroups) { return 4064 * 32 / (MFMA_CLASSES / rgroups); }
 constexpr int64_t MFMA_PADB = 64;
 

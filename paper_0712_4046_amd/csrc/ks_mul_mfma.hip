@@ -156,8 +156,9 @@ __device__ __forceinline__ v4i mfma_bop(uint32_t win, int sel, uint32_t sh) {
     return b;
 }
 
+template <int RT>
 __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
-    constexpr int RT = MFMA_RT;
+    constexpr int MFMA_ROWS = mfma_rows(RT), MFMA_LIMBS = mfma_limbs(RT);
     constexpr int PF = 8;  // steps loaded ahead (the b-window is consumed one step early)
     constexpr int UN = RT > PF ? RT : PF;  // steps per unrolled group: slot and ring indices are constants
     static_assert(UN % RT == 0 && UN % PF == 0, "fragment slots and prefetch ring must divide the unroll");
@@ -286,9 +287,14 @@ hipError_t launch_digitize(const Launch<DigitJob> &L, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, hipStream_t s) {
+hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, int rt, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    ks_launch(mul_mfma_kernel, dim3((unsigned)L.total_blocks), dim3(MFMA_TPB), 0, s, L);
+    if (rt == 4)
+        ks_launch(mul_mfma_kernel<4>, dim3((unsigned)L.total_blocks), dim3(MFMA_TPB), 0, s, L);
+    else if (rt == 8)
+        ks_launch(mul_mfma_kernel<8>, dim3((unsigned)L.total_blocks), dim3(MFMA_TPB), 0, s, L);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

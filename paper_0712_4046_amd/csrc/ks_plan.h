@@ -52,6 +52,7 @@ struct MulGeom {
     // each part shared by `rgroups` blocks (residue groups)
     int64_t nad = 0, nbd = 0, nA32 = 0, nB32 = 0, a_front = 0, a_len = 0, b_len = 0, b_top = 0;
     int64_t groups = 0, splits = 1, part = 0, rgroups = 1;
+    int rt = 8;  // row tiles per block
     int64_t ad_off = 0, bd_off = 0;
 };
 struct NormGeom {
@@ -113,6 +114,7 @@ struct Ctl {
 // jobs of one or many products, per stage (anchor and chain lists keyed by template parameter)
 struct JobLists {
     int ipt = SCAN_IPT_SINGLE;  // limbs per thread of the carry-scan launches (as planned)
+    int mfma_rt = 8;            // row tiles per matrix-core block (the same for every product of a list)
     std::vector<PackJob> pack;
     std::vector<PackJob> pack_small;  // jobs of at most small_bl(ipt) limbs
     std::vector<MulJob> mul;

@@ -266,3 +266,17 @@ def test_mfma_long_shift_ranges_sampled(torch_dev, oracle, variant):
                                     wl.rng(42).integers(0, D, 300)]))
     exp = oracle.coeffs_classical(f, g, True, idx, got.shape[1])
     assert_same(got[idx], exp, f"L=65536 {variant} mfma sampled")
+
+
+@pytest.mark.parametrize("rt", ["4", "8"])
+def test_mfma_tiles_per_block(torch_dev, oracle, monkeypatch, rt):
+    # the matrix-core blocks own 4 or 8 tiles of 32 output rows (the planner picks per product)
+    monkeypatch.setenv("KS_MFMA_RT", rt)
+    P = wl.config2()
+    exp = want(oracle, P.f, P.g, P.bits, P.signed)
+    for v in VARIANTS:
+        assert_same(gpu_mul(P.f, P.g, P.bits, v, P.signed, "mfma"), exp, f"config2 {v} rt={rt}")
+    for blocks, part in (("1", "1000000"), ("4096", "32")):
+        monkeypatch.setenv("KS_MFMA_BLOCKS", blocks)
+        monkeypatch.setenv("KS_MFMA_MIN_PART", part)
+        assert_same(gpu_mul(P.f, P.g, P.bits, "ks4", P.signed, "mfma"), exp, f"config2 ks4 rt={rt} blocks={blocks}")
