@@ -244,7 +244,7 @@ int ks_profile_reset(void);
  * Planner tunables (launch shapes), process-wide, read whenever a product or batch is planned;
  * a value set here overrides the environment variable of the same name, which overrides the
  * built-in default.  Names and defaults:
- *   "KS_MFMA_MIN_LIMBS"  4000  both operands at least this many limbs -> matrix-core engine
+ *   "KS_MFMA_MIN_LIMBS"  2500  both operands at least this many limbs -> matrix-core engine
  *                              (unset, the products of a batch use 1000)
  *   "KS_MFMA_BLOCKS"     0     matrix-core launch target of one product, in blocks; 0: the
  *                              launch shape of least modelled time (unset, a batch of n

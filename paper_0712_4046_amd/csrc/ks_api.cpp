@@ -132,7 +132,7 @@ static int auto_variant(int64_t lf, int64_t lg, int b, int e, bool batch, int en
         const double na = (double)cdiv(N * (lf - 1) + b + 2, 32), nb = (double)cdiv(N * (lg - 1) + b + 2, 32);
         int eng = engine;
         if (eng == 0)
-            eng = std::min(na, nb) >= env_int("KS_MFMA_MIN_LIMBS", batch ? 1000 : 4000) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
+            eng = std::min(na, nb) >= env_int("KS_MFMA_MIN_LIMBS", batch ? 1000 : 2500) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
         double us = 0;
         int launches = 4;  // pack, multiply, recombine, extract
         if (eng == KS_ENGINE_MFMA) {
@@ -220,7 +220,7 @@ int plan_product(const Spec &sp, Geom &G) {
         // batch: standard KS 1.95 ms at 2500 limbs, 1.77-1.81 ms at 800-1200; four-point 2.02
         // and 1.91 ms)
         if (eng == 0)
-            eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 1000 : 4000) ? KS_ENGINE_MFMA
+            eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 1000 : 2500) ? KS_ENGINE_MFMA
                                                                                           : KS_ENGINE_VALU;
         m.engine = eng;
         if (eng == KS_ENGINE_MFMA) {
@@ -1137,7 +1137,7 @@ int ks_tune_set(const char *name, int64_t value) {
 
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
-    static const int dflt[] = {4000, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE), 0};  // as for a single product
+    static const int dflt[] = {2500, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE), 0};  // as for a single product
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];

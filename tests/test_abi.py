@@ -79,7 +79,7 @@ def test_tunables_round_trip_and_reach_the_planner():
     L = ks.lib()
     ks.tune_reset()
     try:
-        assert ks.tune_get("KS_MFMA_MIN_LIMBS") == 4000
+        assert ks.tune_get("KS_MFMA_MIN_LIMBS") == 2500
         assert L.ks_tune_set(b"NO_SUCH_TUNABLE", 3) == ks.KS_EINVAL
         assert L.ks_tune_set(b"KS_CHAIN_K", -1) == ks.KS_EINVAL
         # engine threshold: a 2,241-limb product moves to the matrix cores when it is lowered
@@ -95,7 +95,7 @@ def test_tunables_round_trip_and_reach_the_planner():
         assert a4 > 10 * a64 > 0
     finally:
         ks.tune_reset()
-    assert ks.tune_get("KS_MFMA_MIN_LIMBS") == 4000
+    assert ks.tune_get("KS_MFMA_MIN_LIMBS") == 2500
 
 
 def test_poly2_arguments_checked_on_the_host():
