@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # and for the 64-product modular batch (profiles/config4_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
-MEASURED_TRAFFIC = {"pack": 1000791, "digitize": 1120113, "mul_mfma": 6082113, "normalize": 1504369, "recon": 778325,
-                    "finish": 441708}
-MEASURED_TRAFFIC_CONFIG4 = {"pack": 3109286412, "digitize": 344518962, "mul_mfma": 1778630996,
-                            "normalize": 1038492384, "recon": 349080936, "finish": 271310114}
+MEASURED_TRAFFIC = {"pack": 1000590, "digitize": 1021810, "mul_mfma": 5860971, "normalize": 1444723, "recon": 778327,
+                    "finish": 441710}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 3120317962, "digitize": 344511723, "mul_mfma": 1778385256,
+                            "normalize": 1045088195, "recon": 349081158, "finish": 271309832}
 KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
            "p2_eval", "p2_recon")
 
