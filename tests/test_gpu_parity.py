@@ -280,3 +280,26 @@ def test_mfma_tiles_per_block(torch_dev, oracle, monkeypatch, rt):
         monkeypatch.setenv("KS_MFMA_BLOCKS", blocks)
         monkeypatch.setenv("KS_MFMA_MIN_PART", part)
         assert_same(gpu_mul(P.f, P.g, P.bits, "ks4", P.signed, "mfma"), exp, f"config2 ks4 rt={rt} blocks={blocks}")
+
+
+@pytest.mark.parametrize("rt", ["4", "8"])
+def test_mfma_tiles_unequal_modular(torch_dev, oracle, monkeypatch, rt):
+    # both tile counts on unequal lengths and a modular product (the reversed operands of the
+    # four-point and reciprocal variants have their own lengths)
+    monkeypatch.setenv("KS_MFMA_RT", rt)
+    gen = wl.rng(41)
+    f = wl.random_coeffs(gen, 3001, 64, True)
+    g = wl.random_coeffs(gen, 1777, 64, True)
+    exp = want(oracle, f, g, 64, True)
+    for v in VARIANTS:
+        assert_same(gpu_mul(f, g, 64, v, True, "mfma"), exp, f"unequal {v} rt={rt}")
+    p = 2**61 - 1
+    fm = gen.integers(0, p, size=2500, dtype=np.uint64)
+    gm = gen.integers(0, p, size=4100, dtype=np.uint64)
+    expm = oracle.mul_mod(fm, gm, p)
+    tf = torch_dev.from_numpy(fm.view(np.int64)).cuda()
+    tg = torch_dev.from_numpy(gm.view(np.int64)).cuda()
+    for v in VARIANTS:
+        h = ks.mul_mod(tf, tg, p, v, engine="mfma")
+        assert ks.status() == ks.KS_OK
+        assert np.array_equal(h.cpu().numpy().view(np.uint64), expm), f"modular {v} rt={rt}"
