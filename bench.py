@@ -263,6 +263,19 @@ def main():
     plans = {v: ks.plan(L, L, bits, v, signed) for v in variants}
     engine_name = {ks.KS_ENGINE_VALU: "valu", ks.KS_ENGINE_MFMA: "mfma"}
 
+    # spread of single calls: each of 100 calls bracketed by its own events on the stream
+    def spread(v, n=100):
+        s = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for a, b in ev:
+            a.record(s)
+            ks.mul(tf, tg, bits, v, signed, out=outs[v])
+            b.record(s)
+        torch.cuda.synchronize()
+        ms_each = sorted(a.elapsed_time(b) for a, b in ev)
+        return {"p10": ms_each[n // 10], "p50": ms_each[n // 2], "p90": ms_each[(9 * n) // 10]}
+    dist = {v: spread(v) for v in variants}
+
     # per-kernel durations of the four-point product on the library's own stream
     kern = kernel_times(ks, lambda: ks.mul(tf, tg, bits, "ks4", signed, out=outs["ks4"]), args.steps)
     roof = roofline(kern, plans["ks4"], MEASURED_TRAFFIC if args.workload == "config2" else None)
@@ -336,6 +349,7 @@ def main():
         "limb_mults_per_s": p4["limb_mults"] / t["ks4"],
         "schoolbook_limb_mults_per_s": p4["schoolbook_limb_mults"] / t["ks4"],
         "variants_ms": {v: t[v] * 1000.0 for v in t},
+        "variants_ms_single_call": dist,
         "variants_products_per_s": {v: 1.0 / t[v] for v in t},
         "variants_engine": {v: engine_name.get(plans[v]["engine"], "?") for v in variants},
         "speedup_ks4_vs_ks1": t["ks1"] / t["ks4"],
