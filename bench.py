@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: exact dense products in Z[x] by multipoint Kronecker substitution on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config1] [--no-batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload product_4096_s64|product_256_u32] [--no-batch]
 
 A step is one whole product f*g through the library's hot path (pack -> integer products ->
 carry resolution and halving -> reconstruction / read-off), with the inputs already in HBM.
@@ -35,8 +35,8 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
 MFMA_I8_PEAK_TOPS = 5000.0
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated: FETCH x2,
-# WRITE x1) for the four-point product of the L=4096 workload (profiles/config2_ks4_hbm_traffic.txt)
-# and for the 64-product modular batch (profiles/config4_ks4_hbm_traffic.txt).  A kernel whose
+# WRITE x1) for the four-point product of the L=4096 workload (profiles/product_4096_s64_ks4_hbm_traffic.txt)
+# and for the 64-product modular batch (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
 MEASURED_TRAFFIC = {"pack": 1000590, "digitize": 1021810, "mul_mfma": 5860971, "normalize": 1444723, "recon": 778327,
@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2", choices=["config1", "config2"])
+    ap.add_argument("--workload", default="product_4096_s64", choices=["product_256_u32", "product_4096_s64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-paper", action="store_true", help="skip the (Z/nZ)[x] sweep of the paper's figures")
@@ -247,7 +247,7 @@ def main():
     from paper_0712_4046_amd import ks
     from paper_0712_4046_amd import workloads as wl
 
-    P = wl.config2() if args.workload == "config2" else wl.config1()
+    P = wl.product_4096_s64() if args.workload == "product_4096_s64" else wl.product_256_u32()
     L, bits, signed = P.f.shape[0], P.bits, P.signed
     tf, tg = ks.to_device(P.f), ks.to_device(P.g)
     wo = ks.out_limbs(L, L, bits)
@@ -278,7 +278,7 @@ def main():
 
     # per-kernel durations of the four-point product on the library's own stream
     kern = kernel_times(ks, lambda: ks.mul(tf, tg, bits, "ks4", signed, out=outs["ks4"]), args.steps)
-    roof = roofline(kern, plans["ks4"], MEASURED_TRAFFIC if args.workload == "config2" else None)
+    roof = roofline(kern, plans["ks4"], MEASURED_TRAFFIC if args.workload == "product_4096_s64" else None)
 
     # bit-exact check of every variant against the oracle (also the CPU baseline sample)
     cpu = None
@@ -304,26 +304,26 @@ def main():
     batch = None
     if not args.no_batch:
         batch = {}
-        prods = wl.config3()
+        prods = wl.batch_mixed_10000()
         B = ks.Batch()
         for Q in prods:
             B.add(Q.f, Q.g, Q.bits, Q.signed)
         for v in ("ks4", "ks1"):
-            batch[f"config3_{v}"] = batch_line(ks, torch, B, len(prods), v, 10)
+            batch[f"batch_mixed_10000_{v}"] = batch_line(ks, torch, B, len(prods), v, 10)
         del B
-        p, pairs = wl.config4()
+        p, pairs = wl.batch_mod_64x65536()
         B = ks.Batch()
         for f, g in pairs:
             B.add_mod(f, g, p)
         for v in ("ks4", "ks1"):
-            batch[f"config4_{v}"] = batch_line(ks, torch, B, len(pairs), v, 3,
+            batch[f"batch_mod_64x65536_{v}"] = batch_line(ks, torch, B, len(pairs), v, 3,
                                                MEASURED_TRAFFIC_CONFIG4 if v == "ks4" else None)
         del B
-        batch["speedup_ks4_vs_ks1"] = {
-            c: batch[f"{c}_ks1"]["ms_per_batch"] / batch[f"{c}_ks4"]["ms_per_batch"] for c in ("config3", "config4")}
+        batch["speedup_ks4_vs_ks1"] = {c: batch[f"{c}_ks1"]["ms_per_batch"] / batch[f"{c}_ks4"]["ms_per_batch"]
+                                       for c in ("batch_mixed_10000", "batch_mod_64x65536")}
         batch["workloads"] = {
-            "config3": "10,000 signed products, L log-uniform in [16, 1024], b in {16, 32, 64, 128}, seed 3",
-            "config4": "64 products mod a 60-bit odd p, L = 65536, residues uniform in [0, p), seed 4"}
+            "batch_mixed_10000": "10,000 signed products, L log-uniform in [16, 1024], b in {16, 32, 64, 128}, seed 3",
+            "batch_mod_64x65536": "64 products mod a 60-bit odd p, L = 65536, residues uniform in [0, p), seed 4"}
 
     paper = None if args.no_paper else paper_sweep(ks, torch, wl)
     bivariate = None if args.no_poly2 else poly2_line(ks, torch, wl)

@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Autotuner for the planner's launch shapes (the ks_tune_* tunables of include/ks.h).
 
-    python -m paper_0712_4046_amd.autotune --workload config3 [--variant ks4] [--out tuning.json]
+    python -m paper_0712_4046_amd.autotune --workload batch_mixed_10000 [--variant ks4] [--out tuning.json]
 
 For one workload it times the whole run (HIP events on the stream the library launches on,
 median of a few runs after warm-up) for candidate values of each tunable in turn -- a
@@ -14,8 +14,8 @@ them for later plans.  The shapes change only how work
 is cut into launches and blocks, never the result: tests/test_gpu_autotune.py checks a tuned
 run bit for bit against the default one.
 
-Workloads: config2 (one product, L = 4096, signed 64-bit), config3 (the 10,000-product batch),
-config4 (the 64-product modular batch, L = 65536), or `small` (a 300-product batch for tests).
+Workloads: product_4096_s64 (one product, L = 4096, signed 64-bit), batch_mixed_10000 (the 10,000-product batch),
+batch_mod_64x65536 (the 64-product modular batch, L = 65536), or `small` (a 300-product batch for tests).
 """
 from __future__ import annotations
 
@@ -58,8 +58,8 @@ def workload(name: str, variant: str):
     zero-argument callable that runs it once (results on the device)."""
     import torch
     from . import workloads as wl
-    if name == "config2":
-        P = wl.config2()
+    if name == "product_4096_s64":
+        P = wl.product_4096_s64()
         tf, tg = ks.to_device(P.f), ks.to_device(P.g)
         out = torch.empty((2 * P.f.shape[0] - 1, ks.out_limbs(P.f.shape[0], P.g.shape[0], P.bits)),
                           dtype=torch.int32, device="cuda")
@@ -68,12 +68,12 @@ def workload(name: str, variant: str):
             return lambda: ks.mul(tf, tg, P.bits, variant, P.signed, out=out)
         return make
     B = ks.Batch()
-    if name == "config4":
-        p, pairs = wl.config4()
+    if name == "batch_mod_64x65536":
+        p, pairs = wl.batch_mod_64x65536()
         for f, g in pairs:
             B.add_mod(f, g, p)
     else:
-        prods = wl.config3() if name == "config3" else wl.config3(count=300, seed=36)
+        prods = wl.batch_mixed_10000() if name == "batch_mixed_10000" else wl.batch_mixed_10000(count=300, seed=36)
         for Q in prods:
             B.add(Q.f, Q.g, Q.bits, Q.signed)
     ain = ks.to_device(B.arena_in())
@@ -124,7 +124,7 @@ def tune(make, candidates=None, max_passes: int = 2, warmup: int = 2, reps: int 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="config3", choices=["config2", "config3", "config4", "small"])
+    ap.add_argument("--workload", default="batch_mixed_10000", choices=["product_4096_s64", "batch_mixed_10000", "batch_mod_64x65536", "small"])
     ap.add_argument("--variant", default="ks4")
     ap.add_argument("--out", default=None)
     ap.add_argument("--passes", type=int, default=2)

@@ -214,11 +214,11 @@ int plan_product(const Spec &sp, Geom &G) {
         m.nA32 = cdiv(m.nad, 32);
         m.nB32 = cdiv(m.nbd + 31, 32);
         int eng = sp.engine;
-        // the matrix cores cost a digit launch more: a single product needs larger operands to
-        // gain (C2's four-point products of 4481 limbs: 0.054 ms on the vector ALU, 0.060 on
-        // the matrix cores); a batch shares that launch among its products (10,000-product
-        // batch: standard KS 1.95 ms at 2500 limbs, 1.77-1.81 ms at 800-1200; four-point 2.02
-        // and 1.91 ms)
+        // the matrix cores cost a digit launch more: a single product needs operands of about
+        // 2200-2400 limbs to gain (vector ALU / matrix cores 0.99-1.01 there, 1.12-1.17 at
+        // ~4400 limbs); a batch shares that launch among its products (10,000-product batch:
+        // standard KS 1.95 ms at 2500 limbs, 1.77-1.81 ms at 800-1200; four-point 2.02 and
+        // 1.91 ms)
         if (eng == 0)
             eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 1000 : 2500) ? KS_ENGINE_MFMA
                                                                                           : KS_ENGINE_VALU;

@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Helpers for rocprofv3 measurements of the library (used to make the files in profiles/).
 
-    python -m paper_0712_4046_amd.prof_tools workload [config2|config3|config4]  # counter runs
+    python -m paper_0712_4046_amd.prof_tools workload [product_4096_s64|batch_mixed_10000|batch_mod_64x65536]  # counter runs
     python -m paper_0712_4046_amd.prof_tools summarize DB "cmd"  # kernel-trace summary table
     python -m paper_0712_4046_amd.prof_tools counters FETCH_DB WRITE_DB   # HBM bytes per kernel
 
@@ -17,11 +17,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_MIB = 256
 
 
-def workload(name: str = "config2", reps: int = 5):
+def workload(name: str = "product_4096_s64", reps: int = 5):
     """A plain device copy of COPY_MIB MiB (the FETCH_SIZE / WRITE_SIZE calibration), then
-    config2: `reps` four-point products of the L = 4096 signed 64-bit workload (seed 2);
-    config3: one four-point run of the 10,000-product batch (seed 3);
-    config4: one four-point run of the 64-product modular batch (seed 4);
+    product_4096_s64: `reps` four-point products of the L = 4096 signed 64-bit workload (seed 2);
+    batch_mixed_10000: one four-point run of the 10,000-product batch (seed 3);
+    batch_mod_64x65536: one four-point run of the 64-product modular batch (seed 4);
     poly2: `reps` four-point bivariate products of the (Z/pZ)[x, y] workload (seed 7)."""
     sys.path.insert(0, ROOT)
     import torch
@@ -31,8 +31,8 @@ def workload(name: str = "config2", reps: int = 5):
     dst = torch.empty_like(src)
     dst.copy_(src)  # known traffic: COPY_MIB MiB read and COPY_MIB MiB written
     torch.cuda.synchronize()
-    if name == "config2":
-        P = wl.config2()
+    if name == "product_4096_s64":
+        P = wl.product_4096_s64()
         tf, tg = ks.to_device(P.f), ks.to_device(P.g)
         for _ in range(reps):
             ks.mul(tf, tg, P.bits, "ks4", P.signed)
@@ -47,11 +47,11 @@ def workload(name: str = "config2", reps: int = 5):
         ks.check()
     else:
         B = ks.Batch()
-        if name == "config3":
-            for P in wl.config3():
+        if name == "batch_mixed_10000":
+            for P in wl.batch_mixed_10000():
                 B.add(P.f, P.g, P.bits, P.signed)
         else:
-            p, pairs = wl.config4()
+            p, pairs = wl.batch_mod_64x65536()
             for f, g in pairs:
                 B.add_mod(f, g, p)
         plan = ks.BatchPlan(B.desc_array(), "ks4")
@@ -129,7 +129,7 @@ def counters(fetch_db: str, write_db: str):
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else "workload"
     if cmd == "workload":
-        workload(sys.argv[2] if len(sys.argv) > 2 else "config2")
+        workload(sys.argv[2] if len(sys.argv) > 2 else "product_4096_s64")
     elif cmd == "summarize":
         summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "", int(sys.argv[4]) if len(sys.argv) > 4 else 0)
     elif cmd == "counters":

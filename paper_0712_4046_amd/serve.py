@@ -155,7 +155,7 @@ def make_requests(count: int, rate_per_s: float, seed: int = 5, max_len: int = 6
     """The serving mix: L log-uniform in [8, max_len], b uniform in [8, max_bits], signed values,
     Poisson arrivals at `rate_per_s` (rate 0 or less: all arrive at time 0, a closed loop)."""
     from . import workloads as wl
-    lens, bits, seeds = wl.config5_requests(count, seed, max_len, max_bits)
+    lens, bits, seeds = wl.serving_requests(count, seed, max_len, max_bits)
     arr = wl.poisson_arrivals(count, rate_per_s, seed) if rate_per_s > 0 else np.zeros(count)
     reqs = []
     for i in range(count):

@@ -86,19 +86,19 @@ class Product:
 
 # ---- the named workloads -------------------------------------------------------------------
 
-def config1() -> Product:
+def product_256_u32() -> Product:
     """One product, L = 256, coefficients uniform unsigned 32-bit."""
     gen = rng(1)
     return Product(random_coeffs(gen, 256, 32, False), random_coeffs(gen, 256, 32, False), 32, False)
 
 
-def config2() -> Product:
+def product_4096_s64() -> Product:
     """One product, L = 4096, coefficients uniform signed in [-2^63, 2^63) (b = 64 with sign)."""
     gen = rng(2)
     return Product(random_coeffs(gen, 4096, 64, True), random_coeffs(gen, 4096, 64, True), 64, True)
 
 
-def config3(count: int = 10000, independent_lengths: bool = False, seed: int = 3) -> list:
+def batch_mixed_10000(count: int = 10000, independent_lengths: bool = False, seed: int = 3) -> list:
     """Batch: L log-uniform in [16, 1024] per instance, b uniform in {16, 32, 64, 128}, signed."""
     gen = rng(seed)
     out = []
@@ -110,7 +110,7 @@ def config3(count: int = 10000, independent_lengths: bool = False, seed: int = 3
     return out
 
 
-def config4_modulus(seed: int = 4) -> int:
+def batch_mod_modulus(seed: int = 4) -> int:
     """Odd modulus 2^59 <= p < 2^60: p = 2^59 + 2 U[0, 2^58) + 1."""
     gen = rng(seed)
     return (1 << 59) + 2 * int(gen.integers(0, 1 << 58, dtype=np.uint64)) + 1
@@ -156,7 +156,7 @@ def poly2_workload(seed: int = 7):
     return p, f, g
 
 
-def config4(count: int = 64, length: int = 65536, seed: int = 4):
+def batch_mod_64x65536(count: int = 64, length: int = 65536, seed: int = 4):
     """Modular batch: `count` products in (Z/pZ)[x], f, g uniform in [0, p), length 65536."""
     gen = rng(seed)
     p = (1 << 59) + 2 * int(gen.integers(0, 1 << 58, dtype=np.uint64)) + 1
@@ -168,7 +168,7 @@ def config4(count: int = 64, length: int = 65536, seed: int = 4):
     return p, pairs
 
 
-def config5_requests(count: int = 10000, seed: int = 5, max_len: int = 65536, max_bits: int = 256):
+def serving_requests(count: int = 10000, seed: int = 5, max_len: int = 65536, max_bits: int = 256):
     """Serving mix: L log-uniform in [8, max_len], b uniform in [8, max_bits], signed values.
 
     Returns (lengths, bits, seeds) per request; coefficients are drawn lazily with

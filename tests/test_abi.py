@@ -69,7 +69,7 @@ def test_planner_slot_widths_and_operand_lengths(lf, lg, b, signed):
         assert p["schoolbook_limb_mults"] == k * p["operand_limbs_f"] * p["operand_limbs_g"]
 
 
-def test_config2_slot_width():
+def test_product_4096_s64_slot_width():
     # L = 4096, b = 64 (sign included): KS1 N = 2b + e = 140, KS4 N = 35
     assert ks.plan(4096, 4096, 64, "ks1", True)["slot_bits"] == 140
     assert ks.plan(4096, 4096, 64, "ks4", True)["slot_bits"] == 35

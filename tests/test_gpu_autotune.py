@@ -37,7 +37,7 @@ def test_tuned_batch_equals_default(oracle):
         make.state["plan"].close()
     out = ks.to_host(default)
     from paper_0712_4046_amd import workloads as wl
-    prods = wl.config3(count=300, seed=36)
+    prods = wl.batch_mixed_10000(count=300, seed=36)
     for i in (0, 1, 150, 299):
         P = prods[i]
         exp = oracle.mul_classical(P.f, P.g, P.signed, oracle.out_limbs(P.f.shape[0], P.g.shape[0], P.bits))

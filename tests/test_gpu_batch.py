@@ -56,8 +56,8 @@ def test_mixed_batch(torch_dev, oracle, variant, engine):
         assert np.array_equal(B.result(out, i), exp), (variant, i, f.shape[0], g.shape[0], bits, signed)
 
 
-def test_config3_full_batch(torch_dev, oracle):
-    prods = wl.config3()
+def test_mixed_batch_full(torch_dev, oracle):
+    prods = wl.batch_mixed_10000()
     B = ks.Batch()
     for P in prods:
         B.add(P.f, P.g, P.bits, P.signed)
@@ -67,8 +67,8 @@ def test_config3_full_batch(torch_dev, oracle):
         assert np.array_equal(B.result(out, i), exp), i
 
 
-def test_config3_unequal_lengths(torch_dev, oracle):
-    prods = wl.config3(count=600, independent_lengths=True, seed=33)
+def test_mixed_batch_unequal_lengths(torch_dev, oracle):
+    prods = wl.batch_mixed_10000(count=600, independent_lengths=True, seed=33)
     B = ks.Batch()
     for P in prods:
         B.add(P.f, P.g, P.bits, P.signed)
@@ -78,8 +78,8 @@ def test_config3_unequal_lengths(torch_dev, oracle):
         assert np.array_equal(B.result(out, i), exp), i
 
 
-def test_config4_modular_batch_sampled(torch_dev, oracle):
-    p, pairs = wl.config4()
+def test_modular_batch_sampled(torch_dev, oracle):
+    p, pairs = wl.batch_mod_64x65536()
     B = ks.Batch()
     for f, g in pairs:
         B.add_mod(f, g, p)
@@ -93,7 +93,7 @@ def test_config4_modular_batch_sampled(torch_dev, oracle):
 
 def test_graph_capture_replays(torch_dev, oracle):
     torch = torch_dev
-    prods = wl.config3(count=300, seed=35)
+    prods = wl.batch_mixed_10000(count=300, seed=35)
     B = ks.Batch()
     for P in prods:
         B.add(P.f, P.g, P.bits, P.signed)

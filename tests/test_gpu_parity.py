@@ -55,18 +55,18 @@ def test_paper_example(torch_dev, oracle):
 
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_config1_full(torch_dev, oracle, variant, engine):
-    P = wl.config1()
+def test_product_256_u32_full(torch_dev, oracle, variant, engine):
+    P = wl.product_256_u32()
     assert_same(gpu_mul(P.f, P.g, P.bits, variant, P.signed, engine), want(oracle, P.f, P.g, P.bits, P.signed),
-                f"config1 {variant} {engine}")
+                f"product_256_u32 {variant} {engine}")
 
 
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_config2_full(torch_dev, oracle, variant, engine):
-    P = wl.config2()
+def test_product_4096_s64_full(torch_dev, oracle, variant, engine):
+    P = wl.product_4096_s64()
     assert_same(gpu_mul(P.f, P.g, P.bits, variant, P.signed, engine), want(oracle, P.f, P.g, P.bits, P.signed),
-                f"config2 {variant} {engine}")
+                f"product_4096_s64 {variant} {engine}")
 
 
 EDGE_LENGTHS = [(1, 1), (1, 2), (2, 1), (2, 2), (3, 3), (3, 5), (5, 3), (4, 7), (17, 16), (33, 2), (64, 64)]
@@ -113,7 +113,7 @@ def test_multi_block_sizes(torch_dev, oracle, lf, lg, bits, signed):
 
 
 def test_deterministic(torch_dev):
-    P = wl.config2()
+    P = wl.product_4096_s64()
     a = gpu_mul(P.f, P.g, P.bits, "ks4", True)
     b = gpu_mul(P.f, P.g, P.bits, "ks4", True)
     assert np.array_equal(a, b)
@@ -121,7 +121,7 @@ def test_deterministic(torch_dev):
 
 def test_other_stream(torch_dev, oracle):
     torch = torch_dev
-    P = wl.config1()
+    P = wl.product_256_u32()
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         tf, tg = ks.to_device(P.f), ks.to_device(P.g)
@@ -132,7 +132,7 @@ def test_other_stream(torch_dev, oracle):
 
 def test_mod_small(torch_dev, oracle):
     torch = torch_dev
-    for p in (3, 65537, (1 << 31) - 1, wl.config4_modulus(), (1 << 61) - 1):
+    for p in (3, 65537, (1 << 31) - 1, wl.batch_mod_modulus(), (1 << 61) - 1):
         gen = wl.rng(p % 1000)
         for lf, lg in ((1, 1), (2, 3), (300, 257), (1000, 1000)):
             f = gen.integers(0, p, size=lf, dtype=np.uint64)
@@ -147,9 +147,9 @@ def test_mod_small(torch_dev, oracle):
                 assert np.array_equal(got, exp), (p, lf, lg, v)
 
 
-def test_mod_config4_one_product_sampled(torch_dev, oracle):
+def test_mod_one_product_of_the_modular_batch_sampled(torch_dev, oracle):
     torch = torch_dev
-    p, pairs = wl.config4(count=1)
+    p, pairs = wl.batch_mod_64x65536(count=1)
     f, g = pairs[0]
     tf = torch.from_numpy(f.view(np.int64)).cuda()
     tg = torch.from_numpy(g.view(np.int64)).cuda()
@@ -225,10 +225,10 @@ def test_mfma_part_splits(torch_dev, oracle, monkeypatch, blocks, min_part):
     # model (0)
     monkeypatch.setenv("KS_MFMA_BLOCKS", blocks)
     monkeypatch.setenv("KS_MFMA_MIN_PART", min_part)
-    P = wl.config2()
+    P = wl.product_4096_s64()
     exp = want(oracle, P.f, P.g, P.bits, P.signed)
     for v in VARIANTS:
-        assert_same(gpu_mul(P.f, P.g, P.bits, v, P.signed, "mfma"), exp, f"config2 {v} blocks={blocks} part>={min_part}")
+        assert_same(gpu_mul(P.f, P.g, P.bits, v, P.signed, "mfma"), exp, f"product_4096_s64 {v} blocks={blocks} part>={min_part}")
 
 
 @pytest.mark.parametrize("pattern", [0x7F, 0x80, 0xFF])
@@ -272,14 +272,14 @@ def test_mfma_long_shift_ranges_sampled(torch_dev, oracle, variant):
 def test_mfma_tiles_per_block(torch_dev, oracle, monkeypatch, rt):
     # the matrix-core blocks own 4 or 8 tiles of 32 output rows (the planner picks per product)
     monkeypatch.setenv("KS_MFMA_RT", rt)
-    P = wl.config2()
+    P = wl.product_4096_s64()
     exp = want(oracle, P.f, P.g, P.bits, P.signed)
     for v in VARIANTS:
-        assert_same(gpu_mul(P.f, P.g, P.bits, v, P.signed, "mfma"), exp, f"config2 {v} rt={rt}")
+        assert_same(gpu_mul(P.f, P.g, P.bits, v, P.signed, "mfma"), exp, f"product_4096_s64 {v} rt={rt}")
     for blocks, part in (("1", "1000000"), ("4096", "32")):
         monkeypatch.setenv("KS_MFMA_BLOCKS", blocks)
         monkeypatch.setenv("KS_MFMA_MIN_PART", part)
-        assert_same(gpu_mul(P.f, P.g, P.bits, "ks4", P.signed, "mfma"), exp, f"config2 ks4 rt={rt} blocks={blocks}")
+        assert_same(gpu_mul(P.f, P.g, P.bits, "ks4", P.signed, "mfma"), exp, f"product_4096_s64 ks4 rt={rt} blocks={blocks}")
 
 
 @pytest.mark.parametrize("rt", ["4", "8"])

@@ -252,7 +252,7 @@ def test_sampled_coefficients_match_full(oracle):
 # ---- modular route -------------------------------------------------------------------------
 
 def test_mod_p(oracle):
-    p = wl.config4_modulus()
+    p = wl.batch_mod_modulus()
     assert p % 2 == 1 and 2 ** 59 <= p < 2 ** 60
     gen = wl.rng(5)
     f = gen.integers(0, p, size=300, dtype=np.uint64)
