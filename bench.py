@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # and for the 64-product modular batch (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
-MEASURED_TRAFFIC = {"pack": 1000590, "digitize": 1021810, "mul_mfma": 5860971, "normalize": 1444723, "recon": 778327,
-                    "finish": 441710}
-MEASURED_TRAFFIC_CONFIG4 = {"pack": 3120317962, "digitize": 344511723, "mul_mfma": 1778385256,
-                            "normalize": 1045088195, "recon": 349081158, "finish": 271309832}
+MEASURED_TRAFFIC = {"pack": 1000330, "digitize": 1021808, "mul_mfma": 5860964, "normalize": 1449708, "recon": 778324,
+                    "finish": 441708}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 3124533034, "digitize": 344519526, "mul_mfma": 1778670520,
+                            "normalize": 1107333119, "recon": 349084302, "finish": 271311369}
 KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
            "p2_eval", "p2_recon")
 
