@@ -41,9 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # pack-and-anchor launch, "recon" the reconstruction chain.
 MEASURED_TRAFFIC = {"pack": 1000330, "digitize": 1021808, "mul_mfma": 5860964, "normalize": 1449708, "recon": 778324,
                     "finish": 441708}
-MEASURED_TRAFFIC_CONFIG4 = {"pack": 3124533034, "digitize": 344519526, "mul_mfma": 1778670520,
-                            "normalize": 1107333119, "recon": 349084302, "finish": 271311369}
-KERNELS = ("pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
+MEASURED_TRAFFIC_CONFIG4 = {}
+KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
            "p2_eval", "p2_recon")
 
 

@@ -172,7 +172,10 @@ struct ks_plan_info;
  * Plan a batch once: validates every descriptor (KS_EINVAL names nothing; use
  * ks_batch_plan_bad_index), sizes the scratch, orders the work, and uploads the job tables
  * to device memory owned by the plan (a synchronous upload).  `variant` applies to every
- * product (KS_VARIANT_AUTO lets the planner choose per product).
+ * product (KS_VARIANT_AUTO lets the planner choose per product).  A batch of long modular
+ * products of equal lengths (see KS_KARATSUBA_MIN_LEN) is planned as the batch of their
+ * Karatsuba halves f0 g0, f1 g1 and (f0+f1)(g0+g1), h = ceil(L / 2), staged and recombined
+ * mod p by two more launches inside the run; the result and the interface are the same.
  */
 int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, ks_batch_plan **plan);
 /* Index of the first descriptor rejected by the last failed ks_batch_plan_create (-1 if none). */
@@ -234,7 +237,9 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
  * stream it is launched on; ks_profile_read synchronises those streams and returns, for
  * kernel `name`, the number of launches and their summed duration in milliseconds.  Names:
  * "pack" (with the anchors it carries), "mul_valu", "mul_mfma", "normalize", "anchor",
- * "recon", "finish", "extract", "digitize".  Returns KS_EINVAL for an unknown name.
+ * "recon", "finish", "extract", "digitize", "p2_eval", "p2_recon" (bivariate evaluation and
+ * read-off or gluing), "kara" (the Karatsuba split and combination of a batch).  Returns
+ * KS_EINVAL for an unknown name.
  */
 int ks_profile_enable(int32_t on);
 int ks_profile_read(const char *name, int64_t *launches, double *total_ms);
@@ -262,6 +267,11 @@ int ks_profile_reset(void);
  *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
  *                              128; 256 in a batch, and unset, a batch uses 256) run one wave
  *                              per job (0: every job in 256-thread blocks)
+ *   "KS_KARATSUBA_MIN_LEN" 16384  a batch plan whose products are all modular with equal
+ *                              lengths of at least this many coefficients, and at least 16 times
+ *                              this many per input over the batch, splits each product once,
+ *                              Karatsuba's way, on the polynomials (three products of half the
+ *                              length, combined mod p); 0: never
  * ks_tune_set returns KS_EINVAL for an unknown name or a negative value; ks_tune_get returns
  * the value in force (KS_EINVAL if unknown); ks_tune_reset clears every value set here.
  * Plans made before a change keep their shapes.  Used by paper_0712_4046_amd/autotune.py.

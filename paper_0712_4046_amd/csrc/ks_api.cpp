@@ -39,7 +39,7 @@ static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
 // planner tunables: a value set through ks_tune_set, else the environment, else the default
 static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS",  "KS_MFMA_MIN_PART",
                                          "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",     "KS_MUL_WAVE_MAX",
-                                         "KS_SCAN_SMALL",      "KS_MFMA_RT"};
+                                         "KS_SCAN_SMALL",      "KS_MFMA_RT",      "KS_KARATSUBA_MIN_LEN"};
 static std::mutex g_tune_mu;
 static std::map<std::string, int64_t> g_tune;
 
@@ -49,7 +49,7 @@ static bool known_tunable(const char *name) {
     return false;
 }
 
-static int env_int(const char *name, int dflt) {
+int env_int(const char *name, int dflt) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(name);
@@ -431,6 +431,10 @@ static hipError_t timed(const char *name, hipStream_t s, F &&fn) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_pending.push_back(r);
     return e;
+}
+
+hipError_t timed_launch(const char *name, hipStream_t s, const std::function<hipError_t()> &fn) {
+    return timed(name, s, fn);
 }
 
 // ---- job emission (shared by single products and batches) --------------------------------------
@@ -1137,7 +1141,8 @@ int ks_tune_set(const char *name, int64_t value) {
 
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
-    static const int dflt[] = {2500, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE), 0};  // as for a single product
+    static const int dflt[] = {2500, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE), 0,
+                               KARATSUBA_MIN_LEN};  // as for a single product
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];
@@ -1166,7 +1171,7 @@ int ks_profile_reset(void) {
 int ks_profile_read(const char *name, int64_t *launches, double *total_ms) {
     if (!name || !launches || !total_ms) return KS_EINVAL;
     static const char *known[] = {"pack",  "mul_valu", "mul_mfma", "normalize", "anchor",  "recon",
-                                  "extract", "digitize", "finish",  "p2_eval",   "p2_recon"};
+                                  "extract", "digitize", "finish",  "p2_eval",   "p2_recon", "kara"};
     bool ok = false;
     for (const char *k : known) ok = ok || strcmp(k, name) == 0;
     if (!ok) return KS_EINVAL;

@@ -274,6 +274,19 @@ struct P2Glue {
     uint32_t *devstat;
 };
 
+// One modular product of a batch split at the polynomial level (Karatsuba): f = f0 + x^h f1,
+// g = g0 + x^h g1 with h = ceil(L / 2) (f1, g1 zero-padded to h terms), staged as six arrays
+// of h residues [f0 f1 f0+f1 g0 g1 g0+g1] from residue `sub_in` of the staging arena; the three
+// products f0 g0, f1 g1, (f0+f1)(g0+g1), 2h - 1 residues each, come back in that order from
+// residue `sub_out` of the product arena, and
+// f g = f0 g0 + x^h ((f0+f1)(g0+g1) - f0 g0 - f1 g1) + x^(2h) f1 g1.
+struct KaraProd {
+    uint64_t f_off, g_off, h_off;  // uint32-word offsets in the caller's arenas
+    int64_t L, h;
+    int64_t sub_in, sub_out;
+    uint64_t p;
+};
+
 // Pointer fields of a job are addresses relative to a base: inputs (f, g) to base_in,
 // outputs (h) to base_out, scratch to base_ws.  Single products pass absolute addresses with
 // zero bases; batch plans store byte offsets once and the bases arrive with each run.

@@ -49,5 +49,10 @@ hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, int rt, hipStream_t s);  //
 hipError_t launch_p2_eval(const P2Eval &E, hipStream_t s);
 hipError_t launch_p2_readoff(const P2Readoff &R, hipStream_t s);
 hipError_t launch_p2_glue(const P2Glue &G, hipStream_t s);  // two launches (chunk sums, then outputs)
+// polynomial-level Karatsuba of a batch: `tab` holds `count` KaraProd on the device
+hipError_t launch_kara_split(const KaraProd *tab, int64_t count, int64_t max_h, const uint32_t *in, uint64_t *sub,
+                             hipStream_t s);
+hipError_t launch_kara_combine(const KaraProd *tab, int64_t count, int64_t max_out, const uint64_t *sub,
+                               uint32_t *out, hipStream_t s);
 
 }  // namespace ks

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -155,5 +156,12 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
                  uint32_t epoch_norm, hipStream_t s);
 int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s);
 int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_signed);
+// a planner tunable: the value set through ks_tune_set, else the environment, else dflt
+int env_int(const char *name, int dflt);
+// batches of modular products of equal lengths at least this long are split by one level of
+// Karatsuba on the polynomials (KS_KARATSUBA_MIN_LEN; 0 turns the split off)
+constexpr int KARATSUBA_MIN_LEN = 16384;
+// fn's launches under the stage name `name` of the launch profiler (plain launches when it is off)
+hipError_t timed_launch(const char *name, hipStream_t s, const std::function<hipError_t()> &fn);
 
 }  // namespace ks

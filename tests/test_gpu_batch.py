@@ -151,3 +151,126 @@ def test_batch_range_error_reported(torch_dev):
     assert plan.status(ws) == ks.KS_ERANGE
     assert plan.status(ws) == ks.KS_OK
     plan.close()
+
+
+# ---- polynomial-level Karatsuba of modular batches ------------------------------------------
+
+KARA_LENGTHS = [2, 3, 4, 5, 17, 64, 257, 1000, 4097]
+
+
+@pytest.fixture
+def karatsuba_from(request):
+    """Lower the split threshold (KS_KARATSUBA_MIN_LEN) for one test, restored afterwards."""
+    def set_(n):
+        ks.tune_set("KS_KARATSUBA_MIN_LEN", n)
+    yield set_
+    ks.tune_reset()
+
+
+def mod_batch(lengths, p, seed):
+    gen = wl.rng(seed)
+    B = ks.Batch()
+    pairs = []
+    for L in lengths:
+        f = gen.integers(0, p, size=L, dtype=np.uint64)
+        g = gen.integers(0, p, size=L, dtype=np.uint64)
+        B.add_mod(f, g, p)
+        pairs.append((f, g))
+    return B, pairs
+
+
+@pytest.mark.parametrize("variant", ["ks1", "neg2", "recip2", "ks4", "auto"])
+def test_karatsuba_split_against_oracle(torch_dev, oracle, karatsuba_from, variant):
+    # every length from the smallest that splits (2) through odd and even halves, in one plan
+    karatsuba_from(2)
+    p = wl.paper_fig_modulus(60, 9)
+    B, pairs = mod_batch(KARA_LENGTHS, p, 61)
+    out = run_batch(torch_dev, B, variant)
+    for i, (f, g) in enumerate(pairs):
+        assert np.array_equal(B.result(out, i), oracle.mul_mod(f, g, p)), (variant, len(f))
+
+
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_karatsuba_split_equals_unsplit(torch_dev, karatsuba_from, engine):
+    p = (1 << 61) - 1
+    B, _ = mod_batch([3000, 3000, 4500], p, 62)
+    karatsuba_from(0)
+    plain = run_batch(torch_dev, B, "ks4", engine)
+    karatsuba_from(500)
+    split = run_batch(torch_dev, B, "ks4", engine)
+    assert np.array_equal(plain, split)
+
+
+def test_karatsuba_extreme_residues(torch_dev, oracle, karatsuba_from):
+    # all p - 1 (the halves' sums wrap mod p) and all 0
+    karatsuba_from(2)
+    p = wl.paper_fig_modulus(60, 10)
+    B = ks.Batch()
+    pairs = []
+    for L, fill in [(7, p - 1), (64, p - 1), (65, 0), (9, 1)]:
+        f = np.full(L, fill, dtype=np.uint64)
+        B.add_mod(f, f, p)
+        pairs.append((f, f))
+    out = run_batch(torch_dev, B, "ks4")
+    for i, (f, g) in enumerate(pairs):
+        assert np.array_equal(B.result(out, i), oracle.mul_mod(f, g, p)), i
+
+
+def test_karatsuba_not_applied_to_mixed_batches(torch_dev, oracle, karatsuba_from):
+    # a batch with unequal lengths (or integer products) is planned unsplit and stays exact
+    karatsuba_from(2)
+    p = wl.paper_fig_modulus(60, 11)
+    gen = wl.rng(63)
+    B = ks.Batch()
+    f, g = gen.integers(0, p, size=40, dtype=np.uint64), gen.integers(0, p, size=33, dtype=np.uint64)
+    B.add_mod(f, g, p)
+    out = run_batch(torch_dev, B, "ks4")
+    assert np.array_equal(B.result(out, 0), oracle.mul_mod(f, g, p))
+
+
+def test_karatsuba_graph_capture_replays(torch_dev, oracle, karatsuba_from):
+    torch = torch_dev
+    karatsuba_from(100)
+    p = wl.paper_fig_modulus(60, 12)
+    B, pairs = mod_batch([500, 777, 1024], p, 64)
+    plan = ks.BatchPlan(B.desc_array(), "ks4")
+    ain = ks.to_device(B.arena_in())
+    aout = torch.zeros(B.out_words(), dtype=torch.int32, device="cuda")
+    ws = ks.alloc_workspace(plan.workspace_bytes)
+    plan.run(ain, aout, ws)
+    assert plan.status(ws) == ks.KS_OK
+    eager = aout.clone()
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plan.run(ain, aout, ws, stream=s)
+    for rep in range(3):
+        aout.fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(aout, eager), f"replay {rep}"
+        _ = torch.arange(1000, device="cuda").sum().item()
+    out = ks.to_host(aout)
+    for i, (f, g) in enumerate(pairs):
+        assert np.array_equal(B.result(out, i), oracle.mul_mod(f, g, p)), i
+    plan.close()
+
+
+def test_karatsuba_range_error_reported(torch_dev, karatsuba_from):
+    torch = torch_dev
+    karatsuba_from(2)
+    p = 1_000_003
+    B = ks.Batch()
+    good = np.arange(1, 17, dtype=np.uint64)
+    bad = good.copy()
+    bad[13] = p  # not a residue (in the upper half)
+    B.add_mod(good, good, p)
+    B.add_mod(bad, good, p)
+    plan = ks.BatchPlan(B.desc_array(), "ks4")
+    ain = ks.to_device(B.arena_in())
+    aout = torch.zeros(B.out_words(), dtype=torch.int32, device="cuda")
+    ws = ks.alloc_workspace(plan.workspace_bytes)
+    plan.run(ain, aout, ws)
+    assert plan.status(ws) == ks.KS_ERANGE
+    plan.close()
