@@ -39,9 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # and for the 64-product modular batch (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
-MEASURED_TRAFFIC = {"pack": 1000330, "digitize": 1021808, "mul_mfma": 5860964, "normalize": 1449708, "recon": 778324,
-                    "finish": 441708}
-MEASURED_TRAFFIC_CONFIG4 = {}
+MEASURED_TRAFFIC = {"pack": 1000668, "digitize": 1021810, "mul_mfma": 5860972, "normalize": 1361857, "recon": 778328,
+                    "finish": 441710}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 3134364368, "digitize": 525454202, "mul_mfma": 2762916484,
+                            "normalize": 1490971829, "recon": 553026752, "finish": 407324422}
 KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
            "p2_eval", "p2_recon")
 
