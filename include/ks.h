@@ -173,9 +173,10 @@ struct ks_plan_info;
  * ks_batch_plan_bad_index), sizes the scratch, orders the work, and uploads the job tables
  * to device memory owned by the plan (a synchronous upload).  `variant` applies to every
  * product (KS_VARIANT_AUTO lets the planner choose per product).  A batch of long modular
- * products of equal lengths (see KS_KARATSUBA_MIN_LEN) is planned as the batch of their
+ * products of equal lengths (see KS_KARATSUBA_MIN_LIMBS) is planned as the batch of their
  * Karatsuba halves f0 g0, f1 g1 and (f0+f1)(g0+g1), h = ceil(L / 2), staged and recombined
- * mod p by two more launches inside the run; the result and the interface are the same.
+ * mod p by two more launches inside the run (recursively while the halves qualify); the
+ * result and the interface are the same.
  */
 int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, ks_batch_plan **plan);
 /* Index of the first descriptor rejected by the last failed ks_batch_plan_create (-1 if none). */
@@ -267,11 +268,12 @@ int ks_profile_reset(void);
  *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
  *                              128; 256 in a batch, and unset, a batch uses 256) run one wave
  *                              per job (0: every job in 256-thread blocks)
- *   "KS_KARATSUBA_MIN_LEN" 16384  a batch plan whose products are all modular with equal
- *                              lengths of at least this many coefficients, and at least 16 times
- *                              this many per input over the batch, splits each product once,
- *                              Karatsuba's way, on the polynomials (three products of half the
- *                              length, combined mod p); 0: never
+ *   "KS_KARATSUBA_MIN_LIMBS" 16384  t: a batch plan whose products are all modular with equal
+ *                              lengths, whose integer operands total at least 8 t limbs and
+ *                              each have at least t (2 t when the batch totals 128 t), splits
+ *                              each product Karatsuba's way on the polynomials (three products
+ *                              of half the length, combined mod p), and again while the halves
+ *                              qualify; 0: never
  * ks_tune_set returns KS_EINVAL for an unknown name or a negative value; ks_tune_get returns
  * the value in force (KS_EINVAL if unknown); ks_tune_reset clears every value set here.
  * Plans made before a change keep their shapes.  Used by paper_0712_4046_amd/autotune.py.

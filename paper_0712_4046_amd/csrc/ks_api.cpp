@@ -39,7 +39,7 @@ static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
 // planner tunables: a value set through ks_tune_set, else the environment, else the default
 static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS",  "KS_MFMA_MIN_PART",
                                          "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",     "KS_MUL_WAVE_MAX",
-                                         "KS_SCAN_SMALL",      "KS_MFMA_RT",      "KS_KARATSUBA_MIN_LEN"};
+                                         "KS_SCAN_SMALL",      "KS_MFMA_RT",      "KS_KARATSUBA_MIN_LIMBS"};
 static std::mutex g_tune_mu;
 static std::map<std::string, int64_t> g_tune;
 
@@ -1142,7 +1142,7 @@ int ks_tune_set(const char *name, int64_t value) {
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
     static const int dflt[] = {2500, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE), 0,
-                               KARATSUBA_MIN_LEN};  // as for a single product
+                               KARATSUBA_MIN_LIMBS};  // as for a single product
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];

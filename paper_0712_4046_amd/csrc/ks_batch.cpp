@@ -155,28 +155,42 @@ int ks_batch_plan_create(const ks_desc *descs, int64_t count, int32_t variant, k
     return plan_create(descs, count, variant, true, out);
 }
 
-// Every product modular (valid p, even offsets), both inputs of one length L >= max(thr, 2),
-// and at least 16 thr coefficients per input over the batch: the batch is split by Karatsuba
-// (one level); anything else is planned as it is (and any invalid descriptor is reported
-// there).  The split saves a quarter of the multiplication and adds half again to the linear
-// stages and two launches: 64 products mod a 60-bit p at L = 65536 went from 18.7 to 15.6 ms
-// (four points) and from 72.1 to 40.8 ms (standard), while batches of two and four such
-// products of 32K-64K terms gained nothing or lost up to 7%.
+// Every product modular (valid p, even offsets), both inputs of one length L >= 2, and the
+// planner's integer operands (for the batch's variant) long enough: at least 8 t limbs over
+// the batch (t = KS_KARATSUBA_MIN_LIMBS) and, in every product, t limbs, or 2 t once the batch
+// holds 128 t.  Then the batch is split by one Karatsuba level, whose three half-length
+// products are planned the same way, so the split recurses while they qualify.  Anything else
+// is planned as it is (and an invalid descriptor is reported there).  A level saves a quarter
+// of the multiplication and adds half again to the linear stages and two launches.  Measured
+// (60-bit p): 64 products at L = 65536 paid down to operands of ~35K limbs -- four points 18.2
+// ms unsplit, 15.3 / 14.3 / 15.3 ms with 1 / 2 / 3 levels, standard 71.2, 32.2 (2 levels),
+// 22.9 (4), 25.0 ms (5) -- while the bivariate 16 x 4096 product's two or four products of
+// 32K-64K terms paid down to ~17K limbs (four points 0.556 -> 0.487 ms, negated points
+// 0.813 -> 0.598 ms) and lost with a single level.
 static bool karatsuba_applies(const ks_desc *descs, int64_t count, int32_t variant) {
-    const int64_t thr = env_int("KS_KARATSUBA_MIN_LEN", KARATSUBA_MIN_LEN);
+    const int64_t thr = env_int("KS_KARATSUBA_MIN_LIMBS", KARATSUBA_MIN_LIMBS);
     if (thr <= 0 || count > 65535) return false;
-    int64_t total = 0;
-    for (int64_t i = 0; i < count; ++i) total += descs[i].len_f;
-    if (total < 16 * thr) return false;
+    int64_t total = 0, shortest = INT64_MAX;
     for (int64_t i = 0; i < count; ++i) {
         const ks_desc &d = descs[i];
         const uint64_t p = d.mod_p;
         if (d.flags != KS_MOD || p < 3 || !(p & 1) || (p >> 62) || (d.f_off & 1) || (d.g_off & 1) || (d.h_off & 1))
             return false;
-        if (d.len_f != d.len_g || d.len_f < std::max<int64_t>(thr, 2)) return false;
-        if (validate_spec(d.len_f, d.len_g, bitlen_u64(p - 1), variant & KS_VARIANT_MASK, true) != KS_OK) return false;
+        if (d.len_f != d.len_g || d.len_f < 2) return false;
+        const int v = variant & KS_VARIANT_MASK;
+        if (validate_spec(d.len_f, d.len_g, bitlen_u64(p - 1), v, true) != KS_OK) return false;
+        Spec sp{d.len_f, d.len_g, bitlen_u64(p - 1), 2, false, p, v, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+        sp.batch = true;
+        sp.batch_count = count;
+        sp.fill_blocks = std::max<int64_t>(1, 2048 / count);
+        Geom G;
+        if (plan_product(sp, G) != KS_OK) return false;
+        const int64_t n = std::min(G.nf, G.ng);
+        if (n < thr) return false;
+        shortest = std::min(shortest, n);
+        total += n;
     }
-    return true;
+    return total >= 8 * thr && shortest >= (total >= 128 * thr ? 2 * thr : thr);
 }
 
 static int plan_karatsuba(const ks_desc *descs, int64_t count, int32_t variant, ks_batch_plan **out) {
@@ -222,7 +236,7 @@ static int plan_karatsuba(const ks_desc *descs, int64_t count, int32_t variant, 
         if (plan_product(sp, G) == KS_OK) school += G.school_mults;
     }
     ks_batch_plan *inner = nullptr;
-    int rc = plan_create(sub.data(), 3 * count, variant, false, &inner);
+    int rc = plan_create(sub.data(), 3 * count, variant, true, &inner);
     if (rc != KS_OK) return rc;
     ks_batch_plan *P = new ks_batch_plan();
     P->count = count;

@@ -158,9 +158,10 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
 int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_signed);
 // a planner tunable: the value set through ks_tune_set, else the environment, else dflt
 int env_int(const char *name, int dflt);
-// batches of modular products of equal lengths at least this long are split by one level of
-// Karatsuba on the polynomials (KS_KARATSUBA_MIN_LEN; 0 turns the split off)
-constexpr int KARATSUBA_MIN_LEN = 16384;
+// batches of modular products of equal lengths whose integer operands have at least this
+// many limbs (twice as many in large batches) are split by Karatsuba on the polynomials
+// (KS_KARATSUBA_MIN_LIMBS; 0: never)
+constexpr int KARATSUBA_MIN_LIMBS = 16384;
 // fn's launches under the stage name `name` of the launch profiler (plain launches when it is off)
 hipError_t timed_launch(const char *name, hipStream_t s, const std::function<hipError_t()> &fn);
 

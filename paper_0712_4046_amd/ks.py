@@ -222,7 +222,7 @@ def profile_reset():
 
 
 TUNABLES = ("KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",
-            "KS_MUL_WAVE_MAX", "KS_SCAN_SMALL", "KS_MFMA_RT", "KS_KARATSUBA_MIN_LEN")
+            "KS_MUL_WAVE_MAX", "KS_SCAN_SMALL", "KS_MFMA_RT", "KS_KARATSUBA_MIN_LIMBS")
 
 
 def tune_set(name: str, value: int):

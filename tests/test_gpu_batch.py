@@ -160,9 +160,10 @@ KARA_LENGTHS = [2, 3, 4, 5, 17, 64, 257, 1000, 4097]
 
 @pytest.fixture
 def karatsuba_from(request):
-    """Lower the split threshold (KS_KARATSUBA_MIN_LEN) for one test, restored afterwards."""
+    """Lower the split threshold (KS_KARATSUBA_MIN_LIMBS, operand limbs) for one test, restored
+    afterwards; the split recurses while the halves' operands keep that many limbs."""
     def set_(n):
-        ks.tune_set("KS_KARATSUBA_MIN_LEN", n)
+        ks.tune_set("KS_KARATSUBA_MIN_LIMBS", n)
     yield set_
     ks.tune_reset()
 
@@ -192,6 +193,7 @@ def test_karatsuba_split_against_oracle(torch_dev, oracle, karatsuba_from, varia
 
 @pytest.mark.parametrize("engine", ["valu", "mfma"])
 def test_karatsuba_split_equals_unsplit(torch_dev, karatsuba_from, engine):
+    # operands of ~3200-4800 limbs split while the halves keep 500: three levels
     p = (1 << 61) - 1
     B, _ = mod_batch([3000, 3000, 4500], p, 62)
     karatsuba_from(0)
@@ -262,9 +264,9 @@ def test_karatsuba_range_error_reported(torch_dev, karatsuba_from):
     karatsuba_from(2)
     p = 1_000_003
     B = ks.Batch()
-    good = np.arange(1, 17, dtype=np.uint64)
+    good = np.arange(1, 65, dtype=np.uint64)
     bad = good.copy()
-    bad[13] = p  # not a residue (in the upper half)
+    bad[50] = p  # not a residue (in the upper half)
     B.add_mod(good, good, p)
     B.add_mod(bad, good, p)
     plan = ks.BatchPlan(B.desc_array(), "ks4")
