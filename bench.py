@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # and for the 64-product modular batch (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
-MEASURED_TRAFFIC = {"pack": 1000668, "digitize": 1021810, "mul_mfma": 5860972, "normalize": 1361857, "recon": 778328,
+MEASURED_TRAFFIC = {"pack": 1000207, "digitize": 1021810, "mul_mfma": 5860972, "normalize": 1466865, "recon": 778328,
                     "finish": 441710}
-MEASURED_TRAFFIC_CONFIG4 = {"pack": 3134364368, "digitize": 525454202, "mul_mfma": 2762916484,
-                            "normalize": 1490971829, "recon": 553026752, "finish": 407324422}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 2236576422, "digitize": 814249361, "mul_mfma": 4348261044,
+                            "normalize": 2329226092, "recon": 1770008914, "finish": 612174304}
 KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
            "p2_eval", "p2_recon")
 
