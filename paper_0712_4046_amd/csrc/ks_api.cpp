@@ -986,26 +986,27 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
     // two or four univariate products run as one batch (one set of launches: 0.82 -> 0.56 ms on
     // the 16 x 4096 four-point workload), its plan cached per stream; arena offsets (uint32
     // limbs) from the stage, evaluations first, then the products.  A single product keeps the
-    // single-product pipeline (reconstruction segments cut for latency: 1.16 against 1.22 ms).
-    const bool batched = k > 1;
+    // single-product pipeline (reconstruction segments cut for latency: 1.16 against 1.22 ms)
+    // unless it is long enough for the batch plan's Karatsuba split.
+    ks_desc d[4];
+    memset(d, 0, sizeof(d));
+    for (int q = 0; q < k; ++q) {
+        d[q].f_off = (uint64_t)(2 * q * le);
+        d[q].g_off = (uint64_t)(2 * (k + q) * le);
+        d[q].h_off = (uint64_t)(2 * (2 * k * le + q * lh));
+        d[q].len_f = (int32_t)le;
+        d[q].len_g = (int32_t)le;
+        d[q].coeff_bits = bits;
+        d[q].flags = KS_MOD;
+        d[q].mod_p = p;
+    }
+    const bool batched = k > 1 || karatsuba_splits(d, k, inner);
     if (batched &&
         (!pl->p2plan || pl->p2_le != le || pl->p2_k != k || pl->p2_p != p || pl->p2_inner != inner)) {
         if (pl->p2plan) {
             if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;  // its tables may be in use
             ks_batch_plan_destroy(pl->p2plan);
             pl->p2plan = nullptr;
-        }
-        ks_desc d[4];
-        memset(d, 0, sizeof(d));
-        for (int q = 0; q < k; ++q) {
-            d[q].f_off = (uint64_t)(2 * q * le);
-            d[q].g_off = (uint64_t)(2 * (k + q) * le);
-            d[q].h_off = (uint64_t)(2 * (2 * k * le + q * lh));
-            d[q].len_f = (int32_t)le;
-            d[q].len_g = (int32_t)le;
-            d[q].coeff_bits = bits;
-            d[q].flags = KS_MOD;
-            d[q].mod_p = p;
         }
         rc = ks_batch_plan_create(d, k, inner, &pl->p2plan);
         if (rc != KS_OK) return rc;

@@ -193,6 +193,16 @@ static bool karatsuba_applies(const ks_desc *descs, int64_t count, int32_t varia
     return total >= 8 * thr && shortest >= (total >= 128 * thr ? 2 * thr : thr);
 }
 
+}  // extern "C"
+
+namespace ks {
+bool karatsuba_splits(const ks_desc *descs, int64_t count, int32_t variant) {
+    return karatsuba_applies(descs, count, variant);
+}
+}  // namespace ks
+
+extern "C" {
+
 static int plan_karatsuba(const ks_desc *descs, int64_t count, int32_t variant, ks_batch_plan **out) {
     std::vector<ks_desc> sub((size_t)(3 * count));
     std::vector<KaraProd> tab((size_t)count);

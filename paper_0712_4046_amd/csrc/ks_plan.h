@@ -11,6 +11,7 @@
 #include "ks_jobs.h"
 
 struct ks_batch_plan;
+struct ks_desc;
 
 namespace ks {
 
@@ -158,6 +159,8 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
 int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_signed);
 // a planner tunable: the value set through ks_tune_set, else the environment, else dflt
 int env_int(const char *name, int dflt);
+// whether ks_batch_plan_create would split this batch by Karatsuba (see KS_KARATSUBA_MIN_LIMBS)
+bool karatsuba_splits(const ks_desc *descs, int64_t count, int32_t variant);
 // batches of modular products of equal lengths whose integer operands have at least this
 // many limbs (twice as many in large batches) are split by Karatsuba on the polynomials
 // (KS_KARATSUBA_MIN_LIMBS; 0: never)
