@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # and for the 64-product modular batch (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).  "pack" is the fused
 # pack-and-anchor launch, "recon" the reconstruction chain.
-MEASURED_TRAFFIC = {"pack": 1000207, "digitize": 1021810, "mul_mfma": 5860972, "normalize": 1466865, "recon": 778328,
-                    "finish": 441710}
-MEASURED_TRAFFIC_CONFIG4 = {"pack": 2236576422, "digitize": 814249361, "mul_mfma": 4348261044,
-                            "normalize": 2329226092, "recon": 1770008914, "finish": 612174304}
+MEASURED_TRAFFIC = {"pack": 1000619, "digitize": 1021819, "mul_mfma": 5861019, "normalize": 1407366, "recon": 778348,
+                    "finish": 441720}
+MEASURED_TRAFFIC_CONFIG4 = {"pack": 2236843379, "digitize": 814250784, "mul_mfma": 4348159197,
+                            "normalize": 2348495456, "recon": 1779810943, "finish": 612164503}
 KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
            "p2_eval", "p2_recon")
 
