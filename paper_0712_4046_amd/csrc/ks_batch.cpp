@@ -247,7 +247,10 @@ static int plan_karatsuba(const ks_desc *descs, int64_t count, int32_t variant, 
     }
     ks_batch_plan *inner = nullptr;
     int rc = plan_create(sub.data(), 3 * count, variant, true, &inner);
-    if (rc != KS_OK) return rc;
+    if (rc != KS_OK) {
+        g_bad_index = -1;  // the halves are not the caller's descriptors
+        return rc;
+    }
     ks_batch_plan *P = new ks_batch_plan();
     P->count = count;
     P->inner = inner;
