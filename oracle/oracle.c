@@ -17,7 +17,7 @@
  *                       Signed inputs (not covered by the paper) are read off as balanced
  *                       base-2^N digits: |h_k| <= L 2^(2b-2) < 2^(N-1), so each digit is
  *                       unique in [-2^(N-1), 2^(N-1)).
- * and reduction modulo an odd p < 2^63 (Section 4: lift to Z[x], multiply, reduce).
+ * and reduction modulo any p with 2 <= p < 2^63 (Section 4: lift to Z[x], multiply, reduce).
  *
  * Coefficient layout: coefficient i occupies w consecutive little-endian 32-bit limbs; when
  * is_signed is set the limbs hold the two's complement of the value.  Outputs use the same
@@ -271,7 +271,7 @@ int or_mul_ks1(const uint32_t *f, const uint32_t *g, int64_t lf, int64_t lg, int
 
 typedef unsigned __int128 u128;
 
-/* h_k mod p for one k; inputs are residues in [0, p), p odd, p < 2^63 */
+/* h_k mod p for one k; inputs are residues in [0, p), 2 <= p < 2^63 */
 static uint64_t coeff_mod_one(const uint64_t *f, const uint64_t *g, int64_t lf, int64_t lg,
                               uint64_t p, int64_t k)
 {
@@ -288,7 +288,7 @@ static uint64_t coeff_mod_one(const uint64_t *f, const uint64_t *g, int64_t lf, 
 
 int or_mul_mod(const uint64_t *f, const uint64_t *g, int64_t lf, int64_t lg, uint64_t p, uint64_t *h)
 {
-    if (lf < 1 || lg < 1 || p < 3 || !(p & 1u) || (p >> 63)) return -1;
+    if (lf < 1 || lg < 1 || p < 2 || (p >> 63)) return -1;
     for (int64_t i = 0; i < lf; i++) if (f[i] >= p) return -1;
     for (int64_t i = 0; i < lg; i++) if (g[i] >= p) return -1;
     int64_t D = lf + lg - 1;
@@ -300,7 +300,7 @@ int or_mul_mod(const uint64_t *f, const uint64_t *g, int64_t lf, int64_t lg, uin
 int or_coeffs_mod(const uint64_t *f, const uint64_t *g, int64_t lf, int64_t lg, uint64_t p,
                   const int64_t *ks, int64_t nk, uint64_t *out)
 {
-    if (lf < 1 || lg < 1 || p < 3 || !(p & 1u) || (p >> 63)) return -1;
+    if (lf < 1 || lg < 1 || p < 2 || (p >> 63)) return -1;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nk; t++) {

@@ -865,7 +865,7 @@ using namespace ks;
 
 extern "C" {
 
-int32_t ks_version(void) { return 104; }
+int32_t ks_version(void) { return 105; }
 
 const char *ks_strerror(int code) {
     switch (code) {
@@ -912,6 +912,7 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
     out->anchor_limb_mults = G.anchor_mults;
     out->mfma_ops = G.mfma_ops;
     out->valu_limb_mults = G.valu_mults;
+    out->scratch_bytes = std::max<int64_t>(G.ws_status, (int64_t)1 << 20);  // the pool's size for it
     return KS_OK;
 }
 
@@ -942,7 +943,7 @@ int ks_mul(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, i
 int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_g, uint64_t p, int32_t variant,
                void *stream, uint64_t *h) {
     if (!f || !g || !h) return KS_EINVAL;
-    if (p < 3 || !(p & 1) || (p >> 62)) return KS_EINVAL;
+    if (p < 2 || (p >> 62)) return KS_EINVAL;  // any modulus of at most 62 bits (Section 4)
     int bits = bitlen_u64(p - 1);
     int rc = validate_spec(len_f, len_g, bits, variant, false);
     if (rc != KS_OK) return rc;
@@ -1122,10 +1123,9 @@ int ks_stream_status(void *stream) {
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
         auto it = g_pools.find(s);
-        if (it == g_pools.end()) return hipStreamSynchronize(s) == hipSuccess ? KS_OK : KS_EHIP;
-        p = it->second;
+        if (it != g_pools.end()) p = it->second;
     }
-    return read_status(p->ctl.devstat, s);
+    return p ? read_status(p->ctl.devstat, s) : (hipStreamSynchronize(s) == hipSuccess ? KS_OK : KS_EHIP);
 }
 
 int ks_profile_enable(int32_t on) {

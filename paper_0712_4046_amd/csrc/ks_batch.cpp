@@ -174,7 +174,7 @@ static bool karatsuba_applies(const ks_desc *descs, int64_t count, int32_t varia
     for (int64_t i = 0; i < count; ++i) {
         const ks_desc &d = descs[i];
         const uint64_t p = d.mod_p;
-        if (d.flags != KS_MOD || p < 3 || !(p & 1) || (p >> 62) || (d.f_off & 1) || (d.g_off & 1) || (d.h_off & 1))
+        if (d.flags != KS_MOD || p < 2 || (p >> 62) || (d.f_off & 1) || (d.g_off & 1) || (d.h_off & 1))
             return false;
         if (d.len_f != d.len_g || d.len_f < 2) return false;
         const int v = variant & KS_VARIANT_MASK;
@@ -308,8 +308,7 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
         if (d.flags & ~(KS_SIGNED | KS_MOD)) { g_bad_index = i; delete P; return KS_EINVAL; }
         if (mod) {
             const uint64_t p = d.mod_p;
-            if (p < 3 || !(p & 1) || (p >> 62) || (d.flags & KS_SIGNED) || (d.f_off & 1) || (d.g_off & 1) ||
-                (d.h_off & 1)) {
+            if (p < 2 || (p >> 62) || (d.flags & KS_SIGNED) || (d.f_off & 1) || (d.g_off & 1) || (d.h_off & 1)) {
                 g_bad_index = i;
                 delete P;
                 return KS_EINVAL;
@@ -421,6 +420,7 @@ int ks_batch_plan_info(const ks_batch_plan *plan, ks_plan_info *out) {
     out->anchor_limb_mults = plan->anchor_mults;
     out->mfma_ops = plan->mfma_ops;
     out->valu_limb_mults = plan->valu_mults;
+    out->scratch_bytes = plan->ws_bytes;
     return KS_OK;
 }
 

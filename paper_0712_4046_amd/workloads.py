@@ -117,21 +117,29 @@ def batch_mod_modulus(seed: int = 4) -> int:
 
 
 # The paper's example timings (its Section 4, Figures 1-2): (Z/nZ)[x] with a random 4-bit and a
-# random 48-bit modulus n, across degrees.  The modular entry point takes odd moduli, so n is a
-# random odd number of the stated bit length.
+# random 48-bit modulus n, across degrees; n is a random number of the stated bit length (odd
+# or even: the modular entry point lifts, multiplies and reduces modulo any such n).
 PAPER_FIG_BITS = (4, 48)
 PAPER_FIG_LENGTHS = tuple(4 ** k for k in range(1, 9))  # 4 .. 65536
 
 
 def paper_fig_modulus(bits: int, seed: int = 6) -> int:
-    """Random odd n with exactly `bits` bits: 2^(bits-1) + 2 U[0, 2^(bits-2)) + 1."""
+    """Random odd n with exactly `bits` bits: 2^(bits-1) + 2 U[0, 2^(bits-2)) + 1 (the
+    bivariate products and the tests that need 2 invertible draw theirs here)."""
     gen = rng(seed + bits)
     return (1 << (bits - 1)) + 2 * int(gen.integers(0, 1 << (bits - 2), dtype=np.uint64)) + 1
 
 
+def random_modulus(bits: int, seed: int) -> int:
+    """Random n with exactly `bits` bits, odd or even: 2^(bits-1) + U[0, 2^(bits-1))."""
+    gen = rng(seed + 7919 * bits)
+    return (1 << (bits - 1)) + int(gen.integers(0, 1 << (bits - 1), dtype=np.uint64))
+
+
 def paper_fig_pair(bits: int, length: int, seed: int = 6):
-    """(n, f, g): residues uniform in [0, n), f and g of the given length."""
-    n = paper_fig_modulus(bits, seed)
+    """(n, f, g): n a random `bits`-bit modulus (see random_modulus), residues uniform in
+    [0, n), f and g of the given length."""
+    n = random_modulus(bits, seed)
     gen = rng(seed * 1000 + bits * 100 + length)
     return n, gen.integers(0, n, size=length, dtype=np.uint64), gen.integers(0, n, size=length, dtype=np.uint64)
 
