@@ -83,7 +83,8 @@ const char *ks_strerror(int code);
  * Limbs per output coefficient for a product of lengths len_f, len_g with coeff_bits-bit
  * coefficients: ceil((2 b + e + 1) / 32), e = ceil(log2 min(len_f, len_g)) (Section 3's
  * bound 2b + e on the length of each h_i, plus a sign bit).  Returns KS_EINVAL (< 0) for
- * invalid sizes.
+ * invalid sizes.  It takes no variant: every variant computes the same h, whose coefficients
+ * the bound covers, so the output width is the same for all of them.
  */
 int64_t ks_out_limbs(int64_t len_f, int64_t len_g, int32_t coeff_bits);
 
@@ -106,7 +107,8 @@ int ks_mul(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, i
 /*
  * h = f g in (Z/pZ)[x] (Section 4: lift to Z[x], multiply by a Section 3 variant, reduce).
  *   f, g    device, len_f (len_g) uint64 residues, each in [0, p)
- *   p       odd modulus, 3 <= p < 2^62
+ *   p       modulus, 2 <= p < 2^62 (any word-sized modulus of at most 62 bits; the reduction
+ *           estimates quotients in double precision and needs 2 p < 2^63)
  *   variant KS_VARIANT_* | optional KS_ENGINE_* (KS_SIGNED is rejected)
  *   h       device, len_f + len_g - 1 uint64 residues in [0, p)
  * Residues >= p are reported as KS_ERANGE by the next status query.
@@ -162,7 +164,7 @@ typedef struct ks_desc {
     int32_t len_g;
     int32_t coeff_bits;
     int32_t flags;      /* KS_SIGNED, KS_MOD */
-    uint64_t mod_p;     /* odd modulus, 3 <= mod_p < 2^62, when flags & KS_MOD */
+    uint64_t mod_p;     /* modulus, 2 <= mod_p < 2^62, when flags & KS_MOD */
 } ks_desc;
 
 typedef struct ks_batch_plan ks_batch_plan; /* opaque */
@@ -223,11 +225,16 @@ typedef struct ks_plan_info {
     double normalize_bytes;   /*   product column sums read once + recombined values written       */
     double finish_bytes;      /*   recombined values read + h written (extract or reconstruction)  */
     double anchor_limb_mults; /*   limb products of the reconstruction anchors (KS4)              */
-    double mfma_ops;          /* int8 operations (2 per multiply-add) of the 7-bit digit products
-                                 run on the matrix cores: 2 * sum of (digits of a) * (digits of b) */
+    double mfma_ops;          /* int8 operations (2 per multiply-add) of the products run on the
+                                 matrix cores, whose operands are balanced 8-bit digits in
+                                 [-128, 127] (4 per limb and one top carry):
+                                 2 * sum of (digits of a) * (digits of b) */
     double valu_limb_mults;   /* sum of (limbs of a) * (limbs of b) over the products run on the
                                  vector ALU (the rest of schoolbook_limb_mults runs on the matrix
                                  cores) */
+    int64_t scratch_bytes;    /* device scratch one run needs: for ks_plan, the bytes the per-stream
+                                 pool of ks_mul grows to (at least 1 MiB) for this product; for
+                                 ks_batch_plan_info, the run's workspace (= ks_batch_plan_workspace_bytes) */
 } ks_plan_info;
 
 int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, ks_plan_info *out);

@@ -157,6 +157,10 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
                  uint32_t epoch_norm, hipStream_t s);
 int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s);
 int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_signed);
+// 1 when the current device is a gfx950, else -1
+int device_ok();
+// synchronise s, then read and clear a device status word (KS_OK, KS_ERANGE or KS_EINTERNAL)
+int read_status(uint32_t *devstat, hipStream_t s);
 // a planner tunable: the value set through ks_tune_set, else the environment, else dflt
 int env_int(const char *name, int dflt);
 // whether ks_batch_plan_create would split this batch by Karatsuba (see KS_KARATSUBA_MIN_LIMBS)

@@ -39,7 +39,7 @@ class PlanInfo(ctypes.Structure):
                 ("hbm_bytes", ctypes.c_double), ("pack_bytes", ctypes.c_double),
                 ("normalize_bytes", ctypes.c_double), ("finish_bytes", ctypes.c_double),
                 ("anchor_limb_mults", ctypes.c_double), ("mfma_ops", ctypes.c_double),
-                ("valu_limb_mults", ctypes.c_double)]
+                ("valu_limb_mults", ctypes.c_double), ("scratch_bytes", ctypes.c_int64)]
 
 
 class Desc(ctypes.Structure):

@@ -2,8 +2,9 @@
 
 * a mixed batch (unequal lengths, signed and unsigned, every variant) checked product by product;
 * the 10,000-product workload (lengths log-uniform in [16, 1024], b in {16, 32, 64, 128},
-  signed, seed 3) with every product compared against the classical oracle;
-* the modular workload (64 products mod a 60-bit odd p, L = 65536) on sampled coefficients;
+  signed, seed 3) through KS4 and KS1 with every product compared against the classical oracle;
+* the modular workload (64 products mod a 60-bit odd p, L = 65536) as the bench runs it: three
+  products in full and every product sampled, for KS4 and KS1 (equal everywhere);
 * a run captured in a hipGraph, replayed several times with eager work in between;
 * descriptor validation and device range errors.
 """
@@ -56,12 +57,14 @@ def test_mixed_batch(torch_dev, oracle, variant, engine):
         assert np.array_equal(B.result(out, i), exp), (variant, i, f.shape[0], g.shape[0], bits, signed)
 
 
-def test_mixed_batch_full(torch_dev, oracle):
+@pytest.mark.parametrize("variant", ["ks4", "ks1"])
+def test_mixed_batch_full(torch_dev, oracle, variant):
+    # the 10,000-product workload as the bench runs it, every product compared in full
     prods = wl.batch_mixed_10000()
     B = ks.Batch()
     for P in prods:
         B.add(P.f, P.g, P.bits, P.signed)
-    out = run_batch(torch_dev, B, "ks4")
+    out = run_batch(torch_dev, B, variant)
     for i, P in enumerate(prods):
         exp = oracle.mul_classical(P.f, P.g, P.signed, oracle.out_limbs(P.f.shape[0], P.g.shape[0], P.bits))
         assert np.array_equal(B.result(out, i), exp), i
@@ -76,6 +79,51 @@ def test_mixed_batch_unequal_lengths(torch_dev, oracle):
     for i, P in enumerate(prods):
         exp = oracle.mul_classical(P.f, P.g, P.signed, oracle.out_limbs(P.f.shape[0], P.g.shape[0], P.bits))
         assert np.array_equal(B.result(out, i), exp), i
+
+
+def kara_levels(torch, B, variant):
+    """Run the batch at the default plan with per-launch timing on; Karatsuba levels = the
+    split and combination launches of one run / 2."""
+    plan = ks.BatchPlan(B.desc_array(), variant)
+    ain = ks.to_device(B.arena_in())
+    aout = torch.zeros(B.out_words(), dtype=torch.int32, device="cuda")
+    ws = ks.alloc_workspace(plan.workspace_bytes)
+    ks.profile_reset()
+    ks.profile_enable(True)
+    plan.run(ain, aout, ws)
+    torch.cuda.synchronize()
+    ks.profile_enable(False)
+    n, _ms = ks.profile_read("kara")
+    ks.profile_reset()
+    rc = plan.status(ws)
+    assert rc == ks.KS_OK, ks.strerror(rc)
+    out = ks.to_host(aout)
+    plan.close()
+    return out, n // 2
+
+
+def test_modular_batch_full(torch_dev, oracle):
+    # the 64-product modular workload exactly as the bench runs it (default plan: the recursive
+    # Karatsuba split of each variant): three products compared in full (all 131,071
+    # coefficients) for KS4 and KS1, every product sampled, and KS4 equal to KS1 everywhere
+    p, pairs = wl.batch_mod_64x65536()
+    B = ks.Batch()
+    for f, g in pairs:
+        B.add_mod(f, g, p)
+    out4, lv4 = kara_levels(torch_dev, B, "ks4")
+    out1, lv1 = kara_levels(torch_dev, B, "ks1")
+    assert lv4 >= 1 and lv1 >= 1, (lv4, lv1)  # both runs took the split
+    assert np.array_equal(out4, out1)
+    for i in (0, 31, 63):
+        f, g = pairs[i]
+        exp = oracle.mul_mod(f, g, p)
+        assert np.array_equal(B.result(out4, i), exp), ("ks4", i)
+        assert np.array_equal(B.result(out1, i), exp), ("ks1", i)
+    D = 2 * 65536 - 1
+    gen = wl.rng(45)
+    for i, (f, g) in enumerate(pairs):
+        kidx = np.unique(np.concatenate([[0, 1, 32767, 32768, 65535, 65536, D - 2, D - 1], gen.integers(0, D, 24)]))
+        assert np.array_equal(B.result(out1, i)[kidx], oracle.coeffs_mod(f, g, p, kidx)), i
 
 
 def test_modular_batch_sampled(torch_dev, oracle):
@@ -187,6 +235,22 @@ def test_karatsuba_split_against_oracle(torch_dev, oracle, karatsuba_from, varia
     p = wl.paper_fig_modulus(60, 9)
     B, pairs = mod_batch(KARA_LENGTHS, p, 61)
     out = run_batch(torch_dev, B, variant)
+    for i, (f, g) in enumerate(pairs):
+        assert np.array_equal(B.result(out, i), oracle.mul_mod(f, g, p)), (variant, len(f))
+
+
+@pytest.mark.parametrize("variant", ["ks1", "neg2", "recip2", "ks4"])
+def test_karatsuba_three_levels_against_oracle(torch_dev, oracle, karatsuba_from, variant):
+    # lengths of about 1000, the threshold set from the variant's own operand length at a
+    # quarter of it: the split recurses exactly three times (leaves of 125-138 terms), which the
+    # number of split and combination launches shows, and every product matches the oracle
+    lengths = [1000, 1001, 1024, 1100]
+    p = wl.paper_fig_modulus(60, 13)
+    quarter = min(ks.plan((L + 3) // 4, (L + 3) // 4, 60, variant)["operand_limbs_f"] for L in lengths)
+    karatsuba_from(quarter)
+    B, pairs = mod_batch(lengths, p, 65)
+    out, levels = kara_levels(torch_dev, B, variant)
+    assert levels == 3, levels
     for i, (f, g) in enumerate(pairs):
         assert np.array_equal(B.result(out, i), oracle.mul_mod(f, g, p)), (variant, len(f))
 

@@ -132,7 +132,9 @@ def test_other_stream(torch_dev, oracle):
 
 def test_mod_small(torch_dev, oracle):
     torch = torch_dev
-    for p in (3, 65537, (1 << 31) - 1, wl.batch_mod_modulus(), (1 << 61) - 1):
+    # odd and even moduli: Section 4 lifts, multiplies and reduces modulo any word-sized n
+    for p in (2, 3, 10, 65537, (1 << 31) - 1, 1 << 32, wl.batch_mod_modulus(), (1 << 61) - 1, 1 << 61,
+              (1 << 62) - 2):
         gen = wl.rng(p % 1000)
         for lf, lg in ((1, 1), (2, 3), (300, 257), (1000, 1000)):
             f = gen.integers(0, p, size=lf, dtype=np.uint64)
@@ -186,6 +188,32 @@ def test_mod_paper_moduli(torch_dev, oracle, nbits):
             assert ks.status() == ks.KS_OK
             got = h.cpu().numpy().view(np.uint64)
             assert np.array_equal(got if idx is None else got[idx], exp), (nbits, L, v)
+
+
+@pytest.mark.parametrize("bits", [128, 256])
+def test_long_wide_product_sampled(torch_dev, oracle, bits):
+    # one signed product of length 65536 with 128- or 256-bit coefficients (the largest requests
+    # of the serving mix) through every variant: the first and last 20 coefficients and 200
+    # random ones against the classical oracle; the variants agree everywhere
+    gen = wl.rng(900 + bits)
+    L = 65536
+    f, g = wl.random_coeffs(gen, L, bits, True), wl.random_coeffs(gen, L, bits, True)
+    D = 2 * L - 1
+    wo = oracle.out_limbs(L, L, bits)
+    idx = np.unique(np.concatenate([np.arange(0, 20), np.arange(D - 20, D), gen.integers(0, D, 200)]))
+    exp = oracle.coeffs_classical(f, g, True, idx, wo)
+    tf, tg = ks.to_device(f), ks.to_device(g)
+    first = None
+    for v in VARIANTS:
+        h = ks.mul(tf, tg, bits, v, True)
+        rc = ks.status()
+        assert rc == ks.KS_OK, (v, ks.strerror(rc))
+        got = ks.to_host(h)
+        assert np.array_equal(got[idx], exp), (bits, v)
+        if first is None:
+            first = got
+        else:
+            assert np.array_equal(got, first), (bits, v)
 
 
 def test_invalid_arguments(torch_dev):

@@ -44,7 +44,7 @@ def test_small_memory_budget_queues(torch_dev):
     assert st.max_inflight == 1
 
 
-def test_large_mix_equals_alone(torch_dev):
+def test_large_mix_equals_alone(torch_dev, oracle):
     # long products of every size on four streams, each stream's scratch reused by products of
     # different layouts: every result equals the same product computed alone (regression: the
     # look-back status words of a product once lived in that reused scratch, where data of an
@@ -59,3 +59,23 @@ def test_large_mix_equals_alone(torch_dev):
         alone = ks.mul(ks.to_device(r.f), ks.to_device(r.g), r.bits, "auto", True)
         ks.check()
         assert torch_dev.equal(d.out, alone), d.idx
+    # the 20 largest requests (limbs per input) against the classical oracle: the first and last
+    # coefficients and 200 random ones each
+    big = sorted(st.results, key=lambda d: -reqs[d.idx].f.size)[:20]
+    gen = np.random.Generator(np.random.PCG64(53))
+    for d in big:
+        r = reqs[d.idx]
+        L = r.f.shape[0]
+        D = 2 * L - 1
+        idx = np.unique(np.concatenate([[0, D - 1], gen.integers(0, D, 200)]))
+        exp = oracle.coeffs_classical(r.f, r.g, True, idx, oracle.out_limbs(L, L, r.bits))
+        assert np.array_equal(ks.to_host(d.out)[idx], exp), (d.idx, L, r.bits)
+
+
+def test_every_served_result_passes_the_point_check(torch_dev):
+    # the check bench.py applies to every served result, on a small stream
+    reqs = serve.make_requests(200, rate_per_s=0.0, seed=54, max_len=4096, max_bits=256)
+    srv = serve.Server(slots=16, streams=4)
+    st = srv.run(reqs)
+    chk = serve.check_results(reqs, [st])
+    assert chk["checked"] == len(reqs) and chk["failed"] == 0, chk
