@@ -250,6 +250,19 @@ def check_results(reqs: list[Request], runs: list[Stats], checker: PointCheck | 
             "points": [{"q": q, "r": r} for q, r in checker.points]}
 
 
+def make_requests(count: int, rate_per_s: float, seed: int = 5, max_len: int = 65536, max_bits: int = 256):
+    """The serving mix: L log-uniform in [8, max_len], b uniform in [8, max_bits], signed values,
+    Poisson arrivals at `rate_per_s` (rate 0 or less: all arrive at time 0, a closed loop)."""
+    from . import workloads as wl
+    lens, bits, seeds = wl.serving_requests(count, seed, max_len, max_bits)
+    arr = wl.poisson_arrivals(count, rate_per_s, seed) if rate_per_s > 0 else np.zeros(count)
+    reqs = []
+    for i in range(count):
+        P = wl.request_product(int(lens[i]), int(bits[i]), int(seeds[i]))
+        reqs.append(Request(i, float(arr[i]), P.f, P.g, P.bits, True))
+    return reqs
+
+
 def with_arrivals(reqs: list[Request], rate_per_s: float, seed: int = 5) -> list[Request]:
     """The same requests (same operands) with Poisson arrival times at `rate_per_s`."""
     from . import workloads as wl

@@ -37,3 +37,17 @@ def test_residues_of_signed_limbs():
     limbs = O.ints_to_limbs(vals, 3)
     got = serve._residues(limbs, q, True)
     assert [int(x) for x in got] == [v % q for v in vals]
+
+
+def test_request_stream_shapes():
+    # the serving mix is drawn on the host: lengths and widths in range, arrivals ordered, and the
+    # same operands re-timed for the Poisson run
+    reqs = serve.make_requests(50, 0.0, seed=5, max_len=4096, max_bits=256)
+    assert len(reqs) == 50 and all(r.arrival == 0.0 for r in reqs)
+    for r in reqs:
+        assert 8 <= r.f.shape[0] <= 4096 and r.f.shape == r.g.shape
+        assert 8 <= r.bits <= 256 and r.f.shape[1] == (r.bits + 31) // 32
+    timed = serve.with_arrivals(reqs, 1000.0, seed=5)
+    arr = [r.arrival for r in timed]
+    assert arr == sorted(arr) and arr[0] > 0
+    assert all(a.f is b.f and a.idx == b.idx for a, b in zip(reqs, timed))
