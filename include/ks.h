@@ -69,6 +69,7 @@ extern "C" {
 #define KS_ERANGE (-4)        /* (status query) a coefficient was outside its declared range */
 #define KS_EUNSUPPORTED (-5)  /* valid request this build does not handle (e.g. no gfx950)   */
 #define KS_EINTERNAL (-6)     /* (status query) an on-device self-check of the reconstruction failed */
+#define KS_ESCRATCH (-7)      /* ks_mul_noalloc: the product needs more than KS_NOALLOC_SCRATCH_BYTES */
 
 #define KS_MAX_BITS 256       /* largest coeff_bits accepted                                  */
 #define KS_MAX_LEN (1LL << 24) /* largest polynomial length accepted                           */
@@ -103,6 +104,27 @@ int64_t ks_out_limbs(int64_t len_f, int64_t len_g, int32_t coeff_bits);
  */
 int ks_mul(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, int32_t coeff_bits,
            int32_t variant, void *stream, uint32_t *h);
+
+/*
+ * ks_mul for callers that cannot allocate device memory: code under HIP graph capture, serving
+ * loops and harnesses that forbid hipMalloc.  Arguments, layouts, results and errors are those
+ * of ks_mul, and so is the work enqueued (the same kernels); the scratch comes from a fixed
+ * device array of KS_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on until
+ * the process ends, so the call allocates nothing (device or pinned memory) and frees nothing.
+ *   Limit   a product whose scratch exceeds the array (about 63.5 MiB of operands, column sums
+ *           and reconstruction buffers, and 65,536 carry-scan blocks) returns KS_ESCRATCH before
+ *           anything is enqueued; ks_plan's scratch_bytes tells the size beforehand.
+ *   Sharing every call on one GPU uses that GPU's array, whose contents persist between calls:
+ *           calls that may overlap on one GPU (other streams or host threads) race, and the
+ *           caller must order them (one stream, or events).
+ *   Status  device-found errors (KS_ERANGE, KS_EINTERNAL) are reported by the next
+ *           ks_stream_status on the stream of the call (with the device current).
+ * The first call on a device enqueues one more small kernel that clears the array's control
+ * words.
+ */
+#define KS_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int ks_mul_noalloc(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, int32_t coeff_bits,
+                   int32_t variant, void *stream, uint32_t *h);
 
 /*
  * h = f g in (Z/pZ)[x] (Section 4: lift to Z[x], multiply by a Section 3 variant, reduce).

@@ -876,6 +876,7 @@ const char *ks_strerror(int code) {
         case KS_ERANGE: return "coefficient outside its declared range";
         case KS_EUNSUPPORTED: return "not supported by this build or device";
         case KS_EINTERNAL: return "internal self-check failed";
+        case KS_ESCRATCH: return "the product needs more scratch than ks_mul_noalloc's fixed array holds";
     }
     return "unknown status code";
 }
@@ -1125,7 +1126,9 @@ int ks_stream_status(void *stream) {
         auto it = g_pools.find(s);
         if (it != g_pools.end()) p = it->second;
     }
-    return p ? read_status(p->ctl.devstat, s) : (hipStreamSynchronize(s) == hipSuccess ? KS_OK : KS_EHIP);
+    int rc = p ? read_status(p->ctl.devstat, s) : (hipStreamSynchronize(s) == hipSuccess ? KS_OK : KS_EHIP);
+    const int rc2 = noalloc_status(s);  // ks_mul_noalloc's status word on this device
+    return rc != KS_OK ? rc : rc2;
 }
 
 int ks_profile_enable(int32_t on) {

@@ -161,6 +161,8 @@ int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_
 int device_ok();
 // synchronise s, then read and clear a device status word (KS_OK, KS_ERANGE or KS_EINTERNAL)
 int read_status(uint32_t *devstat, hipStream_t s);
+// the status word of ks_mul_noalloc's array on the current device (KS_OK if never used)
+int noalloc_status(hipStream_t s);
 // a planner tunable: the value set through ks_tune_set, else the environment, else dflt
 int env_int(const char *name, int dflt);
 // whether ks_batch_plan_create would split this batch by Karatsuba (see KS_KARATSUBA_MIN_LIMBS)

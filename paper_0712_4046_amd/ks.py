@@ -22,6 +22,8 @@ KS_ENGINE_VALU, KS_ENGINE_MFMA = 0x1000, 0x2000
 KS_ENGINE = {None: 0, "valu": KS_ENGINE_VALU, "mfma": KS_ENGINE_MFMA}
 KS_MOD = 0x10000
 KS_OK, KS_EINVAL, KS_ENOMEM, KS_EHIP, KS_ERANGE, KS_EUNSUPPORTED, KS_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+KS_ESCRATCH = -7
+KS_NOALLOC_SCRATCH_BYTES = 64 << 20
 KS_MAX_BITS = 256
 
 
@@ -65,6 +67,7 @@ def lib() -> ctypes.CDLL:
         "ks_out_limbs": ([i64, i64, i32], i64),
         "ks_mul": ([P, P, i64, i64, i32, i32, P, P], ctypes.c_int),
         "ks_mul_mod": ([P, P, i64, i64, u64, i32, P, P], ctypes.c_int),
+        "ks_mul_noalloc": ([P, P, i64, i64, i32, i32, P, P], ctypes.c_int),
         "ks_mul_poly2": ([P, P, i64, i64, u64, i32, i32, P, P], ctypes.c_int),
         "ks_stream_status": ([P], ctypes.c_int),
         "ks_plan": ([i64, i64, i32, i32, ctypes.POINTER(PlanInfo)], ctypes.c_int),
@@ -161,6 +164,27 @@ def mul(f, g, bits: int, variant: str = "auto", signed: bool = False, engine=Non
     rc = lib().ks_mul(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()), lf, lg, bits,
                       _flags(variant, signed, engine), _stream_ptr(stream), ctypes.c_void_p(out.data_ptr()))
     _check(rc, "ks_mul")
+    return out
+
+
+def mul_noalloc(f, g, bits: int, variant: str = "auto", signed: bool = False, engine=None, stream=None, out=None):
+    """h = f g through ks_mul_noalloc (scratch from the library's fixed device array; the output
+    tensor is the caller's: pass `out` to allocate nothing at all)."""
+    import torch
+    W = limbs_for_bits(bits)
+    if f.dim() != 2 or g.dim() != 2 or f.shape[1] != W or g.shape[1] != W:
+        raise ValueError(f"inputs must be (L, {W}) limb tensors")
+    if not (f.is_cuda and g.is_cuda and f.is_contiguous() and g.is_contiguous()):
+        raise ValueError("inputs must be contiguous CUDA tensors")
+    lf, lg = f.shape[0], g.shape[0]
+    wo = out_limbs(lf, lg, bits)
+    if out is None:
+        out = torch.empty((lf + lg - 1, wo), dtype=torch.int32, device=f.device)
+    elif tuple(out.shape) != (lf + lg - 1, wo) or not out.is_contiguous():
+        raise ValueError("out has the wrong shape")
+    rc = lib().ks_mul_noalloc(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()), lf, lg, bits,
+                              _flags(variant, signed, engine), _stream_ptr(stream), ctypes.c_void_p(out.data_ptr()))
+    _check(rc, "ks_mul_noalloc")
     return out
 
 
