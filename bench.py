@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # x1) on the headline workload (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).
 MEASURED_TRAFFIC_C4 = {}
-KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "normalize", "anchor", "recon", "finish", "extract",
-           "p2_eval", "p2_recon")
+KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows",
+           "ntt_inv_cols", "normalize", "anchor", "recon", "finish", "extract", "p2_eval", "p2_recon")
 METRIC = "polynomial products/s + limb-mults/s at 1 GPU; KS4 vs KS1 speedup, bit-exact"
 
 

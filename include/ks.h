@@ -59,6 +59,9 @@ extern "C" {
 #define KS_SIGNED 0x100        /* coefficients are signed two's complement                   */
 #define KS_ENGINE_VALU 0x1000  /* force the vector-ALU 32x32-bit limb multiplier            */
 #define KS_ENGINE_MFMA 0x2000  /* force the int8 matrix-core (MFMA) limb multiplier          */
+#define KS_ENGINE_NTT 0x4000   /* force the number-theoretic-transform multiplier (products
+                                  beyond its longest transform, 2^24 terms, use the matrix cores) */
+#define KS_ENGINE_ANY (KS_ENGINE_VALU | KS_ENGINE_MFMA | KS_ENGINE_NTT)
 #define KS_MOD 0x10000         /* batch descriptor flag: residues mod desc.mod_p (see below) */
 
 /* ---- status codes ------------------------------------------------------------------------- */
@@ -233,7 +236,8 @@ int ks_mul_batch(const uint32_t *arena_in, uint32_t *arena_out, const ks_desc *d
 
 typedef struct ks_plan_info {
     int32_t variant;          /* resolved KS_VARIANT_* */
-    int32_t engine;           /* KS_ENGINE_VALU or KS_ENGINE_MFMA (a batch: the OR of its products') */
+    int32_t engine;           /* KS_ENGINE_VALU, KS_ENGINE_MFMA or KS_ENGINE_NTT (a batch: the OR of
+                                 its products') */
     int32_t e;                /* ceil(log2 min(len_f, len_g)) */
     int32_t slot_bits;        /* N of the resolved variant */
     int32_t n_products;       /* 1, 2 or 4 integer products */
@@ -257,6 +261,9 @@ typedef struct ks_plan_info {
     int64_t scratch_bytes;    /* device scratch one run needs: for ks_plan, the bytes the per-stream
                                  pool of ks_mul grows to (at least 1 MiB) for this product; for
                                  ks_batch_plan_info, the run's workspace (= ks_batch_plan_workspace_bytes) */
+    double ntt_butterflies;   /* radix-2 butterflies of the products on the transform engine: three
+                                 transforms of length N (two forward, one inverse) modulo each of
+                                 two primes, (N / 2) log2 N butterflies each */
 } ks_plan_info;
 
 int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, ks_plan_info *out);
@@ -268,8 +275,9 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
  * kernel `name`, the number of launches and their summed duration in milliseconds.  Names:
  * "pack" (with the anchors it carries), "mul_valu", "mul_mfma", "normalize", "anchor",
  * "recon", "finish", "extract", "digitize", "p2_eval", "p2_recon" (bivariate evaluation and
- * read-off or gluing), "kara" (the Karatsuba split and combination of a batch).  Returns
- * KS_EINVAL for an unknown name.
+ * read-off or gluing), "kara" (the Karatsuba split and combination of a batch),
+ * "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols" (the four steps of the
+ * transform engine).  Returns KS_EINVAL for an unknown name.
  */
 int ks_profile_enable(int32_t on);
 int ks_profile_read(const char *name, int64_t *launches, double *total_ms);
@@ -297,12 +305,14 @@ int ks_profile_reset(void);
  *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
  *                              128; 256 in a batch, and unset, a batch uses 256) run one wave
  *                              per job (0: every job in 256-thread blocks)
+ *   "KS_NTT_MIN_LIMBS"   12000 both operands at least this many limbs -> transform engine
+ *                              (0: never unless forced)
  *   "KS_KARATSUBA_MIN_LIMBS" 16384  t: a batch plan whose products are all modular with equal
  *                              lengths, whose integer operands total at least 8 t limbs and
  *                              each have at least t (2 t when the batch totals 128 t), splits
  *                              each product Karatsuba's way on the polynomials (three products
  *                              of half the length, combined mod p), and again while the halves
- *                              qualify; 0: never
+ *                              qualify (never when they run on the transform engine); 0: never
  * ks_tune_set returns KS_EINVAL for an unknown name or a negative value; ks_tune_get returns
  * the value in force (KS_EINVAL if unknown); ks_tune_reset clears every value set here.
  * Plans made before a change keep their shapes.  Used by paper_0712_4046_amd/autotune.py.

@@ -39,7 +39,8 @@ static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
 // planner tunables: a value set through ks_tune_set, else the environment, else the default
 static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS",  "KS_MFMA_MIN_PART",
                                          "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",     "KS_MUL_WAVE_MAX",
-                                         "KS_SCAN_SMALL",      "KS_MFMA_RT",      "KS_KARATSUBA_MIN_LIMBS"};
+                                         "KS_SCAN_SMALL",      "KS_MFMA_RT",      "KS_KARATSUBA_MIN_LIMBS",
+                                         "KS_NTT_MIN_LIMBS"};
 static std::mutex g_tune_mu;
 static std::map<std::string, int64_t> g_tune;
 
@@ -214,6 +215,13 @@ int plan_product(const Spec &sp, Geom &G) {
         m.nA32 = cdiv(m.nad, 32);
         m.nB32 = cdiv(m.nbd + 31, 32);
         int eng = sp.engine;
+        // long operands go through the transforms (quasi-linear), when a transform length fits
+        const int64_t ntt_min = env_int("KS_NTT_MIN_LIMBS", NTT_MIN_LIMBS);
+        if (eng == 0 && ntt_min > 0 && std::min(nf, ng) >= ntt_min &&
+            ntt_shape(nf, ng, 0, m.ntt_k1, m.ntt_k2, m.ntt_w, m.ntt_npa, m.ntt_npb))
+            eng = KS_ENGINE_NTT;
+        if (eng == KS_ENGINE_NTT && !ntt_shape(nf, ng, 0, m.ntt_k1, m.ntt_k2, m.ntt_w, m.ntt_npa, m.ntt_npb))
+            eng = KS_ENGINE_MFMA;  // beyond the longest transform
         // the matrix cores cost a digit launch more: a single product needs operands of about
         // 2200-2400 limbs to gain (vector ALU / matrix cores 0.99-1.01 there, 1.12-1.17 at
         // ~4400 limbs); a batch shares that launch among its products (10,000-product batch:
@@ -223,6 +231,20 @@ int plan_product(const Spec &sp, Geom &G) {
             eng = std::min(nf, ng) >= env_int("KS_MFMA_MIN_LIMBS", sp.batch ? 1000 : 2500) ? KS_ENGINE_MFMA
                                                                                           : KS_ENGINE_VALU;
         m.engine = eng;
+        if (eng == KS_ENGINE_NTT) {
+            const int64_t Nt = (int64_t)1 << (m.ntt_k1 + m.ntt_k2);
+            m.ntt_nz = m.ntt_npa + m.ntt_npb - 1;
+            m.ntt_xa = G.ntt_words;
+            m.ntt_xb = m.ntt_xa + 2 * Nt;
+            m.ntt_z = m.ntt_xb + 2 * Nt;
+            G.ntt_words = m.ntt_z + align_up(2 * m.ntt_nz, 64);
+            m.ncols = m.ntt_nz;  // the recombination reads the terms
+            m.cols_off = -1;
+            G.muls.push_back(m);
+            G.school_mults += (double)nf * (double)ng;
+            G.ntt_butterflies += 6.0 * (double)(Nt / 2) * (double)(m.ntt_k1 + m.ntt_k2);
+            continue;
+        }
         if (eng == KS_ENGINE_MFMA) {
             const int64_t rows = cdiv(m.nad + m.nbd - 1, 32);
             // row tiles per block: 8 share each loaded a-fragment among more matrix operations
@@ -374,6 +396,7 @@ int plan_product(const Spec &sp, Geom &G) {
     G.ws_norms = o;   o += align_up(G.norm_limbs * 4, 256);
     G.ws_anchors = o; o += align_up(std::max<int64_t>(G.anchor_limbs, 1) * 4, 256);
     G.ws_hbuf = o;    o += align_up(G.hbuf_words * 4, 256);
+    G.ws_ntt = o;     o += align_up(G.ntt_words * 4, 256);
     G.ws_status = o;  o += align_up(std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1) * 8, 256);
     G.ws_bytes = o;
 
@@ -385,8 +408,15 @@ int plan_product(const Spec &sp, Geom &G) {
     double norm_out = 0;
     for (auto &r : G.norms) norm_out += 4.0 * r.n_out;
     G.pack_bytes = in_bytes + 4.0 * G.op_limbs;
-    const double col_bytes = (!G.muls.empty() && G.muls[0].engine == KS_ENGINE_MFMA) ? 16.0 : 12.0;
-    G.normalize_bytes = col_bytes * npts * prod_limbs + norm_out;
+    const int eng0 = G.muls.empty() ? KS_ENGINE_VALU : G.muls[0].engine;
+    if (eng0 == KS_ENGINE_NTT) {
+        double terms = 0;
+        for (auto &m : G.muls) terms += 8.0 * (double)m.ntt_nz;
+        G.normalize_bytes = terms + norm_out;
+    } else {
+        const double col_bytes = eng0 == KS_ENGINE_MFMA ? 16.0 : 12.0;
+        G.normalize_bytes = col_bytes * npts * prod_limbs + norm_out;
+    }
     G.finish_bytes = norm_out + out_bytes;
     return KS_OK;
 }
@@ -474,7 +504,43 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         pl.push_back(j);
     }
     auto digits = [&](int64_t byte_off) { return reinterpret_cast<uint8_t *>(ws + G.ws_digits + byte_off); };
+    auto nttw = [&](int64_t word_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_ntt + 4 * word_off); };
     for (auto &m : G.muls) {
+        if (m.engine == KS_ENGINE_NTT) {
+            const int k = m.ntt_k1 + m.ntt_k2;
+            NttJob j;
+            memset(&j, 0, sizeof(j));
+            j.k1 = m.ntt_k1;
+            j.k2 = m.ntt_k2;
+            j.w = m.ntt_w;
+            j.kscale[0] = ntt_scale(0, k);
+            j.kscale[1] = ntt_scale(1, k);
+            const int64_t per_prime = (int64_t)1 << (k - 13);  // blocks of one prime in a step
+            for (int side = 0; side < 2; ++side) {
+                NttJob f = j;
+                f.a = ops(G.packs[side ? m.fb : m.fa].op_off);
+                f.na = side ? m.nb : m.na;
+                f.np = side ? m.ntt_npb : m.ntt_npa;
+                f.x = nttw(side ? m.ntt_xb : m.ntt_xa);
+                f.nblocks = 2 * per_prime;
+                f.block0 = next_block(JL.ntt_f1);
+                JL.ntt_f1.push_back(f);
+                f.block0 = next_block(JL.ntt_f2);
+                JL.ntt_f2.push_back(f);
+            }
+            NttJob inv = j;
+            inv.x = nttw(m.ntt_xa);
+            inv.y = nttw(m.ntt_xb);
+            inv.z = reinterpret_cast<uint64_t *>(nttw(m.ntt_z));
+            inv.nz = m.ntt_nz;
+            inv.nblocks = 2 * per_prime;
+            inv.block0 = next_block(JL.ntt_i2);
+            JL.ntt_i2.push_back(inv);
+            inv.nblocks = per_prime;  // both primes in one block (the Chinese remainder step)
+            inv.block0 = next_block(JL.ntt_i1);
+            JL.ntt_i1.push_back(inv);
+            continue;
+        }
         if (m.engine == KS_ENGINE_MFMA) {
             for (int side = 0; side < 2; ++side) {
                 DigitJob d;
@@ -551,14 +617,15 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         for (int t = 0; t < r.nterms; ++t) {
             const MulGeom &m = G.muls[r.prod[t]];
             NormTerm &T = j.term[t];
-            T.cols = cols(m.cols_off);
+            T.cols = m.engine == KS_ENGINE_NTT ? nttw(m.ntt_z) : cols(m.cols_off);
             T.ncols = m.ncols;
             T.a = ops(G.packs[m.fa].op_off);
             T.b = ops(G.packs[m.fb].op_off);
             T.na = m.na;
             T.nb = m.nb;
             T.sign = r.sign[t];
-            T.fmt = m.engine == KS_ENGINE_MFMA ? NORM_FMT_XY : NORM_FMT_PIECES;
+            T.fmt = m.engine == KS_ENGINE_MFMA ? NORM_FMT_XY : m.engine == KS_ENGINE_NTT ? NORM_FMT_WPIECE : NORM_FMT_PIECES;
+            T.pw = m.ntt_w;
         }
         j.shift = r.shift;
         j.off_bit0 = r.off_bit0;
@@ -691,6 +758,17 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         err = timed("mul_mfma", s, [&] { return launch_mul_mfma(L, JL.mfma_rt, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
+    if (!JL.ntt_f1.empty()) {
+        const std::vector<NttJob> *lists[4] = {&JL.ntt_f1, &JL.ntt_f2, &JL.ntt_i2, &JL.ntt_i1};
+        const DevList *tabs[4] = {T ? &T->ntt_f1 : nullptr, T ? &T->ntt_f2 : nullptr, T ? &T->ntt_i2 : nullptr,
+                                  T ? &T->ntt_i1 : nullptr};
+        static const char *names[4] = {"ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols"};
+        for (int st = 0; st < 4; ++st) {
+            auto L = make_launch(*lists[st], tabs[st], env, 0);
+            err = timed(names[st], s, [&] { return launch_ntt_stage(st, L, s); });
+            if (err != hipSuccess) return KS_EHIP;
+        }
+    }
     for (auto it = JL.anchor.begin(); it != JL.anchor.end(); ++it) {
         if (it == first_anchor) continue;
         const auto &kv = *it;
@@ -727,6 +805,12 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
 }
 
 int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, char *ws, Ctl &ctl, hipStream_t s) {
+    for (auto &m : G.muls)
+        if (m.engine == KS_ENGINE_NTT) {
+            const int rc = ntt_prepare();
+            if (rc != KS_OK) return rc;
+            break;
+        }
     JobLists JL;
     emit_jobs(G, reinterpret_cast<uintptr_t>(f), reinterpret_cast<uintptr_t>(g), reinterpret_cast<uintptr_t>(h),
               reinterpret_cast<uintptr_t>(ws), JL);
@@ -845,9 +929,10 @@ int validate_spec(int64_t lf, int64_t lg, int bits, int32_t variant, bool allow_
         v != KS_VARIANT_KS4)
         return KS_EINVAL;
     if ((variant & KS_SIGNED) && !allow_signed) return KS_EINVAL;
-    int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_VALU | KS_ENGINE_MFMA;
+    int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_VALU | KS_ENGINE_MFMA | KS_ENGINE_NTT;
     if (variant & ~known) return KS_EINVAL;
-    if ((variant & KS_ENGINE_MFMA) && (variant & KS_ENGINE_VALU)) return KS_EINVAL;
+    const int eng = variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA | KS_ENGINE_NTT);
+    if (eng & (eng - 1)) return KS_EINVAL;  // at most one engine
     return KS_OK;
 }
 
@@ -892,7 +977,7 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
     int rc = validate_spec(len_f, len_g, coeff_bits, variant, true);
     if (rc != KS_OK) return rc;
     Spec sp{len_f, len_g, coeff_bits, (int)cdiv(coeff_bits, 32), (variant & KS_SIGNED) != 0, 0,
-            variant & KS_VARIANT_MASK, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+            variant & KS_VARIANT_MASK, variant & KS_ENGINE_ANY};
     Geom G;
     rc = plan_product(sp, G);
     if (rc != KS_OK) return rc;
@@ -914,6 +999,7 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
     out->mfma_ops = G.mfma_ops;
     out->valu_limb_mults = G.valu_mults;
     out->scratch_bytes = std::max<int64_t>(G.ws_status, (int64_t)1 << 20);  // the pool's size for it
+    out->ntt_butterflies = G.ntt_butterflies;
     return KS_OK;
 }
 
@@ -937,7 +1023,7 @@ int ks_mul(const uint32_t *f, const uint32_t *g, int64_t len_f, int64_t len_g, i
     int rc = validate_spec(len_f, len_g, coeff_bits, variant, true);
     if (rc != KS_OK) return rc;
     Spec sp{len_f, len_g, coeff_bits, (int)cdiv(coeff_bits, 32), (variant & KS_SIGNED) != 0, 0,
-            variant & KS_VARIANT_MASK, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+            variant & KS_VARIANT_MASK, variant & KS_ENGINE_ANY};
     return mul_common(f, g, sp, stream, h);
 }
 
@@ -948,7 +1034,7 @@ int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_
     int bits = bitlen_u64(p - 1);
     int rc = validate_spec(len_f, len_g, bits, variant, false);
     if (rc != KS_OK) return rc;
-    Spec sp{len_f, len_g, bits, 2, false, p, variant & KS_VARIANT_MASK, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+    Spec sp{len_f, len_g, bits, 2, false, p, variant & KS_VARIANT_MASK, variant & KS_ENGINE_ANY};
     return mul_common(reinterpret_cast<const uint32_t *>(f), reinterpret_cast<const uint32_t *>(g), sp, stream, h);
 }
 
@@ -1059,7 +1145,7 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
         rc = batch_run_into(pl->p2plan, reinterpret_cast<const uint32_t *>(pl->stage),
                             reinterpret_cast<uint32_t *>(pl->stage), pl->stage + ws_off, pl->ctl.devstat, s);
     } else {
-        Spec sp{le, le, bits, 2, false, p, inner & KS_VARIANT_MASK, inner & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+        Spec sp{le, le, bits, 2, false, p, inner & KS_VARIANT_MASK, inner & KS_ENGINE_ANY};
         rc = mul_common(reinterpret_cast<const uint32_t *>(ev), reinterpret_cast<const uint32_t *>(ev + le), sp,
                         stream, prod);
     }
@@ -1146,7 +1232,7 @@ int ks_tune_set(const char *name, int64_t value) {
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
     static const int dflt[] = {2500, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE), 0,
-                               KARATSUBA_MIN_LIMBS};  // as for a single product
+                               KARATSUBA_MIN_LIMBS, NTT_MIN_LIMBS};  // as for a single product
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];
@@ -1175,7 +1261,8 @@ int ks_profile_reset(void) {
 int ks_profile_read(const char *name, int64_t *launches, double *total_ms) {
     if (!name || !launches || !total_ms) return KS_EINVAL;
     static const char *known[] = {"pack",  "mul_valu", "mul_mfma", "normalize", "anchor",  "recon",
-                                  "extract", "digitize", "finish",  "p2_eval",   "p2_recon", "kara"};
+                                  "extract", "digitize", "finish",  "p2_eval",   "p2_recon", "kara",
+                                  "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols"};
     bool ok = false;
     for (const char *k : known) ok = ok || strcmp(k, name) == 0;
     if (!ok) return KS_EINVAL;

@@ -88,6 +88,7 @@ struct ks_batch_plan {
     int64_t ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
     double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0, valu_mults = 0;
+    double ntt_butterflies = 0;
     int32_t engines = 0;  // OR of the engines the products use
     int variant = -1;
     // polynomial-level Karatsuba (every product modular, equal lengths, long): the three
@@ -179,12 +180,14 @@ static bool karatsuba_applies(const ks_desc *descs, int64_t count, int32_t varia
         if (d.len_f != d.len_g || d.len_f < 2) return false;
         const int v = variant & KS_VARIANT_MASK;
         if (validate_spec(d.len_f, d.len_g, bitlen_u64(p - 1), v, true) != KS_OK) return false;
-        Spec sp{d.len_f, d.len_g, bitlen_u64(p - 1), 2, false, p, v, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+        Spec sp{d.len_f, d.len_g, bitlen_u64(p - 1), 2, false, p, v, variant & KS_ENGINE_ANY};
         sp.batch = true;
         sp.batch_count = count;
         sp.fill_blocks = std::max<int64_t>(1, 2048 / count);
         Geom G;
         if (plan_product(sp, G) != KS_OK) return false;
+        // a quasi-linear product gains nothing from the split
+        if (!G.muls.empty() && G.muls[0].engine == KS_ENGINE_NTT) return false;
         const int64_t n = std::min(G.nf, G.ng);
         if (n < thr) return false;
         shortest = std::min(shortest, n);
@@ -238,7 +241,7 @@ static int plan_karatsuba(const ks_desc *descs, int64_t count, int32_t variant, 
         max_out = std::max(max_out, 2 * K.L - 1);
         // the schoolbook count of the unsplit product, for the plan's totals
         Spec sp{d.len_f, d.len_g, bitlen_u64(d.mod_p - 1), 2, false, d.mod_p, variant & KS_VARIANT_MASK,
-                variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+                variant & KS_ENGINE_ANY};
         sp.batch = true;
         sp.batch_count = count;
         sp.fill_blocks = std::max<int64_t>(1, 2048 / count);
@@ -268,6 +271,7 @@ static int plan_karatsuba(const ks_desc *descs, int64_t count, int32_t variant, 
     P->anchor_mults = inner->anchor_mults;
     P->mfma_ops = inner->mfma_ops;
     P->valu_mults = inner->valu_mults;
+    P->ntt_butterflies = inner->ntt_butterflies;
     P->engines = inner->engines;
     P->variant = inner->variant;
     void *t = nullptr;
@@ -287,10 +291,11 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
     g_bad_index = -1;
     if (!descs || !out || count < 1) return KS_EINVAL;
     *out = nullptr;
-    const int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_VALU | KS_ENGINE_MFMA;
+    const int known = KS_VARIANT_MASK | KS_SIGNED | KS_ENGINE_ANY;
     if (variant & ~known) return KS_EINVAL;
     const int v = variant & KS_VARIANT_MASK;
-    const int eng = variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA);
+    const int eng = variant & KS_ENGINE_ANY;
+    if (eng & (eng - 1)) return KS_EINVAL;  // at most one engine
     if (v != KS_VARIANT_AUTO && v != KS_VARIANT_KS1 && v != KS_VARIANT_NEG2 && v != KS_VARIANT_RECIP2 &&
         v != KS_VARIANT_KS4)
         return KS_EINVAL;
@@ -335,6 +340,7 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
         P->anchor_mults += geoms[(size_t)i].anchor_mults;
         P->mfma_ops += geoms[(size_t)i].mfma_ops;
         P->valu_mults += geoms[(size_t)i].valu_mults;
+        P->ntt_butterflies += geoms[(size_t)i].ntt_butterflies;
         for (const auto &m : geoms[(size_t)i].muls) P->engines |= m.engine;
         int rv = geoms[(size_t)i].variant;
         P->variant = i == 0 ? rv : (P->variant == rv ? rv : -1);
@@ -359,6 +365,13 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
     for (auto &j : JL.mul_wave) { sh(j.a); sh(j.b); sh(j.cols); }
     for (auto &j : JL.digit) { sh(j.limbs); sh(j.out); sh(j.zero); }
     for (auto &j : JL.mfma) { sh(j.ad); sh(j.bd); sh(j.cols); }
+    for (auto *nl : {&JL.ntt_f1, &JL.ntt_f2, &JL.ntt_i2, &JL.ntt_i1})
+        for (auto &j : *nl) {  // offsets (0 is a valid one); unused fields are never read
+            sh(j.a);
+            sh(j.x);
+            sh(j.y);
+            sh(j.z);
+        }
     for (auto &kv : JL.anchor) for (auto &j : kv.second) sh(j.anchors);
     for (auto *nl : {&JL.norm, &JL.norm_small})
         for (auto &j : *nl) {
@@ -385,7 +398,12 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
     merge_widths(JL.finish);
 
     int rc = KS_OK;
+    if (!JL.ntt_f1.empty()) rc = ntt_prepare();  // the transforms' root tables on this device
     if (rc == KS_OK) rc = upload(JL.pack, P->T.pack, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.ntt_f1, P->T.ntt_f1, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.ntt_f2, P->T.ntt_f2, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.ntt_i2, P->T.ntt_i2, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.ntt_i1, P->T.ntt_i1, P->allocs);
     if (rc == KS_OK) rc = upload(JL.pack_small, P->T.pack_small, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mul, P->T.mul, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mul_wave, P->T.mul_wave, P->allocs);
@@ -421,6 +439,7 @@ int ks_batch_plan_info(const ks_batch_plan *plan, ks_plan_info *out) {
     out->mfma_ops = plan->mfma_ops;
     out->valu_limb_mults = plan->valu_mults;
     out->scratch_bytes = plan->ws_bytes;
+    out->ntt_butterflies = plan->ntt_butterflies;
     return KS_OK;
 }
 

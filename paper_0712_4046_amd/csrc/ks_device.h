@@ -380,6 +380,13 @@ template <> __device__ __forceinline__ void rebase(MfmaJob &J, const Launch<Mfma
     J.cols = at(L.base_ws, J.cols);
 }
 
+template <> __device__ __forceinline__ void rebase(NttJob &J, const Launch<NttJob> &L) {
+    J.a = at(L.base_ws, J.a);
+    J.x = at(L.base_ws, J.x);
+    J.y = at(L.base_ws, J.y);
+    J.z = at(L.base_ws, J.z);
+}
+
 template <class J>
 __device__ __forceinline__ J get_job(const Launch<J> &L, int64_t blk, int64_t &local) {
     J job = find_job(L, blk, local);

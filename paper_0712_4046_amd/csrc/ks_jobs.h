@@ -125,9 +125,43 @@ struct MfmaJob {
     int64_t nblocks;
 };
 
+// Integer product through number-theoretic transforms (large operands): each operand (unsigned
+// reading of its limbs) is cut into pieces of w bits, the pieces are convolved modulo two
+// primes P = c 2^k + 1 below 2^31 by transforms of length N = 2^k = N1 N2 (four steps: N2
+// column transforms of length N1, a twiddle, N1 row transforms of length N2; each in LDS), and
+// the two residues of every convolution term are joined by the Chinese remainder theorem into
+// the exact term (below P1 P2, guaranteed by the planner's choice of w).  Transforms stay in
+// the order the steps leave them (rows and positions bit-reversed), which the pointwise product
+// does not mind and the inverse steps undo.
+constexpr int NTT_TPB = 256;
+constexpr int NTT_BLOCK = 8192;   // elements a block transforms: C columns of N1, or R rows of N2
+constexpr int NTT_MIN_LOG = 13, NTT_MAX_LOG = 24;  // N1, N2 <= 4096; C = NTT_BLOCK / N1 <= N2
+constexpr int NTT_ROOT_LOG = 26;  // root tables: powers of a root of order 2^26 of each prime
+constexpr uint32_t NTT_P0 = 2013265921u;  // 15 2^27 + 1
+constexpr uint32_t NTT_P1 = 1811939329u;  // 27 2^26 + 1
+
+// One stage of the transforms of one operand (forward) or one product (inverse).
+struct NttJob {
+    const uint32_t *a;  // forward columns: the operand's limbs (unsigned reading)
+    int64_t na;         // limbs of a
+    int64_t np;         // pieces of a (pieces at or above np read 0)
+    uint32_t *x;        // the transform, 2 N words (prime 0, then prime 1); inverse: the
+                        // first operand's transform, overwritten by the product's
+    const uint32_t *y;  // inverse rows: the second operand's transform
+    uint64_t *z;        // inverse columns: the product's terms (nz of them)
+    int64_t nz;
+    int32_t k1, k2;     // N1 = 2^k1, N2 = 2^k2
+    int32_t w;          // piece bits
+    int32_t pad;
+    uint32_t kscale[2]; // inverse rows: R^2 / N mod P (R = 2^32), per prime
+    int64_t block0;
+    int64_t nblocks;
+};
+
 // column-sum formats: three uint32 pieces per column (weights 2^0, 2^32, 2^64; the vector-ALU
-// multiplier) or two uint64 sums per column (weights 2^0, 2^32; the matrix-core multiplier)
-enum : int32_t { NORM_FMT_PIECES = 0, NORM_FMT_XY = 1 };
+// multiplier), two uint64 sums per column (weights 2^0, 2^32; the matrix-core multiplier), or
+// the transforms' convolution terms of pw-bit pieces (term m, below 2^62, at weight 2^(pw m))
+enum : int32_t { NORM_FMT_PIECES = 0, NORM_FMT_XY = 1, NORM_FMT_WPIECE = 2 };
 
 // one product read back from its column sums, corrected for two's-complement operands;
 // column j of the value gets piece 0 of column j, piece 1 of j-1 and piece 2 of j-2
@@ -139,7 +173,9 @@ struct NormTerm {
     int64_t na;
     int64_t nb;
     int32_t sign;  // +1 or -1
-    int32_t fmt;   // NORM_FMT_PIECES or NORM_FMT_XY
+    int32_t fmt;   // NORM_FMT_PIECES, NORM_FMT_XY or NORM_FMT_WPIECE
+    int32_t pw;    // NORM_FMT_WPIECE: bits per piece (ncols counts terms)
+    int32_t pad;
 };
 
 // V = sum_terms sign * product + sum_{k < off_count} 2^(off_bit0 + k off_period);

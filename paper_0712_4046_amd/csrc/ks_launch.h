@@ -46,6 +46,9 @@ hipError_t launch_finish(const Launch<ChainJob> &L, int nw, hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_digitize(const Launch<DigitJob> &L, hipStream_t s);
 hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, int rt, hipStream_t s);  // rt: tiles per block (4 or 8)
+// one of the four transform steps of integer products on the transform engine: 0 forward
+// columns, 1 forward rows, 2 inverse rows (with the pointwise product), 3 inverse columns
+hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, hipStream_t s);
 hipError_t launch_p2_eval(const P2Eval &E, hipStream_t s);
 hipError_t launch_p2_readoff(const P2Readoff &R, hipStream_t s);
 hipError_t launch_p2_glue(const P2Glue &G, hipStream_t s);  // two launches (chunk sums, then outputs)

@@ -86,7 +86,7 @@ extern "C" int ks_mul_noalloc(const uint32_t *f, const uint32_t *g, int64_t len_
     if (rc != KS_OK) return rc;
     if (device_ok() != 1) return KS_EUNSUPPORTED;
     Spec sp{len_f, len_g, coeff_bits, (int)((coeff_bits + 31) / 32), (variant & KS_SIGNED) != 0, 0,
-            variant & KS_VARIANT_MASK, variant & (KS_ENGINE_VALU | KS_ENGINE_MFMA)};
+            variant & KS_VARIANT_MASK, variant & KS_ENGINE_ANY};
     Geom G;
     rc = plan_product(sp, G);
     if (rc != KS_OK) return rc;

@@ -1,0 +1,355 @@
+// ks_ntt.hip -- integer products through number-theoretic transforms, for long operands.
+//
+// The paper's cost model (Section 1) sets M(b) against 4 M(b/4); for very long operands the
+// integer product itself should be quasi-linear, which is what this engine provides.  An
+// operand of n limbs (its unsigned reading; the recombination corrects two's-complement signs)
+// is cut into np = ceil(32 n / w) pieces of w bits, and the pieces of a and b are convolved:
+// c_m = sum_i a'_i b'_{m-i}, so that A B = sum_m c_m 2^(w m).  The convolution is computed
+// modulo P0 = 15 2^27 + 1 and P1 = 27 2^26 + 1 by transforms of length N = 2^k >= npa + npb - 1
+// and joined by the Chinese remainder theorem; the planner picks w so that every c_m stays
+// below P0 P1 (2w + log2 min(npa, npb) <= 61), which makes the joined value exact.
+//
+// A transform of length N = N1 N2 runs in four steps (each step one launch over every job):
+//   forward columns  N2 transforms of length N1 over the stride-N2 columns x[N2 n1 + n2],
+//                    then the twiddle w_N^(n2 k1); stored row-wise (row k1, N2 columns)
+//   forward rows     N1 transforms of length N2 over the rows
+//   inverse rows     the pointwise product of the two operands' transforms (Montgomery), the
+//                    inverse row transforms, the inverse twiddle and the scale 1/N
+//   inverse columns  the inverse column transforms of both primes, the Chinese remainder
+//                    theorem, the convolution terms written in order
+// Forward transforms are decimation in frequency (natural order in, bit-reversed out) and the
+// inverse ones decimation in time (bit-reversed in, natural out), so no step reorders data:
+// rows are kept at their bit-reversed positions and the pointwise product pairs equal positions.
+// Every block transforms NTT_BLOCK elements in LDS: C = NTT_BLOCK / N1 adjacent columns, or
+// R = NTT_BLOCK / N2 rows.
+//
+// Arithmetic: residues below P < 2^31 in 32-bit words; products by Montgomery reduction with
+// R = 2^32 (a b R^-1 mod P), twiddles kept in Montgomery form so that multiplying a residue by
+// one returns the plain product.  Powers of a root of unity of order 2^26 come from two tables
+// of 8192 entries per prime (w^e = w^(8192 hi) w^(lo)), built on the host once per device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "../../include/ks.h"
+#include "ks_device.h"
+#include "ks_launch.h"
+#include "ks_plan.h"
+
+namespace ks {
+
+constexpr int NTT_TAB = 1 << (NTT_ROOT_LOG / 2);  // 8192 entries per half table
+static_assert(NTT_TAB * NTT_TAB == (1 << NTT_ROOT_LOG), "two half tables cover the root's powers");
+
+// [prime][0: w^(8192 i) R, 1: w^i R][i] mod P
+__device__ uint32_t ntt_tab[2][2][NTT_TAB];
+
+struct NttPrime {
+    uint32_t p;
+    uint32_t pn;  // -p^-1 mod 2^32
+};
+
+__host__ __device__ constexpr uint32_t neg_inv32(uint32_t p) {
+    uint32_t x = p;  // Newton's iteration for p^-1 mod 2^32 (p odd): 5 steps from 3 bits
+    for (int i = 0; i < 5; ++i) x *= 2u - p * x;
+    return 0u - x;
+}
+
+// m^-1 mod p (extended Euclid), for the constant of the Chinese remainder step
+constexpr uint64_t inv_mod(uint64_t a, uint64_t p) {
+    int64_t t = 0, nt = 1, r = (int64_t)p, nr = (int64_t)(a % p);
+    while (nr != 0) {
+        const int64_t qq = r / nr;
+        const int64_t t2 = t - qq * nt, r2 = r - qq * nr;
+        t = nt;
+        nt = t2;
+        r = nr;
+        nr = r2;
+    }
+    return (uint64_t)(t < 0 ? t + (int64_t)p : t);
+}
+// P0^-1 R mod P1 (Montgomery form): multiplying by it divides by P0 mod P1
+constexpr uint32_t NTT_CRT_C =
+    (uint32_t)(inv_mod(NTT_P0, NTT_P1) * (((uint64_t)1 << 32) % NTT_P1) % NTT_P1);
+static_assert(inv_mod(NTT_P0, NTT_P1) * (NTT_P0 % NTT_P1) % NTT_P1 == 1, "P0 inverse mod P1");
+
+__device__ __forceinline__ NttPrime ntt_prime(int q) {
+    return q == 0 ? NttPrime{NTT_P0, neg_inv32(NTT_P0)} : NttPrime{NTT_P1, neg_inv32(NTT_P1)};
+}
+
+// a b R^-1 mod p for a, b < p < 2^31
+__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, NttPrime P) {
+    const uint64_t t = (uint64_t)a * b;
+    const uint32_t m = (uint32_t)t * P.pn;
+    const uint32_t u = (uint32_t)((t + (uint64_t)m * P.p) >> 32);  // t + m p < 2^62 + 2^63
+    return u >= P.p ? u - P.p : u;
+}
+__device__ __forceinline__ uint32_t madd(uint32_t a, uint32_t b, uint32_t p) {
+    const uint32_t s = a + b;
+    return s >= p ? s - p : s;
+}
+__device__ __forceinline__ uint32_t msub(uint32_t a, uint32_t b, uint32_t p) { return a >= b ? a - b : a + p - b; }
+
+// w^e R for e in [0, 2^26), w the table root of prime q
+__device__ __forceinline__ uint32_t root_pow(int q, uint32_t e, NttPrime P) {
+    return mmul(ntt_tab[q][0][e >> (NTT_ROOT_LOG / 2)], ntt_tab[q][1][e & (NTT_TAB - 1)], P);
+}
+// w^-e R
+__device__ __forceinline__ uint32_t root_pow_inv(int q, uint32_t e, NttPrime P) {
+    return root_pow(q, (uint32_t)((1u << NTT_ROOT_LOG) - e) & ((1u << NTT_ROOT_LOG) - 1u), P);
+}
+
+// the stage twiddles of a transform of length 2^lg: tw[j] = w_M^(+-j) R, j < M/2
+template <bool INV>
+__device__ __forceinline__ void load_twiddles(uint32_t *tw, int q, int lg, NttPrime P) {
+    for (int j = threadIdx.x; j < (1 << (lg - 1)); j += NTT_TPB) {
+        const uint32_t e = (uint32_t)j << (NTT_ROOT_LOG - lg);
+        tw[j] = INV ? root_pow_inv(q, e, P) : root_pow(q, e, P);
+    }
+}
+
+// nseq transforms of length 2^lg in LDS, sequence s at buf[s * stride ..]: forward by
+// decimation in frequency (natural in, bit-reversed out), inverse by decimation in time
+// (bit-reversed in, natural out; tw holds the inverse twiddles).  Ends with a barrier.
+template <bool INV>
+__device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, int nseq, int lg, const uint32_t *tw,
+                                              NttPrime P) {
+    const int half = 1 << (lg - 1);
+    const int total = nseq * half;
+    for (int st = 0; st < lg; ++st) {
+        // forward: half-size h = M / 2^(st+1), twiddle index j << st; inverse: h = 2^st,
+        // twiddle index j << (lg - 1 - st)
+        const int hl = INV ? st : lg - 1 - st;
+        const int ts = INV ? lg - 1 - st : st;
+        const int h = 1 << hl;
+        for (int b = threadIdx.x; b < total; b += NTT_TPB) {
+            const int seq = b >> (lg - 1), r = b & (half - 1);
+            const int j = r & (h - 1);
+            uint32_t *x = buf + seq * stride + ((r >> hl) << (hl + 1)) + j;
+            const uint32_t u = x[0];
+            if (!INV) {
+                const uint32_t v = x[h];
+                x[0] = madd(u, v, P.p);
+                x[h] = mmul(msub(u, v, P.p), tw[j << ts], P);
+            } else {
+                const uint32_t v = mmul(x[h], tw[j << ts], P);
+                x[0] = madd(u, v, P.p);
+                x[h] = msub(u, v, P.p);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// piece m of a: bits [w m, w m + w) of its limbs (zero at or above np pieces or n limbs)
+__device__ __forceinline__ uint32_t piece(const NttJob &J, int64_t m) {
+    if (m >= J.np) return 0u;
+    const int64_t bit = (int64_t)J.w * m;
+    const int64_t q = bit >> 5;
+    const int sh = (int)(bit & 31);
+    const uint32_t lo = q < J.na ? ldg(J.a + q) : 0u;
+    const uint32_t hi = q + 1 < J.na ? ldg(J.a + q + 1) : 0u;
+    return (uint32_t)(((((uint64_t)hi << 32) | lo) >> sh) & ((1ull << J.w) - 1ull));
+}
+
+__device__ __forceinline__ uint32_t bitrev(uint32_t r, int bits) { return __builtin_bitreverse32(r) >> (32 - bits); }
+
+// ---- the four steps ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L) {
+    __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
+    __shared__ uint32_t tw[2048];
+    int64_t local;
+    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
+    const int C = NTT_BLOCK >> k1, S = (1 << k1) + 1;  // columns, LDS stride of a column
+    const int64_t groups = (int64_t)1 << (k2 - (13 - k1));
+    const int q = (int)(local / groups);
+    const int64_t c0 = (local - q * groups) * C;
+    const NttPrime P = ntt_prime(q);
+    load_twiddles<false>(tw, q, k1, P);
+    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
+        const int c = e & (C - 1), n1 = e >> (13 - k1);
+        buf[c * S + n1] = piece(J, ((int64_t)n1 << k2) + c0 + c);
+    }
+    __syncthreads();
+    lds_transform<false>(buf, S, C, k1, tw, P);
+    uint32_t *x = J.x + ((int64_t)q << k);
+    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
+        const int c = e & (C - 1), r = e >> (13 - k1);
+        const int64_t n2 = c0 + c;
+        const uint32_t ex = (uint32_t)((n2 * (int64_t)bitrev((uint32_t)r, k1)) << (NTT_ROOT_LOG - k));
+        stg(x + ((int64_t)r << k2) + n2, mmul(buf[c * S + r], root_pow(q, ex, P), P));
+    }
+}
+
+__global__ __launch_bounds__(NTT_TPB) void ntt_fwd_rows_kernel(Launch<NttJob> L) {
+    __shared__ uint32_t buf[NTT_BLOCK];
+    __shared__ uint32_t tw[2048];
+    int64_t local;
+    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
+    const int64_t groups = (int64_t)1 << (k1 - (13 - k2));  // blocks per prime: N1 / R
+    const int q = (int)(local / groups);
+    const int64_t base = (local - q * groups) * NTT_BLOCK;  // R whole rows, contiguous
+    const NttPrime P = ntt_prime(q);
+    load_twiddles<false>(tw, q, k2, P);
+    uint32_t *x = J.x + ((int64_t)q << k) + base;
+    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) buf[e] = ldg(x + e);
+    __syncthreads();
+    lds_transform<false>(buf, 1 << k2, NTT_BLOCK >> k2, k2, tw, P);
+    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) stg(x + e, buf[e]);
+}
+
+__global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L) {
+    __shared__ uint32_t buf[NTT_BLOCK];
+    __shared__ uint32_t tw[2048];
+    int64_t local;
+    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
+    const int64_t groups = (int64_t)1 << (k1 - (13 - k2));
+    const int q = (int)(local / groups);
+    const int64_t base = (local - q * groups) * NTT_BLOCK;
+    const int64_t r0 = base >> k2;  // first row of the block
+    const NttPrime P = ntt_prime(q);
+    load_twiddles<true>(tw, q, k2, P);
+    uint32_t *x = J.x + ((int64_t)q << k) + base;
+    const uint32_t *y = J.y + ((int64_t)q << k) + base;
+    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) buf[e] = mmul(ldg(x + e), ldg(y + e), P);  // A B R^-1
+    __syncthreads();
+    lds_transform<true>(buf, 1 << k2, NTT_BLOCK >> k2, k2, tw, P);
+    // inverse twiddle w_N^-(n2 k1) and the scale R / N (the pointwise product left R^-1):
+    // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N
+    const uint32_t K = J.kscale[q];
+    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
+        const int64_t r = r0 + (e >> k2), n2 = e & ((1 << k2) - 1);
+        const uint32_t ex = (uint32_t)((n2 * (int64_t)bitrev((uint32_t)r, k1)) << (NTT_ROOT_LOG - k));
+        const uint32_t T = mmul(root_pow_inv(q, ex, P), K, P);
+        stg(x + e, mmul(buf[e], T, P));
+    }
+}
+
+__global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L) {
+    constexpr int EPT = NTT_BLOCK / NTT_TPB;
+    __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
+    __shared__ uint32_t tw[2048];
+    int64_t local;
+    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
+    const int C = NTT_BLOCK >> k1, S = (1 << k1) + 1;
+    const int64_t c0 = local * C;
+    uint32_t v0[EPT];
+    for (int q = 0; q < 2; ++q) {
+        const NttPrime P = ntt_prime(q);
+        load_twiddles<true>(tw, q, k1, P);
+        const uint32_t *x = J.x + ((int64_t)q << k);
+        for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
+            const int c = e & (C - 1), r = e >> (13 - k1);
+            buf[c * S + r] = ldg(x + ((int64_t)r << k2) + c0 + c);
+        }
+        __syncthreads();
+        lds_transform<true>(buf, S, C, k1, tw, P);
+        if (q == 0) {
+#pragma unroll
+            for (int it = 0; it < EPT; ++it) {
+                const int e = threadIdx.x + it * NTT_TPB;
+                v0[it] = buf[(e & (C - 1)) * S + (e >> (13 - k1))];
+            }
+            __syncthreads();  // before the second prime's columns overwrite buf
+        } else {
+            // Chinese remainder theorem: z = x0 + P0 ((x1 - x0) P0^-1 mod P1), below P0 P1
+            const NttPrime P1 = ntt_prime(1);
+#pragma unroll
+            for (int it = 0; it < EPT; ++it) {
+                const int e = threadIdx.x + it * NTT_TPB;
+                const int c = e & (C - 1), n1 = e >> (13 - k1);
+                const uint32_t x1 = buf[c * S + n1], x0 = v0[it];
+                const uint32_t x0m = x0 >= NTT_P1 ? x0 - NTT_P1 : x0;  // x0 < P0 < 2 P1
+                const uint32_t d = msub(x1, x0m, NTT_P1);
+                const uint32_t t = mmul(d, NTT_CRT_C, P1);  // (x1 - x0) P0^-1 mod P1
+                const int64_t m = ((int64_t)n1 << k2) + c0 + c;
+                if (m < J.nz) stg(J.z + m, (uint64_t)x0 + (uint64_t)NTT_P0 * t);
+            }
+        }
+    }
+}
+
+// ---- host side -----------------------------------------------------------------------------------
+
+static uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)((unsigned __int128)a * b % p); }
+static uint64_t powmod_h(uint64_t a, uint64_t e, uint64_t p) {
+    uint64_t r = 1;
+    for (a %= p; e; e >>= 1, a = mulmod_h(a, a, p))
+        if (e & 1) r = mulmod_h(r, a, p);
+    return r;
+}
+
+uint32_t ntt_scale(int q, int k) {
+    const uint64_t p = q == 0 ? NTT_P0 : NTT_P1;
+    const uint64_t r2 = powmod_h(2, 64, p);                // R^2
+    const uint64_t ninv = powmod_h((p + 1) / 2, (uint64_t)k, p);  // 2^-k
+    return (uint32_t)mulmod_h(r2, ninv, p);
+}
+
+bool ntt_shape(int64_t na, int64_t nb, int min_log, int &k1, int &k2, int &w, int64_t &npa, int64_t &npb) {
+    for (int k = std::max(min_log, NTT_MIN_LOG); k <= NTT_MAX_LOG; ++k) {
+        const int64_t N = (int64_t)1 << k;
+        for (int ww = 1; ww <= 30; ++ww) {
+            const int64_t pa = cdiv(32 * na, ww), pb = cdiv(32 * nb, ww);
+            if (pa + pb - 1 > N) continue;
+            // exact: every term below min(pa, pb) 2^(2w) <= 2^61 < P0 P1
+            if (2 * ww + ceil_log2(std::min(pa, pb)) > 61) break;
+            k1 = k / 2;
+            k2 = k - k1;
+            w = ww;
+            npa = pa;
+            npb = pb;
+            return true;
+        }
+    }
+    return false;
+}
+
+int ntt_prepare() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KS_EHIP;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done[dev]) return KS_OK;
+    static uint32_t host[2][2][NTT_TAB];
+    const uint64_t prime[2] = {NTT_P0, NTT_P1}, gen[2] = {31, 13};  // primitive roots
+    for (int q = 0; q < 2; ++q) {
+        const uint64_t p = prime[q];
+        const uint64_t w = powmod_h(gen[q], (p - 1) >> NTT_ROOT_LOG, p);  // order 2^26
+        const uint64_t R = ((uint64_t)1 << 32) % p;
+        const uint64_t wh = powmod_h(w, NTT_TAB, p);
+        uint64_t a = 1, b = 1;
+        for (int i = 0; i < NTT_TAB; ++i) {
+            host[q][0][i] = (uint32_t)mulmod_h(a, R, p);
+            host[q][1][i] = (uint32_t)mulmod_h(b, R, p);
+            a = mulmod_h(a, wh, p);
+            b = mulmod_h(b, w, p);
+        }
+    }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(ntt_tab), host, sizeof(host), 0, hipMemcpyHostToDevice) != hipSuccess)
+        return KS_EHIP;
+    done[dev] = true;
+    return KS_OK;
+}
+
+hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    const dim3 g((unsigned)L.total_blocks), b(NTT_TPB);
+    switch (stage) {
+        case 0: ks_launch(ntt_fwd_cols_kernel, g, b, 0, s, L); break;
+        case 1: ks_launch(ntt_fwd_rows_kernel, g, b, 0, s, L); break;
+        case 2: ks_launch(ntt_inv_rows_kernel, g, b, 0, s, L); break;
+        case 3: ks_launch(ntt_inv_cols_kernel, g, b, 0, s, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ks

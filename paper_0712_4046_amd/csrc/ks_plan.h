@@ -56,6 +56,10 @@ struct MulGeom {
     int64_t groups = 0, splits = 1, part = 0, rgroups = 1;
     int rt = 8;  // row tiles per block
     int64_t ad_off = 0, bd_off = 0;
+    // transform engine: N = 2^(k1 + k2), w-bit pieces (npa, npb of them), nz convolution terms;
+    // word offsets of the two transforms and the terms in the transform region
+    int ntt_k1 = 0, ntt_k2 = 0, ntt_w = 0;
+    int64_t ntt_npa = 0, ntt_npb = 0, ntt_nz = 0, ntt_xa = 0, ntt_xb = 0, ntt_z = 0;
 };
 struct NormGeom {
     int nterms, prod[2], sign[2], shift;
@@ -87,10 +91,12 @@ struct Geom {
     std::vector<ExtractGeom> extracts;
     std::vector<ChainGeom> chains;
     int64_t op_limbs = 0, col_words = 0, norm_limbs = 0, anchor_limbs = 0, digit_bytes = 0, hbuf_words = 0;
+    int64_t ntt_words = 0;  // transform region (uint32 words)
+    double ntt_butterflies = 0;  // butterflies of the transforms (both primes, all passes)
     int64_t pack_blocks = 0, mul_blocks = 0, norm_blocks = 0, extract_blocks = 0, anchor_blocks = 0,
             chain_blocks = 0, finish_blocks = 0;
-    int64_t ws_ops = 0, ws_cols = 0, ws_digits = 0, ws_norms = 0, ws_anchors = 0, ws_hbuf = 0, ws_status = 0,
-            ws_bytes = 0;
+    int64_t ws_ops = 0, ws_cols = 0, ws_digits = 0, ws_norms = 0, ws_anchors = 0, ws_hbuf = 0, ws_ntt = 0,
+            ws_status = 0, ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
     double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0;
     double valu_mults = 0;  // schoolbook limb products of the vector-ALU products
@@ -123,6 +129,7 @@ struct JobLists {
     std::vector<MulJob> mul_wave;  // small products: one wave per tile (blocks count tiles)
     std::vector<DigitJob> digit;
     std::vector<MfmaJob> mfma;
+    std::vector<NttJob> ntt_f1, ntt_f2, ntt_i2, ntt_i1;  // transform stages (forward per operand)
     std::vector<NormJob> norm;
     std::vector<NormJob> norm_small;  // jobs of at most small_bl(ipt) limbs
     std::vector<ExtractJob> extract;
@@ -137,7 +144,7 @@ struct DevList {
     uint32_t *block_job = nullptr;
 };
 struct DevTables {
-    DevList pack, pack_small, mul, mul_wave, digit, mfma, norm, norm_small, extract;
+    DevList pack, pack_small, mul, mul_wave, digit, mfma, norm, norm_small, extract, ntt_f1, ntt_f2, ntt_i2, ntt_i1;
     std::map<int, DevList> anchor, chain, finish;
 };
 
@@ -165,6 +172,16 @@ int read_status(uint32_t *devstat, hipStream_t s);
 int noalloc_status(hipStream_t s);
 // a planner tunable: the value set through ks_tune_set, else the environment, else dflt
 int env_int(const char *name, int dflt);
+// transform length and piece width of an integer product of na x nb limbs through the
+// transforms: the shortest N = 2^(k1+k2) (k1 = floor(k/2)) with a piece width w whose
+// convolution fits in N terms and stays below the primes' product; false when none does
+bool ntt_shape(int64_t na, int64_t nb, int min_log, int &k1, int &k2, int &w, int64_t &npa, int64_t &npb);
+// R^2 / 2^k mod P_q (R = 2^32): the inverse transform's scale in the Montgomery domain
+uint32_t ntt_scale(int q, int k);
+// the root tables on the current device (uploaded once per device; synchronous)
+int ntt_prepare();
+// planner default of KS_NTT_MIN_LIMBS
+constexpr int NTT_MIN_LIMBS = 12000;
 // whether ks_batch_plan_create would split this batch by Karatsuba (see KS_KARATSUBA_MIN_LIMBS)
 bool karatsuba_splits(const ks_desc *descs, int64_t count, int32_t variant);
 // batches of modular products of equal lengths whose integer operands have at least this

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libksmul.so")
 
 KS_VARIANT = {"auto": 0, "ks1": 1, "neg2": 2, "recip2": 3, "ks4": 4}
 KS_SIGNED = 0x100
-KS_ENGINE_VALU, KS_ENGINE_MFMA = 0x1000, 0x2000
-KS_ENGINE = {None: 0, "valu": KS_ENGINE_VALU, "mfma": KS_ENGINE_MFMA}
+KS_ENGINE_VALU, KS_ENGINE_MFMA, KS_ENGINE_NTT = 0x1000, 0x2000, 0x4000
+KS_ENGINE = {None: 0, "valu": KS_ENGINE_VALU, "mfma": KS_ENGINE_MFMA, "ntt": KS_ENGINE_NTT}
 KS_MOD = 0x10000
 KS_OK, KS_EINVAL, KS_ENOMEM, KS_EHIP, KS_ERANGE, KS_EUNSUPPORTED, KS_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 KS_ESCRATCH = -7
@@ -41,7 +41,8 @@ class PlanInfo(ctypes.Structure):
                 ("hbm_bytes", ctypes.c_double), ("pack_bytes", ctypes.c_double),
                 ("normalize_bytes", ctypes.c_double), ("finish_bytes", ctypes.c_double),
                 ("anchor_limb_mults", ctypes.c_double), ("mfma_ops", ctypes.c_double),
-                ("valu_limb_mults", ctypes.c_double), ("scratch_bytes", ctypes.c_int64)]
+                ("valu_limb_mults", ctypes.c_double), ("scratch_bytes", ctypes.c_int64),
+                ("ntt_butterflies", ctypes.c_double)]
 
 
 class Desc(ctypes.Structure):
@@ -246,7 +247,7 @@ def profile_reset():
 
 
 TUNABLES = ("KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",
-            "KS_MUL_WAVE_MAX", "KS_SCAN_SMALL", "KS_MFMA_RT", "KS_KARATSUBA_MIN_LIMBS")
+            "KS_MUL_WAVE_MAX", "KS_SCAN_SMALL", "KS_MFMA_RT", "KS_KARATSUBA_MIN_LIMBS", "KS_NTT_MIN_LIMBS")
 
 
 def tune_set(name: str, value: int):

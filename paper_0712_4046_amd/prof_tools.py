@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Helpers for rocprofv3 measurements of the library (used to make the files in profiles/).
 
-    python -m paper_0712_4046_amd.prof_tools workload [product_4096_s64|batch_mixed_10000|batch_mod_64x65536]  # counter runs
+    python -m paper_0712_4046_amd.prof_tools workload [product_4096_s64|batch_mixed_10000|batch_mod_64x65536] [valu|mfma|ntt]
     python -m paper_0712_4046_amd.prof_tools summarize DB "cmd"  # kernel-trace summary table
     python -m paper_0712_4046_amd.prof_tools counters FETCH_DB WRITE_DB   # HBM bytes per kernel
 
@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_MIB = 256
 
 
-def workload(name: str = "product_4096_s64", reps: int = 5):
+def workload(name: str = "product_4096_s64", reps: int = 5, engine=None):
     """A plain device copy of COPY_MIB MiB (the FETCH_SIZE / WRITE_SIZE calibration), then
     product_4096_s64: `reps` four-point products of the L = 4096 signed 64-bit workload (seed 2);
     batch_mixed_10000: one four-point run of the 10,000-product batch (seed 3);
@@ -35,7 +35,7 @@ def workload(name: str = "product_4096_s64", reps: int = 5):
         P = wl.product_4096_s64()
         tf, tg = ks.to_device(P.f), ks.to_device(P.g)
         for _ in range(reps):
-            ks.mul(tf, tg, P.bits, "ks4", P.signed)
+            ks.mul(tf, tg, P.bits, "ks4", P.signed, engine=engine)
         ks.check()
     elif name == "poly2":
         import numpy as np
@@ -54,7 +54,7 @@ def workload(name: str = "product_4096_s64", reps: int = 5):
             p, pairs = wl.batch_mod_64x65536()
             for f, g in pairs:
                 B.add_mod(f, g, p)
-        plan = ks.BatchPlan(B.desc_array(), "ks4")
+        plan = ks.BatchPlan(B.desc_array(), "ks4", engine)
         ain = ks.to_device(B.arena_in())
         aout = torch.zeros(B.out_words(), dtype=torch.int32, device="cuda")
         ws = ks.alloc_workspace(plan.workspace_bytes)
@@ -126,11 +126,29 @@ def counters(fetch_db: str, write_db: str):
         print(f"{short:60s} {len(f[k]):4d} {fa:10.1f} {wa:10.1f} {tot:12.0f}")
 
 
+def pmc_table(db: str, cmd: str = ""):
+    """Every counter of a --pmc run, averaged per dispatch, per kernel."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, counter_name, avg(value), count(*) from counters_collection "
+                       "group by kernel_name, counter_name order by kernel_name, counter_name").fetchall()
+    print("# rocprofv3 --pmc counters, average per dispatch")
+    print(f"# command: {cmd}")
+    last = None
+    for k, c, v, n in rows:
+        if k != last:
+            print(k if len(k) <= 100 else k[:97] + "...")
+            last = k
+        print(f"    {c:32s} {v:20.1f}   (dispatches: {n})")
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else "workload"
     if cmd == "workload":
-        workload(sys.argv[2] if len(sys.argv) > 2 else "product_4096_s64")
+        workload(sys.argv[2] if len(sys.argv) > 2 else "product_4096_s64",
+                 engine=sys.argv[3] if len(sys.argv) > 3 else None)
     elif cmd == "summarize":
         summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "", int(sys.argv[4]) if len(sys.argv) > 4 else 0)
     elif cmd == "counters":
         counters(sys.argv[2], sys.argv[3])
+    elif cmd == "pmc":
+        pmc_table(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")

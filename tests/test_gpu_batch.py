@@ -39,7 +39,7 @@ def run_batch(torch, B, variant="auto", engine=None):
     return out
 
 
-@pytest.mark.parametrize("engine", [None, "valu", "mfma"])
+@pytest.mark.parametrize("engine", [None, "valu", "mfma", "ntt"])
 @pytest.mark.parametrize("variant", ["ks1", "neg2", "recip2", "ks4", "auto"])
 def test_mixed_batch(torch_dev, oracle, variant, engine):
     gen = wl.rng(31)
@@ -81,10 +81,10 @@ def test_mixed_batch_unequal_lengths(torch_dev, oracle):
         assert np.array_equal(B.result(out, i), exp), i
 
 
-def kara_levels(torch, B, variant):
-    """Run the batch at the default plan with per-launch timing on; Karatsuba levels = the
-    split and combination launches of one run / 2."""
-    plan = ks.BatchPlan(B.desc_array(), variant)
+def kara_levels(torch, B, variant, engine=None):
+    """Run the batch with per-launch timing on; Karatsuba levels = the split and combination
+    launches of one run / 2."""
+    plan = ks.BatchPlan(B.desc_array(), variant, engine)
     ain = ks.to_device(B.arena_in())
     aout = torch.zeros(B.out_words(), dtype=torch.int32, device="cuda")
     ws = ks.alloc_workspace(plan.workspace_bytes)
@@ -103,16 +103,15 @@ def kara_levels(torch, B, variant):
 
 
 def test_modular_batch_full(torch_dev, oracle):
-    # the 64-product modular workload exactly as the bench runs it (default plan: the recursive
-    # Karatsuba split of each variant): three products compared in full (all 131,071
+    # the 64-product modular workload exactly as the bench runs it (default plan: the transform
+    # engine's products, no Karatsuba split): three products compared in full (all 131,071
     # coefficients) for KS4 and KS1, every product sampled, and KS4 equal to KS1 everywhere
     p, pairs = wl.batch_mod_64x65536()
     B = ks.Batch()
     for f, g in pairs:
         B.add_mod(f, g, p)
-    out4, lv4 = kara_levels(torch_dev, B, "ks4")
-    out1, lv1 = kara_levels(torch_dev, B, "ks1")
-    assert lv4 >= 1 and lv1 >= 1, (lv4, lv1)  # both runs took the split
+    out4, _ = kara_levels(torch_dev, B, "ks4")
+    out1, _ = kara_levels(torch_dev, B, "ks1")
     assert np.array_equal(out4, out1)
     for i in (0, 31, 63):
         f, g = pairs[i]
@@ -126,12 +125,16 @@ def test_modular_batch_full(torch_dev, oracle):
         assert np.array_equal(B.result(out1, i)[kidx], oracle.coeffs_mod(f, g, p, kidx)), i
 
 
-def test_modular_batch_sampled(torch_dev, oracle):
+@pytest.mark.parametrize("variant", ["ks4", "ks1"])
+def test_modular_batch_matrix_cores_sampled(torch_dev, oracle, variant):
+    # the same workload on the matrix cores, where the default plan splits every product by
+    # Karatsuba on the polynomials (recursively): every product sampled
     p, pairs = wl.batch_mod_64x65536()
     B = ks.Batch()
     for f, g in pairs:
         B.add_mod(f, g, p)
-    out = run_batch(torch_dev, B, "ks4", "mfma")
+    out, levels = kara_levels(torch_dev, B, variant, "mfma")
+    assert levels >= 1, levels
     D = 2 * 65536 - 1
     gen = wl.rng(44)
     for i, (f, g) in enumerate(pairs):
@@ -212,6 +215,7 @@ def karatsuba_from(request):
     afterwards; the split recurses while the halves' operands keep that many limbs."""
     def set_(n):
         ks.tune_set("KS_KARATSUBA_MIN_LIMBS", n)
+        ks.tune_set("KS_NTT_MIN_LIMBS", 0)  # products on the transform engine are never split
     yield set_
     ks.tune_reset()
 

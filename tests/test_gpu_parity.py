@@ -24,7 +24,7 @@ def torch_dev():
     return torch
 
 
-ENGINES = ["valu", "mfma"]
+ENGINES = ["valu", "mfma", "ntt"]
 
 
 def gpu_mul(f, g, bits, variant, signed, engine=None):
@@ -214,6 +214,22 @@ def test_long_wide_product_sampled(torch_dev, oracle, bits):
             first = got
         else:
             assert np.array_equal(got, first), (bits, v)
+
+
+@pytest.mark.parametrize("kind,signed", [("max", False), ("min", True), ("max", True)])
+def test_transform_engine_extreme_terms(torch_dev, oracle, kind, signed):
+    # the largest convolution terms the transform engine meets: all-max (or all-min) 256-bit
+    # coefficients at L = 65536 through the standard substitution (one product of ~1.08M-limb
+    # operands, a transform of 2^22 terms), sampled against the oracle
+    L, bits = 65536, 256
+    f = wl.special_coeffs(kind, L, bits, signed)
+    D = 2 * L - 1
+    idx = np.unique(np.concatenate([np.arange(0, 8), np.arange(D - 8, D), wl.rng(5).integers(0, D, 60)]))
+    exp = oracle.coeffs_classical(f, f, signed, idx, oracle.out_limbs(L, L, bits))
+    tf = ks.to_device(f)
+    h = ks.mul(tf, tf, bits, "ks1", signed, engine="ntt")
+    assert ks.status() == ks.KS_OK
+    assert np.array_equal(ks.to_host(h)[idx], exp)
 
 
 def test_invalid_arguments(torch_dev):
