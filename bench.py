@@ -40,12 +40,21 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
 # int8 matrix cores (dense, no sparsity): 5.0e15 operations/s, one multiply-add = 2 operations
 MFMA_I8_PEAK_TOPS = 5000.0
 HBM_PEAK_GBS = 8000.0
+# transform engine: a radix-2 butterfly modulo a 31-bit prime is at least 12 vector instructions
+# (Montgomery product: 2 v_mad_u64_u32, v_mul_lo_u32, compare, select, subtract; modular sum and
+# difference: 3 each), each issuing at most once per lane per cycle:
+# 256 CUs x 64 lanes x 2.4 GHz / 12 = 3.28e12 butterflies/s
+NTT_BUTTERFLY_PEAK_T = 256 * 64 * 2.4e9 / 12 / 1e12
+# butterflies of each transform step as a share of the plan's total (6 (N/2) k per product):
+# forward steps transform both operands, inverse steps the product; columns have 2^k1 terms,
+# rows 2^k2
+NTT_STEPS = {"ntt_fwd_cols": (2, 0), "ntt_fwd_rows": (2, 1), "ntt_inv_rows": (1, 1), "ntt_inv_cols": (1, 0)}
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated: FETCH x2, WRITE
 # x1) on the headline workload (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).
 MEASURED_TRAFFIC_C4 = {}
 KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows",
-           "ntt_inv_cols", "normalize", "anchor", "recon", "finish", "extract", "p2_eval", "p2_recon")
+           "ntt_inv_cols", "ntt_join", "normalize", "anchor", "recon", "finish", "extract", "p2_eval", "p2_recon")
 METRIC = "polynomial products/s + limb-mults/s at 1 GPU; KS4 vs KS1 speedup, bit-exact"
 
 
@@ -118,6 +127,15 @@ def roofline(kern, info, traffic_table=None):
         return {"bound": "mfma", "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS, "unit": "TOP/s",
                 "frac": achieved / MFMA_I8_PEAK_TOPS, **base,
                 "op": "int8 multiply-add of balanced 8-bit digits (2 operations)", "ops_per_run": ops}
+    if dom in NTT_STEPS:
+        share, rows = NTT_STEPS[dom]
+        k1, k2 = info["ntt_k1"], info["ntt_k2"]
+        ops = info["ntt_butterflies"] * share / 3.0 * (k2 if rows else k1) / (k1 + k2)
+        achieved = ops / sec / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": NTT_BUTTERFLY_PEAK_T, "unit": "T butterflies/s",
+                "frac": achieved / NTT_BUTTERFLY_PEAK_T, **base,
+                "op": "radix-2 butterfly modulo a 31-bit prime (12 vector instructions at least)",
+                "ops_per_run": ops}
     if dom in ("mul_valu", "anchor"):
         ops = info["valu_limb_mults"] if dom == "mul_valu" else info["anchor_limb_mults"]
         achieved = ops / sec / 1e12

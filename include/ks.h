@@ -264,6 +264,8 @@ typedef struct ks_plan_info {
     double ntt_butterflies;   /* radix-2 butterflies of the products on the transform engine: three
                                  transforms of length N (two forward, one inverse) modulo each of
                                  two primes, (N / 2) log2 N butterflies each */
+    int32_t ntt_k1, ntt_k2;   /* transform engine: N = 2^(k1 + k2), columns of 2^k1 and rows of 2^k2
+                                 (of the first such product; 0 when none) */
 } ks_plan_info;
 
 int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, ks_plan_info *out);
@@ -276,7 +278,7 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
  * "pack" (with the anchors it carries), "mul_valu", "mul_mfma", "normalize", "anchor",
  * "recon", "finish", "extract", "digitize", "p2_eval", "p2_recon" (bivariate evaluation and
  * read-off or gluing), "kara" (the Karatsuba split and combination of a batch),
- * "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols" (the four steps of the
+ * "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "ntt_join" (the steps of the
  * transform engine).  Returns KS_EINVAL for an unknown name.
  */
 int ks_profile_enable(int32_t on);
@@ -286,7 +288,9 @@ int ks_profile_reset(void);
 /*
  * Planner tunables (launch shapes), process-wide, read whenever a product or batch is planned;
  * a value set here overrides the environment variable of the same name, which overrides the
- * built-in default.  Names and defaults:
+ * autotuner's JSON cache (the file KS_TUNING_FILE names, else $XDG_CACHE_HOME/ksmul/tuning.json
+ * or $HOME/.cache/ksmul/tuning.json; read once per process, every "NAME": integer pair of a
+ * known tunable taken), which overrides the built-in default.  Names and defaults:
  *   "KS_MFMA_MIN_LIMBS"  2500  both operands at least this many limbs -> matrix-core engine
  *                              (unset, the products of a batch use 1000)
  *   "KS_MFMA_BLOCKS"     0     matrix-core launch target of one product, in blocks; 0: the
@@ -305,8 +309,8 @@ int ks_profile_reset(void);
  *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
  *                              128; 256 in a batch, and unset, a batch uses 256) run one wave
  *                              per job (0: every job in 256-thread blocks)
- *   "KS_NTT_MIN_LIMBS"   12000 both operands at least this many limbs -> transform engine
- *                              (0: never unless forced)
+ *   "KS_NTT_MIN_LIMBS"   40000 both operands at least this many limbs -> transform engine
+ *                              (unset, the products of a batch use 12000; 0: never unless forced)
  *   "KS_KARATSUBA_MIN_LIMBS" 16384  t: a batch plan whose products are all modular with equal
  *                              lengths, whose integer operands total at least 8 t limbs and
  *                              each have at least t (2 t when the batch totals 128 t), splits

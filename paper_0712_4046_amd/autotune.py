@@ -9,8 +9,9 @@ coordinate descent, repeated while it still improves.  Each candidate is timed n
 current best, re-timed right before it, and kept only if it beats that pair partner: a GPU
 whose clocks drift over a long sweep (power or heat) then cannot pass drift off as a gain.
 It keeps the fastest value of each tunable, and
-writes them as JSON together with the default and tuned times; `ks.apply_tuning(table)` sets
-them for later plans.  The shapes change only how work
+writes them as JSON together with the default and tuned times to the library's cache file
+(read by every later process at plan time; --out names another file, which KS_TUNING_FILE can
+point the library at), and `ks.apply_tuning(table)` sets them in the running process.  The shapes change only how work
 is cut into launches and blocks, never the result: tests/test_gpu_autotune.py checks a tuned
 run bit for bit against the default one.
 
@@ -27,13 +28,36 @@ import sys
 from . import ks
 
 CANDIDATES = {
+    "KS_NTT_MIN_LIMBS": [0, 4000, 8000, 12000, 20000, 40000, 80000],
     "KS_CHAIN_K": [0, 4, 8, 16, 32, 64, 128, 256, 512, 1024],
     "KS_MFMA_MIN_LIMBS": [2000, 4000, 6000, 10000, 20000, 1 << 30],
+    "KS_MFMA_RT": [0, 4, 8],
+    "KS_KARATSUBA_MIN_LIMBS": [0, 8192, 16384, 32768],
     "KS_MFMA_BLOCKS": [256, 512, 1024, 2048, 4096],
     "KS_MFMA_MIN_PART": [32, 64, 128, 256, 512],
     "KS_MUL_WAVE_MAX": [0, 256, 512, 1024, 2048, 4096],
     "KS_SCAN_SMALL": [0, 64, 128],
 }
+
+
+def cache_path() -> str:
+    """The JSON cache the library reads at plan time (include/ks.h, ks_tune_set): KS_TUNING_FILE,
+    else $XDG_CACHE_HOME/ksmul/tuning.json or ~/.cache/ksmul/tuning.json."""
+    import os
+    if os.environ.get("KS_TUNING_FILE"):
+        return os.environ["KS_TUNING_FILE"]
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "ksmul", "tuning.json")
+
+
+def save(res: dict, path: str | None = None) -> str:
+    """Write a tuning result (its "tunables" table is what the library reads) to the cache."""
+    import os
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    with open(path, "w") as fh:
+        fh.write(json.dumps(res) + "\n")
+    return path
 
 
 def time_ms(run, warmup: int = 2, reps: int = 5) -> float:
@@ -126,17 +150,14 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="batch_mixed_10000", choices=["product_4096_s64", "batch_mixed_10000", "batch_mod_64x65536", "small"])
     ap.add_argument("--variant", default="ks4")
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--out", default=None, help="where to write the result (default: the library's cache)")
     ap.add_argument("--passes", type=int, default=2)
     a = ap.parse_args(argv)
     make = workload(a.workload, a.variant)
     res = tune(make, max_passes=a.passes, log=lambda s: print(s, file=sys.stderr, flush=True))
     res.update(workload=a.workload, variant=a.variant)
-    txt = json.dumps(res)
-    if a.out:
-        with open(a.out, "w") as fh:
-            fh.write(txt + "\n")
-    print(txt)
+    res["cache"] = save(res, a.out)
+    print(json.dumps(res))
 
 
 if __name__ == "__main__":

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -50,6 +51,41 @@ static bool known_tunable(const char *name) {
     return false;
 }
 
+// Tunables from the autotuner's JSON cache, read once per process: the file KS_TUNING_FILE
+// names, else $XDG_CACHE_HOME/ksmul/tuning.json or $HOME/.cache/ksmul/tuning.json when present.
+// Every `"NAME": integer` pair of a known tunable in it is taken (the autotuner writes them under
+// "tunables"); anything else in the file is ignored.
+static const std::map<std::string, int64_t> &file_tunables() {
+    static std::map<std::string, int64_t> table;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        std::string path;
+        if (const char *f = getenv("KS_TUNING_FILE")) path = f;
+        else if (const char *x = getenv("XDG_CACHE_HOME")) path = std::string(x) + "/ksmul/tuning.json";
+        else if (const char *h = getenv("HOME")) path = std::string(h) + "/.cache/ksmul/tuning.json";
+        if (path.empty()) return;
+        FILE *fh = fopen(path.c_str(), "rb");
+        if (!fh) return;
+        std::string txt;
+        char buf[4096];
+        size_t n;
+        while ((n = fread(buf, 1, sizeof(buf), fh)) > 0 && txt.size() < (1u << 20)) txt.append(buf, n);
+        fclose(fh);
+        for (const char *k : k_tunables) {
+            const std::string key = std::string("\"") + k + "\"";
+            const size_t at = txt.find(key);
+            if (at == std::string::npos) continue;
+            size_t i = at + key.size();
+            while (i < txt.size() && (txt[i] == ' ' || txt[i] == '\t' || txt[i] == '\n' || txt[i] == '\r')) ++i;
+            if (i >= txt.size() || txt[i] != ':') continue;
+            char *end = nullptr;
+            const long long v = strtoll(txt.c_str() + i + 1, &end, 10);
+            if (end != txt.c_str() + i + 1 && v >= 0) table[k] = v;
+        }
+    });
+    return table;
+}
+
 int env_int(const char *name, int dflt) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -57,7 +93,10 @@ int env_int(const char *name, int dflt) {
         if (it != g_tune.end()) return (int)std::min<int64_t>(it->second, 0x7fffffff);
     }
     const char *v = getenv(name);
-    return v && *v ? atoi(v) : dflt;
+    if (v && *v) return atoi(v);
+    const auto &ft = file_tunables();
+    auto it = ft.find(name);
+    return it != ft.end() ? (int)std::min<int64_t>(it->second, 0x7fffffff) : dflt;
 }
 
 // ---- planning -----------------------------------------------------------------------------------
@@ -216,7 +255,7 @@ int plan_product(const Spec &sp, Geom &G) {
         m.nB32 = cdiv(m.nbd + 31, 32);
         int eng = sp.engine;
         // long operands go through the transforms (quasi-linear), when a transform length fits
-        const int64_t ntt_min = env_int("KS_NTT_MIN_LIMBS", NTT_MIN_LIMBS);
+        const int64_t ntt_min = env_int("KS_NTT_MIN_LIMBS", sp.batch ? NTT_MIN_LIMBS_BATCH : NTT_MIN_LIMBS);
         if (eng == 0 && ntt_min > 0 && std::min(nf, ng) >= ntt_min &&
             ntt_shape(nf, ng, 0, m.ntt_k1, m.ntt_k2, m.ntt_w, m.ntt_npa, m.ntt_npb))
             eng = KS_ENGINE_NTT;
@@ -236,9 +275,9 @@ int plan_product(const Spec &sp, Geom &G) {
             m.ntt_nz = m.ntt_npa + m.ntt_npb - 1;
             m.ntt_xa = G.ntt_words;
             m.ntt_xb = m.ntt_xa + 2 * Nt;
-            m.ntt_z = m.ntt_xb + 2 * Nt;
-            G.ntt_words = m.ntt_z + align_up(2 * m.ntt_nz, 64);
-            m.ncols = m.ntt_nz;  // the recombination reads the terms
+            m.ntt_cols = m.ntt_xb + 2 * Nt;
+            m.ncols = m.ntt_w * (m.ntt_nz - 1) / 32 + 1;  // the last term's column
+            G.ntt_words = m.ntt_cols + align_up(3 * m.ncols, 64);
             m.cols_off = -1;
             G.muls.push_back(m);
             G.school_mults += (double)nf * (double)ng;
@@ -409,14 +448,8 @@ int plan_product(const Spec &sp, Geom &G) {
     for (auto &r : G.norms) norm_out += 4.0 * r.n_out;
     G.pack_bytes = in_bytes + 4.0 * G.op_limbs;
     const int eng0 = G.muls.empty() ? KS_ENGINE_VALU : G.muls[0].engine;
-    if (eng0 == KS_ENGINE_NTT) {
-        double terms = 0;
-        for (auto &m : G.muls) terms += 8.0 * (double)m.ntt_nz;
-        G.normalize_bytes = terms + norm_out;
-    } else {
-        const double col_bytes = eng0 == KS_ENGINE_MFMA ? 16.0 : 12.0;
-        G.normalize_bytes = col_bytes * npts * prod_limbs + norm_out;
-    }
+    const double col_bytes = eng0 == KS_ENGINE_MFMA ? 16.0 : 12.0;
+    G.normalize_bytes = col_bytes * npts * prod_limbs + norm_out;
     G.finish_bytes = norm_out + out_bytes;
     return KS_OK;
 }
@@ -531,14 +564,22 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
             NttJob inv = j;
             inv.x = nttw(m.ntt_xa);
             inv.y = nttw(m.ntt_xb);
-            inv.z = reinterpret_cast<uint64_t *>(nttw(m.ntt_z));
-            inv.nz = m.ntt_nz;
             inv.nblocks = 2 * per_prime;
             inv.block0 = next_block(JL.ntt_i2);
             JL.ntt_i2.push_back(inv);
-            inv.nblocks = per_prime;  // both primes in one block (the Chinese remainder step)
             inv.block0 = next_block(JL.ntt_i1);
             JL.ntt_i1.push_back(inv);
+            NttJoinJob jj;
+            memset(&jj, 0, sizeof(jj));
+            jj.x = nttw(m.ntt_xa);
+            jj.n = (int64_t)1 << k;
+            jj.nz = m.ntt_nz;
+            jj.w = m.ntt_w;
+            jj.cols = nttw(m.ntt_cols);
+            jj.ncols = m.ncols;
+            jj.nblocks = cdiv(m.ncols, NTT_TPB);
+            jj.block0 = next_block(JL.ntt_join);
+            JL.ntt_join.push_back(jj);
             continue;
         }
         if (m.engine == KS_ENGINE_MFMA) {
@@ -617,15 +658,14 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         for (int t = 0; t < r.nterms; ++t) {
             const MulGeom &m = G.muls[r.prod[t]];
             NormTerm &T = j.term[t];
-            T.cols = m.engine == KS_ENGINE_NTT ? nttw(m.ntt_z) : cols(m.cols_off);
+            T.cols = m.engine == KS_ENGINE_NTT ? nttw(m.ntt_cols) : cols(m.cols_off);
             T.ncols = m.ncols;
             T.a = ops(G.packs[m.fa].op_off);
             T.b = ops(G.packs[m.fb].op_off);
             T.na = m.na;
             T.nb = m.nb;
             T.sign = r.sign[t];
-            T.fmt = m.engine == KS_ENGINE_MFMA ? NORM_FMT_XY : m.engine == KS_ENGINE_NTT ? NORM_FMT_WPIECE : NORM_FMT_PIECES;
-            T.pw = m.ntt_w;
+            T.fmt = m.engine == KS_ENGINE_MFMA ? NORM_FMT_XY : NORM_FMT_PIECES;
         }
         j.shift = r.shift;
         j.off_bit0 = r.off_bit0;
@@ -768,6 +808,9 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
             err = timed(names[st], s, [&] { return launch_ntt_stage(st, L, s); });
             if (err != hipSuccess) return KS_EHIP;
         }
+        auto Lj = make_launch(JL.ntt_join, T ? &T->ntt_join : nullptr, env, 0);
+        err = timed("ntt_join", s, [&] { return launch_ntt_join(Lj, s); });
+        if (err != hipSuccess) return KS_EHIP;
     }
     for (auto it = JL.anchor.begin(); it != JL.anchor.end(); ++it) {
         if (it == first_anchor) continue;
@@ -1000,6 +1043,12 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
     out->valu_limb_mults = G.valu_mults;
     out->scratch_bytes = std::max<int64_t>(G.ws_status, (int64_t)1 << 20);  // the pool's size for it
     out->ntt_butterflies = G.ntt_butterflies;
+    for (auto &m : G.muls)
+        if (m.engine == KS_ENGINE_NTT) {
+            out->ntt_k1 = m.ntt_k1;
+            out->ntt_k2 = m.ntt_k2;
+            break;
+        }
     return KS_OK;
 }
 
@@ -1262,7 +1311,7 @@ int ks_profile_read(const char *name, int64_t *launches, double *total_ms) {
     if (!name || !launches || !total_ms) return KS_EINVAL;
     static const char *known[] = {"pack",  "mul_valu", "mul_mfma", "normalize", "anchor",  "recon",
                                   "extract", "digitize", "finish",  "p2_eval",   "p2_recon", "kara",
-                                  "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols"};
+                                  "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "ntt_join"};
     bool ok = false;
     for (const char *k : known) ok = ok || strcmp(k, name) == 0;
     if (!ok) return KS_EINVAL;

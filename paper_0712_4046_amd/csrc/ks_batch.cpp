@@ -89,6 +89,7 @@ struct ks_batch_plan {
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
     double pack_bytes = 0, normalize_bytes = 0, finish_bytes = 0, anchor_mults = 0, mfma_ops = 0, valu_mults = 0;
     double ntt_butterflies = 0;
+    int32_t ntt_k1 = 0, ntt_k2 = 0;  // the first product on the transform engine
     int32_t engines = 0;  // OR of the engines the products use
     int variant = -1;
     // polynomial-level Karatsuba (every product modular, equal lengths, long): the three
@@ -272,6 +273,8 @@ static int plan_karatsuba(const ks_desc *descs, int64_t count, int32_t variant, 
     P->mfma_ops = inner->mfma_ops;
     P->valu_mults = inner->valu_mults;
     P->ntt_butterflies = inner->ntt_butterflies;
+    P->ntt_k1 = inner->ntt_k1;
+    P->ntt_k2 = inner->ntt_k2;
     P->engines = inner->engines;
     P->variant = inner->variant;
     void *t = nullptr;
@@ -341,6 +344,11 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
         P->mfma_ops += geoms[(size_t)i].mfma_ops;
         P->valu_mults += geoms[(size_t)i].valu_mults;
         P->ntt_butterflies += geoms[(size_t)i].ntt_butterflies;
+        for (const auto &m : geoms[(size_t)i].muls)
+            if (m.engine == KS_ENGINE_NTT && P->ntt_k1 == 0) {
+                P->ntt_k1 = m.ntt_k1;
+                P->ntt_k2 = m.ntt_k2;
+            }
         for (const auto &m : geoms[(size_t)i].muls) P->engines |= m.engine;
         int rv = geoms[(size_t)i].variant;
         P->variant = i == 0 ? rv : (P->variant == rv ? rv : -1);
@@ -370,8 +378,11 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
             sh(j.a);
             sh(j.x);
             sh(j.y);
-            sh(j.z);
         }
+    for (auto &j : JL.ntt_join) {
+        sh(j.x);
+        sh(j.cols);
+    }
     for (auto &kv : JL.anchor) for (auto &j : kv.second) sh(j.anchors);
     for (auto *nl : {&JL.norm, &JL.norm_small})
         for (auto &j : *nl) {
@@ -404,6 +415,7 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
     if (rc == KS_OK) rc = upload(JL.ntt_f2, P->T.ntt_f2, P->allocs);
     if (rc == KS_OK) rc = upload(JL.ntt_i2, P->T.ntt_i2, P->allocs);
     if (rc == KS_OK) rc = upload(JL.ntt_i1, P->T.ntt_i1, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.ntt_join, P->T.ntt_join, P->allocs);
     if (rc == KS_OK) rc = upload(JL.pack_small, P->T.pack_small, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mul, P->T.mul, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mul_wave, P->T.mul_wave, P->allocs);
@@ -440,6 +452,8 @@ int ks_batch_plan_info(const ks_batch_plan *plan, ks_plan_info *out) {
     out->valu_limb_mults = plan->valu_mults;
     out->scratch_bytes = plan->ws_bytes;
     out->ntt_butterflies = plan->ntt_butterflies;
+    out->ntt_k1 = plan->ntt_k1;
+    out->ntt_k2 = plan->ntt_k2;
     return KS_OK;
 }
 

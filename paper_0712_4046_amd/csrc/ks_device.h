@@ -384,7 +384,6 @@ template <> __device__ __forceinline__ void rebase(NttJob &J, const Launch<NttJo
     J.a = at(L.base_ws, J.a);
     J.x = at(L.base_ws, J.x);
     J.y = at(L.base_ws, J.y);
-    J.z = at(L.base_ws, J.z);
 }
 
 template <class J>
@@ -392,6 +391,61 @@ __device__ __forceinline__ J get_job(const Launch<J> &L, int64_t blk, int64_t &l
     J job = find_job(L, blk, local);
     rebase(job, L);
     return job;
+}
+
+// ---- arithmetic modulo the transform engine's primes --------------------------------------------
+
+struct NttPrime {
+    uint32_t p;
+    uint32_t pn;  // -p^-1 mod 2^32
+};
+
+__host__ __device__ constexpr uint32_t neg_inv32(uint32_t p) {
+    uint32_t x = p;  // Newton's iteration for p^-1 mod 2^32 (p odd): 5 steps from 3 bits
+    for (int i = 0; i < 5; ++i) x *= 2u - p * x;
+    return 0u - x;
+}
+
+// a^-1 mod p (extended Euclid), for the constant of the Chinese remainder step
+constexpr uint64_t inv_mod(uint64_t a, uint64_t p) {
+    int64_t t = 0, nt = 1, r = (int64_t)p, nr = (int64_t)(a % p);
+    while (nr != 0) {
+        const int64_t qq = r / nr;
+        const int64_t t2 = t - qq * nt, r2 = r - qq * nr;
+        t = nt;
+        nt = t2;
+        r = nr;
+        nr = r2;
+    }
+    return (uint64_t)(t < 0 ? t + (int64_t)p : t);
+}
+// P0^-1 R mod P1 (Montgomery form, R = 2^32): multiplying by it divides by P0 mod P1
+constexpr uint32_t NTT_CRT_C = (uint32_t)(inv_mod(NTT_P0, NTT_P1) * (((uint64_t)1 << 32) % NTT_P1) % NTT_P1);
+static_assert(inv_mod(NTT_P0, NTT_P1) * (NTT_P0 % NTT_P1) % NTT_P1 == 1, "P0 inverse mod P1");
+
+__device__ __forceinline__ NttPrime ntt_prime(int q) {
+    return q == 0 ? NttPrime{NTT_P0, neg_inv32(NTT_P0)} : NttPrime{NTT_P1, neg_inv32(NTT_P1)};
+}
+
+// a b R^-1 mod p for a, b < p < 2^31 (Montgomery reduction)
+__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, NttPrime P) {
+    const uint64_t t = (uint64_t)a * b;
+    const uint32_t m = (uint32_t)t * P.pn;
+    const uint32_t u = (uint32_t)((t + (uint64_t)m * P.p) >> 32);  // t + m p < 2^62 + 2^63
+    return u >= P.p ? u - P.p : u;
+}
+__device__ __forceinline__ uint32_t madd(uint32_t a, uint32_t b, uint32_t p) {
+    const uint32_t s = a + b;
+    return s >= p ? s - p : s;
+}
+__device__ __forceinline__ uint32_t msub(uint32_t a, uint32_t b, uint32_t p) { return a >= b ? a - b : a + p - b; }
+
+// the value below P0 P1 with residues x0 mod P0 and x1 mod P1 (Chinese remainder theorem):
+// x0 + P0 ((x1 - x0) P0^-1 mod P1)
+__device__ __forceinline__ uint64_t crt2(uint32_t x0, uint32_t x1) {
+    const uint32_t x0m = x0 >= NTT_P1 ? x0 - NTT_P1 : x0;  // x0 < P0 < 2 P1
+    const uint32_t t = mmul(msub(x1, x0m, NTT_P1), NTT_CRT_C, NttPrime{NTT_P1, neg_inv32(NTT_P1)});
+    return (uint64_t)x0 + (uint64_t)NTT_P0 * t;
 }
 
 // ---- small helpers ------------------------------------------------------------------------------

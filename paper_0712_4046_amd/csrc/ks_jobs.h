@@ -146,10 +146,10 @@ struct NttJob {
     int64_t na;         // limbs of a
     int64_t np;         // pieces of a (pieces at or above np read 0)
     uint32_t *x;        // the transform, 2 N words (prime 0, then prime 1); inverse: the
-                        // first operand's transform, overwritten by the product's
+                        // first operand's transform, overwritten by the product's and at last
+                        // by the residues of the product's convolution terms, in order (read
+                        // by the join step, NttJoinJob)
     const uint32_t *y;  // inverse rows: the second operand's transform
-    uint64_t *z;        // inverse columns: the product's terms (nz of them)
-    int64_t nz;
     int32_t k1, k2;     // N1 = 2^k1, N2 = 2^k2
     int32_t w;          // piece bits
     int32_t pad;
@@ -158,10 +158,27 @@ struct NttJob {
     int64_t nblocks;
 };
 
+// The transform engine's last step: the two residues of every convolution term (x[m] mod P0,
+// x[N + m] mod P1, m < nz) joined by the Chinese remainder theorem into the term c_m (below
+// 2^62, at bit weight 2^(w m)), and the terms gathered into limb columns in the vector-ALU
+// multiplier's format: column j (weight 2^(32 j)) = sum of c_m 2^(w m - 32 j) over the terms
+// with floor(w m / 32) = j, as three uint32 pieces cols[3 j + 0..2] (below 2^96 for w >= 11)
+struct NttJoinJob {
+    const uint32_t *x;
+    int64_t n;       // N: words from a term's residue mod P0 to its residue mod P1
+    int64_t nz;      // terms
+    int32_t w;       // piece bits
+    int32_t pad;
+    uint32_t *cols;  // ncols columns of three words
+    int64_t ncols;
+    int64_t block0;
+    int64_t nblocks;
+};
+
 // column-sum formats: three uint32 pieces per column (weights 2^0, 2^32, 2^64; the vector-ALU
-// multiplier), two uint64 sums per column (weights 2^0, 2^32; the matrix-core multiplier), or
-// the transforms' convolution terms of pw-bit pieces (term m, below 2^62, at weight 2^(pw m))
-enum : int32_t { NORM_FMT_PIECES = 0, NORM_FMT_XY = 1, NORM_FMT_WPIECE = 2 };
+// multiplier and the transform engine) or two uint64 sums per column (weights 2^0, 2^32; the
+// matrix-core multiplier)
+enum : int32_t { NORM_FMT_PIECES = 0, NORM_FMT_XY = 1 };
 
 // one product read back from its column sums, corrected for two's-complement operands;
 // column j of the value gets piece 0 of column j, piece 1 of j-1 and piece 2 of j-2
@@ -173,9 +190,7 @@ struct NormTerm {
     int64_t na;
     int64_t nb;
     int32_t sign;  // +1 or -1
-    int32_t fmt;   // NORM_FMT_PIECES, NORM_FMT_XY or NORM_FMT_WPIECE
-    int32_t pw;    // NORM_FMT_WPIECE: bits per piece (ncols counts terms)
-    int32_t pad;
+    int32_t fmt;   // NORM_FMT_PIECES or NORM_FMT_XY
 };
 
 // V = sum_terms sign * product + sum_{k < off_count} 2^(off_bit0 + k off_period);

@@ -49,6 +49,7 @@ hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, int rt, hipStream_t s);  //
 // one of the four transform steps of integer products on the transform engine: 0 forward
 // columns, 1 forward rows, 2 inverse rows (with the pointwise product), 3 inverse columns
 hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, hipStream_t s);
+hipError_t launch_ntt_join(const Launch<NttJoinJob> &L, hipStream_t s);
 hipError_t launch_p2_eval(const P2Eval &E, hipStream_t s);
 hipError_t launch_p2_readoff(const P2Readoff &R, hipStream_t s);
 hipError_t launch_p2_glue(const P2Glue &G, hipStream_t s);  // two launches (chunk sums, then outputs)

@@ -15,8 +15,10 @@
 //   forward rows     N1 transforms of length N2 over the rows
 //   inverse rows     the pointwise product of the two operands' transforms (Montgomery), the
 //                    inverse row transforms, the inverse twiddle and the scale 1/N
-//   inverse columns  the inverse column transforms of both primes, the Chinese remainder
-//                    theorem, the convolution terms written in order
+//   inverse columns  the inverse column transforms, the residues of the convolution terms
+//                    written in order (in place)
+//   join             the two residues of each term joined by the Chinese remainder theorem,
+//                    the terms gathered into 96-bit limb columns for the recombination
 // Forward transforms are decimation in frequency (natural order in, bit-reversed out) and the
 // inverse ones decimation in time (bit-reversed in, natural out), so no step reorders data:
 // rows are kept at their bit-reversed positions and the pointwise product pairs equal positions.
@@ -45,52 +47,6 @@ static_assert(NTT_TAB * NTT_TAB == (1 << NTT_ROOT_LOG), "two half tables cover t
 // [prime][0: w^(8192 i) R, 1: w^i R][i] mod P
 __device__ uint32_t ntt_tab[2][2][NTT_TAB];
 
-struct NttPrime {
-    uint32_t p;
-    uint32_t pn;  // -p^-1 mod 2^32
-};
-
-__host__ __device__ constexpr uint32_t neg_inv32(uint32_t p) {
-    uint32_t x = p;  // Newton's iteration for p^-1 mod 2^32 (p odd): 5 steps from 3 bits
-    for (int i = 0; i < 5; ++i) x *= 2u - p * x;
-    return 0u - x;
-}
-
-// m^-1 mod p (extended Euclid), for the constant of the Chinese remainder step
-constexpr uint64_t inv_mod(uint64_t a, uint64_t p) {
-    int64_t t = 0, nt = 1, r = (int64_t)p, nr = (int64_t)(a % p);
-    while (nr != 0) {
-        const int64_t qq = r / nr;
-        const int64_t t2 = t - qq * nt, r2 = r - qq * nr;
-        t = nt;
-        nt = t2;
-        r = nr;
-        nr = r2;
-    }
-    return (uint64_t)(t < 0 ? t + (int64_t)p : t);
-}
-// P0^-1 R mod P1 (Montgomery form): multiplying by it divides by P0 mod P1
-constexpr uint32_t NTT_CRT_C =
-    (uint32_t)(inv_mod(NTT_P0, NTT_P1) * (((uint64_t)1 << 32) % NTT_P1) % NTT_P1);
-static_assert(inv_mod(NTT_P0, NTT_P1) * (NTT_P0 % NTT_P1) % NTT_P1 == 1, "P0 inverse mod P1");
-
-__device__ __forceinline__ NttPrime ntt_prime(int q) {
-    return q == 0 ? NttPrime{NTT_P0, neg_inv32(NTT_P0)} : NttPrime{NTT_P1, neg_inv32(NTT_P1)};
-}
-
-// a b R^-1 mod p for a, b < p < 2^31
-__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, NttPrime P) {
-    const uint64_t t = (uint64_t)a * b;
-    const uint32_t m = (uint32_t)t * P.pn;
-    const uint32_t u = (uint32_t)((t + (uint64_t)m * P.p) >> 32);  // t + m p < 2^62 + 2^63
-    return u >= P.p ? u - P.p : u;
-}
-__device__ __forceinline__ uint32_t madd(uint32_t a, uint32_t b, uint32_t p) {
-    const uint32_t s = a + b;
-    return s >= p ? s - p : s;
-}
-__device__ __forceinline__ uint32_t msub(uint32_t a, uint32_t b, uint32_t p) { return a >= b ? a - b : a + p - b; }
-
 // w^e R for e in [0, 2^26), w the table root of prime q
 __device__ __forceinline__ uint32_t root_pow(int q, uint32_t e, NttPrime P) {
     return mmul(ntt_tab[q][0][e >> (NTT_ROOT_LOG / 2)], ntt_tab[q][1][e & (NTT_TAB - 1)], P);
@@ -109,36 +65,98 @@ __device__ __forceinline__ void load_twiddles(uint32_t *tw, int q, int lg, NttPr
     }
 }
 
-// nseq transforms of length 2^lg in LDS, sequence s at buf[s * stride ..]: forward by
-// decimation in frequency (natural in, bit-reversed out), inverse by decimation in time
-// (bit-reversed in, natural out; tw holds the inverse twiddles).  Ends with a barrier.
-template <bool INV>
-__device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, int nseq, int lg, const uint32_t *tw,
-                                              NttPrime P) {
-    const int half = 1 << (lg - 1);
-    const int total = nseq * half;
-    for (int st = 0; st < lg; ++st) {
-        // forward: half-size h = M / 2^(st+1), twiddle index j << st; inverse: h = 2^st,
-        // twiddle index j << (lg - 1 - st)
-        const int hl = INV ? st : lg - 1 - st;
-        const int ts = INV ? lg - 1 - st : st;
-        const int h = 1 << hl;
-        for (int b = threadIdx.x; b < total; b += NTT_TPB) {
-            const int seq = b >> (lg - 1), r = b & (half - 1);
+// Transforms of length M = 2^LG over NTT_BLOCK elements in LDS (NTT_BLOCK / M sequences,
+// sequence s at buf[s * stride ..]): forward by decimation in frequency (natural in, bit-reversed
+// out), inverse by decimation in time (bit-reversed in, natural out; tw holds the inverse
+// twiddles, tw[j] = w_M^(+-j) R).  Stages go in pairs (radix 4: each thread reads four elements,
+// runs two stages in registers and writes them back), with one radix-2 stage more when LG is odd
+// (last in the forward order, first in the inverse).  Ends with a barrier.
+template <int LG, bool INV>
+__device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, const uint32_t *tw, NttPrime P) {
+    constexpr int NQ = NTT_BLOCK / 4 / NTT_TPB;  // groups of four per thread and pass
+    constexpr int NH = NTT_BLOCK / 2 / NTT_TPB;  // pairs per thread in a radix-2 stage
+    constexpr int PAIRS = LG / 2;
+    auto radix2 = [&](int hl) {  // one stage of half-size 2^hl (twiddle index j << (LG-1-hl))
+        const int h = 1 << hl, ts = LG - 1 - hl;
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const int b = threadIdx.x + i * NTT_TPB;
+            const int seq = b >> (LG - 1), r = b & ((1 << (LG - 1)) - 1);
             const int j = r & (h - 1);
             uint32_t *x = buf + seq * stride + ((r >> hl) << (hl + 1)) + j;
-            const uint32_t u = x[0];
+            const uint32_t u = x[0], t = tw[j << ts];
             if (!INV) {
                 const uint32_t v = x[h];
                 x[0] = madd(u, v, P.p);
-                x[h] = mmul(msub(u, v, P.p), tw[j << ts], P);
+                x[h] = mmul(msub(u, v, P.p), t, P);
             } else {
-                const uint32_t v = mmul(x[h], tw[j << ts], P);
+                const uint32_t v = mmul(x[h], t, P);
                 x[0] = madd(u, v, P.p);
                 x[h] = msub(u, v, P.p);
             }
         }
         __syncthreads();
+    };
+    // two stages with half-sizes 2^(bl+1) and 2^bl on groups of four elements j, j + Hb,
+    // j + 2 Hb, j + 3 Hb (Hb = 2^bl)
+    auto radix4 = [&](int bl) {
+        const int hb = 1 << bl;
+        const int ta = LG - 2 - bl, tb = LG - 1 - bl;  // twiddle shifts of the larger and smaller stage
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int g = threadIdx.x + i * NTT_TPB;
+            const int seq = g >> (LG - 2), r = g & ((1 << (LG - 2)) - 1);
+            const int j = r & (hb - 1);
+            uint32_t *x = buf + seq * stride + ((r >> bl) << (bl + 2)) + j;
+            uint32_t u0 = x[0], u1 = x[hb], u2 = x[2 * hb], u3 = x[3 * hb];
+            const uint32_t wa0 = tw[j << ta], wa1 = tw[(j + hb) << ta], wb = tw[j << tb];
+            if (!INV) {
+                const uint32_t a0 = madd(u0, u2, P.p), a2 = mmul(msub(u0, u2, P.p), wa0, P);
+                const uint32_t a1 = madd(u1, u3, P.p), a3 = mmul(msub(u1, u3, P.p), wa1, P);
+                u0 = madd(a0, a1, P.p);
+                u1 = mmul(msub(a0, a1, P.p), wb, P);
+                u2 = madd(a2, a3, P.p);
+                u3 = mmul(msub(a2, a3, P.p), wb, P);
+            } else {
+                const uint32_t v1 = mmul(u1, wb, P), v3 = mmul(u3, wb, P);
+                const uint32_t a0 = madd(u0, v1, P.p), a1 = msub(u0, v1, P.p);
+                const uint32_t a2 = madd(u2, v3, P.p), a3 = msub(u2, v3, P.p);
+                const uint32_t c2 = mmul(a2, wa0, P), c3 = mmul(a3, wa1, P);
+                u0 = madd(a0, c2, P.p);
+                u2 = msub(a0, c2, P.p);
+                u1 = madd(a1, c3, P.p);
+                u3 = msub(a1, c3, P.p);
+            }
+            x[0] = u0;
+            x[hb] = u1;
+            x[2 * hb] = u2;
+            x[3 * hb] = u3;
+        }
+        __syncthreads();
+    };
+    if (!INV) {
+#pragma unroll
+        for (int pr = 0; pr < PAIRS; ++pr) radix4(LG - 2 - 2 * pr);  // half-sizes M/2, M/4, ...
+        if (LG & 1) radix2(0);
+    } else {
+        if (LG & 1) radix2(0);
+#pragma unroll
+        for (int pr = 0; pr < PAIRS; ++pr) radix4((LG & 1) + 2 * pr);  // half-sizes 1, 2, ... (after the odd one)
+    }
+}
+
+// the templated transform for a length known only at run time (4 <= lg <= 12)
+template <bool INV>
+__device__ __forceinline__ void lds_transform_any(int lg, uint32_t *buf, int stride, const uint32_t *tw,
+                                                  NttPrime P) {
+    switch (lg) {
+        case 6: lds_transform<6, INV>(buf, stride, tw, P); break;
+        case 7: lds_transform<7, INV>(buf, stride, tw, P); break;
+        case 8: lds_transform<8, INV>(buf, stride, tw, P); break;
+        case 9: lds_transform<9, INV>(buf, stride, tw, P); break;
+        case 10: lds_transform<10, INV>(buf, stride, tw, P); break;
+        case 11: lds_transform<11, INV>(buf, stride, tw, P); break;
+        default: lds_transform<12, INV>(buf, stride, tw, P); break;
     }
 }
 
@@ -164,9 +182,9 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L)
     const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
     const int C = NTT_BLOCK >> k1, S = (1 << k1) + 1;  // columns, LDS stride of a column
-    const int64_t groups = (int64_t)1 << (k2 - (13 - k1));
-    const int q = (int)(local / groups);
-    const int64_t c0 = (local - q * groups) * C;
+    const int gl = k - 13;  // log2 of the blocks of one prime (a power of two: no division)
+    const int q = (int)(local >> gl);
+    const int64_t c0 = (local & (((int64_t)1 << gl) - 1)) * C;
     const NttPrime P = ntt_prime(q);
     load_twiddles<false>(tw, q, k1, P);
     for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
@@ -174,7 +192,7 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L)
         buf[c * S + n1] = piece(J, ((int64_t)n1 << k2) + c0 + c);
     }
     __syncthreads();
-    lds_transform<false>(buf, S, C, k1, tw, P);
+    lds_transform_any<false>(k1, buf, S, tw, P);
     uint32_t *x = J.x + ((int64_t)q << k);
     for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
         const int c = e & (C - 1), r = e >> (13 - k1);
@@ -190,15 +208,15 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_rows_kernel(Launch<NttJob> L)
     int64_t local;
     const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
-    const int64_t groups = (int64_t)1 << (k1 - (13 - k2));  // blocks per prime: N1 / R
-    const int q = (int)(local / groups);
-    const int64_t base = (local - q * groups) * NTT_BLOCK;  // R whole rows, contiguous
+    const int gl = k - 13;  // log2 of the blocks of one prime: N1 / R
+    const int q = (int)(local >> gl);
+    const int64_t base = (local & (((int64_t)1 << gl) - 1)) * NTT_BLOCK;  // R whole rows, contiguous
     const NttPrime P = ntt_prime(q);
     load_twiddles<false>(tw, q, k2, P);
     uint32_t *x = J.x + ((int64_t)q << k) + base;
     for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) buf[e] = ldg(x + e);
     __syncthreads();
-    lds_transform<false>(buf, 1 << k2, NTT_BLOCK >> k2, k2, tw, P);
+    lds_transform_any<false>(k2, buf, 1 << k2, tw, P);
     for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) stg(x + e, buf[e]);
 }
 
@@ -208,9 +226,9 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L)
     int64_t local;
     const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
-    const int64_t groups = (int64_t)1 << (k1 - (13 - k2));
-    const int q = (int)(local / groups);
-    const int64_t base = (local - q * groups) * NTT_BLOCK;
+    const int gl = k - 13;
+    const int q = (int)(local >> gl);
+    const int64_t base = (local & (((int64_t)1 << gl) - 1)) * NTT_BLOCK;
     const int64_t r0 = base >> k2;  // first row of the block
     const NttPrime P = ntt_prime(q);
     load_twiddles<true>(tw, q, k2, P);
@@ -218,10 +236,10 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L)
     const uint32_t *y = J.y + ((int64_t)q << k) + base;
     for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) buf[e] = mmul(ldg(x + e), ldg(y + e), P);  // A B R^-1
     __syncthreads();
-    lds_transform<true>(buf, 1 << k2, NTT_BLOCK >> k2, k2, tw, P);
+    lds_transform_any<true>(k2, buf, 1 << k2, tw, P);
     // inverse twiddle w_N^-(n2 k1) and the scale R / N (the pointwise product left R^-1):
     // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N
-    const uint32_t K = J.kscale[q];
+    const uint32_t K = q == 0 ? J.kscale[0] : J.kscale[1];  // (a dynamic index would copy the job to scratch)
     for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
         const int64_t r = r0 + (e >> k2), n2 = e & ((1 << k2) - 1);
         const uint32_t ex = (uint32_t)((n2 * (int64_t)bitrev((uint32_t)r, k1)) << (NTT_ROOT_LOG - k));
@@ -231,48 +249,57 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L)
 }
 
 __global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L) {
-    constexpr int EPT = NTT_BLOCK / NTT_TPB;
     __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
     __shared__ uint32_t tw[2048];
     int64_t local;
     const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
     const int C = NTT_BLOCK >> k1, S = (1 << k1) + 1;
-    const int64_t c0 = local * C;
-    uint32_t v0[EPT];
-    for (int q = 0; q < 2; ++q) {
-        const NttPrime P = ntt_prime(q);
-        load_twiddles<true>(tw, q, k1, P);
-        const uint32_t *x = J.x + ((int64_t)q << k);
-        for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
-            const int c = e & (C - 1), r = e >> (13 - k1);
-            buf[c * S + r] = ldg(x + ((int64_t)r << k2) + c0 + c);
-        }
-        __syncthreads();
-        lds_transform<true>(buf, S, C, k1, tw, P);
-        if (q == 0) {
-#pragma unroll
-            for (int it = 0; it < EPT; ++it) {
-                const int e = threadIdx.x + it * NTT_TPB;
-                v0[it] = buf[(e & (C - 1)) * S + (e >> (13 - k1))];
-            }
-            __syncthreads();  // before the second prime's columns overwrite buf
-        } else {
-            // Chinese remainder theorem: z = x0 + P0 ((x1 - x0) P0^-1 mod P1), below P0 P1
-            const NttPrime P1 = ntt_prime(1);
-#pragma unroll
-            for (int it = 0; it < EPT; ++it) {
-                const int e = threadIdx.x + it * NTT_TPB;
-                const int c = e & (C - 1), n1 = e >> (13 - k1);
-                const uint32_t x1 = buf[c * S + n1], x0 = v0[it];
-                const uint32_t x0m = x0 >= NTT_P1 ? x0 - NTT_P1 : x0;  // x0 < P0 < 2 P1
-                const uint32_t d = msub(x1, x0m, NTT_P1);
-                const uint32_t t = mmul(d, NTT_CRT_C, P1);  // (x1 - x0) P0^-1 mod P1
-                const int64_t m = ((int64_t)n1 << k2) + c0 + c;
-                if (m < J.nz) stg(J.z + m, (uint64_t)x0 + (uint64_t)NTT_P0 * t);
-            }
-        }
+    const int gl = k - 13;
+    const int q = (int)(local >> gl);
+    const int64_t c0 = (local & (((int64_t)1 << gl) - 1)) * C;
+    const NttPrime P = ntt_prime(q);
+    load_twiddles<true>(tw, q, k1, P);
+    uint32_t *x = J.x + ((int64_t)q << k);
+    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
+        const int c = e & (C - 1), r = e >> (13 - k1);
+        buf[c * S + r] = ldg(x + ((int64_t)r << k2) + c0 + c);
     }
+    __syncthreads();
+    lds_transform_any<true>(k1, buf, S, tw, P);
+    // the residues of terms N2 n1 + n2 in natural order, in place (the block's columns hold
+    // exactly the positions it read)
+    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
+        const int c = e & (C - 1), n1 = e >> (13 - k1);
+        stg(x + ((int64_t)n1 << k2) + c0 + c, buf[c * S + n1]);
+    }
+}
+
+// the join: one thread per limb column, the (at most two for w >= 16, three for w >= 11) terms
+// whose bit weight falls in it
+__global__ __launch_bounds__(NTT_TPB) void ntt_join_kernel(Launch<NttJoinJob> L) {
+    int64_t local;
+    NttJoinJob J = find_job(L, (int64_t)blockIdx.x, local);
+    J.x = at(L.base_ws, J.x);
+    J.cols = at(L.base_ws, J.cols);
+    const int64_t col = local * NTT_TPB + threadIdx.x;
+    if (col >= J.ncols) return;
+    const int64_t w = J.w;
+    const int64_t m0 = (32 * col + w - 1) / w;  // first term with w m >= 32 col
+    int64_t m1 = (32 * col + 31) / w;           // last term with w m < 32 col + 32
+    if (m1 > J.nz - 1) m1 = J.nz - 1;
+    uint64_t lo = 0;
+    uint32_t hi = 0;
+    for (int64_t m = m0; m <= m1; ++m) {
+        const uint64_t z = crt2(ldg(J.x + m), ldg(J.x + J.n + m));
+        const int sh = (int)(w * m - 32 * col);  // 0 .. 31
+        const uint64_t zl = z << sh;
+        const uint32_t zh = sh ? (uint32_t)(z >> (64 - sh)) : 0u;
+        lo += zl;
+        hi += zh + (lo < zl ? 1u : 0u);
+    }
+    uint32_t v[3] = {(uint32_t)lo, (uint32_t)(lo >> 32), hi};
+    stg_words<3>(J.cols + 3 * col, v);
 }
 
 // ---- host side -----------------------------------------------------------------------------------
@@ -337,6 +364,12 @@ int ntt_prepare() {
         return KS_EHIP;
     done[dev] = true;
     return KS_OK;
+}
+
+hipError_t launch_ntt_join(const Launch<NttJoinJob> &L, hipStream_t s) {
+    if (L.total_blocks <= 0) return hipSuccess;
+    ks_launch(ntt_join_kernel, dim3((unsigned)L.total_blocks), dim3(NTT_TPB), 0, s, L);
+    return hipGetLastError();
 }
 
 hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, hipStream_t s) {

@@ -57,9 +57,10 @@ struct MulGeom {
     int rt = 8;  // row tiles per block
     int64_t ad_off = 0, bd_off = 0;
     // transform engine: N = 2^(k1 + k2), w-bit pieces (npa, npb of them), nz convolution terms;
-    // word offsets of the two transforms and the terms in the transform region
+    // word offsets of the two transforms in the transform region (the first ends up holding the
+    // terms' residues)
     int ntt_k1 = 0, ntt_k2 = 0, ntt_w = 0;
-    int64_t ntt_npa = 0, ntt_npb = 0, ntt_nz = 0, ntt_xa = 0, ntt_xb = 0, ntt_z = 0;
+    int64_t ntt_npa = 0, ntt_npb = 0, ntt_nz = 0, ntt_xa = 0, ntt_xb = 0, ntt_cols = 0;  // + the joined columns
 };
 struct NormGeom {
     int nterms, prod[2], sign[2], shift;
@@ -130,6 +131,7 @@ struct JobLists {
     std::vector<DigitJob> digit;
     std::vector<MfmaJob> mfma;
     std::vector<NttJob> ntt_f1, ntt_f2, ntt_i2, ntt_i1;  // transform stages (forward per operand)
+    std::vector<NttJoinJob> ntt_join;
     std::vector<NormJob> norm;
     std::vector<NormJob> norm_small;  // jobs of at most small_bl(ipt) limbs
     std::vector<ExtractJob> extract;
@@ -144,7 +146,8 @@ struct DevList {
     uint32_t *block_job = nullptr;
 };
 struct DevTables {
-    DevList pack, pack_small, mul, mul_wave, digit, mfma, norm, norm_small, extract, ntt_f1, ntt_f2, ntt_i2, ntt_i1;
+    DevList pack, pack_small, mul, mul_wave, digit, mfma, norm, norm_small, extract, ntt_f1, ntt_f2, ntt_i2, ntt_i1,
+        ntt_join;
     std::map<int, DevList> anchor, chain, finish;
 };
 
@@ -180,8 +183,9 @@ bool ntt_shape(int64_t na, int64_t nb, int min_log, int &k1, int &k2, int &w, in
 uint32_t ntt_scale(int q, int k);
 // the root tables on the current device (uploaded once per device; synchronous)
 int ntt_prepare();
-// planner default of KS_NTT_MIN_LIMBS
-constexpr int NTT_MIN_LIMBS = 12000;
+// planner defaults of KS_NTT_MIN_LIMBS: a single product pays the transforms' four launches
+// alone (measured crossing against the matrix cores: 35K-55K operand limbs), a batch shares them
+constexpr int NTT_MIN_LIMBS = 40000, NTT_MIN_LIMBS_BATCH = 12000;
 // whether ks_batch_plan_create would split this batch by Karatsuba (see KS_KARATSUBA_MIN_LIMBS)
 bool karatsuba_splits(const ks_desc *descs, int64_t count, int32_t variant);
 // batches of modular products of equal lengths whose integer operands have at least this

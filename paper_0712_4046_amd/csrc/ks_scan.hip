@@ -92,37 +92,6 @@ __device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int
     }
 }
 
-// The transform engine's terms: term m (below 2^62) at bit weight 2^(pw m).  Position j
-// (bits [32 j, 32 j + 32)) gets the 32-bit slice of every term overlapping it, so the positions
-// add up to the same integer; a term overlaps at most three positions, and a position at most
-// ceil(94 / pw) terms.
-template <int IPT>
-__device__ __forceinline__ void piece_window(const NormTerm &T, int64_t j0, int64_t (&acc)[IPT + 2]) {
-    constexpr int NV = IPT + 2;
-    const int64_t w = T.pw;
-    const uint64_t *z = reinterpret_cast<const uint64_t *>(T.cols);
-    const int64_t lo = 32 * (j0 - 2);  // first bit of the window
-#pragma unroll
-    for (int t = 0; t < NV; ++t) acc[t] = 0;
-    if (lo + 32 * NV <= 0) return;
-    // terms whose 62 bits overlap [lo, lo + 32 NV)
-    const int64_t m0 = lo - 62 < 0 ? 0 : (lo - 62) / w + 1;
-    int64_t m1 = (lo + 32 * NV - 1) / w;
-    if (m1 > T.ncols - 1) m1 = T.ncols - 1;
-    for (int64_t m = m0; m <= m1; ++m) {
-        const uint64_t val = ldg(z + m);
-        const int64_t pos = w * m - lo;  // bit of the term within the window, in (-62, 32 NV)
-#pragma unroll
-        for (int t = 0; t < NV; ++t) {
-            const int64_t off = pos - 32 * t;  // the term's bit 0 relative to position t's bit 0
-            uint32_t sl = 0;
-            if (off >= 0 && off < 32) sl = (uint32_t)(val << off);
-            else if (off < 0 && off > -64) sl = (uint32_t)(val >> -off);
-            acc[t] += sl;
-        }
-    }
-}
-
 template <int IPT>
 __device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bool negB, int64_t j0,
                                                 int64_t (&v)[IPT + 2]) {
@@ -130,8 +99,6 @@ __device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bo
     int64_t acc[NV];
     if (T.fmt == NORM_FMT_XY)
         column_window<4, IPT>(T, j0, acc);
-    else if (T.fmt == NORM_FMT_WPIECE)
-        piece_window<IPT>(T, j0, acc);
     else
         column_window<3, IPT>(T, j0, acc);
     // the multiplier works on the unsigned readings of two's-complement operands:

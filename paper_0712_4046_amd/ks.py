@@ -42,7 +42,7 @@ class PlanInfo(ctypes.Structure):
                 ("normalize_bytes", ctypes.c_double), ("finish_bytes", ctypes.c_double),
                 ("anchor_limb_mults", ctypes.c_double), ("mfma_ops", ctypes.c_double),
                 ("valu_limb_mults", ctypes.c_double), ("scratch_bytes", ctypes.c_int64),
-                ("ntt_butterflies", ctypes.c_double)]
+                ("ntt_butterflies", ctypes.c_double), ("ntt_k1", ctypes.c_int32), ("ntt_k2", ctypes.c_int32)]
 
 
 class Desc(ctypes.Structure):

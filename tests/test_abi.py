@@ -119,3 +119,35 @@ def test_poly2_arguments_checked_on_the_host():
     assert call(p=1) == ks.KS_EINVAL
     assert call(v=0x55) == ks.KS_EINVAL
     assert call(inner=ks.KS_SIGNED) == ks.KS_EINVAL
+
+
+def test_tuning_cache_file_read_at_plan_time(tmp_path):
+    # the autotuner's JSON cache (KS_TUNING_FILE) sets tunables in a fresh process, below
+    # ks_tune_set and the environment; unknown keys are ignored
+    import json
+    import subprocess
+    import sys
+    path = tmp_path / "tuning.json"
+    path.write_text(json.dumps({"tunables": {"KS_CHAIN_K": 77, "KS_NTT_MIN_LIMBS": 5000, "NOT_A_TUNABLE": 3},
+                                "workload": "x"}))
+    code = ("from paper_0712_4046_amd import ks; "
+            "print(ks.tune_get('KS_CHAIN_K'), ks.tune_get('KS_NTT_MIN_LIMBS'), ks.tune_get('KS_MFMA_RT')); "
+            "ks.tune_set('KS_CHAIN_K', 9); print(ks.tune_get('KS_CHAIN_K'))")
+    env = dict(os.environ, KS_TUNING_FILE=str(path))
+    env.pop("KS_CHAIN_K", None)
+    env.pop("KS_NTT_MIN_LIMBS", None)
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, check=True)
+    assert out.stdout.split() == ["77", "5000", "0", "9"]
+    env["KS_CHAIN_K"] = "12"  # the environment wins over the file
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, check=True)
+    assert out.stdout.split()[0] == "12"
+
+
+@pytest.mark.parametrize("L,bits,variant", [(65536, 60, "ks4"), (65536, 256, "ks1"), (32768, 64, "neg2")])
+def test_planner_takes_the_transforms_for_long_operands(L, bits, variant):
+    # long operands go to the transform engine; its exactness condition fixes the piece width
+    p = ks.plan(L, L, bits, variant, True)
+    assert p["engine"] == ks.KS_ENGINE_NTT
+    assert p["ntt_butterflies"] > 0 and p["mfma_ops"] == 0
+    forced = ks.plan(L, L, bits, variant, True, engine="mfma")
+    assert forced["engine"] == ks.KS_ENGINE_MFMA and forced["ntt_butterflies"] == 0
