@@ -157,9 +157,13 @@ static int64_t slot_bits(int variant, int b, int e) {
 // Time model for KS_VARIANT_AUTO (microseconds on one MI355X, fitted to single-product
 // measurements): the products on the engine the planner will pick -- vector ALU 0.21 fs per
 // limb product above a 5 us floor, matrix cores 0.69 fs per int8 operation on balanced digits
-// above a 10 us floor -- plus 0.15 ns per operand limb for the linear stages, 0.2 ns per
-// coefficient for KS4's reconstruction, and 4.5 us per launch (KS4 has one more; the matrix
-// cores add the digit launch).  A batch shares its launches, so there only the rates count.
+// above a 10 us floor, transforms 3.5 ps per term and level -- plus 0.15 ns per operand limb
+// for the linear stages, 0.2 ns per coefficient for KS4's reconstruction, and 4.5 us per launch
+// (KS4 has one more; the matrix cores add the digit launch, the transforms four).  A batch
+// shares its launches, so there only the rates count.  With the quasi-linear transforms the
+// four products of a quarter of the length cost about as much as the one long product, and the
+// standard substitution's lighter linear stages win (Section 1: the gain of several points
+// vanishes as M(b) approaches b log b).
 // It picks NEG2 for the L = 4096 signed 64-bit product (measured 0.043 ms, against 0.045 for
 // KS1 and 0.051 for KS4), KS4 for L = 65536 at 48 bits (0.54 ms, against 0.72 and 1.27), and
 // KS1 or NEG2 for short products, where every variant is launch-bound.
@@ -171,11 +175,22 @@ static int auto_variant(int64_t lf, int64_t lg, int b, int e, bool batch, int en
         const int k = v == KS_VARIANT_KS1 ? 1 : (v == KS_VARIANT_NEG2 ? 2 : 4);
         const double na = (double)cdiv(N * (lf - 1) + b + 2, 32), nb = (double)cdiv(N * (lg - 1) + b + 2, 32);
         int eng = engine;
+        int k1 = 0, k2 = 0, w = 0;
+        int64_t pa = 0, pb = 0;
+        const bool ntt_ok = ntt_shape((int64_t)na, (int64_t)nb, 0, k1, k2, w, pa, pb);
+        const int64_t ntt_min = env_int("KS_NTT_MIN_LIMBS", batch ? NTT_MIN_LIMBS_BATCH : NTT_MIN_LIMBS);
+        if (eng == 0 && ntt_ok && ntt_min > 0 && std::min(na, nb) >= (double)ntt_min) eng = KS_ENGINE_NTT;
+        if (eng == KS_ENGINE_NTT && !ntt_ok) eng = KS_ENGINE_MFMA;
         if (eng == 0)
             eng = std::min(na, nb) >= env_int("KS_MFMA_MIN_LIMBS", batch ? 1000 : 2500) ? KS_ENGINE_MFMA : KS_ENGINE_VALU;
         double us = 0;
         int launches = 4;  // pack, multiply, recombine, extract
-        if (eng == KS_ENGINE_MFMA) {
+        if (eng == KS_ENGINE_NTT) {
+            // 3.5 ps per transform term and level (both primes, three transforms and the join;
+            // 0.34 ms for one product through 2^22 terms, 3.9 ms for 256 through 2^18)
+            us += k * 3.5e-6 * (double)((int64_t)1 << (k1 + k2)) * (k1 + k2);
+            launches += 4;  // four transform steps and the join in place of one multiplier
+        } else if (eng == KS_ENGINE_MFMA) {
             us += k * 2.0 * (4 * na + 1) * (4 * nb + 1) * 6.9e-10;
             launches += 1;  // digits
             if (!batch) us += 10.0;
