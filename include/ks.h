@@ -60,7 +60,7 @@ extern "C" {
 #define KS_ENGINE_VALU 0x1000  /* force the vector-ALU 32x32-bit limb multiplier            */
 #define KS_ENGINE_MFMA 0x2000  /* force the int8 matrix-core (MFMA) limb multiplier          */
 #define KS_ENGINE_NTT 0x4000   /* force the number-theoretic-transform multiplier (products
-                                  beyond its longest transform, 2^24 terms, use the matrix cores) */
+                                  beyond its longest transform, 2^23 terms, use the matrix cores) */
 #define KS_ENGINE_ANY (KS_ENGINE_VALU | KS_ENGINE_MFMA | KS_ENGINE_NTT)
 #define KS_MOD 0x10000         /* batch descriptor flag: residues mod desc.mod_p (see below) */
 

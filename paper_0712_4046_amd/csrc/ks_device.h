@@ -307,6 +307,20 @@ __device__ __forceinline__ LaunchCtl ctl_of(const Launch<J> &L) {
     return LaunchCtl{L.status, L.ctrs, L.devstat, L.epoch};
 }
 
+// ---- XCD-aware block order ----------------------------------------------------------------------
+// The dispatcher deals the blocks of a launch to the GPU's 8 XCDs in turn (block b to XCD
+// b mod 8), and each XCD has an L2 of its own.  Blocks that re-read the same data (the anchors
+// of one product, the matrix-core blocks of one product) share that L2 only if they run on one
+// XCD, so block b of n takes the logical index (b mod 8) floor(n/8) + floor(b/8): the logical
+// blocks [x floor(n/8), (x+1) floor(n/8)) all run on one XCD.  The last n mod 8 blocks keep their
+// index.  A bijection of [0, n), so every logical block runs exactly once.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+    const int64_t per = n / NUM_XCD;
+    if (b >= per * NUM_XCD) return b;
+    return (b % NUM_XCD) * per + b / NUM_XCD;
+}
+
 // ---- job lookup: block index -> (job, block within job) ----------------------------------------
 // Inline jobs: all block0 values are loaded at once (independent scalar loads, one round
 // trip).  Device tables: one load from the block -> job map.
@@ -427,11 +441,19 @@ __device__ __forceinline__ NttPrime ntt_prime(int q) {
     return q == 0 ? NttPrime{NTT_P0, neg_inv32(NTT_P0)} : NttPrime{NTT_P1, neg_inv32(NTT_P1)};
 }
 
-// a b R^-1 mod p for a, b < p < 2^31 (Montgomery reduction)
+// x y + z in 64 bits (one v_mad_u64_u32; the caller knows the sum cannot wrap)
+__device__ __forceinline__ uint64_t mad64(uint32_t x, uint32_t y, uint64_t z) {
+    uint64_t r, cc;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(cc) : "v"(x), "v"(y), "v"(z));
+    return r;
+}
+
+// a b R^-1 mod p for a, b < p < 2^31 (Montgomery reduction): t = a b, m = t p' mod 2^32,
+// (t + m p) / 2^32 < 2p -- three multiply-adds (t + m p < 2^62 + 2^63 does not wrap)
 __device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, NttPrime P) {
-    const uint64_t t = (uint64_t)a * b;
-    const uint32_t m = (uint32_t)t * P.pn;
-    const uint32_t u = (uint32_t)((t + (uint64_t)m * P.p) >> 32);  // t + m p < 2^62 + 2^63
+    const uint64_t t = mad64(a, b, 0);
+    const uint32_t m = (uint32_t)mad64((uint32_t)t, P.pn, 0);
+    const uint32_t u = (uint32_t)(mad64(m, P.p, t) >> 32);
     return u >= P.p ? u - P.p : u;
 }
 __device__ __forceinline__ uint32_t madd(uint32_t a, uint32_t b, uint32_t p) {

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(EXTRACT_TPB) void extract_kernel(Launch<ExtractJob>
 template <int W>
 __global__ __launch_bounds__(ANCHOR_TPB) void anchor_kernel(Launch<AnchorJob> L) {
     int64_t local;
-    const AnchorJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const AnchorJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
     anchor_block<W>(J, local);
 }
 

@@ -135,7 +135,7 @@ struct MfmaJob {
 // does not mind and the inverse steps undo.
 constexpr int NTT_TPB = 256;
 constexpr int NTT_BLOCK = 8192;   // elements a block transforms: C columns of N1, or R rows of N2
-constexpr int NTT_MIN_LOG = 13, NTT_MAX_LOG = 24;  // N1, N2 <= 4096; C = NTT_BLOCK / N1 <= N2
+constexpr int NTT_MIN_LOG = 13, NTT_MAX_LOG = 23;  // N1 <= 2048 <= N2 <= 4096: 4 <= C <= N2
 constexpr int NTT_ROOT_LOG = 26;  // root tables: powers of a root of order 2^26 of each prime
 constexpr uint32_t NTT_P0 = 2013265921u;  // 15 2^27 + 1
 constexpr uint32_t NTT_P1 = 1811939329u;  // 27 2^26 + 1

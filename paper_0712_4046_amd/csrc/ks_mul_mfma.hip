@@ -168,7 +168,8 @@ __global__ __launch_bounds__(MFMA_TPB) void mul_mfma_kernel(Launch<MfmaJob> L) {
     __shared__ long long D[MFMA_WAVES][MFMA_LIMBS];
 
     int64_t local;
-    const MfmaJob J = get_job(L, (int64_t)blockIdx.x, local);
+    // the blocks of one product share its digit buffers: keep them on one XCD's L2
+    const MfmaJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 31, g = lane >> 5;
     // block index within the job: (row group, part, residue group), the residue group fastest

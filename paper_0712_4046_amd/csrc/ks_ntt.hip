@@ -161,17 +161,16 @@ __device__ __forceinline__ void lds_transform_any(int lg, uint32_t *buf, int str
 }
 
 // piece m of a: bits [w m, w m + w) of its limbs (zero at or above np pieces or n limbs)
-__device__ __forceinline__ uint32_t piece(const NttJob &J, int64_t m) {
-    if (m >= J.np) return 0u;
-    const int64_t bit = (int64_t)J.w * m;
-    const int64_t q = bit >> 5;
-    const int sh = (int)(bit & 31);
-    const uint32_t lo = q < J.na ? ldg(J.a + q) : 0u;
-    const uint32_t hi = q + 1 < J.na ? ldg(J.a + q + 1) : 0u;
-    return (uint32_t)(((((uint64_t)hi << 32) | lo) >> sh) & ((1ull << J.w) - 1ull));
+__device__ __forceinline__ uint32_t piece_of(uint32_t lo, uint32_t hi, int sh, int w) {
+    return (uint32_t)(((((uint64_t)hi << 32) | lo) >> sh) & ((1ull << w) - 1ull));
 }
 
 __device__ __forceinline__ uint32_t bitrev(uint32_t r, int bits) { return __builtin_bitreverse32(r) >> (32 - bits); }
+
+// Every thread owns elements tid + NTT_TPB i (i < EPT) of the block; their global loads are
+// issued CH at a time before any is used (a rolled loop waits for each load in turn).
+constexpr int EPT = NTT_BLOCK / NTT_TPB;
+constexpr int CH = 16;
 
 // ---- the four steps ---------------------------------------------------------------------------
 
@@ -181,24 +180,67 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L)
     int64_t local;
     const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
-    const int C = NTT_BLOCK >> k1, S = (1 << k1) + 1;  // columns, LDS stride of a column
+    const int lc = 13 - k1, C = 1 << lc, S = (1 << k1) + 1;  // columns, LDS stride of a column
     const int gl = k - 13;  // log2 of the blocks of one prime (a power of two: no division)
     const int q = (int)(local >> gl);
     const int64_t c0 = (local & (((int64_t)1 << gl) - 1)) * C;
     const NttPrime P = ntt_prime(q);
     load_twiddles<false>(tw, q, k1, P);
-    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
-        const int c = e & (C - 1), n1 = e >> (13 - k1);
-        buf[c * S + n1] = piece(J, ((int64_t)n1 << k2) + c0 + c);
+    const int t = threadIdx.x;
+#pragma unroll 1
+    for (int i0 = 0; i0 < EPT; i0 += CH) {
+        uint32_t lo[CH], hi[CH];
+        int sh[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int e = t + (i0 + i) * NTT_TPB;
+            const int64_t m = ((int64_t)(e >> lc) << k2) + c0 + (e & (C - 1));
+            const int64_t bit = (int64_t)J.w * m;
+            const int64_t w0 = bit >> 5;
+            sh[i] = (int)(bit & 31);
+            const bool in = m < J.np;
+            lo[i] = in && w0 < J.na ? ldg(J.a + w0) : 0u;
+            hi[i] = in && w0 + 1 < J.na ? ldg(J.a + w0 + 1) : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int e = t + (i0 + i) * NTT_TPB;
+            buf[(e & (C - 1)) * S + (e >> lc)] = piece_of(lo[i], hi[i], sh[i], J.w);
+        }
     }
     __syncthreads();
     lds_transform_any<false>(k1, buf, S, tw, P);
+    // twiddle w_N^(n2 k1) and store: each thread takes runs of `cols` adjacent columns of one row
+    // (32 elements in all), so the twiddles of a run follow by one multiplication each from its
+    // first (w^((c0 + c) kk) = w^((c0 + c_first) kk) (w^kk)^(c - c_first)) and the run is
+    // stored with 16-byte stores; LDS reads of adjacent threads fall on adjacent rows
     uint32_t *x = J.x + ((int64_t)q << k);
-    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
-        const int c = e & (C - 1), r = e >> (13 - k1);
-        const int64_t n2 = c0 + c;
-        const uint32_t ex = (uint32_t)((n2 * (int64_t)bitrev((uint32_t)r, k1)) << (NTT_ROOT_LOG - k));
-        stg(x + ((int64_t)r << k2) + n2, mmul(buf[c * S + r], root_pow(q, ex, P), P));
+    const int lcols = lc < 5 ? lc : 5;              // log2 of the run length (columns)
+    const int cols = 1 << lcols;
+    const int runs_per_row = C >> lcols;            // threads sharing a row
+    const int rows_per_thread = EPT >> lcols;     // runs per thread
+    const int sh = NTT_ROOT_LOG - k;
+#pragma unroll 1
+    for (int rr = 0; rr < rows_per_thread; ++rr) {
+        const int run = rr * NTT_TPB + t;           // adjacent threads, adjacent runs (rows)
+        const int r = run / runs_per_row;
+        const int cf = (run - r * runs_per_row) << lcols;
+        const uint32_t kk = bitrev((uint32_t)r, k1);
+        uint32_t w = root_pow(q, (uint32_t)(((c0 + cf) * (int64_t)kk) << sh) & ((1u << NTT_ROOT_LOG) - 1u), P);
+        const uint32_t g = root_pow(q, (uint32_t)(((int64_t)kk) << sh), P);
+        uint32_t *dst = x + ((int64_t)r << k2) + c0 + cf;
+        for (int c4 = 0; c4 < cols; c4 += 4) {
+            u32x4 v;
+            v.x = mmul(buf[(cf + c4) * S + r], w, P);
+            w = mmul(w, g, P);
+            v.y = mmul(buf[(cf + c4 + 1) * S + r], w, P);
+            w = mmul(w, g, P);
+            v.z = mmul(buf[(cf + c4 + 2) * S + r], w, P);
+            w = mmul(w, g, P);
+            v.w = mmul(buf[(cf + c4 + 3) * S + r], w, P);
+            w = mmul(w, g, P);
+            *(__attribute__((address_space(1))) u32x4 *)(dst + c4) = v;
+        }
     }
 }
 
@@ -214,10 +256,19 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_rows_kernel(Launch<NttJob> L)
     const NttPrime P = ntt_prime(q);
     load_twiddles<false>(tw, q, k2, P);
     uint32_t *x = J.x + ((int64_t)q << k) + base;
-    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) buf[e] = ldg(x + e);
+    const int t = threadIdx.x;
+#pragma unroll 1
+    for (int i0 = 0; i0 < EPT; i0 += CH) {
+        uint32_t v[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) v[i] = ldg(x + t + (i0 + i) * NTT_TPB);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) buf[t + (i0 + i) * NTT_TPB] = v[i];
+    }
     __syncthreads();
     lds_transform_any<false>(k2, buf, 1 << k2, tw, P);
-    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) stg(x + e, buf[e]);
+#pragma unroll 8
+    for (int i = 0; i < EPT; ++i) stg(x + t + i * NTT_TPB, buf[t + i * NTT_TPB]);
 }
 
 __global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L) {
@@ -234,17 +285,40 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L)
     load_twiddles<true>(tw, q, k2, P);
     uint32_t *x = J.x + ((int64_t)q << k) + base;
     const uint32_t *y = J.y + ((int64_t)q << k) + base;
-    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) buf[e] = mmul(ldg(x + e), ldg(y + e), P);  // A B R^-1
+    const int t = threadIdx.x;
+#pragma unroll 1
+    for (int i0 = 0; i0 < EPT; i0 += CH) {
+        uint32_t u[CH], v[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            u[i] = ldg(x + t + (i0 + i) * NTT_TPB);
+            v[i] = ldg(y + t + (i0 + i) * NTT_TPB);
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) buf[t + (i0 + i) * NTT_TPB] = mmul(u[i], v[i], P);  // A B R^-1
+    }
     __syncthreads();
     lds_transform_any<true>(k2, buf, 1 << k2, tw, P);
     // inverse twiddle w_N^-(n2 k1) and the scale R / N (the pointwise product left R^-1):
     // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N
     const uint32_t K = q == 0 ? J.kscale[0] : J.kscale[1];  // (a dynamic index would copy the job to scratch)
-    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
-        const int64_t r = r0 + (e >> k2), n2 = e & ((1 << k2) - 1);
-        const uint32_t ex = (uint32_t)((n2 * (int64_t)bitrev((uint32_t)r, k1)) << (NTT_ROOT_LOG - k));
-        const uint32_t T = mmul(root_pow_inv(q, ex, P), K, P);
-        stg(x + e, mmul(buf[e], T, P));
+#pragma unroll 1
+    for (int i0 = 0; i0 < EPT; i0 += CH) {
+        uint32_t a[CH], b[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int e = t + (i0 + i) * NTT_TPB;
+            const int64_t r = r0 + (e >> k2), n2 = e & ((1 << k2) - 1);
+            const uint32_t ex = (uint32_t)((n2 * (int64_t)bitrev((uint32_t)r, k1)) << (NTT_ROOT_LOG - k));
+            const uint32_t ei = (uint32_t)((1u << NTT_ROOT_LOG) - ex) & ((1u << NTT_ROOT_LOG) - 1u);
+            a[i] = ntt_tab[q][0][ei >> (NTT_ROOT_LOG / 2)];
+            b[i] = ntt_tab[q][1][ei & (NTT_TAB - 1)];
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int e = t + (i0 + i) * NTT_TPB;
+            stg(x + e, mmul(buf[e], mmul(mmul(a[i], b[i], P), K, P), P));
+        }
     }
 }
 
@@ -254,23 +328,36 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L)
     int64_t local;
     const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
-    const int C = NTT_BLOCK >> k1, S = (1 << k1) + 1;
+    const int lc = 13 - k1, C = 1 << lc, S = (1 << k1) + 1;
     const int gl = k - 13;
     const int q = (int)(local >> gl);
     const int64_t c0 = (local & (((int64_t)1 << gl) - 1)) * C;
     const NttPrime P = ntt_prime(q);
     load_twiddles<true>(tw, q, k1, P);
     uint32_t *x = J.x + ((int64_t)q << k);
-    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
-        const int c = e & (C - 1), r = e >> (13 - k1);
-        buf[c * S + r] = ldg(x + ((int64_t)r << k2) + c0 + c);
+    const int t = threadIdx.x;
+#pragma unroll 1
+    for (int i0 = 0; i0 < EPT; i0 += CH) {
+        uint32_t v[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int e = t + (i0 + i) * NTT_TPB;
+            v[i] = ldg(x + ((int64_t)(e >> lc) << k2) + c0 + (e & (C - 1)));
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int e = t + (i0 + i) * NTT_TPB;
+            buf[(e & (C - 1)) * S + (e >> lc)] = v[i];
+        }
     }
     __syncthreads();
     lds_transform_any<true>(k1, buf, S, tw, P);
     // the residues of terms N2 n1 + n2 in natural order, in place (the block's columns hold
     // exactly the positions it read)
-    for (int e = threadIdx.x; e < NTT_BLOCK; e += NTT_TPB) {
-        const int c = e & (C - 1), n1 = e >> (13 - k1);
+#pragma unroll 8
+    for (int i = 0; i < EPT; ++i) {
+        const int e = t + i * NTT_TPB;
+        const int c = e & (C - 1), n1 = e >> lc;
         stg(x + ((int64_t)n1 << k2) + c0 + c, buf[c * S + n1]);
     }
 }

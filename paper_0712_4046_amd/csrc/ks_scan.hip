@@ -44,7 +44,10 @@ __global__ __launch_bounds__(SCAN_TPB) void pack_anchor_kernel(Launch<PackJob> L
         const PackJob J = get_job(Lp, (int64_t)blockIdx.x, local);
         pack_block<SCAN_TPB, IPT>(J, local, ctl_of(Lp));
     } else {
-        const AnchorJob J = get_job(La, (int64_t)blockIdx.x - Lp.total_blocks, local);
+        // a product's anchors re-read its inputs: keep them on one XCD (xcd_block); anchor
+        // block a runs on XCD (total pack blocks + a) mod 8, so the grouping is shifted alike
+        const int64_t a = (int64_t)blockIdx.x - Lp.total_blocks;
+        const AnchorJob J = get_job(La, xcd_block(a, La.total_blocks), local);
         anchor_block<W>(J, local);
     }
 }
