@@ -17,6 +17,11 @@ first), so f = sum_i f_i(x) y^i; the product h has 2 L_y - 1 rows of 2 L_x - 1 c
                  (Section 2.3; needs 2 invertible, p odd)
   four        -- y = +-x^N, +-x^-N, N = ceil(L_x / 2), four products, halving, then the
                  Section 2.2 gluing on the even and the odd parts at x^(2N) (Section 2.4)
+  cplx        -- y = x^M, -x^M, i x^M over R[i], M = ceil(L_x / 2): five products, the rows
+                 read off by residue mod 4 (Section 2.5; p odd)
+  cube        -- y = +-x^M, +-w x^M over R[w] (w a primitive cube root of unity),
+                 M = ceil(L_x / 3): eight products, the rows read off by residue mod 6
+                 (Section 2.5; 6 invertible)
 
 Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` use this
 module.  The variants follow the paper's steps in its order; the tests pin ``mul_direct`` to
@@ -182,7 +187,137 @@ def four(f, g, p: int) -> list:
     return h
 
 
-VARIANTS = {"ks1": std, "recip2": recip, "neg2": neg, "ks4": four}
+# ---- Section 2.5: evaluation points in an extension of R -----------------------------------------
+# Elements of S = R[i] (i^2 = -1) or S = R[w] (w^2 + w + 1 = 0) are pairs (a, b) = a + b i or
+# a + b w; a polynomial over S is the pair of its two coefficient lists in R[x].
+
+def _cmul(u, v, p):
+    """(a + b i)(c + d i) in R[i]."""
+    a, b = u
+    c, d = v
+    return ((a * c - b * d) % p, (a * d + b * c) % p)
+
+
+def _wmul(u, v, p):
+    """(a + b w)(c + d w) in R[w], w^2 = -1 - w."""
+    a, b = u
+    c, d = v
+    return ((a * c - b * d) % p, (a * d + b * c - b * d) % p)
+
+
+def substitute_ext(f, m: int, z, mul, p: int):
+    """f(x, z x^M) for z in S: sum_i f_i(x) z^i x^(i M), as the pair (real part, other part)
+    of polynomials in R[x] of length M (L_y - 1) + L_x."""
+    f = _rows(f)
+    ly, lx = len(f), len(f[0])
+    re, im = [0] * (m * (ly - 1) + lx), [0] * (m * (ly - 1) + lx)
+    zi = (1, 0)
+    for i in range(ly):
+        for c, v in enumerate(f[i]):
+            re[i * m + c] += zi[0] * v
+            im[i * m + c] += zi[1] * v
+        zi = mul(zi, z, p)
+    return [v % p for v in re], [v % p for v in im]
+
+
+def _addp(a, b, p):
+    return [(x + y) % p for x, y in zip(a, b)]
+
+
+def _subp(a, b, p):
+    return [(x - y) % p for x, y in zip(a, b)]
+
+
+def cplx(f, g, p: int) -> list:
+    """Section 2.5, complex points: M = ceil(L_x / 2), S = R[i]; h evaluated at y = x^M, -x^M
+    (products in R[x]) and i x^M (a product in S[x], three products in R[x]: ac, bd and
+    (a + b)(c + d)).  The value at -i x^M is the conjugate of the one at i x^M, so the four
+    values are h at the fourth roots of unity times x^M; their inverse transform of length 4
+    gives A_r = sum over rows j = r (mod 4) of h_j x^(j M), whose terms do not overlap (4 M >=
+    2 L_x), and h_j is read off A_(j mod 4) at x^(j M).  Five products in R[x]; needs 2
+    invertible (p odd)."""
+    ly, lx = len(f), len(f[0])
+    m = (lx + 1) // 2
+    one, mone, ii = (1, 0), (p - 1, 0), (0, 1)
+    Fp, _ = substitute_ext(f, m, one, _cmul, p)
+    Gp, _ = substitute_ext(g, m, one, _cmul, p)
+    Fm, _ = substitute_ext(f, m, mone, _cmul, p)
+    Gm, _ = substitute_ext(g, m, mone, _cmul, p)
+    Fa, Fb = substitute_ext(f, m, ii, _cmul, p)
+    Ga, Gb = substitute_ext(g, m, ii, _cmul, p)
+    H1 = pmul(Fp, Gp, p)
+    H2 = pmul(Fm, Gm, p)
+    ac, bd = pmul(Fa, Ga, p), pmul(Fb, Gb, p)
+    ad_bc = _subp(_subp(pmul(_addp(Fa, Fb, p), _addp(Ga, Gb, p), p), ac, p), bd, p)
+    re, im = _subp(ac, bd, p), ad_bc  # h(x, i x^M) = re + i im
+    q = pow(4, -1, p)
+    A = [[(h1 + h2 + 2 * r) * q % p for h1, h2, r in zip(H1, H2, re)],
+         [(h1 - h2 + 2 * t) * q % p for h1, h2, t in zip(H1, H2, im)],
+         [(h1 + h2 - 2 * r) * q % p for h1, h2, r in zip(H1, H2, re)],
+         [(h1 - h2 - 2 * t) * q % p for h1, h2, t in zip(H1, H2, im)]]
+    for a in A:
+        a += [0] * ((2 * ly) * m + 2 * lx)
+    return [A[j % 4][j * m:j * m + 2 * lx - 1] for j in range(2 * ly - 1)]
+
+
+def cube(f, g, p: int) -> list:
+    """Section 2.5, cube roots of unity: M = ceil(L_x / 3), S = R[w] with w^2 + w + 1 = 0; h
+    evaluated at y = x^M, -x^M (products in R[x]) and w x^M, -w x^M (products in S[x], three
+    products in R[x] each).  With z = 1 + w, a primitive sixth root of unity (z^2 = w,
+    z^3 = -1), these are h at z^0, z^3, z^2, z^5 times x^M; the conjugation w -> w^2 of S gives
+    the values at z^4 and z^1.  The inverse transform of length 6 gives A_r = sum over rows
+    j = r (mod 6) of h_j x^(j M) (non-overlapping: 6 M >= 2 L_x), whose second component
+    vanishes, and h_j is read off A_(j mod 6) at x^(j M).  Eight products in R[x], each about a
+    sixth of the standard substitution's; needs 6 invertible."""
+    ly, lx = len(f), len(f[0])
+    m = (lx + 2) // 3
+    w, mw = (0, 1), (0, p - 1)
+
+    def val(z):  # h(x, z x^M) as a pair of polynomials, through three products in R[x]
+        Fa, Fb = substitute_ext(f, m, z, _wmul, p)
+        Ga, Gb = substitute_ext(g, m, z, _wmul, p)
+        ac, bd = pmul(Fa, Ga, p), pmul(Fb, Gb, p)
+        s = pmul(_addp(Fa, Fb, p), _addp(Ga, Gb, p), p)
+        # (a + b w)(c + d w) = (ac - bd) + (ad + bc - bd) w, ad + bc = s - ac - bd
+        return _subp(ac, bd, p), [(x - y - 2 * z2) % p for x, y, z2 in zip(s, ac, bd)]
+
+    Fp, _ = substitute_ext(f, m, (1, 0), _wmul, p)
+    Gp, _ = substitute_ext(g, m, (1, 0), _wmul, p)
+    Fm, _ = substitute_ext(f, m, (p - 1, 0), _wmul, p)
+    Gm, _ = substitute_ext(g, m, (p - 1, 0), _wmul, p)
+    n = 2 * (m * (ly - 1) + lx) - 1
+    V = [None] * 6
+    V[0] = (pmul(Fp, Gp, p), [0] * n)
+    V[3] = (pmul(Fm, Gm, p), [0] * n)
+    V[2] = val(w)
+    V[5] = val(mw)
+
+    def conj(u):  # a + b w -> a + b w^2 = (a - b) - b w
+        return ([(a - b) % p for a, b in zip(*u)], [(-b) % p for b in u[1]])
+
+    V[4], V[1] = conj(V[2]), conj(V[5])
+    z = (1, 1)  # 1 + w
+    zinv = (0, p - 1)  # z^5 = -w
+    zp = [(1, 0)]
+    for _ in range(5):
+        zp.append(_wmul(zp[-1], zinv, p))  # z^(-k)
+    six = pow(6, -1, p)
+    A = []
+    for r in range(6):
+        acc_a, acc_b = [0] * n, [0] * n
+        for k in range(6):
+            c = zp[(r * k) % 6]
+            for t in range(n):
+                e = _wmul(c, (V[k][0][t], V[k][1][t]), p)
+                acc_a[t] += e[0]
+                acc_b[t] += e[1]
+        assert all(v % p == 0 for v in acc_b), "the inverse transform left a second component"
+        A.append([v * six % p for v in acc_a] + [0] * ((2 * ly) * m + 2 * lx))
+    assert _wmul(z, zinv, p) == (1, 0)
+    return [A[j % 6][j * m:j * m + 2 * lx - 1] for j in range(2 * ly - 1)]
+
+
+VARIANTS = {"ks1": std, "recip2": recip, "neg2": neg, "ks4": four, "cplx": cplx, "cube": cube}
 
 
 def random_poly2(rng: np.random.Generator, ly: int, lx: int, p: int) -> list:

@@ -64,6 +64,8 @@ def test_coeff_direct_matches():
 @pytest.mark.parametrize("p", ODD)
 @pytest.mark.parametrize("ly,lx", [(1, 1), (1, 4), (4, 1), (2, 2), (2, 3), (3, 5), (5, 8), (7, 7), (8, 3)])
 def test_variants_equal_definition(variant, p, ly, lx):
+    if variant == "cube" and p % 3 == 0:
+        pytest.skip("the cube-root points divide by 6 (Section 2.5): 3 must be invertible")
     f, g = rnd(10 + ly, ly, lx, p), rnd(20 + lx, ly, lx, p)
     assert poly2.VARIANTS[variant](f, g, p) == poly2.mul_direct(f, g, p)
 
@@ -93,3 +95,33 @@ def test_planted_mistakes_are_caught(monkeypatch):
     with monkeypatch.context() as m:  # no alternating sign at -x^N (Section 2.3)
         m.setattr(poly2, "substitute", lambda ff, n, s, r, q: real(ff, n, 1, r, q))
         assert poly2.neg(f, g, p) != want
+
+
+def test_extension_points_planted_mistakes(monkeypatch):
+    # Section 2.5: a wrong product in the extension ring or a wrong conjugation must break the
+    # reconstruction (the cube-root variant also checks that the second components vanish)
+    p = 2**61 - 1
+    f, g = rnd(40, 5, 7, p), rnd(41, 5, 7, p)
+    want = poly2.mul_direct(f, g, p)
+    assert poly2.cplx(f, g, p) == want and poly2.cube(f, g, p) == want
+    with monkeypatch.context() as m:  # i^2 = +1 instead of -1
+        m.setattr(poly2, "_cmul", lambda u, v, q: ((u[0] * v[0] + u[1] * v[1]) % q, (u[0] * v[1] + u[1] * v[0]) % q))
+        assert poly2.cplx(f, g, p) != want
+    with monkeypatch.context() as m:  # w^2 = -1 (the complex rule) instead of -1 - w
+        m.setattr(poly2, "_wmul", lambda u, v, q: ((u[0] * v[0] - u[1] * v[1]) % q, (u[0] * v[1] + u[1] * v[0]) % q))
+        with pytest.raises(AssertionError):
+            assert poly2.cube(f, g, p) == want
+
+
+def test_extension_points_fewer_longer_products():
+    # the sizes Section 2.5 states: complex points multiply polynomials of length
+    # ceil(L_x / 2)(L_y - 1) + L_x (five of them); cube roots of length ceil(L_x / 3)(L_y - 1)
+    # + L_x (eight), a sixth of the standard substitution's length for large L_x
+    p = 97
+    ly, lx = 6, 30
+    f = rnd(42, ly, lx, p)
+    a, _ = poly2.substitute_ext(f, (lx + 1) // 2, (0, 1), poly2._cmul, p)
+    b, _ = poly2.substitute_ext(f, (lx + 2) // 3, (0, 1), poly2._wmul, p)
+    std_len = len(poly2.substitute(f, 2 * lx - 1, 1, False, p))
+    assert len(a) == 15 * (ly - 1) + lx and len(b) == 10 * (ly - 1) + lx
+    assert std_len == (2 * lx - 1) * (ly - 1) + lx
