@@ -55,6 +55,11 @@ extern "C" {
                                   never chosen by KS_VARIANT_AUTO (same products as NEG2 plus the
                                   reconstruction, which the paper also finds slower)            */
 #define KS_VARIANT_KS4 4       /* Section 3.4: points +-2^N, +-2^-N                          */
+#define KS_P2_COMPLEX 5        /* ks_mul_poly2 only (Section 2.5): y = x^M, -x^M, i x^M over R[i],
+                                  M = ceil(len_x / 2): five products in (Z/pZ)[x]            */
+#define KS_P2_CUBE 6           /* ks_mul_poly2 only (Section 2.5): y = +-x^M, +-w x^M over R[w]
+                                  (w a primitive cube root of unity), M = ceil(len_x / 3): eight
+                                  products; needs p not divisible by 3                      */
 #define KS_VARIANT_MASK 0xff
 #define KS_SIGNED 0x100        /* coefficients are signed two's complement                   */
 #define KS_ENGINE_VALU 0x1000  /* force the vector-ALU 32x32-bit limb multiplier            */
@@ -152,8 +157,11 @@ int ks_mul_mod(const uint64_t *f, const uint64_t *g, int64_t len_f, int64_t len_
  *           (y = x^N and x^-N, N = len_x, two products of length len_x len_y; Section 2.2),
  *           KS_VARIANT_NEG2 (y = +-x^N, N = len_x; Section 2.3), KS_VARIANT_KS4 (y = +-x^N,
  *           +-x^-N, N = ceil(len_x / 2), four products of length N (len_y - 1) + len_x;
- *           Section 2.4), KS_VARIANT_AUTO (four points when len_x >= 2 and len_x len_y >=
- *           24576, else the standard substitution)
+ *           Section 2.4), KS_P2_COMPLEX, KS_P2_CUBE (Section 2.5's points in an extension of
+ *           R: five products of length ceil(len_x / 2)(len_y - 1) + len_x, or eight of
+ *           ceil(len_x / 3)(len_y - 1) + len_x; rows read off by residue mod 4 or 6),
+ *           KS_VARIANT_AUTO (four points when len_x >= 2 and len_x len_y >= 24576, else the
+ *           standard substitution)
  *   inner   KS_VARIANT_* | optional KS_ENGINE_* for the products in (Z/pZ)[x], which run as
  *           ks_mul_mod does (KS_SIGNED is rejected)
  *   h       device, (2 len_y - 1) rows of (2 len_x - 1) uint64 residues in [0, p)
@@ -278,8 +286,7 @@ int ks_plan(int64_t len_f, int64_t len_g, int32_t coeff_bits, int32_t variant, k
  * "pack" (with the anchors it carries), "mul_valu", "mul_mfma", "normalize", "anchor",
  * "recon", "finish", "extract", "digitize", "p2_eval", "p2_recon" (bivariate evaluation and
  * read-off or gluing), "kara" (the Karatsuba split and combination of a batch),
- * "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "ntt_join" (the steps of the
- * transform engine).  Returns KS_EINVAL for an unknown name.
+ * "ntt_fwd_cols", "ntt_rows", "ntt_inv_cols", "ntt_join" (the steps of the transform engine).  Returns KS_EINVAL for an unknown name.
  */
 int ks_profile_enable(int32_t on);
 int ks_profile_read(const char *name, int64_t *launches, double *total_ms);

@@ -44,6 +44,12 @@ static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", 
                                          "KS_NTT_MIN_LIMBS"};
 static std::mutex g_tune_mu;
 static std::map<std::string, int64_t> g_tune;
+static uint64_t g_tune_gen = 0;  // bumped by every ks_tune_set / ks_tune_reset
+
+uint64_t tune_generation() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune_gen;
+}
 
 static bool known_tunable(const char *name) {
     for (const char *k : k_tunables)
@@ -563,7 +569,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
             j.w = m.ntt_w;
             j.kscale[0] = ntt_scale(0, k);
             j.kscale[1] = ntt_scale(1, k);
-            const int64_t per_prime = (int64_t)1 << (k - 13);  // blocks of one prime in a step
+            const int64_t per_prime = (int64_t)1 << (k - 13);  // column blocks of one prime
             for (int side = 0; side < 2; ++side) {
                 NttJob f = j;
                 f.a = ops(G.packs[side ? m.fb : m.fa].op_off);
@@ -573,15 +579,14 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
                 f.nblocks = 2 * per_prime;
                 f.block0 = next_block(JL.ntt_f1);
                 JL.ntt_f1.push_back(f);
-                f.block0 = next_block(JL.ntt_f2);
-                JL.ntt_f2.push_back(f);
             }
             NttJob inv = j;
             inv.x = nttw(m.ntt_xa);
             inv.y = nttw(m.ntt_xb);
+            inv.nblocks = 4 * per_prime;  // row blocks take half as many residues of each operand
+            inv.block0 = next_block(JL.ntt_rows);
+            JL.ntt_rows.push_back(inv);
             inv.nblocks = 2 * per_prime;
-            inv.block0 = next_block(JL.ntt_i2);
-            JL.ntt_i2.push_back(inv);
             inv.block0 = next_block(JL.ntt_i1);
             JL.ntt_i1.push_back(inv);
             NttJoinJob jj;
@@ -814,11 +819,10 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.ntt_f1.empty()) {
-        const std::vector<NttJob> *lists[4] = {&JL.ntt_f1, &JL.ntt_f2, &JL.ntt_i2, &JL.ntt_i1};
-        const DevList *tabs[4] = {T ? &T->ntt_f1 : nullptr, T ? &T->ntt_f2 : nullptr, T ? &T->ntt_i2 : nullptr,
-                                  T ? &T->ntt_i1 : nullptr};
-        static const char *names[4] = {"ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols"};
-        for (int st = 0; st < 4; ++st) {
+        const std::vector<NttJob> *lists[3] = {&JL.ntt_f1, &JL.ntt_rows, &JL.ntt_i1};
+        const DevList *tabs[3] = {T ? &T->ntt_f1 : nullptr, T ? &T->ntt_rows : nullptr, T ? &T->ntt_i1 : nullptr};
+        static const char *names[3] = {"ntt_fwd_cols", "ntt_rows", "ntt_inv_cols"};
+        for (int st = 0; st < 3; ++st) {
             auto L = make_launch(*lists[st], tabs[st], env, 0);
             err = timed(names[st], s, [&] { return launch_ntt_stage(st, L, s); });
             if (err != hipSuccess) return KS_EHIP;
@@ -894,7 +898,7 @@ struct Pool {
     // (length, count, modulus, inner variant) repeats
     ks_batch_plan *p2plan = nullptr;
     int64_t p2_le = 0, p2_k = 0;
-    uint64_t p2_p = 0;
+    uint64_t p2_p = 0, p2_gen = 0;  // p2_gen: the tunables' generation the plan was made under
     int32_t p2_inner = -1;
 };
 static std::mutex g_pool_mu;
@@ -1123,8 +1127,15 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
         case KS_VARIANT_RECIP2: k = 2; n = len_x; break;            // Section 2.2
         case KS_VARIANT_NEG2: k = 2; n = len_x; break;              // Section 2.3
         case KS_VARIANT_KS4: k = 4; n = (len_x + 1) / 2; break;     // Section 2.4
+        case KS_P2_COMPLEX: k = 5; n = (len_x + 1) / 2; break;      // Section 2.5, y = x^M, -x^M, i x^M
+        case KS_P2_CUBE:                                            // Section 2.5, y = +-x^M, +-w x^M
+            if (p % 3 == 0) return KS_EINVAL;                       // divides by 6
+            k = 8;
+            n = (len_x + 2) / 3;
+            break;
         default: return KS_EINVAL;
     }
+    const bool ext = v == KS_P2_COMPLEX || v == KS_P2_CUBE;
     const int64_t le = n * (len_y - 1) + len_x, lh = 2 * le - 1;
     if (le > (int64_t)1 << 30) return KS_EINVAL;
     const int bits = bitlen_u64(p - 1);
@@ -1140,7 +1151,7 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
     // limbs) from the stage, evaluations first, then the products.  A single product keeps the
     // single-product pipeline (reconstruction segments cut for latency: 1.16 against 1.22 ms)
     // unless it is long enough for the batch plan's Karatsuba split.
-    ks_desc d[4];
+    ks_desc d[8];
     memset(d, 0, sizeof(d));
     for (int q = 0; q < k; ++q) {
         d[q].f_off = (uint64_t)(2 * q * le);
@@ -1153,8 +1164,9 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
         d[q].mod_p = p;
     }
     const bool batched = k > 1 || karatsuba_splits(d, k, inner);
-    if (batched &&
-        (!pl->p2plan || pl->p2_le != le || pl->p2_k != k || pl->p2_p != p || pl->p2_inner != inner)) {
+    const uint64_t gen = tune_generation();
+    if (batched && (!pl->p2plan || pl->p2_le != le || pl->p2_k != k || pl->p2_p != p || pl->p2_inner != inner ||
+                    pl->p2_gen != gen)) {
         if (pl->p2plan) {
             if (hipStreamSynchronize(s) != hipSuccess) return KS_EHIP;  // its tables may be in use
             ks_batch_plan_destroy(pl->p2plan);
@@ -1166,10 +1178,11 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
         pl->p2_k = k;
         pl->p2_p = p;
         pl->p2_inner = inner;
+        pl->p2_gen = gen;
     }
     // stage: 2k evaluations, k products, chunk sums of up to two gluings, the batch workspace
     const int64_t m = v == KS_VARIANT_KS4 ? 2 * n : n, count = v == KS_VARIANT_KS4 ? len_y : 2 * len_y - 1;
-    const int64_t nchunks = cdiv((count + 1) / 2, P2_CHUNK);
+    const int64_t nchunks = ext ? 0 : cdiv((count + 1) / 2, P2_CHUNK);
     const int64_t words = 2 * k * le + k * lh + 2 * nchunks * 4 * m;
     const size_t ws_off = ((size_t)words * 8 + 255) / 256 * 256;
     const size_t need = ws_off + (batched ? ks_batch_plan_workspace_bytes(pl->p2plan) : 0);
@@ -1186,6 +1199,67 @@ int ks_mul_poly2(const uint64_t *f, const uint64_t *g, int64_t len_x, int64_t le
         pl->stage_bytes = need;
     }
     uint64_t *ev = reinterpret_cast<uint64_t *>(pl->stage), *prod = ev + 2 * k * le, *sums = prod + k * lh;
+    if (ext) {
+        // the evaluations: the points' components as small integer weights of the rows
+        // (period 4 for i^row, 3 for w^row, 6 for (-w)^row), and the sums of the two components
+        // that the ring products' middle terms multiply
+        P2ExtEval E;
+        memset(&E, 0, sizeof(E));
+        E.f = f;
+        E.g = g;
+        E.out = ev;
+        E.lx = len_x;
+        E.ly = len_y;
+        E.m = n;
+        E.le = le;
+        E.p = p;
+        E.np = k;
+        E.devstat = pl->ctl.devstat;
+        static const int8_t cplx[5][4] = {{1, 1, 1, 1},     // y = x^M
+                                          {1, -1, 1, -1},   // y = -x^M
+                                          {1, 0, -1, 0},    // real part of i^row
+                                          {0, 1, 0, -1},    // imaginary part
+                                          {1, 1, -1, -1}};  // their sum
+        static const int8_t cube[8][6] = {{1, 1, 1, 1, 1, 1},       // y = x^M
+                                          {1, -1, 1, -1, 1, -1},    // y = -x^M
+                                          {1, 0, -1, 1, 0, -1},     // w^row = a + b w: a
+                                          {0, 1, -1, 0, 1, -1},     //                  b
+                                          {1, 1, -2, 1, 1, -2},     //                  a + b
+                                          {1, 0, -1, -1, 0, 1},     // (-w)^row: a
+                                          {0, -1, -1, 0, 1, 1},     //           b
+                                          {1, -1, -2, -1, 1, 2}};   //           a + b
+        E.period = v == KS_P2_COMPLEX ? 4 : 6;
+        for (int q = 0; q < k; ++q)
+            for (int i = 0; i < E.period; ++i) E.coef[q][i] = v == KS_P2_COMPLEX ? cplx[q][i] : cube[q][i];
+        if (timed("p2_eval", s, [&] { return launch_p2_ext_eval(E, s); }) != hipSuccess) return KS_EHIP;
+        rc = batch_run_into(pl->p2plan, reinterpret_cast<const uint32_t *>(pl->stage),
+                            reinterpret_cast<uint32_t *>(pl->stage), pl->stage + ws_off, pl->ctl.devstat, s);
+        if (rc != KS_OK) return rc;
+        P2ExtReadoff R;
+        memset(&R, 0, sizeof(R));
+        R.prod = prod;
+        R.out = h;
+        R.lh = lh;
+        R.rows = 2 * len_y - 1;
+        R.width = 2 * len_x - 1;
+        R.m = n;
+        R.p = p;
+        R.cube = v == KS_P2_CUBE;
+        const uint64_t d4 = v == KS_P2_COMPLEX ? 4 : 6;  // its inverse mod p by Euclid
+        {
+            __int128 t0 = 0, t1 = 1, r0 = (__int128)p, r1 = (__int128)(d4 % p);
+            while (r1 != 0) {
+                const __int128 qq = r0 / r1, t2 = t0 - qq * t1, r2 = r0 - qq * r1;
+                t0 = t1;
+                t1 = t2;
+                r0 = r1;
+                r1 = r2;
+            }
+            R.inv = (uint64_t)(t0 < 0 ? t0 + (__int128)p : t0);
+        }
+        const hipError_t e2 = timed("p2_recon", s, [&] { return launch_p2_ext_readoff(R, s); });
+        return e2 == hipSuccess ? KS_OK : KS_EHIP;
+    }
     P2Eval E;
     memset(&E, 0, sizeof(E));
     E.f = f;
@@ -1290,6 +1364,7 @@ int ks_tune_set(const char *name, int64_t value) {
     if (!name || !known_tunable(name) || value < 0) return KS_EINVAL;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[name] = value;
+    ++g_tune_gen;  // cached plans (the bivariate products') are made again
     return KS_OK;
 }
 
@@ -1307,6 +1382,7 @@ int ks_tune_get(const char *name, int64_t *value) {
 int ks_tune_reset(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
+    ++g_tune_gen;
     return KS_OK;
 }
 
@@ -1326,7 +1402,7 @@ int ks_profile_read(const char *name, int64_t *launches, double *total_ms) {
     if (!name || !launches || !total_ms) return KS_EINVAL;
     static const char *known[] = {"pack",  "mul_valu", "mul_mfma", "normalize", "anchor",  "recon",
                                   "extract", "digitize", "finish",  "p2_eval",   "p2_recon", "kara",
-                                  "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "ntt_join"};
+                                  "ntt_fwd_cols", "ntt_rows", "ntt_inv_cols", "ntt_join"};
     bool ok = false;
     for (const char *k : known) ok = ok || strcmp(k, name) == 0;
     if (!ok) return KS_EINVAL;

@@ -373,7 +373,7 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
     for (auto &j : JL.mul_wave) { sh(j.a); sh(j.b); sh(j.cols); }
     for (auto &j : JL.digit) { sh(j.limbs); sh(j.out); sh(j.zero); }
     for (auto &j : JL.mfma) { sh(j.ad); sh(j.bd); sh(j.cols); }
-    for (auto *nl : {&JL.ntt_f1, &JL.ntt_f2, &JL.ntt_i2, &JL.ntt_i1})
+    for (auto *nl : {&JL.ntt_f1, &JL.ntt_rows, &JL.ntt_i1})
         for (auto &j : *nl) {  // offsets (0 is a valid one); unused fields are never read
             sh(j.a);
             sh(j.x);
@@ -412,8 +412,7 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
     if (!JL.ntt_f1.empty()) rc = ntt_prepare();  // the transforms' root tables on this device
     if (rc == KS_OK) rc = upload(JL.pack, P->T.pack, P->allocs);
     if (rc == KS_OK) rc = upload(JL.ntt_f1, P->T.ntt_f1, P->allocs);
-    if (rc == KS_OK) rc = upload(JL.ntt_f2, P->T.ntt_f2, P->allocs);
-    if (rc == KS_OK) rc = upload(JL.ntt_i2, P->T.ntt_i2, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.ntt_rows, P->T.ntt_rows, P->allocs);
     if (rc == KS_OK) rc = upload(JL.ntt_i1, P->T.ntt_i1, P->allocs);
     if (rc == KS_OK) rc = upload(JL.ntt_join, P->T.ntt_join, P->allocs);
     if (rc == KS_OK) rc = upload(JL.pack_small, P->T.pack_small, P->allocs);

@@ -325,6 +325,32 @@ struct P2Glue {
     uint32_t *devstat;
 };
 
+// Section 2.5's evaluation points in an extension S of R = Z/pZ (S = R[i] or R[w], w a
+// primitive cube root of unity): out holds np polynomials of `le` residues for f, then the same
+// for g; polynomial q is sum_i coef[q][i mod period] f_i(x) x^(i m) with small integer
+// coefficients (the real and second parts of z^i for the points z x^m, and their sums for the
+// ring products' middle terms)
+struct P2ExtEval {
+    const uint64_t *f, *g;
+    uint64_t *out;
+    int64_t lx, ly, m, le;
+    uint64_t p;
+    int32_t np, period;
+    int8_t coef[8][8];
+    uint32_t *devstat;
+};
+
+// Recovery from the products (product q at prod + q lh, lh = 2 le - 1 residues): the inverse
+// transform of length 4 (complex points) or 6 (cube roots) per position, row j of h read off
+// the class j mod 4 (or 6) at x^(j m); `inv` is 4^-1 (or 6^-1) mod p
+struct P2ExtReadoff {
+    const uint64_t *prod;
+    uint64_t *out;
+    int64_t lh, rows, width, m;
+    uint64_t p, inv;
+    int32_t cube, pad;
+};
+
 // One modular product of a batch split at the polynomial level (Karatsuba): f = f0 + x^h f1,
 // g = g0 + x^h g1 with h = ceil(L / 2) (f1, g1 zero-padded to h terms), staged as six arrays
 // of h residues [f0 f1 f0+f1 g0 g1 g0+g1] from residue `sub_in` of the staging arena; the three

@@ -46,13 +46,15 @@ hipError_t launch_finish(const Launch<ChainJob> &L, int nw, hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_digitize(const Launch<DigitJob> &L, hipStream_t s);
 hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, int rt, hipStream_t s);  // rt: tiles per block (4 or 8)
-// one of the four transform steps of integer products on the transform engine: 0 forward
-// columns, 1 forward rows, 2 inverse rows (with the pointwise product), 3 inverse columns
+// one of the transform steps of integer products on the transform engine: 0 forward columns,
+// 1 rows (both operands forward, the pointwise product, inverse), 2 inverse columns
 hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, hipStream_t s);
 hipError_t launch_ntt_join(const Launch<NttJoinJob> &L, hipStream_t s);
 hipError_t launch_p2_eval(const P2Eval &E, hipStream_t s);
 hipError_t launch_p2_readoff(const P2Readoff &R, hipStream_t s);
 hipError_t launch_p2_glue(const P2Glue &G, hipStream_t s);  // two launches (chunk sums, then outputs)
+hipError_t launch_p2_ext_eval(const P2ExtEval &E, hipStream_t s);
+hipError_t launch_p2_ext_readoff(const P2ExtReadoff &R, hipStream_t s);
 // polynomial-level Karatsuba of a batch: `tab` holds `count` KaraProd on the device
 hipError_t launch_kara_split(const KaraProd *tab, int64_t count, int64_t max_h, const uint32_t *in, uint64_t *sub,
                              hipStream_t s);

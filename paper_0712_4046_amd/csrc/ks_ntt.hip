@@ -9,12 +9,14 @@
 // and joined by the Chinese remainder theorem; the planner picks w so that every c_m stays
 // below P0 P1 (2w + log2 min(npa, npb) <= 61), which makes the joined value exact.
 //
-// A transform of length N = N1 N2 runs in four steps (each step one launch over every job):
-//   forward columns  N2 transforms of length N1 over the stride-N2 columns x[N2 n1 + n2],
-//                    then the twiddle w_N^(n2 k1); stored row-wise (row k1, N2 columns)
-//   forward rows     N1 transforms of length N2 over the rows
-//   inverse rows     the pointwise product of the two operands' transforms (Montgomery), the
-//                    inverse row transforms, the inverse twiddle and the scale 1/N
+// A product's transforms of length N = N1 N2 run in three steps (each one launch over every
+// job) and a join:
+//   forward columns  per operand, N2 transforms of length N1 over the stride-N2 columns
+//                    x[N2 n1 + n2], then the twiddle w_N^(n2 k1); stored row-wise (row k1,
+//                    N2 columns)
+//   rows             per product, N1 transforms of length N2 over the rows of both operands,
+//                    their pointwise product (Montgomery), the inverse row transforms, the
+//                    inverse twiddle and the scale 1/N
 //   inverse columns  the inverse column transforms, the residues of the convolution terms
 //                    written in order (in place)
 //   join             the two residues of each term joined by the Chinese remainder theorem,
@@ -22,8 +24,8 @@
 // Forward transforms are decimation in frequency (natural order in, bit-reversed out) and the
 // inverse ones decimation in time (bit-reversed in, natural out), so no step reorders data:
 // rows are kept at their bit-reversed positions and the pointwise product pairs equal positions.
-// Every block transforms NTT_BLOCK elements in LDS: C = NTT_BLOCK / N1 adjacent columns, or
-// R = NTT_BLOCK / N2 rows.
+// A column block transforms NTT_BLOCK elements in LDS (C = NTT_BLOCK / N1 adjacent columns), a
+// row block NTT_BLOCK / 2 elements of each operand (R = NTT_BLOCK / 2 / N2 rows).
 //
 // Arithmetic: residues below P < 2^31 in 32-bit words; products by Montgomery reduction with
 // R = 2^32 (a b R^-1 mod P), twiddles kept in Montgomery form so that multiplying a residue by
@@ -71,10 +73,10 @@ __device__ __forceinline__ void load_twiddles(uint32_t *tw, int q, int lg, NttPr
 // twiddles, tw[j] = w_M^(+-j) R).  Stages go in pairs (radix 4: each thread reads four elements,
 // runs two stages in registers and writes them back), with one radix-2 stage more when LG is odd
 // (last in the forward order, first in the inverse).  Ends with a barrier.
-template <int LG, bool INV>
+template <int LG, bool INV, int NE = NTT_BLOCK>
 __device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, const uint32_t *tw, NttPrime P) {
-    constexpr int NQ = NTT_BLOCK / 4 / NTT_TPB;  // groups of four per thread and pass
-    constexpr int NH = NTT_BLOCK / 2 / NTT_TPB;  // pairs per thread in a radix-2 stage
+    constexpr int NQ = NE / 4 / NTT_TPB;  // groups of four per thread and pass
+    constexpr int NH = NE / 2 / NTT_TPB;  // pairs per thread in a radix-2 stage
     constexpr int PAIRS = LG / 2;
     auto radix2 = [&](int hl) {  // one stage of half-size 2^hl (twiddle index j << (LG-1-hl))
         const int h = 1 << hl, ts = LG - 1 - hl;
@@ -145,18 +147,18 @@ __device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, const u
     }
 }
 
-// the templated transform for a length known only at run time (4 <= lg <= 12)
-template <bool INV>
+// the templated transform for a length known only at run time (6 <= lg <= 12)
+template <bool INV, int NE = NTT_BLOCK>
 __device__ __forceinline__ void lds_transform_any(int lg, uint32_t *buf, int stride, const uint32_t *tw,
                                                   NttPrime P) {
     switch (lg) {
-        case 6: lds_transform<6, INV>(buf, stride, tw, P); break;
-        case 7: lds_transform<7, INV>(buf, stride, tw, P); break;
-        case 8: lds_transform<8, INV>(buf, stride, tw, P); break;
-        case 9: lds_transform<9, INV>(buf, stride, tw, P); break;
-        case 10: lds_transform<10, INV>(buf, stride, tw, P); break;
-        case 11: lds_transform<11, INV>(buf, stride, tw, P); break;
-        default: lds_transform<12, INV>(buf, stride, tw, P); break;
+        case 6: lds_transform<6, INV, NE>(buf, stride, tw, P); break;
+        case 7: lds_transform<7, INV, NE>(buf, stride, tw, P); break;
+        case 8: lds_transform<8, INV, NE>(buf, stride, tw, P); break;
+        case 9: lds_transform<9, INV, NE>(buf, stride, tw, P); break;
+        case 10: lds_transform<10, INV, NE>(buf, stride, tw, P); break;
+        case 11: lds_transform<11, INV, NE>(buf, stride, tw, P); break;
+        default: lds_transform<12, INV, NE>(buf, stride, tw, P); break;
     }
 }
 
@@ -244,50 +246,30 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L)
     }
 }
 
-__global__ __launch_bounds__(NTT_TPB) void ntt_fwd_rows_kernel(Launch<NttJob> L) {
-    __shared__ uint32_t buf[NTT_BLOCK];
-    __shared__ uint32_t tw[2048];
-    int64_t local;
-    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
-    const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
-    const int gl = k - 13;  // log2 of the blocks of one prime: N1 / R
-    const int q = (int)(local >> gl);
-    const int64_t base = (local & (((int64_t)1 << gl) - 1)) * NTT_BLOCK;  // R whole rows, contiguous
-    const NttPrime P = ntt_prime(q);
-    load_twiddles<false>(tw, q, k2, P);
-    uint32_t *x = J.x + ((int64_t)q << k) + base;
-    const int t = threadIdx.x;
-#pragma unroll 1
-    for (int i0 = 0; i0 < EPT; i0 += CH) {
-        uint32_t v[CH];
-#pragma unroll
-        for (int i = 0; i < CH; ++i) v[i] = ldg(x + t + (i0 + i) * NTT_TPB);
-#pragma unroll
-        for (int i = 0; i < CH; ++i) buf[t + (i0 + i) * NTT_TPB] = v[i];
-    }
-    __syncthreads();
-    lds_transform_any<false>(k2, buf, 1 << k2, tw, P);
-#pragma unroll 8
-    for (int i = 0; i < EPT; ++i) stg(x + t + i * NTT_TPB, buf[t + i * NTT_TPB]);
-}
+// The row step of a product: both operands' rows forward, the pointwise product, the inverse
+// row transform, the inverse twiddle and the scale, in one pass over HBM.  A block takes
+// NTT_ROWS_BLOCK residues (R = NTT_ROWS_BLOCK / N2 whole rows) of each operand for one prime.
+constexpr int NTT_ROWS_BLOCK = NTT_BLOCK / 2;
+constexpr int EPT_R = NTT_ROWS_BLOCK / NTT_TPB;
 
-__global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L) {
-    __shared__ uint32_t buf[NTT_BLOCK];
+__global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
+    __shared__ uint32_t bufa[NTT_ROWS_BLOCK];
+    __shared__ uint32_t bufb[NTT_ROWS_BLOCK];
     __shared__ uint32_t tw[2048];
     int64_t local;
     const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
-    const int gl = k - 13;
+    const int gl = k - 12;  // log2 of the blocks of one prime: N / NTT_ROWS_BLOCK
     const int q = (int)(local >> gl);
-    const int64_t base = (local & (((int64_t)1 << gl) - 1)) * NTT_BLOCK;
+    const int64_t base = (local & (((int64_t)1 << gl) - 1)) * NTT_ROWS_BLOCK;  // whole rows, contiguous
     const int64_t r0 = base >> k2;  // first row of the block
     const NttPrime P = ntt_prime(q);
-    load_twiddles<true>(tw, q, k2, P);
+    load_twiddles<false>(tw, q, k2, P);
     uint32_t *x = J.x + ((int64_t)q << k) + base;
     const uint32_t *y = J.y + ((int64_t)q << k) + base;
     const int t = threadIdx.x;
 #pragma unroll 1
-    for (int i0 = 0; i0 < EPT; i0 += CH) {
+    for (int i0 = 0; i0 < EPT_R; i0 += CH) {
         uint32_t u[CH], v[CH];
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
@@ -295,15 +277,29 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L)
             v[i] = ldg(y + t + (i0 + i) * NTT_TPB);
         }
 #pragma unroll
-        for (int i = 0; i < CH; ++i) buf[t + (i0 + i) * NTT_TPB] = mmul(u[i], v[i], P);  // A B R^-1
+        for (int i = 0; i < CH; ++i) {
+            bufa[t + (i0 + i) * NTT_TPB] = u[i];
+            bufb[t + (i0 + i) * NTT_TPB] = v[i];
+        }
     }
     __syncthreads();
-    lds_transform_any<true>(k2, buf, 1 << k2, tw, P);
+    lds_transform_any<false, NTT_ROWS_BLOCK>(k2, bufa, 1 << k2, tw, P);
+    lds_transform_any<false, NTT_ROWS_BLOCK>(k2, bufb, 1 << k2, tw, P);
+    // pointwise A B R^-1 (equal positions: both in the order the forward steps left), then the
+    // inverse twiddles replace the forward ones
+#pragma unroll 4
+    for (int i = 0; i < EPT_R; ++i) {
+        const int e = t + i * NTT_TPB;
+        bufa[e] = mmul(bufa[e], bufb[e], P);
+    }
+    load_twiddles<true>(tw, q, k2, P);  // every thread is past the forward transforms' barrier
+    __syncthreads();
+    lds_transform_any<true, NTT_ROWS_BLOCK>(k2, bufa, 1 << k2, tw, P);
     // inverse twiddle w_N^-(n2 k1) and the scale R / N (the pointwise product left R^-1):
     // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N
     const uint32_t K = q == 0 ? J.kscale[0] : J.kscale[1];  // (a dynamic index would copy the job to scratch)
 #pragma unroll 1
-    for (int i0 = 0; i0 < EPT; i0 += CH) {
+    for (int i0 = 0; i0 < EPT_R; i0 += CH) {
         uint32_t a[CH], b[CH];
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
@@ -317,7 +313,7 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_rows_kernel(Launch<NttJob> L)
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             const int e = t + (i0 + i) * NTT_TPB;
-            stg(x + e, mmul(buf[e], mmul(mmul(a[i], b[i], P), K, P), P));
+            stg(x + e, mmul(bufa[e], mmul(mmul(a[i], b[i], P), K, P), P));
         }
     }
 }
@@ -464,9 +460,8 @@ hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, hipStream_t s) {
     const dim3 g((unsigned)L.total_blocks), b(NTT_TPB);
     switch (stage) {
         case 0: ks_launch(ntt_fwd_cols_kernel, g, b, 0, s, L); break;
-        case 1: ks_launch(ntt_fwd_rows_kernel, g, b, 0, s, L); break;
-        case 2: ks_launch(ntt_inv_rows_kernel, g, b, 0, s, L); break;
-        case 3: ks_launch(ntt_inv_cols_kernel, g, b, 0, s, L); break;
+        case 1: ks_launch(ntt_rows_kernel, g, b, 0, s, L); break;
+        case 2: ks_launch(ntt_inv_cols_kernel, g, b, 0, s, L); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -130,7 +130,7 @@ struct JobLists {
     std::vector<MulJob> mul_wave;  // small products: one wave per tile (blocks count tiles)
     std::vector<DigitJob> digit;
     std::vector<MfmaJob> mfma;
-    std::vector<NttJob> ntt_f1, ntt_f2, ntt_i2, ntt_i1;  // transform stages (forward per operand)
+    std::vector<NttJob> ntt_f1, ntt_rows, ntt_i1;  // transform steps (forward columns per operand)
     std::vector<NttJoinJob> ntt_join;
     std::vector<NormJob> norm;
     std::vector<NormJob> norm_small;  // jobs of at most small_bl(ipt) limbs
@@ -146,7 +146,7 @@ struct DevList {
     uint32_t *block_job = nullptr;
 };
 struct DevTables {
-    DevList pack, pack_small, mul, mul_wave, digit, mfma, norm, norm_small, extract, ntt_f1, ntt_f2, ntt_i2, ntt_i1,
+    DevList pack, pack_small, mul, mul_wave, digit, mfma, norm, norm_small, extract, ntt_f1, ntt_rows, ntt_i1,
         ntt_join;
     std::map<int, DevList> anchor, chain, finish;
 };
@@ -173,8 +173,11 @@ int device_ok();
 int read_status(uint32_t *devstat, hipStream_t s);
 // the status word of ks_mul_noalloc's array on the current device (KS_OK if never used)
 int noalloc_status(hipStream_t s);
-// a planner tunable: the value set through ks_tune_set, else the environment, else dflt
+// a planner tunable: the value set through ks_tune_set, else the environment, else the
+// autotuner's cache file, else dflt
 int env_int(const char *name, int dflt);
+// counts the changes made through ks_tune_set / ks_tune_reset (cached plans compare it)
+uint64_t tune_generation();
 // transform length and piece width of an integer product of na x nb limbs through the
 // transforms: the shortest N = 2^(k1+k2) (k1 = floor(k/2)) with a piece width w whose
 // convolution fits in N terms and stays below the primes' product; false when none does

@@ -193,6 +193,113 @@ __global__ __launch_bounds__(256) void p2_glue_out_kernel(P2Glue G) {
 
 // ---- host launchers -----------------------------------------------------------------------------
 
+// ---- Section 2.5: points in an extension of R ------------------------------------------------
+
+// c v mod p for a small integer c (|c| <= 2)
+__device__ __forceinline__ uint64_t small_mul(int c, uint64_t v, uint64_t p) {
+    const uint64_t a = c == 0 ? 0 : (c == 2 || c == -2) ? add_mod(v, v, p) : v;
+    return c < 0 ? (a ? p - a : 0) : a;
+}
+
+// Position i m + r of polynomial q of input w: sum over the rows reaching it (rows overlap
+// when m < L_x), row i - t at column r + t m weighted by coef[q][(i - t) mod period]
+__global__ __launch_bounds__(256) void p2_ext_eval_kernel(P2ExtEval E) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= 2 * E.np * E.le) return;
+    const int64_t wq = t / E.le, pos = t - wq * E.le;
+    const int w = (int)(wq / E.np), q = (int)(wq - (int64_t)w * E.np);
+    const uint64_t *src = w ? E.g : E.f;
+    const int64_t i = pos / E.m, r = pos - i * E.m;
+    uint64_t acc = 0;
+    bool bad = false;
+    for (int64_t s = 0; i - s >= 0 && r + s * E.m < E.lx; ++s) {
+        const int64_t row = i - s;
+        if (row >= E.ly) continue;
+        const uint64_t v = src[row * E.lx + r + s * E.m];
+        bad |= v >= E.p;
+        acc = add_mod(acc, small_mul(E.coef[q][row % E.period], v, E.p), E.p);
+    }
+    if (bad) set_status(E.devstat, KS_DEVSTAT_RANGE);
+    E.out[wq * E.le + pos] = acc;
+}
+
+// first component of (c0 + c1 w)(a + b w) for c0, c1 in {-1, 0, 1}: c0 a - c1 b
+__device__ __forceinline__ uint64_t wmul_re(int c0, int c1, uint64_t a, uint64_t b, uint64_t p) {
+    uint64_t r = c0 > 0 ? a : c0 < 0 ? (a ? p - a : 0) : 0;
+    if (c1 > 0) r = sub_mod_p(r, b, p);
+    else if (c1 < 0) r = add_mod(r, b, p);
+    return r;
+}
+
+__global__ __launch_bounds__(256) void p2_ext_readoff_kernel(P2ExtReadoff R) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= R.rows * R.width) return;
+    const int64_t j = t / R.width, c = t - j * R.width;
+    const int64_t pos = j * R.m + c;
+    const uint64_t p = R.p;
+    auto P = [&](int q) -> uint64_t { return pos < R.lh ? R.prod[q * R.lh + pos] : 0; };
+    uint64_t v;
+    if (!R.cube) {
+        // h at y = x^m, -x^m and i x^m = re + i im (re = ac - bd, im = (a+b)(c+d) - ac - bd);
+        // A_r = (H1 + (-1)^r H2 + 2 Re(i^-r (re + i im))) / 4
+        const uint64_t h1 = P(0), h2 = P(1), ac = P(2), bd = P(3), s = P(4);
+        const uint64_t re = sub_mod_p(ac, bd, p), im = sub_mod_p(sub_mod_p(s, ac, p), bd, p);
+        const int rr = (int)(j & 3);
+        const uint64_t e = (rr & 1) ? sub_mod_p(h1, h2, p) : add_mod(h1, h2, p);
+        const uint64_t x = (rr & 1) ? im : re;
+        const uint64_t x2 = add_mod(x, x, p);
+        v = rr < 2 ? add_mod(e, x2, p) : sub_mod_p(e, x2, p);
+    } else {
+        // V_k = h at z^k x^m, z = 1 + w: V0 = H+, V3 = H-, V2 = (ac - bd, s - ac - 2 bd) at w,
+        // V5 the same at -w, V4 and V1 their conjugates (a, b) -> (a - b, -b);
+        // A_r = sum_k first component of (-w)^(r k) V_k (times 6^-1 below)
+        uint64_t va[6], vb[6];
+        va[0] = P(0);
+        vb[0] = 0;
+        va[3] = P(1);
+        vb[3] = 0;
+        {
+            const uint64_t ac = P(2), bd = P(3), s = P(4);
+            va[2] = sub_mod_p(ac, bd, p);
+            vb[2] = sub_mod_p(sub_mod_p(s, ac, p), add_mod(bd, bd, p), p);
+        }
+        {
+            const uint64_t ac = P(5), bd = P(6), s = P(7);
+            va[5] = sub_mod_p(ac, bd, p);
+            vb[5] = sub_mod_p(sub_mod_p(s, ac, p), add_mod(bd, bd, p), p);
+        }
+        va[4] = sub_mod_p(va[2], vb[2], p);
+        vb[4] = vb[2] ? p - vb[2] : 0;
+        va[1] = sub_mod_p(va[5], vb[5], p);
+        vb[1] = vb[5] ? p - vb[5] : 0;
+        // (-w)^e for e = 0..5 as (c0, c1): 1, -w, -1 - w, -1, w, 1 + w
+        const int c0[6] = {1, 0, -1, -1, 0, 1}, c1[6] = {0, -1, -1, 0, 1, 1};
+        const int rr = (int)(j % 6);
+        v = 0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int e = (rr * k) % 6;
+            v = add_mod(v, wmul_re(c0[e], c1[e], va[k], vb[k], p), p);
+        }
+    }
+    // times 4^-1 (or 6^-1): v < p < 2^62 and inv < p, the product reduced by the 128-bit quotient
+    R.out[t] = (uint64_t)(((unsigned __int128)v * R.inv) % p);
+}
+
+hipError_t launch_p2_ext_eval(const P2ExtEval &E, hipStream_t s) {
+    const int64_t n = 2 * E.np * E.le;
+    if (n <= 0) return hipSuccess;
+    ks_launch(p2_ext_eval_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2_ext_readoff(const P2ExtReadoff &R, hipStream_t s) {
+    const int64_t n = R.rows * R.width;
+    if (n <= 0) return hipSuccess;
+    ks_launch(p2_ext_readoff_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, R);
+    return hipGetLastError();
+}
+
 hipError_t launch_p2_eval(const P2Eval &E, hipStream_t s) {
     const int64_t n = 2 * E.k * E.le;
     if (n <= 0) return hipSuccess;

@@ -17,6 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libksmul.so")
 
 KS_VARIANT = {"auto": 0, "ks1": 1, "neg2": 2, "recip2": 3, "ks4": 4}
+# substitutions of the bivariate products: the variants above and Section 2.5's points in an
+# extension of R (complex points, cube roots of unity)
+P2_VARIANT = {**KS_VARIANT, "cplx": 5, "cube": 6}
 KS_SIGNED = 0x100
 KS_ENGINE_VALU, KS_ENGINE_MFMA, KS_ENGINE_NTT = 0x1000, 0x2000, 0x4000
 KS_ENGINE = {None: 0, "valu": KS_ENGINE_VALU, "mfma": KS_ENGINE_MFMA, "ntt": KS_ENGINE_NTT}
@@ -221,7 +224,7 @@ def mul_poly2(f, g, p: int, variant: str = "auto", inner: str = "auto", engine=N
     if out is None:
         out = torch.empty((2 * ly - 1, 2 * lx - 1), dtype=torch.int64, device=f.device)
     rc = lib().ks_mul_poly2(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr()), lx, ly, p,
-                            KS_VARIANT[variant], _flags(inner, False, engine), _stream_ptr(stream),
+                            P2_VARIANT[variant], _flags(inner, False, engine), _stream_ptr(stream),
                             ctypes.c_void_p(out.data_ptr()))
     _check(rc, "ks_mul_poly2")
     return out

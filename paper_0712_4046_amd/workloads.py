@@ -158,8 +158,13 @@ POLY2_LX, POLY2_LY = 16, 4096
 
 
 def poly2_workload(seed: int = 7):
-    """(p, f, g) of the bivariate workload."""
-    p = paper_fig_modulus(60, seed)
+    """(p, f, g) of the bivariate workload: p the first random odd 60-bit modulus (seeds
+    seed, seed + 1, ...) prime to 3, so that every substitution applies (the cube roots of
+    Section 2.5 divide by 6)."""
+    s = seed
+    while paper_fig_modulus(60, s) % 3 == 0:
+        s += 1
+    p = paper_fig_modulus(60, s)
     f, g = poly2_pair(POLY2_LY, POLY2_LX, p, seed)
     return p, f, g
 

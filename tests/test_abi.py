@@ -119,6 +119,8 @@ def test_poly2_arguments_checked_on_the_host():
     assert call(p=1) == ks.KS_EINVAL
     assert call(v=0x55) == ks.KS_EINVAL
     assert call(inner=ks.KS_SIGNED) == ks.KS_EINVAL
+    assert call(v=ks.P2_VARIANT["cube"], p=3 * 1_000_003) == ks.KS_EINVAL  # the cube roots divide by 6
+    assert call(v=7) == ks.KS_EINVAL
 
 
 def test_tuning_cache_file_read_at_plan_time(tmp_path):

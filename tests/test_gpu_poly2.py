@@ -106,3 +106,46 @@ def test_poly2_errors(torch_dev):
     ks.mul_poly2(bad, bad, 5, "neg2")  # residues >= p
     assert ks.status() == ks.KS_ERANGE
     assert ks.status() == ks.KS_OK
+
+
+# ---- Section 2.5: evaluation points in an extension of R ---------------------------------------
+
+@pytest.mark.parametrize("p", MODULI)
+@pytest.mark.parametrize("ly,lx", [(1, 1), (1, 5), (5, 1), (2, 2), (3, 4), (4, 7), (7, 3), (8, 6), (16, 16),
+                                   (33, 9), (64, 17)])
+def test_poly2_extension_points_against_definition(torch_dev, poly2, ly, lx, p):
+    # the complex points (five products, rows by residue mod 4) and the cube roots of unity
+    # (eight products, rows by residue mod 6; p must not be divisible by 3) element by element
+    f, g = wl.poly2_pair(ly, lx, p, seed=300 * ly + lx)
+    want = poly2.mul_direct(rows(f), rows(g), p)
+    for v in ("cplx", "cube"):
+        if v == "cube" and p % 3 == 0:
+            continue
+        got = gpu(torch_dev, f, g, p, v)
+        assert got.shape == (2 * ly - 1, 2 * lx - 1), v
+        assert rows(got) == want, f"{v} ly={ly} lx={lx} p={p}"
+
+
+def test_poly2_extension_points_workload_sampled(torch_dev, poly2):
+    # the bivariate workload's shape (L_x = 16, L_y = 4096, 60-bit p): both extension-point
+    # substitutions equal the standard one everywhere and the definition on 200 samples
+    p, f, g = wl.poly2_workload()
+    ref = gpu(torch_dev, f, g, p, "ks1")
+    rng = np.random.default_rng(9)
+    for v in ("cplx", "cube"):
+        got = gpu(torch_dev, f, g, p, v)
+        assert np.array_equal(got, ref), v
+    for _ in range(200):
+        k, c = int(rng.integers(0, 2 * f.shape[0] - 1)), int(rng.integers(0, 2 * f.shape[1] - 1))
+        assert int(ref[k, c]) == poly2.coeff_direct(f, g, p, k, c), (k, c)
+
+
+def test_poly2_extension_points_range_error(torch_dev):
+    torch = torch_dev
+    p = 1_000_003
+    f = torch.ones((4, 5), dtype=torch.int64, device="cuda")
+    g = f.clone()
+    g[2, 3] = p  # not a residue
+    for v in ("cplx", "cube"):
+        ks.mul_poly2(f, g, p, v)
+        assert ks.status() == ks.KS_ERANGE, v
