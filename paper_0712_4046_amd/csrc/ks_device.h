@@ -441,21 +441,24 @@ __device__ __forceinline__ NttPrime ntt_prime(int q) {
     return q == 0 ? NttPrime{NTT_P0, neg_inv32(NTT_P0)} : NttPrime{NTT_P1, neg_inv32(NTT_P1)};
 }
 
-// x y + z in 64 bits (one v_mad_u64_u32; the caller knows the sum cannot wrap)
-__device__ __forceinline__ uint64_t mad64(uint32_t x, uint32_t y, uint64_t z) {
-    uint64_t r, cc;
-    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(cc) : "v"(x), "v"(y), "v"(z));
-    return r;
-}
+// Residues may be held partly reduced, below 2p or 4p: with p < 2^30, 4p still fits in a
+// 32-bit word.  s < 2p -> [0, p) and s < 4p -> [0, 2p), each as min(s, s - c): the subtraction
+// wraps to a large value exactly when s < c.
+__device__ __forceinline__ uint32_t red1(uint32_t s, uint32_t p) { return min(s, s - p); }
+__device__ __forceinline__ uint32_t red2(uint32_t s, uint32_t p) { return min(s, s - 2u * p); }
 
-// a b R^-1 mod p for a, b < p < 2^31 (Montgomery reduction): t = a b, m = t p' mod 2^32,
-// (t + m p) / 2^32 < 2p -- three multiply-adds (t + m p < 2^62 + 2^63 does not wrap)
-__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, NttPrime P) {
-    const uint64_t t = mad64(a, b, 0);
-    const uint32_t m = (uint32_t)mad64((uint32_t)t, P.pn, 0);
-    const uint32_t u = (uint32_t)(mad64(m, P.p, t) >> 32);
-    return u >= P.p ? u - P.p : u;
+// a b R^-1 mod p below 2p (Montgomery reduction without its final subtraction) whenever
+// a b < p 2^32 -- any 32-bit a with b < p, or a, b < 2p, or a < 4p with b < p, as 4p < 2^32:
+// t = a b, m = t p' mod 2^32, and (t + m p) / 2^32 < a b / 2^32 + p < 2p, with t + m p < 2^63
+// not wrapping.  The compiler turns it into three multiply-adds (v_mad_u64_u32, v_mul_lo_u32,
+// v_mad_u64_u32).
+__device__ __forceinline__ uint32_t mmul_lazy(uint32_t a, uint32_t b, NttPrime P) {
+    const uint64_t t = (uint64_t)a * b;
+    const uint32_t m = (uint32_t)t * P.pn;
+    return (uint32_t)((t + (uint64_t)m * P.p) >> 32);
 }
+// the same, fully reduced (below p)
+__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, NttPrime P) { return red1(mmul_lazy(a, b, P), P.p); }
 __device__ __forceinline__ uint32_t madd(uint32_t a, uint32_t b, uint32_t p) {
     const uint32_t s = a + b;
     return s >= p ? s - p : s;

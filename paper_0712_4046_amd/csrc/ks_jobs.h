@@ -136,9 +136,10 @@ struct MfmaJob {
 constexpr int NTT_TPB = 256;
 constexpr int NTT_BLOCK = 8192;   // elements a block transforms: C columns of N1, or R rows of N2
 constexpr int NTT_MIN_LOG = 13, NTT_MAX_LOG = 23;  // N1 <= 2048 <= N2 <= 4096: 4 <= C <= N2
-constexpr int NTT_ROOT_LOG = 26;  // root tables: powers of a root of order 2^26 of each prime
-constexpr uint32_t NTT_P0 = 2013265921u;  // 15 2^27 + 1
-constexpr uint32_t NTT_P1 = 1811939329u;  // 27 2^26 + 1
+constexpr int NTT_ROOT_LOG = 23;  // root tables: powers of a root of order 2^23 of each prime
+// both below 2^30 (so 4p fits in 32 bits), P0 P1 > 2^59
+constexpr uint32_t NTT_P0 = 998244353u;  // 119 2^23 + 1, primitive root 3
+constexpr uint32_t NTT_P1 = 897581057u;  // 107 2^23 + 1, primitive root 3
 
 // One stage of the transforms of one operand (forward) or one product (inverse).
 struct NttJob {

@@ -5,9 +5,9 @@
 // operand of n limbs (its unsigned reading; the recombination corrects two's-complement signs)
 // is cut into np = ceil(32 n / w) pieces of w bits, and the pieces of a and b are convolved:
 // c_m = sum_i a'_i b'_{m-i}, so that A B = sum_m c_m 2^(w m).  The convolution is computed
-// modulo P0 = 15 2^27 + 1 and P1 = 27 2^26 + 1 by transforms of length N = 2^k >= npa + npb - 1
+// modulo P0 = 119 2^23 + 1 and P1 = 107 2^23 + 1 by transforms of length N = 2^k >= npa + npb - 1
 // and joined by the Chinese remainder theorem; the planner picks w so that every c_m stays
-// below P0 P1 (2w + log2 min(npa, npb) <= 61), which makes the joined value exact.
+// below P0 P1 > 2^59 (2w + log2 min(npa, npb) <= 59), which makes the joined value exact.
 //
 // A product's transforms of length N = N1 N2 run in three steps (each one launch over every
 // job) and a join:
@@ -27,10 +27,15 @@
 // A column block transforms NTT_BLOCK elements in LDS (C = NTT_BLOCK / N1 adjacent columns), a
 // row block NTT_BLOCK / 2 elements of each operand (R = NTT_BLOCK / 2 / N2 rows).
 //
-// Arithmetic: residues below P < 2^31 in 32-bit words; products by Montgomery reduction with
+// Arithmetic: residues of P < 2^30 in 32-bit words; products by Montgomery reduction with
 // R = 2^32 (a b R^-1 mod P), twiddles kept in Montgomery form so that multiplying a residue by
-// one returns the plain product.  Powers of a root of unity of order 2^26 come from two tables
-// of 8192 entries per prime (w^e = w^(8192 hi) w^(lo)), built on the host once per device.
+// one returns the plain product.  Residues stay partly reduced between butterflies (after
+// D. Harvey, "Faster arithmetic for number-theoretic transforms", 2014): the forward
+// butterflies take and give values below 2P, the inverse ones below 4P, and a product is
+// left below 2P (no final subtraction), so a butterfly costs three multiply-adds and five
+// additions, subtractions or minima.  Powers of a root of unity of order 2^23 come from two
+// tables of 4096 entries per prime (w^e = w^(4096 hi) w^(lo)), built on the host once per
+// device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,15 +48,19 @@
 
 namespace ks {
 
-constexpr int NTT_TAB = 1 << (NTT_ROOT_LOG / 2);  // 8192 entries per half table
-static_assert(NTT_TAB * NTT_TAB == (1 << NTT_ROOT_LOG), "two half tables cover the root's powers");
+constexpr int NTT_TAB_LOG = (NTT_ROOT_LOG + 1) / 2;
+constexpr int NTT_TAB = 1 << NTT_TAB_LOG;  // 4096 entries per half table
+static_assert(2 * NTT_TAB_LOG >= NTT_ROOT_LOG, "two half tables cover the root's powers");
+static_assert(NTT_MAX_LOG <= NTT_ROOT_LOG, "the root's order covers the longest transform");
+static_assert(4ull * NTT_P0 < (1ull << 32) && 4ull * NTT_P1 < (1ull << 32), "4P fits in a word");
+static_assert(NTT_P0 < 2ull * NTT_P1 && (double)NTT_P0 * NTT_P1 > (double)(1ull << 59), "the join's bounds");
 
-// [prime][0: w^(8192 i) R, 1: w^i R][i] mod P
+// [prime][0: w^(4096 i) R, 1: w^i R][i] mod P (fully reduced)
 __device__ uint32_t ntt_tab[2][2][NTT_TAB];
 
-// w^e R for e in [0, 2^26), w the table root of prime q
+// w^e R for e in [0, 2^23), w the table root of prime q (fully reduced)
 __device__ __forceinline__ uint32_t root_pow(int q, uint32_t e, NttPrime P) {
-    return mmul(ntt_tab[q][0][e >> (NTT_ROOT_LOG / 2)], ntt_tab[q][1][e & (NTT_TAB - 1)], P);
+    return mmul(ntt_tab[q][0][e >> NTT_TAB_LOG], ntt_tab[q][1][e & (NTT_TAB - 1)], P);
 }
 // w^-e R
 __device__ __forceinline__ uint32_t root_pow_inv(int q, uint32_t e, NttPrime P) {
@@ -67,12 +76,27 @@ __device__ __forceinline__ void load_twiddles(uint32_t *tw, int q, int lg, NttPr
     }
 }
 
-// Transforms of length M = 2^LG over NTT_BLOCK elements in LDS (NTT_BLOCK / M sequences,
-// sequence s at buf[s * stride ..]): forward by decimation in frequency (natural in, bit-reversed
-// out), inverse by decimation in time (bit-reversed in, natural out; tw holds the inverse
-// twiddles, tw[j] = w_M^(+-j) R).  Stages go in pairs (radix 4: each thread reads four elements,
-// runs two stages in registers and writes them back), with one radix-2 stage more when LG is odd
-// (last in the forward order, first in the inverse).  Ends with a barrier.
+// The two butterflies on partly reduced residues (P < 2^30).
+// Forward, decimation in frequency: u, v < 2P -> u + v and (u - v) w, both below 2P.
+__device__ __forceinline__ void bfly_dif(uint32_t &u, uint32_t &v, uint32_t w, NttPrime P) {
+    const uint32_t s = red2(u + v, P.p), d = mmul_lazy(u + 2u * P.p - v, w, P);
+    u = s;
+    v = d;
+}
+// Inverse, decimation in time: u, v < 4P -> u + v w and u - v w, both below 4P.
+__device__ __forceinline__ void bfly_dit(uint32_t &u, uint32_t &v, uint32_t w, NttPrime P) {
+    const uint32_t a = red2(u, P.p), t = mmul_lazy(v, w, P);
+    u = a + t;
+    v = a + 2u * P.p - t;
+}
+
+// Transforms of length M = 2^LG over NE elements in LDS (NE / M sequences, sequence s at
+// buf[s * stride ..]): forward by decimation in frequency (natural in, bit-reversed out; values
+// below 2P in and out), inverse by decimation in time (bit-reversed in, natural out; below 4P in
+// and out; tw holds the inverse twiddles, tw[j] = w_M^(+-j) R).  Stages go in pairs (radix 4:
+// each thread reads four elements, runs two stages in registers and writes them back), with one
+// radix-2 stage more when LG is odd (last in the forward order, first in the inverse).  Ends
+// with a barrier.
 template <int LG, bool INV, int NE = NTT_BLOCK>
 __device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, const uint32_t *tw, NttPrime P) {
     constexpr int NQ = NE / 4 / NTT_TPB;  // groups of four per thread and pass
@@ -86,16 +110,14 @@ __device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, const u
             const int seq = b >> (LG - 1), r = b & ((1 << (LG - 1)) - 1);
             const int j = r & (h - 1);
             uint32_t *x = buf + seq * stride + ((r >> hl) << (hl + 1)) + j;
-            const uint32_t u = x[0], t = tw[j << ts];
-            if (!INV) {
-                const uint32_t v = x[h];
-                x[0] = madd(u, v, P.p);
-                x[h] = mmul(msub(u, v, P.p), t, P);
-            } else {
-                const uint32_t v = mmul(x[h], t, P);
-                x[0] = madd(u, v, P.p);
-                x[h] = msub(u, v, P.p);
-            }
+            uint32_t u = x[0], v = x[h];
+            const uint32_t t = tw[j << ts];
+            if (!INV)
+                bfly_dif(u, v, t, P);
+            else
+                bfly_dit(u, v, t, P);
+            x[0] = u;
+            x[h] = v;
         }
         __syncthreads();
     };
@@ -112,22 +134,16 @@ __device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, const u
             uint32_t *x = buf + seq * stride + ((r >> bl) << (bl + 2)) + j;
             uint32_t u0 = x[0], u1 = x[hb], u2 = x[2 * hb], u3 = x[3 * hb];
             const uint32_t wa0 = tw[j << ta], wa1 = tw[(j + hb) << ta], wb = tw[j << tb];
-            if (!INV) {
-                const uint32_t a0 = madd(u0, u2, P.p), a2 = mmul(msub(u0, u2, P.p), wa0, P);
-                const uint32_t a1 = madd(u1, u3, P.p), a3 = mmul(msub(u1, u3, P.p), wa1, P);
-                u0 = madd(a0, a1, P.p);
-                u1 = mmul(msub(a0, a1, P.p), wb, P);
-                u2 = madd(a2, a3, P.p);
-                u3 = mmul(msub(a2, a3, P.p), wb, P);
-            } else {
-                const uint32_t v1 = mmul(u1, wb, P), v3 = mmul(u3, wb, P);
-                const uint32_t a0 = madd(u0, v1, P.p), a1 = msub(u0, v1, P.p);
-                const uint32_t a2 = madd(u2, v3, P.p), a3 = msub(u2, v3, P.p);
-                const uint32_t c2 = mmul(a2, wa0, P), c3 = mmul(a3, wa1, P);
-                u0 = madd(a0, c2, P.p);
-                u2 = msub(a0, c2, P.p);
-                u1 = madd(a1, c3, P.p);
-                u3 = msub(a1, c3, P.p);
+            if (!INV) {  // half-size 2 Hb (pairs 0-2, 1-3), then Hb (pairs 0-1, 2-3)
+                bfly_dif(u0, u2, wa0, P);
+                bfly_dif(u1, u3, wa1, P);
+                bfly_dif(u0, u1, wb, P);
+                bfly_dif(u2, u3, wb, P);
+            } else {  // half-size Hb first, then 2 Hb
+                bfly_dit(u0, u1, wb, P);
+                bfly_dit(u2, u3, wb, P);
+                bfly_dit(u0, u2, wa0, P);
+                bfly_dit(u1, u3, wa1, P);
             }
             x[0] = u0;
             x[hb] = u1;
@@ -176,11 +192,14 @@ constexpr int CH = 16;
 
 // ---- the four steps ---------------------------------------------------------------------------
 
+// Column blocks read C words of each row: with C = 16 that is half of a 128-byte line, whose
+// other half the next block reads -- both run on one XCD at about the same time (xcd_block), so
+// the line comes from HBM once.
 __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L) {
     __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
     __shared__ uint32_t tw[2048];
     int64_t local;
-    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const NttJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
     const int lc = 13 - k1, C = 1 << lc, S = (1 << k1) + 1;  // columns, LDS stride of a column
     const int gl = k - 13;  // log2 of the blocks of one prime (a power of two: no division)
@@ -232,14 +251,14 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L)
         const uint32_t g = root_pow(q, (uint32_t)(((int64_t)kk) << sh), P);
         uint32_t *dst = x + ((int64_t)r << k2) + c0 + cf;
         for (int c4 = 0; c4 < cols; c4 += 4) {
-            u32x4 v;
-            v.x = mmul(buf[(cf + c4) * S + r], w, P);
+            u32x4 v;  // below 2P; the running twiddle is kept fully reduced
+            v.x = mmul_lazy(buf[(cf + c4) * S + r], w, P);
             w = mmul(w, g, P);
-            v.y = mmul(buf[(cf + c4 + 1) * S + r], w, P);
+            v.y = mmul_lazy(buf[(cf + c4 + 1) * S + r], w, P);
             w = mmul(w, g, P);
-            v.z = mmul(buf[(cf + c4 + 2) * S + r], w, P);
+            v.z = mmul_lazy(buf[(cf + c4 + 2) * S + r], w, P);
             w = mmul(w, g, P);
-            v.w = mmul(buf[(cf + c4 + 3) * S + r], w, P);
+            v.w = mmul_lazy(buf[(cf + c4 + 3) * S + r], w, P);
             w = mmul(w, g, P);
             *(__attribute__((address_space(1))) u32x4 *)(dst + c4) = v;
         }
@@ -285,12 +304,13 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
     __syncthreads();
     lds_transform_any<false, NTT_ROWS_BLOCK>(k2, bufa, 1 << k2, tw, P);
     lds_transform_any<false, NTT_ROWS_BLOCK>(k2, bufb, 1 << k2, tw, P);
-    // pointwise A B R^-1 (equal positions: both in the order the forward steps left), then the
-    // inverse twiddles replace the forward ones
+    // pointwise A B R^-1 (equal positions: both in the order the forward steps left; A, B < 2P,
+    // so A B < P 2^32 and the product is below 2P), then the inverse twiddles replace the
+    // forward ones
 #pragma unroll 4
     for (int i = 0; i < EPT_R; ++i) {
         const int e = t + i * NTT_TPB;
-        bufa[e] = mmul(bufa[e], bufb[e], P);
+        bufa[e] = mmul_lazy(bufa[e], bufb[e], P);
     }
     load_twiddles<true>(tw, q, k2, P);  // every thread is past the forward transforms' barrier
     __syncthreads();
@@ -307,13 +327,13 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
             const int64_t r = r0 + (e >> k2), n2 = e & ((1 << k2) - 1);
             const uint32_t ex = (uint32_t)((n2 * (int64_t)bitrev((uint32_t)r, k1)) << (NTT_ROOT_LOG - k));
             const uint32_t ei = (uint32_t)((1u << NTT_ROOT_LOG) - ex) & ((1u << NTT_ROOT_LOG) - 1u);
-            a[i] = ntt_tab[q][0][ei >> (NTT_ROOT_LOG / 2)];
+            a[i] = ntt_tab[q][0][ei >> NTT_TAB_LOG];
             b[i] = ntt_tab[q][1][ei & (NTT_TAB - 1)];
         }
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             const int e = t + (i0 + i) * NTT_TPB;
-            stg(x + e, mmul(bufa[e], mmul(mmul(a[i], b[i], P), K, P), P));
+            stg(x + e, mmul_lazy(bufa[e], mmul(mmul(a[i], b[i], P), K, P), P));  // below 2P
         }
     }
 }
@@ -322,7 +342,7 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L)
     __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
     __shared__ uint32_t tw[2048];
     int64_t local;
-    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
+    const NttJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
     const int lc = 13 - k1, C = 1 << lc, S = (1 << k1) + 1;
     const int gl = k - 13;
@@ -348,13 +368,13 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L)
     }
     __syncthreads();
     lds_transform_any<true>(k1, buf, S, tw, P);
-    // the residues of terms N2 n1 + n2 in natural order, in place (the block's columns hold
-    // exactly the positions it read)
+    // the residues of terms N2 n1 + n2 in natural order, fully reduced, in place (the block's
+    // columns hold exactly the positions it read)
 #pragma unroll 8
     for (int i = 0; i < EPT; ++i) {
         const int e = t + i * NTT_TPB;
         const int c = e & (C - 1), n1 = e >> lc;
-        stg(x + ((int64_t)n1 << k2) + c0 + c, buf[c * S + n1]);
+        stg(x + ((int64_t)n1 << k2) + c0 + c, red1(red2(buf[c * S + n1], P.p), P.p));
     }
 }
 
@@ -408,8 +428,8 @@ bool ntt_shape(int64_t na, int64_t nb, int min_log, int &k1, int &k2, int &w, in
         for (int ww = 1; ww <= 30; ++ww) {
             const int64_t pa = cdiv(32 * na, ww), pb = cdiv(32 * nb, ww);
             if (pa + pb - 1 > N) continue;
-            // exact: every term below min(pa, pb) 2^(2w) <= 2^61 < P0 P1
-            if (2 * ww + ceil_log2(std::min(pa, pb)) > 61) break;
+            // exact: every term below min(pa, pb) 2^(2w) <= 2^59 < P0 P1
+            if (2 * ww + ceil_log2(std::min(pa, pb)) > 59) break;
             k1 = k / 2;
             k2 = k - k1;
             w = ww;
@@ -429,10 +449,10 @@ int ntt_prepare() {
     std::lock_guard<std::mutex> lk(mu);
     if (done[dev]) return KS_OK;
     static uint32_t host[2][2][NTT_TAB];
-    const uint64_t prime[2] = {NTT_P0, NTT_P1}, gen[2] = {31, 13};  // primitive roots
+    const uint64_t prime[2] = {NTT_P0, NTT_P1}, gen[2] = {3, 3};  // primitive roots
     for (int q = 0; q < 2; ++q) {
         const uint64_t p = prime[q];
-        const uint64_t w = powmod_h(gen[q], (p - 1) >> NTT_ROOT_LOG, p);  // order 2^26
+        const uint64_t w = powmod_h(gen[q], (p - 1) >> NTT_ROOT_LOG, p);  // order 2^23
         const uint64_t R = ((uint64_t)1 << 32) % p;
         const uint64_t wh = powmod_h(w, NTT_TAB, p);
         uint64_t a = 1, b = 1;
