@@ -34,17 +34,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # vector-ALU peak for the limb multiplier: one limb-mult is a v_mad_u64_u32 (32x32+64 -> 64)
-# plus a v_addc (carry into the top word of a 96-bit column sum), both issuing at full rate:
-# 256 CUs x 64 lanes x 2.4 GHz / 2 instructions = 19.66e12 limb-mults/s
+# plus a v_addc (carry into the top word of a 96-bit column sum), each taken at one instruction
+# per lane per clock (16 lanes per SIMD, the fp64 FMA rate; the instruction-rate probe,
+# `python -m paper_0712_4046_amd.prof_tools valu`, measures multiply-adds at 13-16 lanes per
+# SIMD per clock and 32-bit adds faster): 256 CUs x 64 lanes x 2.4 GHz / 2 = 19.66e12 limb-mults/s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
 # int8 matrix cores (dense, no sparsity): 5.0e15 operations/s, one multiply-add = 2 operations
 MFMA_I8_PEAK_TOPS = 5000.0
 HBM_PEAK_GBS = 8000.0
-# transform engine: a radix-2 butterfly modulo a 31-bit prime is at least 12 vector instructions
-# (Montgomery product: 2 v_mad_u64_u32, v_mul_lo_u32, compare, select, subtract; modular sum and
-# difference: 3 each), each issuing at most once per lane per cycle:
-# 256 CUs x 64 lanes x 2.4 GHz / 12 = 3.28e12 butterflies/s
-NTT_BUTTERFLY_PEAK_T = 256 * 64 * 2.4e9 / 12 / 1e12
+# transform engine: a radix-2 butterfly modulo a prime below 2^30 on partly reduced residues is
+# 8 vector instructions (the Montgomery product without its final subtraction: v_mad_u64_u32,
+# v_mul_lo_u32, v_mad_u64_u32; the sum and its reduction: add, subtract, minimum; the
+# difference plus 2P: subtract, add), each at one per lane per clock:
+# 256 CUs x 64 lanes x 2.4 GHz / 8 = 4.92e12 butterflies/s
+NTT_BUTTERFLY_PEAK_T = 256 * 64 * 2.4e9 / 8 / 1e12
 # butterflies of each transform step as a share of the plan's total (6 (N/2) k per product,
 # three transforms per prime): the forward columns transform both operands (2, columns of 2^k1),
 # the row step both operands and the product (3, rows of 2^k2), the inverse columns the
@@ -137,7 +140,7 @@ def roofline(kern, info, traffic_table=None):
         achieved = ops / sec / 1e12
         return {"bound": "alu", "achieved": achieved, "peak": NTT_BUTTERFLY_PEAK_T, "unit": "T butterflies/s",
                 "frac": achieved / NTT_BUTTERFLY_PEAK_T, **base,
-                "op": "radix-2 butterfly modulo a 31-bit prime (12 vector instructions at least)",
+                "op": "radix-2 butterfly modulo a prime below 2^30 (8 vector instructions)",
                 "ops_per_run": ops}
     if dom in ("mul_valu", "anchor"):
         ops = info["valu_limb_mults"] if dom == "mul_valu" else info["anchor_limb_mults"]

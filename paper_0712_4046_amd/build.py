@@ -3,7 +3,9 @@
     python -m paper_0712_4046_amd.build
 
 Every translation unit under csrc/ is compiled with hipcc for gfx950 only, in parallel, and
-linked into paper_0712_4046_amd/libksmul.so next to this file.
+linked into paper_0712_4046_amd/libksmul.so next to this file.  The instruction-rate probe
+under probe/ (a measurement aid for prof_tools.py, not part of the library) is built beside it
+as libksprobe.so.
 """
 from __future__ import annotations
 
@@ -16,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libksmul.so")
+PROBE_SRC = os.path.join(HERE, "probe", "valu_rates.hip")
+PROBE_LIB = os.path.join(HERE, "libksprobe.so")
 ROOT = os.path.dirname(HERE)
 
 ARCH = "gfx950"
@@ -52,8 +56,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, "-shared", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
     if verbose:
         print(LIB)
+        print(PROBE_LIB)
     return LIB
 
 

@@ -4,6 +4,7 @@
     python -m paper_0712_4046_amd.prof_tools workload [product_4096_s64|batch_mixed_10000|batch_mod_64x65536] [valu|mfma|ntt]
     python -m paper_0712_4046_amd.prof_tools summarize DB "cmd"  # kernel-trace summary table
     python -m paper_0712_4046_amd.prof_tools counters FETCH_DB WRITE_DB   # HBM bytes per kernel
+    python -m paper_0712_4046_amd.prof_tools valu   # vector-ALU instruction rates (libksprobe.so)
 
 The workload is a plain device copy of known size (to calibrate FETCH_SIZE / WRITE_SIZE) and
 then the benchmark product (one Z[x] product, L = 4096, signed 64-bit coefficients, seed 2)
@@ -141,6 +142,31 @@ def pmc_table(db: str, cmd: str = ""):
         print(f"    {c:32s} {v:20.1f}   (dispatches: {n})")
 
 
+def valu_rates(blocks: int = 4096, iters: int = 4096, reps: int = 5):
+    """Issue rate of each probe operation (probe/valu_rates.hip): lane-operations per second
+    over the whole chip, and the lanes per SIMD per clock that rate means at the nominal
+    2.4 GHz (256 CUs, 4 SIMDs each).  A wave64 instruction at 16 lanes per clock takes four
+    clocks (the fp64 FMA rate); at 32 lanes, two (the fp32 rate)."""
+    import ctypes
+    import torch
+    torch.cuda.init()
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_0712_4046_amd", "libksprobe.so"))
+    lib.ks_probe_name.restype = ctypes.c_char_p
+    print("# vector-ALU issue rates (paper_0712_4046_amd/probe/valu_rates.hip)")
+    print(f"# command: python -m paper_0712_4046_amd.prof_tools valu   ({blocks} blocks x 256 threads, "
+          f"{iters} steps of 8 chains, mean of {reps} launches)")
+    print("# (for the ds_read patterns: lanes/SIMD/clk x 4 = words a CU reads per clock)")
+    print(f"{'operation':76s} {'ms':>8s} {'T inst/s':>9s} {'lanes/SIMD/clk @2.4GHz':>23s}")
+    for op in range(lib.ks_probe_count()):
+        ms = ctypes.c_float()
+        if lib.ks_probe_valu(op, blocks, iters, reps, ctypes.byref(ms)) != 0:
+            raise SystemExit(f"probe {op} failed")
+        inst = blocks * 256 * iters * 8 * lib.ks_probe_insts(op)
+        rate = inst / (ms.value * 1e-3)
+        print(f"{lib.ks_probe_name(op).decode():76s} {ms.value:8.3f} {rate / 1e12:9.2f} "
+              f"{rate / (256 * 4 * 2.4e9):23.1f}")
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else "workload"
     if cmd == "workload":
@@ -152,3 +178,5 @@ if __name__ == "__main__":
         counters(sys.argv[2], sys.argv[3])
     elif cmd == "pmc":
         pmc_table(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
+    elif cmd == "valu":
+        valu_rates()
