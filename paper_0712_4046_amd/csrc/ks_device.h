@@ -437,9 +437,10 @@ constexpr uint64_t inv_mod(uint64_t a, uint64_t p) {
 constexpr uint32_t NTT_CRT_C = (uint32_t)(inv_mod(NTT_P0, NTT_P1) * (((uint64_t)1 << 32) % NTT_P1) % NTT_P1);
 static_assert(inv_mod(NTT_P0, NTT_P1) * (NTT_P0 % NTT_P1) % NTT_P1 == 1, "P0 inverse mod P1");
 
-__device__ __forceinline__ NttPrime ntt_prime(int q) {
+__host__ __device__ constexpr NttPrime ntt_prime_c(int q) {
     return q == 0 ? NttPrime{NTT_P0, neg_inv32(NTT_P0)} : NttPrime{NTT_P1, neg_inv32(NTT_P1)};
 }
+__device__ __forceinline__ NttPrime ntt_prime(int q) { return ntt_prime_c(q); }
 
 // Residues may be held partly reduced, below 2p or 4p: with p < 2^30, 4p still fits in a
 // 32-bit word.  s < 2p -> [0, p) and s < 4p -> [0, 2p), each as min(s, s - c): the subtraction

@@ -40,6 +40,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "../../include/ks.h"
 #include "ks_device.h"
@@ -192,43 +193,61 @@ constexpr int CH = 16;
 
 // ---- the four steps ---------------------------------------------------------------------------
 
+// twiddles of a column transform (N1 / 2, N1 <= 2048): with them a column block takes 37 KB of
+// LDS, so four blocks fit on a CU
+constexpr int NTT_COL_TW = 1 << (NTT_MAX_LOG / 2 - 1);
+static_assert(NTT_COL_TW == 1024, "columns of at most 2^11");
+
 // Column blocks read C words of each row: with C = 16 that is half of a 128-byte line, whose
 // other half the next block reads -- both run on one XCD at about the same time (xcd_block), so
 // the line comes from HBM once.
-__global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L) {
-    __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
-    __shared__ uint32_t tw[2048];
-    int64_t local;
-    const NttJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
+template <int Q>
+__device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, uint32_t *buf, uint32_t *tw) {
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
     const int lc = 13 - k1, C = 1 << lc, S = (1 << k1) + 1;  // columns, LDS stride of a column
     const int gl = k - 13;  // log2 of the blocks of one prime (a power of two: no division)
-    const int q = (int)(local >> gl);
+    constexpr int q = Q;
     const int64_t c0 = (local & (((int64_t)1 << gl) - 1)) * C;
-    const NttPrime P = ntt_prime(q);
+    constexpr NttPrime P = ntt_prime_c(Q);
     load_twiddles<false>(tw, q, k1, P);
     const int t = threadIdx.x;
+    // element e = t + 256 i of the block: column c = t mod C (256 is a multiple of C), row
+    // n1 = t / C + i 256 / C; its piece m = n1 N2 + c0 + c < N <= 2^23 and first bit w m < 2^28
+    // fit in 32 bits.  The two words holding the piece come in one 8-byte load (dword alignment
+    // is enough) from a word clamped to n - 2, so that every load stays inside the operand and
+    // none waits on a branch; the words past the operand (or past np pieces) read as zero.
+    const uint32_t w = (uint32_t)J.w, np = (uint32_t)J.np, na = (uint32_t)J.na;
+    const uint32_t mt = ((uint32_t)(t >> lc) << k2) + (uint32_t)c0 + (uint32_t)(t & (C - 1));
+    const uint32_t mstep = (uint32_t)(NTT_TPB >> lc) << k2;
+    const uint32_t last = na >= 2 ? na - 2 : 0;
+    uint32_t *bt = buf + (t & (C - 1)) * S + (t >> lc);
+    auto load = [&](auto wide) {  // wide: 8-byte loads (an operand of two limbs or more)
 #pragma unroll 1
-    for (int i0 = 0; i0 < EPT; i0 += CH) {
-        uint32_t lo[CH], hi[CH];
-        int sh[CH];
+        for (int i0 = 0; i0 < EPT; i0 += CH) {
+            u32x2 v[CH];
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int e = t + (i0 + i) * NTT_TPB;
-            const int64_t m = ((int64_t)(e >> lc) << k2) + c0 + (e & (C - 1));
-            const int64_t bit = (int64_t)J.w * m;
-            const int64_t w0 = bit >> 5;
-            sh[i] = (int)(bit & 31);
-            const bool in = m < J.np;
-            lo[i] = in && w0 < J.na ? ldg(J.a + w0) : 0u;
-            hi[i] = in && w0 + 1 < J.na ? ldg(J.a + w0 + 1) : 0u;
-        }
+            for (int i = 0; i < CH; ++i) {
+                const uint32_t m = mt + (uint32_t)(i0 + i) * mstep, w0 = (w * m) >> 5;
+                const uint32_t *src = J.a + min(w0, last);
+                if constexpr (decltype(wide)::value)
+                    v[i] = *(const __attribute__((address_space(1))) u32x2 *)src;
+                else
+                    v[i] = u32x2{ldg(src), 0u};
+            }
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int e = t + (i0 + i) * NTT_TPB;
-            buf[(e & (C - 1)) * S + (e >> lc)] = piece_of(lo[i], hi[i], sh[i], J.w);
+            for (int i = 0; i < CH; ++i) {
+                const uint32_t m = mt + (uint32_t)(i0 + i) * mstep, bit = w * m, w0 = bit >> 5;
+                const bool in = m < np;
+                const uint32_t lo = in && w0 < na ? (w0 <= last ? v[i].x : v[i].y) : 0u;
+                const uint32_t hi = in && w0 + 1 < na ? v[i].y : 0u;
+                bt[(i0 + i) * (NTT_TPB >> lc)] = piece_of(lo, hi, (int)(bit & 31u), (int)w);
+            }
         }
-    }
+    };
+    if (na >= 2)
+        load(std::true_type{});
+    else
+        load(std::false_type{});
     __syncthreads();
     lds_transform_any<false>(k1, buf, S, tw, P);
     // twiddle w_N^(n2 k1) and store: each thread takes runs of `cols` adjacent columns of one row
@@ -265,24 +284,32 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L)
     }
 }
 
+__global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L) {
+    __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
+    __shared__ uint32_t tw[NTT_COL_TW];
+    int64_t local;
+    const NttJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
+    if ((local >> (J.k1 + J.k2 - 13)) == 0)  // the prime: a compile-time constant in each body
+        fwd_cols_body<0>(J, local, buf, tw);
+    else
+        fwd_cols_body<1>(J, local, buf, tw);
+}
+
 // The row step of a product: both operands' rows forward, the pointwise product, the inverse
 // row transform, the inverse twiddle and the scale, in one pass over HBM.  A block takes
 // NTT_ROWS_BLOCK residues (R = NTT_ROWS_BLOCK / N2 whole rows) of each operand for one prime.
 constexpr int NTT_ROWS_BLOCK = NTT_BLOCK / 2;
 constexpr int EPT_R = NTT_ROWS_BLOCK / NTT_TPB;
 
-__global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
-    __shared__ uint32_t bufa[NTT_ROWS_BLOCK];
-    __shared__ uint32_t bufb[NTT_ROWS_BLOCK];
-    __shared__ uint32_t tw[2048];
-    int64_t local;
-    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
+template <int Q>
+__device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32_t *bufa, uint32_t *bufb,
+                                          uint32_t *tw) {
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
     const int gl = k - 12;  // log2 of the blocks of one prime: N / NTT_ROWS_BLOCK
-    const int q = (int)(local >> gl);
+    constexpr int q = Q;
     const int64_t base = (local & (((int64_t)1 << gl) - 1)) * NTT_ROWS_BLOCK;  // whole rows, contiguous
     const int64_t r0 = base >> k2;  // first row of the block
-    const NttPrime P = ntt_prime(q);
+    constexpr NttPrime P = ntt_prime_c(Q);
     load_twiddles<false>(tw, q, k2, P);
     uint32_t *x = J.x + ((int64_t)q << k) + base;
     const uint32_t *y = J.y + ((int64_t)q << k) + base;
@@ -317,7 +344,7 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
     lds_transform_any<true, NTT_ROWS_BLOCK>(k2, bufa, 1 << k2, tw, P);
     // inverse twiddle w_N^-(n2 k1) and the scale R / N (the pointwise product left R^-1):
     // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N
-    const uint32_t K = q == 0 ? J.kscale[0] : J.kscale[1];  // (a dynamic index would copy the job to scratch)
+    const uint32_t K = J.kscale[Q];
 #pragma unroll 1
     for (int i0 = 0; i0 < EPT_R; i0 += CH) {
         uint32_t a[CH], b[CH];
@@ -338,17 +365,26 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
     }
 }
 
-__global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L) {
-    __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
+__global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
+    __shared__ uint32_t bufa[NTT_ROWS_BLOCK];
+    __shared__ uint32_t bufb[NTT_ROWS_BLOCK];
     __shared__ uint32_t tw[2048];
     int64_t local;
-    const NttJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
+    const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
+    if ((local >> (J.k1 + J.k2 - 12)) == 0)
+        rows_body<0>(J, local, bufa, bufb, tw);
+    else
+        rows_body<1>(J, local, bufa, bufb, tw);
+}
+
+template <int Q>
+__device__ __forceinline__ void inv_cols_body(const NttJob &J, int64_t local, uint32_t *buf, uint32_t *tw) {
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
     const int lc = 13 - k1, C = 1 << lc, S = (1 << k1) + 1;
     const int gl = k - 13;
-    const int q = (int)(local >> gl);
+    constexpr int q = Q;
     const int64_t c0 = (local & (((int64_t)1 << gl) - 1)) * C;
-    const NttPrime P = ntt_prime(q);
+    constexpr NttPrime P = ntt_prime_c(Q);
     load_twiddles<true>(tw, q, k1, P);
     uint32_t *x = J.x + ((int64_t)q << k);
     const int t = threadIdx.x;
@@ -376,6 +412,17 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L)
         const int c = e & (C - 1), n1 = e >> lc;
         stg(x + ((int64_t)n1 << k2) + c0 + c, red1(red2(buf[c * S + n1], P.p), P.p));
     }
+}
+
+__global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L) {
+    __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
+    __shared__ uint32_t tw[NTT_COL_TW];
+    int64_t local;
+    const NttJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
+    if ((local >> (J.k1 + J.k2 - 13)) == 0)
+        inv_cols_body<0>(J, local, buf, tw);
+    else
+        inv_cols_body<1>(J, local, buf, tw);
 }
 
 // the join: one thread per limb column, the (at most two for w >= 16, three for w >= 11) terms
