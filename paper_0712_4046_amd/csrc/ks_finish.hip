@@ -294,7 +294,11 @@ __device__ __forceinline__ void chain_seg(const ChainJob &J, int64_t s, uint32_t
         load_raw(ru[j], J.A, J.nA, cc * (int64_t)Nd);
         load_raw(rw[j], J.B, J.nB, (m - (cc + 1)) * (int64_t)Nd);
     };
-    // step c: digits from ring slot j, which is refilled with step c + P's
+    // step c: digits from ring slot j, which is refilled with step c + P's; alpha_c and beta_c
+    // (for the finishing pass) go to ab[j] -- in whole rounds they are stored after the round,
+    // behind the round's refills: memory operations complete in order for the wait counter, so
+    // a store issued between a refill and its use would put the store's latency on every step
+    uint32_t ab[P][2 * NW];
     auto step = [&](int j, int64_t c) {
         const MW<NW> u = raw_digit(ru[j], J.nA, c * (int64_t)Nd, Nd);
         const MW<NW> wn = raw_digit(rw[j], J.nB, (m - (c + 1)) * (int64_t)Nd, Nd);
@@ -307,14 +311,11 @@ __device__ __forceinline__ void chain_seg(const ChainJob &J, int64_t s, uint32_t
         sigma = add_bit(beta, delta);                // sigma_c = beta_c + delta
         aprev = alpha;
         wc = wn;
-        // alpha_c and beta_c for the finishing pass, one vector store
-        uint32_t ab[2 * NW];
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
-            ab[t] = alpha.w[t];
-            ab[NW + t] = beta.w[t];
+            ab[j][t] = alpha.w[t];
+            ab[j][NW + t] = beta.w[t];
         }
-        stg_words<2 * NW>(J.hbuf + c * (2 * NW), ab);
     };
 #pragma unroll
     for (int j = 0; j < P; ++j) fetch(j, k0 + j);
@@ -323,12 +324,17 @@ __device__ __forceinline__ void chain_seg(const ChainJob &J, int64_t s, uint32_t
         for (; cb + P <= k1; cb += P) {
 #pragma unroll
             for (int j = 0; j < P; ++j) step(j, cb + j);
+            // the round's P (alpha, beta) pairs are contiguous: wide stores
+            stg_words<2 * NW * P>(J.hbuf + cb * (2 * NW), &ab[0][0]);
         }
     }
     for (; cb < k1; cb += P) {
 #pragma unroll
         for (int j = 0; j < P; ++j)
-            if (cb + j < k1) step(j, cb + j);
+            if (cb + j < k1) {
+                step(j, cb + j);
+                stg_words<2 * NW>(J.hbuf + (cb + j) * (2 * NW), ab[j]);
+            }
     }
     // self-checks: the segment ends on the next anchor; the chain ends on the two unused relations
     bool ok = true;
