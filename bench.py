@@ -56,7 +56,9 @@ NTT_STEPS = {"ntt_fwd_cols": (2, 0), "ntt_rows": (3, 1), "ntt_inv_cols": (1, 0)}
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated: FETCH x2, WRITE
 # x1) on the headline workload (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).
-MEASURED_TRAFFIC_C4 = {}
+MEASURED_TRAFFIC_C4 = {"pack": 402730252, "ntt_fwd_cols": 1217781532, "ntt_rows": 1615455525,
+                       "ntt_inv_cols": 1076716558, "ntt_join": 975776029, "normalize": 823656284,
+                       "recon": 349765242, "finish": 271327081}
 KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "ntt_fwd_cols", "ntt_rows",
            "ntt_inv_cols", "ntt_join", "normalize", "anchor", "recon", "finish", "extract", "p2_eval", "p2_recon")
 METRIC = "polynomial products/s + limb-mults/s at 1 GPU; KS4 vs KS1 speedup, bit-exact"
@@ -351,6 +353,15 @@ def paper_sweep(ks, torch, wl):
     t(KS1) / t(variant), the quantity of the paper's Figures 1 and 2.  Each variant's result must
     equal KS1's."""
     out = {}
+    # the serving loop before this ends with seconds of host-only checking: bring the GPU back
+    # to its working clock before timing microsecond-scale products
+    n0, f0, g0 = wl.paper_fig_pair(wl.PAPER_FIG_BITS[0], wl.PAPER_FIG_LENGTHS[0])
+    tf0, tg0 = torch.from_numpy(f0.view(np.int64)).cuda(), torch.from_numpy(g0.view(np.int64)).cuda()
+    t_end = time.perf_counter() + 0.3
+    while time.perf_counter() < t_end:
+        for _ in range(50):
+            ks.mul_mod(tf0, tg0, n0, "ks1")
+        torch.cuda.synchronize()
     for nb in wl.PAPER_FIG_BITS:
         rows = []
         n = None
