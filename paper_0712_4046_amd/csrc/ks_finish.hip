@@ -349,13 +349,139 @@ __device__ __forceinline__ void chain_seg(const ChainJob &J, int64_t s, uint32_t
 #undef W_DIGIT
 }
 
+// ---- the chain's fast path ----------------------------------------------------------------------
+//
+// When every digit a segment reads lies inside A and B (the recombined products hold
+// ceil((m + 1) Nd / 32) + 1 limbs, which covers the NW + 1 words of digit m - 1 once Nd >= 16) and
+// the bit offsets fit in 32 bits, a step needs no bounds checks: a digit is NW funnel shifts
+// of the NW + 1 words one vector load brought in, and the chain's state is (beta, delta) rather
+// than sigma = beta + delta, so that alpha = (u - beta - delta) mod Y and delta' = [u < sigma]
+// come out of one subtraction with borrow.
+template <int NW>
+__device__ __forceinline__ bool chain_fast_ok(const ChainJob &J) {
+    const int64_t top = (((J.m - 1) * (int64_t)J.Nd) >> 5) + NW;
+    return J.Nd >= 16 && J.m >= 1 && (J.m + 1) * (int64_t)J.Nd < ((int64_t)1 << 31) && top < J.nA &&
+           top < J.nB;
+}
+
+// a - b - bin over NW words into r; returns the borrow out, [a < b + bin]
+template <int NW>
+__device__ __forceinline__ uint32_t mw_sub_borrow(const MW<NW> &a, const MW<NW> &b, uint32_t bin, MW<NW> &r) {
+    uint32_t br = bin;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+        const uint64_t d = (uint64_t)a.w[t] - b.w[t] - br;
+        r.w[t] = (uint32_t)d;
+        br = (uint32_t)(d >> 63);
+    }
+    return br;
+}
+
+template <int NW>
+__device__ __forceinline__ MW<NW> funnel_digit(const uint32_t (&l)[NW + 1], uint32_t sh, uint32_t topmask) {
+    MW<NW> d;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) d.w[t] = __builtin_amdgcn_alignbit(l[t + 1], l[t], sh);
+    d.w[NW - 1] &= topmask;
+    return d;
+}
+
+template <int NW>
+__device__ __forceinline__ void chain_seg_fast(const ChainJob &J, int64_t s, uint32_t *devstat) {
+    constexpr int P = ChainRing<NW>::P;
+    if (s >= J.nseg) return;
+    const uint32_t Nd = (uint32_t)J.Nd;
+    const int64_t m = J.m;
+    const int64_t k0 = s * J.K;
+    const int64_t k1 = k0 + J.K < m ? k0 + J.K : m;
+    const int hw = (int)((2 * Nd + 31) >> 5);
+    const uint32_t tb = Nd - 32u * (NW - 1);
+    const uint32_t topmask = tb >= 32 ? 0xffffffffu : (1u << tb) - 1u;
+    const uint32_t mm1 = (uint32_t)(m - 1), last = (uint32_t)(k1 - 1);
+    MW<NW> beta, aprev, wc;
+    uint32_t dl = 0;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) { beta.w[t] = 0; aprev.w[t] = 0; }
+    if (s > 0) {
+        const uint32_t *anc = J.anchors + s * J.aw;
+        const MW<NW> al = read_digit<NW>(anc, J.aw, 0, (int)Nd);
+        beta = read_digit<NW>(anc, J.aw, Nd, (int)Nd);
+        const MW<NW> u = read_digit<NW>(J.A, J.nA, (k0 - 1) * (int64_t)Nd, (int)Nd);
+        aprev = al;
+        MW<NW> scratch;
+        dl = mw_sub_borrow(u, al, 0u, scratch);  // [u < al]: sigma = beta + dl
+    }
+    wc = read_digit<NW>(J.B, J.nB, (m - k0) * (int64_t)Nd, (int)Nd);
+    MW<NW> alpha = aprev;
+    uint32_t ru[P][NW + 1], rw[P][NW + 1], su[P], sw[P];
+    // step c's words (clamped to the segment's last step: a refill past it reads words that stay
+    // unused); B's digit of step c is w_{c+1}, at m - c - 1
+    auto fetch = [&](int j, int64_t c) {
+        const uint32_t cc = c < k1 ? (uint32_t)c : last;
+        const uint32_t ou = cc * Nd, ow = (mm1 - cc) * Nd;
+        ldg_words<NW + 1>(J.A + (ou >> 5), ru[j]);
+        ldg_words<NW + 1>(J.B + (ow >> 5), rw[j]);
+        su[j] = ou & 31u;
+        sw[j] = ow & 31u;
+    };
+    uint32_t ab[P][2 * NW];
+    auto step = [&](int j, int64_t c) {
+        const MW<NW> u = funnel_digit<NW>(ru[j], su[j], topmask);
+        const MW<NW> wn = funnel_digit<NW>(rw[j], sw[j], topmask);
+        fetch(j, c + P);
+        __builtin_amdgcn_sched_barrier(0);
+        dl = mw_sub_borrow(u, beta, dl, alpha);  // alpha_c = u_c - sigma_{c-1}, delta_c
+        alpha.w[NW - 1] &= topmask;
+        MW<NW> scratch;
+        const uint32_t eps = mw_sub_borrow(wn, alpha, 0u, scratch);  // [w_{c+1} < alpha_c]
+        mw_sub_borrow(wc, aprev, eps, beta);                         // beta_c = w_c - alpha_{c-1} - eps_c
+        beta.w[NW - 1] &= topmask;
+        aprev = alpha;
+        wc = wn;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            ab[j][t] = alpha.w[t];
+            ab[j][NW + t] = beta.w[t];
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < P; ++j) fetch(j, k0 + j);
+    int64_t cb = k0;
+    for (; cb + P <= k1; cb += P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) step(j, cb + j);
+        stg_words<2 * NW * P>(J.hbuf + cb * (2 * NW), &ab[0][0]);  // after the round's refills
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+        if (cb + j < k1) {
+            step(j, cb + j);
+            stg_words<2 * NW>(J.hbuf + (cb + j) * (2 * NW), ab[j]);
+        }
+    // self-checks, as in chain_seg
+    bool ok = true;
+    if (k1 < m) {
+        const uint32_t *anc = J.anchors + (s + 1) * J.aw;
+        for (int t = 0; t < J.aw; ++t) ok = ok && (anc[t] == (t < hw ? hword(alpha, beta, (int)Nd, t) : 0u));
+    } else if (k1 > k0) {
+        const MW<NW> sigma = add_bit(beta, dl);
+        ok = mw_eq(alpha, read_digit<NW>(J.B, J.nB, 0, (int)Nd)) &&
+             mw_eq(sigma, read_digit<NW>(J.A, J.nA, m * (int64_t)Nd, (int)Nd));
+    }
+    if (!ok) set_status(devstat, KS_DEVSTAT_CHECK);
+}
+
 // A job's blocks of CHAIN_TPB lanes take its segments in order (single products).
 template <int NW>
 __global__ __launch_bounds__(CHAIN_TPB) void chain_kernel(Launch<ChainJob> L) {
     int64_t local;
     const ChainJob J = get_job(L, (int64_t)blockIdx.x, local);
     const int64_t s = local * CHAIN_TPB + threadIdx.x;
-    if (s < J.nseg) chain_seg<NW, false>(J, s, L.devstat);
+    if (s >= J.nseg) return;
+    if (chain_fast_ok<NW>(J))
+        chain_seg_fast<NW>(J, s, L.devstat);
+    else
+        chain_seg<NW, false>(J, s, L.devstat);
 }
 
 // Batches: the launch's units are segments, not blocks (a job's block0 and nblocks count its
@@ -369,18 +495,22 @@ __global__ __launch_bounds__(CHAIN_TPB) void chain_lanes_kernel(Launch<ChainJob>
     int64_t s;
     const ChainJob J = get_job(L, g, s);
     if constexpr (NW > 0) {
-        chain_seg<NW, true>(J, s, L.devstat);
+        if (chain_fast_ok<NW>(J))
+            chain_seg_fast<NW>(J, s, L.devstat);
+        else
+            chain_seg<NW, true>(J, s, L.devstat);
     } else {
         switch ((J.Nd + 31) >> 5) {
-            case 1: chain_seg<1, true>(J, s, L.devstat); break;
-            case 2: chain_seg<2, true>(J, s, L.devstat); break;
-            case 3: chain_seg<3, true>(J, s, L.devstat); break;
-            case 4: chain_seg<4, true>(J, s, L.devstat); break;
-            case 5: chain_seg<5, true>(J, s, L.devstat); break;
-            case 6: chain_seg<6, true>(J, s, L.devstat); break;
-            case 7: chain_seg<7, true>(J, s, L.devstat); break;
-            case 8: chain_seg<8, true>(J, s, L.devstat); break;
-            case 9: chain_seg<9, true>(J, s, L.devstat); break;
+#define KS_CHAIN_CASE(W)                        \
+    case W:                                     \
+        if (chain_fast_ok<W>(J))                \
+            chain_seg_fast<W>(J, s, L.devstat); \
+        else                                    \
+            chain_seg<W, true>(J, s, L.devstat); \
+        break;
+            KS_CHAIN_CASE(1) KS_CHAIN_CASE(2) KS_CHAIN_CASE(3) KS_CHAIN_CASE(4) KS_CHAIN_CASE(5)
+            KS_CHAIN_CASE(6) KS_CHAIN_CASE(7) KS_CHAIN_CASE(8) KS_CHAIN_CASE(9)
+#undef KS_CHAIN_CASE
             default: break;
         }
     }
