@@ -158,4 +158,164 @@ __device__ __forceinline__ void anchor_block(const AnchorJob &J, int64_t local) 
     }
 }
 
+// acc (AW words) += 2^(32 c) clo/chi (the NC 96-bit column sums) and the sign corrections
+template <int W>
+__device__ __forceinline__ void anchor_collect(uint32_t (&acc)[2 * W + 2], const uint64_t (&clo)[2 * W - 1],
+                                               const uint32_t (&chi)[2 * W - 1], const uint64_t (&corr)[W],
+                                               uint32_t nn, bool sgn) {
+    constexpr int AW = 2 * W + 2, NC = 2 * W - 1;
+#pragma unroll
+    for (int t = 0; t < AW; ++t) acc[t] = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t v[3] = {(uint32_t)clo[c], (uint32_t)(clo[c] >> 32), chi[c]};
+        add_words(acc, c, v);
+    }
+    if (sgn) {
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            const uint32_t v[2] = {(uint32_t)corr[t], (uint32_t)(corr[t] >> 32)};
+            sub_words(acc, W + t, v);
+        }
+        const uint32_t v[1] = {nn};
+        add_words(acc, 2 * W, v);
+    }
+}
+
+// one term f_i g_j into a column-sum accumulator (and its sign corrections)
+template <int W>
+__device__ __forceinline__ void anchor_term(uint64_t (&clo)[2 * W - 1], uint32_t (&chi)[2 * W - 1],
+                                            uint64_t (&corr)[W], uint32_t &nn, const uint32_t *a,
+                                            const uint32_t *b, bool sgn) {
+#pragma unroll
+    for (int x = 0; x < W; ++x)
+#pragma unroll
+        for (int y = 0; y < W; ++y) mac96(clo[x + y], chi[x + y], a[x], b[y]);
+    if (sgn) {
+        const bool nf = a[W - 1] >> 31, ng = b[W - 1] >> 31;
+#pragma unroll
+        for (int t = 0; t < W; ++t) corr[t] += (uint64_t)(nf ? b[t] : 0u) + (ng ? a[t] : 0u);
+        nn += (nf && ng) ? 1u : 0u;
+    }
+}
+
+// Two anchors in one pass: h_k for job J's chain (anchor s) and h_{k+1} for its second chain
+// (anchor s of anchors2, when s < nseg2).  Both read f_i against neighbouring coefficients of
+// g, so the pair costs one stream of the inputs instead of two: the two g coefficients of a
+// term, g_{k-i} and g_{k+1-i}, come in one vector load.  Terms where only one of the two g's
+// lies inside g (i = k - lg + 1 for h_k, i = k + 1 for h_{k+1}) are added by thread 0.
+template <int W>
+__device__ __forceinline__ void anchor_pair_block(const AnchorJob &J, int64_t local) {
+    constexpr int AW = 2 * W + 2, NC = 2 * W - 1;
+    __shared__ uint32_t s_acc2[ANCHOR_TPB / 64][2][AW];
+    const int64_t s = local + 1;
+    const int64_t k = J.kstep * (s * J.K - 1) + J.par;
+    int64_t lo = k - (J.lg - 2);  // g_{k-i} and g_{k+1-i} both inside g
+    if (lo < 0) lo = 0;
+    const int64_t hi = k < J.lf - 1 ? k : J.lf - 1;
+    const bool sgn = J.sgn != 0;
+    uint64_t clo[2][NC], corr[2][W];
+    uint32_t chi[2][NC], nn[2] = {0u, 0u};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { clo[h][c] = 0; chi[h][c] = 0; }
+#pragma unroll
+        for (int t = 0; t < W; ++t) corr[h][t] = 0;
+    }
+    constexpr int U = 4;
+    for (int64_t i0 = lo + threadIdx.x; i0 <= hi; i0 += U * ANCHOR_TPB) {
+        uint32_t a[U][W], b[U][2 * W];
+        bool live[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t i = i0 + (int64_t)q * ANCHOR_TPB;
+            live[q] = i <= hi;
+            const int64_t ii = live[q] ? i : lo;
+            load_raw<W>(J.f + ii * W, a[q]);
+            ldg_words<2 * W>(J.g + (k - ii) * W, b[q]);  // g_{k-i}, g_{k-i+1}
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+#pragma unroll
+            for (int x = 0; x < W; ++x) a[q][x] = live[q] ? a[q][x] : 0u;
+            anchor_term<W>(clo[0], chi[0], corr[0], nn[0], a[q], b[q], sgn);
+            anchor_term<W>(clo[1], chi[1], corr[1], nn[1], a[q], b[q] + W, sgn);
+        }
+    }
+    if (threadIdx.x == 0) {
+        const int64_t ie = k - (J.lg - 1);  // h_k's term with g_{lg-1}
+        if (ie >= 0 && ie <= hi) {
+            uint32_t a[W], b[W];
+            load_raw<W>(J.f + ie * W, a);
+            load_raw<W>(J.g + (J.lg - 1) * W, b);
+            anchor_term<W>(clo[0], chi[0], corr[0], nn[0], a, b, sgn);
+        }
+        if (k + 1 <= J.lf - 1 && k + 1 >= 0) {  // h_{k+1}'s term with g_0
+            uint32_t a[W], b[W];
+            load_raw<W>(J.f + (k + 1) * W, a);
+            load_raw<W>(J.g, b);
+            anchor_term<W>(clo[1], chi[1], corr[1], nn[1], a, b, sgn);
+        }
+    }
+    uint32_t acc[2][AW];
+    anchor_collect<W>(acc[0], clo[0], chi[0], corr[0], nn[0], sgn);
+    anchor_collect<W>(acc[1], clo[1], chi[1], corr[1], nn[1], sgn);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t o[AW];
+#pragma unroll
+            for (int t = 0; t < AW; ++t) o[t] = (uint32_t)__shfl_down((int)acc[h][t], d, 64);
+            uint64_t c = 0;
+#pragma unroll
+            for (int t = 0; t < AW; ++t) {
+                const uint64_t sm = (uint64_t)acc[h][t] + o[t] + c;
+                acc[h][t] = (uint32_t)sm;
+                c = sm >> 32;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int t = 0; t < AW; ++t) s_acc2[wv][h][t] = acc[h][t];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            for (int q = 1; q < ANCHOR_TPB / 64; ++q) {
+                uint64_t c = 0;
+#pragma unroll
+                for (int t = 0; t < AW; ++t) {
+                    const uint64_t sm = (uint64_t)acc[h][t] + s_acc2[q][h][t] + c;
+                    acc[h][t] = (uint32_t)sm;
+                    c = sm >> 32;
+                }
+            }
+            if (J.off_bit >= 0) {
+                uint64_t c = 0;
+#pragma unroll
+                for (int t = 0; t < AW; ++t) {
+                    const uint32_t add = ((J.off_bit >> 5) == t) ? (1u << (J.off_bit & 31)) : 0u;
+                    const uint64_t sm = (uint64_t)acc[h][t] + add + c;
+                    acc[h][t] = (uint32_t)sm;
+                    c = sm >> 32;
+                }
+            }
+        }
+        uint32_t *dst = J.anchors + s * J.aw;
+#pragma unroll
+        for (int t = 0; t < AW; ++t) dst[t] = acc[0][t];
+        if (s < J.nseg2) {
+            uint32_t *dst2 = J.anchors2 + s * J.aw;
+#pragma unroll
+            for (int t = 0; t < AW; ++t) dst2[t] = acc[1][t];
+        }
+    }
+}
+
 }  // namespace ks

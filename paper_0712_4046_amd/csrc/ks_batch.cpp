@@ -383,7 +383,7 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
         sh(j.x);
         sh(j.cols);
     }
-    for (auto &kv : JL.anchor) for (auto &j : kv.second) sh(j.anchors);
+    for (auto &kv : JL.anchor) for (auto &j : kv.second) { sh(j.anchors); sh(j.anchors2); }
     for (auto *nl : {&JL.norm, &JL.norm_small})
         for (auto &j : *nl) {
             for (int q = 0; q < j.nterms; ++q) { sh(j.term[q].cols); sh(j.term[q].a); sh(j.term[q].b); }

@@ -374,6 +374,7 @@ template <> __device__ __forceinline__ void rebase(AnchorJob &J, const Launch<An
     J.f = at(L.base_in, J.f);
     J.g = at(L.base_in, J.g);
     J.anchors = at(L.base_ws, J.anchors);
+    J.anchors2 = at(L.base_ws, J.anchors2);
 }
 template <> __device__ __forceinline__ void rebase(ChainJob &J, const Launch<ChainJob> &L) {
     J.A = at(L.base_ws, J.A);

@@ -87,7 +87,10 @@ template <int W>
 __global__ __launch_bounds__(ANCHOR_TPB) void anchor_kernel(Launch<AnchorJob> L) {
     int64_t local;
     const AnchorJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
-    anchor_block<W>(J, local);
+    if (J.nseg2 > 0)
+        anchor_pair_block<W>(J, local);
+    else
+        anchor_block<W>(J, local);
 }
 
 // ---- chains ------------------------------------------------------------------------------------

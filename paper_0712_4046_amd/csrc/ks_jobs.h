@@ -244,6 +244,11 @@ struct AnchorJob {
     uint32_t *anchors;  // nseg * aw limbs; entry 0 unused
     int32_t off_bit;    // -1: nothing added
     int32_t kstep;      // anchor s is coefficient kstep (s K - 1) + par
+    // a second chain whose anchor s is the next coefficient, kstep (s K - 1) + par + 1 (the odd
+    // chain beside the even one): computed in the same pass for s < nseg2 (0: no second chain;
+    // anchors2 then repeats anchors)
+    uint32_t *anchors2;
+    int64_t nseg2;
     int64_t block0;
     int64_t nblocks;
 };

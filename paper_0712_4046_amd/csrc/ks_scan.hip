@@ -48,7 +48,10 @@ __global__ __launch_bounds__(SCAN_TPB) void pack_anchor_kernel(Launch<PackJob> L
         // block a runs on XCD (total pack blocks + a) mod 8, so the grouping is shifted alike
         const int64_t a = (int64_t)blockIdx.x - Lp.total_blocks;
         const AnchorJob J = get_job(La, xcd_block(a, La.total_blocks), local);
-        anchor_block<W>(J, local);
+        if (J.nseg2 > 0)
+            anchor_pair_block<W>(J, local);
+        else
+            anchor_block<W>(J, local);
     }
 }
 
