@@ -174,6 +174,24 @@ def test_graph_capture_replays(torch_dev, oracle):
     plan.close()
 
 
+def test_transform_rows_of_two_sizes_in_one_batch(torch_dev, oracle):
+    # one batch whose transform products have rows of 2048 (2^22 terms) and of 4096 (2^23, the
+    # longest transform), sampled against the oracle
+    gen = wl.rng(4242)
+    B = ks.Batch()
+    prods = []
+    for L in (65536, 98304):
+        f, g = wl.random_coeffs(gen, L, 256, True), wl.random_coeffs(gen, L, 256, True)
+        prods.append((B.add(f, g, 256, True), f, g))
+    out = run_batch(torch_dev, B, "ks1", "ntt")
+    for i, f, g in prods:
+        L = f.shape[0]
+        D = 2 * L - 1
+        idx = np.unique(np.concatenate([np.arange(0, 4), np.arange(D - 4, D), gen.integers(0, D, 24)]))
+        exp = oracle.coeffs_classical(f, g, True, idx, oracle.out_limbs(L, L, 256))
+        assert np.array_equal(B.result(out, i)[idx], exp), L
+
+
 def test_invalid_descriptor_named(torch_dev):
     B = ks.Batch()
     f = np.zeros((4, 1), dtype=np.uint32)

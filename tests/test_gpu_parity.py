@@ -232,6 +232,23 @@ def test_transform_engine_extreme_terms(torch_dev, oracle, kind, signed):
     assert np.array_equal(ks.to_host(h)[idx], exp)
 
 
+def test_transform_engine_longest_transform(torch_dev, oracle):
+    # L = 98304 signed 256-bit coefficients through the standard substitution: the planner
+    # reaches the longest transform (2^23 terms, rows of 4096 in the row step), sampled against
+    # the oracle
+    L, bits = 98304, 256
+    plan = ks.plan(L, L, bits, "ks1", True, "ntt")
+    assert plan["ntt_k1"] + plan["ntt_k2"] == 23 and plan["ntt_k2"] == 12
+    gen = wl.rng(2323)
+    f, g = wl.random_coeffs(gen, L, bits, True), wl.random_coeffs(gen, L, bits, True)
+    D = 2 * L - 1
+    idx = np.unique(np.concatenate([np.arange(0, 8), np.arange(D - 8, D), gen.integers(0, D, 40)]))
+    exp = oracle.coeffs_classical(f, g, True, idx, oracle.out_limbs(L, L, bits))
+    h = ks.mul(ks.to_device(f), ks.to_device(g), bits, "ks1", True, engine="ntt")
+    assert ks.status() == ks.KS_OK
+    assert np.array_equal(ks.to_host(h)[idx], exp)
+
+
 def test_invalid_arguments(torch_dev):
     torch = torch_dev
     t = torch.zeros((4, 1), dtype=torch.int32, device="cuda")
