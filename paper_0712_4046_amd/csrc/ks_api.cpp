@@ -798,11 +798,14 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
     auto first_anchor = JL.anchor.begin();
     {
         auto L = make_launch(JL.pack, T ? &T->pack : nullptr, env, epoch_pack, env.ctr_pack);
+        int pack_w = 0;  // the widest input coefficient selects the pack's register layout
+        for (const auto &j : JL.pack) pack_w = std::max(pack_w, (int)j.w_in);
         if (first_anchor != JL.anchor.end()) {
             auto La = make_launch(first_anchor->second, T ? &T->anchor.at(first_anchor->first) : nullptr, env, 0);
-            err = timed("pack", s, [&] { return launch_pack_anchor(L, La, first_anchor->first, JL.ipt, s); });
+            err = timed("pack", s,
+                        [&] { return launch_pack_anchor(L, La, first_anchor->first, JL.ipt, pack_w, s); });
         } else {
-            err = timed("pack", s, [&] { return launch_pack(L, JL.ipt, s); });
+            err = timed("pack", s, [&] { return launch_pack(L, JL.ipt, pack_w, s); });
         }
         if (err != hipSuccess) return KS_EHIP;
     }

@@ -28,10 +28,11 @@ inline void ks_launch(K kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t
     }
 }
 
-// ipt: limbs per thread of the carry-scan kernels (SCAN_IPT_SINGLE or SCAN_IPT_BATCH), as planned
-hipError_t launch_pack(const Launch<PackJob> &L, int ipt, hipStream_t s);
+// ipt: limbs per thread of the carry-scan kernels (SCAN_IPT_SINGLE or SCAN_IPT_BATCH), as planned;
+// pack_w: the widest input coefficient (limbs) among the pack jobs
+hipError_t launch_pack(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_t s);
 hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, int ipt,
-                              hipStream_t s);
+                              int pack_w, hipStream_t s);
 hipError_t launch_normalize(const Launch<NormJob> &L, int ipt, hipStream_t s);
 hipError_t launch_pack_small(const Launch<PackJob> &L, int ipt, hipStream_t s);
 hipError_t launch_normalize_small(const Launch<NormJob> &L, int ipt, hipStream_t s);

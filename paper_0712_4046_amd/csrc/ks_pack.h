@@ -11,14 +11,17 @@ namespace ks {
 // the block's range that the carry scan needs are filled the same way.
 constexpr int PK_MAXW = 8;  // limbs of one input coefficient (coeff_bits <= 256)
 
-// bits [s, s+32) of a coefficient held in registers (s may be negative: bits below 0 read 0)
-__device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[PK_MAXW], int w, uint32_t fill, int s) {
+// bits [s, s+32) of a coefficient held in registers (s may be negative: bits below 0 read 0);
+// MW bounds the coefficient's limbs (a launch whose inputs are all one or two limbs wide, like
+// residues modulo p < 2^62, selects among two words instead of eight)
+template <int MW>
+__device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[MW], int w, uint32_t fill, int s) {
     if (s <= -32) return 0u;
     if (s < 0) return cl[0] << (-s);
     const int q = s >> 5, o = s & 31;
     uint32_t a = fill, b = fill;
 #pragma unroll
-    for (int t = 0; t < PK_MAXW; ++t) {
+    for (int t = 0; t < MW; ++t) {
         if (t < w && t == q) a = cl[t];
         if (t < w && t == q + 1) b = cl[t];
     }
@@ -28,7 +31,7 @@ __device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[PK_MAXW], int 
 // A block of pack job J with TPB threads (TPB * IPT limbs per block); `local` is its position
 // in the job when the job has one block (else it draws a ticket).  The caller looks the job
 // up in its own kernel arguments.
-template <int TPB, int IPT>
+template <int TPB, int IPT, int MW = PK_MAXW>
 __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, const LaunchCtl L) {
     constexpr int64_t BL = (int64_t)TPB * IPT;
     typedef BlockCarryScan<TPB, IPT> Scan;
@@ -52,7 +55,7 @@ __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, cons
     if (i1 > J.L - 1) i1 = J.L - 1;
     constexpr int U = 4;  // coefficients per thread per round, loads issued together
     for (int64_t ib = i0 + tid; ib <= i1; ib += U * TPB) {
-        uint32_t cl[U][PK_MAXW];
+        uint32_t cl[U][MW];
         const uint32_t *cq[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -61,14 +64,16 @@ __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, cons
             const int64_t src = (J.flags & PK_REVERSE) ? J.L - 1 - ii : ii;
             cq[q] = J.coeffs + src * w_in;
 #pragma unroll
-            for (int t = 0; t < PK_MAXW; ++t) cl[q][t] = 0u;
+            for (int t = 0; t < MW; ++t) cl[q][t] = 0u;
         }
         // the round's coefficients with vector loads of exactly w_in words each, all in one
         // block (w_in is uniform: one scalar branch per round)
         switch (w_in) {
-#define PK_LOAD(W)                                                              \
-    case W:                                                                     \
-        _Pragma("unroll") for (int q = 0; q < U; ++q) ldg_words<W>(cq[q], cl[q]); \
+#define PK_LOAD(W)                                                                                  \
+    case W:                                                                                         \
+        if constexpr (W <= MW) {                                                                    \
+            _Pragma("unroll") for (int q = 0; q < U; ++q) ldg_words<W>(cq[q], cl[q]);               \
+        }                                                                                           \
         break;
             PK_LOAD(1) PK_LOAD(2) PK_LOAD(3) PK_LOAD(4) PK_LOAD(5) PK_LOAD(6) PK_LOAD(7) PK_LOAD(8)
 #undef PK_LOAD
@@ -80,7 +85,7 @@ __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, cons
             if (i > i1) continue;
             uint32_t top = 0;
 #pragma unroll
-            for (int t = 0; t < PK_MAXW; ++t) top = (t == w_in - 1) ? cl[q][t] : top;
+            for (int t = 0; t < MW; ++t) top = (t == w_in - 1) ? cl[q][t] : top;
             const uint32_t fill = (sgn && (top >> 31)) ? 0xffffffffu : 0u;
             const int64_t p = i * N;
             const int64_t w = p >> 5;

@@ -19,11 +19,11 @@ namespace ks {
 
 // ---- pack ------------------------------------------------------------------------------------
 
-template <int IPT>
+template <int IPT, int MW = PK_MAXW>
 __global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) {
     int64_t local;
     const PackJob J = get_job(L, (int64_t)blockIdx.x, local);
-    pack_block<SCAN_TPB, IPT>(J, local, ctl_of(L));
+    pack_block<SCAN_TPB, IPT, MW>(J, local, ctl_of(L));
 }
 
 // jobs of at most small_bl(IPT) limbs (one block each): one wave per job
@@ -37,12 +37,12 @@ __global__ __launch_bounds__(SMALL_TPB) void pack_small_kernel(Launch<PackJob> L
 // Pack and anchors in one launch: blocks [0, pack blocks) pack,
 // the rest compute anchors, which read only the inputs and so run beside the packing.
 static_assert(SCAN_TPB == ANCHOR_TPB, "pack and anchor blocks share one launch");
-template <int W, int IPT>
+template <int W, int IPT, int MW = PK_MAXW>
 __global__ __launch_bounds__(SCAN_TPB) void pack_anchor_kernel(Launch<PackJob> Lp, Launch<AnchorJob> La) {
     int64_t local;
     if ((int64_t)blockIdx.x < Lp.total_blocks) {
         const PackJob J = get_job(Lp, (int64_t)blockIdx.x, local);
-        pack_block<SCAN_TPB, IPT>(J, local, ctl_of(Lp));
+        pack_block<SCAN_TPB, IPT, MW>(J, local, ctl_of(Lp));
     } else {
         // a product's anchors re-read its inputs: keep them on one XCD (xcd_block); anchor
         // block a runs on XCD (total pack blocks + a) mod 8, so the grouping is shifted alike
@@ -259,15 +259,31 @@ hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s) {
             ks_launch(K<SCAN_IPT_SINGLE>, __VA_ARGS__);     \
     } while (0)
 
-hipError_t launch_pack(const Launch<PackJob> &L, int ipt, hipStream_t s) {
+hipError_t launch_pack(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    KS_SCAN_IPT(ipt, pack_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
+    const dim3 g((unsigned)L.total_blocks), b(SCAN_TPB);
+    if (pack_w <= 2) {
+        if (ipt == SCAN_IPT_BATCH)
+            ks_launch(pack_kernel<SCAN_IPT_BATCH, 2>, g, b, 0, s, L);
+        else
+            ks_launch(pack_kernel<SCAN_IPT_SINGLE, 2>, g, b, 0, s, L);
+    } else {
+        KS_SCAN_IPT(ipt, pack_kernel, g, b, 0, s, L);
+    }
     return hipGetLastError();
 }
 
 template <int IPT>
-static hipError_t pack_anchor_w(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, hipStream_t s) {
+static hipError_t pack_anchor_w(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, int pack_w,
+                                hipStream_t s) {
     dim3 g((unsigned)(Lp.total_blocks + La.total_blocks)), b(SCAN_TPB);
+    if (pack_w <= 2 && w_in <= 2) {  // every input one or two limbs wide (residues)
+        if (w_in == 1)
+            ks_launch(pack_anchor_kernel<1, IPT, 2>, g, b, 0, s, Lp, La);
+        else
+            ks_launch(pack_anchor_kernel<2, IPT, 2>, g, b, 0, s, Lp, La);
+        return hipGetLastError();
+    }
     switch (w_in) {
         case 1: ks_launch(pack_anchor_kernel<1, IPT>, g, b, 0, s, Lp, La); break;
         case 2: ks_launch(pack_anchor_kernel<2, IPT>, g, b, 0, s, Lp, La); break;
@@ -283,10 +299,10 @@ static hipError_t pack_anchor_w(const Launch<PackJob> &Lp, const Launch<AnchorJo
 }
 
 hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, int ipt,
-                              hipStream_t s) {
-    if (La.total_blocks <= 0) return launch_pack(Lp, ipt, s);
-    return ipt == SCAN_IPT_BATCH ? pack_anchor_w<SCAN_IPT_BATCH>(Lp, La, w_in, s)
-                                 : pack_anchor_w<SCAN_IPT_SINGLE>(Lp, La, w_in, s);
+                              int pack_w, hipStream_t s) {
+    if (La.total_blocks <= 0) return launch_pack(Lp, ipt, pack_w, s);
+    return ipt == SCAN_IPT_BATCH ? pack_anchor_w<SCAN_IPT_BATCH>(Lp, La, w_in, pack_w, s)
+                                 : pack_anchor_w<SCAN_IPT_SINGLE>(Lp, La, w_in, pack_w, s);
 }
 
 hipError_t launch_pack_small(const Launch<PackJob> &L, int ipt, hipStream_t s) {
