@@ -446,6 +446,18 @@ int plan_product(const Spec &sp, Geom &G) {
         }
     }
     G.norm_limbs = noff;
+    // recombinations of the same two products with signs (+, +) and (+, -) -- P0 and P1, Q0 and
+    // Q1 of the negated and four-point substitutions -- run as one job: the column windows are
+    // read once and feed two carry scans (the second looks back through words of its own)
+    for (size_t i = 0; i + 1 < G.norms.size(); ++i) {
+        NormGeom &a = G.norms[i], &b = G.norms[i + 1];
+        if (a.merged || a.small || b.small || a.nterms != 2 || b.nterms != 2 || a.prod[0] != b.prod[0] ||
+            a.prod[1] != b.prod[1] || a.off_period != b.off_period || a.blocks != b.blocks)
+            continue;
+        a.pair = (int)(i + 1);
+        b.merged = true;
+        G.norm_status_extra += a.blocks;
+    }
     for (auto &x : G.extracts) G.extract_blocks += x.blocks;
 
     // scratch layout (bytes)
@@ -457,7 +469,8 @@ int plan_product(const Spec &sp, Geom &G) {
     G.ws_anchors = o; o += align_up(std::max<int64_t>(G.anchor_limbs, 1) * 4, 256);
     G.ws_hbuf = o;    o += align_up(G.hbuf_words * 4, 256);
     G.ws_ntt = o;     o += align_up(G.ntt_words * 4, 256);
-    G.ws_status = o;  o += align_up(std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1) * 8, 256);
+    G.ws_status = o;
+    o += align_up(std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks + G.norm_status_extra), 1) * 8, 256);
     G.ws_bytes = o;
 
     // algorithmic HBM bytes: inputs, outputs, operands written+read, products written+read
@@ -525,6 +538,21 @@ hipError_t timed_launch(const char *name, hipStream_t s, const std::function<hip
 
 // Append the jobs of one planned product.  f, g, h, ws are addresses (single products) or byte
 // offsets from the run's bases (batches); each job's block0 continues its list.
+// the look-back words of paired recombinations' second scans: after every job's own blocks
+// (launched in block order), one range per paired job; returns the status words the norm list
+// needs in all
+int64_t assign_dual_status(JobLists &JL) {
+    int64_t total = 0;
+    for (const auto &j : JL.norm) total = std::max<int64_t>(total, j.block0 + j.nblocks);
+    int64_t extra = 0;
+    for (auto &j : JL.norm)
+        if (j.dual && j.nblocks > 1) {
+            j.status1 = total + extra;
+            extra += j.nblocks;
+        }
+    return total + extra;
+}
+
 void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t ws, JobLists &JL) {
     const Spec &sp = G.sp;
     JL.ipt = G.ipt;  // the products of one list are planned alike (all single or all batched)
@@ -683,6 +711,7 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         list.push_back(j);
     }
     for (auto &r : G.norms) {
+        if (r.merged) continue;  // its partner's job computes it
         NormJob j;
         memset(&j, 0, sizeof(j));
         j.nterms = r.nterms;
@@ -706,6 +735,19 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
         j.out = norms(r.out_off);
         j.n_out = r.n_out;
         j.n_in = r.n_in;
+        j.out2 = j.out;
+        if (r.pair >= 0) {
+            const NormGeom &r2 = G.norms[(size_t)r.pair];
+            j.dual = 1;
+            j.shift2 = r2.shift;
+            j.sign2[0] = r2.sign[0];
+            j.sign2[1] = r2.sign[1];
+            j.off_bit0_2 = r2.off_bit0;
+            j.off_count2 = r2.off_count;
+            j.out2 = norms(r2.out_off);
+            j.n_out2 = r2.n_out;
+            j.n_in = std::max(r.n_in, r2.n_in);
+        }
         auto &nl = r.small ? JL.norm_small : JL.norm;
         j.ctr = (int64_t)nl.size();
         j.block0 = next_block(nl);
@@ -854,7 +896,9 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
     }
     {
         auto L = make_launch(JL.norm, T ? &T->norm : nullptr, env, epoch_norm, env.ctr_norm);
-        err = timed("normalize", s, [&] { return launch_normalize(L, JL.ipt, s); });
+        bool dual = false;
+        for (const auto &j : JL.norm) dual = dual || j.dual;
+        err = timed("normalize", s, [&] { return launch_normalize(L, JL.ipt, dual, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.norm_small.empty()) {
@@ -890,6 +934,7 @@ int run_product(const Geom &G, const uint32_t *f, const uint32_t *g, void *h, ch
     JobLists JL;
     emit_jobs(G, reinterpret_cast<uintptr_t>(f), reinterpret_cast<uintptr_t>(g), reinterpret_cast<uintptr_t>(h),
               reinterpret_cast<uintptr_t>(ws), JL);
+    assign_dual_status(JL);
     LaunchEnv env;
     env.status = ctl.status;
     env.ctr_pack = ctl.ctrs;
@@ -1094,7 +1139,8 @@ static int mul_common(const uint32_t *f, const uint32_t *g, const Spec &sp, void
     Pool *p = nullptr;
     // the scratch regions end where the status words would start; those live in the pool's
     // own status buffer
-    rc = get_pool(s, (size_t)G.ws_status, std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1), &p);
+    rc = get_pool(s, (size_t)G.ws_status,
+                  std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks + G.norm_status_extra), 1), &p);
     if (rc != KS_OK) return rc;
     return run_product(G, f, g, h, p->ws, p->ctl, s);
 }

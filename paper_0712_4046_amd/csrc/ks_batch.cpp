@@ -361,7 +361,7 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
         emit_jobs(geoms[(size_t)i], (uintptr_t)(4 * d.f_off), (uintptr_t)(4 * d.g_off), (uintptr_t)(4 * d.h_off),
                   (uintptr_t)inst_off[(size_t)i], JL);
     }
-    P->status_words = std::max(blocks_of(JL.pack), blocks_of(JL.norm));
+    P->status_words = std::max(blocks_of(JL.pack), assign_dual_status(JL));
     P->ctr_pack = WS_STATUS / 8 + std::max<int64_t>(P->status_words, 1);
     P->ctr_norm = P->ctr_pack + (int64_t)JL.pack.size();
     P->header_words = P->ctr_norm + (int64_t)JL.norm.size();
@@ -388,6 +388,7 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
         for (auto &j : *nl) {
             for (int q = 0; q < j.nterms; ++q) { sh(j.term[q].cols); sh(j.term[q].a); sh(j.term[q].b); }
             sh(j.out);
+            sh(j.out2);
         }
     for (auto &j : JL.extract) sh(j.src);
     for (auto &kv : JL.chain) for (auto &j : kv.second) { sh(j.A); sh(j.B); sh(j.anchors); sh(j.hbuf); }

@@ -365,6 +365,7 @@ template <> __device__ __forceinline__ void rebase(NormJob &J, const Launch<Norm
         J.term[q].b = at(L.base_ws, J.term[q].b);
     }
     J.out = at(L.base_ws, J.out);
+    J.out2 = at(L.base_ws, J.out2);
 }
 template <> __device__ __forceinline__ void rebase(ExtractJob &J, const Launch<ExtractJob> &L) {
     J.src = at(L.base_ws, J.src);

@@ -208,6 +208,17 @@ struct NormJob {
     int64_t n_out;
     int64_t n_in;
     int64_t ctr;  // the job's block-ticket counter (see job_ticket)
+    // dual: a second value V2 = sign2[0] product0 + sign2[1] product1 + its own slot constants
+    // (off_bit0_2, off_count2, same period), out2 = V2 >> shift2 (n_out2 limbs), from the same
+    // column windows; its carry scan looks back through the words at status1
+    int32_t dual;
+    int32_t shift2;
+    int32_t sign2[2];
+    int64_t off_bit0_2;
+    int64_t off_count2;
+    uint32_t *out2;
+    int64_t n_out2;
+    int64_t status1;
     int64_t block0;
     int64_t nblocks;
 };

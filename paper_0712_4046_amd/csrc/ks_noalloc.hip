@@ -93,7 +93,7 @@ extern "C" int ks_mul_noalloc(const uint32_t *f, const uint32_t *g, int64_t len_
     // the product's scratch regions end where its status words would start; those have their
     // own part of the array
     if (G.ws_status > KS_NOALLOC_SCRATCH_BYTES - NA_WS ||
-        std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks), 1) > NA_STATUS)
+        std::max<int64_t>(std::max(G.pack_blocks, G.norm_blocks + G.norm_status_extra), 1) > NA_STATUS)
         return KS_ESCRATCH;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(g_na_mu);

@@ -65,7 +65,9 @@ struct MulGeom {
 struct NormGeom {
     int nterms, prod[2], sign[2], shift;
     int64_t off_bit0, off_period, off_count, n_in, n_out, out_off, blocks;
-    bool small;  // at most small_bl(ipt) limbs: one wave
+    bool small;        // at most small_bl(ipt) limbs: one wave
+    int pair = -1;     // the recombination computed in the same job (same products, other signs)
+    bool merged = false;  // computed in its partner's job
 };
 struct ExtractGeom {
     int src;  // norm index
@@ -96,6 +98,7 @@ struct Geom {
     double ntt_butterflies = 0;  // butterflies of the transforms (both primes, all passes)
     int64_t pack_blocks = 0, mul_blocks = 0, norm_blocks = 0, extract_blocks = 0, anchor_blocks = 0,
             chain_blocks = 0, finish_blocks = 0;
+    int64_t norm_status_extra = 0;  // look-back words of paired recombinations' second scans
     int64_t ws_ops = 0, ws_cols = 0, ws_digits = 0, ws_norms = 0, ws_anchors = 0, ws_hbuf = 0, ws_ntt = 0,
             ws_status = 0, ws_bytes = 0;
     double limb_mults = 0, school_mults = 0, hbm_bytes = 0;
@@ -160,6 +163,7 @@ struct LaunchEnv {
 };
 
 int plan_product(const Spec &sp, Geom &G);
+int64_t assign_dual_status(JobLists &JL);
 void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t ws, JobLists &JL);
 int batch_run_into(const ks_batch_plan *plan, const uint32_t *arena_in, uint32_t *arena_out, char *ws,
                    uint32_t *devstat, hipStream_t s);

@@ -98,11 +98,11 @@ __device__ __forceinline__ void column_window(const NormTerm &T, int64_t j0, int
     }
 }
 
+// the window of one product (signs of its operands corrected, its own sign not applied)
 template <int IPT>
-__device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bool negB, int64_t j0,
-                                                int64_t (&v)[IPT + 2]) {
+__device__ __forceinline__ void term_window(const NormTerm &T, bool negA, bool negB, int64_t j0,
+                                            int64_t (&acc)[IPT + 2]) {
     constexpr int NV = IPT + 2;
-    int64_t acc[NV];
     if (T.fmt == NORM_FMT_XY)
         column_window<4, IPT>(T, j0, acc);
     else
@@ -131,21 +131,32 @@ __device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bo
 #pragma unroll
         for (int m = 0; m < NV; ++m) acc[m] += (j0 - 2 + m == T.na + T.nb) ? 1 : 0;
     }
+}
+
+template <int IPT>
+__device__ __forceinline__ void add_term_window(const NormTerm &T, bool negA, bool negB, int64_t j0,
+                                                int64_t (&v)[IPT + 2]) {
+    constexpr int NV = IPT + 2;
+    int64_t acc[NV];
+    term_window<IPT>(T, negA, negB, j0, acc);
 #pragma unroll
     for (int m = 0; m < NV; ++m) v[m] += T.sign > 0 ? acc[m] : -acc[m];
 }
 
-// the slot constants 2^(off_bit0 + k period) that land in limb j
-__device__ __forceinline__ int64_t offset_column(const NormJob &J, int64_t j) {
+// the slot constants 2^(bit0 + k period), k < count, that land in limb j
+__device__ __forceinline__ int64_t offset_column(const NormJob &J, int64_t j, int64_t bit0, int64_t count) {
     int64_t v = 0;
-    if (J.off_count > 0 && j >= 0 && 32 * j + 31 >= J.off_bit0) {
-        const int64_t a = 32 * j - J.off_bit0;
+    if (count > 0 && j >= 0 && 32 * j + 31 >= bit0) {
+        const int64_t a = 32 * j - bit0;
         int64_t klo = a <= 0 ? 0 : div_by(a + J.off_period - 1, J.off_recip);
-        int64_t khi = div_by(32 * j + 31 - J.off_bit0, J.off_recip);
-        if (khi > J.off_count - 1) khi = J.off_count - 1;
-        for (int64_t k = klo; k <= khi; ++k) v += (int64_t)1 << (J.off_bit0 + k * J.off_period - 32 * j);
+        int64_t khi = div_by(32 * j + 31 - bit0, J.off_recip);
+        if (khi > count - 1) khi = count - 1;
+        for (int64_t k = klo; k <= khi; ++k) v += (int64_t)1 << (bit0 + k * J.off_period - 32 * j);
     }
     return v;
+}
+__device__ __forceinline__ int64_t offset_column(const NormJob &J, int64_t j) {
+    return offset_column(J, j, J.off_bit0, J.off_count);
 }
 
 // column values for positions j0-2 .. j0+IPT-1 (zero outside [0, n_in))
@@ -164,9 +175,30 @@ __device__ __forceinline__ void norm_window(const NormJob &J, const TermSigns &t
     }
 }
 
+// both values of a dual job: V = sign[0] P0 + sign[1] P1 + its slot constants and V2 =
+// sign2[0] P0 + sign2[1] P1 + its own, from one read of each product's window
+template <int IPT>
+__device__ __forceinline__ void norm_window_dual(const NormJob &J, const TermSigns &ts, int64_t j0,
+                                                 int64_t (&v0)[IPT + 2], int64_t (&v1)[IPT + 2]) {
+    constexpr int NV = IPT + 2;
+    int64_t a0[NV], a1[NV];
+    term_window<IPT>(J.term[0], ts.negA[0], ts.negB[0], j0, a0);
+    term_window<IPT>(J.term[1], ts.negA[1], ts.negB[1], j0, a1);
+    const int s0 = J.term[0].sign, s1 = J.term[1].sign, t0 = J.sign2[0], t1 = J.sign2[1];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const int64_t j = j0 - 2 + m;
+        const bool in = j >= 0 && j < J.n_in;
+        const int64_t x = (s0 > 0 ? a0[m] : -a0[m]) + (s1 > 0 ? a1[m] : -a1[m]);
+        const int64_t y = (t0 > 0 ? a0[m] : -a0[m]) + (t1 > 0 ? a1[m] : -a1[m]);
+        v0[m] = in ? x + offset_column(J, j) : 0;
+        v1[m] = in ? y + offset_column(J, j, J.off_bit0_2, J.off_count2) : 0;
+    }
+}
+
 // A block of recombination job J with TPB threads (TPB * IPT limbs per block); the caller
 // looks the job up in its own kernel arguments.
-template <int TPB, int IPT>
+template <int TPB, int IPT, bool DUAL = true>
 __device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local, const LaunchCtl L) {
     constexpr int64_t BL = (int64_t)TPB * IPT;
     constexpr int NV = IPT + 2;
@@ -188,50 +220,76 @@ __device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local,
         ts.negA[q] = q < J.nterms && (T.a[T.na - 1] >> 31) != 0;
         ts.negB[q] = q < J.nterms && (T.b[T.nb - 1] >> 31) != 0;
     }
+    // scan u (this block's pre-carry values; tail: the next block's first one) and write
+    // V >> shift: output limb o takes limbs o + w and o + w + 1 (striped, coalesced)
+    auto scan_out = [&](const int64_t (&u)[IPT], int64_t tail, uint64_t *st, uint32_t *dst, int64_t n_out,
+                        int shift) {
+        uint32_t out[IPT];
+        const int kout = Scan::run(sm, u, out, st, local, L.epoch, L.devstat);
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) s_limb[tid * IPT + q] = out[q];
+        if (tid == TPB - 1) s_limb[BL] = (uint32_t)(uint64_t)(tail + kout);
+        __syncthreads();
+        const int64_t w = shift >> 5;
+        const int r = shift & 31;
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            const int li = q * TPB + tid;
+            const int64_t o = jb + li - w;
+            if (o < 0 || o >= n_out) continue;
+            const uint32_t lo = s_limb[li];
+            dst[o] = r ? ((lo >> r) | (s_limb[li + 1] << (32 - r))) : lo;
+        }
+    };
     int64_t v[NV];
-    norm_window<IPT>(J, ts, j0, v);
     int64_t u[IPT];
+    if (!DUAL || !J.dual) {
+        norm_window<IPT>(J, ts, j0, v);
 #pragma unroll
-    for (int q = 0; q < IPT; ++q) u[q] = u_of(v[q + 2], v[q + 1], v[q]);
-    if (tid == TPB - 1) {
-        // the first limb of the next block is needed by the shift: its value before carries
-        int64_t vn[NV];
-        norm_window<IPT>(J, ts, j0 + IPT, vn);
-        s_tail[0] = u_of(vn[2], vn[1], vn[0]);
+        for (int q = 0; q < IPT; ++q) u[q] = u_of(v[q + 2], v[q + 1], v[q]);
+        if (tid == TPB - 1) {
+            // the first limb of the next block is needed by the shift: its value before carries
+            int64_t vn[NV];
+            norm_window<IPT>(J, ts, j0 + IPT, vn);
+            s_tail[0] = u_of(vn[2], vn[1], vn[0]);
+        }
+        scan_out(u, s_tail[0], J.nblocks > 1 ? L.status + J.block0 : nullptr, J.out, J.n_out, J.shift);
+        return;
     }
-    uint32_t out[IPT];
-    const int kout = Scan::run(sm, u, out, J.nblocks > 1 ? L.status + J.block0 : nullptr, local, L.epoch, L.devstat);
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) s_limb[tid * IPT + q] = out[q];
-    if (tid == TPB - 1) s_limb[BL] = (uint32_t)(uint64_t)(s_tail[0] + kout);
-    __syncthreads();
-    // write V >> shift: output limb o takes limbs o + w and o + w + 1 (striped, coalesced)
-    const int64_t w = J.shift >> 5;
-    const int r = J.shift & 31;
+    int64_t v2[NV], u2[IPT];
+    norm_window_dual<IPT>(J, ts, j0, v, v2);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        const int li = q * TPB + tid;
-        const int64_t o = jb + li - w;
-        if (o < 0 || o >= J.n_out) continue;
-        const uint32_t lo = s_limb[li];
-        J.out[o] = r ? ((lo >> r) | (s_limb[li + 1] << (32 - r))) : lo;
+        u[q] = u_of(v[q + 2], v[q + 1], v[q]);
+        u2[q] = u_of(v2[q + 2], v2[q + 1], v2[q]);
     }
+    if (tid == TPB - 1) {
+        int64_t vn[NV], vn2[NV];
+        norm_window_dual<IPT>(J, ts, j0 + IPT, vn, vn2);
+        s_tail[0] = u_of(vn[2], vn[1], vn[0]);
+        s_tail[1] = u_of(vn2[2], vn2[1], vn2[0]);
+    }
+    if constexpr (!DUAL) return;
+    scan_out(u, s_tail[0], J.nblocks > 1 ? L.status + J.block0 : nullptr, J.out, J.n_out, J.shift);
+    __syncthreads();  // s_limb and the scan's shared words are reused
+    scan_out(u2, s_tail[1], J.nblocks > 1 ? L.status + J.status1 : nullptr, J.out2, J.n_out2, J.shift2);
 }
 
 // at least five waves per SIMD: the register budget (96) that keeps the column window's loads
 // in flight without spilling, and one more wave than the unconstrained allocation (100)
-template <int IPT>
+// DUAL: the launch has paired jobs (the single-value kernel keeps its own register allocation)
+template <int IPT, bool DUAL = false>
 __global__ __launch_bounds__(SCAN_TPB, 5) void normalize_kernel(Launch<NormJob> L) {
     int64_t local;
     const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
-    normalize_block<SCAN_TPB, IPT>(J, local, ctl_of(L));
+    normalize_block<SCAN_TPB, IPT, DUAL>(J, local, ctl_of(L));
 }
 
 template <int IPT>
 __global__ __launch_bounds__(SMALL_TPB, 5) void normalize_small_kernel(Launch<NormJob> L) {
     int64_t local;
     const NormJob J = get_job(L, (int64_t)blockIdx.x, local);
-    normalize_block<SMALL_TPB, IPT>(J, local, ctl_of(L));
+    normalize_block<SMALL_TPB, IPT, false>(J, local, ctl_of(L));
 }
 
 // ---- clearing scratch words (a kernel rather than a memset, so runs can be graph-captured) ------
@@ -317,9 +375,17 @@ hipError_t launch_normalize_small(const Launch<NormJob> &L, int ipt, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_normalize(const Launch<NormJob> &L, int ipt, hipStream_t s) {
+hipError_t launch_normalize(const Launch<NormJob> &L, int ipt, bool dual, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    KS_SCAN_IPT(ipt, normalize_kernel, dim3((unsigned)L.total_blocks), dim3(SCAN_TPB), 0, s, L);
+    const dim3 g((unsigned)L.total_blocks), b(SCAN_TPB);
+    if (dual) {
+        if (ipt == SCAN_IPT_BATCH)
+            ks_launch(normalize_kernel<SCAN_IPT_BATCH, true>, g, b, 0, s, L);
+        else
+            ks_launch(normalize_kernel<SCAN_IPT_SINGLE, true>, g, b, 0, s, L);
+    } else {
+        KS_SCAN_IPT(ipt, normalize_kernel, g, b, 0, s, L);
+    }
     return hipGetLastError();
 }
 
