@@ -853,7 +853,9 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
     }
     if (!JL.pack_small.empty()) {
         auto L = make_launch(JL.pack_small, T ? &T->pack_small : nullptr, env, epoch_pack);
-        err = timed("pack", s, [&] { return launch_pack_small(L, JL.ipt, s); });
+        int pack_w = 0;
+        for (const auto &j : JL.pack_small) pack_w = std::max(pack_w, (int)j.w_in);
+        err = timed("pack", s, [&] { return launch_pack_small(L, JL.ipt, pack_w, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.mul.empty()) {

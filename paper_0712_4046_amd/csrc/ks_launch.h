@@ -34,7 +34,7 @@ hipError_t launch_pack(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_
 hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, int ipt,
                               int pack_w, hipStream_t s);
 hipError_t launch_normalize(const Launch<NormJob> &L, int ipt, bool dual, hipStream_t s);  // dual: paired jobs present
-hipError_t launch_pack_small(const Launch<PackJob> &L, int ipt, hipStream_t s);
+hipError_t launch_pack_small(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_t s);
 hipError_t launch_normalize_small(const Launch<NormJob> &L, int ipt, hipStream_t s);
 hipError_t launch_mul_valu(const Launch<MulJob> &L, hipStream_t s);
 hipError_t launch_mul_valu_wave(const Launch<MulJob> &L, hipStream_t s);

@@ -27,11 +27,11 @@ __global__ __launch_bounds__(SCAN_TPB) void pack_kernel(Launch<PackJob> L) {
 }
 
 // jobs of at most small_bl(IPT) limbs (one block each): one wave per job
-template <int IPT>
+template <int IPT, int MW = PK_MAXW>
 __global__ __launch_bounds__(SMALL_TPB) void pack_small_kernel(Launch<PackJob> L) {
     int64_t local;
     const PackJob J = get_job(L, (int64_t)blockIdx.x, local);
-    pack_block<SMALL_TPB, IPT>(J, local, ctl_of(L));
+    pack_block<SMALL_TPB, IPT, MW>(J, local, ctl_of(L));
 }
 
 // Pack and anchors in one launch: blocks [0, pack blocks) pack,
@@ -320,11 +320,17 @@ hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s) {
 hipError_t launch_pack(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     const dim3 g((unsigned)L.total_blocks), b(SCAN_TPB);
+    const bool batch = ipt == SCAN_IPT_BATCH;
     if (pack_w <= 2) {
-        if (ipt == SCAN_IPT_BATCH)
+        if (batch)
             ks_launch(pack_kernel<SCAN_IPT_BATCH, 2>, g, b, 0, s, L);
         else
             ks_launch(pack_kernel<SCAN_IPT_SINGLE, 2>, g, b, 0, s, L);
+    } else if (pack_w <= 4) {
+        if (batch)
+            ks_launch(pack_kernel<SCAN_IPT_BATCH, 4>, g, b, 0, s, L);
+        else
+            ks_launch(pack_kernel<SCAN_IPT_SINGLE, 4>, g, b, 0, s, L);
     } else {
         KS_SCAN_IPT(ipt, pack_kernel, g, b, 0, s, L);
     }
@@ -340,6 +346,15 @@ static hipError_t pack_anchor_w(const Launch<PackJob> &Lp, const Launch<AnchorJo
             ks_launch(pack_anchor_kernel<1, IPT, 2>, g, b, 0, s, Lp, La);
         else
             ks_launch(pack_anchor_kernel<2, IPT, 2>, g, b, 0, s, Lp, La);
+        return hipGetLastError();
+    }
+    if (pack_w <= 4 && w_in <= 4) {  // at most four limbs (coefficients of up to 128 bits)
+        switch (w_in) {
+            case 1: ks_launch(pack_anchor_kernel<1, IPT, 4>, g, b, 0, s, Lp, La); break;
+            case 2: ks_launch(pack_anchor_kernel<2, IPT, 4>, g, b, 0, s, Lp, La); break;
+            case 3: ks_launch(pack_anchor_kernel<3, IPT, 4>, g, b, 0, s, Lp, La); break;
+            default: ks_launch(pack_anchor_kernel<4, IPT, 4>, g, b, 0, s, Lp, La); break;
+        }
         return hipGetLastError();
     }
     switch (w_in) {
@@ -363,9 +378,23 @@ hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob>
                                  : pack_anchor_w<SCAN_IPT_SINGLE>(Lp, La, w_in, pack_w, s);
 }
 
-hipError_t launch_pack_small(const Launch<PackJob> &L, int ipt, hipStream_t s) {
+hipError_t launch_pack_small(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
-    KS_SCAN_IPT(ipt, pack_small_kernel, dim3((unsigned)L.total_blocks), dim3(SMALL_TPB), 0, s, L);
+    const dim3 g((unsigned)L.total_blocks), b(SMALL_TPB);
+    const bool batch = ipt == SCAN_IPT_BATCH;
+    if (pack_w <= 2) {
+        if (batch)
+            ks_launch(pack_small_kernel<SCAN_IPT_BATCH, 2>, g, b, 0, s, L);
+        else
+            ks_launch(pack_small_kernel<SCAN_IPT_SINGLE, 2>, g, b, 0, s, L);
+    } else if (pack_w <= 4) {
+        if (batch)
+            ks_launch(pack_small_kernel<SCAN_IPT_BATCH, 4>, g, b, 0, s, L);
+        else
+            ks_launch(pack_small_kernel<SCAN_IPT_SINGLE, 4>, g, b, 0, s, L);
+    } else {
+        KS_SCAN_IPT(ipt, pack_small_kernel, g, b, 0, s, L);
+    }
     return hipGetLastError();
 }
 
