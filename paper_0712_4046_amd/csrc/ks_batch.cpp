@@ -33,13 +33,36 @@ static thread_local int64_t g_bad_index = -1;
 
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
+// A job list and its block -> job map on the device.  interleave: the carry-scan stages, whose
+// blocks draw their positions from their job's ticket counter and look back over their job's
+// status words -- the launch's blocks go round-robin over the jobs (the first block of every
+// job, then the second, ...), so that the blocks running at one time draw from many counters
+// and poll many status lines.  Taken in job order, the ~1300 blocks resident at once belonged
+// to a handful of jobs, and their same-address atomics serialised: the 64-product modular
+// batch's pack and recombination spent about half their time there.
 template <class J>
-static int upload(const std::vector<J> &jobs, DevList &d, std::vector<void *> &allocs) {
+static int upload(const std::vector<J> &jobs, DevList &d, std::vector<void *> &allocs, bool interleave = false) {
     if (jobs.empty()) return KS_OK;
     const int64_t nb = jobs.back().block0 + jobs.back().nblocks;
     std::vector<uint32_t> map((size_t)nb);
-    for (size_t i = 0; i < jobs.size(); ++i)
-        for (int64_t b = 0; b < jobs[i].nblocks; ++b) map[(size_t)(jobs[i].block0 + b)] = (uint32_t)i;
+    if (interleave) {
+        std::vector<size_t> live(jobs.size());
+        for (size_t i = 0; i < jobs.size(); ++i) live[i] = i;
+        int64_t g = 0;
+        for (int64_t r = 0; !live.empty(); ++r) {
+            size_t keep = 0;
+            for (size_t i : live)
+                if (jobs[i].nblocks > r) {
+                    map[(size_t)g++] = (uint32_t)i;
+                    if (jobs[i].nblocks > r + 1) live[keep++] = i;
+                }
+            live.resize(keep);
+        }
+        if (g != nb) return KS_EINTERNAL;  // the list's blocks must be numbered without gaps
+    } else {
+        for (size_t i = 0; i < jobs.size(); ++i)
+            for (int64_t b = 0; b < jobs[i].nblocks; ++b) map[(size_t)(jobs[i].block0 + b)] = (uint32_t)i;
+    }
     void *t = nullptr, *m = nullptr;
     if (hipMalloc(&t, sizeof(J) * jobs.size()) != hipSuccess) return KS_ENOMEM;
     allocs.push_back(t);
@@ -411,18 +434,18 @@ static int plan_create(const ks_desc *descs, int64_t count, int32_t variant, boo
 
     int rc = KS_OK;
     if (!JL.ntt_f1.empty()) rc = ntt_prepare();  // the transforms' root tables on this device
-    if (rc == KS_OK) rc = upload(JL.pack, P->T.pack, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.pack, P->T.pack, P->allocs, true);
     if (rc == KS_OK) rc = upload(JL.ntt_f1, P->T.ntt_f1, P->allocs);
     if (rc == KS_OK) rc = upload(JL.ntt_rows, P->T.ntt_rows, P->allocs);
     if (rc == KS_OK) rc = upload(JL.ntt_i1, P->T.ntt_i1, P->allocs);
     if (rc == KS_OK) rc = upload(JL.ntt_join, P->T.ntt_join, P->allocs);
-    if (rc == KS_OK) rc = upload(JL.pack_small, P->T.pack_small, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.pack_small, P->T.pack_small, P->allocs, true);
     if (rc == KS_OK) rc = upload(JL.mul, P->T.mul, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mul_wave, P->T.mul_wave, P->allocs);
     if (rc == KS_OK) rc = upload(JL.digit, P->T.digit, P->allocs);
     if (rc == KS_OK) rc = upload(JL.mfma, P->T.mfma, P->allocs);
-    if (rc == KS_OK) rc = upload(JL.norm, P->T.norm, P->allocs);
-    if (rc == KS_OK) rc = upload(JL.norm_small, P->T.norm_small, P->allocs);
+    if (rc == KS_OK) rc = upload(JL.norm, P->T.norm, P->allocs, true);
+    if (rc == KS_OK) rc = upload(JL.norm_small, P->T.norm_small, P->allocs, true);
     if (rc == KS_OK) rc = upload(JL.extract, P->T.extract, P->allocs);
     for (auto &kv : JL.anchor) if (rc == KS_OK) rc = upload(kv.second, P->T.anchor[kv.first], P->allocs);
     for (auto &kv : JL.chain) if (rc == KS_OK) rc = upload(kv.second, P->T.chain[kv.first], P->allocs);

@@ -83,7 +83,8 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t *st) {
 // the look-back order from the job's own counter, so a block only ever waits on blocks that
 // are already running; the block that draws the last ticket puts the counter back to zero for
 // the next launch (launches of one stream run one after the other).  Jobs of one block need
-// no ticket, and no two jobs share a counter, so the atomics never pile up on one word.
+// no ticket.  No two jobs share a counter, and a batch's launch interleaves its jobs' blocks,
+// so that the atomics of the blocks running at one time spread over many words.
 __device__ __forceinline__ int64_t job_ticket(uint64_t *ctr, int64_t nblocks) {
     const uint64_t t = __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((int64_t)t == nblocks - 1) __hip_atomic_store(ctr, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -41,7 +41,7 @@ __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, cons
     if (J.nblocks > 1 && threadIdx.x == 0) s_ticket = (uint32_t)job_ticket(L.ctrs + J.ctr, J.nblocks);
     for (int x = threadIdx.x; x < BL + 3; x += TPB) s_v[x] = 0;
     __syncthreads();
-    if (J.nblocks > 1) local = s_ticket;
+    local = J.nblocks > 1 ? (int64_t)s_ticket : 0;  // (blocks may be interleaved across jobs)
     const int tid = threadIdx.x;
     const int64_t jb = local * BL;
     const int64_t jlo = jb - 2, jhi = jb + BL + 1;  // columns [jlo, jhi)

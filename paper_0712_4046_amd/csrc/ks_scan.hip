@@ -209,7 +209,7 @@ __device__ __forceinline__ void normalize_block(const NormJob &J, int64_t local,
     __shared__ int64_t s_tail[2];
     if (J.nblocks > 1 && threadIdx.x == 0) s_ticket = (uint32_t)job_ticket(L.ctrs + J.ctr, J.nblocks);
     __syncthreads();
-    if (J.nblocks > 1) local = s_ticket;
+    local = J.nblocks > 1 ? (int64_t)s_ticket : 0;  // (blocks may be interleaved across jobs)
     const int tid = threadIdx.x;
     const int64_t jb = local * BL;
     const int64_t j0 = jb + (int64_t)tid * IPT;
