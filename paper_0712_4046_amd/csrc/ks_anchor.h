@@ -79,6 +79,9 @@ __device__ __forceinline__ void anchor_block(const AnchorJob &J, int64_t local) 
             load_raw<W>(J.f + ii * W, a[q]);
             load_raw<W>(J.g + (k - ii) * W, b[q]);
         }
+        // every load of the round is issued before the first use (left to itself, the compiler
+        // masked the first term right after its load and so waited on it with the rest unissued)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
 #pragma unroll
@@ -235,6 +238,7 @@ __device__ __forceinline__ void anchor_pair_block(const AnchorJob &J, int64_t lo
             load_raw<W>(J.f + ii * W, a[q]);
             ldg_words<2 * W>(J.g + (k - ii) * W, b[q]);  // g_{k-i}, g_{k-i+1}
         }
+        __builtin_amdgcn_sched_barrier(0);  // all of the round's loads in flight, as above
 #pragma unroll
         for (int q = 0; q < U; ++q) {
 #pragma unroll

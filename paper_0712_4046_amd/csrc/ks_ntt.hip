@@ -58,6 +58,11 @@ static_assert(NTT_P0 < 2ull * NTT_P1 && (double)NTT_P0 * NTT_P1 > (double)(1ull 
 
 // [prime][0: w^(4096 i) R, 1: w^i R][i] mod P (fully reduced)
 __device__ uint32_t ntt_tab[2][2][NTT_TAB];
+// stage twiddles for transforms of up to 2^12 in LDS: [prime][0: forward, 1: inverse][h + j] =
+// w_(2h)^(+-j) R mod P for the stage of half-size h = 2^s (j < h; entry 0 unused).  The entries of
+// a half-size do not depend on the transform length, so one table serves every length.
+constexpr int NTT_STAGE_TW = 1 << 12;
+__device__ uint32_t ntt_stage_tab[2][2][NTT_STAGE_TW];
 
 // w^e R for e in [0, 2^23), w the table root of prime q (fully reduced)
 __device__ __forceinline__ uint32_t root_pow(int q, uint32_t e, NttPrime P) {
@@ -176,6 +181,156 @@ __device__ __forceinline__ void lds_transform_any(int lg, uint32_t *buf, int str
         case 10: lds_transform<10, INV, NE>(buf, stride, tw, P); break;
         case 11: lds_transform<11, INV, NE>(buf, stride, tw, P); break;
         default: lds_transform<12, INV, NE>(buf, stride, tw, P); break;
+    }
+}
+
+// ---- the row step's LDS layout --------------------------------------------------------------------
+// Element a of a row block lives at word a + (a >> 5): a spare word after every 32.  Then the
+// passes are free of bank conflicts (32 lanes of a wave access 32 banks at once): contiguous
+// runs of 32 elements keep their banks, and 32 lanes reading runs of 16 elements each (lane l at
+// 16 l + i) spread over all 32 banks instead of two.  The twiddles are kept per stage,
+// tws[h + j] = w_(2h)^(+-j) R for the stage of half-size h (j < h; tws[0] unused), so that the
+// lanes of a pass read consecutive words of them instead of a stride (copied from ntt_stage_tab).
+__device__ __forceinline__ int pad_ix(int a) { return a + (a >> 5); }
+constexpr int pad_len(int n) { return n + n / 32; }
+
+// one radix-4 pass (stages of half-sizes 2 Hb and Hb, Hb = 2^BL >= 16) in the padded layout:
+// the group's elements j + m Hb sit at fixed offsets from element j (its block of 4 Hb
+// elements starts at a multiple of 64, so the spare words between them are known)
+template <int LG, int BL, bool INV, int NE>
+__device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, NttPrime P) {
+    constexpr int hb = 1 << BL, NQ = NE / 4 / NTT_TPB;
+    static_assert(BL >= 4 && BL + 2 <= LG, "radix-4 pass of half-sizes 16 and up");
+    constexpr int o1 = hb >= 32 ? hb + hb / 32 : 16, o2 = hb >= 32 ? 2 * o1 : 33, o3 = hb >= 32 ? 3 * o1 : 49;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int g = threadIdx.x + i * NTT_TPB;
+        const int seq = g >> (LG - 2), r = g & ((1 << (LG - 2)) - 1);
+        const int j = r & (hb - 1);
+        uint32_t *x = buf + pad_ix((seq << LG) + ((r >> BL) << (BL + 2)) + j);
+        uint32_t u0 = x[0], u1 = x[o1], u2 = x[o2], u3 = x[o3];
+        const uint32_t wa0 = tws[2 * hb + j], wa1 = tws[3 * hb + j], wb = tws[hb + j];
+        if (!INV) {
+            bfly_dif(u0, u2, wa0, P);
+            bfly_dif(u1, u3, wa1, P);
+            bfly_dif(u0, u1, wb, P);
+            bfly_dif(u2, u3, wb, P);
+        } else {
+            bfly_dit(u0, u1, wb, P);
+            bfly_dit(u2, u3, wb, P);
+            bfly_dit(u0, u2, wa0, P);
+            bfly_dit(u1, u3, wa1, P);
+        }
+        x[0] = u0;
+        x[o1] = u1;
+        x[o2] = u2;
+        x[o3] = u3;
+    }
+    __syncthreads();
+}
+
+// Transforms of length M = 2^LG over NE contiguous elements in the padded layout (NE / M
+// sequences), by the same butterflies as lds_transform: a radix-2 stage of half-size M / 2 when
+// LG is odd, radix-4 passes down to half-size 16, and the four stages of half-sizes 8, 4, 2, 1
+// in registers, each thread on runs of 16 consecutive elements (their twiddles, w_16^j and its
+// powers, are the same for every run).  Forward in that order, the inverse in reverse.  Ends
+// with a barrier.
+template <int LG, bool INV, int NE>
+__device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t *tws, NttPrime P) {
+    constexpr bool ODD = ((LG - 4) & 1) != 0;
+    constexpr int TOP = LG - 2 - (ODD ? 1 : 0);  // the first (forward) radix-4 pass's BL, even
+    static_assert(LG >= 6 && NE % (16 * NTT_TPB) == 0 && NE % (1 << LG) == 0, "padded transform shape");
+    auto radix2 = [&]() {  // half-size h = M / 2 >= 32: elements j and j + h, h + h / 32 words apart
+        constexpr int h = 1 << (LG - 1), NH = NE / 2 / NTT_TPB, oh = h + h / 32;
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const int b = threadIdx.x + i * NTT_TPB;
+            const int j = b & (h - 1);
+            uint32_t *x = buf + pad_ix(((b >> (LG - 1)) << LG) + j);
+            uint32_t u = x[0], v = x[oh];
+            if (!INV)
+                bfly_dif(u, v, tws[h + j], P);
+            else
+                bfly_dit(u, v, tws[h + j], P);
+            x[0] = u;
+            x[oh] = v;
+        }
+        __syncthreads();
+    };
+    auto tail = [&]() {
+        uint32_t t16[8], t8[4], t4[2];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t16[j] = tws[8 + j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t8[j] = tws[4 + j];
+        t4[0] = tws[2];
+        t4[1] = tws[3];
+        const uint32_t t2 = tws[1];
+#pragma unroll
+        for (int i = 0; i < NE / 16 / NTT_TPB; ++i) {
+            uint32_t *x = buf + pad_ix((threadIdx.x + i * NTT_TPB) << 4);  // a run never crosses a spare word
+            uint32_t v[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = x[e];
+            if (!INV) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bfly_dif(v[j], v[j + 8], t16[j], P);
+#pragma unroll
+                for (int b = 0; b < 16; b += 8)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bfly_dif(v[b + j], v[b + j + 4], t8[j], P);
+#pragma unroll
+                for (int b = 0; b < 16; b += 4)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) bfly_dif(v[b + j], v[b + j + 2], t4[j], P);
+#pragma unroll
+                for (int b = 0; b < 16; b += 2) bfly_dif(v[b], v[b + 1], t2, P);
+            } else {
+#pragma unroll
+                for (int b = 0; b < 16; b += 2) bfly_dit(v[b], v[b + 1], t2, P);
+#pragma unroll
+                for (int b = 0; b < 16; b += 4)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) bfly_dit(v[b + j], v[b + j + 2], t4[j], P);
+#pragma unroll
+                for (int b = 0; b < 16; b += 8)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bfly_dit(v[b + j], v[b + j + 4], t8[j], P);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bfly_dit(v[j], v[j + 8], t16[j], P);
+            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = v[e];
+        }
+        __syncthreads();
+    };
+    if (!INV) {
+        if constexpr (ODD) radix2();
+        if constexpr (TOP >= 10) pad_radix4<LG, 10, false, NE>(buf, tws, P);
+        if constexpr (TOP >= 8) pad_radix4<LG, 8, false, NE>(buf, tws, P);
+        if constexpr (TOP >= 6) pad_radix4<LG, 6, false, NE>(buf, tws, P);
+        pad_radix4<LG, 4, false, NE>(buf, tws, P);
+        tail();
+    } else {
+        tail();
+        pad_radix4<LG, 4, true, NE>(buf, tws, P);
+        if constexpr (TOP >= 6) pad_radix4<LG, 6, true, NE>(buf, tws, P);
+        if constexpr (TOP >= 8) pad_radix4<LG, 8, true, NE>(buf, tws, P);
+        if constexpr (TOP >= 10) pad_radix4<LG, 10, true, NE>(buf, tws, P);
+        if constexpr (ODD) radix2();
+    }
+}
+
+template <bool INV, int NE>
+__device__ __forceinline__ void lds_transform_pad_any(int lg, uint32_t *buf, const uint32_t *tws, NttPrime P) {
+    switch (lg) {
+        case 6: lds_transform_pad<6, INV, NE>(buf, tws, P); break;
+        case 7: lds_transform_pad<7, INV, NE>(buf, tws, P); break;
+        case 8: lds_transform_pad<8, INV, NE>(buf, tws, P); break;
+        case 9: lds_transform_pad<9, INV, NE>(buf, tws, P); break;
+        case 10: lds_transform_pad<10, INV, NE>(buf, tws, P); break;
+        case 11: lds_transform_pad<11, INV, NE>(buf, tws, P); break;
+        default: lds_transform_pad<12, INV, NE>(buf, tws, P); break;
     }
 }
 
@@ -301,19 +456,30 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L)
 constexpr int NTT_ROWS_BLOCK = NTT_BLOCK / 2;
 constexpr int EPT_R = NTT_ROWS_BLOCK / NTT_TPB;
 
-template <int Q>
+// the padded position of element t + NTT_TPB m is tp + PSTEP m (NTT_TPB is a multiple of 32)
+constexpr int PSTEP = NTT_TPB + NTT_TPB / 32;
+
+template <int Q, int TWS>
 __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32_t *bufa, uint32_t *bufb,
-                                          uint32_t *tw) {
+                                          uint32_t *tws) {
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
     const int gl = k - 12;  // log2 of the blocks of one prime: N / NTT_ROWS_BLOCK
     constexpr int q = Q;
     const int64_t base = (local & (((int64_t)1 << gl) - 1)) * NTT_ROWS_BLOCK;  // whole rows, contiguous
-    const int64_t r0 = base >> k2;  // first row of the block
+    const uint32_t r0 = (uint32_t)(base >> k2);  // first row of the block (below 2^11)
     constexpr NttPrime P = ntt_prime_c(Q);
-    load_twiddles<false>(tw, q, k2, P);
     uint32_t *x = J.x + ((int64_t)q << k) + base;
     const uint32_t *y = J.y + ((int64_t)q << k) + base;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, tp = pad_ix(t);
+    // both directions' stage twiddles, loaded with the first residues (the inverse ones wait in
+    // registers until the forward transforms are done)
+    constexpr int TPT = TWS / NTT_TPB;
+    uint32_t twf[TPT], twi[TPT];
+#pragma unroll
+    for (int m = 0; m < TPT; ++m) {
+        twf[m] = ldg(&ntt_stage_tab[q][0][t + m * NTT_TPB]);
+        twi[m] = ldg(&ntt_stage_tab[q][1][t + m * NTT_TPB]);
+    }
 #pragma unroll 1
     for (int i0 = 0; i0 < EPT_R; i0 += CH) {
         uint32_t u[CH], v[CH];
@@ -324,58 +490,68 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
         }
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            bufa[t + (i0 + i) * NTT_TPB] = u[i];
-            bufb[t + (i0 + i) * NTT_TPB] = v[i];
+            bufa[tp + (i0 + i) * PSTEP] = u[i];
+            bufb[tp + (i0 + i) * PSTEP] = v[i];
         }
     }
+#pragma unroll
+    for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twf[m];
     __syncthreads();
-    lds_transform_any<false, NTT_ROWS_BLOCK>(k2, bufa, 1 << k2, tw, P);
-    lds_transform_any<false, NTT_ROWS_BLOCK>(k2, bufb, 1 << k2, tw, P);
+    lds_transform_pad_any<false, NTT_ROWS_BLOCK>(k2, bufa, tws, P);
+    lds_transform_pad_any<false, NTT_ROWS_BLOCK>(k2, bufb, tws, P);
     // pointwise A B R^-1 (equal positions: both in the order the forward steps left; A, B < 2P,
     // so A B < P 2^32 and the product is below 2P), then the inverse twiddles replace the
-    // forward ones
+    // forward ones (every thread is past the forward transforms' barrier)
 #pragma unroll 4
     for (int i = 0; i < EPT_R; ++i) {
-        const int e = t + i * NTT_TPB;
+        const int e = tp + i * PSTEP;
         bufa[e] = mmul_lazy(bufa[e], bufb[e], P);
     }
-    load_twiddles<true>(tw, q, k2, P);  // every thread is past the forward transforms' barrier
+#pragma unroll
+    for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twi[m];
     __syncthreads();
-    lds_transform_any<true, NTT_ROWS_BLOCK>(k2, bufa, 1 << k2, tw, P);
+    lds_transform_pad_any<true, NTT_ROWS_BLOCK>(k2, bufa, tws, P);
     // inverse twiddle w_N^-(n2 k1) and the scale R / N (the pointwise product left R^-1):
-    // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N
+    // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N.  The exponent
+    // n2 bitrev(r) < 2^k <= 2^23 fits in 32 bits.
     const uint32_t K = J.kscale[Q];
+    const uint32_t emask = (1u << NTT_ROOT_LOG) - 1u;
+    const int sh = NTT_ROOT_LOG - k;
 #pragma unroll 1
     for (int i0 = 0; i0 < EPT_R; i0 += CH) {
         uint32_t a[CH], b[CH];
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            const int e = t + (i0 + i) * NTT_TPB;
-            const int64_t r = r0 + (e >> k2), n2 = e & ((1 << k2) - 1);
-            const uint32_t ex = (uint32_t)((n2 * (int64_t)bitrev((uint32_t)r, k1)) << (NTT_ROOT_LOG - k));
-            const uint32_t ei = (uint32_t)((1u << NTT_ROOT_LOG) - ex) & ((1u << NTT_ROOT_LOG) - 1u);
+            const uint32_t e = (uint32_t)(t + (i0 + i) * NTT_TPB);
+            const uint32_t r = r0 + (e >> k2), n2 = e & ((1u << k2) - 1u);
+            const uint32_t ei = (0u - ((n2 * bitrev(r, k1)) << sh)) & emask;
             a[i] = ntt_tab[q][0][ei >> NTT_TAB_LOG];
             b[i] = ntt_tab[q][1][ei & (NTT_TAB - 1)];
         }
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             const int e = t + (i0 + i) * NTT_TPB;
-            stg(x + e, mmul_lazy(bufa[e], mmul(mmul(a[i], b[i], P), K, P), P));  // below 2P
+            stg(x + e, mmul_lazy(bufa[tp + (i0 + i) * PSTEP], mmul(mmul(a[i], b[i], P), K, P), P));  // below 2P
         }
     }
 }
 
+// TWS: words of stage twiddles, 2^k2 (rows of up to 2^10 take 38 KB of LDS and four blocks fit
+// on a CU; longer rows take the larger table and three blocks)
+template <int TWS>
 __global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
-    __shared__ uint32_t bufa[NTT_ROWS_BLOCK];
-    __shared__ uint32_t bufb[NTT_ROWS_BLOCK];
-    __shared__ uint32_t tw[2048];
+    __shared__ uint32_t bufa[pad_len(NTT_ROWS_BLOCK)];
+    __shared__ uint32_t bufb[pad_len(NTT_ROWS_BLOCK)];
+    __shared__ uint32_t tws[TWS];
     int64_t local;
     const NttJob J = get_job(L, (int64_t)blockIdx.x, local);
     if ((local >> (J.k1 + J.k2 - 12)) == 0)
-        rows_body<0>(J, local, bufa, bufb, tw);
+        rows_body<0, TWS>(J, local, bufa, bufb, tws);
     else
-        rows_body<1>(J, local, bufa, bufb, tw);
+        rows_body<1, TWS>(J, local, bufa, bufb, tws);
 }
+constexpr int NTT_ROWS_TWS_SMALL = 1 << 10, NTT_ROWS_TWS = 1 << 12;
+static_assert(NTT_ROWS_TWS >= (1 << (NTT_MAX_LOG - NTT_MAX_LOG / 2)), "stage twiddles of the longest rows");
 
 template <int Q>
 __device__ __forceinline__ void inv_cols_body(const NttJob &J, int64_t local, uint32_t *buf, uint32_t *tw) {
@@ -512,6 +688,23 @@ int ntt_prepare() {
     }
     if (hipMemcpyToSymbol(HIP_SYMBOL(ntt_tab), host, sizeof(host), 0, hipMemcpyHostToDevice) != hipSuccess)
         return KS_EHIP;
+    static uint32_t stage[2][2][NTT_STAGE_TW];
+    for (int q = 0; q < 2; ++q) {
+        const uint64_t p = prime[q];
+        const uint64_t w = powmod_h(gen[q], (p - 1) >> NTT_ROOT_LOG, p);
+        const uint64_t R = ((uint64_t)1 << 32) % p;
+        stage[q][0][0] = stage[q][1][0] = 0;
+        for (int i = 1; i < NTT_STAGE_TW; ++i) {
+            int sl = 0;
+            while ((2 << sl) <= i) ++sl;  // half-size 2^sl <= i < 2^(sl+1)
+            const uint64_t e = (uint64_t)(i - (1 << sl)) << (NTT_ROOT_LOG - 1 - sl);  // w_(2h)^j = w^e
+            const uint64_t ei = (((uint64_t)1 << NTT_ROOT_LOG) - e) & (((uint64_t)1 << NTT_ROOT_LOG) - 1);
+            stage[q][0][i] = (uint32_t)mulmod_h(powmod_h(w, e, p), R, p);
+            stage[q][1][i] = (uint32_t)mulmod_h(powmod_h(w, ei, p), R, p);
+        }
+    }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(ntt_stage_tab), stage, sizeof(stage), 0, hipMemcpyHostToDevice) != hipSuccess)
+        return KS_EHIP;
     done[dev] = true;
     return KS_OK;
 }
@@ -522,12 +715,17 @@ hipError_t launch_ntt_join(const Launch<NttJoinJob> &L, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, hipStream_t s) {
+hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, int max_k2, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     const dim3 g((unsigned)L.total_blocks), b(NTT_TPB);
     switch (stage) {
         case 0: ks_launch(ntt_fwd_cols_kernel, g, b, 0, s, L); break;
-        case 1: ks_launch(ntt_rows_kernel, g, b, 0, s, L); break;
+        case 1:
+            if (max_k2 <= 10)
+                ks_launch(ntt_rows_kernel<NTT_ROWS_TWS_SMALL>, g, b, 0, s, L);
+            else
+                ks_launch(ntt_rows_kernel<NTT_ROWS_TWS>, g, b, 0, s, L);
+            break;
         case 2: ks_launch(ntt_inv_cols_kernel, g, b, 0, s, L); break;
         default: return hipErrorInvalidValue;
     }
