@@ -880,11 +880,14 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         const std::vector<NttJob> *lists[3] = {&JL.ntt_f1, &JL.ntt_rows, &JL.ntt_i1};
         const DevList *tabs[3] = {T ? &T->ntt_f1 : nullptr, T ? &T->ntt_rows : nullptr, T ? &T->ntt_i1 : nullptr};
         static const char *names[3] = {"ntt_fwd_cols", "ntt_rows", "ntt_inv_cols"};
-        int max_k2 = 0;
-        for (const auto &j : JL.ntt_rows) max_k2 = std::max(max_k2, (int)j.k2);
+        int max_k1 = 0, max_k2 = 0;
+        for (const auto &j : JL.ntt_rows) {
+            max_k1 = std::max(max_k1, (int)j.k1);
+            max_k2 = std::max(max_k2, (int)j.k2);
+        }
         for (int st = 0; st < 3; ++st) {
             auto L = make_launch(*lists[st], tabs[st], env, 0);
-            err = timed(names[st], s, [&] { return launch_ntt_stage(st, L, max_k2, s); });
+            err = timed(names[st], s, [&] { return launch_ntt_stage(st, L, max_k1, max_k2, s); });
             if (err != hipSuccess) return KS_EHIP;
         }
         auto Lj = make_launch(JL.ntt_join, T ? &T->ntt_join : nullptr, env, 0);

@@ -49,8 +49,9 @@ hipError_t launch_digitize(const Launch<DigitJob> &L, hipStream_t s);
 hipError_t launch_mul_mfma(const Launch<MfmaJob> &L, int rt, hipStream_t s);  // rt: tiles per block (4 or 8)
 // one of the transform steps of integer products on the transform engine: 0 forward columns,
 // 1 rows (both operands forward, the pointwise product, inverse), 2 inverse columns
-// max_k2: the longest rows (log2 N2) among the launch's jobs (sizes the row step's twiddle table)
-hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, int max_k2, hipStream_t s);
+// max_k1, max_k2: the longest columns and rows (log2 N1, log2 N2) among the launch's jobs
+// (they size the steps' twiddle tables in LDS)
+hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, int max_k1, int max_k2, hipStream_t s);
 hipError_t launch_ntt_join(const Launch<NttJoinJob> &L, hipStream_t s);
 hipError_t launch_p2_eval(const P2Eval &E, hipStream_t s);
 hipError_t launch_p2_readoff(const P2Readoff &R, hipStream_t s);

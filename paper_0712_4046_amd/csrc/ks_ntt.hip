@@ -68,19 +68,6 @@ __device__ uint32_t ntt_stage_tab[2][2][NTT_STAGE_TW];
 __device__ __forceinline__ uint32_t root_pow(int q, uint32_t e, NttPrime P) {
     return mmul(ntt_tab[q][0][e >> NTT_TAB_LOG], ntt_tab[q][1][e & (NTT_TAB - 1)], P);
 }
-// w^-e R
-__device__ __forceinline__ uint32_t root_pow_inv(int q, uint32_t e, NttPrime P) {
-    return root_pow(q, (uint32_t)((1u << NTT_ROOT_LOG) - e) & ((1u << NTT_ROOT_LOG) - 1u), P);
-}
-
-// the stage twiddles of a transform of length 2^lg: tw[j] = w_M^(+-j) R, j < M/2
-template <bool INV>
-__device__ __forceinline__ void load_twiddles(uint32_t *tw, int q, int lg, NttPrime P) {
-    for (int j = threadIdx.x; j < (1 << (lg - 1)); j += NTT_TPB) {
-        const uint32_t e = (uint32_t)j << (NTT_ROOT_LOG - lg);
-        tw[j] = INV ? root_pow_inv(q, e, P) : root_pow(q, e, P);
-    }
-}
 
 // The two butterflies on partly reduced residues (P < 2^30).
 // Forward, decimation in frequency: u, v < 2P -> u + v and (u - v) w, both below 2P.
@@ -96,94 +83,6 @@ __device__ __forceinline__ void bfly_dit(uint32_t &u, uint32_t &v, uint32_t w, N
     v = a + 2u * P.p - t;
 }
 
-// Transforms of length M = 2^LG over NE elements in LDS (NE / M sequences, sequence s at
-// buf[s * stride ..]): forward by decimation in frequency (natural in, bit-reversed out; values
-// below 2P in and out), inverse by decimation in time (bit-reversed in, natural out; below 4P in
-// and out; tw holds the inverse twiddles, tw[j] = w_M^(+-j) R).  Stages go in pairs (radix 4:
-// each thread reads four elements, runs two stages in registers and writes them back), with one
-// radix-2 stage more when LG is odd (last in the forward order, first in the inverse).  Ends
-// with a barrier.
-template <int LG, bool INV, int NE = NTT_BLOCK>
-__device__ __forceinline__ void lds_transform(uint32_t *buf, int stride, const uint32_t *tw, NttPrime P) {
-    constexpr int NQ = NE / 4 / NTT_TPB;  // groups of four per thread and pass
-    constexpr int NH = NE / 2 / NTT_TPB;  // pairs per thread in a radix-2 stage
-    constexpr int PAIRS = LG / 2;
-    auto radix2 = [&](int hl) {  // one stage of half-size 2^hl (twiddle index j << (LG-1-hl))
-        const int h = 1 << hl, ts = LG - 1 - hl;
-#pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            const int b = threadIdx.x + i * NTT_TPB;
-            const int seq = b >> (LG - 1), r = b & ((1 << (LG - 1)) - 1);
-            const int j = r & (h - 1);
-            uint32_t *x = buf + seq * stride + ((r >> hl) << (hl + 1)) + j;
-            uint32_t u = x[0], v = x[h];
-            const uint32_t t = tw[j << ts];
-            if (!INV)
-                bfly_dif(u, v, t, P);
-            else
-                bfly_dit(u, v, t, P);
-            x[0] = u;
-            x[h] = v;
-        }
-        __syncthreads();
-    };
-    // two stages with half-sizes 2^(bl+1) and 2^bl on groups of four elements j, j + Hb,
-    // j + 2 Hb, j + 3 Hb (Hb = 2^bl)
-    auto radix4 = [&](int bl) {
-        const int hb = 1 << bl;
-        const int ta = LG - 2 - bl, tb = LG - 1 - bl;  // twiddle shifts of the larger and smaller stage
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            const int g = threadIdx.x + i * NTT_TPB;
-            const int seq = g >> (LG - 2), r = g & ((1 << (LG - 2)) - 1);
-            const int j = r & (hb - 1);
-            uint32_t *x = buf + seq * stride + ((r >> bl) << (bl + 2)) + j;
-            uint32_t u0 = x[0], u1 = x[hb], u2 = x[2 * hb], u3 = x[3 * hb];
-            const uint32_t wa0 = tw[j << ta], wa1 = tw[(j + hb) << ta], wb = tw[j << tb];
-            if (!INV) {  // half-size 2 Hb (pairs 0-2, 1-3), then Hb (pairs 0-1, 2-3)
-                bfly_dif(u0, u2, wa0, P);
-                bfly_dif(u1, u3, wa1, P);
-                bfly_dif(u0, u1, wb, P);
-                bfly_dif(u2, u3, wb, P);
-            } else {  // half-size Hb first, then 2 Hb
-                bfly_dit(u0, u1, wb, P);
-                bfly_dit(u2, u3, wb, P);
-                bfly_dit(u0, u2, wa0, P);
-                bfly_dit(u1, u3, wa1, P);
-            }
-            x[0] = u0;
-            x[hb] = u1;
-            x[2 * hb] = u2;
-            x[3 * hb] = u3;
-        }
-        __syncthreads();
-    };
-    if (!INV) {
-#pragma unroll
-        for (int pr = 0; pr < PAIRS; ++pr) radix4(LG - 2 - 2 * pr);  // half-sizes M/2, M/4, ...
-        if (LG & 1) radix2(0);
-    } else {
-        if (LG & 1) radix2(0);
-#pragma unroll
-        for (int pr = 0; pr < PAIRS; ++pr) radix4((LG & 1) + 2 * pr);  // half-sizes 1, 2, ... (after the odd one)
-    }
-}
-
-// the templated transform for a length known only at run time (6 <= lg <= 12)
-template <bool INV, int NE = NTT_BLOCK>
-__device__ __forceinline__ void lds_transform_any(int lg, uint32_t *buf, int stride, const uint32_t *tw,
-                                                  NttPrime P) {
-    switch (lg) {
-        case 6: lds_transform<6, INV, NE>(buf, stride, tw, P); break;
-        case 7: lds_transform<7, INV, NE>(buf, stride, tw, P); break;
-        case 8: lds_transform<8, INV, NE>(buf, stride, tw, P); break;
-        case 9: lds_transform<9, INV, NE>(buf, stride, tw, P); break;
-        case 10: lds_transform<10, INV, NE>(buf, stride, tw, P); break;
-        case 11: lds_transform<11, INV, NE>(buf, stride, tw, P); break;
-        default: lds_transform<12, INV, NE>(buf, stride, tw, P); break;
-    }
-}
-
 // ---- the row step's LDS layout --------------------------------------------------------------------
 // Element a of a row block lives at word a + (a >> 5): a spare word after every 32.  Then the
 // passes are free of bank conflicts (32 lanes of a wave access 32 banks at once): contiguous
@@ -197,9 +96,9 @@ constexpr int pad_len(int n) { return n + n / 32; }
 // one radix-4 pass (stages of half-sizes 2 Hb and Hb, Hb = 2^BL >= 16) in the padded layout:
 // the group's elements j + m Hb sit at fixed offsets from element j (its block of 4 Hb
 // elements starts at a multiple of 64, so the spare words between them are known)
-template <int LG, int BL, bool INV, int NE>
+template <int LG, int BL, bool INV, int NE, int GAP>
 __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, NttPrime P) {
-    constexpr int hb = 1 << BL, NQ = NE / 4 / NTT_TPB;
+    constexpr int hb = 1 << BL, NQ = NE / 4 / NTT_TPB, SS = pad_len(1 << LG) + GAP;
     static_assert(BL >= 4 && BL + 2 <= LG, "radix-4 pass of half-sizes 16 and up");
     constexpr int o1 = hb >= 32 ? hb + hb / 32 : 16, o2 = hb >= 32 ? 2 * o1 : 33, o3 = hb >= 32 ? 3 * o1 : 49;
 #pragma unroll
@@ -207,7 +106,7 @@ __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, N
         const int g = threadIdx.x + i * NTT_TPB;
         const int seq = g >> (LG - 2), r = g & ((1 << (LG - 2)) - 1);
         const int j = r & (hb - 1);
-        uint32_t *x = buf + pad_ix((seq << LG) + ((r >> BL) << (BL + 2)) + j);
+        uint32_t *x = buf + seq * SS + pad_ix(((r >> BL) << (BL + 2)) + j);
         uint32_t u0 = x[0], u1 = x[o1], u2 = x[o2], u3 = x[o3];
         const uint32_t wa0 = tws[2 * hb + j], wa1 = tws[3 * hb + j], wb = tws[hb + j];
         if (!INV) {
@@ -229,14 +128,18 @@ __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, N
     __syncthreads();
 }
 
-// Transforms of length M = 2^LG over NE contiguous elements in the padded layout (NE / M
-// sequences), by the same butterflies as lds_transform: a radix-2 stage of half-size M / 2 when
-// LG is odd, radix-4 passes down to half-size 16, and the four stages of half-sizes 8, 4, 2, 1
-// in registers, each thread on runs of 16 consecutive elements (their twiddles, w_16^j and its
-// powers, are the same for every run).  Forward in that order, the inverse in reverse.  Ends
-// with a barrier.
-template <int LG, bool INV, int NE>
+// Transforms of length M = 2^LG over NE elements in the padded layout: NE / M sequences, each
+// padded on its own, sequence s at word s (pad_len(M) + GAP) (GAP = 0: one contiguous padded
+// array; GAP = 1: columns an odd number of words apart, so that 32 lanes writing one element
+// of 32 columns each hit 32 banks).  Forward by decimation in frequency (natural in, bit-reversed
+// out, values below 2P), inverse by decimation in time (bit-reversed in, natural out, below 4P):
+// a radix-2 stage of half-size M / 2 when LG is odd, radix-4 passes (two stages per LDS round
+// trip) down to half-size 16, and the four stages of half-sizes 8, 4, 2, 1 in registers, each
+// thread on runs of 16 consecutive elements (their twiddles, w_16^j and its powers, are the same
+// for every run).  Forward in that order, the inverse in reverse.  Ends with a barrier.
+template <int LG, bool INV, int NE, int GAP>
 __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t *tws, NttPrime P) {
+    constexpr int SS = pad_len(1 << LG) + GAP;
     constexpr bool ODD = ((LG - 4) & 1) != 0;
     constexpr int TOP = LG - 2 - (ODD ? 1 : 0);  // the first (forward) radix-4 pass's BL, even
     static_assert(LG >= 6 && NE % (16 * NTT_TPB) == 0 && NE % (1 << LG) == 0, "padded transform shape");
@@ -246,7 +149,7 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
         for (int i = 0; i < NH; ++i) {
             const int b = threadIdx.x + i * NTT_TPB;
             const int j = b & (h - 1);
-            uint32_t *x = buf + pad_ix(((b >> (LG - 1)) << LG) + j);
+            uint32_t *x = buf + (b >> (LG - 1)) * SS + pad_ix(j);
             uint32_t u = x[0], v = x[oh];
             if (!INV)
                 bfly_dif(u, v, tws[h + j], P);
@@ -268,7 +171,8 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
         const uint32_t t2 = tws[1];
 #pragma unroll
         for (int i = 0; i < NE / 16 / NTT_TPB; ++i) {
-            uint32_t *x = buf + pad_ix((threadIdx.x + i * NTT_TPB) << 4);  // a run never crosses a spare word
+            const int run = threadIdx.x + i * NTT_TPB;  // a run never crosses a spare word
+            uint32_t *x = buf + (run >> (LG - 4)) * SS + pad_ix((run & ((1 << (LG - 4)) - 1)) << 4);
             uint32_t v[16];
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = x[e];
@@ -306,31 +210,33 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
     };
     if (!INV) {
         if constexpr (ODD) radix2();
-        if constexpr (TOP >= 10) pad_radix4<LG, 10, false, NE>(buf, tws, P);
-        if constexpr (TOP >= 8) pad_radix4<LG, 8, false, NE>(buf, tws, P);
-        if constexpr (TOP >= 6) pad_radix4<LG, 6, false, NE>(buf, tws, P);
-        pad_radix4<LG, 4, false, NE>(buf, tws, P);
+        if constexpr (TOP >= 10) pad_radix4<LG, 10, false, NE, GAP>(buf, tws, P);
+        if constexpr (TOP >= 8) pad_radix4<LG, 8, false, NE, GAP>(buf, tws, P);
+        if constexpr (TOP >= 6) pad_radix4<LG, 6, false, NE, GAP>(buf, tws, P);
+        pad_radix4<LG, 4, false, NE, GAP>(buf, tws, P);
         tail();
     } else {
         tail();
-        pad_radix4<LG, 4, true, NE>(buf, tws, P);
-        if constexpr (TOP >= 6) pad_radix4<LG, 6, true, NE>(buf, tws, P);
-        if constexpr (TOP >= 8) pad_radix4<LG, 8, true, NE>(buf, tws, P);
-        if constexpr (TOP >= 10) pad_radix4<LG, 10, true, NE>(buf, tws, P);
+        pad_radix4<LG, 4, true, NE, GAP>(buf, tws, P);
+        if constexpr (TOP >= 6) pad_radix4<LG, 6, true, NE, GAP>(buf, tws, P);
+        if constexpr (TOP >= 8) pad_radix4<LG, 8, true, NE, GAP>(buf, tws, P);
+        if constexpr (TOP >= 10) pad_radix4<LG, 10, true, NE, GAP>(buf, tws, P);
         if constexpr (ODD) radix2();
     }
 }
 
-template <bool INV, int NE>
+template <bool INV, int NE, int GAP>
 __device__ __forceinline__ void lds_transform_pad_any(int lg, uint32_t *buf, const uint32_t *tws, NttPrime P) {
     switch (lg) {
-        case 6: lds_transform_pad<6, INV, NE>(buf, tws, P); break;
-        case 7: lds_transform_pad<7, INV, NE>(buf, tws, P); break;
-        case 8: lds_transform_pad<8, INV, NE>(buf, tws, P); break;
-        case 9: lds_transform_pad<9, INV, NE>(buf, tws, P); break;
-        case 10: lds_transform_pad<10, INV, NE>(buf, tws, P); break;
-        case 11: lds_transform_pad<11, INV, NE>(buf, tws, P); break;
-        default: lds_transform_pad<12, INV, NE>(buf, tws, P); break;
+        case 6: lds_transform_pad<6, INV, NE, GAP>(buf, tws, P); break;
+        case 7: lds_transform_pad<7, INV, NE, GAP>(buf, tws, P); break;
+        case 8: lds_transform_pad<8, INV, NE, GAP>(buf, tws, P); break;
+        case 9: lds_transform_pad<9, INV, NE, GAP>(buf, tws, P); break;
+        case 10: lds_transform_pad<10, INV, NE, GAP>(buf, tws, P); break;
+        case 11: lds_transform_pad<11, INV, NE, GAP>(buf, tws, P); break;
+        default:  // rows only (columns have at most 2^11)
+            if constexpr (GAP == 0) lds_transform_pad<12, INV, NE, GAP>(buf, tws, P);
+            break;
     }
 }
 
@@ -348,24 +254,30 @@ constexpr int CH = 16;
 
 // ---- the four steps ---------------------------------------------------------------------------
 
-// twiddles of a column transform (N1 / 2, N1 <= 2048): with them a column block takes 37 KB of
-// LDS, so four blocks fit on a CU
-constexpr int NTT_COL_TW = 1 << (NTT_MAX_LOG / 2 - 1);
-static_assert(NTT_COL_TW == 1024, "columns of at most 2^11");
+// A column block's C columns of N1 residues in LDS: column c at word c SC, SC = pad_len(N1) + 1
+// (each column in the padded layout, columns an odd number of words apart), at most
+// NTT_COL_BUF words for N1 >= 64.  With 1024 stage twiddles (columns of up to 2^10) a block
+// takes 38 KB and four fit on a CU.
+constexpr int NTT_COL_BUF = NTT_BLOCK + NTT_BLOCK / 32 + NTT_BLOCK / 64;
+static_assert(NTT_MIN_LOG / 2 >= 6, "columns of at least 64");
+constexpr int NTT_COLS_TWS_SMALL = 1 << 10, NTT_COLS_TWS = 1 << (NTT_MAX_LOG / 2);
 
 // Column blocks read C words of each row: with C = 16 that is half of a 128-byte line, whose
 // other half the next block reads -- both run on one XCD at about the same time (xcd_block), so
 // the line comes from HBM once.
-template <int Q>
-__device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, uint32_t *buf, uint32_t *tw) {
+template <int Q, int TWS>
+__device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, uint32_t *buf, uint32_t *tws) {
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
-    const int lc = 13 - k1, C = 1 << lc, S = (1 << k1) + 1;  // columns, LDS stride of a column
+    const int lc = 13 - k1, C = 1 << lc, SC = pad_len(1 << k1) + 1;  // columns, LDS stride of a column
     const int gl = k - 13;  // log2 of the blocks of one prime (a power of two: no division)
     constexpr int q = Q;
     const int64_t c0 = (local & (((int64_t)1 << gl) - 1)) * C;
     constexpr NttPrime P = ntt_prime_c(Q);
-    load_twiddles<false>(tw, q, k1, P);
     const int t = threadIdx.x;
+    constexpr int TPT = TWS / NTT_TPB;
+    uint32_t twf[TPT];  // the stage twiddles, loaded with the pieces
+#pragma unroll
+    for (int m = 0; m < TPT; ++m) twf[m] = ldg(&ntt_stage_tab[q][0][t + m * NTT_TPB]);
     // element e = t + 256 i of the block: column c = t mod C (256 is a multiple of C), row
     // n1 = t / C + i 256 / C; its piece m = n1 N2 + c0 + c < N <= 2^23 and first bit w m < 2^28
     // fit in 32 bits.  The two words holding the piece come in one 8-byte load (dword alignment
@@ -375,7 +287,8 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
     const uint32_t mt = ((uint32_t)(t >> lc) << k2) + (uint32_t)c0 + (uint32_t)(t & (C - 1));
     const uint32_t mstep = (uint32_t)(NTT_TPB >> lc) << k2;
     const uint32_t last = na >= 2 ? na - 2 : 0;
-    uint32_t *bt = buf + (t & (C - 1)) * S + (t >> lc);
+    uint32_t *bt = buf + (t & (C - 1)) * SC;
+    const int n1t = t >> lc, n1s = NTT_TPB >> lc;
     auto load = [&](auto wide) {  // wide: 8-byte loads (an operand of two limbs or more)
 #pragma unroll 1
         for (int i0 = 0; i0 < EPT; i0 += CH) {
@@ -395,7 +308,7 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
                 const bool in = m < np;
                 const uint32_t lo = in && w0 < na ? (w0 <= last ? v[i].x : v[i].y) : 0u;
                 const uint32_t hi = in && w0 + 1 < na ? v[i].y : 0u;
-                bt[(i0 + i) * (NTT_TPB >> lc)] = piece_of(lo, hi, (int)(bit & 31u), (int)w);
+                bt[pad_ix(n1t + (i0 + i) * n1s)] = piece_of(lo, hi, (int)(bit & 31u), (int)w);
             }
         }
     };
@@ -403,8 +316,10 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
         load(std::true_type{});
     else
         load(std::false_type{});
+#pragma unroll
+    for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twf[m];
     __syncthreads();
-    lds_transform_any<false>(k1, buf, S, tw, P);
+    lds_transform_pad_any<false, NTT_BLOCK, 1>(k1, buf, tws, P);
     // twiddle w_N^(n2 k1) and store: each thread takes runs of `cols` adjacent columns of one row
     // (32 elements in all), so the twiddles of a run follow by one multiplication each from its
     // first (w^((c0 + c) kk) = w^((c0 + c_first) kk) (w^kk)^(c - c_first)) and the run is
@@ -412,42 +327,44 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
     uint32_t *x = J.x + ((int64_t)q << k);
     const int lcols = lc < 5 ? lc : 5;              // log2 of the run length (columns)
     const int cols = 1 << lcols;
-    const int runs_per_row = C >> lcols;            // threads sharing a row
+    const int lrpr = lc - lcols;                    // log2 of the threads sharing a row
     const int rows_per_thread = EPT >> lcols;     // runs per thread
     const int sh = NTT_ROOT_LOG - k;
 #pragma unroll 1
     for (int rr = 0; rr < rows_per_thread; ++rr) {
         const int run = rr * NTT_TPB + t;           // adjacent threads, adjacent runs (rows)
-        const int r = run / runs_per_row;
-        const int cf = (run - r * runs_per_row) << lcols;
+        const int r = run >> lrpr;
+        const int cf = (run - (r << lrpr)) << lcols;
         const uint32_t kk = bitrev((uint32_t)r, k1);
         uint32_t w = root_pow(q, (uint32_t)(((c0 + cf) * (int64_t)kk) << sh) & ((1u << NTT_ROOT_LOG) - 1u), P);
         const uint32_t g = root_pow(q, (uint32_t)(((int64_t)kk) << sh), P);
         uint32_t *dst = x + ((int64_t)r << k2) + c0 + cf;
+        const uint32_t *src = buf + cf * SC + pad_ix(r);
         for (int c4 = 0; c4 < cols; c4 += 4) {
             u32x4 v;  // below 2P; the running twiddle is kept fully reduced
-            v.x = mmul_lazy(buf[(cf + c4) * S + r], w, P);
+            v.x = mmul_lazy(src[c4 * SC], w, P);
             w = mmul(w, g, P);
-            v.y = mmul_lazy(buf[(cf + c4 + 1) * S + r], w, P);
+            v.y = mmul_lazy(src[(c4 + 1) * SC], w, P);
             w = mmul(w, g, P);
-            v.z = mmul_lazy(buf[(cf + c4 + 2) * S + r], w, P);
+            v.z = mmul_lazy(src[(c4 + 2) * SC], w, P);
             w = mmul(w, g, P);
-            v.w = mmul_lazy(buf[(cf + c4 + 3) * S + r], w, P);
+            v.w = mmul_lazy(src[(c4 + 3) * SC], w, P);
             w = mmul(w, g, P);
             *(__attribute__((address_space(1))) u32x4 *)(dst + c4) = v;
         }
     }
 }
 
+template <int TWS>
 __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L) {
-    __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
-    __shared__ uint32_t tw[NTT_COL_TW];
+    __shared__ uint32_t buf[NTT_COL_BUF];
+    __shared__ uint32_t tws[TWS];
     int64_t local;
     const NttJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
     if ((local >> (J.k1 + J.k2 - 13)) == 0)  // the prime: a compile-time constant in each body
-        fwd_cols_body<0>(J, local, buf, tw);
+        fwd_cols_body<0, TWS>(J, local, buf, tws);
     else
-        fwd_cols_body<1>(J, local, buf, tw);
+        fwd_cols_body<1, TWS>(J, local, buf, tws);
 }
 
 // The row step of a product: both operands' rows forward, the pointwise product, the inverse
@@ -497,8 +414,8 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
 #pragma unroll
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twf[m];
     __syncthreads();
-    lds_transform_pad_any<false, NTT_ROWS_BLOCK>(k2, bufa, tws, P);
-    lds_transform_pad_any<false, NTT_ROWS_BLOCK>(k2, bufb, tws, P);
+    lds_transform_pad_any<false, NTT_ROWS_BLOCK, 0>(k2, bufa, tws, P);
+    lds_transform_pad_any<false, NTT_ROWS_BLOCK, 0>(k2, bufb, tws, P);
     // pointwise A B R^-1 (equal positions: both in the order the forward steps left; A, B < 2P,
     // so A B < P 2^32 and the product is below 2P), then the inverse twiddles replace the
     // forward ones (every thread is past the forward transforms' barrier)
@@ -510,7 +427,7 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
 #pragma unroll
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twi[m];
     __syncthreads();
-    lds_transform_pad_any<true, NTT_ROWS_BLOCK>(k2, bufa, tws, P);
+    lds_transform_pad_any<true, NTT_ROWS_BLOCK, 0>(k2, bufa, tws, P);
     // inverse twiddle w_N^-(n2 k1) and the scale R / N (the pointwise product left R^-1):
     // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N.  The exponent
     // n2 bitrev(r) < 2^k <= 2^23 fits in 32 bits.
@@ -553,52 +470,54 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_rows_kernel(Launch<NttJob> L) {
 constexpr int NTT_ROWS_TWS_SMALL = 1 << 10, NTT_ROWS_TWS = 1 << 12;
 static_assert(NTT_ROWS_TWS >= (1 << (NTT_MAX_LOG - NTT_MAX_LOG / 2)), "stage twiddles of the longest rows");
 
-template <int Q>
-__device__ __forceinline__ void inv_cols_body(const NttJob &J, int64_t local, uint32_t *buf, uint32_t *tw) {
+template <int Q, int TWS>
+__device__ __forceinline__ void inv_cols_body(const NttJob &J, int64_t local, uint32_t *buf, uint32_t *tws) {
     const int k1 = J.k1, k2 = J.k2, k = k1 + k2;
-    const int lc = 13 - k1, C = 1 << lc, S = (1 << k1) + 1;
+    const int lc = 13 - k1, C = 1 << lc, SC = pad_len(1 << k1) + 1;
     const int gl = k - 13;
     constexpr int q = Q;
     const int64_t c0 = (local & (((int64_t)1 << gl) - 1)) * C;
     constexpr NttPrime P = ntt_prime_c(Q);
-    load_twiddles<true>(tw, q, k1, P);
     uint32_t *x = J.x + ((int64_t)q << k);
     const int t = threadIdx.x;
+    constexpr int TPT = TWS / NTT_TPB;
+    uint32_t twi[TPT];
+#pragma unroll
+    for (int m = 0; m < TPT; ++m) twi[m] = ldg(&ntt_stage_tab[q][1][t + m * NTT_TPB]);
+    // element e = t + 256 i: column c = t mod C, row n1 = t / C + i 256 / C
+    const int ct = t & (C - 1), n1t = t >> lc, n1s = NTT_TPB >> lc;
+    uint32_t *bt = buf + ct * SC;
 #pragma unroll 1
     for (int i0 = 0; i0 < EPT; i0 += CH) {
         uint32_t v[CH];
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int e = t + (i0 + i) * NTT_TPB;
-            v[i] = ldg(x + ((int64_t)(e >> lc) << k2) + c0 + (e & (C - 1)));
-        }
+        for (int i = 0; i < CH; ++i) v[i] = ldg(x + ((int64_t)(n1t + (i0 + i) * n1s) << k2) + c0 + ct);
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int e = t + (i0 + i) * NTT_TPB;
-            buf[(e & (C - 1)) * S + (e >> lc)] = v[i];
-        }
+        for (int i = 0; i < CH; ++i) bt[pad_ix(n1t + (i0 + i) * n1s)] = v[i];
     }
+#pragma unroll
+    for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twi[m];
     __syncthreads();
-    lds_transform_any<true>(k1, buf, S, tw, P);
+    lds_transform_pad_any<true, NTT_BLOCK, 1>(k1, buf, tws, P);
     // the residues of terms N2 n1 + n2 in natural order, fully reduced, in place (the block's
     // columns hold exactly the positions it read)
 #pragma unroll 8
     for (int i = 0; i < EPT; ++i) {
-        const int e = t + i * NTT_TPB;
-        const int c = e & (C - 1), n1 = e >> lc;
-        stg(x + ((int64_t)n1 << k2) + c0 + c, red1(red2(buf[c * S + n1], P.p), P.p));
+        const int n1 = n1t + i * n1s;
+        stg(x + ((int64_t)n1 << k2) + c0 + ct, red1(red2(bt[pad_ix(n1)], P.p), P.p));
     }
 }
 
+template <int TWS>
 __global__ __launch_bounds__(NTT_TPB) void ntt_inv_cols_kernel(Launch<NttJob> L) {
-    __shared__ uint32_t buf[NTT_BLOCK + 128];  // C columns of N1 + 1 words (C <= 128)
-    __shared__ uint32_t tw[NTT_COL_TW];
+    __shared__ uint32_t buf[NTT_COL_BUF];
+    __shared__ uint32_t tws[TWS];
     int64_t local;
     const NttJob J = get_job(L, xcd_block((int64_t)blockIdx.x, L.total_blocks), local);
     if ((local >> (J.k1 + J.k2 - 13)) == 0)
-        inv_cols_body<0>(J, local, buf, tw);
+        inv_cols_body<0, TWS>(J, local, buf, tws);
     else
-        inv_cols_body<1>(J, local, buf, tw);
+        inv_cols_body<1, TWS>(J, local, buf, tws);
 }
 
 // the join: one thread per limb column, the (at most two for w >= 16, three for w >= 11) terms
@@ -715,18 +634,28 @@ hipError_t launch_ntt_join(const Launch<NttJoinJob> &L, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, int max_k2, hipStream_t s) {
+hipError_t launch_ntt_stage(int stage, const Launch<NttJob> &L, int max_k1, int max_k2, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     const dim3 g((unsigned)L.total_blocks), b(NTT_TPB);
     switch (stage) {
-        case 0: ks_launch(ntt_fwd_cols_kernel, g, b, 0, s, L); break;
+        case 0:
+            if (max_k1 <= 10)
+                ks_launch(ntt_fwd_cols_kernel<NTT_COLS_TWS_SMALL>, g, b, 0, s, L);
+            else
+                ks_launch(ntt_fwd_cols_kernel<NTT_COLS_TWS>, g, b, 0, s, L);
+            break;
         case 1:
             if (max_k2 <= 10)
                 ks_launch(ntt_rows_kernel<NTT_ROWS_TWS_SMALL>, g, b, 0, s, L);
             else
                 ks_launch(ntt_rows_kernel<NTT_ROWS_TWS>, g, b, 0, s, L);
             break;
-        case 2: ks_launch(ntt_inv_cols_kernel, g, b, 0, s, L); break;
+        case 2:
+            if (max_k1 <= 10)
+                ks_launch(ntt_inv_cols_kernel<NTT_COLS_TWS_SMALL>, g, b, 0, s, L);
+            else
+                ks_launch(ntt_inv_cols_kernel<NTT_COLS_TWS>, g, b, 0, s, L);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
