@@ -289,9 +289,20 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
     const uint32_t last = na >= 2 ? na - 2 : 0;
     uint32_t *bt = buf + (t & (C - 1)) * SC;
     const int n1t = t >> lc, n1s = NTT_TPB >> lc;
+    // The pieces at or beyond np are the transform's zero padding (about half of them).  Lane 0
+    // of a wave holds its smallest piece index and element i adds i mstep to every lane's, so
+    // the chunks of elements from iz on are zero on the whole wave: stored as zeros, unloaded.
+    const uint32_t mt0 = __builtin_amdgcn_readfirstlane(mt);
+    const int lms = 8 - lc + k2;  // mstep = 2^lms
+    const int iz = mt0 >= np ? 0 : (int)min((uint32_t)EPT, (np - mt0 + mstep - 1u) >> lms);
     auto load = [&](auto wide) {  // wide: 8-byte loads (an operand of two limbs or more)
 #pragma unroll 1
         for (int i0 = 0; i0 < EPT; i0 += CH) {
+            if (i0 >= iz) {  // wave-uniform
+#pragma unroll
+                for (int i = 0; i < CH; ++i) bt[pad_ix(n1t + (i0 + i) * n1s)] = 0u;
+                continue;
+            }
             u32x2 v[CH];
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
