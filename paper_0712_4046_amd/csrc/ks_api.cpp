@@ -448,8 +448,10 @@ int plan_product(const Spec &sp, Geom &G) {
     G.norm_limbs = noff;
     // recombinations of the same two products with signs (+, +) and (+, -) -- P0 and P1, Q0 and
     // Q1 of the negated and four-point substitutions -- run as one job: the column windows are
-    // read once and feed two carry scans (the second looks back through words of its own)
-    for (size_t i = 0; i + 1 < G.norms.size(); ++i) {
+    // read once and feed two carry scans (the second looks back through words of its own).  In
+    // batches only: a single product is bound by latency, which the longer blocks raise (the
+    // L = 4096 product's recombination 13 -> 18 us).
+    for (size_t i = 0; sp.batch && i + 1 < G.norms.size(); ++i) {
         NormGeom &a = G.norms[i], &b = G.norms[i + 1];
         if (a.merged || a.small || b.small || a.nterms != 2 || b.nterms != 2 || a.prod[0] != b.prod[0] ||
             a.prod[1] != b.prod[1] || a.off_period != b.off_period || a.blocks != b.blocks)
@@ -680,8 +682,9 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
     // the even and odd chains of the four-point reconstruction have their anchors at
     // neighbouring coefficients: for long inputs one job computes both (one stream of f and g
     // instead of two; 64-product modular batch: pack with anchors 679 -> 549 us), while short
-    // ones keep a block per anchor (the 10,000-product batch lost 10 us paired)
-    const bool pair = std::min(sp.lf, sp.lg) >= 4096 && G.chains.size() == 2 && G.chains[0].step == 2 &&
+    // ones keep a block per anchor (the 10,000-product batch lost 10 us paired), and so does a
+    // single product, bound by latency
+    const bool pair = sp.batch && std::min(sp.lf, sp.lg) >= 4096 && G.chains.size() == 2 && G.chains[0].step == 2 &&
                       G.chains[1].step == 2 &&
                       G.chains[0].par == 0 && G.chains[1].par == 1 && G.chains[0].K == G.chains[1].K &&
                       G.chains[1].nseg <= G.chains[0].nseg;
