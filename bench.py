@@ -56,9 +56,9 @@ NTT_STEPS = {"ntt_fwd_cols": (2, 0), "ntt_rows": (3, 1), "ntt_inv_cols": (1, 0)}
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated: FETCH x2, WRITE
 # x1) on the headline workload (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).
-MEASURED_TRAFFIC_C4 = {"pack": 402730252, "ntt_fwd_cols": 1217781532, "ntt_rows": 1615455525,
-                       "ntt_inv_cols": 1076716558, "ntt_join": 975776029, "normalize": 823656284,
-                       "recon": 349765242, "finish": 271327081}
+MEASURED_TRAFFIC_C4 = {"pack": 488380937, "ntt_fwd_cols": 1218347967, "ntt_rows": 1617599622,
+                       "ntt_inv_cols": 1075294095, "ntt_join": 977412525, "normalize": 651028179,
+                       "recon": 349134244, "finish": 271337857}
 KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "ntt_fwd_cols", "ntt_rows",
            "ntt_inv_cols", "ntt_join", "normalize", "anchor", "recon", "finish", "extract", "p2_eval", "p2_recon")
 METRIC = "polynomial products/s + limb-mults/s at 1 GPU; KS4 vs KS1 speedup, bit-exact"
@@ -220,7 +220,9 @@ def headline(ks, torch, wl, args):
         dt, spread, kern = timed_steps(torch, R, args.steps, args.warmup, ks)
         R.check_status()
         outs[v] = ks.to_host(R.aout).copy()
-        eng = {ks.KS_ENGINE_VALU: "valu", ks.KS_ENGINE_MFMA: "mfma"}.get(R.info["engine"], "valu+mfma")
+        e = R.info["engine"]
+        eng = "+".join(n for n, f in (("valu", ks.KS_ENGINE_VALU), ("mfma", ks.KS_ENGINE_MFMA),
+                                      ("ntt", ks.KS_ENGINE_NTT)) if e & f) or "none"
         res[v] = {"variant": v, "engine": eng, "ms_per_batch": dt * 1e3, "ms_per_batch_spread": spread,
                   "products_per_s": len(pairs) / dt, "limb_mults_per_s": R.info["limb_mults"] / dt,
                   "schoolbook_limb_mults_per_s": R.info["schoolbook_limb_mults"] / dt,
