@@ -540,15 +540,15 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_join_kernel(Launch<NttJoinJob> L)
     J.cols = at(L.base_ws, J.cols);
     const int64_t col = local * NTT_TPB + threadIdx.x;
     if (col >= J.ncols) return;
-    const int64_t w = J.w;
-    const int64_t m0 = (32 * col + w - 1) / w;  // first term with w m >= 32 col
-    int64_t m1 = (32 * col + 31) / w;           // last term with w m < 32 col + 32
-    if (m1 > J.nz - 1) m1 = J.nz - 1;
+    // bit positions fit in 32 bits (a product has at most 30 2^23 < 2^28 bits): one 32-bit
+    // division finds the column's first term, the rest follow by adding w
+    const uint32_t w = (uint32_t)J.w, b0 = 32u * (uint32_t)col, nz = (uint32_t)J.nz;
+    uint32_t m = (b0 + w - 1u) / w;  // first term with w m >= 32 col
     uint64_t lo = 0;
     uint32_t hi = 0;
-    for (int64_t m = m0; m <= m1; ++m) {
+    for (uint32_t bit = m * w; bit < b0 + 32u && m < nz; ++m, bit += w) {
         const uint64_t z = crt2(ldg(J.x + m), ldg(J.x + J.n + m));
-        const int sh = (int)(w * m - 32 * col);  // 0 .. 31
+        const int sh = (int)(bit - b0);  // 0 .. 31
         const uint64_t zl = z << sh;
         const uint32_t zh = sh ? (uint32_t)(z >> (64 - sh)) : 0u;
         lo += zl;
