@@ -8,25 +8,10 @@ namespace ks {
 
 // Pack by scattering: each thread takes whole coefficients (coalesced loads, all independent)
 // and adds their 32-bit pieces into the block's LDS limb columns; the columns before and after
-// the block's range that the carry scan needs are filled the same way.
+// the block's range that the carry scan needs are filled the same way.  MW bounds the
+// coefficients' limbs in a launch (a launch whose inputs are all one or two limbs wide, like
+// residues modulo p < 2^62, shifts two words instead of eight).
 constexpr int PK_MAXW = 8;  // limbs of one input coefficient (coeff_bits <= 256)
-
-// bits [s, s+32) of a coefficient held in registers (s may be negative: bits below 0 read 0);
-// MW bounds the coefficient's limbs (a launch whose inputs are all one or two limbs wide, like
-// residues modulo p < 2^62, selects among two words instead of eight)
-template <int MW>
-__device__ __forceinline__ uint32_t reg_word(const uint32_t (&cl)[MW], int w, uint32_t fill, int s) {
-    if (s <= -32) return 0u;
-    if (s < 0) return cl[0] << (-s);
-    const int q = s >> 5, o = s & 31;
-    uint32_t a = fill, b = fill;
-#pragma unroll
-    for (int t = 0; t < MW; ++t) {
-        if (t < w && t == q) a = cl[t];
-        if (t < w && t == q + 1) b = cl[t];
-    }
-    return o ? (a >> o) | (b << (32 - o)) : a;
-}
 
 // A block of pack job J with TPB threads (TPB * IPT limbs per block); `local` is its position
 // in the job when the job has one block (else it draws a ticket).  The caller looks the job
@@ -83,24 +68,35 @@ __device__ __forceinline__ void pack_block(const PackJob &J, int64_t local, cons
         for (int q = 0; q < U; ++q) {
             const int64_t i = ib + (int64_t)q * TPB;
             if (i > i1) continue;
+            // the coefficient's words with their sign fill above w_in: ext[0..MW]
             uint32_t top = 0;
 #pragma unroll
             for (int t = 0; t < MW; ++t) top = (t == w_in - 1) ? cl[q][t] : top;
             const uint32_t fill = (sgn && (top >> 31)) ? 0xffffffffu : 0u;
-            const int64_t p = i * N;
-            const int64_t w = p >> 5;
-            const int r = (int)(p & 31);
-            const int npieces = (bits + r + 31) >> 5;
-            const bool neg = (J.flags & PK_ALTERNATE) && (i & 1);
-            for (int t = 0; t < npieces; ++t) {
-                const int64_t j = w + t;
-                if (j < jlo || j >= jhi) continue;
-                const uint32_t word = reg_word(cl[q], w_in, fill, 32 * t - r);
-                int64_t piece = (sgn && t == npieces - 1) ? (int64_t)(int32_t)word : (int64_t)word;
-                if (neg) piece = -piece;
-                atomicAdd(reinterpret_cast<unsigned long long *>(&s_v[j - jb + 2]), (unsigned long long)piece);
+            uint32_t ext[MW + 1];
+#pragma unroll
+            for (int t = 0; t < MW; ++t) ext[t] = t < w_in ? cl[q][t] : fill;
+            ext[MW] = fill;
+            // its first bit relative to column jlo, in (-bits, 32 (BL + 3)): the low 32 bits of
+            // i N and 32 jlo determine it
+            const int32_t rel = (int32_t)((uint32_t)i * (uint32_t)N - ((uint32_t)jlo << 5));
+            const int32_t cr = rel >> 5;  // its lowest column, relative to jlo
+            const int r = rel & 31;
+            const int npieces = (bits + r + 31) >> 5;  // at most MW + 1
+            const uint64_t nmask = ((J.flags & PK_ALTERNATE) && (i & 1)) ? ~0ull : 0ull;
+            // piece t: bits [32 t - r, 32 t - r + 32) of the coefficient, the top one read signed
+#pragma unroll
+            for (int t = 0; t <= MW; ++t) {
+                const int32_t jr = cr + t;
+                if (t < npieces && (uint32_t)jr < (uint32_t)(BL + 3)) {
+                    const uint32_t word =
+                        t == 0 ? ext[0] << r : (r ? __builtin_amdgcn_alignbit(ext[t], ext[t - 1], 32 - r) : ext[t]);
+                    const int64_t piece = (sgn && t == npieces - 1) ? (int64_t)(int32_t)word : (int64_t)word;
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&s_v[jr]),
+                              (unsigned long long)(((uint64_t)piece ^ nmask) - nmask));
+                }
             }
-            if ((J.flags & PK_CHECK) && w >= jb && w < jb + BL) {
+            if ((J.flags & PK_CHECK) && (uint32_t)(cr - 2) < (uint32_t)BL) {
                 // range check, once per coefficient (in the block holding its lowest limb)
                 bool ok;
                 if (J.mod_p) {
