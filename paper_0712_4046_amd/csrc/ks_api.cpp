@@ -219,6 +219,7 @@ int plan_product(const Spec &sp, Geom &G) {
     G = Geom();
     G.sp = sp;
     G.ipt = sp.batch ? SCAN_IPT_BATCH : SCAN_IPT_SINGLE;
+    G.pack_ipt = sp.batch ? PACK_IPT_BATCH : SCAN_IPT_SINGLE;
     const int64_t lf = sp.lf, lg = sp.lg;
     const int b = sp.bits;
     G.e = ceil_log2(std::min(lf, lg));
@@ -254,8 +255,8 @@ int plan_product(const Spec &sp, Geom &G) {
             p.L = which ? lg : lf;
             p.n_out = which ? ng : nf;
             p.op_off = off;
-            p.small = p.n_out <= std::min<int64_t>(small_bl(G.ipt), env_int("KS_SCAN_SMALL", (int)small_bl(G.ipt)));
-            p.blocks = p.small ? 1 : cdiv(p.n_out, scan_bl(G.ipt));
+            p.small = p.n_out <= std::min<int64_t>(small_bl(G.pack_ipt), env_int("KS_SCAN_SMALL", (int)small_bl(G.pack_ipt)));
+            p.blocks = p.small ? 1 : cdiv(p.n_out, scan_bl(G.pack_ipt));
             off += align_up(p.n_out, 64);
             G.packs.push_back(p);
             G.pack_blocks += p.blocks;
@@ -558,6 +559,7 @@ int64_t assign_dual_status(JobLists &JL) {
 void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t ws, JobLists &JL) {
     const Spec &sp = G.sp;
     JL.ipt = G.ipt;  // the products of one list are planned alike (all single or all batched)
+    JL.pack_ipt = G.pack_ipt;
     for (auto &m : G.muls)
         if (m.engine == KS_ENGINE_MFMA) JL.mfma_rt = m.rt;
     auto ops = [&](int64_t limb_off) { return reinterpret_cast<uint32_t *>(ws + G.ws_ops + 4 * limb_off); };
@@ -848,9 +850,9 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         if (first_anchor != JL.anchor.end()) {
             auto La = make_launch(first_anchor->second, T ? &T->anchor.at(first_anchor->first) : nullptr, env, 0);
             err = timed("pack", s,
-                        [&] { return launch_pack_anchor(L, La, first_anchor->first, JL.ipt, pack_w, s); });
+                        [&] { return launch_pack_anchor(L, La, first_anchor->first, JL.pack_ipt, pack_w, s); });
         } else {
-            err = timed("pack", s, [&] { return launch_pack(L, JL.ipt, pack_w, s); });
+            err = timed("pack", s, [&] { return launch_pack(L, JL.pack_ipt, pack_w, s); });
         }
         if (err != hipSuccess) return KS_EHIP;
     }
@@ -858,7 +860,7 @@ int launch_lists(const JobLists &JL, const DevTables *T, const LaunchEnv &env, u
         auto L = make_launch(JL.pack_small, T ? &T->pack_small : nullptr, env, epoch_pack);
         int pack_w = 0;
         for (const auto &j : JL.pack_small) pack_w = std::max(pack_w, (int)j.w_in);
-        err = timed("pack", s, [&] { return launch_pack_small(L, JL.ipt, pack_w, s); });
+        err = timed("pack", s, [&] { return launch_pack_small(L, JL.pack_ipt, pack_w, s); });
         if (err != hipSuccess) return KS_EHIP;
     }
     if (!JL.mul.empty()) {

@@ -22,6 +22,9 @@ constexpr int MAX_INLINE_JOBS = 8;
 constexpr int SCAN_TPB = 256;
 constexpr int SMALL_TPB = 64;
 constexpr int SCAN_IPT_SINGLE = 2, SCAN_IPT_BATCH = 4;
+// limbs per thread of a batch's pack blocks: twice the recombination's (pack keeps few values
+// per limb in registers, and larger blocks pay the ticket and the look-back half as often)
+constexpr int PACK_IPT_BATCH = 8;
 constexpr int64_t scan_bl(int ipt) { return (int64_t)SCAN_TPB * ipt; }
 constexpr int64_t small_bl(int ipt) { return (int64_t)SMALL_TPB * ipt; }
 

@@ -28,7 +28,8 @@ inline void ks_launch(K kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t
     }
 }
 
-// ipt: limbs per thread of the carry-scan kernels (SCAN_IPT_SINGLE or SCAN_IPT_BATCH), as planned;
+// ipt: limbs per thread of the carry-scan kernels, as planned (pack: SCAN_IPT_SINGLE or
+// PACK_IPT_BATCH; recombination: SCAN_IPT_SINGLE or SCAN_IPT_BATCH);
 // pack_w: the widest input coefficient (limbs) among the pack jobs
 hipError_t launch_pack(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_t s);
 hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, int ipt,

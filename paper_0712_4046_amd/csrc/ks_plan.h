@@ -85,6 +85,7 @@ struct ChainGeom {
 struct Geom {
     Spec sp;
     int ipt = SCAN_IPT_SINGLE;  // limbs per thread of the carry-scan kernels
+    int pack_ipt = SCAN_IPT_SINGLE;  // of the pack kernels
     int variant = 0, e = 0, w_out = 0, off = -1, nw = 0, aw = 0, chain_lds = 0;
     int64_t chain_nd = 0;  // bits of a reconstruction digit (2N four-point, N reciprocal)
     int64_t N = 0, D = 0, m0 = 0, m1 = 0, nf = 0, ng = 0;
@@ -126,6 +127,7 @@ struct Ctl {
 // jobs of one or many products, per stage (anchor and chain lists keyed by template parameter)
 struct JobLists {
     int ipt = SCAN_IPT_SINGLE;  // limbs per thread of the carry-scan launches (as planned)
+    int pack_ipt = SCAN_IPT_SINGLE;  // of the pack launches
     int mfma_rt = 8;            // row tiles per matrix-core block (the same for every product of a list)
     std::vector<PackJob> pack;
     std::vector<PackJob> pack_small;  // jobs of at most small_bl(ipt) limbs

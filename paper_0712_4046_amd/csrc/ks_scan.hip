@@ -317,22 +317,31 @@ hipError_t launch_fill_zero(uint64_t *p, int64_t n, hipStream_t s) {
             ks_launch(K<SCAN_IPT_SINGLE>, __VA_ARGS__);     \
     } while (0)
 
+// the pack kernels of a batch (PACK_IPT_BATCH limbs per thread) or of a single product
+#define KS_PACK_IPT(ipt, K, ...)                            \
+    do {                                                    \
+        if ((ipt) == PACK_IPT_BATCH)                        \
+            ks_launch(K<PACK_IPT_BATCH>, __VA_ARGS__);      \
+        else                                                \
+            ks_launch(K<SCAN_IPT_SINGLE>, __VA_ARGS__);     \
+    } while (0)
+
 hipError_t launch_pack(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     const dim3 g((unsigned)L.total_blocks), b(SCAN_TPB);
-    const bool batch = ipt == SCAN_IPT_BATCH;
+    const bool batch = ipt == PACK_IPT_BATCH;
     if (pack_w <= 2) {
         if (batch)
-            ks_launch(pack_kernel<SCAN_IPT_BATCH, 2>, g, b, 0, s, L);
+            ks_launch(pack_kernel<PACK_IPT_BATCH, 2>, g, b, 0, s, L);
         else
             ks_launch(pack_kernel<SCAN_IPT_SINGLE, 2>, g, b, 0, s, L);
     } else if (pack_w <= 4) {
         if (batch)
-            ks_launch(pack_kernel<SCAN_IPT_BATCH, 4>, g, b, 0, s, L);
+            ks_launch(pack_kernel<PACK_IPT_BATCH, 4>, g, b, 0, s, L);
         else
             ks_launch(pack_kernel<SCAN_IPT_SINGLE, 4>, g, b, 0, s, L);
     } else {
-        KS_SCAN_IPT(ipt, pack_kernel, g, b, 0, s, L);
+        KS_PACK_IPT(ipt, pack_kernel, g, b, 0, s, L);
     }
     return hipGetLastError();
 }
@@ -374,26 +383,26 @@ static hipError_t pack_anchor_w(const Launch<PackJob> &Lp, const Launch<AnchorJo
 hipError_t launch_pack_anchor(const Launch<PackJob> &Lp, const Launch<AnchorJob> &La, int w_in, int ipt,
                               int pack_w, hipStream_t s) {
     if (La.total_blocks <= 0) return launch_pack(Lp, ipt, pack_w, s);
-    return ipt == SCAN_IPT_BATCH ? pack_anchor_w<SCAN_IPT_BATCH>(Lp, La, w_in, pack_w, s)
+    return ipt == PACK_IPT_BATCH ? pack_anchor_w<PACK_IPT_BATCH>(Lp, La, w_in, pack_w, s)
                                  : pack_anchor_w<SCAN_IPT_SINGLE>(Lp, La, w_in, pack_w, s);
 }
 
 hipError_t launch_pack_small(const Launch<PackJob> &L, int ipt, int pack_w, hipStream_t s) {
     if (L.total_blocks <= 0) return hipSuccess;
     const dim3 g((unsigned)L.total_blocks), b(SMALL_TPB);
-    const bool batch = ipt == SCAN_IPT_BATCH;
+    const bool batch = ipt == PACK_IPT_BATCH;
     if (pack_w <= 2) {
         if (batch)
-            ks_launch(pack_small_kernel<SCAN_IPT_BATCH, 2>, g, b, 0, s, L);
+            ks_launch(pack_small_kernel<PACK_IPT_BATCH, 2>, g, b, 0, s, L);
         else
             ks_launch(pack_small_kernel<SCAN_IPT_SINGLE, 2>, g, b, 0, s, L);
     } else if (pack_w <= 4) {
         if (batch)
-            ks_launch(pack_small_kernel<SCAN_IPT_BATCH, 4>, g, b, 0, s, L);
+            ks_launch(pack_small_kernel<PACK_IPT_BATCH, 4>, g, b, 0, s, L);
         else
             ks_launch(pack_small_kernel<SCAN_IPT_SINGLE, 4>, g, b, 0, s, L);
     } else {
-        KS_SCAN_IPT(ipt, pack_small_kernel, g, b, 0, s, L);
+        KS_PACK_IPT(ipt, pack_small_kernel, g, b, 0, s, L);
     }
     return hipGetLastError();
 }
