@@ -17,6 +17,11 @@ __device__ __forceinline__ void load_raw(const uint32_t *c, uint32_t (&m)[W]) {
     ldg_words<W>(c, m);
 }
 
+// p + off bytes, off unsigned 32-bit
+__device__ __forceinline__ const uint32_t *byte_at(const uint32_t *p, uint32_t off) {
+    return reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p) + off);
+}
+
 // acc (n words, mod 2^(32 n)) += v 2^(32 off), v given as words v[0..nv)
 template <int N, int NV>
 __device__ __forceinline__ void add_words(uint32_t (&acc)[N], int off, const uint32_t (&v)[NV]) {
@@ -44,6 +49,47 @@ __device__ __forceinline__ void sub_words(uint32_t (&acc)[N], int off, const uin
     }
 }
 
+// acc (AW words) += 2^(32 c) clo/chi (the NC 96-bit column sums) and the sign corrections
+template <int W>
+__device__ __forceinline__ void anchor_collect(uint32_t (&acc)[2 * W + 2], const uint64_t (&clo)[2 * W - 1],
+                                               const uint32_t (&chi)[2 * W - 1], const uint64_t (&corr)[W],
+                                               uint32_t nn, bool sgn) {
+    constexpr int AW = 2 * W + 2, NC = 2 * W - 1;
+#pragma unroll
+    for (int t = 0; t < AW; ++t) acc[t] = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t v[3] = {(uint32_t)clo[c], (uint32_t)(clo[c] >> 32), chi[c]};
+        add_words(acc, c, v);
+    }
+    if (sgn) {
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            const uint32_t v[2] = {(uint32_t)corr[t], (uint32_t)(corr[t] >> 32)};
+            sub_words(acc, W + t, v);
+        }
+        const uint32_t v[1] = {nn};
+        add_words(acc, 2 * W, v);
+    }
+}
+
+// one term f_i g_j into a column-sum accumulator (and its sign corrections)
+template <int W>
+__device__ __forceinline__ void anchor_term(uint64_t (&clo)[2 * W - 1], uint32_t (&chi)[2 * W - 1],
+                                            uint64_t (&corr)[W], uint32_t &nn, const uint32_t *a,
+                                            const uint32_t *b, bool sgn) {
+#pragma unroll
+    for (int x = 0; x < W; ++x)
+#pragma unroll
+        for (int y = 0; y < W; ++y) mac96(clo[x + y], chi[x + y], a[x], b[y]);
+    if (sgn) {
+        const bool nf = a[W - 1] >> 31, ng = b[W - 1] >> 31;
+#pragma unroll
+        for (int t = 0; t < W; ++t) corr[t] += (uint64_t)(nf ? b[t] : 0u) + (ng ? a[t] : 0u);
+        nn += (nf && ng) ? 1u : 0u;
+    }
+}
+
 // One block computes one anchor: block `local` of anchor job J.  Each lane keeps a 96-bit sum
 // per limb column of the products (mac96), plus the sign corrections above.
 template <int W>
@@ -65,10 +111,30 @@ __device__ __forceinline__ void anchor_block(const AnchorJob &J, int64_t local) 
     for (int c = 0; c < NC; ++c) { clo[c] = 0; chi[c] = 0; }
 #pragma unroll
     for (int t = 0; t < W; ++t) corr[t] = 0;
-    // U terms per round, their loads issued together (clamped addresses; a dead term's f is
-    // zeroed, which also clears its sign)
+    // U terms per round, their loads issued together.  Whole rounds (every term inside [lo, hi])
+    // need no guards and address f and g by 32-bit word offsets that move by constants; the
+    // last, partial round clamps its addresses and zeroes a dead term's f (which also clears
+    // its sign).
     constexpr int U = 4;
-    for (int64_t i0 = lo + threadIdx.x; i0 <= hi; i0 += U * ANCHOR_TPB) {
+    constexpr uint32_t STEP = (uint32_t)(ANCHOR_TPB * W * 4);  // bytes between a thread's terms
+    int64_t i0 = lo + threadIdx.x;
+    if (i0 + (U - 1) * ANCHOR_TPB <= hi) {
+        // byte offsets from f and g (below 2^32 for inputs of less than 2^27 coefficients):
+        // the loads take a scalar base and a 32-bit vector offset, no 64-bit address arithmetic
+        uint32_t fo = (uint32_t)(i0 * W * 4), go = (uint32_t)((k - i0) * W * 4);
+        for (; i0 + (U - 1) * ANCHOR_TPB <= hi; i0 += U * ANCHOR_TPB, fo += U * STEP, go -= U * STEP) {
+            uint32_t a[U][W], b[U][W];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                load_raw<W>(byte_at(J.f, fo + q * STEP), a[q]);
+                load_raw<W>(byte_at(J.g, go - q * STEP), b[q]);
+            }
+            __builtin_amdgcn_sched_barrier(0);  // all of the round's loads in flight first
+#pragma unroll
+            for (int q = 0; q < U; ++q) anchor_term<W>(clo, chi, corr, nn, a[q], b[q], sgn);
+        }
+    }
+    if (i0 <= hi) {
         uint32_t a[U][W], b[U][W];
         bool live[U];
 #pragma unroll
@@ -79,24 +145,12 @@ __device__ __forceinline__ void anchor_block(const AnchorJob &J, int64_t local) 
             load_raw<W>(J.f + ii * W, a[q]);
             load_raw<W>(J.g + (k - ii) * W, b[q]);
         }
-        // every load of the round is issued before the first use (left to itself, the compiler
-        // masked the first term right after its load and so waited on it with the rest unissued)
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
 #pragma unroll
             for (int x = 0; x < W; ++x) a[q][x] = live[q] ? a[q][x] : 0u;
-#pragma unroll
-            for (int x = 0; x < W; ++x)
-#pragma unroll
-                for (int y = 0; y < W; ++y) mac96(clo[x + y], chi[x + y], a[q][x], b[q][y]);
-            if (sgn) {
-                const bool nf = a[q][W - 1] >> 31, ng = b[q][W - 1] >> 31;
-#pragma unroll
-                for (int t = 0; t < W; ++t)
-                    corr[t] += (uint64_t)(nf ? b[q][t] : 0u) + (ng ? a[q][t] : 0u);
-                nn += (nf && ng) ? 1u : 0u;
-            }
+            anchor_term<W>(clo, chi, corr, nn, a[q], b[q], sgn);
         }
     }
     uint32_t acc[AW];
@@ -161,47 +215,6 @@ __device__ __forceinline__ void anchor_block(const AnchorJob &J, int64_t local) 
     }
 }
 
-// acc (AW words) += 2^(32 c) clo/chi (the NC 96-bit column sums) and the sign corrections
-template <int W>
-__device__ __forceinline__ void anchor_collect(uint32_t (&acc)[2 * W + 2], const uint64_t (&clo)[2 * W - 1],
-                                               const uint32_t (&chi)[2 * W - 1], const uint64_t (&corr)[W],
-                                               uint32_t nn, bool sgn) {
-    constexpr int AW = 2 * W + 2, NC = 2 * W - 1;
-#pragma unroll
-    for (int t = 0; t < AW; ++t) acc[t] = 0;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const uint32_t v[3] = {(uint32_t)clo[c], (uint32_t)(clo[c] >> 32), chi[c]};
-        add_words(acc, c, v);
-    }
-    if (sgn) {
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-            const uint32_t v[2] = {(uint32_t)corr[t], (uint32_t)(corr[t] >> 32)};
-            sub_words(acc, W + t, v);
-        }
-        const uint32_t v[1] = {nn};
-        add_words(acc, 2 * W, v);
-    }
-}
-
-// one term f_i g_j into a column-sum accumulator (and its sign corrections)
-template <int W>
-__device__ __forceinline__ void anchor_term(uint64_t (&clo)[2 * W - 1], uint32_t (&chi)[2 * W - 1],
-                                            uint64_t (&corr)[W], uint32_t &nn, const uint32_t *a,
-                                            const uint32_t *b, bool sgn) {
-#pragma unroll
-    for (int x = 0; x < W; ++x)
-#pragma unroll
-        for (int y = 0; y < W; ++y) mac96(clo[x + y], chi[x + y], a[x], b[y]);
-    if (sgn) {
-        const bool nf = a[W - 1] >> 31, ng = b[W - 1] >> 31;
-#pragma unroll
-        for (int t = 0; t < W; ++t) corr[t] += (uint64_t)(nf ? b[t] : 0u) + (ng ? a[t] : 0u);
-        nn += (nf && ng) ? 1u : 0u;
-    }
-}
-
 // Two anchors in one pass: h_k for job J's chain (anchor s) and h_{k+1} for its second chain
 // (anchor s of anchors2, when s < nseg2).  Both read f_i against neighbouring coefficients of
 // g, so the pair costs one stream of the inputs instead of two: the two g coefficients of a
@@ -227,7 +240,26 @@ __device__ __forceinline__ void anchor_pair_block(const AnchorJob &J, int64_t lo
         for (int t = 0; t < W; ++t) corr[h][t] = 0;
     }
     constexpr int U = 4;
-    for (int64_t i0 = lo + threadIdx.x; i0 <= hi; i0 += U * ANCHOR_TPB) {
+    constexpr uint32_t STEP = (uint32_t)(ANCHOR_TPB * W * 4);
+    int64_t i0 = lo + threadIdx.x;
+    if (i0 + (U - 1) * ANCHOR_TPB <= hi) {  // whole rounds, unguarded (as in anchor_block)
+        uint32_t fo = (uint32_t)(i0 * W * 4), go = (uint32_t)((k - i0) * W * 4);
+        for (; i0 + (U - 1) * ANCHOR_TPB <= hi; i0 += U * ANCHOR_TPB, fo += U * STEP, go -= U * STEP) {
+            uint32_t a[U][W], b[U][2 * W];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                load_raw<W>(byte_at(J.f, fo + q * STEP), a[q]);
+                ldg_words<2 * W>(byte_at(J.g, go - q * STEP), b[q]);  // g_{k-i}, g_{k-i+1}
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                anchor_term<W>(clo[0], chi[0], corr[0], nn[0], a[q], b[q], sgn);
+                anchor_term<W>(clo[1], chi[1], corr[1], nn[1], a[q], b[q] + W, sgn);
+            }
+        }
+    }
+    if (i0 <= hi) {  // the last, partial round
         uint32_t a[U][W], b[U][2 * W];
         bool live[U];
 #pragma unroll
@@ -236,9 +268,9 @@ __device__ __forceinline__ void anchor_pair_block(const AnchorJob &J, int64_t lo
             live[q] = i <= hi;
             const int64_t ii = live[q] ? i : lo;
             load_raw<W>(J.f + ii * W, a[q]);
-            ldg_words<2 * W>(J.g + (k - ii) * W, b[q]);  // g_{k-i}, g_{k-i+1}
+            ldg_words<2 * W>(J.g + (k - ii) * W, b[q]);
         }
-        __builtin_amdgcn_sched_barrier(0);  // all of the round's loads in flight, as above
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
 #pragma unroll
