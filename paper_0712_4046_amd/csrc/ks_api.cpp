@@ -604,6 +604,10 @@ void emit_jobs(const Geom &G, uintptr_t f, uintptr_t g, uintptr_t h, uintptr_t w
             const int64_t per_prime = (int64_t)1 << (k - 13);  // column blocks of one prime
             for (int side = 0; side < 2; ++side) {
                 NttJob f = j;
+                if (side == 0) {  // the first operand's twiddles carry no factor (R in Montgomery form)
+                    f.kscale[0] = (uint32_t)(((uint64_t)1 << 32) % NTT_P0);
+                    f.kscale[1] = (uint32_t)(((uint64_t)1 << 32) % NTT_P1);
+                }
                 f.a = ops(G.packs[side ? m.fb : m.fa].op_off);
                 f.na = side ? m.nb : m.na;
                 f.np = side ? m.ntt_npb : m.ntt_npa;

@@ -157,7 +157,9 @@ struct NttJob {
     int32_t k1, k2;     // N1 = 2^k1, N2 = 2^k2
     int32_t w;          // piece bits
     int32_t pad;
-    uint32_t kscale[2]; // inverse rows: R^2 / N mod P (R = 2^32), per prime
+    uint32_t kscale[2]; // forward columns: the factor the four-step twiddles carry, per prime: R^2 / N
+                        // mod P (R = 2^32) for the second operand, which with the pointwise product's
+                        // R^-1 makes the inverse's scale 1 / N; R mod P (none) for the first
     int64_t block0;
     int64_t nblocks;
 };

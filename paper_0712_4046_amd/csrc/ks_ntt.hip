@@ -12,11 +12,11 @@
 // A product's transforms of length N = N1 N2 run in three steps (each one launch over every
 // job) and a join:
 //   forward columns  per operand, N2 transforms of length N1 over the stride-N2 columns
-//                    x[N2 n1 + n2], then the twiddle w_N^(n2 k1); stored row-wise (row k1,
-//                    N2 columns)
+//                    x[N2 n1 + n2], then the twiddle w_N^(n2 k1) (for the second operand times
+//                    R^2 / N, the inverse's scale); stored row-wise (row k1, N2 columns)
 //   rows             per product, N1 transforms of length N2 over the rows of both operands,
-//                    their pointwise product (Montgomery), the inverse row transforms, the
-//                    inverse twiddle and the scale 1/N
+//                    their pointwise product (Montgomery), the inverse row transforms and the
+//                    inverse twiddle
 //   inverse columns  the inverse column transforms, the residues of the convolution terms
 //                    written in order (in place)
 //   join             the two residues of each term joined by the Chinese remainder theorem,
@@ -347,7 +347,10 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
         const int r = run >> lrpr;
         const int cf = (run - (r << lrpr)) << lcols;
         const uint32_t kk = bitrev((uint32_t)r, k1);
-        uint32_t w = root_pow(q, (uint32_t)(((c0 + cf) * (int64_t)kk) << sh) & ((1u << NTT_ROOT_LOG) - 1u), P);
+        // (times the job's factor: R^2 / N for the second operand, so that the inverse needs
+        // no scaling of its own)
+        uint32_t w = mmul(root_pow(q, (uint32_t)(((c0 + cf) * (int64_t)kk) << sh) & ((1u << NTT_ROOT_LOG) - 1u), P),
+                          J.kscale[Q], P);
         const uint32_t g = root_pow(q, (uint32_t)(((int64_t)kk) << sh), P);
         uint32_t *dst = x + ((int64_t)r << k2) + c0 + cf;
         const uint32_t *src = buf + cf * SC + pad_ix(r);
@@ -439,10 +442,8 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twi[m];
     __syncthreads();
     lds_transform_pad_any<true, NTT_ROWS_BLOCK, 0>(k2, bufa, tws, P);
-    // inverse twiddle w_N^-(n2 k1) and the scale R / N (the pointwise product left R^-1):
-    // multiplying by T = w^-e R^2 / N in Montgomery form gives v w^-e R / N.  The exponent
-    // n2 bitrev(r) < 2^k <= 2^23 fits in 32 bits.
-    const uint32_t K = J.kscale[Q];
+    // inverse twiddle w_N^-(n2 k1) (the scale 1 / N came in with the second operand's forward
+    // twiddles).  The exponent n2 bitrev(r) < 2^k <= 2^23 fits in 32 bits.
     const uint32_t emask = (1u << NTT_ROOT_LOG) - 1u;
     const int sh = NTT_ROOT_LOG - k;
 #pragma unroll 1
@@ -459,7 +460,7 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
             const int e = t + (i0 + i) * NTT_TPB;
-            stg(x + e, mmul_lazy(bufa[tp + (i0 + i) * PSTEP], mmul(mmul(a[i], b[i], P), K, P), P));  // below 2P
+            stg(x + e, mmul_lazy(bufa[tp + (i0 + i) * PSTEP], mmul(a[i], b[i], P), P));  // below 2P
         }
     }
 }
