@@ -34,20 +34,24 @@ __global__ __launch_bounds__(SMALL_TPB) void pack_small_kernel(Launch<PackJob> L
     pack_block<SMALL_TPB, IPT, MW>(J, local, ctl_of(L));
 }
 
-// Pack and anchors in one launch: blocks [0, anchor blocks) compute anchors, which read only
-// the inputs and so run beside the packing, the rest pack.  The anchor blocks are few and long
-// (a dot product over the inputs each) and go first; the short pack blocks fill in around them.
-// (Pack blocks wait only on pack blocks that drew earlier tickets, anchor blocks on nothing.)
+// Pack and anchors in one launch: anchors read only the inputs and so run beside the packing.
+// In a batch the anchor blocks, fewer and longer (a dot product over the inputs each), go
+// first (blocks [0, anchor blocks)) and the short pack blocks fill in around them; a single
+// product, bound by its pack's look-back chain, dispatches its pack blocks first.  (Pack
+// blocks wait only on pack blocks that drew earlier tickets, anchor blocks on nothing.)
 static_assert(SCAN_TPB == ANCHOR_TPB, "pack and anchor blocks share one launch");
 template <int W, int IPT, int MW = PK_MAXW>
 __global__ __launch_bounds__(SCAN_TPB) void pack_anchor_kernel(Launch<PackJob> Lp, Launch<AnchorJob> La) {
     int64_t local;
-    if ((int64_t)blockIdx.x >= La.total_blocks) {
-        const PackJob J = get_job(Lp, (int64_t)blockIdx.x - La.total_blocks, local);
+    constexpr bool AFIRST = IPT == PACK_IPT_BATCH;
+    const int64_t pb = AFIRST ? (int64_t)blockIdx.x - La.total_blocks : (int64_t)blockIdx.x;
+    const int64_t ab = AFIRST ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - Lp.total_blocks;
+    if (pb >= 0 && pb < Lp.total_blocks) {
+        const PackJob J = get_job(Lp, pb, local);
         pack_block<SCAN_TPB, IPT, MW>(J, local, ctl_of(Lp));
     } else {
         // a product's anchors re-read its inputs: keep them on one XCD (xcd_block)
-        const AnchorJob J = get_job(La, xcd_block((int64_t)blockIdx.x, La.total_blocks), local);
+        const AnchorJob J = get_job(La, xcd_block(ab, La.total_blocks), local);
         if (J.nseg2 > 0)
             anchor_pair_block<W>(J, local);
         else
