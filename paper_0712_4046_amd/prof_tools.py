@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Helpers for rocprofv3 measurements of the library (used to make the files in profiles/).
 
-    python -m paper_0712_4046_amd.prof_tools workload [product_4096_s64|batch_mixed_10000|batch_mod_64x65536] [valu|mfma|ntt]
+    python -m paper_0712_4046_amd.prof_tools workload [product_4096_s64[_variants]|batch_mixed_10000|batch_mod_64x65536|poly2] [valu|mfma|ntt]
     python -m paper_0712_4046_amd.prof_tools summarize DB "cmd"  # kernel-trace summary table
     python -m paper_0712_4046_amd.prof_tools counters FETCH_DB WRITE_DB   # HBM bytes per kernel
     python -m paper_0712_4046_amd.prof_tools valu   # vector-ALU instruction rates (libksprobe.so)
@@ -21,6 +21,7 @@ COPY_MIB = 256
 def workload(name: str = "product_4096_s64", reps: int = 5, engine=None):
     """A plain device copy of COPY_MIB MiB (the FETCH_SIZE / WRITE_SIZE calibration), then
     product_4096_s64: `reps` four-point products of the L = 4096 signed 64-bit workload (seed 2);
+    product_4096_s64_variants: 50 products of the same workload through each of ks4, ks1, neg2, recip2;
     batch_mixed_10000: one four-point run of the 10,000-product batch (seed 3);
     batch_mod_64x65536: one four-point run of the 64-product modular batch (seed 4);
     poly2: `reps` four-point bivariate products of the (Z/pZ)[x, y] workload (seed 7)."""
@@ -32,11 +33,13 @@ def workload(name: str = "product_4096_s64", reps: int = 5, engine=None):
     dst = torch.empty_like(src)
     dst.copy_(src)  # known traffic: COPY_MIB MiB read and COPY_MIB MiB written
     torch.cuda.synchronize()
-    if name == "product_4096_s64":
+    if name in ("product_4096_s64", "product_4096_s64_variants"):
         P = wl.product_4096_s64()
         tf, tg = ks.to_device(P.f), ks.to_device(P.g)
-        for _ in range(reps):
-            ks.mul(tf, tg, P.bits, "ks4", P.signed, engine=engine)
+        variants = ("ks4",) if name == "product_4096_s64" else ("ks4", "ks1", "neg2", "recip2")
+        for v in variants:
+            for _ in range(reps if name == "product_4096_s64" else 50):
+                ks.mul(tf, tg, P.bits, v, P.signed, engine=engine)
         ks.check()
     elif name == "poly2":
         import numpy as np
