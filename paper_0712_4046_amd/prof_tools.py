@@ -5,6 +5,7 @@
     python -m paper_0712_4046_amd.prof_tools summarize DB "cmd"  # kernel-trace summary table
     python -m paper_0712_4046_amd.prof_tools counters FETCH_DB WRITE_DB   # HBM bytes per kernel
     python -m paper_0712_4046_amd.prof_tools valu   # vector-ALU instruction rates (libksprobe.so)
+    python -m paper_0712_4046_amd.prof_tools issue DB [DB ...]   # per-kernel counters, VALU issue rate
 
 The workload is a plain device copy of known size (to calibrate FETCH_SIZE / WRITE_SIZE) and
 then the benchmark product (one Z[x] product, L = 4096, signed 64-bit coefficients, seed 2)
@@ -145,6 +146,34 @@ def pmc_table(db: str, cmd: str = ""):
         print(f"    {c:32s} {v:20.1f}   (dispatches: {n})")
 
 
+def issue_table(dbs, cus: int = 256, xcds: int = 8):
+    """Per kernel, the counters of several --pmc runs of one workload (one dispatch each) and the
+    vector-ALU issue rate: SQ_INSTS_VALU (wave instructions) / (CUs x GRBM_GUI_ACTIVE / XCDs).
+    GRBM_GUI_ACTIVE adds up the busy cycles of the XCDs; a CU issues at most one wave64 vector
+    instruction per cycle (four SIMDs, four cycles each), so the rate is the fraction of the
+    vector ALUs' issue slots used."""
+    rows = {}
+    for db in dbs:
+        con = sqlite3.connect(db)
+        for k, c, v in con.execute("select kernel_name, counter_name, avg(value) from counters_collection "
+                                   "group by kernel_name, counter_name"):
+            rows.setdefault(k, {})[c] = v
+    print("# rocprofv3 --pmc counters per dispatch and the vector-ALU issue rate")
+    print(f"# issue = SQ_INSTS_VALU / ({cus} CUs x GRBM_GUI_ACTIVE / {xcds} XCDs); "
+          "wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES; conflicts = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS")
+    print(f"{'kernel':60s} {'VALU (M)':>9s} {'LDS (M)':>8s} {'issue':>6s} {'wait':>6s} {'conflicts':>9s}")
+    for k, c in rows.items():
+        if "ks::" not in k or "fill_zero" in k or "GRBM_GUI_ACTIVE" not in c or "SQ_INSTS_VALU" not in c:
+            continue
+        clk = c["GRBM_GUI_ACTIVE"] / xcds
+        issue = c["SQ_INSTS_VALU"] / (cus * clk) if clk else 0.0
+        wait = c.get("SQ_WAIT_ANY", 0.0) / c["SQ_WAVE_CYCLES"] if c.get("SQ_WAVE_CYCLES") else 0.0
+        conf = (c.get("SQ_LDS_BANK_CONFLICT", 0.0) / c["SQ_ACTIVE_INST_LDS"]) if c.get("SQ_ACTIVE_INST_LDS") else 0.0
+        short = k if len(k) <= 60 else k[:57] + "..."
+        print(f"{short:60s} {c['SQ_INSTS_VALU'] / 1e6:9.1f} {c.get('SQ_INSTS_LDS', 0.0) / 1e6:8.1f} "
+              f"{issue:6.2f} {wait:6.2f} {conf:9.2f}")
+
+
 def valu_rates(blocks: int = 4096, iters: int = 4096, reps: int = 5):
     """Issue rate of each probe operation (probe/valu_rates.hip): lane-operations per second
     over the whole chip, and the lanes per SIMD per clock that rate means at the nominal
@@ -183,3 +212,5 @@ if __name__ == "__main__":
         pmc_table(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
     elif cmd == "valu":
         valu_rates()
+    elif cmd == "issue":
+        issue_table(sys.argv[2:])
