@@ -314,8 +314,12 @@ int ks_profile_reset(void);
  *   "KS_MFMA_RT"         0     row tiles per matrix-core block, 4 or 8 (0: 4 for a single product
  *                              of at most 256 eight-tile row groups, else 8)
  *   "KS_SCAN_SMALL"      128   pack and recombination jobs of at most this many limbs (at most
- *                              128; 256 in a batch, and unset, a batch uses 256) run one wave
- *                              per job (0: every job in 256-thread blocks)
+ *                              128; in a batch at most 512 for pack and 256 for recombination,
+ *                              and unset, a batch uses those) run one wave per job (0: every
+ *                              job in 256-thread blocks)
+ *   "KS_SCAN_BIG"        150000 a single product whose result has at least this many limbs
+ *                              (D (2b + e) / 32) takes a batch's larger carry-scan blocks
+ *                              (0: never)
  *   "KS_NTT_MIN_LIMBS"   40000 both operands at least this many limbs -> transform engine
  *                              (unset, the products of a batch use 12000; 0: never unless forced)
  *   "KS_KARATSUBA_MIN_LIMBS" 16384  t: a batch plan whose products are all modular with equal

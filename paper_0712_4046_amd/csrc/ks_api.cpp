@@ -41,7 +41,7 @@ static int64_t align_up(int64_t x, int64_t a) { return cdiv(x, a) * a; }
 static const char *const k_tunables[] = {"KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS",  "KS_MFMA_MIN_PART",
                                          "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",     "KS_MUL_WAVE_MAX",
                                          "KS_SCAN_SMALL",      "KS_MFMA_RT",      "KS_KARATSUBA_MIN_LIMBS",
-                                         "KS_NTT_MIN_LIMBS"};
+                                         "KS_NTT_MIN_LIMBS",   "KS_SCAN_BIG"};
 static std::mutex g_tune_mu;
 static std::map<std::string, int64_t> g_tune;
 static uint64_t g_tune_gen = 0;  // bumped by every ks_tune_set / ks_tune_reset
@@ -238,6 +238,15 @@ int plan_product(const Spec &sp, Geom &G) {
     const int64_t nf = cdiv(N * (lf - 1) + b + 2, 32), ng = cdiv(N * (lg - 1) + b + 2, 32);
     G.nf = nf;
     G.ng = ng;
+    // A single product whose result holds many limbs is bound by throughput like a batch: it
+    // takes a batch's carry-scan blocks, which pay the ticket and the look-back over twice or
+    // four times as many limbs (L = 65536, b = 256: 0.35 -> 0.29 ms standard, 0.70 -> 0.57 ms
+    // four-point).  Small ones keep the short blocks that their latency favours.
+    const int64_t big_min = env_int("KS_SCAN_BIG", SCAN_BIG_LIMBS);
+    if (!sp.batch && big_min > 0 && G.D * (2 * (int64_t)b + G.e) / 32 >= big_min) {
+        G.ipt = SCAN_IPT_BATCH;
+        G.pack_ipt = PACK_IPT_BATCH;
+    }
 
     // evaluations: f points first, then the same points for g
     std::vector<int> pf;
@@ -1447,7 +1456,7 @@ int ks_tune_set(const char *name, int64_t value) {
 int ks_tune_get(const char *name, int64_t *value) {
     if (!name || !value || !known_tunable(name)) return KS_EINVAL;
     static const int dflt[] = {2500, 0, 128, 10, 0, 128, (int)small_bl(SCAN_IPT_SINGLE), 0,
-                               KARATSUBA_MIN_LIMBS, NTT_MIN_LIMBS};  // as for a single product
+                               KARATSUBA_MIN_LIMBS, NTT_MIN_LIMBS, SCAN_BIG_LIMBS};  // as for a single product
     int d = 0;
     for (size_t q = 0; q < sizeof(k_tunables) / sizeof(k_tunables[0]); ++q)
         if (strcmp(k_tunables[q], name) == 0) d = dflt[q];

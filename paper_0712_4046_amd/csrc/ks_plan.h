@@ -195,6 +195,9 @@ int ntt_prepare();
 // planner defaults of KS_NTT_MIN_LIMBS: a single product pays the transforms' four launches
 // alone (measured crossing against the matrix cores: 35K-55K operand limbs), a batch shares them
 constexpr int NTT_MIN_LIMBS = 40000, NTT_MIN_LIMBS_BATCH = 12000;
+// planner default of KS_SCAN_BIG: a single product whose result has at least this many limbs
+// (D (2b + e) / 32) takes a batch's carry-scan blocks
+constexpr int SCAN_BIG_LIMBS = 150000;
 // whether ks_batch_plan_create would split this batch by Karatsuba (see KS_KARATSUBA_MIN_LIMBS)
 bool karatsuba_splits(const ks_desc *descs, int64_t count, int32_t variant);
 // batches of modular products of equal lengths whose integer operands have at least this

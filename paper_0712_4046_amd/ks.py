@@ -250,7 +250,7 @@ def profile_reset():
 
 
 TUNABLES = ("KS_MFMA_MIN_LIMBS", "KS_MFMA_BLOCKS", "KS_MFMA_MIN_PART", "KS_MFMA_BLOCK_COST", "KS_CHAIN_K",
-            "KS_MUL_WAVE_MAX", "KS_SCAN_SMALL", "KS_MFMA_RT", "KS_KARATSUBA_MIN_LIMBS", "KS_NTT_MIN_LIMBS")
+            "KS_MUL_WAVE_MAX", "KS_SCAN_SMALL", "KS_MFMA_RT", "KS_KARATSUBA_MIN_LIMBS", "KS_NTT_MIN_LIMBS", "KS_SCAN_BIG")
 
 
 def tune_set(name: str, value: int):

@@ -112,6 +112,21 @@ def test_multi_block_sizes(torch_dev, oracle, lf, lg, bits, signed):
             assert_same(gpu_mul(f, g, bits, v, signed, e), exp, f"{v} {e} lf={lf} lg={lg} b={bits}")
 
 
+@pytest.mark.parametrize("lf,lg,bits,signed", [(4096, 4096, 64, True), (3000, 1001, 64, False), (7, 9000, 100, True),
+                                               (300, 300, 17, False)])
+def test_single_product_with_batch_scan_blocks(torch_dev, oracle, monkeypatch, lf, lg, bits, signed):
+    # KS_SCAN_BIG = 1: every single product takes a batch's carry-scan blocks (8 limbs per
+    # thread in pack, 4 in the recombination), as large single products do by default
+    monkeypatch.setenv("KS_SCAN_BIG", "1")
+    gen = wl.rng(3 * lf + lg + bits)
+    f = wl.random_coeffs(gen, lf, bits, signed)
+    g = wl.random_coeffs(gen, lg, bits, signed)
+    exp = want(oracle, f, g, bits, signed)
+    for v in VARIANTS:
+        for e in ENGINES:
+            assert_same(gpu_mul(f, g, bits, v, signed, e), exp, f"{v} {e} lf={lf} lg={lg} b={bits} batch scan blocks")
+
+
 def test_deterministic(torch_dev):
     P = wl.product_4096_s64()
     a = gpu_mul(P.f, P.g, P.bits, "ks4", True)
