@@ -25,7 +25,9 @@
 // inverse ones decimation in time (bit-reversed in, natural out), so no step reorders data:
 // rows are kept at their bit-reversed positions and the pointwise product pairs equal positions.
 // A column block transforms NTT_BLOCK elements in LDS (C = NTT_BLOCK / N1 adjacent columns), a
-// row block NTT_BLOCK / 2 elements of each operand (R = NTT_BLOCK / 2 / N2 rows).
+// row block NTT_BLOCK / 2 elements of each operand (R = NTT_BLOCK / 2 / N2 rows), both in a
+// padded layout (a spare word after every 32 elements) with per-stage twiddle tables: radix-4
+// passes down to half-size 16, then the last four stages in registers on runs of 16 elements.
 //
 // Arithmetic: residues of P < 2^30 in 32-bit words; products by Montgomery reduction with
 // R = 2^32 (a b R^-1 mod P), twiddles kept in Montgomery form so that multiplying a residue by
@@ -34,8 +36,9 @@
 // butterflies take and give values below 2P, the inverse ones below 4P, and a product is
 // left below 2P (no final subtraction), so a butterfly costs three multiply-adds and five
 // additions, subtractions or minima.  Powers of a root of unity of order 2^23 come from two
-// tables of 4096 entries per prime (w^e = w^(4096 hi) w^(lo)), built on the host once per
-// device.
+// tables of 4096 entries per prime (w^e = w^(4096 hi) w^(lo)), and the stage twiddles of the
+// transforms in LDS from a table of 4096 per prime and direction, all built on the host once
+// per device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
