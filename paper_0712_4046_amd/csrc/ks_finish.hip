@@ -367,15 +367,16 @@ __device__ __forceinline__ bool chain_fast_ok(const ChainJob &J) {
            top < J.nB;
 }
 
-// a - b - bin over NW words into r; returns the borrow out, [a < b + bin]
+// a - b - bin over NW words into r; returns the borrow out, [a < b + bin] (a chain of
+// subtractions with borrow, one instruction per word)
 template <int NW>
 __device__ __forceinline__ uint32_t mw_sub_borrow(const MW<NW> &a, const MW<NW> &b, uint32_t bin, MW<NW> &r) {
-    uint32_t br = bin;
+    unsigned int br = bin;
 #pragma unroll
     for (int t = 0; t < NW; ++t) {
-        const uint64_t d = (uint64_t)a.w[t] - b.w[t] - br;
-        r.w[t] = (uint32_t)d;
-        br = (uint32_t)(d >> 63);
+        unsigned int bo;
+        r.w[t] = __builtin_subc(a.w[t], b.w[t], br, &bo);
+        br = bo;
     }
     return br;
 }
@@ -400,7 +401,7 @@ __device__ __forceinline__ void chain_seg_fast(const ChainJob &J, int64_t s, uin
     const int hw = (int)((2 * Nd + 31) >> 5);
     const uint32_t tb = Nd - 32u * (NW - 1);
     const uint32_t topmask = tb >= 32 ? 0xffffffffu : (1u << tb) - 1u;
-    const uint32_t mm1 = (uint32_t)(m - 1), last = (uint32_t)(k1 - 1);
+    const uint32_t mm1 = (uint32_t)(m - 1), last = (uint32_t)(k1 - 1), k1u = (uint32_t)k1;
     MW<NW> beta, aprev, wc;
     uint32_t dl = 0;
 #pragma unroll
@@ -418,17 +419,18 @@ __device__ __forceinline__ void chain_seg_fast(const ChainJob &J, int64_t s, uin
     MW<NW> alpha = aprev;
     uint32_t ru[P][NW + 1], rw[P][NW + 1], su[P], sw[P];
     // step c's words (clamped to the segment's last step: a refill past it reads words that stay
-    // unused); B's digit of step c is w_{c+1}, at m - c - 1
-    auto fetch = [&](int j, int64_t c) {
-        const uint32_t cc = c < k1 ? (uint32_t)c : last;
+    // unused); B's digit of step c is w_{c+1}, at m - c - 1.  Steps, bit offsets and byte
+    // offsets fit in 32 bits ((m + 1) Nd < 2^31): the loads take a scalar base and a vector offset
+    auto fetch = [&](int j, uint32_t c) {
+        const uint32_t cc = c < k1u ? c : last;
         const uint32_t ou = cc * Nd, ow = (mm1 - cc) * Nd;
-        ldg_words<NW + 1>(J.A + (ou >> 5), ru[j]);
-        ldg_words<NW + 1>(J.B + (ow >> 5), rw[j]);
+        ldg_words<NW + 1>(byte_at(J.A, (ou >> 5) << 2), ru[j]);
+        ldg_words<NW + 1>(byte_at(J.B, (ow >> 5) << 2), rw[j]);
         su[j] = ou & 31u;
         sw[j] = ow & 31u;
     };
     uint32_t ab[P][2 * NW];
-    auto step = [&](int j, int64_t c) {
+    auto step = [&](int j, uint32_t c) {
         const MW<NW> u = funnel_digit<NW>(ru[j], su[j], topmask);
         const MW<NW> wn = funnel_digit<NW>(rw[j], sw[j], topmask);
         fetch(j, c + P);
@@ -448,18 +450,18 @@ __device__ __forceinline__ void chain_seg_fast(const ChainJob &J, int64_t s, uin
         }
     };
 #pragma unroll
-    for (int j = 0; j < P; ++j) fetch(j, k0 + j);
-    int64_t cb = k0;
-    for (; cb + P <= k1; cb += P) {
+    for (int j = 0; j < P; ++j) fetch(j, (uint32_t)k0 + j);
+    uint32_t cb = (uint32_t)k0;
+    for (; cb + P <= k1u; cb += P) {
 #pragma unroll
         for (int j = 0; j < P; ++j) step(j, cb + j);
-        stg_words<2 * NW * P>(J.hbuf + cb * (2 * NW), &ab[0][0]);  // after the round's refills
+        stg_words<2 * NW * P>(J.hbuf + (int64_t)cb * (2 * NW), &ab[0][0]);  // after the round's refills
     }
 #pragma unroll
     for (int j = 0; j < P; ++j)
-        if (cb + j < k1) {
+        if (cb + j < k1u) {
             step(j, cb + j);
-            stg_words<2 * NW>(J.hbuf + (cb + j) * (2 * NW), ab[j]);
+            stg_words<2 * NW>(J.hbuf + (int64_t)(cb + j) * (2 * NW), ab[j]);
         }
     // self-checks, as in chain_seg
     bool ok = true;
