@@ -56,9 +56,9 @@ NTT_STEPS = {"ntt_fwd_cols": (2, 0), "ntt_rows": (3, 1), "ntt_inv_cols": (1, 0)}
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated: FETCH x2, WRITE
 # x1) on the headline workload (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).
-MEASURED_TRAFFIC_C4 = {"pack": 487093777, "ntt_fwd_cols": 1218204347, "ntt_rows": 1617494059,
-                       "ntt_inv_cols": 1077588957, "ntt_join": 975757733, "normalize": 651052551,
-                       "recon": 349208749, "finish": 271340361}
+MEASURED_TRAFFIC_C4 = {"pack": 486531905, "ntt_fwd_cols": 1218446874, "ntt_rows": 1617373987,
+                       "ntt_inv_cols": 1078637707, "ntt_join": 975755648, "normalize": 650886852,
+                       "recon": 348692778, "finish": 271339905}
 KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "ntt_fwd_cols", "ntt_rows",
            "ntt_inv_cols", "ntt_join", "normalize", "anchor", "recon", "finish", "extract", "p2_eval", "p2_recon")
 METRIC = "polynomial products/s + limb-mults/s at 1 GPU; KS4 vs KS1 speedup, bit-exact"
