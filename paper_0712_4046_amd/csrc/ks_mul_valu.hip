@@ -107,24 +107,34 @@ __global__ __launch_bounds__(MUL_TPB) void mul_valu_kernel(Launch<MulJob> L) {
         sync();
         if (it + 1 < niter) fetch(it + 1);
         if (active) {
-            // E[idx] = sb[base - x0 + idx]; column r at step x0 + u uses E[R - 1 + r - u]
+            // E[idx] = sb[base - x0 + idx]; column r at step x0 + u uses E[R - 1 + r - u].  The
+            // chunk's steps at or beyond ihi read a_i = 0 (staged as zeros): the loop stops at the
+            // last step that meets a (the tail chunk of a short i range is often a few steps)
+            constexpr int XG = 4 * MUL_R;  // steps per unrolled group (MUL_CI is a multiple)
+            static_assert(MUL_CI % XG == 0, "whole groups of steps per chunk");
+            const int xlen = (int)(ihi - c0 < (int64_t)MUL_CI ? ihi - c0 : (int64_t)MUL_CI);
+            const int xend = (xlen + XG - 1) / XG * XG;
             uint32_t ehi[MUL_R];
             lds_words(&sb[wv][base + MUL_R], ehi);
-            for (int x0 = 0; x0 < MUL_CI; x0 += MUL_R) {
-                uint32_t elo[MUL_R], A[MUL_R], E[2 * MUL_R];
-                lds_words(&sb[wv][base - x0], elo);
-                lds_words(&sa[wv][x0], A);
+            for (int xg = 0; xg < xend; xg += XG) {
 #pragma unroll
-                for (int t = 0; t < MUL_R; ++t) {
-                    E[t] = elo[t];
-                    E[MUL_R + t] = ehi[t];
+                for (int xu = 0; xu < XG; xu += MUL_R) {
+                    const int x0 = xg + xu;
+                    uint32_t elo[MUL_R], A[MUL_R], E[2 * MUL_R];
+                    lds_words(&sb[wv][base - x0], elo);
+                    lds_words(&sa[wv][x0], A);
+#pragma unroll
+                    for (int t = 0; t < MUL_R; ++t) {
+                        E[t] = elo[t];
+                        E[MUL_R + t] = ehi[t];
+                    }
+#pragma unroll
+                    for (int u = 0; u < MUL_R; ++u)
+#pragma unroll
+                        for (int r = 0; r < MUL_R; ++r) mac96(lo[r], hi[r], A[u], E[MUL_R - 1 + r - u]);
+#pragma unroll
+                    for (int t = 0; t < MUL_R; ++t) ehi[t] = elo[t];
                 }
-#pragma unroll
-                for (int u = 0; u < MUL_R; ++u)
-#pragma unroll
-                    for (int r = 0; r < MUL_R; ++r) mac96(lo[r], hi[r], A[u], E[MUL_R - 1 + r - u]);
-#pragma unroll
-                for (int t = 0; t < MUL_R; ++t) ehi[t] = elo[t];
             }
         }
         sync();
