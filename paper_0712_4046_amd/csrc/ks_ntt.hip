@@ -98,9 +98,12 @@ constexpr int pad_len(int n) { return n + n / 32; }
 
 // one radix-4 pass (stages of half-sizes 2 Hb and Hb, Hb = 2^BL >= 16) in the padded layout:
 // the group's elements j + m Hb sit at fixed offsets from element j (its block of 4 Hb
-// elements starts at a multiple of 64, so the spare words between them are known)
-template <int LG, int BL, bool INV, int NE, int GAP>
+// elements starts at a multiple of 64, so the spare words between them are known).  HALF
+// (forward, first pass of a sequence whose upper half is zero): u2 = u3 = 0 are not read, and
+// the first stage's butterflies reduce to u2 = u0 w, u3 = u1 w (u0 and u1 stay below 2P)
+template <int LG, int BL, bool INV, int NE, int GAP, bool HALF = false>
 __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, NttPrime P) {
+    static_assert(!(HALF && INV), "the zero upper half is a forward-transform input");
     constexpr int hb = 1 << BL, NQ = NE / 4 / NTT_TPB, SS = pad_len(1 << LG) + GAP;
     static_assert(BL >= 4 && BL + 2 <= LG, "radix-4 pass of half-sizes 16 and up");
     constexpr int o1 = hb >= 32 ? hb + hb / 32 : 16, o2 = hb >= 32 ? 2 * o1 : 33, o3 = hb >= 32 ? 3 * o1 : 49;
@@ -110,9 +113,14 @@ __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, N
         const int seq = g >> (LG - 2), r = g & ((1 << (LG - 2)) - 1);
         const int j = r & (hb - 1);
         uint32_t *x = buf + seq * SS + pad_ix(((r >> BL) << (BL + 2)) + j);
-        uint32_t u0 = x[0], u1 = x[o1], u2 = x[o2], u3 = x[o3];
+        uint32_t u0 = x[0], u1 = x[o1], u2 = HALF ? 0u : x[o2], u3 = HALF ? 0u : x[o3];
         const uint32_t wa0 = tws[2 * hb + j], wa1 = tws[3 * hb + j], wb = tws[hb + j];
-        if (!INV) {
+        if (HALF) {
+            u2 = mmul_lazy(u0, wa0, P);
+            u3 = mmul_lazy(u1, wa1, P);
+            bfly_dif(u0, u1, wb, P);
+            bfly_dif(u2, u3, wb, P);
+        } else if (!INV) {
             bfly_dif(u0, u2, wa0, P);
             bfly_dif(u1, u3, wa1, P);
             bfly_dif(u0, u1, wb, P);
@@ -140,7 +148,9 @@ __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, N
 // trip) down to half-size 16, and the four stages of half-sizes 8, 4, 2, 1 in registers, each
 // thread on runs of 16 consecutive elements (their twiddles, w_16^j and its powers, are the same
 // for every run).  Forward in that order, the inverse in reverse.  Ends with a barrier.
-template <int LG, bool INV, int NE, int GAP>
+// HALF (forward only): the upper half of every sequence is zero and is not read, only
+// written, by the first stage (the caller need not store those zeros).
+template <int LG, bool INV, int NE, int GAP, bool HALF = false>
 __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t *tws, NttPrime P) {
     constexpr int SS = pad_len(1 << LG) + GAP;
     constexpr bool ODD = ((LG - 4) & 1) != 0;
@@ -153,6 +163,10 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
             const int b = threadIdx.x + i * NTT_TPB;
             const int j = b & (h - 1);
             uint32_t *x = buf + (b >> (LG - 1)) * SS + pad_ix(j);
+            if constexpr (HALF && !INV) {  // v = 0: u stays, v = u w
+                x[oh] = mmul_lazy(x[0], tws[h + j], P);
+                continue;
+            }
             uint32_t u = x[0], v = x[oh];
             if (!INV)
                 bfly_dif(u, v, tws[h + j], P);
@@ -212,11 +226,12 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
         __syncthreads();
     };
     if (!INV) {
+        constexpr bool H1 = HALF && !ODD;  // the zero half goes into the first radix-4 pass
         if constexpr (ODD) radix2();
-        if constexpr (TOP >= 10) pad_radix4<LG, 10, false, NE, GAP>(buf, tws, P);
-        if constexpr (TOP >= 8) pad_radix4<LG, 8, false, NE, GAP>(buf, tws, P);
-        if constexpr (TOP >= 6) pad_radix4<LG, 6, false, NE, GAP>(buf, tws, P);
-        pad_radix4<LG, 4, false, NE, GAP>(buf, tws, P);
+        if constexpr (TOP >= 10) pad_radix4<LG, 10, false, NE, GAP, H1 && TOP == 10>(buf, tws, P);
+        if constexpr (TOP >= 8) pad_radix4<LG, 8, false, NE, GAP, H1 && TOP == 8>(buf, tws, P);
+        if constexpr (TOP >= 6) pad_radix4<LG, 6, false, NE, GAP, H1 && TOP == 6>(buf, tws, P);
+        pad_radix4<LG, 4, false, NE, GAP, H1 && TOP == 4>(buf, tws, P);
         tail();
     } else {
         tail();
@@ -228,17 +243,17 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
     }
 }
 
-template <bool INV, int NE, int GAP>
+template <bool INV, int NE, int GAP, bool HALF = false>
 __device__ __forceinline__ void lds_transform_pad_any(int lg, uint32_t *buf, const uint32_t *tws, NttPrime P) {
     switch (lg) {
-        case 6: lds_transform_pad<6, INV, NE, GAP>(buf, tws, P); break;
-        case 7: lds_transform_pad<7, INV, NE, GAP>(buf, tws, P); break;
-        case 8: lds_transform_pad<8, INV, NE, GAP>(buf, tws, P); break;
-        case 9: lds_transform_pad<9, INV, NE, GAP>(buf, tws, P); break;
-        case 10: lds_transform_pad<10, INV, NE, GAP>(buf, tws, P); break;
-        case 11: lds_transform_pad<11, INV, NE, GAP>(buf, tws, P); break;
+        case 6: lds_transform_pad<6, INV, NE, GAP, HALF>(buf, tws, P); break;
+        case 7: lds_transform_pad<7, INV, NE, GAP, HALF>(buf, tws, P); break;
+        case 8: lds_transform_pad<8, INV, NE, GAP, HALF>(buf, tws, P); break;
+        case 9: lds_transform_pad<9, INV, NE, GAP, HALF>(buf, tws, P); break;
+        case 10: lds_transform_pad<10, INV, NE, GAP, HALF>(buf, tws, P); break;
+        case 11: lds_transform_pad<11, INV, NE, GAP, HALF>(buf, tws, P); break;
         default:  // rows only (columns have at most 2^11)
-            if constexpr (GAP == 0) lds_transform_pad<12, INV, NE, GAP>(buf, tws, P);
+            if constexpr (GAP == 0) lds_transform_pad<12, INV, NE, GAP, HALF>(buf, tws, P);
             break;
     }
 }
@@ -298,12 +313,19 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
     const uint32_t mt0 = __builtin_amdgcn_readfirstlane(mt);
     const int lms = 8 - lc + k2;  // mstep = 2^lms
     const int iz = mt0 >= np ? 0 : (int)min((uint32_t)EPT, (np - mt0 + mstep - 1u) >> lms);
+    // When np <= N / 2 every column's upper half (rows n1 >= N1 / 2, this thread's elements
+    // i >= EPT / 2, all at or beyond iz) is zero padding: the transform's first stage then
+    // writes it without reading it, so it is not stored here.
+    const bool half = (uint64_t)np * 2u <= ((uint64_t)1 << k);
+    static_assert((EPT / 2) % CH == 0, "the upper half is whole chunks");
     auto load = [&](auto wide) {  // wide: 8-byte loads (an operand of two limbs or more)
 #pragma unroll 1
         for (int i0 = 0; i0 < EPT; i0 += CH) {
             if (i0 >= iz) {  // wave-uniform
+                if (!half || i0 < EPT / 2) {
 #pragma unroll
-                for (int i = 0; i < CH; ++i) bt[pad_ix(n1t + (i0 + i) * n1s)] = 0u;
+                    for (int i = 0; i < CH; ++i) bt[pad_ix(n1t + (i0 + i) * n1s)] = 0u;
+                }
                 continue;
             }
             u32x2 v[CH];
@@ -333,7 +355,10 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
 #pragma unroll
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twf[m];
     __syncthreads();
-    lds_transform_pad_any<false, NTT_BLOCK, 1>(k1, buf, tws, P);
+    if (half)
+        lds_transform_pad_any<false, NTT_BLOCK, 1, true>(k1, buf, tws, P);
+    else
+        lds_transform_pad_any<false, NTT_BLOCK, 1>(k1, buf, tws, P);
     // twiddle w_N^(n2 k1) and store: each thread takes runs of `cols` adjacent columns of one row
     // (32 elements in all), so the twiddles of a run follow by one multiplication each from its
     // first (w^((c0 + c) kk) = w^((c0 + c_first) kk) (w^kk)^(c - c_first)) and the run is
