@@ -409,8 +409,8 @@ __global__ __launch_bounds__(NTT_TPB) void ntt_fwd_cols_kernel(Launch<NttJob> L)
         fwd_cols_body<1, TWS>(J, local, buf, tws);
 }
 
-// The row step of a product: both operands' rows forward, the pointwise product, the inverse
-// row transform, the inverse twiddle and the scale, in one pass over HBM.  A block takes
+// The row step of a product: both operands' rows forward, the pointwise product and the
+// inverse row transform, in one pass over HBM.  A block takes
 // NTT_ROWS_BLOCK residues (R = NTT_ROWS_BLOCK / N2 whole rows) of each operand for one prime.
 constexpr int NTT_ROWS_BLOCK = NTT_BLOCK / 2;
 constexpr int EPT_R = NTT_ROWS_BLOCK / NTT_TPB;
@@ -425,7 +425,6 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
     const int gl = k - 12;  // log2 of the blocks of one prime: N / NTT_ROWS_BLOCK
     constexpr int q = Q;
     const int64_t base = (local & (((int64_t)1 << gl) - 1)) * NTT_ROWS_BLOCK;  // whole rows, contiguous
-    const uint32_t r0 = (uint32_t)(base >> k2);  // first row of the block (below 2^11)
     constexpr NttPrime P = ntt_prime_c(Q);
     uint32_t *x = J.x + ((int64_t)q << k) + base;
     const uint32_t *y = J.y + ((int64_t)q << k) + base;
@@ -470,27 +469,10 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twi[m];
     __syncthreads();
     lds_transform_pad_any<true, NTT_ROWS_BLOCK, 0>(k2, bufa, tws, P);
-    // inverse twiddle w_N^-(n2 k1) (the scale 1 / N came in with the second operand's forward
-    // twiddles).  The exponent n2 bitrev(r) < 2^k <= 2^23 fits in 32 bits.
-    const uint32_t emask = (1u << NTT_ROOT_LOG) - 1u;
-    const int sh = NTT_ROOT_LOG - k;
-#pragma unroll 1
-    for (int i0 = 0; i0 < EPT_R; i0 += CH) {
-        uint32_t a[CH], b[CH];
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const uint32_t e = (uint32_t)(t + (i0 + i) * NTT_TPB);
-            const uint32_t r = r0 + (e >> k2), n2 = e & ((1u << k2) - 1u);
-            const uint32_t ei = (0u - ((n2 * bitrev(r, k1)) << sh)) & emask;
-            a[i] = ntt_tab[q][0][ei >> NTT_TAB_LOG];
-            b[i] = ntt_tab[q][1][ei & (NTT_TAB - 1)];
-        }
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int e = t + (i0 + i) * NTT_TPB;
-            stg(x + e, mmul_lazy(bufa[tp + (i0 + i) * PSTEP], mmul(a[i], b[i], P), P));  // below 2P
-        }
-    }
+    // out as they are (below 4P): the inverse columns apply the inverse twiddles as they read
+    // them back (the scale 1 / N came in with the second operand's forward twiddles)
+#pragma unroll 8
+    for (int i = 0; i < EPT_R; ++i) stg(x + t + i * NTT_TPB, bufa[tp + i * PSTEP]);
 }
 
 // TWS: words of stage twiddles, 2^k2 (rows of up to 2^10 take 38 KB of LDS and four blocks fit
@@ -527,13 +509,28 @@ __device__ __forceinline__ void inv_cols_body(const NttJob &J, int64_t local, ui
     // element e = t + 256 i: column c = t mod C, row n1 = t / C + i 256 / C
     const int ct = t & (C - 1), n1t = t >> lc, n1s = NTT_TPB >> lc;
     uint32_t *bt = buf + ct * SC;
+    // The inverse twiddle of row n1, column n2 is w_N^-(n2 bitrev_k1(n1)).  With n1s = 2^(k1 - 5)
+    // and i < 32, bitrev_k1(n1t + i n1s) = 32 bitrev_(k1-5)(n1t) + bitrev_5(i), so a thread's
+    // twiddles are A g^j (A = w_N^-(32 n2 bitrev(n1t)), g = w_N^-n2, j = bitrev_5(i)): the even j
+    // (i < 16) first, then the odd ones, each run of 16 by a recurrence in g^2.  Inputs below 4P,
+    // twiddles fully reduced: the products stay below 2P.
+    static_assert(EPT == 32 && CH == 16, "two runs of 16 twiddles per thread");
+    const int sh = NTT_ROOT_LOG - k;
+    const uint32_t emask = (1u << NTT_ROOT_LOG) - 1u, n2 = (uint32_t)(c0 + ct);
+    const uint32_t g = root_pow(q, (0u - (n2 << sh)) & emask, P);
+    const uint32_t g2 = mmul(g, g, P);
+    uint32_t a0 = root_pow(q, (0u - (((n2 * bitrev((uint32_t)n1t, k1 - 5)) << 5) << sh)) & emask, P);
 #pragma unroll 1
     for (int i0 = 0; i0 < EPT; i0 += CH) {
-        uint32_t v[CH];
+        uint32_t v[CH], tw[CH];
 #pragma unroll
         for (int i = 0; i < CH; ++i) v[i] = ldg(x + ((int64_t)(n1t + (i0 + i) * n1s) << k2) + c0 + ct);
+        tw[0] = a0;  // A g^(i0 / 16)
 #pragma unroll
-        for (int i = 0; i < CH; ++i) bt[pad_ix(n1t + (i0 + i) * n1s)] = v[i];
+        for (int m = 1; m < CH; ++m) tw[m] = mmul(tw[m - 1], g2, P);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) bt[pad_ix(n1t + (i0 + i) * n1s)] = mmul_lazy(v[i], tw[bitrev((uint32_t)i, 4)], P);
+        a0 = mmul(a0, g, P);
     }
 #pragma unroll
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twi[m];
