@@ -100,9 +100,11 @@ constexpr int pad_len(int n) { return n + n / 32; }
 // the group's elements j + m Hb sit at fixed offsets from element j (its block of 4 Hb
 // elements starts at a multiple of 64, so the spare words between them are known).  HALF
 // (forward, first pass of a sequence whose upper half is zero): u2 = u3 = 0 are not read, and
-// the first stage's butterflies reduce to u2 = u0 w, u3 = u1 w (u0 and u1 stay below 2P)
-template <int LG, int BL, bool INV, int NE, int GAP, bool HALF = false>
-__device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, NttPrime P) {
+// the first stage's butterflies reduce to u2 = u0 w, u3 = u1 w (u0 and u1 stay below 2P).
+// NB = 2: the same pass over a second buffer of the same shape, in the same loop (shared
+// twiddle reads, twice the independent work between barriers)
+template <int LG, int BL, bool INV, int NE, int GAP, bool HALF = false, int NB = 1>
+__device__ __forceinline__ void pad_radix4(uint32_t *buf, uint32_t *buf2, const uint32_t *tws, NttPrime P) {
     static_assert(!(HALF && INV), "the zero upper half is a forward-transform input");
     constexpr int hb = 1 << BL, NQ = NE / 4 / NTT_TPB, SS = pad_len(1 << LG) + GAP;
     static_assert(BL >= 4 && BL + 2 <= LG, "radix-4 pass of half-sizes 16 and up");
@@ -112,9 +114,10 @@ __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, N
         const int g = threadIdx.x + i * NTT_TPB;
         const int seq = g >> (LG - 2), r = g & ((1 << (LG - 2)) - 1);
         const int j = r & (hb - 1);
-        uint32_t *x = buf + seq * SS + pad_ix(((r >> BL) << (BL + 2)) + j);
-        uint32_t u0 = x[0], u1 = x[o1], u2 = HALF ? 0u : x[o2], u3 = HALF ? 0u : x[o3];
+        const int off = seq * SS + pad_ix(((r >> BL) << (BL + 2)) + j);
         const uint32_t wa0 = tws[2 * hb + j], wa1 = tws[3 * hb + j], wb = tws[hb + j];
+        auto one = [&](uint32_t *x) {
+        uint32_t u0 = x[0], u1 = x[o1], u2 = HALF ? 0u : x[o2], u3 = HALF ? 0u : x[o3];
         if (HALF) {
             u2 = mmul_lazy(u0, wa0, P);
             u3 = mmul_lazy(u1, wa1, P);
@@ -135,6 +138,9 @@ __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, N
         x[o1] = u1;
         x[o2] = u2;
         x[o3] = u3;
+        };
+        one(buf + off);
+        if constexpr (NB == 2) one(buf2 + off);
     }
     __syncthreads();
 }
@@ -149,9 +155,11 @@ __device__ __forceinline__ void pad_radix4(uint32_t *buf, const uint32_t *tws, N
 // thread on runs of 16 consecutive elements (their twiddles, w_16^j and its powers, are the same
 // for every run).  Forward in that order, the inverse in reverse.  Ends with a barrier.
 // HALF (forward only): the upper half of every sequence is zero and is not read, only
-// written, by the first stage (the caller need not store those zeros).
-template <int LG, bool INV, int NE, int GAP, bool HALF = false>
-__device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t *tws, NttPrime P) {
+// written, by the first stage (the caller need not store those zeros).  NB = 2: two buffers of
+// the same shape (buf and buf2) transformed together, pass by pass.
+template <int LG, bool INV, int NE, int GAP, bool HALF = false, int NB = 1>
+__device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t *tws, NttPrime P,
+                                                  uint32_t *buf2 = nullptr) {
     constexpr int SS = pad_len(1 << LG) + GAP;
     constexpr bool ODD = ((LG - 4) & 1) != 0;
     constexpr int TOP = LG - 2 - (ODD ? 1 : 0);  // the first (forward) radix-4 pass's BL, even
@@ -162,18 +170,23 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
         for (int i = 0; i < NH; ++i) {
             const int b = threadIdx.x + i * NTT_TPB;
             const int j = b & (h - 1);
-            uint32_t *x = buf + (b >> (LG - 1)) * SS + pad_ix(j);
-            if constexpr (HALF && !INV) {  // v = 0: u stays, v = u w
-                x[oh] = mmul_lazy(x[0], tws[h + j], P);
-                continue;
-            }
-            uint32_t u = x[0], v = x[oh];
-            if (!INV)
-                bfly_dif(u, v, tws[h + j], P);
-            else
-                bfly_dit(u, v, tws[h + j], P);
-            x[0] = u;
-            x[oh] = v;
+            const int off = (b >> (LG - 1)) * SS + pad_ix(j);
+            const uint32_t w = tws[h + j];
+            auto one = [&](uint32_t *x) {
+                if constexpr (HALF && !INV) {  // v = 0: u stays, v = u w
+                    x[oh] = mmul_lazy(x[0], w, P);
+                    return;
+                }
+                uint32_t u = x[0], v = x[oh];
+                if (!INV)
+                    bfly_dif(u, v, w, P);
+                else
+                    bfly_dit(u, v, w, P);
+                x[0] = u;
+                x[oh] = v;
+            };
+            one(buf + off);
+            if constexpr (NB == 2) one(buf2 + off);
         }
         __syncthreads();
     };
@@ -189,7 +202,8 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
 #pragma unroll
         for (int i = 0; i < NE / 16 / NTT_TPB; ++i) {
             const int run = threadIdx.x + i * NTT_TPB;  // a run never crosses a spare word
-            uint32_t *x = buf + (run >> (LG - 4)) * SS + pad_ix((run & ((1 << (LG - 4)) - 1)) << 4);
+            const int off = (run >> (LG - 4)) * SS + pad_ix((run & ((1 << (LG - 4)) - 1)) << 4);
+            auto one = [&](uint32_t *x) {
             uint32_t v[16];
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = x[e];
@@ -222,38 +236,42 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
             }
 #pragma unroll
             for (int e = 0; e < 16; ++e) x[e] = v[e];
+            };
+            one(buf + off);
+            if constexpr (NB == 2) one(buf2 + off);
         }
         __syncthreads();
     };
     if (!INV) {
         constexpr bool H1 = HALF && !ODD;  // the zero half goes into the first radix-4 pass
         if constexpr (ODD) radix2();
-        if constexpr (TOP >= 10) pad_radix4<LG, 10, false, NE, GAP, H1 && TOP == 10>(buf, tws, P);
-        if constexpr (TOP >= 8) pad_radix4<LG, 8, false, NE, GAP, H1 && TOP == 8>(buf, tws, P);
-        if constexpr (TOP >= 6) pad_radix4<LG, 6, false, NE, GAP, H1 && TOP == 6>(buf, tws, P);
-        pad_radix4<LG, 4, false, NE, GAP, H1 && TOP == 4>(buf, tws, P);
+        if constexpr (TOP >= 10) pad_radix4<LG, 10, false, NE, GAP, H1 && TOP == 10, NB>(buf, buf2, tws, P);
+        if constexpr (TOP >= 8) pad_radix4<LG, 8, false, NE, GAP, H1 && TOP == 8, NB>(buf, buf2, tws, P);
+        if constexpr (TOP >= 6) pad_radix4<LG, 6, false, NE, GAP, H1 && TOP == 6, NB>(buf, buf2, tws, P);
+        pad_radix4<LG, 4, false, NE, GAP, H1 && TOP == 4, NB>(buf, buf2, tws, P);
         tail();
     } else {
         tail();
-        pad_radix4<LG, 4, true, NE, GAP>(buf, tws, P);
-        if constexpr (TOP >= 6) pad_radix4<LG, 6, true, NE, GAP>(buf, tws, P);
-        if constexpr (TOP >= 8) pad_radix4<LG, 8, true, NE, GAP>(buf, tws, P);
-        if constexpr (TOP >= 10) pad_radix4<LG, 10, true, NE, GAP>(buf, tws, P);
+        pad_radix4<LG, 4, true, NE, GAP, false, NB>(buf, buf2, tws, P);
+        if constexpr (TOP >= 6) pad_radix4<LG, 6, true, NE, GAP, false, NB>(buf, buf2, tws, P);
+        if constexpr (TOP >= 8) pad_radix4<LG, 8, true, NE, GAP, false, NB>(buf, buf2, tws, P);
+        if constexpr (TOP >= 10) pad_radix4<LG, 10, true, NE, GAP, false, NB>(buf, buf2, tws, P);
         if constexpr (ODD) radix2();
     }
 }
 
-template <bool INV, int NE, int GAP, bool HALF = false>
-__device__ __forceinline__ void lds_transform_pad_any(int lg, uint32_t *buf, const uint32_t *tws, NttPrime P) {
+template <bool INV, int NE, int GAP, bool HALF = false, int NB = 1>
+__device__ __forceinline__ void lds_transform_pad_any(int lg, uint32_t *buf, const uint32_t *tws, NttPrime P,
+                                                      uint32_t *buf2 = nullptr) {
     switch (lg) {
-        case 6: lds_transform_pad<6, INV, NE, GAP, HALF>(buf, tws, P); break;
-        case 7: lds_transform_pad<7, INV, NE, GAP, HALF>(buf, tws, P); break;
-        case 8: lds_transform_pad<8, INV, NE, GAP, HALF>(buf, tws, P); break;
-        case 9: lds_transform_pad<9, INV, NE, GAP, HALF>(buf, tws, P); break;
-        case 10: lds_transform_pad<10, INV, NE, GAP, HALF>(buf, tws, P); break;
-        case 11: lds_transform_pad<11, INV, NE, GAP, HALF>(buf, tws, P); break;
+        case 6: lds_transform_pad<6, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 7: lds_transform_pad<7, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 8: lds_transform_pad<8, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 9: lds_transform_pad<9, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 10: lds_transform_pad<10, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 11: lds_transform_pad<11, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
         default:  // rows only (columns have at most 2^11)
-            if constexpr (GAP == 0) lds_transform_pad<12, INV, NE, GAP, HALF>(buf, tws, P);
+            if constexpr (GAP == 0) lds_transform_pad<12, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2);
             break;
     }
 }
@@ -455,8 +473,7 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
 #pragma unroll
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twf[m];
     __syncthreads();
-    lds_transform_pad_any<false, NTT_ROWS_BLOCK, 0>(k2, bufa, tws, P);
-    lds_transform_pad_any<false, NTT_ROWS_BLOCK, 0>(k2, bufb, tws, P);
+    lds_transform_pad_any<false, NTT_ROWS_BLOCK, 0, false, 2>(k2, bufa, tws, P, bufb);  // both operands
     // pointwise A B R^-1 (equal positions: both in the order the forward steps left; A, B < 2P,
     // so A B < P 2^32 and the product is below 2P), then the inverse twiddles replace the
     // forward ones (every thread is past the forward transforms' barrier)
