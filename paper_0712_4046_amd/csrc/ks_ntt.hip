@@ -157,7 +157,7 @@ __device__ __forceinline__ void pad_radix4(uint32_t *buf, uint32_t *buf2, const 
 // HALF (forward only): the upper half of every sequence is zero and is not read, only
 // written, by the first stage (the caller need not store those zeros).  NB = 2: two buffers of
 // the same shape (buf and buf2) transformed together, pass by pass.
-template <int LG, bool INV, int NE, int GAP, bool HALF = false, int NB = 1>
+template <int LG, bool INV, int NE, int GAP, bool HALF = false, int NB = 1, bool OUTER = true>
 __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t *tws, NttPrime P,
                                                   uint32_t *buf2 = nullptr) {
     constexpr int SS = pad_len(1 << LG) + GAP;
@@ -242,36 +242,42 @@ __device__ __forceinline__ void lds_transform_pad(uint32_t *buf, const uint32_t 
         }
         __syncthreads();
     };
+    // !OUTER: the outermost pass (the forward's first, the inverse's last: the radix-2 stage,
+    // else the radix-4 pass of half-size 2^TOP) is left to the caller, who holds its elements
+    // in registers
+    static_assert(OUTER || !HALF, "the zero half enters the outermost pass");
+    constexpr bool R2 = ODD && OUTER;
+    constexpr int T4 = ODD || OUTER ? TOP : TOP - 2;  // the largest radix-4 pass run here
     if (!INV) {
         constexpr bool H1 = HALF && !ODD;  // the zero half goes into the first radix-4 pass
-        if constexpr (ODD) radix2();
-        if constexpr (TOP >= 10) pad_radix4<LG, 10, false, NE, GAP, H1 && TOP == 10, NB>(buf, buf2, tws, P);
-        if constexpr (TOP >= 8) pad_radix4<LG, 8, false, NE, GAP, H1 && TOP == 8, NB>(buf, buf2, tws, P);
-        if constexpr (TOP >= 6) pad_radix4<LG, 6, false, NE, GAP, H1 && TOP == 6, NB>(buf, buf2, tws, P);
-        pad_radix4<LG, 4, false, NE, GAP, H1 && TOP == 4, NB>(buf, buf2, tws, P);
+        if constexpr (R2) radix2();
+        if constexpr (T4 >= 10) pad_radix4<LG, 10, false, NE, GAP, H1 && T4 == 10, NB>(buf, buf2, tws, P);
+        if constexpr (T4 >= 8) pad_radix4<LG, 8, false, NE, GAP, H1 && T4 == 8, NB>(buf, buf2, tws, P);
+        if constexpr (T4 >= 6) pad_radix4<LG, 6, false, NE, GAP, H1 && T4 == 6, NB>(buf, buf2, tws, P);
+        if constexpr (T4 >= 4) pad_radix4<LG, 4, false, NE, GAP, H1 && T4 == 4, NB>(buf, buf2, tws, P);
         tail();
     } else {
         tail();
-        pad_radix4<LG, 4, true, NE, GAP, false, NB>(buf, buf2, tws, P);
-        if constexpr (TOP >= 6) pad_radix4<LG, 6, true, NE, GAP, false, NB>(buf, buf2, tws, P);
-        if constexpr (TOP >= 8) pad_radix4<LG, 8, true, NE, GAP, false, NB>(buf, buf2, tws, P);
-        if constexpr (TOP >= 10) pad_radix4<LG, 10, true, NE, GAP, false, NB>(buf, buf2, tws, P);
-        if constexpr (ODD) radix2();
+        if constexpr (T4 >= 4) pad_radix4<LG, 4, true, NE, GAP, false, NB>(buf, buf2, tws, P);
+        if constexpr (T4 >= 6) pad_radix4<LG, 6, true, NE, GAP, false, NB>(buf, buf2, tws, P);
+        if constexpr (T4 >= 8) pad_radix4<LG, 8, true, NE, GAP, false, NB>(buf, buf2, tws, P);
+        if constexpr (T4 >= 10) pad_radix4<LG, 10, true, NE, GAP, false, NB>(buf, buf2, tws, P);
+        if constexpr (R2) radix2();
     }
 }
 
-template <bool INV, int NE, int GAP, bool HALF = false, int NB = 1>
+template <bool INV, int NE, int GAP, bool HALF = false, int NB = 1, bool OUTER = true>
 __device__ __forceinline__ void lds_transform_pad_any(int lg, uint32_t *buf, const uint32_t *tws, NttPrime P,
                                                       uint32_t *buf2 = nullptr) {
     switch (lg) {
-        case 6: lds_transform_pad<6, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
-        case 7: lds_transform_pad<7, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
-        case 8: lds_transform_pad<8, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
-        case 9: lds_transform_pad<9, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
-        case 10: lds_transform_pad<10, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
-        case 11: lds_transform_pad<11, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 6: if constexpr (OUTER) lds_transform_pad<6, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 7: if constexpr (OUTER) lds_transform_pad<7, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 8: if constexpr (OUTER) lds_transform_pad<8, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2); break;
+        case 9: lds_transform_pad<9, INV, NE, GAP, HALF, NB, OUTER>(buf, tws, P, buf2); break;
+        case 10: lds_transform_pad<10, INV, NE, GAP, HALF, NB, OUTER>(buf, tws, P, buf2); break;
+        case 11: lds_transform_pad<11, INV, NE, GAP, HALF, NB, OUTER>(buf, tws, P, buf2); break;
         default:  // rows only (columns have at most 2^11)
-            if constexpr (GAP == 0) lds_transform_pad<12, INV, NE, GAP, HALF, NB>(buf, tws, P, buf2);
+            if constexpr (GAP == 0) lds_transform_pad<12, INV, NE, GAP, HALF, NB, OUTER>(buf, tws, P, buf2);
             break;
     }
 }
@@ -436,6 +442,57 @@ constexpr int EPT_R = NTT_ROWS_BLOCK / NTT_TPB;
 // the padded position of element t + NTT_TPB m is tp + PSTEP m (NTT_TPB is a multiple of 32)
 constexpr int PSTEP = NTT_TPB + NTT_TPB / 32;
 
+// The outermost pass of rows of 2^K2 residues (K2 >= 9) on a thread's own elements: element i
+// of the thread sits at t + 256 i of the row block, so its elements of one row are j + 256 a
+// (a < GS = 2^(K2-8), j = t), and the pass's groups (half-sizes of 256 and more) lie inside
+// them; tw[m] = tws[t + 256 m] of the pass's direction.  The same butterflies as the radix-2
+// stage or the radix-4 pass of lds_transform_pad.
+template <int K2, bool INV, int TPT>
+__device__ __forceinline__ void row_outer_pass(uint32_t (&u)[EPT_R], const uint32_t (&tw)[TPT], NttPrime P) {
+    constexpr int GS = 1 << (K2 - 8);
+    static_assert(K2 >= 9 && GS <= TPT && EPT_R % GS == 0, "outer pass in registers");
+#pragma unroll
+    for (int g0 = 0; g0 < EPT_R; g0 += GS) {
+        if constexpr ((K2 & 1) != 0) {  // radix-2 stage of half-size 2^(K2-1)
+#pragma unroll
+            for (int a = 0; a < GS / 2; ++a) {
+                if (!INV)
+                    bfly_dif(u[g0 + a], u[g0 + a + GS / 2], tw[GS / 2 + a], P);
+                else
+                    bfly_dit(u[g0 + a], u[g0 + a + GS / 2], tw[GS / 2 + a], P);
+            }
+        } else {  // radix-4 pass of half-sizes 2^(K2-1) and 2^(K2-2)
+#pragma unroll
+            for (int a = 0; a < GS / 4; ++a) {
+                uint32_t &u0 = u[g0 + a], &u1 = u[g0 + a + GS / 4], &u2 = u[g0 + a + GS / 2], &u3 = u[g0 + a + 3 * GS / 4];
+                const uint32_t wa0 = tw[GS / 2 + a], wa1 = tw[3 * GS / 4 + a], wb = tw[GS / 4 + a];
+                if (!INV) {
+                    bfly_dif(u0, u2, wa0, P);
+                    bfly_dif(u1, u3, wa1, P);
+                    bfly_dif(u0, u1, wb, P);
+                    bfly_dif(u2, u3, wb, P);
+                } else {
+                    bfly_dit(u0, u1, wb, P);
+                    bfly_dit(u2, u3, wb, P);
+                    bfly_dit(u0, u2, wa0, P);
+                    bfly_dit(u1, u3, wa1, P);
+                }
+            }
+        }
+    }
+}
+
+template <bool INV, int TPT>
+__device__ __forceinline__ void row_outer(int k2, uint32_t (&u)[EPT_R], const uint32_t (&tw)[TPT], NttPrime P) {
+    switch (k2) {
+        case 9: row_outer_pass<9, INV>(u, tw, P); break;
+        case 10: row_outer_pass<10, INV>(u, tw, P); break;
+        case 11: if constexpr (TPT >= 8) row_outer_pass<11, INV>(u, tw, P); break;
+        case 12: if constexpr (TPT >= 16) row_outer_pass<12, INV>(u, tw, P); break;
+        default: break;
+    }
+}
+
 template <int Q, int TWS>
 __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32_t *bufa, uint32_t *bufb,
                                           uint32_t *tws) {
@@ -456,24 +513,35 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
         twf[m] = ldg(&ntt_stage_tab[q][0][t + m * NTT_TPB]);
         twi[m] = ldg(&ntt_stage_tab[q][1][t + m * NTT_TPB]);
     }
-#pragma unroll 1
-    for (int i0 = 0; i0 < EPT_R; i0 += CH) {
-        uint32_t u[CH], v[CH];
+    // Rows of 2^9 and more: the outermost pass of each direction runs in registers, on the
+    // residues as they come from HBM (forward) and as they go back (inverse), which saves an
+    // LDS round trip and a barrier each way
+    const bool regs = k2 >= 9 && (k2 <= 10 || TPT >= 16);
+    static_assert(EPT_R == CH, "a thread's residues of one operand in one round of loads");
+    {
+        uint32_t u[EPT_R], v[EPT_R];
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            u[i] = ldg(x + t + (i0 + i) * NTT_TPB);
-            v[i] = ldg(y + t + (i0 + i) * NTT_TPB);
+        for (int i = 0; i < EPT_R; ++i) {
+            u[i] = ldg(x + t + i * NTT_TPB);
+            v[i] = ldg(y + t + i * NTT_TPB);
+        }
+        if (regs) {
+            row_outer<false>(k2, u, twf, P);
+            row_outer<false>(k2, v, twf, P);
         }
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            bufa[tp + (i0 + i) * PSTEP] = u[i];
-            bufb[tp + (i0 + i) * PSTEP] = v[i];
+        for (int i = 0; i < EPT_R; ++i) {
+            bufa[tp + i * PSTEP] = u[i];
+            bufb[tp + i * PSTEP] = v[i];
         }
     }
 #pragma unroll
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twf[m];
     __syncthreads();
-    lds_transform_pad_any<false, NTT_ROWS_BLOCK, 0, false, 2>(k2, bufa, tws, P, bufb);  // both operands
+    if (regs)  // both operands
+        lds_transform_pad_any<false, NTT_ROWS_BLOCK, 0, false, 2, false>(k2, bufa, tws, P, bufb);
+    else
+        lds_transform_pad_any<false, NTT_ROWS_BLOCK, 0, false, 2>(k2, bufa, tws, P, bufb);
     // pointwise A B R^-1 (equal positions: both in the order the forward steps left; A, B < 2P,
     // so A B < P 2^32 and the product is below 2P), then the inverse twiddles replace the
     // forward ones (every thread is past the forward transforms' barrier)
@@ -485,11 +553,21 @@ __device__ __forceinline__ void rows_body(const NttJob &J, int64_t local, uint32
 #pragma unroll
     for (int m = 0; m < TPT; ++m) tws[t + m * NTT_TPB] = twi[m];
     __syncthreads();
-    lds_transform_pad_any<true, NTT_ROWS_BLOCK, 0>(k2, bufa, tws, P);
     // out as they are (below 4P): the inverse columns apply the inverse twiddles as they read
     // them back (the scale 1 / N came in with the second operand's forward twiddles)
+    if (regs) {
+        lds_transform_pad_any<true, NTT_ROWS_BLOCK, 0, false, 1, false>(k2, bufa, tws, P);
+        uint32_t u[EPT_R];
+#pragma unroll
+        for (int i = 0; i < EPT_R; ++i) u[i] = bufa[tp + i * PSTEP];
+        row_outer<true>(k2, u, twi, P);
+#pragma unroll
+        for (int i = 0; i < EPT_R; ++i) stg(x + t + i * NTT_TPB, u[i]);
+    } else {
+        lds_transform_pad_any<true, NTT_ROWS_BLOCK, 0>(k2, bufa, tws, P);
 #pragma unroll 8
-    for (int i = 0; i < EPT_R; ++i) stg(x + t + i * NTT_TPB, bufa[tp + i * PSTEP]);
+        for (int i = 0; i < EPT_R; ++i) stg(x + t + i * NTT_TPB, bufa[tp + i * PSTEP]);
+    }
 }
 
 // TWS: words of stage twiddles, 2^k2 (rows of up to 2^10 take 38 KB of LDS and four blocks fit
