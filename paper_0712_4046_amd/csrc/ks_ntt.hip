@@ -73,6 +73,7 @@ __device__ __forceinline__ uint32_t root_pow(int q, uint32_t e, NttPrime P) {
 }
 
 // The two butterflies on partly reduced residues (P < 2^30).
+static_assert(NTT_P0 < (1u << 30) && NTT_P1 < (1u << 30), "partly reduced residues need 4P < 2^32");
 // Forward, decimation in frequency: u, v < 2P -> u + v and (u - v) w, both below 2P.
 __device__ __forceinline__ void bfly_dif(uint32_t &u, uint32_t &v, uint32_t w, NttPrime P) {
     const uint32_t s = red2(u + v, P.p), d = mmul_lazy(u + 2u * P.p - v, w, P);
@@ -407,15 +408,17 @@ __device__ __forceinline__ void fwd_cols_body(const NttJob &J, int64_t local, ui
         uint32_t *dst = x + ((int64_t)r << k2) + c0 + cf;
         const uint32_t *src = buf + cf * SC + pad_ix(r);
         for (int c4 = 0; c4 < cols; c4 += 4) {
-            u32x4 v;  // below 2P; the running twiddle is kept fully reduced
+            // below 2P.  The running twiddle stays partly reduced, below 2P (w g < 2P^2 < P 2^32
+            // with g < P), and so do the products (src w < 4P^2 < P 2^32, as P < 2^30)
+            u32x4 v;
             v.x = mmul_lazy(src[c4 * SC], w, P);
-            w = mmul(w, g, P);
+            w = mmul_lazy(w, g, P);
             v.y = mmul_lazy(src[(c4 + 1) * SC], w, P);
-            w = mmul(w, g, P);
+            w = mmul_lazy(w, g, P);
             v.z = mmul_lazy(src[(c4 + 2) * SC], w, P);
-            w = mmul(w, g, P);
+            w = mmul_lazy(w, g, P);
             v.w = mmul_lazy(src[(c4 + 3) * SC], w, P);
-            w = mmul(w, g, P);
+            w = mmul_lazy(w, g, P);
             *(__attribute__((address_space(1))) u32x4 *)(dst + c4) = v;
         }
     }
