@@ -707,8 +707,10 @@ bool ntt_shape(int64_t na, int64_t nb, int min_log, int &k1, int &k2, int &w, in
             if (pa + pb - 1 > N) continue;
             // exact: every term below min(pa, pb) 2^(2w) <= 2^59 < P0 P1
             if (2 * ww + ceil_log2(std::min(pa, pb)) > 59) break;
-            k1 = k / 2;
-            k2 = k - k1;
+            // rows as long as the small stage table allows (2^10), columns at most 2^11 and at
+            // least 2^6: the row step costs less per transform stage than the column steps
+            k2 = std::min(std::max(10, k - 11), k - 6);
+            k1 = k - k2;
             w = ww;
             npa = pa;
             npb = pb;
