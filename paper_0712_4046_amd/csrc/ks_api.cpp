@@ -390,13 +390,14 @@ int plan_product(const Spec &sp, Geom &G) {
     // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement: K = 8 is
     // the optimum of the L = 4096 product).  In a batch of n products the anchors of all
     // products share the GPU while their chains run side by side, which favours longer
-    // segments: the factor sqrt(n), c = 5e5 and the floor of 256 match the measured optima of
+    // segments: the factor sqrt(n), c = 2.8e5 and the floor of 256 match the measured optima of
     // the 10,000-product (K = 256: 1.52 ms against 1.54 at 128 and 1.66 at 64, once a chain step
-    // took ~77 instructions) and 64-product modular (K = 512-1024) workloads.
+    // took ~77 instructions) and 64-product modular workloads (K ~ 990 with ~34 instructions a
+    // step and 16 steps in flight: 2.31-2.35 ms at K = 900-1100 against 2.40-2.45 at 741).
     auto add_chain = [&](int a, int bb, int64_t m, int first, int64_t Nd, int step) {
         const double Lm = (double)std::min(lf, lg);
         const double nbat = std::sqrt((double)sp.batch_count);
-        const double cK = sp.batch ? 5.0e5 : 2.0e6;
+        const double cK = sp.batch ? 2.8e5 : 2.0e6;
         int64_t K = (int64_t)(std::sqrt(nbat * G.D * Lm * sp.w_in * sp.w_in / cK) + 0.5);
         K = std::max<int64_t>(sp.batch ? 256 : 4, std::min<int64_t>(K, 4096));
         const int64_t Kset = env_int("KS_CHAIN_K", 0);
