@@ -56,9 +56,9 @@ NTT_STEPS = {"ntt_fwd_cols": (2, 0), "ntt_rows": (3, 1), "ntt_inv_cols": (1, 0)}
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (copy-calibrated: FETCH x2, WRITE
 # x1) on the headline workload (profiles/batch_mod_64x65536_ks4_hbm_traffic.txt).  A kernel whose
 # code changed after the counters were taken has no entry (traffic: null).
-MEASURED_TRAFFIC_C4 = {"pack": 500420560, "ntt_fwd_cols": 1218371526, "ntt_rows": 1614477443,
-                       "ntt_inv_cols": 1078786408, "ntt_join": 975751249, "normalize": 652477498,
-                       "recon": 347540232, "finish": 271353845}
+MEASURED_TRAFFIC_C4 = {"pack": 499244704, "ntt_fwd_cols": 1218383264, "ntt_rows": 1614460572,
+                       "ntt_inv_cols": 1077944815, "ntt_join": 975755152, "normalize": 653600101,
+                       "recon": 347516170, "finish": 271342628}
 KERNELS = ("kara", "pack", "mul_valu", "digitize", "mul_mfma", "ntt_fwd_cols", "ntt_rows",
            "ntt_inv_cols", "ntt_join", "normalize", "anchor", "recon", "finish", "extract", "p2_eval", "p2_recon")
 METRIC = "polynomial products/s + limb-mults/s at 1 GPU; KS4 vs KS1 speedup, bit-exact"

@@ -390,16 +390,16 @@ int plan_product(const Spec &sp, Geom &G) {
     // dependent steps; K ~ sqrt(D L W^2 / c) balances the two (c from measurement: K = 8 is
     // the optimum of the L = 4096 product).  In a batch of n products the anchors of all
     // products share the GPU while their chains run side by side, which favours longer
-    // segments: the factor sqrt(n), c = 2.8e5 and the floor of 256 match the measured optima of
-    // the 10,000-product (K = 256: 1.52 ms against 1.54 at 128 and 1.66 at 64, once a chain step
-    // took ~77 instructions) and 64-product modular workloads (K ~ 990 with ~34 instructions a
-    // step and 16 steps in flight: 2.31-2.35 ms at K = 900-1100 against 2.40-2.45 at 741).
+    // segments: the factor sqrt(n), c = 2.8e5 and the floor of 384 match the measured optima of
+    // the 10,000-product (K = 384: 1.39-1.40 ms against 1.41 at 256, 1.41-1.42 at 512 and 1.43
+    // at 192) and 64-product modular workloads (K ~ 990: 2.31-2.35 ms at K = 900-1100 against
+    // 2.40-2.45 at 741), with ~34 instructions a chain step and 16 steps in flight.
     auto add_chain = [&](int a, int bb, int64_t m, int first, int64_t Nd, int step) {
         const double Lm = (double)std::min(lf, lg);
         const double nbat = std::sqrt((double)sp.batch_count);
         const double cK = sp.batch ? 2.8e5 : 2.0e6;
         int64_t K = (int64_t)(std::sqrt(nbat * G.D * Lm * sp.w_in * sp.w_in / cK) + 0.5);
-        K = std::max<int64_t>(sp.batch ? 256 : 4, std::min<int64_t>(K, 4096));
+        K = std::max<int64_t>(sp.batch ? 384 : 4, std::min<int64_t>(K, 4096));
         const int64_t Kset = env_int("KS_CHAIN_K", 0);
         if (Kset > 0) K = Kset;
         G.nw = (int)cdiv(Nd, 32);
